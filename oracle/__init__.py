@@ -1,0 +1,235 @@
+"""Python access to the FP64 oracle (kf_oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the CPU-baseline leg of the
+benchmark use it to check and time the GPU library.  The GPU library never
+imports it.
+
+build() compiles liboracle.so with g++ (-O2, OpenMP over tracks/seeds); load()
+returns the ctypes handle, building on first use when the library is absent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kf_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+ST_PROP_FAIL = 1
+ST_NEAR_TANGENT = 2
+ST_ILLCOND = 4
+ST_NONFINITE = 8
+ST_BAD_INPUT = 16
+ST_TERM_MISSES = 32
+
+
+class OGeom(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("n_phi_bins", C.c_int32), ("n_z_bins", C.c_int32),
+                ("pad", C.c_int32), ("B", C.c_double), ("sigma_rphi", C.c_double),
+                ("sigma_z", C.c_double), ("sigma_r", C.c_double), ("mass", C.c_double),
+                ("radius", C.c_double * 32), ("zhalf", C.c_double * 32)]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+                               SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _lib = C.CDLL(LIB)
+        _lib.oracle_total_chi2.restype = C.c_double
+    return _lib
+
+
+def ogeom(geom) -> OGeom:
+    g = OGeom()
+    g.n_layers = geom.n_layers
+    g.n_phi_bins = geom.n_phi_bins
+    g.n_z_bins = geom.n_z_bins
+    g.B = geom.B
+    g.sigma_rphi = geom.sigma_rphi
+    g.sigma_z = geom.sigma_z
+    g.sigma_r = geom.sigma_r
+    g.mass = geom.mass
+    for i in range(geom.n_layers):
+        g.radius[i] = geom.radius[i]
+        g.zhalf[i] = geom.zhalf[i]
+    return g
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def propagate(state, center, r, B):
+    out = np.zeros(6)
+    s = C.c_double(0)
+    st = np.ascontiguousarray(state, np.float64)
+    ok = load().oracle_propagate(_p(st), C.c_double(center[0]), C.c_double(center[1]), C.c_double(r),
+                                 C.c_double(B), _p(out), C.byref(s))
+    return (out, s.value) if ok else (None, None)
+
+
+def transport_jacobian(state, s, B):
+    J = np.zeros(36)
+    st = np.ascontiguousarray(state, np.float64)
+    load().oracle_transport_jacobian(_p(st), C.c_double(s), C.c_double(B), _p(J))
+    return J.reshape(6, 6)
+
+
+def helix_at(state, s, B):
+    out = np.zeros(6)
+    st = np.ascontiguousarray(state, np.float64)
+    load().oracle_helix_at(_p(st), C.c_double(s), C.c_double(B), _p(out))
+    return out
+
+
+def measurement(state, center, m):
+    H = np.zeros(18)
+    r = np.zeros(3)
+    st = np.ascontiguousarray(state, np.float64)
+    mm = np.ascontiguousarray(m, np.float64)
+    load().oracle_measurement(_p(st), C.c_double(center[0]), C.c_double(center[1]), _p(mm), _p(H), _p(r))
+    return H.reshape(3, 6), r
+
+
+def scattering(geom, state, center, xX0):
+    Q = np.zeros(36)
+    g = ogeom(geom)
+    st = np.ascontiguousarray(state, np.float64)
+    load().oracle_scattering(C.byref(g), _p(st), C.c_double(center[0]), C.c_double(center[1]),
+                             C.c_double(xX0), _p(Q))
+    return Q.reshape(6, 6)
+
+
+def kalman_update(x, Cm, H, V, r):
+    x = np.array(x, np.float64)
+    Cm = np.array(Cm, np.float64)
+    H = np.ascontiguousarray(H, np.float64)
+    V = np.ascontiguousarray(V, np.float64)
+    r = np.ascontiguousarray(r, np.float64)
+    n, m = x.shape[0], r.shape[0]
+    chi2 = C.c_double(0)
+    ok = load().oracle_kalman_update(n, m, _p(x), _p(Cm), _p(H), _p(V), _p(r), C.byref(chi2))
+    if not ok:
+        raise ValueError("singular S")
+    return x, Cm, chi2.value
+
+
+def seed(geom, m0, m1, m2):
+    st = np.zeros(6)
+    cv = np.zeros(36)
+    g = ogeom(geom)
+    a, b, c = (np.ascontiguousarray(v, np.float64) for v in (m0, m1, m2))
+    load().oracle_seed(C.byref(g), _p(a), _p(b), _p(c), _p(st), _p(cv))
+    return st, cv.reshape(6, 6)
+
+
+def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, records=False):
+    """Batched FP64 fit; seeds from hits 0-2 unless seed_state/seed_cov are given.
+
+    hits [L][3][n] float32 (float64 hits select the float64-input entry), mask [n]
+    uint32.  Returns a dict of float64 outputs.
+    """
+    dt = np.float64 if np.asarray(hits).dtype == np.float64 else np.float32
+    hits = np.ascontiguousarray(hits, dt)
+    mask = np.ascontiguousarray(mask, np.uint32)
+    L, _, n = hits.shape
+    from_hits = seed_state is None
+    ss = None if from_hits else np.ascontiguousarray(seed_state, dt)
+    sc = None if from_hits else np.ascontiguousarray(seed_cov, dt)
+    out = dict(state=np.zeros((6, n)), cov=np.zeros((21, n)), chi2=np.zeros(n),
+               ndf=np.zeros(n, np.int32), status=np.zeros(n, np.uint32))
+    rec = np.zeros((n, L, 27)) if records else None
+    g = ogeom(geom)
+    xx = geom.xX0 if xX0 is None else xX0
+    fn = load().oracle_fit_f64 if dt == np.float64 else load().oracle_fit
+    fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(hits), _p(mask),
+                      int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]), _p(out["chi2"]),
+                      _p(out["ndf"]), _p(out["status"]), _p(rec))
+    if records:
+        out["records"] = rec
+    return out
+
+
+def total_chi2(geom, hits, mask, align, xX0, weight=None):
+    hits = np.ascontiguousarray(hits, np.float32)
+    mask = np.ascontiguousarray(mask, np.uint32)
+    g = ogeom(geom)
+    return load().oracle_total_chi2(C.byref(g), _p(_f64(align)), _p(_f64(xX0)), C.c_int64(hits.shape[2]),
+                                    _p(hits), _p(mask), _p(_f64(weight)))
+
+
+def fit_grad(geom, hits, mask, align, xX0, weight=None):
+    """FP64 gradient of sum_i weight_i chi2_i w.r.t. align [L][4] and xX0 [L] (dual numbers)."""
+    hits = np.ascontiguousarray(hits, np.float32)
+    mask = np.ascontiguousarray(mask, np.uint32)
+    L = hits.shape[0]
+    ga = np.zeros((L, 4))
+    gx = np.zeros(L)
+    g = ogeom(geom)
+    load().oracle_fit_grad(C.byref(g), _p(_f64(align)), _p(_f64(xX0)), C.c_int64(hits.shape[2]), _p(hits),
+                           _p(mask), _p(_f64(weight)), _p(ga), _p(gx))
+    return ga, gx
+
+
+def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, refit=False,
+         align=None, xX0=None, tol_abs=0.05, tol_rel=1e-4, tol_win=5e-3):
+    """FP64 combinatorial search of every seed of a synth.EventBatch."""
+    L = geom.n_layers
+    S = ev.seed_hits.shape[1]
+    H = ev.hits.shape[1]
+    hits = np.ascontiguousarray(ev.hits, np.float32)
+    off = np.ascontiguousarray(ev.hit_off, np.int64)
+    sev = np.ascontiguousarray(ev.seed_event, np.int32)
+    sh = np.ascontiguousarray(ev.seed_hits, np.int32)
+    o = dict(n_cand=np.zeros(S, np.int32), hit_idx=np.zeros((keep, L, S), np.int32),
+             n_hits=np.zeros((keep, S), np.int32), n_miss=np.zeros((keep, S), np.int32),
+             chi2=np.zeros((keep, S)), state=np.zeros((keep, 6, S)), cov=np.zeros((keep, 21, S)),
+             status=np.zeros((keep, S), np.uint32), ambig=np.zeros(S, np.uint32))
+    if refit:
+        o.update(rf_state=np.zeros((6, S)), rf_cov=np.zeros((21, S)), rf_chi2=np.zeros(S),
+                 rf_ndf=np.zeros(S, np.int32), rf_status=np.zeros(S, np.uint32))
+    g = ogeom(geom)
+    xx = geom.xX0 if xX0 is None else xX0
+    load().oracle_find(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int32(off.shape[0]), _p(off),
+                       C.c_int64(H), _p(hits), C.c_int64(S), _p(sev), _p(sh), C.c_double(chi2_cut),
+                       C.c_double(nsigma), C.c_int32(keep), C.c_int32(max_miss), C.c_int32(int(brute)),
+                       C.c_double(tol_abs), C.c_double(tol_rel), C.c_double(tol_win),
+                       _p(o["n_cand"]), _p(o["hit_idx"]), _p(o["n_hits"]), _p(o["n_miss"]), _p(o["chi2"]),
+                       _p(o["state"]), _p(o["cov"]), _p(o["status"]), _p(o["ambig"]),
+                       _p(o.get("rf_state")), _p(o.get("rf_cov")), _p(o.get("rf_chi2")),
+                       _p(o.get("rf_ndf")), _p(o.get("rf_status")))
+    return o
+
+
+def unpack_cov(c21):
+    """[21, ...] packed lower triangle -> [6, 6, ...] symmetric."""
+    c21 = np.asarray(c21)
+    out = np.zeros((6, 6) + c21.shape[1:], dtype=c21.dtype)
+    k = 0
+    for i in range(6):
+        for j in range(i + 1):
+            out[i, j] = c21[k]
+            out[j, i] = c21[k]
+            k += 1
+    return out

@@ -1,0 +1,1092 @@
+// FP64 oracle of the batched Kalman fit, the combinatorial track finder and the
+// gradient of the fit's total chi2 with respect to per-layer alignment and material.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or call
+// this file: it exists so that tests, the smoke check and the CPU baseline of the
+// benchmark can compare the GPU library against a plain, slow, independently
+// written implementation.  It shares no code, header or constant table with the
+// GPU library.
+//
+// What it follows.  The paper (Sec. 2) states that track building and fitting are
+// the Kalman filter method applied layer by layer to symmetric 6x6 covariances,
+// that the geometry supplies layer positions, search windows and radiation
+// lengths for multiple scattering (Sec. 3), that the field is a constant 3.8 T
+// (Sec. 4), and that candidates are ranked by scores inside search windows
+// (Sec. 4.3).  It prints no formula; every formula below is the textbook reading
+// of those statements (extended Kalman filter, helix in a uniform solenoidal
+// field, Highland multiple scattering), as listed in the design notes.
+//
+// Deliberately different numerical routes from the GPU library:
+//   * the crossing of the helix with a layer is bracketed by marching along the helix,
+//     bisected, then polished by Newton steps on the transverse arc length;
+//   * the residual's azimuth difference is a difference of two atan2 values;
+//   * S is inverted by Gauss-Jordan elimination with partial pivoting on the full
+//     3x3 matrix; every matrix product is a dense loop over all indices.
+//
+// Everything is templated on the scalar type so that forward-mode dual numbers
+// give the FP64 reference gradient (Dual<N> below).
+//
+// Parity pins (tests/test_oracle_*.py): linear-Gaussian filter = batch weighted
+// least squares; straight-line limit of the crossing; noiseless hits return the
+// generating helix; covariances stay symmetric positive definite; pulls and
+// chi2/ndf of simulated tracks have unit scale; Jacobians agree with central
+// differences of the oracle's own maps; binned search = brute-force search;
+// dual-number gradient = central finite differences; global translation and
+// rotation leave the total chi2 unchanged.  Parity unpinned: the candidate score
+// and its tie rule, and the Highland variant, which are conventions.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------------------------
+// forward-mode dual numbers
+// ------------------------------------------------------------------------------
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0) { for (int i = 0; i < N; ++i) d[i] = 0; }
+  Dual(double x) : v(x) { for (int i = 0; i < N; ++i) d[i] = 0; }  // NOLINT
+};
+template <int N> Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+template <int N> Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v * b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+template <int N> Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v / b.v; for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a) { Dual<N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
+template <int N> Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
+template <int N> Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
+template <int N> Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
+template <int N> Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
+template <int N> Dual<N> operator*(const Dual<N>& a, double b) { Dual<N> r; r.v = a.v * b; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b; return r; }
+template <int N> Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
+template <int N> Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+template <int N> Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N> Dual<N>& operator+=(Dual<N>& a, const Dual<N>& b) { a = a + b; return a; }
+template <int N> Dual<N>& operator-=(Dual<N>& a, const Dual<N>& b) { a = a - b; return a; }
+template <int N> Dual<N>& operator*=(Dual<N>& a, const Dual<N>& b) { a = a * b; return a; }
+template <int N> Dual<N> chain(const Dual<N>& a, double f, double df) { Dual<N> r; r.v = f; for (int i = 0; i < N; ++i) r.d[i] = df * a.d[i]; return r; }
+template <int N> Dual<N> sqrt(const Dual<N>& a) { double s = std::sqrt(a.v); return chain(a, s, 0.5 / s); }
+template <int N> Dual<N> sin(const Dual<N>& a) { return chain(a, std::sin(a.v), std::cos(a.v)); }
+template <int N> Dual<N> cos(const Dual<N>& a) { return chain(a, std::cos(a.v), -std::sin(a.v)); }
+template <int N> Dual<N> atan(const Dual<N>& a) { return chain(a, std::atan(a.v), 1.0 / (1.0 + a.v * a.v)); }
+template <int N> Dual<N> asin(const Dual<N>& a) { return chain(a, std::asin(a.v), 1.0 / std::sqrt(1.0 - a.v * a.v)); }
+template <int N> Dual<N> log(const Dual<N>& a) { return chain(a, std::log(a.v), 1.0 / a.v); }
+template <int N> Dual<N> fabs(const Dual<N>& a) { return a.v < 0 ? -a : a; }
+template <int N> Dual<N> atan2(const Dual<N>& y, const Dual<N>& x) {
+  Dual<N> r; r.v = std::atan2(y.v, x.v);
+  double q = x.v * x.v + y.v * y.v;
+  for (int i = 0; i < N; ++i) r.d[i] = (x.v * y.d[i] - y.v * x.d[i]) / q;
+  return r;
+}
+
+inline double val(double x) { return x; }
+template <int N> double val(const Dual<N>& x) { return x.v; }
+
+template <class T> T wrap_pi(const T& a) {  // to (-pi, pi]
+  double k = std::floor((val(a) + kPi) / (2 * kPi));
+  T r = a - 2 * kPi * k;
+  if (val(r) <= -kPi) r = r + 2 * kPi;
+  if (val(r) > kPi) r = r - 2 * kPi;
+  return r;
+}
+
+// ------------------------------------------------------------------------------
+// geometry, options, status
+// ------------------------------------------------------------------------------
+}  // namespace
+
+extern "C" {
+// Mirrors the Python-side ctypes structure in oracle/__init__.py.
+struct OGeom {
+  int32_t n_layers, n_phi_bins, n_z_bins, pad;
+  double B, sigma_rphi, sigma_z, sigma_r, mass;
+  double radius[32];
+  double zhalf[32];
+};
+}
+
+namespace {
+
+enum : uint32_t {
+  ST_PROP_FAIL = 1u,      // the helix does not reach a layer it has to cross
+  ST_NEAR_TANGENT = 2u,   // some crossing has |cos alpha| < 0.3
+  ST_ILLCOND = 4u,        // equilibrated det(S) below the FP32 trust threshold
+  ST_NONFINITE = 8u,
+  ST_BAD_INPUT = 16u,     // hit mask lacks the seed layers
+  ST_TERM_MISSES = 32u,   // finder: candidate stopped after max_miss missing layers
+};
+
+constexpr double kHighlandA = 0.0136, kHighlandB = 0.038;
+constexpr double kIllCond = 1e-2;
+
+template <class T>
+struct Layer {
+  T cx, cy, dz, cphi, sphi, xX0;  // alignment (centre, z shift, rotation) and x/X0
+  double r;
+};
+
+struct Geo {
+  int nl;
+  double kB, srphi, sz, sr, mass;
+  double radius[32], zhalf[32];
+  int nphi, nz;
+};
+
+Geo make_geo(const OGeom* g) {
+  Geo o;
+  o.nl = g->n_layers;
+  o.kB = 0.299792458e-2 * g->B;
+  o.srphi = g->sigma_rphi; o.sz = g->sigma_z; o.sr = g->sigma_r; o.mass = g->mass;
+  for (int l = 0; l < 32; ++l) { o.radius[l] = g->radius[l]; o.zhalf[l] = g->zhalf[l]; }
+  o.nphi = g->n_phi_bins; o.nz = g->n_z_bins;
+  return o;
+}
+
+template <class T>
+void make_layers(const Geo& g, const T* align /*[L][4]*/, const T* xX0, Layer<T>* lay) {
+  using std::cos; using std::sin;
+  for (int l = 0; l < g.nl; ++l) {
+    lay[l].cx = align ? align[4 * l + 0] : T(0.0);
+    lay[l].cy = align ? align[4 * l + 1] : T(0.0);
+    lay[l].dz = align ? align[4 * l + 2] : T(0.0);
+    T dphi = align ? align[4 * l + 3] : T(0.0);
+    lay[l].cphi = cos(dphi);
+    lay[l].sphi = sin(dphi);
+    lay[l].xX0 = xX0 ? xX0[l] : T(0.0);
+    lay[l].r = g.radius[l];
+  }
+}
+
+// Nominal-frame hit -> the layer's actual position (rigid transform about its axis).
+template <class T>
+void place_hit(const Layer<T>& ly, double hx, double hy, double hz, T m[3]) {
+  m[0] = ly.cx + ly.cphi * hx - ly.sphi * hy;
+  m[1] = ly.cy + ly.sphi * hx + ly.cphi * hy;
+  m[2] = ly.dz + hz;
+}
+
+// ------------------------------------------------------------------------------
+// track model: helix in a uniform field along +z
+// state (x, y, z, kappa = q/pT, phi, theta); omega = -k_B kappa is the turning rate
+// per unit transverse arc length.
+// ------------------------------------------------------------------------------
+
+// Position and direction after a transverse arc s.
+template <class T>
+void helix_at(const T x[6], const T& s, double kB, T out[6]) {
+  using std::cos; using std::sin;
+  T w = -kB * x[3];
+  T u = w * s;
+  T A, Bn;  // displacement = s (A t + Bn n)
+  if (std::fabs(val(u)) < 1e-4) {
+    T u2 = u * u;
+    A = 1.0 - u2 / 6.0 + u2 * u2 / 120.0;
+    Bn = u * (0.5 - u2 / 24.0 + u2 * u2 / 720.0);
+  } else {
+    T sh = sin(0.5 * u);
+    A = sin(u) / u;
+    Bn = 2.0 * sh * sh / u;
+  }
+  T tx = cos(x[4]), ty = sin(x[4]);
+  out[0] = x[0] + s * (A * tx - Bn * ty);
+  out[1] = x[1] + s * (A * ty + Bn * tx);
+  out[2] = x[2] + s * cos(x[5]) / sin(x[5]);
+  out[3] = x[3];
+  out[4] = wrap_pi(x[4] + u);
+  out[5] = x[5];
+}
+
+// Transverse arc length to the first forward crossing with |p - c| = r, within the
+// first half turn.  f(s) = |p(s) - c|^2 - r^2 is negative at s = 0 (inside); march
+// along the helix until it changes sign, bisect the bracket, then polish with
+// Newton steps (which also settle the derivative parts of dual numbers).
+template <class T>
+T crossing_residual(const T x[6], const T& s, const T& cx, const T& cy, double r, double kB, T* fp) {
+  using std::cos; using std::sin;
+  T p[6];
+  helix_at(x, s, kB, p);
+  T dx = p[0] - cx, dy = p[1] - cy;
+  if (fp) *fp = 2.0 * (dx * cos(p[4]) + dy * sin(p[4]));
+  return dx * dx + dy * dy - r * r;
+}
+
+template <class T>
+bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, double kB, T& s) {
+  T ex = x[0] - cx, ey = x[1] - cy;
+  double c0 = val(ex * ex + ey * ey) - r * r;
+  if (!(c0 < 0)) return false;
+  double w = -kB * val(x[3]);
+  double smax = w != 0 ? kPi / std::fabs(w) : 4.0 * r;
+  double h = 0.125 * r;
+  if (w != 0) h = std::min(h, 0.125 / std::fabs(w));
+  double lo = 0.0, hi = -1.0;
+  for (double t = h; t < smax + h; t += h) {
+    double tt = std::min(t, smax);
+    double f = val(crossing_residual<T>(x, T(tt), cx, cy, r, kB, nullptr));
+    if (f >= 0) { hi = tt; break; }
+    lo = tt;
+    if (tt >= smax) break;
+  }
+  if (hi < 0) return false;
+  for (int it = 0; it < 200 && hi - lo > 1e-14 * hi; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (val(crossing_residual<T>(x, T(mid), cx, cy, r, kB, nullptr)) >= 0) hi = mid; else lo = mid;
+  }
+  s = T(0.5 * (lo + hi));
+  for (int it = 0; it < 3; ++it) {
+    T fp;
+    T f = crossing_residual<T>(x, s, cx, cy, r, kB, &fp);
+    if (val(fp) == 0) return false;
+    s = s - f / fp;
+  }
+  if (!(val(s) > 0)) return false;
+  if (w != 0 && std::fabs(w * val(s)) >= kPi) return false;
+  return true;
+}
+
+// Transport Jacobian of the helix map at fixed transverse arc s (start state x,
+// end state xe).  J = I plus six terms: d(x,y)/dphi, d(x,y)/dkappa, dz/dtheta,
+// dphi/dkappa.
+template <class T>
+void transport_jacobian(const T x[6], const T xe[6], const T& s, double kB, T J[6][6]) {
+  using std::cos; using std::sin;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) J[i][j] = T(i == j ? 1.0 : 0.0);
+  T w = -kB * x[3];
+  T u = w * s;
+  T F1, F2;  // d(displacement)/d(omega) = s^2 (F1 t + F2 n)
+  if (std::fabs(val(u)) < 1e-2) {
+    T u2 = u * u;
+    F1 = u * (-1.0 / 3.0 + u2 / 30.0 - u2 * u2 / 840.0);
+    F2 = 0.5 - u2 / 8.0 + u2 * u2 / 144.0 - u2 * u2 * u2 / 5760.0;
+  } else {
+    F1 = (u * cos(u) - sin(u)) / (u * u);
+    F2 = (u * sin(u) - 1.0 + cos(u)) / (u * u);
+  }
+  T tx = cos(x[4]), ty = sin(x[4]);
+  T s2 = s * s;
+  J[0][4] = -(xe[1] - x[1]);
+  J[1][4] = xe[0] - x[0];
+  J[0][3] = -kB * s2 * (F1 * tx - F2 * ty);
+  J[1][3] = -kB * s2 * (F1 * ty + F2 * tx);
+  T st = sin(x[5]);
+  J[2][5] = -s / (st * st);
+  J[4][3] = T(-kB) * s;
+}
+
+template <class T>
+void sandwich(const T J[6][6], T C[6][6]) {  // C <- J C J^T
+  T JC[6][6], R[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      T acc = 0.0;
+      for (int k = 0; k < 6; ++k) acc += J[i][k] * C[k][j];
+      JC[i][j] = acc;
+    }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      T acc = 0.0;
+      for (int k = 0; k < 6; ++k) acc += JC[i][k] * J[j][k];
+      R[i][j] = acc;
+    }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) C[i][j] = 0.5 * (R[i][j] + R[j][i]);
+}
+
+// Multiple scattering of a thin layer at the predicted state: Highland's width with
+// the 1/cos(psi) path-length factor, mapped to (kappa, phi, theta).
+template <class T>
+void add_scattering(const Geo& g, const Layer<T>& ly, const T x[6], T C[6][6]) {
+  using std::cos; using std::sin; using std::sqrt; using std::log; using std::fabs;
+  if (!(val(ly.xX0) > 0)) return;
+  T ex = x[0] - ly.cx, ey = x[1] - ly.cy;
+  T rho = sqrt(ex * ex + ey * ey);
+  T st = sin(x[5]), ct = cos(x[5]);
+  T cpsi = st * fabs((ex * cos(x[4]) + ey * sin(x[4])) / rho);
+  T p = 1.0 / (fabs(x[3]) * st);
+  T beta = p / sqrt(p * p + g.mass * g.mass);
+  T xe = ly.xX0 / cpsi;
+  T th0 = kHighlandA / (beta * p) * sqrt(xe) * (1.0 + kHighlandB * log(xe));
+  T th2 = th0 * th0;
+  T cot = ct / st;
+  C[4][4] += th2 / (st * st);
+  C[5][5] += th2;
+  C[3][3] += x[3] * x[3] * cot * cot * th2;
+  C[3][5] -= x[3] * cot * th2;
+  C[5][3] -= x[3] * cot * th2;
+}
+
+// Gauss-Jordan inverse with partial pivoting (n <= 4); returns false if singular.
+template <class T>
+bool invert(int n, const T* A, T* Ai) {
+  T M[4][8];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < 2 * n; ++j) M[i][j] = j < n ? A[i * n + j] : T(j - n == i ? 1.0 : 0.0);
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(val(M[r][c])) > std::fabs(val(M[piv][c]))) piv = r;
+    if (val(M[piv][c]) == 0) return false;
+    if (piv != c)
+      for (int j = 0; j < 2 * n; ++j) std::swap(M[c][j], M[piv][j]);
+    T inv = 1.0 / M[c][c];
+    for (int j = 0; j < 2 * n; ++j) M[c][j] = M[c][j] * inv;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      T f = M[r][c];
+      for (int j = 0; j < 2 * n; ++j) M[r][j] = M[r][j] - f * M[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Ai[i * n + j] = M[i][n + j];
+  return true;
+}
+
+// Generic Kalman update for an n-dim state and m-dim measurement:
+//   S = H C H^T + V, chi2 = r^T S^-1 r, K = C H^T S^-1, x += K r,
+//   C <- (I - K H) C (I - K H)^T + K V K^T  (Joseph form), symmetrised.
+template <class T>
+bool kalman_update(int n, int m, T* x, T* C, const T* H, const T* V, const T* r, T& chi2, T* Sout = nullptr) {
+  T HC[4 * 8], S[16], Si[16], K[8 * 4];
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) {
+      T acc = 0.0;
+      for (int k = 0; k < n; ++k) acc += H[i * n + k] * C[k * n + j];
+      HC[i * n + j] = acc;
+    }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      T acc = V[i * m + j];
+      for (int k = 0; k < n; ++k) acc += HC[i * n + k] * H[j * n + k];
+      S[i * m + j] = acc;
+    }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) { T a = 0.5 * (S[i * m + j] + S[j * m + i]); S[i * m + j] = a; S[j * m + i] = a; }
+  if (Sout) for (int i = 0; i < m * m; ++i) Sout[i] = S[i];
+  if (!invert(m, S, Si)) return false;
+  chi2 = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) chi2 += r[i] * Si[i * m + j] * r[j];
+  for (int i = 0; i < n; ++i)  // K = (H C)^T S^-1
+    for (int j = 0; j < m; ++j) {
+      T acc = 0.0;
+      for (int k = 0; k < m; ++k) acc += HC[k * n + i] * Si[k * m + j];
+      K[i * m + j] = acc;
+    }
+  for (int i = 0; i < n; ++i) {
+    T acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += K[i * m + j] * r[j];
+    x[i] += acc;
+  }
+  T A[64], AC[64], N[64];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      T acc = T(i == j ? 1.0 : 0.0);
+      for (int k = 0; k < m; ++k) acc -= K[i * m + k] * H[k * n + j];
+      A[i * n + j] = acc;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      T acc = 0.0;
+      for (int k = 0; k < n; ++k) acc += A[i * n + k] * C[k * n + j];
+      AC[i * n + j] = acc;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      T acc = 0.0;
+      for (int k = 0; k < n; ++k) acc += AC[i * n + k] * A[j * n + k];
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) acc += K[i * m + a] * V[a * m + b] * K[j * m + b];
+      N[i * n + j] = acc;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) C[i * n + j] = 0.5 * (N[i * n + j] + N[j * n + i]);
+  return true;
+}
+
+// Measurement model at a predicted state on a cylindrical layer.
+// Local frame about the layer axis at the prediction: (rho, rho*phi, z).
+// Residual is cylindrical: (rho_m - rho_p, rho_p * wrap(phi_m - phi_p), z_m - z_p).
+// H projects the state's position along its 3-D tangent onto the cylinder:
+//   row 0 = 0, row 1 = phi_hat - tan(alpha) r_hat, row 2 = (-cot(theta)/cos(alpha) r_hat, 1),
+// with cos(alpha) = r_hat . t and tan(alpha) = (phi_hat . t) / cos(alpha).
+template <class T>
+struct Meas {
+  T H[3 * 6];
+  T r[3];
+  T rho, phip, cosa;
+};
+
+template <class T>
+void measurement(const Layer<T>& ly, const T x[6], const T m[3], Meas<T>& o) {
+  using std::atan2; using std::cos; using std::sin; using std::sqrt;
+  T ex = x[0] - ly.cx, ey = x[1] - ly.cy;
+  T rho = sqrt(ex * ex + ey * ey);
+  T rx = ex / rho, ry = ey / rho;
+  T fx = -ry, fy = rx;
+  T tx = cos(x[4]), ty = sin(x[4]);
+  T cosa = rx * tx + ry * ty;
+  T tana = (fx * tx + fy * ty) / cosa;
+  T cot = cos(x[5]) / sin(x[5]);
+  for (int i = 0; i < 18; ++i) o.H[i] = 0.0;
+  o.H[6 + 0] = fx - tana * rx;
+  o.H[6 + 1] = fy - tana * ry;
+  o.H[12 + 0] = -cot / cosa * rx;
+  o.H[12 + 1] = -cot / cosa * ry;
+  o.H[12 + 2] = 1.0;
+  T mx = m[0] - ly.cx, my = m[1] - ly.cy;
+  T rhom = sqrt(mx * mx + my * my);
+  T phim = atan2(my, mx), phip = atan2(ey, ex);
+  o.r[0] = rhom - rho;
+  o.r[1] = rho * wrap_pi(phim - phip);
+  o.r[2] = m[2] - x[2];
+  o.rho = rho;
+  o.phip = phip;
+  o.cosa = cosa;
+}
+
+template <class T>
+double equilibrated_det(const T S[9]) {
+  double d0 = val(S[0]), d1 = val(S[4]), d2 = val(S[8]);
+  if (!(d0 > 0 && d1 > 0 && d2 > 0)) return 0.0;
+  double a = val(S[1]) / std::sqrt(d0 * d1), b = val(S[2]) / std::sqrt(d0 * d2), c = val(S[5]) / std::sqrt(d1 * d2);
+  return 1.0 + 2 * a * b * c - a * a - b * b - c * c;
+}
+
+template <class T>
+struct Track {
+  T x[6];
+  T C[6][6];
+  T chi2;
+  int n;
+  uint32_t status;
+};
+
+template <class T>
+bool update_with_hit(const Geo& g, const Layer<T>& ly, Track<T>& tk, const T m[3], T* chi2_out = nullptr) {
+  Meas<T> me;
+  measurement(ly, tk.x, m, me);
+  if (std::fabs(val(me.cosa)) < 0.3) tk.status |= ST_NEAR_TANGENT;
+  T V[9] = {g.sr * g.sr, 0.0, 0.0, 0.0, g.srphi * g.srphi, 0.0, 0.0, 0.0, g.sz * g.sz};
+  T S[9] = {};
+  T chi2;
+  if (!kalman_update(6, 3, tk.x, &tk.C[0][0], me.H, V, me.r, chi2, S)) { tk.status |= ST_NONFINITE; return false; }
+  if (equilibrated_det(S) < kIllCond) tk.status |= ST_ILLCOND;
+  if (val(chi2) < 0) chi2 = 0.0;
+  tk.x[4] = wrap_pi(tk.x[4]);
+  tk.chi2 += chi2;
+  tk.n += 1;
+  if (chi2_out) *chi2_out = chi2;
+  return true;
+}
+
+// Propagate to layer L: crossing, C <- J C J^T, then + Q of the layer's material.
+template <class T>
+bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk) {
+  T s;
+  if (!crossing_arc(tk.x, ly.cx, ly.cy, ly.r, g.kB, s)) { tk.status |= ST_PROP_FAIL; return false; }
+  T xe[6];
+  helix_at(tk.x, s, g.kB, xe);
+  T J[6][6];
+  transport_jacobian(tk.x, xe, s, g.kB, J);
+  sandwich(J, tk.C);
+  for (int i = 0; i < 6; ++i) tk.x[i] = xe[i];
+  add_scattering(g, ly, tk.x, tk.C);
+  return true;
+}
+
+// Three-hit helix seed at hit 0 (signed Menger curvature, chord angles), with the
+// diagonal prior covariance inflated ten times in variance.
+template <class T>
+void seed_from_hits(const Geo& g, const T m0[3], const T m1[3], const T m2[3], Track<T>& tk) {
+  using std::asin; using std::atan2; using std::sqrt;
+  T ax = m1[0] - m0[0], ay = m1[1] - m0[1];
+  T bx = m2[0] - m1[0], by = m2[1] - m1[1];
+  T cx = m2[0] - m0[0], cy = m2[1] - m0[1];
+  T la = sqrt(ax * ax + ay * ay), lb = sqrt(bx * bx + by * by), lc = sqrt(cx * cx + cy * cy);
+  T w = 2.0 * (ax * by - ay * bx) / (la * lb * lc);
+  T qa = 0.5 * w * la, qc = 0.5 * w * lc;
+  if (val(qa) > 1) qa = 1.0;
+  if (val(qa) < -1) qa = -1.0;
+  if (val(qc) > 1) qc = 1.0;
+  if (val(qc) < -1) qc = -1.0;
+  T phi0 = atan2(ay, ax) - asin(qa);
+  T s02;
+  if (std::fabs(val(qc)) < 1e-4) s02 = lc * (1.0 + qc * qc / 6.0 + 0.075 * qc * qc * qc * qc);
+  else s02 = lc * asin(qc) / qc;
+  T theta = atan2(s02, m2[2] - m0[2]);
+  tk.x[0] = m0[0]; tk.x[1] = m0[1]; tk.x[2] = m0[2];
+  tk.x[3] = -w / g.kB;
+  tk.x[4] = wrap_pi(phi0);
+  tk.x[5] = theta;
+  double dr = g.radius[2] - g.radius[0];
+  double sphi = std::sqrt(2.0) * g.srphi / dr, sth = std::sqrt(2.0) * g.sz / dr;
+  double skap = 8.0 * std::sqrt(1.5) * g.srphi / (dr * dr * g.kB);
+  double d[6] = {g.srphi * g.srphi, g.srphi * g.srphi, g.sz * g.sz, skap * skap, sphi * sphi, sth * sth};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) tk.C[i][j] = T(i == j ? 10.0 * d[i] : 0.0);
+  tk.chi2 = 0.0;
+  tk.n = 0;
+  tk.status = 0;
+}
+
+
+inline int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+// The fit of one track: seed at layer 0, update on hit 0, then for every later layer
+// up to the last hit: predict (crossing, transport, scattering) and, where the layer
+// has a hit, update.  m[l] are the placed hits, mask bit l marks a hit on layer l.
+// rec (optional) receives the filtered state and covariance after each update, [L][27].
+template <class T>
+Track<T> fit_core(const Geo& g, const Layer<T>* lay, const T (*m)[3], uint32_t mask, bool from_hits,
+                  const double* seed_x, const double* seed_C, double* rec) {
+  Track<T> tk;
+  for (int i = 0; i < 6; ++i) { tk.x[i] = 0.0; for (int j = 0; j < 6; ++j) tk.C[i][j] = 0.0; }
+  tk.chi2 = 0.0; tk.n = 0; tk.status = 0;
+  uint32_t need = from_hits ? 7u : 1u;
+  if ((mask & need) != need) { tk.status = ST_BAD_INPUT; return tk; }
+  if (from_hits) {
+    seed_from_hits(g, m[0], m[1], m[2], tk);
+  } else {
+    for (int i = 0; i < 6; ++i) tk.x[i] = seed_x[i];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) tk.C[i][j] = seed_C[i * 6 + j];
+  }
+  auto record = [&](int l) {
+    if (!rec) return;
+    for (int i = 0; i < 6; ++i) rec[(int64_t)l * 27 + i] = val(tk.x[i]);
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j <= i; ++j) rec[(int64_t)l * 27 + 6 + tri(i, j)] = val(tk.C[i][j]);
+  };
+  if (!update_with_hit(g, lay[0], tk, m[0])) return tk;
+  record(0);
+  int last = 31 - __builtin_clz(mask);
+  if (last >= g.nl) last = g.nl - 1;
+  for (int l = 1; l <= last; ++l) {
+    if (!predict(g, lay[l], tk)) break;
+    if (mask >> l & 1u) {
+      if (!update_with_hit(g, lay[l], tk, m[l])) break;
+      record(l);
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(val(tk.x[i]))) tk.status |= ST_NONFINITE;
+  return tk;
+}
+
+// Gather and place the hits of track i from the [L][3][n] layout.
+template <class T, class HT>
+void gather_hits(const Geo& g, const Layer<T>* lay, const HT* hits, int64_t n, int64_t i, uint32_t mask, T (*m)[3]) {
+  for (int l = 0; l < g.nl; ++l) {
+    if (!(mask >> l & 1u)) { m[l][0] = 0.0; m[l][1] = 0.0; m[l][2] = 0.0; continue; }
+    const HT* h = hits + (int64_t)l * 3 * n;
+    place_hit(lay[l], (double)h[i], (double)h[n + i], (double)h[2 * n + i], m[l]);
+  }
+}
+
+template <class T, class HT>
+Track<T> fit_track_i(const Geo& g, const Layer<T>* lay, const HT* hits, int64_t n, int64_t i, uint32_t mask,
+                     bool from_hits, const HT* seed_state, const HT* seed_cov, double* rec) {
+  T m[32][3];
+  gather_hits(g, lay, hits, n, i, mask, m);
+  double sx[6], sC[36];
+  if (!from_hits) {
+    for (int k = 0; k < 6; ++k) sx[k] = (double)seed_state[(int64_t)k * n + i];
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) sC[a * 6 + b] = (double)seed_cov[(int64_t)tri(a, b) * n + i];
+  }
+  return fit_core<T>(g, lay, m, mask, from_hits, sx, sC, rec);
+}
+
+}  // namespace
+
+// ==============================================================================
+// C entry points (called from Python through ctypes)
+// ==============================================================================
+extern "C" {
+
+// Crossing of one state with the cylinder |p - c| = r: writes the propagated state
+// and the transverse arc; returns 1 on success, 0 if the layer is not reached.
+int oracle_propagate(const double* state, double cx, double cy, double r, double B, double* out, double* s_out) {
+  double kB = 0.299792458e-2 * B;
+  double s;
+  if (!crossing_arc<double>(state, cx, cy, r, kB, s)) return 0;
+  helix_at<double>(state, s, kB, out);
+  *s_out = s;
+  return 1;
+}
+
+// Fixed-s transport Jacobian (row-major 6x6) of the state at arc s.
+void oracle_transport_jacobian(const double* state, double s, double B, double* J) {
+  double kB = 0.299792458e-2 * B;
+  double xe[6], Jm[6][6];
+  helix_at<double>(state, s, kB, xe);
+  transport_jacobian<double>(state, xe, s, kB, Jm);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) J[i * 6 + j] = Jm[i][j];
+}
+
+// Helix map at fixed arc s (for finite-difference checks of the Jacobian).
+void oracle_helix_at(const double* state, double s, double B, double* out) {
+  helix_at<double>(state, s, 0.299792458e-2 * B, out);
+}
+
+// Measurement model of a state against a placed hit on a cylinder centred at
+// (cx, cy): H (row-major 3x6) and the residual r (3).
+void oracle_measurement(const double* state, double cx, double cy, const double* m, double* H, double* r) {
+  Layer<double> ly{cx, cy, 0.0, 1.0, 0.0, 0.0, 0.0};
+  Meas<double> me;
+  measurement(ly, state, m, me);
+  for (int i = 0; i < 18; ++i) H[i] = me.H[i];
+  for (int i = 0; i < 3; ++i) r[i] = me.r[i];
+}
+
+// Multiple-scattering covariance Q (row-major 6x6) at a state on a layer.
+void oracle_scattering(const OGeom* og, const double* state, double cx, double cy, double xX0, double* Q) {
+  Geo g = make_geo(og);
+  Layer<double> ly{cx, cy, 0.0, 1.0, 0.0, xX0, 0.0};
+  double C[6][6] = {};
+  add_scattering(g, ly, state, C);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) Q[i * 6 + j] = C[i][j];
+}
+
+// Generic Kalman update (n <= 8, m <= 4), row-major matrices, in place on x and C.
+int oracle_kalman_update(int n, int m, double* x, double* C, const double* H, const double* V, const double* r, double* chi2) {
+  double c2;
+  if (!kalman_update<double>(n, m, x, C, H, V, r, c2)) return 0;
+  *chi2 = c2;
+  return 1;
+}
+
+// Three-hit seed (state 6, covariance row-major 6x6) from three placed hits.
+void oracle_seed(const OGeom* og, const double* m0, const double* m1, const double* m2, double* state, double* cov) {
+  Geo g = make_geo(og);
+  Track<double> tk;
+  seed_from_hits(g, m0, m1, m2, tk);
+  for (int i = 0; i < 6; ++i) state[i] = tk.x[i];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) cov[i * 6 + j] = tk.C[i][j];
+}
+
+// Batched fit.  hits [L][3][n] float32 in each layer's nominal frame; align [L][4]
+// and xX0 [L] (either may be null: zero).  seed_from_hits != 0 builds each seed from
+// hits 0-2; otherwise seed_state [6][n] and seed_cov [21][n] are used.  Outputs in
+// float64: state [6][n], cov [21][n] (packed lower triangle, index i(i+1)/2 + j),
+// chi2 [n], ndf [n] = 2 n_hits - 5, status [n]; rec (optional) [n][L][27] filtered
+// state and covariance after each update (NaN elsewhere).
+}  // extern "C"
+
+namespace {
+template <class HT>
+void fit_batch(const OGeom* og, const double* align, const double* xX0, int64_t n, const HT* hits,
+               const uint32_t* mask, int seed_from_hits_flag, const HT* seed_state, const HT* seed_cov,
+               double* state, double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec) {
+  Geo g = make_geo(og);
+  Layer<double> lay[32];
+  make_layers<double>(g, align, xX0, lay);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double* r = nullptr;
+    if (rec) {
+      r = rec + i * (int64_t)g.nl * 27;
+      for (int64_t k = 0; k < (int64_t)g.nl * 27; ++k) r[k] = std::numeric_limits<double>::quiet_NaN();
+    }
+    Track<double> tk = fit_track_i<double, HT>(g, lay, hits, n, i, mask[i], seed_from_hits_flag != 0, seed_state, seed_cov, r);
+    for (int k = 0; k < 6; ++k) state[k * n + i] = tk.x[k];
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b <= a; ++b) cov[(int64_t)tri(a, b) * n + i] = tk.C[a][b];
+    chi2[i] = tk.chi2;
+    ndf[i] = 2 * tk.n - 5;
+    status[i] = tk.status;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+void oracle_fit(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
+                const uint32_t* mask, int seed_from_hits_flag, const float* seed_state, const float* seed_cov,
+                double* state, double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec) {
+  fit_batch<float>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, state, cov, chi2, ndf,
+                   status, rec);
+}
+
+// As oracle_fit with float64 hits and seeds (for noiseless checks finer than float32).
+void oracle_fit_f64(const OGeom* og, const double* align, const double* xX0, int64_t n, const double* hits,
+                    const uint32_t* mask, int seed_from_hits_flag, const double* seed_state, const double* seed_cov,
+                    double* state, double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec) {
+  fit_batch<double>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, state, cov, chi2, ndf,
+                    status, rec);
+}
+
+// Weighted total chi2, sum_i weight[i] * chi2_i (weight may be null: all ones),
+// summed in track order, seeds built from hits.  For central finite differences.
+double oracle_total_chi2(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
+                         const uint32_t* mask, const double* weight) {
+  Geo g = make_geo(og);
+  Layer<double> lay[32];
+  make_layers<double>(g, align, xX0, lay);
+  std::vector<double> c(n);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    Track<double> tk = fit_track_i<double, float>(g, lay, hits, n, i, mask[i], true, nullptr, nullptr, nullptr);
+    c[i] = tk.chi2;
+  }
+  double acc = 0;
+  for (int64_t i = 0; i < n; ++i) acc += (weight ? weight[i] : 1.0) * c[i];
+  return acc;
+}
+
+// Gradient of sum_i weight[i] chi2_i with respect to align [L][4] and xX0 [L], by
+// forward-mode dual numbers through the whole fit (seeds built from the placed
+// hits), one layer's five parameters per pass.
+void oracle_fit_grad(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
+                     const uint32_t* mask, const double* weight, double* g_align, double* g_xX0) {
+  using D = Dual<5>;
+  Geo g = make_geo(og);
+  for (int pl = 0; pl < g.nl; ++pl) {
+    D al[32 * 4], xx[32];
+    for (int l = 0; l < g.nl; ++l) {
+      for (int k = 0; k < 4; ++k) al[4 * l + k] = D(align ? align[4 * l + k] : 0.0);
+      xx[l] = D(xX0 ? xX0[l] : 0.0);
+    }
+    for (int k = 0; k < 4; ++k) al[4 * pl + k].d[k] = 1.0;
+    xx[pl].d[4] = 1.0;
+    Layer<D> lay[32];
+    make_layers<D>(g, al, xx, lay);
+    std::vector<double> part((size_t)n * 5);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      Track<D> tk = fit_track_i<D, float>(g, lay, hits, n, i, mask[i], true, nullptr, nullptr, nullptr);
+      double w = weight ? weight[i] : 1.0;
+      for (int k = 0; k < 5; ++k) part[(size_t)i * 5 + k] = w * tk.chi2.d[k];
+    }
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < 5; ++k) acc[k] += part[(size_t)i * 5 + k];
+    for (int k = 0; k < 4; ++k) g_align[4 * pl + k] = acc[k];
+    g_xX0[pl] = acc[4];
+  }
+}
+
+}  // extern "C"
+
+// ==============================================================================
+// combinatorial track finder
+// ==============================================================================
+namespace {
+
+struct BinnedLayer {
+  std::vector<double> phi, z;   // azimuth about the layer axis and z of each binned hit
+  std::vector<int64_t> idx;     // global hit index, in bin order
+  std::vector<int64_t> off;     // [nphi * nz + 1]
+  int64_t begin = 0, end = 0;   // the layer's slice of the global hit arrays
+};
+
+int64_t bin_floor(double v, double lo, double span, int nb) {
+  return (int64_t)std::floor((v - lo) * nb / span);
+}
+int clamp_bin(int64_t b, int nb) { return (int)(b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b)); }
+
+struct Cand {
+  Track<double> tk;
+  int nmiss = 0;
+  bool term = false;
+  std::vector<int32_t> hist;
+};
+
+struct Branch {
+  int parent;
+  int kind;      // 0 hit, 1 miss, 2 carry (terminated parent)
+  int64_t hit;
+  int nhits;
+  double chi2tot, chi2h;
+};
+
+// Candidate score: more hits first, then smaller total chi2, then the parent's
+// rank, then the hit's index (the miss branch after every hit branch).
+bool branch_less(const Branch& a, const Branch& b) {
+  if (a.nhits != b.nhits) return a.nhits > b.nhits;
+  if (a.chi2tot != b.chi2tot) return a.chi2tot < b.chi2tot;
+  if (a.parent != b.parent) return a.parent < b.parent;
+  int64_t ha = a.kind == 0 ? a.hit : std::numeric_limits<int64_t>::max();
+  int64_t hb = b.kind == 0 ? b.hit : std::numeric_limits<int64_t>::max();
+  return ha < hb;
+}
+
+struct FindCfg {
+  double chi2_cut, nsigma, tol_abs, tol_rel, tol_win;
+  int keep, max_miss;
+  bool brute;
+};
+
+struct EventView {
+  const float* hits;  // [3][H]
+  int64_t H;
+  const int64_t* off;  // [L+1] of this event
+};
+
+void place_global(const Layer<double>& ly, const EventView& ev, int64_t j, double m[3]) {
+  place_hit(ly, (double)ev.hits[j], (double)ev.hits[ev.H + j], (double)ev.hits[2 * ev.H + j], m);
+}
+
+// phi/z bins of one layer of one event: counting sort, stable in hit index.
+void bin_layer(const Geo& g, const Layer<double>& ly, int l, const EventView& ev, BinnedLayer& B) {
+  const int nphi = g.nphi, nz = g.nz, nb = nphi * nz;
+  B.begin = ev.off[l];
+  B.end = ev.off[l + 1];
+  int64_t nh = B.end - B.begin;
+  std::vector<int> bin(nh);
+  std::vector<double> ph(nh), zz(nh);
+  for (int64_t j = 0; j < nh; ++j) {
+    double m[3];
+    place_global(ly, ev, B.begin + j, m);
+    ph[j] = std::atan2(m[1] - val(ly.cy), m[0] - val(ly.cx));
+    zz[j] = m[2];
+    int bp = clamp_bin(bin_floor(ph[j], -kPi, 2 * kPi, nphi), nphi);
+    int bz = clamp_bin(bin_floor(zz[j], -g.zhalf[l], 2 * g.zhalf[l], nz), nz);
+    bin[j] = bp * nz + bz;
+  }
+  B.off.assign(nb + 1, 0);
+  for (int64_t j = 0; j < nh; ++j) B.off[bin[j] + 1]++;
+  for (int b = 0; b < nb; ++b) B.off[b + 1] += B.off[b];
+  std::vector<int64_t> cur(B.off.begin(), B.off.end() - 1);
+  B.phi.resize(nh); B.z.resize(nh); B.idx.resize(nh);
+  for (int64_t j = 0; j < nh; ++j) {
+    int64_t p = cur[bin[j]]++;
+    B.phi[p] = ph[j]; B.z[p] = zz[j]; B.idx[p] = B.begin + j;
+  }
+}
+
+// chi2 of a placed hit against a prediction whose S^-1 is known.
+double hit_chi2(const Layer<double>& ly, const double x[6], const double Si[9], const double m[3]) {
+  Meas<double> me;
+  measurement(ly, x, m, me);
+  double c = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) c += me.r[i] * Si[i * 3 + j] * me.r[j];
+  return c < 0 ? 0 : c;
+}
+
+// One seed through layers 3 .. L-1.  Returns the candidates in rank order; ambig gets
+// bit L set when some decision on layer L that can change the set of surviving
+// candidates lies within the FP32 tolerance of its threshold: a chi2 near the cut, a
+// hit near a window edge, or the last kept and first dropped branch scores near a tie.
+std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCfg& o, const EventView& ev,
+                            const std::vector<BinnedLayer>& bl, const int32_t sh[3], uint32_t& ambig) {
+  ambig = 0;
+  std::vector<Cand> cands;
+  Cand c0;
+  c0.hist.assign(g.nl, -2);
+  double m[3][3];
+  for (int l = 0; l < 3; ++l) { place_global(lay[l], ev, sh[l], m[l]); c0.hist[l] = sh[l]; }
+  seed_from_hits(g, m[0], m[1], m[2], c0.tk);
+  bool ok = update_with_hit(g, lay[0], c0.tk, m[0]);
+  for (int l = 1; ok && l < 3; ++l) {
+    ok = predict(g, lay[l], c0.tk);
+    if (ok) ok = update_with_hit(g, lay[l], c0.tk, m[l]);
+  }
+  if (!ok) c0.term = true;
+  cands.push_back(c0);
+  const int nphi = g.nphi, nz = g.nz;
+  auto tol = [&](double c) { return o.tol_abs + o.tol_rel * std::fabs(c); };
+  for (int L = 3; L < g.nl; ++L) {
+    const Layer<double>& ly = lay[L];
+    const BinnedLayer& B = bl[L];
+    std::vector<Branch> br;
+    std::vector<Track<double>> pred(cands.size());
+    for (size_t k = 0; k < cands.size(); ++k) {
+      Cand& cd = cands[k];
+      if (cd.term) { br.push_back({(int)k, 2, -1, cd.tk.n, cd.tk.chi2, 0.0}); continue; }
+      Track<double> p = cd.tk;
+      if (!predict(g, ly, p)) {
+        cd.term = true;
+        cd.tk.status |= ST_PROP_FAIL;
+        br.push_back({(int)k, 2, -1, cd.tk.n, cd.tk.chi2, 0.0});
+        continue;
+      }
+      pred[k] = p;
+      // S at the prediction: the frame and H belong to the prediction, so S is shared
+      // by every hit of the window.
+      Meas<double> me;
+      double self[3] = {p.x[0], p.x[1], p.x[2]};
+      measurement(ly, p.x, self, me);
+      double HC[18], S[9], Si[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 6; ++j) {
+          double a = 0;
+          for (int q = 0; q < 6; ++q) a += me.H[i * 6 + q] * p.C[q][j];
+          HC[i * 6 + j] = a;
+        }
+      double V[3] = {g.sr * g.sr, g.srphi * g.srphi, g.sz * g.sz};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double a = i == j ? V[i] : 0.0;
+          for (int q = 0; q < 6; ++q) a += HC[i * 6 + q] * me.H[j * 6 + q];
+          S[i * 3 + j] = a;
+        }
+      if (!invert(3, S, Si)) {
+        cd.term = true;
+        cd.tk.status |= ST_NONFINITE;
+        br.push_back({(int)k, 2, -1, cd.tk.n, cd.tk.chi2, 0.0});
+        continue;
+      }
+      double wphi = o.nsigma * std::sqrt(S[4]) / me.rho;
+      double wz = o.nsigma * std::sqrt(S[8]);
+      double phip = me.phip, zp = p.x[2];
+      auto consider = [&](int64_t j, double phih, double zh) {
+        double dphi = wrap_pi(phih - phip), dz = zh - zp;
+        double ephi = std::fabs(dphi) - wphi, ez = std::fabs(dz) - wz;
+        bool inside = ephi <= 0 && ez <= 0;
+        bool near_edge = (std::fabs(ephi) <= o.tol_win * wphi && ez <= o.tol_win * wz) ||
+                         (std::fabs(ez) <= o.tol_win * wz && ephi <= o.tol_win * wphi);
+        if (!inside && !near_edge) return;
+        double mh[3];
+        place_global(ly, ev, j, mh);
+        double c = hit_chi2(ly, p.x, Si, mh);
+        if (near_edge && c < o.chi2_cut + tol(o.chi2_cut)) ambig |= 1u << L;
+        if (!inside) return;
+        if (std::fabs(c - o.chi2_cut) <= tol(o.chi2_cut)) ambig |= 1u << L;
+        if (c < o.chi2_cut) br.push_back({(int)k, 0, j, cd.tk.n + 1, cd.tk.chi2 + c, c});
+      };
+      if (o.brute) {
+        for (int64_t j = B.begin; j < B.end; ++j) {
+          double mh[3];
+          place_global(ly, ev, j, mh);
+          consider(j, std::atan2(mh[1] - ly.cy, mh[0] - ly.cx), mh[2]);
+        }
+      } else {
+        // every bin that can hold a hit within (1 + tol_win) of the window, and more
+        double wq = (1.0 + 2 * o.tol_win) * wphi + 1e-6;
+        double zq = (1.0 + 2 * o.tol_win) * wz + 1e-6;
+        int zlo = clamp_bin(bin_floor(zp - zq, -g.zhalf[L], 2 * g.zhalf[L], nz), nz);
+        int zhi = clamp_bin(bin_floor(zp + zq, -g.zhalf[L], 2 * g.zhalf[L], nz), nz);
+        int64_t blo = 0, bhi = nphi - 1;
+        if (wq < kPi) {
+          blo = bin_floor(phip - wq, -kPi, 2 * kPi, nphi);
+          bhi = bin_floor(phip + wq, -kPi, 2 * kPi, nphi);
+          if (bhi - blo + 1 >= nphi) { blo = 0; bhi = nphi - 1; }
+        }
+        for (int64_t b = blo; b <= bhi; ++b) {
+          int pb = (int)(((b % nphi) + nphi) % nphi);
+          for (int64_t q = B.off[pb * nz + zlo]; q < B.off[pb * nz + zhi + 1]; ++q) consider(B.idx[q], B.phi[q], B.z[q]);
+        }
+      }
+      br.push_back({(int)k, 1, -1, cd.tk.n, cd.tk.chi2, 0.0});
+    }
+    std::sort(br.begin(), br.end(), branch_less);
+    size_t nk = std::min<size_t>((size_t)o.keep, br.size());
+    // Which branches survive is decided at the boundary between the last kept and the
+    // first dropped branch; near-ties among kept branches only relabel ranks.
+    if (br.size() > nk) {
+      const Branch& a = br[nk - 1];
+      const Branch& b = br[nk];
+      if (a.nhits == b.nhits && std::fabs(a.chi2tot - b.chi2tot) <= tol(std::max(a.chi2tot, b.chi2tot)))
+        ambig |= 1u << L;
+    }
+    std::vector<Cand> next;
+    for (size_t i = 0; i < nk; ++i) {
+      const Branch& b = br[i];
+      Cand nc = cands[b.parent];
+      if (b.kind == 1) {
+        nc.tk = pred[b.parent];
+        nc.nmiss += 1;
+        nc.hist[L] = -1;
+        if (nc.nmiss >= o.max_miss) { nc.term = true; nc.tk.status |= ST_TERM_MISSES; }
+      } else if (b.kind == 0) {
+        nc.tk = pred[b.parent];
+        double mh[3];
+        place_global(ly, ev, b.hit, mh);
+        if (!update_with_hit(g, ly, nc.tk, mh)) nc.term = true;
+        nc.tk.chi2 = b.chi2tot;
+        nc.hist[L] = (int32_t)b.hit;
+      }
+      next.push_back(std::move(nc));
+    }
+    cands.swap(next);
+  }
+  return cands;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Combinatorial search of every seed of every event, then (refit != 0) a fit of each
+// seed's rank-0 candidate from its own hits.
+//   hit_off [E][L+1] slices of the global hits [3][H] per event and layer;
+//   seed_event [S], seed_hits [3][S] global indices of the seed's hits on layers 0-2;
+//   brute != 0 tests every hit of a layer instead of the phi/z bins.
+// Outputs (k < keep slots per seed, unused slots zero / -2):
+//   n_cand [S]; hit_idx [keep][L][S] (global index, -1 missing layer, -2 not reached);
+//   n_hits, n_miss [keep][S]; chi2 [keep][S]; state [keep][6][S]; cov [keep][21][S];
+//   status [keep][S]; ambig [S] (bit L: an FP32-sensitive decision on layer L);
+//   rf_* [S]: refit of rank 0 (may be null).
+void oracle_find(const OGeom* og, const double* align, const double* xX0, int32_t n_events, const int64_t* hit_off,
+                 int64_t n_hits_total, const float* hits, int64_t n_seeds, const int32_t* seed_event,
+                 const int32_t* seed_hits, double chi2_cut, double nsigma, int32_t keep, int32_t max_miss,
+                 int32_t brute, double tol_abs, double tol_rel, double tol_win, int32_t* n_cand, int32_t* hit_idx,
+                 int32_t* n_hits, int32_t* n_miss, double* chi2, double* state, double* cov, uint32_t* status,
+                 uint32_t* ambig, double* rf_state, double* rf_cov, double* rf_chi2, int32_t* rf_ndf,
+                 uint32_t* rf_status) {
+  Geo g = make_geo(og);
+  Layer<double> lay[32];
+  make_layers<double>(g, align, xX0, lay);
+  const int L = g.nl;
+  std::vector<std::vector<BinnedLayer>> bins(n_events, std::vector<BinnedLayer>(L));
+#pragma omp parallel for schedule(dynamic)
+  for (int e = 0; e < n_events; ++e) {
+    EventView ev{hits, n_hits_total, hit_off + (int64_t)e * (L + 1)};
+    for (int l = 0; l < L; ++l) bin_layer(g, lay[l], l, ev, bins[e][l]);
+  }
+  FindCfg o{chi2_cut, nsigma, tol_abs, tol_rel, tol_win, keep, max_miss, brute != 0};
+  const int64_t S = n_seeds;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < S; ++s) {
+    int e = seed_event[s];
+    EventView ev{hits, n_hits_total, hit_off + (int64_t)e * (L + 1)};
+    int32_t sh[3] = {seed_hits[s], seed_hits[S + s], seed_hits[2 * S + s]};
+    uint32_t amb = 0;
+    std::vector<Cand> cs = find_seed(g, lay, o, ev, bins[e], sh, amb);
+    ambig[s] = amb;
+    n_cand[s] = (int32_t)cs.size();
+    for (int k = 0; k < keep; ++k) {
+      bool have = k < (int)cs.size();
+      for (int l = 0; l < L; ++l) hit_idx[((int64_t)k * L + l) * S + s] = have ? cs[k].hist[l] : -2;
+      n_hits[(int64_t)k * S + s] = have ? cs[k].tk.n : 0;
+      n_miss[(int64_t)k * S + s] = have ? cs[k].nmiss : 0;
+      chi2[(int64_t)k * S + s] = have ? cs[k].tk.chi2 : 0.0;
+      status[(int64_t)k * S + s] = have ? cs[k].tk.status : 0u;
+      for (int i = 0; i < 6; ++i) state[((int64_t)k * 6 + i) * S + s] = have ? cs[k].tk.x[i] : 0.0;
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b <= a; ++b) cov[((int64_t)k * 21 + tri(a, b)) * S + s] = have ? cs[k].tk.C[a][b] : 0.0;
+    }
+    if (rf_state) {
+      double m[32][3];
+      uint32_t mask = 0;
+      for (int l = 0; l < L; ++l) {
+        int32_t h = cs[0].hist[l];
+        if (h >= 0) { mask |= 1u << l; place_global(lay[l], ev, h, m[l]); }
+        else { m[l][0] = m[l][1] = m[l][2] = 0.0; }
+      }
+      Track<double> tk = fit_core<double>(g, lay, m, mask, true, nullptr, nullptr, nullptr);
+      for (int i = 0; i < 6; ++i) rf_state[(int64_t)i * S + s] = tk.x[i];
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b <= a; ++b) rf_cov[(int64_t)tri(a, b) * S + s] = tk.C[a][b];
+      rf_chi2[s] = tk.chi2;
+      rf_ndf[s] = 2 * tk.n - 5;
+      rf_status[s] = tk.status;
+    }
+  }
+}
+
+}  // extern "C"

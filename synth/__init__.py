@@ -1,0 +1,416 @@
+"""Seeded synthetic detector events for the Kalman fit and the combinatorial finder.
+
+Stand-in for the simulated CMS events the paper measures on (Sec. 4 and Sec. 5:
+ttbar at PU 50/70 with the Phase-I geometry), which are not available here.
+This module only *simulates* particles: exact helix crossings with cylindrical
+layers, Gaussian hit smearing, Highland multiple-scattering kicks, uniform noise
+hits and the bookkeeping around them.  It contains none of the filter's
+arithmetic (no propagation Jacobian, no covariance, no gain, no seed fit).
+Both the GPU path and the oracle consume exactly the float32 arrays produced
+here.
+
+Conventions shared with the filter (inputs only):
+  * units: cm, GeV, rad, tesla; B is uniform along +z;
+  * transverse direction phi, polar angle theta, kappa = q / pT;
+  * the signed turning rate per unit transverse arc is omega = -k_B * kappa with
+    k_B = 0.299792458e-2 * B  (cm^-1 GeV);
+  * a layer L is an infinite cylinder of radius r_L; its alignment
+    (dx, dy, dz, dphi) is a rigid transform about its own axis: the axis moves
+    to (dx, dy), hits move by dz along z and rotate by dphi about the axis.
+    Hits are always reported in the *nominal* frame of their layer.
+
+The random stream is numpy's Philox4x32-10 (Salmon et al., SC'11) keyed by
+(1906117440 + workload index, event index).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+BASE_SEED = 1906117440
+K_B_PER_TESLA = 0.299792458e-2   # GeV / (cm T)
+M_PION = 0.13957039              # GeV
+HIGHLAND_A = 0.0136              # GeV
+HIGHLAND_B = 0.038
+
+
+@dataclasses.dataclass
+class Geometry:
+    """Ideal barrel: concentric cylinders plus per-layer material and alignment."""
+    radius: np.ndarray            # [L] cm, strictly increasing
+    zhalf: np.ndarray             # [L] cm, half length used for z binning
+    B: float = 3.8                # tesla
+    xX0: np.ndarray | None = None  # [L] radiation lengths per layer crossing at normal incidence
+    sigma_rphi: float = 0.01      # cm
+    sigma_z: float = 0.1          # cm
+    sigma_r: float = 0.001        # cm, radial regulariser of the 3-D hit
+    mass: float = M_PION          # GeV, used in beta of the Highland formula
+    n_phi_bins: int = 128
+    n_z_bins: int = 32
+
+    def __post_init__(self):
+        self.radius = np.asarray(self.radius, dtype=np.float64)
+        self.zhalf = np.asarray(self.zhalf, dtype=np.float64)
+        if self.xX0 is None:
+            self.xX0 = np.zeros_like(self.radius)
+        self.xX0 = np.asarray(self.xX0, dtype=np.float64)
+
+    @property
+    def n_layers(self) -> int:
+        return int(self.radius.shape[0])
+
+    @property
+    def k_B(self) -> float:
+        return K_B_PER_TESLA * self.B
+
+
+def barrel(n_layers: int, r_min: float, r_max: float, B: float = 3.8,
+           xX0: float = 0.0, eta_max: float = 1.5, **kw) -> Geometry:
+    """Evenly spaced radii r_L = r_min + (r_max - r_min) L / (n_layers - 1).
+
+    The binning half length is Z_L = 1.1 r_L sinh(eta_max): every track
+    generated with |eta| < eta_max crosses layer L inside it (hits that stray
+    beyond it after scattering are clamped into the edge bins by the finder).
+    """
+    r = r_min + (r_max - r_min) * np.arange(n_layers) / (n_layers - 1)
+    z = 1.1 * r * math.sinh(eta_max)
+    return Geometry(radius=r, zhalf=z, B=B, xX0=np.full(n_layers, xX0), **kw)
+
+
+def rng_for(workload: int, event: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=[BASE_SEED + workload, event]))
+
+
+# --------------------------------------------------------------------------------------
+# particle kinematics
+# --------------------------------------------------------------------------------------
+
+def sample_particles(rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max=1.0):
+    """Prompt particles from the origin: (pT, phi, eta, q)."""
+    u = rng.random(n)
+    if pt_log:
+        lo, hi = pt_range
+        pt = lo * (hi / lo) ** u
+    else:
+        pt = pt_range[0] + (pt_range[1] - pt_range[0]) * u
+    phi = rng.uniform(-math.pi, math.pi, n)
+    eta = rng.uniform(-eta_max, eta_max, n)
+    q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    return pt, phi, eta, q
+
+
+def highland_theta0(p, beta, x):
+    """Highland's width of the projected scattering angle (PDG review, passage of
+    particles through matter), for x radiation lengths traversed."""
+    return HIGHLAND_A / (beta * p) * np.sqrt(x) * (1.0 + HIGHLAND_B * np.log(x))
+
+
+def first_crossing(px, py, phi, omega, cx, cy, r):
+    """Transverse arc length from (px, py) to the first forward crossing of the helix
+    with the circle |p - c| = r, and the crossing point.
+
+    Route: intersection of the helix's circle (centre p + n/omega) with the layer
+    circle; of the two intersection points the one reached first moving forward
+    wins.  Straight lines (omega == 0) use the line-circle root.  Returns
+    (s, qx, qy); NaN where the layer is never reached.
+    """
+    px = np.asarray(px, np.float64)
+    n = px.shape[0]
+    s = np.full(n, np.nan)
+    qx = np.full(n, np.nan)
+    qy = np.full(n, np.nan)
+    tx, ty = np.cos(phi), np.sin(phi)
+    ex, ey = px - cx, py - cy                     # start relative to the layer axis
+    e2 = ex * ex + ey * ey
+    straight = omega == 0.0
+    if np.any(straight):
+        i = straight
+        a = ex[i] * tx[i] + ey[i] * ty[i]
+        disc = a * a - (e2[i] - r * r)
+        ok = disc >= 0
+        root = np.where(ok, -a + np.sqrt(np.maximum(disc, 0)), np.nan)
+        root = np.where(root > 0, root, np.nan)
+        s[i] = root
+        qx[i] = px[i] + root * tx[i]
+        qy[i] = py[i] + root * ty[i]
+    curved = ~straight
+    if np.any(curved):
+        i = curved
+        w = omega[i]
+        nx, ny = -ty[i], tx[i]
+        R = 1.0 / np.abs(w)
+        ccx = px[i] + nx / w                      # centre of curvature
+        ccy = py[i] + ny / w
+        dx = ccx - cx
+        dy = ccy - cy
+        d = np.sqrt(dx * dx + dy * dy)
+        # d^2 - R^2 written without cancelling the two large squares
+        d2mR2 = e2[i] + 2.0 * (ex[i] * nx + ey[i] * ny) / w
+        a_ = (r * r + d2mR2) / (2.0 * d)          # distance from the layer axis to the chord
+        h2 = r * r - a_ * a_
+        ok = h2 >= 0
+        h = np.sqrt(np.maximum(h2, 0.0))
+        ux, uy = dx / d, dy / d
+        mx, my = cx + a_ * ux, cy + a_ * uy
+        cand = [(mx - h * uy, my + h * ux), (mx + h * uy, my - h * ux)]
+        psi_p = np.arctan2(py[i] - ccy, px[i] - ccx)
+        best = np.full(w.shape, np.inf)
+        bx = np.full(w.shape, np.nan)
+        by = np.full(w.shape, np.nan)
+        for (kx, ky) in cand:
+            psi_q = np.arctan2(ky - ccy, kx - ccx)
+            du = np.mod((psi_q - psi_p) * np.sign(w), 2.0 * math.pi)
+            sq = du * R
+            take = ok & (sq > 1e-9) & (sq < best)
+            best = np.where(take, sq, best)
+            bx = np.where(take, kx, bx)
+            by = np.where(take, ky, by)
+        best = np.where(np.isfinite(best), best, np.nan)
+        s[i], qx[i], qy[i] = best, bx, by
+    return s, qx, qy
+
+
+@dataclasses.dataclass
+class TrackSample:
+    """Simulated tracks of one or more events (structure of arrays over tracks)."""
+    hits: np.ndarray        # [L][3][N] float32, nominal-frame hit positions (NaN if absent)
+    hit_mask: np.ndarray    # [N] uint32, bit L set <=> a hit on layer L
+    truth: np.ndarray | None  # [L][6][N] float64, post-scatter state at each crossing
+    truth_hit: np.ndarray | None  # [L][3][N] float64, unsmeared crossing points (aligned frame)
+    pt: np.ndarray
+    phi: np.ndarray
+    eta: np.ndarray
+    q: np.ndarray
+
+
+def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max=1.0,
+             align=None, smear=True, scatter=True, keep_truth=True, particles=None,
+             hit_dtype=np.float32):
+    """Simulate n prompt tracks through every layer in turn.
+
+    At each layer: exact crossing (first_crossing), record the unsmeared point,
+    smear it along the cylinder (sigma_rphi in r*phi, sigma_z in z), then apply a
+    Gaussian multiple-scattering kick with the Highland width for the crossing's
+    path length (x/X0 / cos psi, cos psi = sin(theta) |r_hat . t|).  The momentum
+    magnitude is conserved (no energy loss).  A track that cannot reach a layer
+    stops there; later layers have no hit.
+    """
+    L = geom.n_layers
+    if particles is None:
+        pt, phi0, eta, q = sample_particles(rng, n, pt_range, pt_log, eta_max)
+    else:
+        pt, phi0, eta, q = (np.asarray(a, np.float64) for a in particles)
+        n = pt.shape[0]
+    if align is None:
+        align = np.zeros((L, 4))
+    align = np.asarray(align, np.float64)
+    theta = 2.0 * np.arctan(np.exp(-eta))
+    kappa = q / pt
+    phi = phi0.copy()
+    x = np.zeros(n)
+    y = np.zeros(n)
+    z = np.zeros(n)
+    alive = np.ones(n, dtype=bool)
+    hits = np.full((L, 3, n), np.nan, dtype=hit_dtype)
+    mask = np.zeros(n, dtype=np.uint32)
+    truth = np.full((L, 6, n), np.nan) if keep_truth else None
+    truth_hit = np.full((L, 3, n), np.nan) if keep_truth else None
+    kB = geom.k_B
+    for l in range(L):
+        dx, dy, dz, dphi = align[l]
+        r = geom.radius[l]
+        omega = -kB * kappa
+        s, qx, qy = first_crossing(x, y, phi, omega, dx, dy, r)
+        reach = alive & np.isfinite(s)
+        alive = reach
+        s = np.where(reach, s, 0.0)
+        x = np.where(reach, qx, x)
+        y = np.where(reach, qy, y)
+        z = z + s * np.cos(theta) / np.sin(theta)
+        phi = np.mod(phi + omega * s + math.pi, 2.0 * math.pi) - math.pi
+        # smeared measurement in the layer's true frame, reported in its nominal frame
+        g1 = rng.standard_normal(n)
+        g2 = rng.standard_normal(n)
+        if not smear:
+            g1[:] = 0.0
+            g2[:] = 0.0
+        ang = np.arctan2(y - dy, x - dx) + g1 * geom.sigma_rphi / r
+        zm = z + g2 * geom.sigma_z
+        loc = ang - dphi
+        hits[l, 0] = np.where(reach, r * np.cos(loc), np.nan)
+        hits[l, 1] = np.where(reach, r * np.sin(loc), np.nan)
+        hits[l, 2] = np.where(reach, zm - dz, np.nan)
+        mask |= np.where(reach, np.uint32(1) << np.uint32(l), np.uint32(0)).astype(np.uint32)
+        if keep_truth:
+            truth_hit[l] = np.where(reach, np.stack([x, y, z]), np.nan)
+        # multiple scattering at the crossing
+        k1 = rng.standard_normal(n)
+        k2 = rng.standard_normal(n)
+        xx = geom.xX0[l]
+        if scatter and xx > 0:
+            st, ct = np.sin(theta), np.cos(theta)
+            rhx, rhy = (x - dx) / r, (y - dy) / r
+            cpsi = st * np.abs(rhx * np.cos(phi) + rhy * np.sin(phi))
+            p = np.abs(1.0 / kappa) / st
+            beta = p / np.sqrt(p * p + geom.mass ** 2)
+            th0 = highland_theta0(p, beta, xx / cpsi)
+            a = k1 * th0
+            b = k2 * th0
+            cp, sp = np.cos(phi), np.sin(phi)
+            d0 = np.stack([st * cp, st * sp, ct])
+            e1 = np.stack([ct * cp, ct * sp, -st])
+            e2 = np.stack([-sp, cp, np.zeros(n)])
+            dn = d0 + a * e1 + b * e2
+            dn /= np.linalg.norm(dn, axis=0)
+            th_new = np.arccos(np.clip(dn[2], -1.0, 1.0))
+            ph_new = np.arctan2(dn[1], dn[0])
+            pt_new = p * np.sin(th_new)
+            theta = np.where(reach, th_new, theta)
+            phi = np.where(reach, ph_new, phi)
+            kappa = np.where(reach, q / pt_new, kappa)
+        if keep_truth:
+            truth[l] = np.where(reach, np.stack([x, y, z, kappa, phi, theta]), np.nan)
+    return TrackSample(hits=hits, hit_mask=mask, truth=truth, truth_hit=truth_hit,
+                       pt=pt, phi=phi0, eta=eta, q=q)
+
+
+# --------------------------------------------------------------------------------------
+# the five workloads
+# --------------------------------------------------------------------------------------
+
+def workload_geometry(k: int) -> Geometry:
+    """Geometry of workload k (1..5)."""
+    if k == 1:
+        return barrel(10, 4.0, 100.0, B=3.8, xX0=0.0, eta_max=1.0)
+    return barrel(17, 4.0, 110.0, B=3.8, xX0=0.02, eta_max=1.5)
+
+
+def fit_workload(k: int, n: int | None = None, keep_truth=False, align=None, event=0):
+    """Tracks for the fit workloads.
+
+    k = 1: 1 000 tracks, 10 layers 4..100 cm, no material, pT ~ U(0.5, 10), |eta| < 1.
+    k = 2: 1e6 tracks, 17 layers 4..110 cm, x/X0 = 0.02, pT log-uniform 0.5..50, |eta| < 1.5.
+    k = 4: as 2 with 1e5 tracks and a per-layer misalignment (see misalignment()).
+    """
+    geom = workload_geometry(k)
+    rng = rng_for(k, event)
+    if k == 1:
+        n = 1000 if n is None else n
+        ts = simulate(geom, rng, n, (0.5, 10.0), False, 1.0, keep_truth=keep_truth, align=align)
+    else:
+        n = (1_000_000 if k == 2 else 100_000) if n is None else n
+        if k == 4 and align is None:
+            align = misalignment(geom.n_layers)
+        ts = simulate(geom, rng, n, (0.5, 50.0), True, 1.5, keep_truth=keep_truth, align=align)
+    return geom, ts
+
+
+def misalignment(n_layers: int, sigma_shift=0.005, sigma_rot=1e-4, workload=4):
+    """True per-layer alignment (dx, dy, dz, dphi): N(0, 50 um) shifts, N(0, 0.1 mrad) rotation."""
+    rng = np.random.Generator(np.random.Philox(key=[BASE_SEED + workload, 2 ** 31 - 1]))
+    a = rng.standard_normal((n_layers, 4))
+    a[:, :3] *= sigma_shift
+    a[:, 3] *= sigma_rot
+    return a
+
+
+@dataclasses.dataclass
+class EventBatch:
+    """Hits of several events for the finder, grouped by event then by layer.
+
+    hit_off[e][L] .. hit_off[e][L+1] is the slice of event e's hits on layer L in the
+    global arrays (hit_off[e][n_layers] == hit_off[e+1][0]).
+    """
+    hits: np.ndarray        # [3][H] float32 nominal-frame positions
+    hit_off: np.ndarray     # [E][L+1] int64
+    hit_track: np.ndarray   # [H] int64 global track id, -1 for noise
+    seed_hits: np.ndarray   # [3][S] int32 global hit indices on layers 0, 1, 2
+    seed_event: np.ndarray  # [S] int32
+    seed_track: np.ndarray  # [S] int64 global track id of the seed
+    track_event: np.ndarray  # [T] int32
+    track_hits: np.ndarray  # [L][T] int64 global hit index of each track's hit (-1 none)
+    n_tracks: np.ndarray    # [E]
+
+
+def make_events(geom: Geometry, n_tracks_per_event, workload=3, noise_frac=0.2,
+                pt_range=(0.5, 50.0), pt_log=True, eta_max=1.5, scatter=True, smear=True,
+                first_event=0):
+    """Events for the finder: simulated tracks plus noise hits, shuffled per layer.
+
+    Noise: round(noise_frac * true hits on L) hits uniform in phi in [-pi, pi) and in
+    z in [-Z_L, Z_L], on the cylinder.  Seeds are the true triplets on layers 0-2.
+    """
+    L = geom.n_layers
+    all_hits, offs, tr_ids, seeds, seed_ev, seed_tr = [], [], [], [], [], []
+    track_ev, track_hits = [], []
+    base = 0
+    tid_base = 0
+    for e, nt in enumerate(n_tracks_per_event):
+        rng = rng_for(workload, first_event + e)
+        ts = simulate(geom, rng, int(nt), pt_range, pt_log, eta_max, keep_truth=False,
+                      smear=smear, scatter=scatter)
+        off = np.zeros(L + 1, dtype=np.int64)
+        ev_hits = []
+        ev_trk = []
+        pos_of = np.full((L, int(nt)), -1, dtype=np.int64)
+        for l in range(L):
+            have = (ts.hit_mask >> np.uint32(l)) & np.uint32(1)
+            idx = np.nonzero(have)[0]
+            h = ts.hits[l][:, idx].astype(np.float32)
+            nn = int(round(noise_frac * idx.shape[0]))
+            ph = rng.uniform(-math.pi, math.pi, nn)
+            zz = rng.uniform(-geom.zhalf[l], geom.zhalf[l], nn)
+            rr = geom.radius[l]
+            hn = np.stack([rr * np.cos(ph), rr * np.sin(ph), zz]).astype(np.float32)
+            hl = np.concatenate([h, hn], axis=1)
+            tl = np.concatenate([idx.astype(np.int64) + tid_base, np.full(nn, -1, np.int64)])
+            perm = rng.permutation(hl.shape[1])
+            hl = hl[:, perm]
+            tl = tl[perm]
+            inv = np.empty_like(perm)
+            inv[perm] = np.arange(perm.shape[0])
+            pos_of[l, idx] = base + off[l] + inv[: idx.shape[0]]
+            ev_hits.append(hl)
+            ev_trk.append(tl)
+            off[l + 1] = off[l] + hl.shape[1]
+        all_hits.append(np.concatenate(ev_hits, axis=1))
+        tr_ids.append(np.concatenate(ev_trk))
+        offs.append(off + base)
+        ok = (pos_of[0] >= 0) & (pos_of[1] >= 0) & (pos_of[2] >= 0)
+        sidx = np.nonzero(ok)[0]
+        seeds.append(pos_of[:3, sidx].astype(np.int32))
+        seed_ev.append(np.full(sidx.shape[0], e, np.int32))
+        seed_tr.append(sidx.astype(np.int64) + tid_base)
+        track_ev.append(np.full(int(nt), e, np.int32))
+        track_hits.append(pos_of)
+        base += int(off[L])
+        tid_base += int(nt)
+    return EventBatch(
+        hits=np.ascontiguousarray(np.concatenate(all_hits, axis=1)),
+        hit_off=np.stack(offs).astype(np.int64),
+        hit_track=np.concatenate(tr_ids),
+        seed_hits=np.ascontiguousarray(np.concatenate(seeds, axis=1)),
+        seed_event=np.concatenate(seed_ev),
+        seed_track=np.concatenate(seed_tr),
+        track_event=np.concatenate(track_ev),
+        track_hits=np.concatenate(track_hits, axis=1),
+        n_tracks=np.asarray(n_tracks_per_event, dtype=np.int64),
+    )
+
+
+def find_workload(k: int = 3, n_tracks: int | None = None, n_events: int | None = None):
+    """k = 3: one event of 5 000 tracks.  k = 5: 64 events with Poisson(mu_e) tracks,
+    mu_e ~ U(5 000, 20 000).  Geometry and noise as in the 17-layer fit workload."""
+    geom = workload_geometry(2)
+    if k == 3:
+        nt = [5000 if n_tracks is None else n_tracks] * (1 if n_events is None else n_events)
+    else:
+        ne = 64 if n_events is None else n_events
+        rng = rng_for(k, 2 ** 31 - 2)
+        mu = rng.uniform(5000, 20000, ne)
+        nt = rng.poisson(mu)
+        if n_tracks is not None:   # scaled-down copy of the same pileup mix
+            nt = np.maximum(1, np.round(nt * (n_tracks / 12500.0))).astype(np.int64)
+    return geom, make_events(geom, nt, workload=k)

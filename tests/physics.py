@@ -1,0 +1,60 @@
+"""Physics helpers for validation tests (numpy, float64): not part of any compute path.
+
+project_to_surface moves a filtered state along its own helix onto the cylinder of
+its layer and maps its covariance with the surface projection
+Pi = I - g a^T, where g = (t_x, t_y, cot(theta), 0, omega, 0) is the change of the
+state per unit transverse arc along the helix and a = (r_hat, 0, 0, 0, 0) / (r_hat . t)
+is the arc needed to return a position offset to the surface.  Only projected
+states are comparable with the simulated truth at the crossing.
+"""
+import numpy as np
+
+
+def helix_point(x, s, kB):
+    w = -kB * x[3]
+    u = w * s
+    small = np.abs(u) < 1e-6
+    us = np.where(small, 1.0, u)
+    A = np.where(small, 1 - u * u / 6, np.sin(us) / us)
+    Bn = np.where(small, u / 2, 2 * np.sin(0.5 * us) ** 2 / us)
+    tx, ty = np.cos(x[4]), np.sin(x[4])
+    px = x[0] + s * (A * tx - Bn * ty)
+    py = x[1] + s * (A * ty + Bn * tx)
+    pz = x[2] + s / np.tan(x[5])
+    ph = x[4] + u
+    return px, py, pz, ph
+
+
+def project_to_surface(x, Cm, r, kB, cx=0.0, cy=0.0):
+    """x [6, n], Cm [6, 6, n] -> projected (x, C)."""
+    x = np.array(x, np.float64)
+    s = np.zeros(x.shape[1])
+    for _ in range(30):
+        px, py, pz, ph = helix_point(x, s, kB)
+        ex, ey = px - cx, py - cy
+        f = ex * ex + ey * ey - r * r
+        fp = 2 * (ex * np.cos(ph) + ey * np.sin(ph))
+        s = s - f / fp
+    px, py, pz, ph = helix_point(x, s, kB)
+    xp = x.copy()
+    xp[0], xp[1], xp[2], xp[4] = px, py, pz, (ph + np.pi) % (2 * np.pi) - np.pi
+    n = x.shape[1]
+    rx, ry = (px - cx) / r, (py - cy) / r
+    tx, ty = np.cos(ph), np.sin(ph)
+    ca = rx * tx + ry * ty
+    g = np.stack([tx, ty, 1 / np.tan(x[5]), np.zeros(n), -kB * x[3], np.zeros(n)])
+    a = np.stack([rx / ca, ry / ca, np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)])
+    Pi = np.eye(6)[:, :, None] - g[:, None, :] * a[None, :, :]
+    Cp = np.einsum('ijn,jkn,lkn->iln', Pi, Cm, Pi)
+    return xp, Cp
+
+
+def pulls(est, cov, truth, idx=(3, 4, 5)):
+    """Pulls of state components; phi differences are wrapped."""
+    out = {}
+    for p in idx:
+        d = est[p] - truth[p]
+        if p == 4:
+            d = (d + np.pi) % (2 * np.pi) - np.pi
+        out[p] = d / np.sqrt(cov[p, p])
+    return out
