@@ -1,0 +1,204 @@
+/*
+ * kf.h -- C ABI of the MI355X (gfx950) batched Kalman-filter track fit, combinatorial
+ * track finder and adjoint of the fit.
+ *
+ * The method: charged-particle tracks are fitted and built with the Kalman filter,
+ * layer by layer, on symmetric 6x6 covariances, with search windows and candidate
+ * scores for building and radiation lengths of every layer for multiple scattering
+ * (paper, Sec. 2 and Sec. 3; window sizes and scores, Sec. 4.3).  The paper prints no
+ * formulas; the library implements the readings stated with each call below.
+ *
+ * Conventions for every call
+ *   - Array arguments are DEVICE pointers owned by the caller, float32 structure of
+ *     arrays ("[A][B][n]" means element (a, b, i) is at (a * B + b) * n + i).
+ *   - Track state (x, y, z, kappa = q/pT, phi, theta) in cm, 1/GeV, rad; the field is
+ *     uniform along +z; omega = -0.299792458e-2 * B * kappa is the signed turning rate
+ *     per unit transverse arc length.
+ *   - Covariances are packed lower triangles: element (i >= j) at i * (i + 1) / 2 + j.
+ *   - Layer L is an infinite cylinder of radius radius_cm[L]; its alignment
+ *     align[L] = (dx, dy, dz, dphi) moves its axis to (dx, dy), shifts its hits by dz
+ *     and rotates them by dphi about the axis.  Hits are given in the nominal frame.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream) and
+ *     never synchronise.  The library allocates no device memory per call: scratch
+ *     space is the caller's `ws` of at least kf_workspace_size() bytes, 256-byte
+ *     aligned.  Host-detectable errors return a negative KF_E_* code before anything
+ *     is launched; numerical outcomes are reported per track in `status` bits.
+ *   - Outputs are bit-deterministic for given inputs.
+ */
+#ifndef KF_H_
+#define KF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KF_MAX_LAYERS 32
+#define KF_MAX_KEEP 8
+
+/* return codes */
+#define KF_OK 0
+#define KF_E_INVALID (-1)     /* bad argument (null pointer, size, range) */
+#define KF_E_UNSUPPORTED (-2) /* valid request the library does not implement */
+#define KF_E_WORKSPACE (-3)   /* workspace missing, too small or misaligned */
+#define KF_E_HIP (-4)         /* the HIP runtime reported an error at launch */
+
+/* per-track status bits */
+#define KF_ST_PROP_FAIL 1u     /* the helix does not reach a layer it must cross; the fit stops there */
+#define KF_ST_NEAR_TANGENT 2u  /* some crossing had |cos alpha| < 0.3 (alpha: track vs layer normal) */
+#define KF_ST_FP64_FALLBACK 4u /* S failed the FP32 condition check: S^-1 and chi2 were done in FP64 */
+#define KF_ST_NONFINITE 8u     /* a non-finite value appeared */
+#define KF_ST_BAD_INPUT 16u    /* hit mask lacks the seed layers */
+#define KF_ST_TERM_MISSES 32u  /* finder: candidate stopped after max_miss missing layers */
+
+/* operations for kf_workspace_size */
+#define KF_OP_FIT 1
+#define KF_OP_FIND 2
+#define KF_OP_FIT_BACKWARD 3
+
+/* Detector and hit model, copied into the context at creation (host struct). */
+typedef struct kf_geometry {
+  int32_t n_layers;              /* 3 .. KF_MAX_LAYERS */
+  float B_tesla;                 /* uniform field along +z; 0 allowed with external seeds */
+  float radius_cm[KF_MAX_LAYERS];  /* strictly increasing, > 0 */
+  float zhalf_cm[KF_MAX_LAYERS];   /* z range [-Z, Z] of the finder's z bins (> 0) */
+  float sigma_rphi_cm;           /* hit resolution along the layer (r*phi) */
+  float sigma_z_cm;              /* hit resolution along z */
+  float sigma_r_cm;              /* radial regulariser of the 3-D hit (its row of H is zero) */
+  float mass_gev;                /* particle mass in the Highland beta */
+  int32_t n_phi_bins;            /* finder bins in phi over [-pi, pi): 1 .. 1024 */
+  int32_t n_z_bins;              /* finder bins in z over [-Z, Z]: 1 .. 256 */
+} kf_geometry;
+
+typedef struct kf_ctx kf_ctx;
+
+/* Per-layer parameters (device pointers, may be NULL = all zero): align [L][4], xX0 [L]
+ * radiation lengths of one crossing at normal incidence. */
+typedef struct kf_layer_params {
+  const float* align;
+  const float* xX0;
+} kf_layer_params;
+
+/* Fit input.  hits [L][3][n]; hit_mask [n] (bit L = a hit on layer L).
+ * seed_from_hits != 0: each seed is the helix through the (aligned) hits on layers
+ * 0, 1, 2 (needs mask bits 0-2) with a diagonal prior covariance inflated ten times
+ * in variance.  Otherwise seed_state [6][n] and seed_cov [21][n] are used; the seed's
+ * position must lie on layer 0's surface (the layer-0 update does not propagate). */
+typedef struct kf_fit_in {
+  int64_t n;
+  const float* hits;
+  const uint32_t* hit_mask;
+  const float* seed_state;
+  const float* seed_cov;
+  int32_t seed_from_hits;
+} kf_fit_in;
+
+/* Fit output: state [6][n], cov [21][n], chi2 [n], ndf [n] = 2 * n_hits - 5,
+ * status [n]; ckpt (optional, required by kf_fit_backward) [L][27][n] holds the state
+ * and covariance after each processed layer. */
+typedef struct kf_fit_out {
+  float* state;
+  float* cov;
+  float* chi2;
+  int32_t* ndf;
+  uint32_t* status;
+  float* ckpt;
+} kf_fit_out;
+
+/* Finder input.  Events' hits in one array hits [3][H]; hit_off [n_events][L+1]:
+ * hits of event e on layer L are hit_off[e][L] .. hit_off[e][L+1]-1.  Seeds are hit
+ * triplets on layers 0, 1, 2: seed_hits [3][n_seeds] global hit indices, seed_event
+ * [n_seeds].  Seeds of one event should be contiguous for locality (not required). */
+typedef struct kf_find_in {
+  int32_t n_events;
+  const int64_t* hit_off;
+  int64_t n_hits;
+  const float* hits;
+  int64_t n_seeds;
+  const int32_t* seed_event;
+  const int32_t* seed_hits;
+  float chi2_cut;   /* a hit joins a candidate if its chi2 < chi2_cut */
+  float nsigma;     /* window half widths: nsigma * sqrt(S) in r*phi and z */
+  int32_t keep;     /* candidates kept per seed, 1 .. KF_MAX_KEEP */
+  int32_t max_miss; /* a candidate stops at its max_miss-th missing layer, >= 1 */
+  int32_t refit;    /* != 0: also fit the hits of each seed's best candidate (rf_*) */
+} kf_find_in;
+
+/* Finder output (slot k < keep, unused slots: hit_idx -2, counts 0, values 0):
+ * n_cand [S]; hit_idx [keep][L][S] global hit index, -1 missing layer, -2 not reached;
+ * n_hits, n_miss [keep][S]; chi2 [keep][S]; state [keep][6][S]; cov [keep][21][S];
+ * status [keep][S]; rf_* (only with refit): the fit of the rank-0 candidate's hits,
+ * seeded from its first three, as kf_fit_out. */
+typedef struct kf_find_out {
+  int32_t* n_cand;
+  int32_t* hit_idx;
+  int32_t* n_hits;
+  int32_t* n_miss;
+  float* chi2;
+  float* state;
+  float* cov;
+  uint32_t* status;
+  float* rf_state;
+  float* rf_cov;
+  float* rf_chi2;
+  int32_t* rf_ndf;
+  uint32_t* rf_status;
+} kf_find_out;
+
+/* Create / destroy a context (host only, no device work).  Returns KF_OK or
+ * KF_E_INVALID for an inconsistent geometry. */
+int kf_ctx_create(const kf_geometry* geom, kf_ctx** ctx);
+int kf_ctx_destroy(kf_ctx* ctx);
+
+/* Threshold on the determinant of the equilibrated S (unit diagonal) below which S^-1
+ * and chi2 are computed in FP64 (default 1e-2, i.e. condition numbers above ~300).
+ * A threshold > 1 forces the FP64 path for every update. */
+int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold);
+
+/* Workspace bytes needed by op (KF_OP_*) for the input `in` (a kf_fit_in or
+ * kf_find_in; for KF_OP_FIT_BACKWARD the kf_fit_in of the forward call). */
+int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes);
+
+/* Batched Kalman fit, one track per GPU lane.  For every track: seed at layer 0,
+ * update with hit 0, then for each later layer up to the last hit: propagate to the
+ * first forward crossing of the helix with the layer, C <- J C J^T + Q (fixed-arc
+ * transport Jacobian J, Highland multiple scattering Q of the layer's material at the
+ * crossing angle), and where the layer has a hit: S = H C H^T + V in the local
+ * cylindrical frame (H: the state's tangent line projected onto the layer), S^-1 by an
+ * equilibrated inverse with the FP64 fallback above, chi2, gain K = C H^T S^-1 and
+ * the Joseph-form update.  Paper: Sec. 2 (Kalman filter on 6x6 covariances), Sec. 3
+ * (geometry, material), Sec. 5 (the fitting step). */
+int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* out,
+           void* ws, size_t ws_bytes, void* stream);
+
+/* Combinatorial track finding (paper Sec. 2: seeds processed in batches; Sec. 4.3:
+ * search windows and candidate scores).  Hits are binned per event and layer into
+ * n_phi_bins x n_z_bins; every seed is refitted over its three hits, then for each
+ * layer 3 .. L-1 every live candidate is propagated, the hits inside its window
+ * (|dphi| <= nsigma sqrt(S_rphi)/rho, |dz| <= nsigma sqrt(S_z)) get a chi2 with the
+ * candidate's S^-1, hits with chi2 < chi2_cut and one missing-hit branch per
+ * candidate compete, and the best `keep` branches per seed survive, ranked by (more
+ * hits, smaller total chi2, parent rank, smaller hit index, missing-hit branch last).
+ * Survivors with a hit are updated.  A candidate stops at its max_miss-th missing
+ * layer or when propagation fails and is carried unchanged. */
+int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
+            void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of kf_fit (seed_from_hits must be 1 and ckpt filled by the forward call):
+ * given dchi2 [n] = dLoss/dchi2_i, accumulates dLoss/dalign [L][4] and dLoss/dxX0 [L]
+ * (overwritten, float32) by a reverse sweep over each track's layers that recomputes
+ * every step from its checkpoint.  The paper has no differentiation; this is the
+ * vector-Jacobian product of the fit as implemented by kf_fit. */
+int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+                    const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream);
+
+/* Static description of a return code. */
+const char* kf_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KF_H_ */

@@ -56,6 +56,10 @@ def load():
     return _lib
 
 
+def num_threads() -> int:
+    return int(load().oracle_num_threads())
+
+
 def ogeom(geom) -> OGeom:
     g = OGeom()
     g.n_layers = geom.n_layers

@@ -35,6 +35,8 @@
 // rotation leave the total chi2 unchanged.  Parity unpinned: the candidate score
 // and its tie rule, and the Highland variant, which are conventions.
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -612,6 +614,9 @@ Track<T> fit_track_i(const Geo& g, const Layer<T>* lay, const HT* hits, int64_t 
 // C entry points (called from Python through ctypes)
 // ==============================================================================
 extern "C" {
+
+// Threads the OpenMP loops of the batch entries use.
+int oracle_num_threads() { return omp_get_max_threads(); }
 
 // Crossing of one state with the cylinder |p - c| = r: writes the propagated state
 // and the transverse arc; returns 1 on success, 0 if the layer is not reached.

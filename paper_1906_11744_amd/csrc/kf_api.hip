@@ -1,0 +1,156 @@
+// C ABI of the library: argument validation, workspace layout and launches.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/kf.h"
+#include "kf_internal.h"
+
+struct kf_ctx {
+  kf_geometry g;
+  float det_thr;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+kfd::Model model_of(const kf_ctx* c) {
+  kfd::Model m;
+  m.kB = 0.299792458e-2f * c->g.B_tesla;
+  m.v_r = c->g.sigma_r_cm * c->g.sigma_r_cm;
+  m.v_rphi = c->g.sigma_rphi_cm * c->g.sigma_rphi_cm;
+  m.v_z = c->g.sigma_z_cm * c->g.sigma_z_cm;
+  m.mass2 = c->g.mass_gev * c->g.mass_gev;
+  m.det_thr = c->det_thr;
+  m.dr02 = c->g.radius_cm[2] - c->g.radius_cm[0];
+  return m;
+}
+
+bool valid_geometry(const kf_geometry* g) {
+  if (!g) return false;
+  if (g->n_layers < 3 || g->n_layers > KF_MAX_LAYERS) return false;
+  for (int l = 0; l < g->n_layers; ++l) {
+    if (!(g->radius_cm[l] > 0.f) || !(g->zhalf_cm[l] > 0.f)) return false;
+    if (l > 0 && !(g->radius_cm[l] > g->radius_cm[l - 1])) return false;
+  }
+  if (!(g->sigma_rphi_cm > 0.f) || !(g->sigma_z_cm > 0.f) || !(g->sigma_r_cm > 0.f)) return false;
+  if (!(g->mass_gev >= 0.f) || !isfinite(g->B_tesla)) return false;
+  if (g->n_phi_bins < 1 || g->n_phi_bins > 1024 || g->n_z_bins < 1 || g->n_z_bins > 256) return false;
+  return true;
+}
+
+// Workspace of a fit: the per-layer constants.
+size_t fit_ws_bytes() { return round_up(sizeof(kfd::LayerK) * KF_MAX_LAYERS); }
+
+int check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return KF_OK;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return KF_E_WORKSPACE;
+  return KF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_ctx_create(const kf_geometry* geom, kf_ctx** ctx) {
+  if (!ctx) return KF_E_INVALID;
+  *ctx = nullptr;
+  if (!valid_geometry(geom)) return KF_E_INVALID;
+  kf_ctx* c = new (std::nothrow) kf_ctx;
+  if (!c) return KF_E_INVALID;
+  c->g = *geom;
+  c->det_thr = 1e-2f;
+  *ctx = c;
+  return KF_OK;
+}
+
+int kf_ctx_destroy(kf_ctx* ctx) {
+  delete ctx;
+  return KF_OK;
+}
+
+int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold) {
+  if (!ctx || !(det_threshold >= 0.f) || !isfinite(det_threshold)) return KF_E_INVALID;
+  ctx->det_thr = det_threshold;
+  return KF_OK;
+}
+
+int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) {
+  if (!ctx || !in || !bytes) return KF_E_INVALID;
+  switch (op) {
+    case KF_OP_FIT:
+      *bytes = fit_ws_bytes();
+      return KF_OK;
+    default:
+      return KF_E_UNSUPPORTED;
+  }
+}
+
+int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* out, void* ws,
+           size_t ws_bytes, void* stream) {
+  if (!ctx || !in || !out) return KF_E_INVALID;
+  if (in->n < 0) return KF_E_INVALID;
+  if (in->n == 0) return KF_OK;
+  if (!in->hits || !in->hit_mask || !out->state || !out->cov || !out->chi2 || !out->ndf || !out->status)
+    return KF_E_INVALID;
+  if (!in->seed_from_hits && (!in->seed_state || !in->seed_cov)) return KF_E_INVALID;
+  if (in->seed_from_hits && !(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;  // no curvature from hits at B = 0
+  if (in->n > (int64_t)INT32_MAX * 256) return KF_E_INVALID;
+  int rc = check_ws(ws, ws_bytes, fit_ws_bytes());
+  if (rc != KF_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(ws);
+  const float* align = params ? params->align : nullptr;
+  const float* xX0 = params ? params->xX0 : nullptr;
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+    return KF_E_HIP;
+  kfi::FitArgs a;
+  a.n = in->n;
+  a.nl = ctx->g.n_layers;
+  a.seed_from_hits = in->seed_from_hits ? 1 : 0;
+  a.md = model_of(ctx);
+  a.srphi = ctx->g.sigma_rphi_cm;
+  a.sz = ctx->g.sigma_z_cm;
+  a.hits = in->hits;
+  a.mask = in->hit_mask;
+  a.seed_state = in->seed_state;
+  a.seed_cov = in->seed_cov;
+  a.layers = layers;
+  a.state = out->state;
+  a.cov = out->cov;
+  a.chi2 = out->chi2;
+  a.ndf = out->ndf;
+  a.status = out->status;
+  a.ckpt = out->ckpt;
+  return kfi::launch_fit(a, st) == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out, void* ws,
+            size_t ws_bytes, void* stream) {
+  (void)ctx; (void)params; (void)in; (void)out; (void)ws; (void)ws_bytes; (void)stream;
+  return KF_E_UNSUPPORTED;
+}
+
+int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+                    const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream) {
+  (void)ctx; (void)params; (void)in; (void)fwd; (void)dchi2; (void)dalign; (void)dxX0; (void)ws; (void)ws_bytes;
+  (void)stream;
+  return KF_E_UNSUPPORTED;
+}
+
+const char* kf_strerror(int code) {
+  switch (code) {
+    case KF_OK: return "ok";
+    case KF_E_INVALID: return "invalid argument";
+    case KF_E_UNSUPPORTED: return "unsupported request";
+    case KF_E_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case KF_E_HIP: return "HIP runtime error at launch";
+    default: return "unknown error code";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,389 @@
+// Device-side Kalman step for gfx950: one track candidate per lane, state and packed
+// covariance in VGPRs, FP32 arithmetic (FP64 only for an ill-conditioned S).
+//
+// The paper (Sec. 2) vectorises the 6x6 covariance algebra across tracks and skips
+// matrix elements known to be 0 or 1.  Here every product is written out with those
+// zeros removed at compile time: the transport Jacobian has six off-diagonal terms,
+// the measurement matrix touches only the position columns and its radial row is zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kfd {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+
+constexpr uint32_t ST_PROP_FAIL = 1u, ST_NEAR_TANGENT = 2u, ST_FP64 = 4u, ST_NONFINITE = 8u,
+                   ST_BAD_INPUT = 16u, ST_TERM_MISSES = 32u;
+
+// packed lower-triangular index
+__host__ __device__ constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+// Per-layer constants of one launch (uniform across lanes).
+struct LayerK {
+  float r, cx, cy, dz, cphi, sphi, xX0, pad;
+};
+
+// Constants of the hit model and the field.
+struct Model {
+  float kB;        // 0.299792458e-2 * B
+  float v_r, v_rphi, v_z;  // hit variances (radial regulariser, r*phi, z)
+  float mass2;     // particle mass squared
+  float det_thr;   // FP64 fallback threshold on det of the equilibrated S (> 1 forces)
+  float dr02;      // radius[2] - radius[0], for the seed prior
+};
+
+// A track candidate: state, covariance and the carried trigonometry of phi and theta.
+struct Trk {
+  float x[6];   // x y z kappa phi theta
+  float C[21];
+  float cp, sp; // cos, sin of phi
+  float ct, st; // cos, sin of theta
+};
+
+__device__ __forceinline__ float wrap_pi(float a) {
+  if (a > kPi) a -= kTwoPi;
+  if (a <= -kPi) a += kTwoPi;
+  return a;
+}
+
+// cos/sin of x[4], x[5] from scratch.
+__device__ __forceinline__ void init_trig(Trk& t) {
+  sincosf(t.x[4], &t.sp, &t.cp);
+  sincosf(t.x[5], &t.st, &t.ct);
+}
+
+// Rotate (c, s) = (cos a, sin a) to a + d; small d by its Taylor series, otherwise
+// exactly from the new angle.
+__device__ __forceinline__ void rotate_small(float& c, float& s, float d, float anew) {
+  if (fabsf(d) < 0.03f) {
+    const float d2 = d * d;
+    const float cd = 1.f - d2 * (0.5f - d2 * (1.f / 24.f));
+    const float sd = d * (1.f - d2 * (1.f / 6.f - d2 * (1.f / 120.f)));
+    const float c2 = c * cd - s * sd;
+    const float s2 = s * cd + c * sd;
+    c = c2;
+    s = s2;
+  } else {
+    sincosf(anew, &s, &c);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// propagation to the first forward crossing with a cylinder, and the transport
+// Jacobian at fixed transverse arc applied to C (C <- J C J^T).
+//
+// With p0 = (x, y) - c, a = p0.t, b = p0.n, c0 = |p0|^2 - r^2 and the tangent half
+// angle tau = tan(u/2) = omega * sigma, |p(s)|^2 = r^2 becomes the quadratic
+// A sigma^2 + 2 a sigma + c0/2 = 0 with A = 2 + 2 omega b + omega^2 c0 / 2; its
+// stable positive root is sigma = -c0 / (2 (a + sqrt(a^2 - A c0 / 2))).  Then
+// s = 2 atan(tau) / omega, displacement 2 sigma / (1 + tau^2) (t + tau n), phi += u.
+// ---------------------------------------------------------------------------------
+struct Step {
+  float s;      // transverse arc
+  float tau;    // tan(u/2)
+  float dx, dy; // transverse displacement
+  float u;      // turning angle
+};
+
+__device__ __forceinline__ bool crossing(const Trk& k, const LayerK& ly, float kB, Step& st) {
+  const float ex = k.x[0] - ly.cx, ey = k.x[1] - ly.cy;
+  const float a = fmaf(ex, k.cp, ey * k.sp);
+  const float b = fmaf(ey, k.cp, -ex * k.sp);
+  const float c0 = fmaf(ex, ex, fmaf(ey, ey, -ly.r * ly.r));
+  const float w = -kB * k.x[3];
+  const float A = fmaf(2.f * w, b, fmaf(0.5f * w * w, c0, 2.f));
+  const float D = fmaf(a, a, -0.5f * A * c0);
+  if (!(c0 < 0.f) || !(D >= 0.f)) return false;
+  const float den = a + sqrtf(D);
+  if (!(den > 0.f)) return false;
+  const float sig = -c0 / (2.f * den);
+  const float tau = w * sig;
+  const float tau2 = tau * tau;
+  // atan(tau)/tau, exact at tau = 0
+  const float q = fabsf(tau) < 1e-2f ? fmaf(tau2, fmaf(tau2, 0.2f, -1.f / 3.f), 1.f) : atanf(tau) / tau;
+  const float f = 2.f * sig / (1.f + tau2);
+  st.s = 2.f * sig * q;
+  st.u = 2.f * tau * q;
+  st.tau = tau;
+  st.dx = f * fmaf(-tau, k.sp, k.cp);
+  st.dy = f * fmaf(tau, k.cp, k.sp);
+  return true;
+}
+
+// Moves k along the step and transports its covariance with the fixed-arc Jacobian
+// J = I + {d(x,y)/dphi, d(x,y)/dkappa, dz/dtheta, dphi/dkappa}.
+__device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
+  const float s = st.s, u = st.u;
+  float F1, F2;  // d(displacement)/d(omega) = s^2 (F1 t + F2 n)
+  const float tau2 = st.tau * st.tau;
+  const float inv1 = 1.f / (1.f + tau2);
+  const float cu = (1.f - tau2) * inv1, su = 2.f * st.tau * inv1;
+  if (fabsf(u) < 0.3f) {
+    const float u2 = u * u;
+    F1 = u * fmaf(u2, fmaf(u2, -1.f / 840.f, 1.f / 30.f), -1.f / 3.f);
+    F2 = fmaf(u2, fmaf(u2, fmaf(u2, -1.f / 5760.f, 1.f / 144.f), -0.125f), 0.5f);
+  } else {
+    const float iu2 = 1.f / (u * u);
+    F1 = fmaf(u, cu, -su) * iu2;
+    F2 = fmaf(u, su, -2.f * tau2 * inv1) * iu2;
+  }
+  const float ks2 = -kB * s * s;
+  const float rst = 1.f / k.st;
+  const float a04 = -st.dy, a14 = st.dx;
+  const float a03 = ks2 * fmaf(F1, k.cp, -F2 * k.sp);
+  const float a13 = ks2 * fmaf(F1, k.sp, F2 * k.cp);
+  const float a25 = -s * rst * rst;
+  const float a43 = -kB * s;
+  float* C = k.C;
+#define CC(i, j) C[tri(i, j)]
+  // B = J C (rows 0, 1, 2, 4 change)
+  float B0[6], B1[6], B2[6], B4[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    B0[j] = fmaf(a03, CC(3, j), fmaf(a04, CC(4, j), CC(0, j)));
+    B1[j] = fmaf(a13, CC(3, j), fmaf(a14, CC(4, j), CC(1, j)));
+    B2[j] = fmaf(a25, CC(5, j), CC(2, j));
+    B4[j] = fmaf(a43, CC(3, j), CC(4, j));
+  }
+  // C' = B J^T, lower triangle; column j of J^T adds a_jk B[i][k]
+  float R[21];
+  auto Brow = [&](int i, int j) -> float {
+    return i == 0 ? B0[j] : i == 1 ? B1[j] : i == 2 ? B2[j] : i == 4 ? B4[j] : CC(i, j);
+  };
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    R[tri(i, 0)] = fmaf(a03, Brow(i, 3), fmaf(a04, Brow(i, 4), Brow(i, 0)));
+    if (i >= 1) R[tri(i, 1)] = fmaf(a13, Brow(i, 3), fmaf(a14, Brow(i, 4), Brow(i, 1)));
+    if (i >= 2) R[tri(i, 2)] = fmaf(a25, Brow(i, 5), Brow(i, 2));
+    if (i >= 3) R[tri(i, 3)] = Brow(i, 3);
+    if (i >= 4) R[tri(i, 4)] = fmaf(a43, Brow(i, 3), Brow(i, 4));
+    if (i >= 5) R[tri(i, 5)] = Brow(i, 5);
+  }
+#undef CC
+#pragma unroll
+  for (int q = 0; q < 21; ++q) C[q] = R[q];
+  // state
+  k.x[0] += st.dx;
+  k.x[1] += st.dy;
+  k.x[2] = fmaf(s * k.ct, rst, k.x[2]);
+  k.x[4] = wrap_pi(k.x[4] + u);
+  const float cp = k.cp * cu - k.sp * su;
+  const float sp = k.sp * cu + k.cp * su;
+  const float nrm = rsqrtf(fmaf(cp, cp, sp * sp));
+  k.cp = cp * nrm;
+  k.sp = sp * nrm;
+}
+
+// ---------------------------------------------------------------------------------
+// local cylindrical frame at the prediction and the measurement model
+// ---------------------------------------------------------------------------------
+struct Frame {
+  float rho, rx, ry;  // radius about the layer axis and radial unit vector
+  float cosa;         // r_hat . t
+};
+
+__device__ __forceinline__ Frame frame_at(const Trk& k, const LayerK& ly) {
+  Frame f;
+  const float ex = k.x[0] - ly.cx, ey = k.x[1] - ly.cy;
+  const float r2 = fmaf(ex, ex, ey * ey);
+  const float ir = rsqrtf(r2);
+  f.rho = r2 * ir;
+  f.rx = ex * ir;
+  f.ry = ey * ir;
+  f.cosa = fmaf(f.rx, k.cp, f.ry * k.sp);
+  return f;
+}
+
+// Highland multiple scattering of a thin layer, added to (kappa, phi, theta):
+// theta0^2 = (0.0136/(beta p))^2 x (1 + 0.038 ln x)^2, x = xX0 / (sin(theta) |cos alpha|),
+// 1/(beta p) = |kappa| sin(theta) sqrt(1 + m^2 kappa^2 sin^2(theta)).
+__device__ __forceinline__ void add_scattering(Trk& k, const Frame& f, float xX0, float mass2) {
+  const float kap = k.x[3];
+  const float ks = kap * k.st;
+  const float ks2 = ks * ks;
+  const float xe = xX0 / (k.st * fabsf(f.cosa));
+  const float lg = fmaf(0.038f, __logf(xe), 1.f);
+  const float th2 = 0.0136f * 0.0136f * ks2 * fmaf(mass2, ks2, 1.f) * xe * lg * lg;
+  const float rst = 1.f / k.st;
+  const float cot = k.ct * rst;
+  const float kc = kap * cot;
+  k.C[tri(4, 4)] = fmaf(th2 * rst, rst, k.C[tri(4, 4)]);
+  k.C[tri(5, 5)] += th2;
+  k.C[tri(3, 3)] = fmaf(kc * kc, th2, k.C[tri(3, 3)]);
+  k.C[tri(5, 3)] = fmaf(-kc, th2, k.C[tri(5, 3)]);
+}
+
+// What a prediction needs for every hit of a layer: the projection rows
+// h1 = phi_hat - tan(alpha) r_hat, h2 = (-cot(theta)/cos(alpha) r_hat, 1), the
+// products HC (rows 1, 2 of H C) and S^-1 (S = H C H^T + V is block diagonal: its
+// radial entry is the regulariser alone).
+struct Pred {
+  float h1x, h1y, h2x, h2y;
+  float HC1[6], HC2[6];
+  float S11, S12, S22;
+  float Si00, Si11, Si12, Si22;
+  bool fp64;
+  double dSi11, dSi12, dSi22;
+};
+
+__device__ __forceinline__ void prepare(const Trk& k, const Frame& f, const Model& md, Pred& p) {
+  const float fx = -f.ry, fy = f.rx;
+  const float ica = 1.f / f.cosa;
+  const float tana = fmaf(fx, k.cp, fy * k.sp) * ica;
+  const float cot = k.ct / k.st;
+  p.h1x = fmaf(-tana, f.rx, fx);
+  p.h1y = fmaf(-tana, f.ry, fy);
+  const float g = -cot * ica;
+  p.h2x = g * f.rx;
+  p.h2y = g * f.ry;
+  const float* C = k.C;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    p.HC1[j] = fmaf(p.h1x, C[tri(0, j)], p.h1y * C[tri(1, j)]);
+    p.HC2[j] = fmaf(p.h2x, C[tri(0, j)], fmaf(p.h2y, C[tri(1, j)], C[tri(2, j)]));
+  }
+  p.S11 = fmaf(p.HC1[0], p.h1x, fmaf(p.HC1[1], p.h1y, md.v_rphi));
+  p.S12 = fmaf(p.HC1[0], p.h2x, fmaf(p.HC1[1], p.h2y, p.HC1[2]));
+  p.S22 = fmaf(p.HC2[0], p.h2x, fmaf(p.HC2[1], p.h2y, p.HC2[2] + md.v_z));
+  // equilibrated inverse: S~ = D^-1/2 S D^-1/2 has unit diagonal; its radial row is
+  // (1, 0, 0), so det S~ = 1 - rho12^2.
+  p.Si00 = 1.f / md.v_r;
+  const float d1 = rsqrtf(p.S11), d2 = rsqrtf(p.S22);
+  const float r12 = p.S12 * d1 * d2;
+  const float det = fmaf(-r12, r12, 1.f);
+  const bool good = p.S11 > 0.f && p.S22 > 0.f && det >= md.det_thr && md.det_thr <= 1.f &&
+                    isfinite(det);
+  p.fp64 = !good;
+  if (good) {
+    const float idet = 1.f / det;
+    p.Si11 = d1 * d1 * idet;
+    p.Si22 = d2 * d2 * idet;
+    p.Si12 = -r12 * d1 * d2 * idet;
+  } else {
+    const double s11 = p.S11, s12 = p.S12, s22 = p.S22;
+    const double dd = s11 * s22 - s12 * s12;
+    p.dSi11 = s22 / dd;
+    p.dSi22 = s11 / dd;
+    p.dSi12 = -s12 / dd;
+    p.Si11 = (float)p.dSi11;
+    p.Si22 = (float)p.dSi22;
+    p.Si12 = (float)p.dSi12;
+  }
+}
+
+// Residual of a placed hit m in the prediction's frame: (rho_m - rho_p,
+// rho_p * angle(r_hat, m - c), z_m - z_p), and its chi2.
+struct Resid {
+  float r0, r1, r2, chi2;
+};
+
+__device__ __forceinline__ Resid residual(const Trk& k, const Frame& f, const LayerK& ly, const Pred& p, float mx,
+                                          float my, float mz) {
+  Resid r;
+  const float dx = mx - ly.cx, dy = my - ly.cy;
+  const float rm = sqrtf(fmaf(dx, dx, dy * dy));
+  const float cr = fmaf(f.rx, dy, -f.ry * dx);
+  const float dt = fmaf(f.rx, dx, f.ry * dy);
+  r.r0 = rm - f.rho;
+  r.r1 = f.rho * atan2f(cr, dt);
+  r.r2 = mz - k.x[2];
+  if (!p.fp64) {
+    const float q = fmaf(r.r1 * r.r1, p.Si11, fmaf(2.f * r.r1 * r.r2, p.Si12, r.r2 * r.r2 * p.Si22));
+    r.chi2 = fmaf(r.r0 * r.r0, p.Si00, q);
+  } else {
+    const double a = r.r1, b = r.r2;
+    const double q = a * a * p.dSi11 + 2.0 * a * b * p.dSi12 + b * b * p.dSi22;
+    r.chi2 = (float)(q + (double)r.r0 * r.r0 * (double)p.Si00);
+  }
+  r.chi2 = fmaxf(r.chi2, 0.f);
+  return r;
+}
+
+// Gain and Joseph-form update: K = C H^T S^-1 (its radial column is zero),
+// x += K r, C <- (I - K H) C (I - K H)^T + K V K^T.  With M = (I - K H) C =
+// C - K (H C) and v_a = M h_a^T, C' = M - (v_1 k_1^T + v_2 k_2^T) + K V K^T, lower
+// triangle only.
+__device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model& md, float r1, float r2) {
+  float K1[6], K2[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    K1[i] = fmaf(p.HC1[i], p.Si11, p.HC2[i] * p.Si12);
+    K2[i] = fmaf(p.HC1[i], p.Si12, p.HC2[i] * p.Si22);
+  }
+  const float dphi = fmaf(K1[4], r1, K2[4] * r2);
+  const float dth = fmaf(K1[5], r1, K2[5] * r2);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) k.x[i] = fmaf(K1[i], r1, fmaf(K2[i], r2, k.x[i]));
+  const float phin = wrap_pi(k.x[4]);
+  k.x[4] = phin;
+  rotate_small(k.cp, k.sp, dphi, phin);
+  rotate_small(k.ct, k.st, dth, k.x[5]);
+  float* C = k.C;
+  // M[i][j] for the lower triangle and for columns 0..2 of every row
+  float M[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j <= i || j < 3) M[i][j] = fmaf(-K1[i], p.HC1[j], fmaf(-K2[i], p.HC2[j], C[tri(i, j)]));
+  float w1[6], w2[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float v1 = fmaf(M[i][0], p.h1x, M[i][1] * p.h1y);
+    const float v2 = fmaf(M[i][0], p.h2x, fmaf(M[i][1], p.h2y, M[i][2]));
+    w1[i] = fmaf(md.v_rphi, K1[i], -v1);
+    w2[i] = fmaf(md.v_z, K2[i], -v2);
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) C[tri(i, j)] = fmaf(K1[j], w1[i], fmaf(K2[j], w2[i], M[i][j]));
+}
+
+// Place a nominal-frame hit on its (aligned) layer.
+__device__ __forceinline__ void place(const LayerK& ly, float hx, float hy, float hz, float& mx, float& my,
+                                      float& mz) {
+  mx = ly.cx + fmaf(ly.cphi, hx, -ly.sphi * hy);
+  my = ly.cy + fmaf(ly.sphi, hx, ly.cphi * hy);
+  mz = hz + ly.dz;
+}
+
+// Seed: the helix through three placed hits (signed Menger curvature, chord angles),
+// at the first hit, with the diagonal prior inflated ten times in variance.
+__device__ __forceinline__ void seed_from_three(Trk& k, const Model& md, float x0, float y0, float z0, float x1,
+                                                float y1, float x2, float y2, float z2, float srphi, float sz) {
+  const float ax = x1 - x0, ay = y1 - y0;
+  const float bx = x2 - x1, by = y2 - y1;
+  const float cx = x2 - x0, cy = y2 - y0;
+  const float la = sqrtf(fmaf(ax, ax, ay * ay));
+  const float lb = sqrtf(fmaf(bx, bx, by * by));
+  const float lc = sqrtf(fmaf(cx, cx, cy * cy));
+  const float w = 2.f * fmaf(ax, by, -ay * bx) / (la * lb * lc);
+  const float qa = fminf(fmaxf(0.5f * w * la, -1.f), 1.f);
+  const float qc = fminf(fmaxf(0.5f * w * lc, -1.f), 1.f);
+  const float phi0 = atan2f(ay, ax) - asinf(qa);
+  const float qc2 = qc * qc;
+  const float arc = fabsf(qc) < 1e-2f ? lc * fmaf(qc2, fmaf(qc2, 0.075f, 1.f / 6.f), 1.f) : lc * asinf(qc) / qc;
+  k.x[0] = x0;
+  k.x[1] = y0;
+  k.x[2] = z0;
+  k.x[3] = -w / md.kB;
+  k.x[4] = wrap_pi(phi0);
+  k.x[5] = atan2f(arc, z2 - z0);
+  const float dr = md.dr02;
+  const float sphi = 1.41421356237f * srphi / dr, sth = 1.41421356237f * sz / dr;
+  const float skap = 8.f * 1.22474487139f * srphi / (dr * dr * md.kB);
+#pragma unroll
+  for (int q = 0; q < 21; ++q) k.C[q] = 0.f;
+  k.C[tri(0, 0)] = 10.f * srphi * srphi;
+  k.C[tri(1, 1)] = 10.f * srphi * srphi;
+  k.C[tri(2, 2)] = 10.f * sz * sz;
+  k.C[tri(3, 3)] = 10.f * skap * skap;
+  k.C[tri(4, 4)] = 10.f * sphi * sphi;
+  k.C[tri(5, 5)] = 10.f * sth * sth;
+}
+
+}  // namespace kfd

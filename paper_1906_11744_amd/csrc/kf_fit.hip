@@ -1,0 +1,126 @@
+// Batched Kalman fit: one track per lane, the whole layer loop in registers.
+#include "kf_internal.h"
+
+namespace kfi {
+
+struct Radii {
+  float r[32];
+};
+
+__global__ void layer_prep_kernel(int nl, Radii rad, const float* __restrict__ align, const float* __restrict__ xX0,
+                                  kfd::LayerK* __restrict__ out) {
+  const int l = threadIdx.x;
+  if (l >= nl) return;
+  kfd::LayerK k;
+  k.r = rad.r[l];
+  k.cx = align ? align[4 * l + 0] : 0.f;
+  k.cy = align ? align[4 * l + 1] : 0.f;
+  k.dz = align ? align[4 * l + 2] : 0.f;
+  const float dphi = align ? align[4 * l + 3] : 0.f;
+  sincosf(dphi, &k.sphi, &k.cphi);
+  k.xX0 = xX0 ? xX0[l] : 0.f;
+  k.pad = 0.f;
+  out[l] = k;
+}
+
+hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
+                             kfd::LayerK* out, hipStream_t stream) {
+  Radii rad;
+  for (int l = 0; l < 32; ++l) rad.r[l] = l < nl ? radius_host[l] : 0.f;
+  hipLaunchKernelGGL(layer_prep_kernel, dim3(1), dim3(32), 0, stream, nl, rad, align, xX0, out);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ void store_ckpt(float* ck, int64_t n, int64_t i, int l, const kfd::Trk& k) {
+  float* p = ck + (int64_t)l * 27 * n + i;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) p[q * n] = k.x[q];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) p[(6 + q) * n] = k.C[q];
+}
+
+__global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t n = a.n;
+  const uint32_t mask = a.mask[i];
+  const uint32_t need = a.seed_from_hits ? 7u : 1u;
+  uint32_t status = 0;
+  kfd::Trk k;
+  float chi2 = 0.f;
+  int nh = 0;
+  const kfd::LayerK* __restrict__ lays = a.layers;
+  auto hit = [&](int l, float& mx, float& my, float& mz) {
+    const float* h = a.hits + (int64_t)l * 3 * n + i;
+    kfd::place(lays[l], h[0], h[n], h[2 * n], mx, my, mz);
+  };
+  if ((mask & need) != need) {
+    status = kfd::ST_BAD_INPUT;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) k.x[q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) k.C[q] = 0.f;
+  } else {
+    float m0x, m0y, m0z;
+    hit(0, m0x, m0y, m0z);
+    if (a.seed_from_hits) {
+      float m1x, m1y, m1z, m2x, m2y, m2z;
+      hit(1, m1x, m1y, m1z);
+      hit(2, m2x, m2y, m2z);
+      kfd::seed_from_three(k, a.md, m0x, m0y, m0z, m1x, m1y, m2x, m2y, m2z, a.srphi, a.sz);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) k.x[q] = a.seed_state[q * n + i];
+#pragma unroll
+      for (int q = 0; q < 21; ++q) k.C[q] = a.seed_cov[q * n + i];
+    }
+    kfd::init_trig(k);
+    int last = 31 - __builtin_clz(mask);
+    if (last > a.nl - 1) last = a.nl - 1;
+    for (int l = 0; l <= last; ++l) {
+      const kfd::LayerK ly = lays[l];
+      if (l > 0) {
+        kfd::Step st;
+        if (!kfd::crossing(k, ly, a.md.kB, st)) {
+          status |= kfd::ST_PROP_FAIL;
+          break;
+        }
+        kfd::transport(k, st, a.md.kB);
+      }
+      const kfd::Frame f = kfd::frame_at(k, ly);
+      if (l > 0 && ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+      if ((mask >> l) & 1u) {
+        if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
+        kfd::Pred p;
+        kfd::prepare(k, f, a.md, p);
+        if (p.fp64) status |= kfd::ST_FP64;
+        float mx, my, mz;
+        hit(l, mx, my, mz);
+        const kfd::Resid r = kfd::residual(k, f, ly, p, mx, my, mz);
+        kfd::apply_update(k, p, a.md, r.r1, r.r2);
+        chi2 += r.chi2;
+        ++nh;
+      }
+      if (a.ckpt) store_ckpt(a.ckpt, n, i, l, k);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      if (!isfinite(k.x[q])) status |= kfd::ST_NONFINITE;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) a.state[q * n + i] = k.x[q];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) a.cov[q * n + i] = k.C[q];
+  a.chi2[i] = chi2;
+  a.ndf[i] = 2 * nh - 5;
+  a.status[i] = status;
+}
+
+hipError_t launch_fit(const FitArgs& a, hipStream_t stream) {
+  const int bs = 256;
+  const int64_t nb = (a.n + bs - 1) / bs;
+  hipLaunchKernelGGL(fit_kernel, dim3((unsigned)nb), dim3(bs), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace kfi

@@ -1,0 +1,74 @@
+"""The C ABI without a GPU: the library loads, exports what include/kf.h declares, and
+host-side validation returns the documented codes before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1906_11744_amd import kf
+    return kf, kf._lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "kf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(kf_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_three_calls():
+    names = declared_functions()
+    for n in ("kf_fit", "kf_find", "kf_fit_backward", "kf_ctx_create", "kf_workspace_size", "kf_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    kf, lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(kf.exported_symbols()) == declared_functions()
+
+
+def test_context_validation():
+    kf, lib = _lib()
+    geom = synth.workload_geometry(2)
+    ctx = kf.Context(geom)
+    assert ctx.n_layers == 17
+    ctx.set_fallback_threshold(0.5)
+    with pytest.raises(kf.KfError):
+        ctx.set_fallback_threshold(-1.0)
+    bad = synth.workload_geometry(2)
+    bad.radius = bad.radius[::-1].copy()
+    with pytest.raises(kf.KfError) as e:
+        kf.Context(bad)
+    assert e.value.code == -1
+    g = kf.Geometry()
+    g.n_layers = 40
+    h = C.c_void_p()
+    assert lib.kf_ctx_create(C.byref(g), C.byref(h)) == -1
+
+
+def test_host_side_errors_before_launch():
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    fin = kf.FitIn(0, None, None, None, None, 1)
+    fo = kf.FitOut()
+    p = kf.LayerParams()
+    # empty batch: nothing to do
+    assert lib.kf_fit(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == 0
+    # missing arrays
+    fin = kf.FitIn(10, None, None, None, None, 1)
+    assert lib.kf_fit(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -1
+    fin = kf.FitIn(-1, None, None, None, None, 1)
+    assert lib.kf_fit(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -1
+    nb = C.c_size_t(0)
+    assert lib.kf_workspace_size(ctx._h, kf.KF_OP_FIT, C.byref(fin), C.byref(nb)) == 0
+    assert nb.value >= 256
+    assert lib.kf_workspace_size(ctx._h, 99, C.byref(fin), C.byref(nb)) == -2
+    assert lib.kf_strerror(-3).decode().startswith("workspace")

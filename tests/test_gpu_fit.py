@@ -1,0 +1,236 @@
+"""GPU kf_fit (through the C ABI) against the FP64 oracle.
+
+Tolerances (float32 path vs float64 oracle), tracks without KF_ST_NEAR_TANGENT:
+  state: |d| / max(|p|, floor) < 1e-4 (floors 1 cm for x, y, z and 1 rad for phi,
+         theta; none for kappa);
+  cov:   |dC_ij| / sqrt(C_ii C_jj) < 1e-4;
+  chi2:  |d chi2| < 0.05 + 1e-4 chi2 (total over the track);
+  ndf and the PROP_FAIL / BAD_INPUT status bits: exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import cov_err, mask_dev, need_gpu, rel_state_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_STATE = 1e-4
+TOL_COV = 1e-4
+
+
+def _ctx(geom):
+    from paper_1906_11744_amd import Context
+    return Context(geom)
+
+
+def _grazing(geom, ref, i, m, align=None):
+    """FP64 margin of the crossing with layer m attempted from the oracle's filtered
+    state at layer m - 1 (track i): the helix circle reaches at most
+    |centre - axis| + R from the layer axis; a relative margin below 1e-4 makes
+    reach / no-reach an FP32-sensitive decision."""
+    if m < 1 or m >= geom.n_layers:
+        return False
+    x = ref["records"][i][m - 1, :6]
+    if not np.isfinite(x[0]):
+        return False
+    c = np.zeros(2) if align is None else np.asarray(align)[m, :2]
+    w = -geom.k_B * x[3]
+    R = 1.0 / abs(w)
+    cc = np.array([x[0] - np.sin(x[4]) / w, x[1] + np.cos(x[4]) / w]) - c
+    margin = (np.hypot(*cc) + R - geom.radius[m]) / geom.radius[m]
+    return abs(margin) < 1e-4
+
+
+def _compare(geom, hits, mask, out, ref, label, idx=None, tol_cov=None, align=None):
+    st = out["state"].cpu().numpy()
+    cv = out["cov"].cpu().numpy()
+    c2 = out["chi2"].cpu().numpy()
+    ndf = out["ndf"].cpu().numpy()
+    status = out["status"].cpu().numpy().view(np.uint32)
+    if idx is not None:
+        st, cv, c2, ndf, status = st[:, idx], cv[:, idx], c2[idx], ndf[idx], status[idx]
+    np.testing.assert_array_equal(status & oracle.ST_BAD_INPUT, ref["status"] & oracle.ST_BAD_INPUT,
+                                  err_msg=label)
+    # Reach / no-reach of a layer is exact except for helices that graze it (FP64 margin
+    # below 1e-4 of the radius); those tracks are counted and excluded.
+    pf = (status & oracle.ST_PROP_FAIL) != (ref["status"] & oracle.ST_PROP_FAIL)
+    first = np.minimum(ndf + 5, ref["ndf"] + 5) // 2     # layer of the first failure (contiguous masks)
+    bad = [i for i in np.nonzero(pf)[0] if "records" not in ref or not _grazing(geom, ref, i, first[i], align)]
+    assert not bad, (label, "propagation failure disagrees on non-grazing tracks", bad[:10])
+    assert pf.mean() < 1e-3, (label, pf.mean())
+    live = ((ref["status"] & oracle.ST_BAD_INPUT) == 0) & ~pf
+    np.testing.assert_array_equal(ndf[live], ref["ndf"][live], err_msg=label)
+    ok = live & ((ref["status"] & oracle.ST_NEAR_TANGENT) == 0)
+    rel = rel_state_err(st, ref["state"])
+    ce = cov_err(cv, ref["cov"])
+    dchi = np.abs(c2.astype(np.float64) - ref["chi2"])
+    print(f"[{label}] n={ok.sum()} max rel state err per param {np.array2string(rel[:, ok].max(axis=1), precision=2)}"
+          f" p99.9 {np.quantile(rel[:, ok].max(axis=0), 0.999):.2e}; max cov err {ce[ok].max():.2e};"
+          f" max |dchi2| {dchi[ok].max():.2e}; near-tangent n={int((live & ~ok).sum())}"
+          f" max rel err {rel[:, live & ~ok].max() if (live & ~ok).any() else 0:.2e}; grazing n={int(pf.sum())}")
+    assert rel[:, ok].max() < TOL_STATE, label
+    assert ce[ok].max() < (TOL_COV if tol_cov is None else tol_cov), label
+    assert np.all(dchi[ok] < 0.05 + 1e-4 * ref["chi2"][ok]), label
+    return rel, ok
+
+
+def _run(geom, ts, align=None, xX0=None, seeds=None, thr=None):
+    need_gpu()
+    ctx = _ctx(geom)
+    if thr is not None:
+        ctx.set_fallback_threshold(thr)
+    hits = to_dev(ts.hits)
+    mask = mask_dev(ts.hit_mask)
+    a = None if align is None else to_dev(np.asarray(align, np.float32))
+    x = to_dev(np.asarray(geom.xX0 if xX0 is None else xX0, np.float32))
+    kw = {}
+    if seeds is not None:
+        kw = dict(seed_state=to_dev(seeds[0]), seed_cov=to_dev(seeds[1]))
+    out = ctx.fit(hits, mask, align=a, xX0=x, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_fit_10_layers_1000_tracks():
+    geom, ts = synth.fit_workload(1)
+    out = _run(geom, ts)
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, "10 layers, 1000 tracks")
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 257, 4099])
+def test_fit_ragged_sizes(n):
+    geom, ts = synth.fit_workload(2, n=n)
+    out = _run(geom, ts)
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask, records=True)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, f"17 layers, n={n}")
+
+
+def test_fit_1e6_tracks_sampled():
+    """The benchmark's workload at full size (1e6 tracks, 17 layers, x/X0 = 0.02):
+    every track is fitted on the GPU in one launch; 20 000 sampled tracks are
+    compared with the oracle, and global properties are checked for all."""
+    geom, ts = synth.fit_workload(2)
+    out = _run(geom, ts)
+    n = ts.hits.shape[2]
+    idx = np.sort(np.random.default_rng(0).choice(n, 20000, replace=False))
+    ref = oracle.fit(geom, np.ascontiguousarray(ts.hits[:, :, idx]), ts.hit_mask[idx], records=True)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, "1e6 tracks (sample)", idx=idx)
+    status = out["status"].cpu().numpy().view(np.uint32)
+    chi2 = out["chi2"].cpu().numpy()
+    ndf = out["ndf"].cpu().numpy()
+    good = status == 0
+    assert good.mean() > 0.9
+    assert np.all(np.isfinite(chi2[good]))
+    r = (chi2[good] / ndf[good]).mean()
+    assert 1.0 < r < 1.15, r
+
+
+@pytest.mark.parametrize("inflate,tol_cov", [(1.0, TOL_COV), (100.0, 2e-3)])
+def test_fit_external_seeds_and_misalignment(inflate, tol_cov):
+    """External seeds on the layer-0 surface with the workloads' prior (ten times the
+    nominal variances) meet the standard tolerance.  With a prior a thousand times the
+    nominal variances the FP32 covariance keeps ~1e-3 of relative cancellation error
+    from the first updates (the state still meets 1e-4): tolerance 2e-3."""
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    _, ts = synth.fit_workload(4, n=3000, align=a_true)
+    n = ts.hits.shape[2]
+    ss = np.zeros((6, n), np.float32)
+    sc = np.zeros((21, n), np.float32)
+    for i in range(n):   # on-surface external seeds: the oracle's three-hit helix, inflated prior
+        m = [np.array([a_true[l, 0], a_true[l, 1], a_true[l, 2]]) +
+             np.array([np.cos(a_true[l, 3]) * ts.hits[l, 0, i] - np.sin(a_true[l, 3]) * ts.hits[l, 1, i],
+                       np.sin(a_true[l, 3]) * ts.hits[l, 0, i] + np.cos(a_true[l, 3]) * ts.hits[l, 1, i],
+                       ts.hits[l, 2, i]]) for l in range(3)]
+        st, cv = oracle.seed(geom, *m)
+        ss[:, i] = st
+        sc[:, i] = [cv[a, b] * inflate for a in range(6) for b in range(a + 1)]
+    out = _run(geom, ts, align=a_true, seeds=(ss, sc))
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask, align=a_true, seed_state=ss, seed_cov=sc, records=True)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, f"external seeds x{inflate:g}, misaligned", tol_cov=tol_cov,
+             align=a_true)
+    out2 = _run(geom, ts, align=a_true)
+    ref2 = oracle.fit(geom, ts.hits, ts.hit_mask, align=a_true, records=True)
+    _compare(geom, ts.hits, ts.hit_mask, out2, ref2, "seeds from hits, misaligned", align=a_true)
+
+
+def test_forced_fp64_fallback_matches():
+    """Threshold > 1 sends every S^-1 and chi2 through FP64: flagged on every track,
+    and the results still meet the tolerance (and agree with the FP32 path)."""
+    geom, ts = synth.fit_workload(2, n=5000)
+    out32 = _run(geom, ts)
+    out64 = _run(geom, ts, thr=2.0)
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask, records=True)
+    st = out64["status"].cpu().numpy().view(np.uint32)
+    live = (ref["status"] & oracle.ST_BAD_INPUT) == 0
+    assert np.all(st[live] & 4)
+    assert not np.any(out32["status"].cpu().numpy().view(np.uint32)[live] & 4 & ~(ref["status"][live] & 4))
+    _compare(geom, ts.hits, ts.hit_mask, out64, ref, "forced FP64")
+    d = np.abs(out64["state"].cpu().numpy() - out32["state"].cpu().numpy())
+    assert rel_state_err(out64["state"].cpu().numpy(), out32["state"].cpu().numpy().astype(np.float64)).max() < 1e-4
+    assert np.isfinite(d).all()
+
+
+def test_straight_tracks_zero_field():
+    """B = 0 with external seeds (curvature is not measurable)."""
+    geom = synth.barrel(10, 5.0, 100.0, B=0.0, xX0=0.0, eta_max=1.0)
+    ts = synth.simulate(geom, synth.rng_for(96), 2000, (1.0, 5.0), False, 1.0, scatter=False)
+    n = 2000
+    tr0 = ts.truth[0].copy()
+    tr0[3] = 0.1
+    seeds = tr0.astype(np.float32)
+    w = np.array([1e-2, 1e-2, 1e-1, 1.0, 1e-2, 1e-2])
+    covs = np.array([[(w[a] ** 2 if a == b else 0.0) for a in range(6) for b in range(a + 1)]] * n,
+                    np.float32).T.copy()
+    out = _run(geom, ts, seeds=(seeds, covs))
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask, seed_state=seeds, seed_cov=covs)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, "B = 0")
+
+
+def test_bad_inputs_flagged():
+    """A mask without the seed layers is rejected per track; a NaN seed is reported
+    as non-finite; neither disturbs the other tracks."""
+    geom, ts = synth.fit_workload(2, n=256)
+    mask = ts.hit_mask.copy()
+    mask[3] &= ~np.uint32(1)      # no hit on layer 0
+    mask[5] &= ~np.uint32(4)      # no hit on layer 2 (seeding needs it)
+    ts.hit_mask = mask
+    out = _run(geom, ts)
+    st = out["status"].cpu().numpy().view(np.uint32)
+    assert st[3] == 16 and st[5] == 16
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, "bad masks")
+    n = ts.hits.shape[2]
+    seeds = np.zeros((6, n), np.float32)
+    seeds[:, :] = np.nan
+    covs = np.zeros((21, n), np.float32)
+    out2 = _run(geom, ts, seeds=(seeds, covs))
+    st2 = out2["status"].cpu().numpy().view(np.uint32)
+    assert np.all((st2 & (8 | 16)) != 0)
+
+
+def test_empty_and_invalid_calls():
+    need_gpu()
+    from paper_1906_11744_amd import KfError
+    geom, ts = synth.fit_workload(2, n=16)
+    ctx = _ctx(geom)
+    empty = torch.empty((geom.n_layers, 3, 0), dtype=torch.float32, device="cuda")
+    out = ctx.fit(empty, torch.empty(0, dtype=torch.int32, device="cuda"))
+    assert out["state"].shape == (6, 0)
+    with pytest.raises(TypeError):
+        ctx.fit(torch.from_numpy(ts.hits), torch.from_numpy(ts.hit_mask.view(np.int32)))
+    geom0 = synth.barrel(10, 5.0, 100.0, B=0.0)
+    with pytest.raises(KfError):
+        _ctx(geom0).fit(to_dev(synth.fit_workload(1, n=8)[1].hits), mask_dev(np.full(8, 1023, np.uint32)))
+
+
+def test_fit_is_deterministic():
+    geom, ts = synth.fit_workload(2, n=20000)
+    a = _run(geom, ts)
+    b = _run(geom, ts)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
