@@ -229,9 +229,30 @@ bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, double kB, T
   double smax = w != 0 ? kPi / std::fabs(w) : 4.0 * r;
   double h = 0.125 * r;
   if (w != 0) h = std::min(h, 0.125 / std::fabs(w));
+  // Along the helix circle the squared distance to the layer axis is a sinusoid of
+  // the turning angle, largest where the circle is farthest from the axis.  That
+  // point is always sampled, so a helix that only grazes the layer is bracketed too.
+  double speak = -1.0;
+  if (w != 0) {
+    double tx = std::cos(val(x[4])), ty = std::sin(val(x[4]));
+    double ccx = val(ex) - ty / w, ccy = val(ey) + tx / w;     // circle centre relative to the axis
+    if (ccx * ccx + ccy * ccy > 0) {
+      double psi_p = std::atan2(val(ey) - ccy, val(ex) - ccx);  // start, seen from the centre
+      double psi_f = std::atan2(ccy, ccx);                      // farthest point, seen from the centre
+      double du = std::fmod((psi_f - psi_p) * (w > 0 ? 1.0 : -1.0), 2 * kPi);
+      if (du < 0) du += 2 * kPi;
+      speak = du / std::fabs(w);
+    }
+  }
   double lo = 0.0, hi = -1.0;
+  bool peak_done = !(speak > 0 && speak < smax);
   for (double t = h; t < smax + h; t += h) {
     double tt = std::min(t, smax);
+    if (!peak_done && speak <= tt) {
+      peak_done = true;
+      if (val(crossing_residual<T>(x, T(speak), cx, cy, r, kB, nullptr)) >= 0) { hi = speak; break; }
+      lo = speak;
+    }
     double f = val(crossing_residual<T>(x, T(tt), cx, cy, r, kB, nullptr));
     if (f >= 0) { hi = tt; break; }
     lo = tt;
@@ -501,6 +522,11 @@ bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk) {
   transport_jacobian(tk.x, xe, s, g.kB, J);
   sandwich(J, tk.C);
   for (int i = 0; i < 6; ++i) tk.x[i] = xe[i];
+  {  // crossing angle: |cos alpha| = |r_hat . t| below 0.3 marks a near-tangent crossing
+    double ex = val(tk.x[0]) - val(ly.cx), ey = val(tk.x[1]) - val(ly.cy);
+    double ca = (ex * std::cos(val(tk.x[4])) + ey * std::sin(val(tk.x[4]))) / std::sqrt(ex * ex + ey * ey);
+    if (std::fabs(ca) < 0.3) tk.status |= ST_NEAR_TANGENT;
+  }
   add_scattering(g, ly, tk.x, tk.C);
   return true;
 }
@@ -834,6 +860,16 @@ struct FindCfg {
   bool brute;
 };
 
+// Relative margin by which the helix of state x clears (> 0) or misses (< 0) the
+// cylinder of layer ly: its circle reaches |centre - axis| + R from the axis.
+double reach_margin(const Geo& g, const Layer<double>& ly, const double x[6]) {
+  double w = -g.kB * x[3];
+  if (w == 0) return 1.0;
+  double R = 1.0 / std::fabs(w);
+  double cx = x[0] - std::sin(x[4]) / w - ly.cx, cy = x[1] + std::cos(x[4]) / w - ly.cy;
+  return (std::sqrt(cx * cx + cy * cy) + R - ly.r) / ly.r;
+}
+
 struct EventView {
   const float* hits;  // [3][H]
   int64_t H;
@@ -884,8 +920,9 @@ double hit_chi2(const Layer<double>& ly, const double x[6], const double Si[9], 
 
 // One seed through layers 3 .. L-1.  Returns the candidates in rank order; ambig gets
 // bit L set when some decision on layer L that can change the set of surviving
-// candidates lies within the FP32 tolerance of its threshold: a chi2 near the cut, a
-// hit near a window edge, or the last kept and first dropped branch scores near a tie.
+// candidates lies within the FP32 tolerance of its threshold: a helix grazing the
+// layer (reach margin below 1e-4), a chi2 near the cut, a hit near a window edge, or
+// the last kept and first dropped branch scores near a tie.
 std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCfg& o, const EventView& ev,
                             const std::vector<BinnedLayer>& bl, const int32_t sh[3], uint32_t& ambig) {
   ambig = 0;
@@ -912,6 +949,8 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
     for (size_t k = 0; k < cands.size(); ++k) {
       Cand& cd = cands[k];
       if (cd.term) { br.push_back({(int)k, 2, -1, cd.tk.n, cd.tk.chi2, 0.0}); continue; }
+      // reaching the layer at all is FP32-sensitive for a helix that grazes it
+      if (std::fabs(reach_margin(g, ly, cd.tk.x)) < 1e-4) ambig |= 1u << L;
       Track<double> p = cd.tk;
       if (!predict(g, ly, p)) {
         cd.term = true;

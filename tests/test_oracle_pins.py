@@ -128,6 +128,33 @@ def test_crossing_matches_circle_intersection(oracle_lib):
     assert n_ok > 400
 
 
+@pytest.mark.parametrize("turn", [1, -1])
+def test_grazing_crossings_are_found(oracle_lib, turn):
+    """A helix whose circle overlaps the layer by 1e-5 .. 1e-3 of its radius crosses it
+    over a short arc; one that falls short by as much does not.  Built from the circle
+    geometry: centre at distance d from the axis, radius R, d + R = r (1 +/- eps), the
+    track starting 0.3 rad before the circle's farthest point and moving towards it."""
+    kB = synth.K_B_PER_TESLA * 3.8
+    r, R, beta, delta = 103.375, 60.0, 0.9, 0.3
+    for eps in (1e-5, 1e-4, 1e-3):
+        for sign in (+1, -1):
+            d = r * (1 + sign * eps) - R
+            cc = d * np.array([math.cos(beta), math.sin(beta)])
+            psi = beta - turn * delta                       # start, seen from the centre
+            p0 = cc + R * np.array([math.cos(psi), math.sin(psi)])
+            t = turn * np.array([-math.sin(psi), math.cos(psi)])   # direction of motion
+            w = turn / R
+            x = np.array([p0[0], p0[1], 0.0, -w / kB, math.atan2(t[1], t[0]), 1.2])
+            out, s_arc = oracle.propagate(x, (0.0, 0.0), r, 3.8)
+            if sign > 0:
+                assert out is not None, eps
+                assert abs(math.hypot(out[0], out[1]) - r) < 1e-9 * r
+                # the crossing lies before the farthest point, reached after delta * R
+                assert 0 < s_arc < delta * R
+            else:
+                assert out is None, eps
+
+
 def test_transport_jacobian_central_differences(oracle_lib):
     """Fixed-arc transport Jacobian = central differences of the oracle's helix map."""
     rng = np.random.default_rng(6)
