@@ -69,7 +69,8 @@ typedef struct kf_geometry {
   float sigma_r_cm;              /* radial regulariser of the 3-D hit (its row of H is zero) */
   float mass_gev;                /* particle mass in the Highland beta */
   int32_t n_phi_bins;            /* finder bins in phi over [-pi, pi): 1 .. 1024 */
-  int32_t n_z_bins;              /* finder bins in z over [-Z, Z]: 1 .. 256 */
+  int32_t n_z_bins;              /* finder bins in z over [-Z, Z]: 1 .. 256; kf_find needs */
+                                 /* n_phi_bins * n_z_bins <= 8192 */
 } kf_geometry;
 
 typedef struct kf_ctx kf_ctx;
@@ -111,7 +112,7 @@ typedef struct kf_fit_out {
  * hits of event e on layer L are hit_off[e][L] .. hit_off[e][L+1]-1.  Seeds are hit
  * triplets on layers 0, 1, 2: seed_hits [3][n_seeds] global hit indices, seed_event
  * [n_seeds].  Seeds of one event should be contiguous for locality (not required). */
-typedef struct kf_find_in {
+typedef struct kf_find_in {  /* n_hits < 2^28 - 2 */
   int32_t n_events;
   const int64_t* hit_off;
   int64_t n_hits;
@@ -130,7 +131,9 @@ typedef struct kf_find_in {
  * n_cand [S]; hit_idx [keep][L][S] global hit index, -1 missing layer, -2 not reached;
  * n_hits, n_miss [keep][S]; chi2 [keep][S]; state [keep][6][S]; cov [keep][21][S];
  * status [keep][S]; rf_* (only with refit): the fit of the rank-0 candidate's hits,
- * seeded from its first three, as kf_fit_out. */
+ * seeded from its first three, as kf_fit_out.  A seed whose event or hit indices are
+ * out of range gets n_cand 0 and status[0][s] = KF_ST_BAD_INPUT; hit_off slices are
+ * clamped to [0, n_hits]. */
 typedef struct kf_find_out {
   int32_t* n_cand;
   int32_t* hit_idx;

@@ -10,6 +10,8 @@
 struct kf_ctx {
   kf_geometry g;
   float det_thr;
+  int grid_device = -1;   // device the persistent grid below was sized for
+  int grid_blocks = 0;
 };
 
 namespace {
@@ -45,6 +47,41 @@ bool valid_geometry(const kf_geometry* g) {
 
 // Workspace of a fit: the per-layer constants.
 size_t fit_ws_bytes() { return round_up(sizeof(kfd::LayerK) * KF_MAX_LAYERS); }
+
+// Workspace of a find: layer constants | binned records [H] float4 | binned indices [H]
+// | bin offsets [E][L][nbins + 1] | tile counter.
+struct FindWs {
+  size_t layers, brec, bidx, boff, counter, total;
+};
+
+FindWs find_ws(const kf_ctx* c, const kf_find_in* in) {
+  FindWs w;
+  const size_t H = (size_t)(in->n_hits > 0 ? in->n_hits : 0);
+  const size_t nb = (size_t)c->g.n_phi_bins * c->g.n_z_bins + 1;
+  const size_t E = (size_t)(in->n_events > 0 ? in->n_events : 0);
+  w.layers = 0;
+  w.brec = w.layers + fit_ws_bytes();
+  w.bidx = w.brec + round_up(H * 16);
+  w.boff = w.bidx + round_up(H * 4);
+  w.counter = w.boff + round_up(E * c->g.n_layers * nb * 4);
+  w.total = w.counter + kAlign;
+  return w;
+}
+
+// Persistent find grid: as many workgroups as fit on the device at once.
+int persistent_grid(kf_ctx* c, int nl, int* grid) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return KF_E_HIP;
+  if (c->grid_device != dev) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return KF_E_HIP;
+    if (kfi::find_max_blocks(nl, &per) != hipSuccess) return KF_E_HIP;
+    c->grid_blocks = cus * (per > 0 ? per : 1);
+    c->grid_device = dev;
+  }
+  *grid = c->grid_blocks;
+  return KF_OK;
+}
 
 int check_ws(void* ws, size_t ws_bytes, size_t need) {
   if (need == 0) return KF_OK;
@@ -84,6 +121,9 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
   switch (op) {
     case KF_OP_FIT:
       *bytes = fit_ws_bytes();
+      return KF_OK;
+    case KF_OP_FIND:
+      *bytes = find_ws(ctx, static_cast<const kf_find_in*>(in)).total;
       return KF_OK;
     default:
       return KF_E_UNSUPPORTED;
@@ -131,8 +171,104 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
 
 int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out, void* ws,
             size_t ws_bytes, void* stream) {
-  (void)ctx; (void)params; (void)in; (void)out; (void)ws; (void)ws_bytes; (void)stream;
-  return KF_E_UNSUPPORTED;
+  if (!ctx || !in || !out) return KF_E_INVALID;
+  if (in->n_events < 0 || in->n_seeds < 0 || in->n_hits < 0) return KF_E_INVALID;
+  if (in->keep < 1 || in->keep > KF_MAX_KEEP || in->max_miss < 1) return KF_E_INVALID;
+  if (!(in->chi2_cut > 0.f) || !(in->nsigma > 0.f)) return KF_E_INVALID;
+  if (in->n_seeds == 0) return KF_OK;
+  if (in->n_events == 0 || !in->hit_off || !in->hits || !in->seed_event || !in->seed_hits) return KF_E_INVALID;
+  if (!out->n_cand || !out->hit_idx || !out->n_hits || !out->n_miss || !out->chi2 || !out->state || !out->cov ||
+      !out->status)
+    return KF_E_INVALID;
+  if (in->refit && (!out->rf_state || !out->rf_cov || !out->rf_chi2 || !out->rf_ndf || !out->rf_status))
+    return KF_E_INVALID;
+  // hit indices travel as (index + 2) << 3 in 32-bit backpointers
+  if (in->n_hits >= (int64_t(1) << 28) - 2 || in->n_seeds >= (int64_t)INT32_MAX * 32) return KF_E_UNSUPPORTED;
+  if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
+  if ((int64_t)ctx->g.n_phi_bins * ctx->g.n_z_bins > 8192) return KF_E_UNSUPPORTED;  // LDS of the bin kernel
+  const FindWs w = find_ws(ctx, in);
+  int rc = check_ws(ws, ws_bytes, w.total);
+  if (rc != KF_OK) return rc;
+  char* base = static_cast<char*>(ws);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base + w.layers);
+  const float* align = params ? params->align : nullptr;
+  const float* xX0 = params ? params->xX0 : nullptr;
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+    return KF_E_HIP;
+  kfi::BinArgs b;
+  b.nl = ctx->g.n_layers;
+  b.nphi = ctx->g.n_phi_bins;
+  b.nz = ctx->g.n_z_bins;
+  b.n_events = in->n_events;
+  b.H = in->n_hits;
+  b.hit_off = in->hit_off;
+  b.hits = in->hits;
+  b.layers = layers;
+  for (int l = 0; l < 32; ++l) b.zhalf[l] = l < ctx->g.n_layers ? ctx->g.zhalf_cm[l] : 1.f;
+  b.brec = reinterpret_cast<float4*>(base + w.brec);
+  b.bidx = reinterpret_cast<int32_t*>(base + w.bidx);
+  b.boff = reinterpret_cast<int32_t*>(base + w.boff);
+  b.counter = reinterpret_cast<int32_t*>(base + w.counter);
+  if (kfi::launch_bin(b, st) != hipSuccess) return KF_E_HIP;
+  kfi::FindArgs f;
+  f.nl = b.nl;
+  f.nphi = b.nphi;
+  f.nz = b.nz;
+  f.keep = in->keep;
+  f.max_miss = in->max_miss;
+  f.n_events = in->n_events;
+  f.chi2_cut = in->chi2_cut;
+  f.nsigma = in->nsigma;
+  f.md = model_of(ctx);
+  f.srphi = ctx->g.sigma_rphi_cm;
+  f.sz = ctx->g.sigma_z_cm;
+  f.n_seeds = in->n_seeds;
+  f.H = in->n_hits;
+  f.n_tiles = (in->n_seeds + 31) / 32;
+  f.hits = in->hits;
+  f.seed_event = in->seed_event;
+  f.seed_hits = in->seed_hits;
+  f.layers = layers;
+  f.brec = b.brec;
+  f.bidx = b.bidx;
+  f.boff = b.boff;
+  for (int l = 0; l < 32; ++l) f.zhalf[l] = b.zhalf[l];
+  f.counter = b.counter;
+  f.n_cand = out->n_cand;
+  f.hit_idx = out->hit_idx;
+  f.n_hits = out->n_hits;
+  f.n_miss = out->n_miss;
+  f.chi2 = out->chi2;
+  f.state = out->state;
+  f.cov = out->cov;
+  f.status = out->status;
+  int grid = 0;
+  if (persistent_grid(ctx, b.nl, &grid) != KF_OK) return KF_E_HIP;
+  if ((int64_t)grid > f.n_tiles) grid = (int)f.n_tiles;
+  if (kfi::launch_find(f, grid, st) != hipSuccess) return KF_E_HIP;
+  if (in->refit) {
+    kfi::FitArgs a;
+    a.n = in->n_seeds;
+    a.nl = ctx->g.n_layers;
+    a.seed_from_hits = 1;
+    a.md = f.md;
+    a.srphi = f.srphi;
+    a.sz = f.sz;
+    a.hits = nullptr;
+    a.mask = nullptr;
+    a.seed_state = nullptr;
+    a.seed_cov = nullptr;
+    a.layers = layers;
+    a.state = out->rf_state;
+    a.cov = out->rf_cov;
+    a.chi2 = out->rf_chi2;
+    a.ndf = out->rf_ndf;
+    a.status = out->rf_status;
+    a.ckpt = nullptr;
+    if (kfi::launch_refit(a, in->hits, in->n_hits, out->hit_idx, st) != hipSuccess) return KF_E_HIP;
+  }
+  return KF_OK;
 }
 
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,

@@ -1,0 +1,422 @@
+// Combinatorial track finding on gfx950.
+//
+//  * bin_kernel: one workgroup per (event, layer) slice; places every hit on its
+//    (aligned) layer and counting-sorts it into n_phi x n_z bins in LDS.  Binned
+//    records are (x, y, z, phi about the layer axis) plus the caller's hit index.
+//  * find_kernel: persistent workgroups pull tiles of 32 seeds from a counter.  A
+//    seed owns a group of 8 lanes; lane k holds candidate k (state and packed
+//    covariance in registers).  Per layer every live candidate predicts, scans the
+//    bins its window overlaps keeping its best `keep` hit branches in registers, the
+//    group merges all branches with min-reductions of 64-bit score keys over lane
+//    shuffles, and each surviving slot pulls its parent's predicted state by shuffle
+//    and applies its update.  Backpointers (parent slot and hit, one dword per layer
+//    and slot) live in LDS; candidates' hit lists are rebuilt from them at the end.
+#include "kf_internal.h"
+
+namespace kfi {
+
+namespace {
+
+constexpr int kGroup = 8;        // lanes per seed (>= keep)
+constexpr int kTileSeeds = 32;   // seeds per 256-lane workgroup
+constexpr int kMaxList = 8;      // hit branches kept per candidate
+
+__device__ __forceinline__ int bin_index(float v, float lo, float scale, int nb) {
+  const int b = (int)floorf((v - lo) * scale);
+  return b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
+  extern __shared__ int cnt[];  // [nbins + 1] counts, then running write offsets
+  __shared__ int part[256];
+  const int tid = threadIdx.x;
+  const int seg = blockIdx.x;
+  const int e = seg / a.nl, l = seg % a.nl;
+  if (seg == 0 && tid == 0 && a.counter) *a.counter = 0;  // the find kernel's tile queue
+  const int nb = a.nphi * a.nz;
+  for (int b = tid; b <= nb; b += 256) cnt[b] = 0;
+  __syncthreads();
+  // slices outside [0, H] or reversed are clamped (never read out of bounds)
+  int64_t beg = a.hit_off[(int64_t)e * (a.nl + 1) + l];
+  int64_t end = a.hit_off[(int64_t)e * (a.nl + 1) + l + 1];
+  beg = beg < 0 ? 0 : (beg > a.H ? a.H : beg);
+  end = end < beg ? beg : (end > a.H ? a.H : end);
+  const kfd::LayerK ly = a.layers[l];
+  const float Z = a.zhalf[l];
+  const float sphi = a.nphi / kfd::kTwoPi, sz = a.nz / (2.f * Z);
+  auto place_bin = [&](int64_t j, float4& rec) -> int {
+    float mx, my, mz;
+    kfd::place(ly, a.hits[j], a.hits[a.H + j], a.hits[2 * a.H + j], mx, my, mz);
+    const float ph = atan2f(my - ly.cy, mx - ly.cx);
+    rec = make_float4(mx, my, mz, ph);
+    return bin_index(ph, -kfd::kPi, sphi, a.nphi) * a.nz + bin_index(mz, -Z, sz, a.nz);
+  };
+  for (int64_t j = beg + tid; j < end; j += 256) {
+    float4 rec;
+    atomicAdd(&cnt[place_bin(j, rec)], 1);
+  }
+  __syncthreads();
+  // exclusive scan of nb counts: each thread a contiguous chunk, then the 256 chunk sums
+  const int chunk = (nb + 255) / 256;
+  const int c0 = tid * chunk, c1 = min(nb, c0 + chunk);
+  int acc = 0;
+  for (int b = c0; b < c1; ++b) acc += cnt[b];
+  part[tid] = acc;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = (int)beg + (tid > 0 ? part[tid - 1] : 0);
+  int32_t* out_off = a.boff + ((int64_t)e * a.nl + l) * (nb + 1);
+  for (int b = c0; b < c1; ++b) {
+    const int c = cnt[b];
+    cnt[b] = run;
+    out_off[b] = run;
+    run += c;
+  }
+  if (tid == 0) out_off[nb] = (int)end;
+  __syncthreads();
+  for (int64_t j = beg + tid; j < end; j += 256) {
+    float4 rec;
+    const int b = place_bin(j, rec);
+    const int p = atomicAdd(&cnt[b], 1);
+    a.brec[p] = rec;
+    a.bidx[p] = (int32_t)j;
+  }
+}
+
+namespace {
+
+enum : int { EMPTY = 0, LIVE = 1, TERM = 2 };
+enum : int { K_NONE = 0, K_HIT = 1, K_MISS = 2, K_CARRY = 3 };
+
+__device__ __forceinline__ bool key_lt(float c1, int h1, float c2, int h2) { return c1 < c2 || (c1 == c2 && h1 < h2); }
+
+__device__ __forceinline__ float shfl_f(float v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64); }
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void find_kernel(FindArgs a) {
+  // backpointer of every (layer, slot): ((hit + 2) << 3) | parent slot, hit >= -2
+  extern __shared__ int32_t bp[];  // [nl][256]
+  __shared__ int tile_sh;
+  const int tid = threadIdx.x;
+  const int slot = tid & (kGroup - 1);
+  const int grp = tid / kGroup;
+  const int lane = __lane_id();
+  const int gbase = lane & ~(kGroup - 1);
+  const int nl = a.nl;
+  const int64_t S = a.n_seeds;
+  const int nb_all = a.nphi * a.nz;
+  const float kphi = a.nphi / kfd::kTwoPi;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) tile_sh = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int64_t tile = tile_sh;
+    if (tile >= a.n_tiles) break;
+    const int64_t s = tile * kTileSeeds + grp;
+    const bool active = s < S;
+    // ---------------- seed and its refit over hits 0..2 ----------------
+    kfd::Trk k;
+    float c2 = 0.f;
+    int nh = 0, nm = 0, mode = EMPTY;
+    uint32_t st = 0;
+    int e = 0;
+    int sh[3] = {0, 0, 0};
+    bool bad = false;
+    if (active) {
+      e = a.seed_event[s];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sh[q] = a.seed_hits[q * S + s];
+      bad = e < 0 || e >= a.n_events;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) bad = bad || sh[q] < 0 || (int64_t)sh[q] >= a.H;
+      if (bad) {
+        e = 0;
+        sh[0] = sh[1] = sh[2] = 0;
+      }
+    }
+    if (active && !bad) {
+      float m[3][3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        kfd::place(a.layers[q], a.hits[sh[q]], a.hits[a.H + sh[q]], a.hits[2 * a.H + sh[q]], m[q][0], m[q][1],
+                   m[q][2]);
+      kfd::seed_from_three(k, a.md, m[0][0], m[0][1], m[0][2], m[1][0], m[1][1], m[2][0], m[2][1], m[2][2],
+                           a.srphi, a.sz);
+      kfd::init_trig(k);
+      bool ok = true;
+      for (int q = 0; q < 3 && ok; ++q) {
+        const kfd::LayerK ly = a.layers[q];
+        if (q > 0) {
+          kfd::Step stp;
+          ok = kfd::crossing(k, ly, a.md.kB, stp);
+          if (!ok) {
+            st |= kfd::ST_PROP_FAIL;
+            break;
+          }
+          kfd::transport(k, stp, a.md.kB);
+        }
+        const kfd::Frame f = kfd::frame_at(k, ly);
+        if (q > 0 && ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+        if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
+        kfd::Pred p;
+        kfd::prepare(k, f, a.md, p);
+        if (p.fp64) st |= kfd::ST_FP64;
+        const kfd::Resid r = kfd::residual(k, f, ly, p, m[q][0], m[q][1], m[q][2]);
+        kfd::apply_update(k, p, a.md, r.r1, r.r2);
+        c2 += r.chi2;
+        ++nh;
+      }
+      mode = slot == 0 ? (ok ? LIVE : TERM) : EMPTY;
+    }
+    int ncand = active && !bad ? 1 : 0;
+    // ---------------- layers 3 .. L-1 ----------------
+    for (int l = 3; l < nl; ++l) {
+      const kfd::LayerK ly = a.layers[l];
+      float bc[kMaxList];
+      int bi[kMaxList];
+#pragma unroll
+      for (int q = 0; q < kMaxList; ++q) {
+        bc[q] = INFINITY;
+        bi[q] = 0x7fffffff;
+      }
+      int nlist = 0;
+      bool predicted = false;
+      if (mode == LIVE) {
+        kfd::Step stp;
+        if (kfd::crossing(k, ly, a.md.kB, stp)) {
+          predicted = true;
+          kfd::transport(k, stp, a.md.kB);
+          const kfd::Frame f = kfd::frame_at(k, ly);
+          if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
+          if (ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+          kfd::Pred p;
+          kfd::prepare(k, f, a.md, p);
+          const float phip = atan2f(f.ry, f.rx), zp = k.x[2] + k.xl[2];
+          const float wphi = a.nsigma * sqrtf(p.S11) / f.rho;
+          const float wz = a.nsigma * sqrtf(p.S22);
+          const float Z = a.zhalf[l];
+          const float kz = a.nz / (2.f * Z);
+          const float zq = fmaf(wz, 1e-4f, wz) + 1e-6f;
+          const int zlo = bin_index(zp - zq, -Z, kz, a.nz), zhi = bin_index(zp + zq, -Z, kz, a.nz);
+          const float wq = fmaf(wphi, 1e-4f, wphi) + 1e-6f;
+          int blo = 0, bhi = a.nphi - 1;
+          if (wq < kfd::kPi) {
+            blo = (int)floorf((phip - wq + kfd::kPi) * kphi);
+            bhi = (int)floorf((phip + wq + kfd::kPi) * kphi);
+            if (bhi - blo + 1 >= a.nphi) {
+              blo = 0;
+              bhi = a.nphi - 1;
+            }
+          }
+          const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
+          for (int b = blo; b <= bhi; ++b) {
+            const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
+            const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
+            for (int q = q0; q < q1; ++q) {
+              const float4 rec = a.brec[q];
+              const float dphi = kfd::wrap_pi(rec.w - phip);
+              const float dz = rec.z - zp;
+              if (!(fabsf(dphi) <= wphi && fabsf(dz) <= wz)) continue;
+              const kfd::Resid r = kfd::residual(k, f, ly, p, rec.x, rec.y, rec.z);
+              if (!(r.chi2 < a.chi2_cut)) continue;
+              const float cc = c2 + r.chi2;
+              const int hh = a.bidx[q];
+              // Sorted insertion written as one select per slot: slot t keeps its entry
+              // if that entry precedes the new one, takes the new one if only the entry
+              // before it does, and otherwise takes the entry before it.  (No element
+              // moves under a lane mask: register-pair copies followed by a partial
+              // overwrite of the same pair have lost the new element on gfx950.)
+              bool prev_lt = true;
+              float oc = 0.f;
+              int oh = 0;
+#pragma unroll
+              for (int t = 0; t < kMaxList; ++t) {
+                const bool lt = t < nlist && key_lt(bc[t], bi[t], cc, hh);
+                const float ct = bc[t];
+                const int ht = bi[t];
+                bc[t] = lt ? ct : (prev_lt ? cc : oc);
+                bi[t] = lt ? ht : (prev_lt ? hh : oh);
+                prev_lt = lt;
+                oc = ct;
+                oh = ht;
+              }
+              nlist = nlist < kMaxList ? nlist + 1 : kMaxList;
+            }
+          }
+        } else {
+          mode = TERM;
+          st |= kfd::ST_PROP_FAIL;
+        }
+      }
+      // ---- merge the group's branches: `keep` rounds of a 64-bit min over 8 lanes ----
+      // The list is not shifted when its head is taken (register-array moves); the
+      // head is an index resolved by a chain of selects.
+      bool other_used = false;   // the miss (live) or carry (terminated) branch was taken
+      int head = 0;
+      int my_par = slot, my_kind = K_NONE, my_hit = -2;
+      float my_c = 0.f;
+      int new_n = 0;
+      for (int r = 0; r < a.keep; ++r) {
+        int hk = K_NONE, hh = -2, hn = 0;
+        float hc = 0.f;
+        if (head < nlist) {
+          hk = K_HIT;
+          hh = bi[0];
+          hc = bc[0];
+#pragma unroll
+          for (int t = 1; t < kMaxList; ++t) {
+            if (head == t) {
+              hh = bi[t];
+              hc = bc[t];
+            }
+          }
+          hn = nh + 1;
+        } else if (!other_used && mode == LIVE && predicted) {
+          hk = K_MISS;
+          hc = c2;
+          hn = nh;
+        } else if (!other_used && mode == TERM) {
+          hk = K_CARRY;
+          hc = c2;
+          hn = nh;
+        }
+        unsigned long long key = ~0ull;
+        if (hk != K_NONE)
+          key = ((unsigned long long)(255 - hn) << 40) | ((unsigned long long)__float_as_uint(hc) << 8) |
+                (unsigned long long)slot;
+#pragma unroll
+        for (int m = 1; m < kGroup; m <<= 1) {
+          const unsigned long long o = __shfl_xor(key, m, kGroup);
+          key = o < key ? o : key;
+        }
+        if (key == ~0ull) break;
+        const int w = (int)(key & 7ull);
+        const int wk = shfl_i(hk, gbase + w);
+        const int wh = shfl_i(hh, gbase + w);
+        const float wc = shfl_f(hc, gbase + w);
+        if (slot == r) {
+          my_par = w;
+          my_kind = wk;
+          my_hit = wh;
+          my_c = wc;
+        }
+        if (slot == w) {
+          if (hk == K_HIT) ++head;
+          else other_used = true;
+        }
+        ++new_n;
+      }
+      // ---- every surviving slot takes its parent's (predicted) candidate ----
+      const int src = gbase + my_par;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) k.x[q] = shfl_f(k.x[q], src);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) k.xl[q] = shfl_f(k.xl[q], src);
+#pragma unroll
+      for (int q = 0; q < 21; ++q) k.C[q] = shfl_f(k.C[q], src);
+      k.cp = shfl_f(k.cp, src);
+      k.sp = shfl_f(k.sp, src);
+      k.ct = shfl_f(k.ct, src);
+      k.st = shfl_f(k.st, src);
+      c2 = shfl_f(c2, src);
+      nh = shfl_i(nh, src);
+      nm = shfl_i(nm, src);
+      mode = shfl_i(mode, src);
+      st = (uint32_t)shfl_i((int)st, src);
+      if (active) {
+        if (slot < new_n) {
+          if (my_kind == K_HIT) {
+            const kfd::Frame f = kfd::frame_at(k, ly);
+            if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
+            kfd::Pred p;
+            kfd::prepare(k, f, a.md, p);
+            if (p.fp64) st |= kfd::ST_FP64;
+            float mx, my, mz;
+            kfd::place(ly, a.hits[my_hit], a.hits[a.H + my_hit], a.hits[2 * a.H + my_hit], mx, my, mz);
+            const kfd::Resid r = kfd::residual(k, f, ly, p, mx, my, mz);
+            kfd::apply_update(k, p, a.md, r.r1, r.r2);
+            c2 = my_c;
+            nh += 1;
+          } else if (my_kind == K_MISS) {
+            nm += 1;
+            my_hit = -1;
+            if (nm >= a.max_miss) {
+              mode = TERM;
+              st |= kfd::ST_TERM_MISSES;
+            }
+          } else {
+            my_hit = -2;
+          }
+          bp[l * 256 + tid] = ((my_hit + 2) << 3) | my_par;
+        } else {
+          mode = EMPTY;
+        }
+      }
+      ncand = new_n;
+    }
+    __syncthreads();
+    // ---------------- outputs ----------------
+    if (active) {
+      const int keep = a.keep;
+      if (slot < keep) {
+        const bool have = slot < ncand;
+        auto at = [&](int kk, int64_t inner) { return ((int64_t)kk * inner) * S + s; };
+        int cur = slot;
+        for (int l = nl - 1; l >= 0; --l) {
+          int h = -2;
+          if (have) {
+            if (l >= 3) {
+              const int v = bp[l * 256 + grp * kGroup + cur];
+              h = (v >> 3) - 2;
+              cur = v & (kGroup - 1);
+            } else {
+              h = sh[l];
+            }
+          }
+          a.hit_idx[((int64_t)slot * nl + l) * S + s] = h;
+        }
+        a.n_hits[at(slot, 1)] = have ? nh : 0;
+        a.n_miss[at(slot, 1)] = have ? nm : 0;
+        a.chi2[at(slot, 1)] = have ? c2 : 0.f;
+        a.status[at(slot, 1)] = have ? st : 0u;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          a.state[((int64_t)slot * 6 + q) * S + s] = have ? (q < 3 ? k.x[q] + k.xl[q] : k.x[q]) : 0.f;
+#pragma unroll
+        for (int q = 0; q < 21; ++q) a.cov[((int64_t)slot * 21 + q) * S + s] = have ? k.C[q] : 0.f;
+      }
+      if (slot == 0) {
+        a.n_cand[s] = ncand;
+        if (bad) a.status[s] = kfd::ST_BAD_INPUT;
+      }
+    }
+  }
+}
+
+hipError_t launch_bin(const BinArgs& a, hipStream_t stream) {
+  const size_t lds = (size_t)(a.nphi * a.nz + 1) * sizeof(int);
+  hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(a.n_events * a.nl)), dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+size_t find_lds_bytes(int nl) { return (size_t)nl * 256 * sizeof(int32_t); }
+
+hipError_t find_max_blocks(int nl, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel, 256, find_lds_bytes(nl));
+}
+
+hipError_t launch_find(const FindArgs& a, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(find_kernel, dim3((unsigned)grid), dim3(256), find_lds_bytes(a.nl), stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace kfi

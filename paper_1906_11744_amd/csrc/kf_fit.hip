@@ -34,16 +34,39 @@ hipError_t launch_layer_prep(int nl, const float* radius_host, const float* alig
 __device__ __forceinline__ void store_ckpt(float* ck, int64_t n, int64_t i, int l, const kfd::Trk& k) {
   float* p = ck + (int64_t)l * 27 * n + i;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) p[q * n] = k.x[q];
+  for (int q = 0; q < 6; ++q) p[q * n] = q < 3 ? k.x[q] + k.xl[q] : k.x[q];
 #pragma unroll
   for (int q = 0; q < 21; ++q) p[(6 + q) * n] = k.C[q];
 }
 
-__global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+// Hits of track i in the [L][3][n] layout, mask from the caller.
+struct SoaHits {
+  const float* hits;
+  const uint32_t* mask;
+  __device__ void get(int64_t i, int64_t n, int l, float& hx, float& hy, float& hz) const {
+    const float* h = hits + (int64_t)l * 3 * n + i;
+    hx = h[0];
+    hy = h[n];
+    hz = h[2 * n];
+  }
+};
+
+// Hits of seed i's rank-0 finder candidate: global indices hit_idx[l][i] into [3][H].
+struct GatherHits {
+  const float* hits;
+  int64_t H;
+  const int32_t* idx;  // [L][n] (slot 0 of the finder's hit_idx)
+  __device__ void get(int64_t i, int64_t n, int l, float& hx, float& hy, float& hz) const {
+    const int32_t j = idx[(int64_t)l * n + i];
+    hx = hits[j];
+    hy = hits[H + j];
+    hz = hits[2 * H + j];
+  }
+};
+
+template <class Src>
+__device__ __forceinline__ void fit_one(const FitArgs& a, int64_t i, uint32_t mask, const Src& src) {
   const int64_t n = a.n;
-  const uint32_t mask = a.mask[i];
   const uint32_t need = a.seed_from_hits ? 7u : 1u;
   uint32_t status = 0;
   kfd::Trk k;
@@ -51,13 +74,15 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
   int nh = 0;
   const kfd::LayerK* __restrict__ lays = a.layers;
   auto hit = [&](int l, float& mx, float& my, float& mz) {
-    const float* h = a.hits + (int64_t)l * 3 * n + i;
-    kfd::place(lays[l], h[0], h[n], h[2 * n], mx, my, mz);
+    float hx, hy, hz;
+    src.get(i, n, l, hx, hy, hz);
+    kfd::place(lays[l], hx, hy, hz, mx, my, mz);
   };
   if ((mask & need) != need) {
     status = kfd::ST_BAD_INPUT;
 #pragma unroll
     for (int q = 0; q < 6; ++q) k.x[q] = 0.f;
+    k.xl[0] = k.xl[1] = k.xl[2] = 0.f;
 #pragma unroll
     for (int q = 0; q < 21; ++q) k.C[q] = 0.f;
   } else {
@@ -71,6 +96,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
     } else {
 #pragma unroll
       for (int q = 0; q < 6; ++q) k.x[q] = a.seed_state[q * n + i];
+      k.xl[0] = k.xl[1] = k.xl[2] = 0.f;
 #pragma unroll
       for (int q = 0; q < 21; ++q) k.C[q] = a.seed_cov[q * n + i];
     }
@@ -88,9 +114,9 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
         kfd::transport(k, st, a.md.kB);
       }
       const kfd::Frame f = kfd::frame_at(k, ly);
+      if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
       if (l > 0 && ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
       if ((mask >> l) & 1u) {
-        if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
         kfd::Pred p;
         kfd::prepare(k, f, a.md, p);
         if (p.fp64) status |= kfd::ST_FP64;
@@ -108,12 +134,37 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
       if (!isfinite(k.x[q])) status |= kfd::ST_NONFINITE;
   }
 #pragma unroll
-  for (int q = 0; q < 6; ++q) a.state[q * n + i] = k.x[q];
+  for (int q = 0; q < 6; ++q) a.state[q * n + i] = q < 3 ? k.x[q] + k.xl[q] : k.x[q];
 #pragma unroll
   for (int q = 0; q < 21; ++q) a.cov[q * n + i] = k.C[q];
   a.chi2[i] = chi2;
   a.ndf[i] = 2 * nh - 5;
   a.status[i] = status;
+}
+
+__global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  SoaHits src{a.hits, a.mask};
+  fit_one(a, i, a.mask[i], src);
+}
+
+// Fit of each seed's best finder candidate from its own hits (slot 0 of hit_idx).
+__global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __restrict__ hits, int64_t H,
+                                                    const int32_t* __restrict__ idx0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  uint32_t mask = 0;
+  for (int l = 0; l < a.nl; ++l) mask |= (idx0[(int64_t)l * a.n + i] >= 0 ? 1u : 0u) << l;
+  GatherHits src{hits, H, idx0};
+  fit_one(a, i, mask, src);
+}
+
+hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream) {
+  const int bs = 256;
+  const int64_t nb = (a.n + bs - 1) / bs;
+  hipLaunchKernelGGL(refit_kernel, dim3((unsigned)nb), dim3(bs), 0, stream, a, hits, H, idx0);
+  return hipGetLastError();
 }
 
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream) {

@@ -28,9 +28,54 @@ struct FitArgs {
   float* ckpt;
 };
 
+struct BinArgs {
+  int32_t nl, nphi, nz, n_events;
+  int64_t H;
+  const int64_t* hit_off;  // [E][L+1]
+  const float* hits;       // [3][H]
+  const kfd::LayerK* layers;
+  float zhalf[32];
+  float4* brec;            // [H] binned (x, y, z, phi) of placed hits
+  int32_t* bidx;           // [H] caller's index of each binned hit
+  int32_t* boff;           // [E][L][nbins + 1] absolute start of every bin
+  int32_t* counter;        // find tile queue, zeroed here
+};
+
+struct FindArgs {
+  int32_t nl, nphi, nz, keep, max_miss, n_events;
+  float chi2_cut, nsigma;
+  kfd::Model md;
+  float srphi, sz;
+  int64_t n_seeds, H, n_tiles;
+  const float* hits;
+  const int32_t* seed_event;
+  const int32_t* seed_hits;
+  const kfd::LayerK* layers;
+  const float4* brec;
+  const int32_t* bidx;
+  const int32_t* boff;
+  float zhalf[32];
+  int32_t* counter;
+  int32_t* n_cand;
+  int32_t* hit_idx;
+  int32_t* n_hits;
+  int32_t* n_miss;
+  float* chi2;
+  float* state;
+  float* cov;
+  uint32_t* status;
+};
+
+hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
+size_t find_lds_bytes(int nl);
+hipError_t find_max_blocks(int nl, int* blocks_per_cu);
+hipError_t launch_find(const FindArgs& a, int grid, hipStream_t stream);
+
 // Writes the per-layer constants (radius, alignment, its cos/sin, material).
 hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
                              kfd::LayerK* out, hipStream_t stream);
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream);
+// Fit of each seed's rank-0 finder candidate: idx0 [L][n] hit indices into hits [3][H].
+hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream);
 
 }  // namespace kfi

@@ -5,7 +5,8 @@ import torch
 
 import oracle
 
-FLOORS = np.array([1.0, 1.0, 1.0, 0.0, 1.0, 1.0])   # cm, cm, cm, (kappa: none), rad, rad
+# cm, cm, cm, 1/GeV (1/50 GeV: the smallest |kappa| the workloads generate), rad, rad
+FLOORS = np.array([1.0, 1.0, 1.0, 0.02, 1.0, 1.0])
 
 
 def need_gpu():
