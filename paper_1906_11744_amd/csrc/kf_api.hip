@@ -125,6 +125,12 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
     case KF_OP_FIND:
       *bytes = find_ws(ctx, static_cast<const kf_find_in*>(in)).total;
       return KF_OK;
+    case KF_OP_FIT_BACKWARD: {
+      const kf_fit_in* f = static_cast<const kf_fit_in*>(in);
+      const size_t n = (size_t)(f->n > 0 ? f->n : 0);
+      *bytes = fit_ws_bytes() + round_up((size_t)ctx->g.n_layers * 5 * n * sizeof(float));
+      return KF_OK;
+    }
     default:
       return KF_E_UNSUPPORTED;
   }
@@ -273,9 +279,44 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
 
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream) {
-  (void)ctx; (void)params; (void)in; (void)fwd; (void)dchi2; (void)dalign; (void)dxX0; (void)ws; (void)ws_bytes;
-  (void)stream;
-  return KF_E_UNSUPPORTED;
+  if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
+  if (in->n < 0) return KF_E_INVALID;
+  if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
+  if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
+  if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
+    return KF_E_INVALID;
+  size_t need = 0;
+  kf_workspace_size(ctx, KF_OP_FIT_BACKWARD, in, &need);
+  int rc = check_ws(ws, ws_bytes, need);
+  if (rc != KF_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base);
+  const float* align = params ? params->align : nullptr;
+  const float* xX0 = params ? params->xX0 : nullptr;
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+    return KF_E_HIP;
+  const kfd::Model md = model_of(ctx);
+  kfi::AdjArgs a;
+  a.n = in->n;
+  a.nl = ctx->g.n_layers;
+  a.k.kB = md.kB;
+  a.k.v_r = md.v_r;
+  a.k.v_rphi = md.v_rphi;
+  a.k.v_z = md.v_z;
+  a.k.mass2 = md.mass2;
+  a.srphi = ctx->g.sigma_rphi_cm;
+  a.sz = ctx->g.sigma_z_cm;
+  a.dr02 = md.dr02;
+  a.hits = in->hits;
+  a.mask = in->hit_mask;
+  a.ndf = fwd->ndf;
+  a.status = fwd->status;
+  a.ckpt = fwd->ckpt;
+  a.dchi2 = dchi2;
+  a.layers = layers;
+  a.part = reinterpret_cast<float*>(base + fit_ws_bytes());
+  return kfi::launch_adjoint(a, dalign, dxX0, st) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
 const char* kf_strerror(int code) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kf_adjoint.h"
 #include "kf_device.h"
 
 namespace kfi {
@@ -66,6 +67,22 @@ struct FindArgs {
   uint32_t* status;
 };
 
+struct AdjArgs {
+  int64_t n;
+  int32_t nl;
+  kfa::Consts<float> k;
+  float srphi, sz, dr02;
+  const float* hits;
+  const uint32_t* mask;
+  const int32_t* ndf;
+  const uint32_t* status;
+  const float* ckpt;
+  const float* dchi2;
+  const kfd::LayerK* layers;
+  float* part;  // [L][5][n] per-track gradient contributions
+};
+
+hipError_t launch_adjoint(const AdjArgs& a, float* dalign, float* dxX0, hipStream_t stream);
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
 size_t find_lds_bytes(int nl);
 hipError_t find_max_blocks(int nl, int* blocks_per_cu);

@@ -1,0 +1,67 @@
+"""The library's hand-written adjoint of the fit (kf_adjoint.h), instantiated in FP64
+on the host, equals the oracle's forward-mode dual-number gradient of the same total
+chi2 (no GPU).  Both differentiate the same filter with independent code, so they
+agree to rounding."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def host_adjoint(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("adj") / "libadjoint_host.so")
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-fPIC", "-shared",
+                           os.path.join(HERE, "adjoint_host.hip"), "-o", out],
+                          stderr=subprocess.DEVNULL)
+    lib = C.CDLL(out)
+    return lib
+
+
+def run_host(lib, geom, ts, align, xX0, w=None):
+    L = geom.n_layers
+    n = ts.hits.shape[2]
+    ga = np.zeros((L, 4))
+    gx = np.zeros(L)
+    hits = np.ascontiguousarray(ts.hits, np.float32)
+    mask = np.ascontiguousarray(ts.hit_mask, np.uint32)
+    f64 = lambda a: np.ascontiguousarray(a, np.float64)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    rad, al, xx = f64(geom.radius), f64(align), f64(xX0)
+    ww = None if w is None else f64(w)
+    rc = lib.adjoint_host_fp64(C.c_int(L), p(rad), C.c_double(geom.B), C.c_double(geom.sigma_rphi),
+                               C.c_double(geom.sigma_z), C.c_double(geom.sigma_r), C.c_double(geom.mass), p(al),
+                               p(xx), C.c_long(n), p(hits), p(mask), None if ww is None else p(ww), p(ga), p(gx))
+    assert rc == 0
+    return ga, gx
+
+
+@pytest.mark.parametrize("at_truth", [False, True])
+def test_host_adjoint_equals_dual_gradient(host_adjoint, at_truth):
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    _, ts = synth.fit_workload(4, n=60, align=a_true)
+    align = a_true if at_truth else np.zeros_like(a_true)
+    w = np.random.default_rng(3).uniform(0.5, 1.5, ts.hits.shape[2])
+    ga, gx = run_host(host_adjoint, geom, ts, align, geom.xX0, w)
+    ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w)
+    scale = max(np.abs(ra).max(), np.abs(rx).max())
+    np.testing.assert_allclose(ga, ra, rtol=1e-9, atol=1e-10 * scale)
+    np.testing.assert_allclose(gx, rx, rtol=1e-9, atol=1e-10 * scale)
+
+
+def test_host_adjoint_no_material(host_adjoint):
+    geom = synth.workload_geometry(1)
+    _, ts = synth.fit_workload(1, n=50)
+    align = synth.misalignment(geom.n_layers) * 0.5
+    ga, gx = run_host(host_adjoint, geom, ts, align, np.zeros(geom.n_layers))
+    ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, np.zeros(geom.n_layers))
+    scale = np.abs(ra).max()
+    np.testing.assert_allclose(ga, ra, rtol=1e-9, atol=1e-10 * scale)
