@@ -8,7 +8,9 @@ inflated prior.  Synthetic, seeded data (see synth/).
 
 One step = one kf_fit launch over all tracks (inputs resident in HBM).  The metric is
 Kalman propagate+update steps per second: every hit used by the filter is one step.
-Prints one JSON line.
+The same JSON line also reports track finding (events/s for one event of 5 000 tracks
+and for 64 events of uneven pileup in one call versus one call per event) and the
+adjoint's cost relative to the forward fit on 1e5 tracks.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -36,6 +38,28 @@ FLOPS_SEED = 60
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of one fit_kernel launch on the 1e6-track workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean of 5 launches), each scaled by
+# what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
+# WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
+FIT_TRAFFIC = {"sources": "dba0d043d2d0a82c", "tracks": 1_000_000,
+               "fetch_kib": 102694.2, "write_kib": 117187.5,
+               "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
+FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
+
+
+def fit_traffic_bytes(n_tracks):
+    """Measured HBM bytes per fit launch, or None if the kernel or workload differs."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in FIT_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != FIT_TRAFFIC["sources"] or n_tracks != FIT_TRAFFIC["tracks"]:
+        return None
+    t = FIT_TRAFFIC
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def algorithmic_flops(n_hits_per_track, xX0_positive=True):
     n = np.asarray(n_hits_per_track, np.int64)
@@ -50,6 +74,109 @@ def algorithmic_bytes(n_tracks, n_layers, n_steps):
     return float(n_steps * 12 + n_tracks * (4 + 24 + 84 + 12))
 
 
+def _time_launches(fn, steps, warmup):
+    """Average device time (s) of fn() over `steps` launches after `warmup`, from HIP
+    events on the current stream, plus the wall-clock seconds of the timed loop."""
+    import torch
+    for _ in range(max(1, warmup)):
+        fn()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        fn()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
+    return float(per.mean()), wall
+
+
+def bench_find(steps, warmup):
+    """Track finding: one event of 5 000 tracks, and 64 events of uneven pileup in one
+    call (find + refit of each seed's best candidate) against a loop of per-event calls."""
+    import torch
+
+    import synth
+    from paper_1906_11744_amd import Context
+    dev = torch.device("cuda:0")
+    res = {}
+    geom, ev = synth.find_workload(3)
+    kf = Context(geom)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    xX0 = t(geom.xX0.astype(np.float32))
+    args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
+    out = kf.find(*args, xX0=xX0)
+    avg, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
+    res["single_event_5000_tracks"] = {"events_per_s": 1.0 / avg, "ms_per_event": avg * 1e3,
+                                       "seeds": int(ev.seed_hits.shape[1])}
+    t0 = time.time()
+    geom, ev = synth.find_workload(5)
+    print(f"# generated 64 events ({ev.seed_hits.shape[1]} seeds, {ev.hits.shape[1]} hits) in "
+          f"{time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    kf = Context(geom)
+    xX0 = t(geom.xX0.astype(np.float32))
+    args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
+    out = kf.find(*args, xX0=xX0, refit=True)
+    avg_b, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
+    # per-event calls on the same data
+    E = ev.hit_off.shape[0]
+    per_event = []
+    for e in range(E):
+        sel = np.nonzero(ev.seed_event == e)[0]
+        lo, hi = int(ev.hit_off[e, 0]), int(ev.hit_off[e, -1])
+        per_event.append((t(ev.hits[:, lo:hi]), t(ev.hit_off[e:e + 1] - lo),
+                          t((ev.seed_hits[:, sel] - lo).astype(np.int32)),
+                          t(np.zeros(sel.shape[0], np.int32))))
+    outs = [kf.find(*a, xX0=xX0, refit=True) for a in per_event]
+
+    def loop():
+        for a, o in zip(per_event, outs):
+            kf.find(*a, xX0=xX0, refit=True, out=o)
+    avg_l, _ = _time_launches(loop, max(3, steps // 4), warmup)
+    res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3,
+                                "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1])}
+    res["per_event_loop_64_events"] = {"events_per_s": E / avg_l, "ms_total": avg_l * 1e3}
+    res["batched_speedup"] = avg_l / avg_b
+    return res
+
+
+def bench_grad(steps, warmup):
+    """Differentiable fit: 1e5 misaligned tracks; forward (fit with checkpoints) and the
+    adjoint (kf_fit_backward), each timed alone."""
+    import torch
+
+    import synth
+    from paper_1906_11744_amd import Context
+    dev = torch.device("cuda:0")
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    _, ts = synth.fit_workload(4, align=a_true)
+    kf = Context(geom)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    hits, mask = t(ts.hits), t(ts.hit_mask.view(np.int32))
+    al, xX0 = t(np.zeros((geom.n_layers, 4), np.float32)), t(geom.xX0.astype(np.float32))
+    fwd = kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True)
+    w = torch.ones(ts.hits.shape[2], dtype=torch.float32, device=dev)
+    t_f, _ = _time_launches(lambda: kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
+    t_b, _ = _time_launches(lambda: kf.fit_backward(hits, mask, fwd, w, align=al, xX0=xX0), steps, warmup)
+    return {"tracks": int(ts.hits.shape[2]), "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
+            "backward_over_forward": t_b / t_f}
+
+
+def copy_calibration(steps):
+    """A plain device copy of 1 GiB, `steps` times: the reference kernel whose HBM
+    counters (FETCH_SIZE, WRITE_SIZE) calibrate those of the fit kernel."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    avg, _ = _time_launches(lambda: b.copy_(a), steps, 1)
+    return {"copy_bytes_each_way": 4 * n, "avg_ms": avg * 1e3, "GB_per_s": 8 * n / avg / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +184,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "copy"], default="all")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the fit shards tracks across GPUs with no exchange, "
@@ -68,78 +196,74 @@ def main():
     import synth
     from paper_1906_11744_amd import Context
 
-    t0 = time.time()
-    geom, ts = synth.fit_workload(2, n=args.tracks)
-    print(f"# generated {args.tracks} tracks in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    dev = torch.device("cuda:0")
-    ctx = Context(geom)
-    hits = torch.from_numpy(np.ascontiguousarray(ts.hits)).to(dev)
-    mask = torch.from_numpy(ts.hit_mask.view(np.int32)).to(dev)
-    xX0 = torch.from_numpy(geom.xX0.astype(np.float32)).to(dev)
-    n = args.tracks
-    out = None
-    for _ in range(max(1, args.warmup)):
-        out = ctx.fit(hits, mask, xX0=xX0, out=out)
-    torch.cuda.synchronize()
-    ndf = out["ndf"].cpu().numpy()
-    status = out["status"].cpu().numpy().view(np.uint32)
-    n_hits = np.where(status & 16, 0, (ndf + 5) // 2)
-    steps_per_launch = int(n_hits.sum())
-    flops = algorithmic_flops(n_hits)
-    nbytes = algorithmic_bytes(n, geom.n_layers, steps_per_launch)
-
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        ctx.fit(hits, mask, xX0=xX0, out=out)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    per = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3   # s per launch
-    ms_per_step = wall / args.steps * 1e3
-    value = steps_per_launch * args.steps / wall
-    avg = float(per.mean())
-    achieved_tflops = flops / avg / 1e12
-
-    res = {
-        "metric": "KF propagate+update steps/s (FP32 vs oracle tol)",
-        "value": value,
-        "unit": "steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "fit: 1e6 tracks x 17 barrel layers (4-110 cm), B=3.8 T, x/X0=0.02, "
-                               "pT log-uniform 0.5-50 GeV, |eta|<1.5, seeds from first 3 hits (10x cov)",
-                   "tracks": n, "layers": geom.n_layers, "kalman_steps_per_launch": steps_per_launch},
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "fit_kernel", "avg_launch_ms": avg * 1e3,
-                     "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
-                     "hbm_frac": nbytes / avg / 1e9 / PEAK_HBM_GBS},
-    }
-    if not args.no_cpu_baseline:
-        import oracle
-        sample = min(n, 200_000)
-        idx = np.arange(sample)
-        h = np.ascontiguousarray(ts.hits[:, :, idx])
-        m = ts.hit_mask[idx]
-        t1 = time.perf_counter()
-        ref = oracle.fit(geom, h, m)
-        dt = time.perf_counter() - t1
-        ref_steps = int(np.where(ref["status"] & 16, 0, (ref["ndf"] + 5) // 2).sum())
-        res["cpu_baseline"] = {"value": ref_steps / dt, "unit": "steps/s", "cores": oracle.num_threads(),
-                               "kind": "oracle",
-                               "sample": f"first {sample} tracks of the same workload, FP64 C++ oracle, "
-                                         f"{dt:.1f} s"}
+    res = None
+    if args.only in ("all", "fit"):
+        t0 = time.time()
+        geom, ts = synth.fit_workload(2, n=args.tracks)
+        print(f"# generated {args.tracks} tracks in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+        dev = torch.device("cuda:0")
+        ctx = Context(geom)
+        hits = torch.from_numpy(np.ascontiguousarray(ts.hits)).to(dev)
+        mask = torch.from_numpy(ts.hit_mask.view(np.int32)).to(dev)
+        xX0 = torch.from_numpy(geom.xX0.astype(np.float32)).to(dev)
+        n = args.tracks
+        out = ctx.fit(hits, mask, xX0=xX0)
+        torch.cuda.synchronize()
+        ndf = out["ndf"].cpu().numpy()
+        status = out["status"].cpu().numpy().view(np.uint32)
+        n_hits = np.where(status & 16, 0, (ndf + 5) // 2)
+        steps_per_launch = int(n_hits.sum())
+        flops = algorithmic_flops(n_hits)
+        nbytes = algorithmic_bytes(n, geom.n_layers, steps_per_launch)
+        avg, wall = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, out=out), args.steps, args.warmup)
+        value = steps_per_launch * args.steps / wall
+        achieved_tflops = flops / avg / 1e12
+        res = {
+            "metric": "KF propagate+update steps/s (FP32 vs oracle tol)",
+            "value": value,
+            "unit": "steps/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "fit: 1e6 tracks x 17 barrel layers (4-110 cm), B=3.8 T, x/X0=0.02, "
+                                   "pT log-uniform 0.5-50 GeV, |eta|<1.5, seeds from first 3 hits (10x cov)",
+                       "tracks": n, "layers": geom.n_layers, "kalman_steps_per_launch": steps_per_launch},
+            "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": fit_traffic_bytes(n),
+                         "traffic_unit": "B per launch",
+                         "kernel": "fit_kernel", "avg_launch_ms": avg * 1e3,
+                         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+                         "hbm_frac": nbytes / avg / 1e9 / PEAK_HBM_GBS},
+        }
+        if not args.no_cpu_baseline:
+            import oracle
+            sample = min(n, 200_000)
+            h = np.ascontiguousarray(ts.hits[:, :, :sample])
+            m = ts.hit_mask[:sample]
+            t1 = time.perf_counter()
+            ref = oracle.fit(geom, h, m)
+            dt = time.perf_counter() - t1
+            ref_steps = int(np.where(ref["status"] & 16, 0, (ref["ndf"] + 5) // 2).sum())
+            res["cpu_baseline"] = {"value": ref_steps / dt, "unit": "steps/s", "cores": oracle.num_threads(),
+                                   "kind": "oracle",
+                                   "sample": f"first {sample} tracks of the same workload, FP64 C++ oracle "
+                                             f"(OpenMP over tracks), {dt:.1f} s"}
+        del hits, mask, out
+    else:
+        res = {"metric": "KF propagate+update steps/s (FP32 vs oracle tol)", "value": None, "unit": "steps/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup}
+    if args.only == "copy":
+        res["copy_calibration"] = copy_calibration(args.steps)
+    if args.only in ("all", "find"):
+        res["find"] = bench_find(args.steps, args.warmup)
+    if args.only in ("all", "grad"):
+        res["adjoint"] = bench_grad(args.steps, args.warmup)
     print(json.dumps(res), flush=True)
 
 

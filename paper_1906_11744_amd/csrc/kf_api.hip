@@ -128,7 +128,8 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
     case KF_OP_FIT_BACKWARD: {
       const kf_fit_in* f = static_cast<const kf_fit_in*>(in);
       const size_t n = (size_t)(f->n > 0 ? f->n : 0);
-      *bytes = fit_ws_bytes() + round_up((size_t)ctx->g.n_layers * 5 * n * sizeof(float));
+      *bytes = fit_ws_bytes() + round_up((size_t)ctx->g.n_layers * 5 * (size_t)kfi::adjoint_blocks((int64_t)n) *
+                                         sizeof(double));
       return KF_OK;
     }
     default:
@@ -315,7 +316,8 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   a.ckpt = fwd->ckpt;
   a.dchi2 = dchi2;
   a.layers = layers;
-  a.part = reinterpret_cast<float*>(base + fit_ws_bytes());
+  a.n_blocks = kfi::adjoint_blocks(in->n);
+  a.part = reinterpret_cast<double*>(base + fit_ws_bytes());
   return kfi::launch_adjoint(a, dalign, dxX0, st) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 

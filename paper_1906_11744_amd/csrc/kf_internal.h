@@ -79,8 +79,12 @@ struct AdjArgs {
   const float* ckpt;
   const float* dchi2;
   const kfd::LayerK* layers;
-  float* part;  // [L][5][n] per-track gradient contributions
+  int64_t n_blocks;  // adjoint_blocks(n)
+  double* part;      // [L][5][n_blocks] per-block gradient sums
 };
+
+// Blocks of the adjoint kernel for n tracks (one FP64 partial per block and parameter).
+int64_t adjoint_blocks(int64_t n);
 
 hipError_t launch_adjoint(const AdjArgs& a, float* dalign, float* dxX0, hipStream_t stream);
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
