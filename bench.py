@@ -108,10 +108,10 @@ def bench_find(steps, warmup):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     xX0 = t(geom.xX0.astype(np.float32))
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
-    out = kf.find(*args, xX0=xX0)
+    out = kf.find(*args, xX0=xX0, autotune=True)
     avg, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
     res["single_event_5000_tracks"] = {"events_per_s": 1.0 / avg, "ms_per_event": avg * 1e3,
-                                       "seeds": int(ev.seed_hits.shape[1])}
+                                       "seeds": int(ev.seed_hits.shape[1]), "config": kf.find_config()}
     t0 = time.time()
     geom, ev = synth.find_workload(5)
     print(f"# generated 64 events ({ev.seed_hits.shape[1]} seeds, {ev.hits.shape[1]} hits) in "
@@ -119,7 +119,7 @@ def bench_find(steps, warmup):
     kf = Context(geom)
     xX0 = t(geom.xX0.astype(np.float32))
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
-    out = kf.find(*args, xX0=xX0, refit=True)
+    out = kf.find(*args, xX0=xX0, refit=True, autotune=True)
     avg_b, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
     # per-event calls on the same data
     E = ev.hit_off.shape[0]
@@ -136,7 +136,7 @@ def bench_find(steps, warmup):
         for a, o in zip(per_event, outs):
             kf.find(*a, xX0=xX0, refit=True, out=o)
     avg_l, _ = _time_launches(loop, max(3, steps // 4), warmup)
-    res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3,
+    res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3, "config": kf.find_config(),
                                 "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1])}
     res["per_event_loop_64_events"] = {"events_per_s": E / avg_l, "ms_total": avg_l * 1e3}
     res["batched_speedup"] = avg_l / avg_b

@@ -19,7 +19,7 @@
  *     align[L] = (dx, dy, dz, dphi) moves its axis to (dx, dy), shifts its hits by dz
  *     and rotates them by dphi about the axis.  Hits are given in the nominal frame.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream) and
- *     never synchronise.  The library allocates no device memory per call: scratch
+ *     never synchronise (kf_find_autotune excepted).  The library allocates no device memory per call: scratch
  *     space is the caller's `ws` of at least kf_workspace_size() bytes, 256-byte
  *     aligned.  Host-detectable errors return a negative KF_E_* code before anything
  *     is launched; numerical outcomes are reported per track in `status` bits.
@@ -160,6 +160,22 @@ int kf_ctx_destroy(kf_ctx* ctx);
  * A threshold > 1 forces the FP64 path for every update. */
 int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold);
 
+/* Launch configuration of kf_find, held by the context.  Outputs do not depend on it
+ * (same bits for every valid configuration); only the time does.
+ *   wide_window_bins: a candidate whose search window overlaps more than this many
+ *     bins is scanned by all 64 lanes of its wave instead of its own lane (>= 0;
+ *     default 16; 0 sends every window to the wave-wide scan).
+ *   blocks_per_cu: persistent find workgroups per compute unit (0 = as many as fit;
+ *     default 0). */
+typedef struct kf_find_config {
+  int32_t wide_window_bins;
+  int32_t blocks_per_cu;
+} kf_find_config;
+
+/* Set / read the context's kf_find configuration.  KF_E_INVALID for negative fields. */
+int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg);
+int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg);
+
 /* Workspace bytes needed by op (KF_OP_*) for the input `in` (a kf_fit_in or
  * kf_find_in; for KF_OP_FIT_BACKWARD the kf_fit_in of the forward call). */
 int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes);
@@ -188,6 +204,15 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
  * layer or when propagation fails and is carried unchanged. */
 int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
             void* ws, size_t ws_bytes, void* stream);
+
+/* Autotuner of kf_find's configuration for inputs like `in`: runs kf_find (arguments
+ * as for kf_find; `out` receives the usual results) under each candidate configuration
+ * (wide_window_bins 4, 8, 16, 32, 64 x blocks_per_cu 0, 1), times two calls of each
+ * with HIP events on `stream`, keeps the fastest in the context and copies it to
+ * *best (if not NULL).  Unlike every other call it SYNCHRONISES on `stream`.  On error
+ * the previous configuration is kept and the error code returned. */
+int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
+                     void* ws, size_t ws_bytes, void* stream, kf_find_config* best);
 
 /* Adjoint of kf_fit (seed_from_hits must be 1 and ckpt filled by the forward call):
  * given dchi2 [n] = dLoss/dchi2_i, accumulates dLoss/dalign [L][4] and dLoss/dxX0 [L]

@@ -10,8 +10,10 @@
 struct kf_ctx {
   kf_geometry g;
   float det_thr;
-  int grid_device = -1;   // device the persistent grid below was sized for
-  int grid_blocks = 0;
+  kf_find_config fcfg{16, 0};
+  int grid_device = -1;   // device the occupancy figures below were taken on
+  int grid_cus = 0;       // compute units
+  int grid_per_cu = 0;    // find workgroups that fit on one compute unit
 };
 
 namespace {
@@ -68,7 +70,8 @@ FindWs find_ws(const kf_ctx* c, const kf_find_in* in) {
   return w;
 }
 
-// Persistent find grid: as many workgroups as fit on the device at once.
+// Persistent find grid: blocks_per_cu workgroups per compute unit, at most as many as
+// fit at once.
 int persistent_grid(kf_ctx* c, int nl, int* grid) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return KF_E_HIP;
@@ -76,10 +79,12 @@ int persistent_grid(kf_ctx* c, int nl, int* grid) {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return KF_E_HIP;
     if (kfi::find_max_blocks(nl, &per) != hipSuccess) return KF_E_HIP;
-    c->grid_blocks = cus * (per > 0 ? per : 1);
+    c->grid_cus = cus;
+    c->grid_per_cu = per > 0 ? per : 1;
     c->grid_device = dev;
   }
-  *grid = c->grid_blocks;
+  const int want = c->fcfg.blocks_per_cu;
+  *grid = c->grid_cus * (want > 0 && want < c->grid_per_cu ? want : c->grid_per_cu);
   return KF_OK;
 }
 
@@ -113,6 +118,18 @@ int kf_ctx_destroy(kf_ctx* ctx) {
 int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold) {
   if (!ctx || !(det_threshold >= 0.f) || !isfinite(det_threshold)) return KF_E_INVALID;
   ctx->det_thr = det_threshold;
+  return KF_OK;
+}
+
+int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg) {
+  if (!ctx || !cfg || cfg->wide_window_bins < 0 || cfg->blocks_per_cu < 0) return KF_E_INVALID;
+  ctx->fcfg = *cfg;
+  return KF_OK;
+}
+
+int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg) {
+  if (!ctx || !cfg) return KF_E_INVALID;
+  *cfg = ctx->fcfg;
   return KF_OK;
 }
 
@@ -225,6 +242,7 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
   f.keep = in->keep;
   f.max_miss = in->max_miss;
   f.n_events = in->n_events;
+  f.wide_bins = ctx->fcfg.wide_window_bins;
   f.chi2_cut = in->chi2_cut;
   f.nsigma = in->nsigma;
   f.md = model_of(ctx);
@@ -319,6 +337,51 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   a.n_blocks = kfi::adjoint_blocks(in->n);
   a.part = reinterpret_cast<double*>(base + fit_ws_bytes());
   return kfi::launch_adjoint(a, dalign, dxX0, st) == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
+                     void* ws, size_t ws_bytes, void* stream, kf_find_config* best) {
+  if (!ctx) return KF_E_INVALID;
+  static const int kWide[] = {4, 8, 16, 32, 64};
+  static const int kPer[] = {0, 1};
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return KF_E_HIP;
+  }
+  const kf_find_config saved = ctx->fcfg;
+  kf_find_config pick = saved;
+  float best_ms = INFINITY;
+  int rc = KF_OK;
+  for (int per : kPer) {
+    for (int wide : kWide) {
+      ctx->fcfg = kf_find_config{wide, per};
+      rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);  // warm-up, and validates the call
+      if (rc != KF_OK) break;
+      float ms = INFINITY;
+      for (int rep = 0; rep < 2 && rc == KF_OK; ++rep) {
+        if (hipEventRecord(e0, st) != hipSuccess) rc = KF_E_HIP;
+        if (rc == KF_OK) rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);
+        if (rc == KF_OK && hipEventRecord(e1, st) != hipSuccess) rc = KF_E_HIP;
+        if (rc == KF_OK && hipEventSynchronize(e1) != hipSuccess) rc = KF_E_HIP;
+        float t = 0.f;
+        if (rc == KF_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = KF_E_HIP;
+        if (rc == KF_OK && t < ms) ms = t;
+      }
+      if (rc != KF_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        pick = ctx->fcfg;
+      }
+    }
+    if (rc != KF_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->fcfg = rc == KF_OK ? pick : saved;
+  if (rc == KF_OK && best) *best = pick;
+  return rc;
 }
 
 const char* kf_strerror(int code) {

@@ -21,6 +21,22 @@ constexpr int kGroup = 8;        // lanes per seed (>= keep)
 constexpr int kTileSeeds = 32;   // seeds per 256-lane workgroup
 constexpr int kMaxList = 8;      // hit branches kept per candidate
 
+// A candidate whose window overlaps more than FindArgs::wide_bins bins is scanned by
+// its whole wave: its window and the quantities its chi2 needs go to LDS, the 64
+// lanes split its hits, and their sorted lists are merged into the candidate's.
+constexpr int kWideStride = 128;  // bytes reserved per lane slot
+struct alignas(8) WideWin {
+  float phip, zp, wphi, wz;
+  int32_t blo, bhi, zlo, zhi, e;
+  float c2;
+  float x[3], xl[3];
+  float rho, rx, ry;
+  float Si00, Si11, Si12, Si22;
+  int32_t fp64;
+  double dSi11, dSi12, dSi22;
+};
+static_assert(sizeof(WideWin) <= kWideStride, "WideWin layout");
+
 __device__ __forceinline__ int bin_index(float v, float lo, float scale, int nb) {
   const int b = (int)floorf((v - lo) * scale);
   return b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
@@ -102,9 +118,16 @@ __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void find_kernel(FindArgs a) {
-  // backpointer of every (layer, slot): ((hit + 2) << 3) | parent slot, hit >= -2
-  extern __shared__ int32_t bp[];  // [nl][256]
+__global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
+  // LDS: wide-window slots [256] x 128 B, stashed branch lists (chi2 [8][256],
+  // hit [8][256], count [256]), backpointers [nl][256] of every (layer, slot):
+  // ((hit + 2) << 3) | parent slot, hit >= -2.
+  extern __shared__ __align__(16) unsigned char lds[];
+  WideWin* const ww = reinterpret_cast<WideWin*>(lds);
+  float* const stc = reinterpret_cast<float*>(lds + 256 * kWideStride);
+  int32_t* const sti = reinterpret_cast<int32_t*>(stc + kMaxList * 256);
+  int32_t* const stn = sti + kMaxList * 256;
+  int32_t* const bp = stn + 256;
   __shared__ int tile_sh;
   const int tid = threadIdx.x;
   const int slot = tid & (kGroup - 1);
@@ -190,6 +213,39 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a) {
       }
       int nlist = 0;
       bool predicted = false;
+      bool wide = false;
+      // One hit of the window: rectangle test, chi2 with the candidate's S^-1, and the
+      // sorted insertion of a passing branch into (bc, bi).  Slot t keeps its entry if
+      // that entry precedes the new one, takes the new one if only the entry before it
+      // does, and otherwise takes the entry before it: one select per slot, no element
+      // moves under a lane mask (register-pair copies followed by a partial overwrite
+      // of the same pair have lost the new element on gfx950).
+      auto consider = [&](int q, const kfd::Trk& kk, const kfd::Frame& ff, const kfd::Pred& pp, float php,
+                          float zpp, float wph, float wzz, float cbase) __attribute__((always_inline)) {
+        const float4 rec = a.brec[q];
+        const float dphi = kfd::wrap_pi(rec.w - php);
+        const float dz = rec.z - zpp;
+        if (!(fabsf(dphi) <= wph && fabsf(dz) <= wzz)) return;
+        const kfd::Resid r = kfd::residual(kk, ff, ly, pp, rec.x, rec.y, rec.z);
+        if (!(r.chi2 < a.chi2_cut)) return;
+        const float cc = cbase + r.chi2;
+        const int hh = a.bidx[q];
+        bool prev_lt = true;
+        float oc = 0.f;
+        int oh = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxList; ++t) {
+          const bool lt = t < nlist && key_lt(bc[t], bi[t], cc, hh);
+          const float ct = bc[t];
+          const int ht = bi[t];
+          bc[t] = lt ? ct : (prev_lt ? cc : oc);
+          bi[t] = lt ? ht : (prev_lt ? hh : oh);
+          prev_lt = lt;
+          oc = ct;
+          oh = ht;
+        }
+        nlist = nlist < kMaxList ? nlist + 1 : kMaxList;
+      };
       if (mode == LIVE) {
         kfd::Step stp;
         if (kfd::crossing(k, ly, a.md.kB, stp)) {
@@ -217,45 +273,139 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a) {
               bhi = a.nphi - 1;
             }
           }
-          const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
-          for (int b = blo; b <= bhi; ++b) {
-            const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
-            const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
-            for (int q = q0; q < q1; ++q) {
-              const float4 rec = a.brec[q];
-              const float dphi = kfd::wrap_pi(rec.w - phip);
-              const float dz = rec.z - zp;
-              if (!(fabsf(dphi) <= wphi && fabsf(dz) <= wz)) continue;
-              const kfd::Resid r = kfd::residual(k, f, ly, p, rec.x, rec.y, rec.z);
-              if (!(r.chi2 < a.chi2_cut)) continue;
-              const float cc = c2 + r.chi2;
-              const int hh = a.bidx[q];
-              // Sorted insertion written as one select per slot: slot t keeps its entry
-              // if that entry precedes the new one, takes the new one if only the entry
-              // before it does, and otherwise takes the entry before it.  (No element
-              // moves under a lane mask: register-pair copies followed by a partial
-              // overwrite of the same pair have lost the new element on gfx950.)
-              bool prev_lt = true;
-              float oc = 0.f;
-              int oh = 0;
+          if ((bhi - blo + 1) * (zhi - zlo + 1) > a.wide_bins) {
+            wide = true;
+            WideWin w;
+            w.phip = phip;
+            w.zp = zp;
+            w.wphi = wphi;
+            w.wz = wz;
+            w.blo = blo;
+            w.bhi = bhi;
+            w.zlo = zlo;
+            w.zhi = zhi;
+            w.e = e;
+            w.c2 = c2;
 #pragma unroll
-              for (int t = 0; t < kMaxList; ++t) {
-                const bool lt = t < nlist && key_lt(bc[t], bi[t], cc, hh);
-                const float ct = bc[t];
-                const int ht = bi[t];
-                bc[t] = lt ? ct : (prev_lt ? cc : oc);
-                bi[t] = lt ? ht : (prev_lt ? hh : oh);
-                prev_lt = lt;
-                oc = ct;
-                oh = ht;
-              }
-              nlist = nlist < kMaxList ? nlist + 1 : kMaxList;
+            for (int q = 0; q < 3; ++q) {
+              w.x[q] = k.x[q];
+              w.xl[q] = k.xl[q];
+            }
+            w.rho = f.rho;
+            w.rx = f.rx;
+            w.ry = f.ry;
+            w.Si00 = p.Si00;
+            w.Si11 = p.Si11;
+            w.Si12 = p.Si12;
+            w.Si22 = p.Si22;
+            w.fp64 = p.fp64 ? 1 : 0;
+            w.dSi11 = p.dSi11;
+            w.dSi12 = p.dSi12;
+            w.dSi22 = p.dSi22;
+            ww[tid] = w;
+          } else {
+            const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
+            for (int b = blo; b <= bhi; ++b) {
+              const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
+              const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
+              for (int q = q0; q < q1; ++q) consider(q, k, f, p, phip, zp, wphi, wz, c2);
             }
           }
         } else {
           mode = TERM;
           st |= kfd::ST_PROP_FAIL;
         }
+      }
+      // ---- wide windows: each is scanned by the whole wave ----
+      unsigned long long wide_m = __ballot(wide);
+      if (wide_m != 0ull) {
+#pragma unroll
+        for (int t = 0; t < kMaxList; ++t) {
+          stc[t * 256 + tid] = bc[t];
+          sti[t * 256 + tid] = bi[t];
+        }
+        stn[tid] = nlist;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int wbase = tid & ~63;
+        while (wide_m != 0ull) {
+          const int c = __ffsll((unsigned long long)wide_m) - 1;
+          wide_m &= wide_m - 1ull;
+          const WideWin w = ww[wbase + c];
+          kfd::Trk kc;
+          kfd::Frame fc;
+          kfd::Pred pc;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            kc.x[q] = w.x[q];
+            kc.xl[q] = w.xl[q];
+          }
+          fc.rho = w.rho;
+          fc.rx = w.rx;
+          fc.ry = w.ry;
+          fc.cosa = 1.f;
+          pc.Si00 = w.Si00;
+          pc.Si11 = w.Si11;
+          pc.Si12 = w.Si12;
+          pc.Si22 = w.Si22;
+          pc.fp64 = w.fp64 != 0;
+          pc.dSi11 = w.dSi11;
+          pc.dSi12 = w.dSi12;
+          pc.dSi22 = w.dSi22;
+#pragma unroll
+          for (int t = 0; t < kMaxList; ++t) {
+            bc[t] = INFINITY;
+            bi[t] = 0x7fffffff;
+          }
+          nlist = 0;
+          const int32_t* boff = a.boff + ((int64_t)w.e * nl + l) * (nb_all + 1);
+          for (int b = w.blo; b <= w.bhi; ++b) {
+            const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
+            const int q0 = boff[pb * a.nz + w.zlo], q1 = boff[pb * a.nz + w.zhi + 1];
+            for (int q = q0 + lane; q < q1; q += 64) consider(q, kc, fc, pc, w.phip, w.zp, w.wphi, w.wz, w.c2);
+          }
+          // the candidate's list: kMaxList rounds of a 64-lane min over (chi2, hit) keys
+          int hd = 0, cnt = 0;
+          for (int r = 0; r < kMaxList; ++r) {
+            float hc = bc[0];
+            int hx = bi[0];
+#pragma unroll
+            for (int t = 1; t < kMaxList; ++t) {
+              if (hd == t) {
+                hc = bc[t];
+                hx = bi[t];
+              }
+            }
+            const bool has = hd < nlist;
+            const uint32_t mhi = has ? __float_as_uint(hc) : 0xffffffffu;
+            const uint32_t mlo = has ? (uint32_t)hx : 0xffffffffu;
+            const unsigned long long mine = ((unsigned long long)mhi << 32) | mlo;
+            unsigned long long key = mine;
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) {
+              const unsigned long long o = __shfl_xor(key, m, 64);
+              key = o < key ? o : key;
+            }
+            if (key == ~0ull) break;
+            if (mine == key) ++hd;
+            if (lane == c) {
+              stc[r * 256 + tid] = __uint_as_float((uint32_t)(key >> 32));
+              sti[r * 256 + tid] = (int32_t)(uint32_t)(key & 0xffffffffull);
+            }
+            ++cnt;
+          }
+          if (lane == c) stn[tid] = cnt;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int t = 0; t < kMaxList; ++t) {
+          bc[t] = stc[t * 256 + tid];
+          bi[t] = sti[t * 256 + tid];
+        }
+        nlist = stn[tid];
       }
       // ---- merge the group's branches: `keep` rounds of a 64-bit min over 8 lanes ----
       // The list is not shifted when its head is taken (register-array moves); the
@@ -289,10 +439,11 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a) {
           hc = c2;
           hn = nh;
         }
-        unsigned long long key = ~0ull;
-        if (hk != K_NONE)
-          key = ((unsigned long long)(255 - hn) << 40) | ((unsigned long long)__float_as_uint(hc) << 8) |
-                (unsigned long long)slot;
+        // 64-bit key built from two 32-bit halves chosen by selects
+        const bool has = hk != K_NONE;
+        const uint32_t khi = has ? ((uint32_t)(255 - hn) << 8) | (__float_as_uint(hc) >> 24) : 0xffffffffu;
+        const uint32_t klo = has ? (__float_as_uint(hc) << 8) | (uint32_t)slot : 0xffffffffu;
+        unsigned long long key = ((unsigned long long)khi << 32) | klo;
 #pragma unroll
         for (int m = 1; m < kGroup; m <<= 1) {
           const unsigned long long o = __shfl_xor(key, m, kGroup);
@@ -408,9 +559,15 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-size_t find_lds_bytes(int nl) { return (size_t)nl * 256 * sizeof(int32_t); }
+size_t find_lds_bytes(int nl) {
+  return (size_t)256 * kWideStride + (size_t)(2 * kMaxList + 1) * 256 * 4 + (size_t)nl * 256 * sizeof(int32_t);
+}
 
 hipError_t find_max_blocks(int nl, int* blocks_per_cu) {
+  // more than 64 KiB of dynamic LDS per workgroup (gfx950 has 160 KiB per CU)
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(find_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)find_lds_bytes(nl));
+  if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel, 256, find_lds_bytes(nl));
 }
 

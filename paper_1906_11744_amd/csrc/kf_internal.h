@@ -44,6 +44,7 @@ struct BinArgs {
 
 struct FindArgs {
   int32_t nl, nphi, nz, keep, max_miss, n_events;
+  int32_t wide_bins;  // windows over more bins than this are scanned by the whole wave
   float chi2_cut, nsigma;
   kfd::Model md;
   float srphi, sz;

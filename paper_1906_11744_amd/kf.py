@@ -80,11 +80,16 @@ def _lib():
         lib.kf_ctx_create.argtypes = [C.POINTER(Geometry), C.POINTER(C.c_void_p)]
         lib.kf_ctx_destroy.argtypes = [C.c_void_p]
         lib.kf_ctx_set_fallback_threshold.argtypes = [C.c_void_p, C.c_float]
+        lib.kf_ctx_set_find_config.argtypes = [C.c_void_p, C.POINTER(FindConfig)]
+        lib.kf_ctx_get_find_config.argtypes = [C.c_void_p, C.POINTER(FindConfig)]
         lib.kf_workspace_size.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]
         lib.kf_fit.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn), C.POINTER(FitOut),
                                C.c_void_p, C.c_size_t, C.c_void_p]
         lib.kf_find.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FindIn), C.POINTER(FindOut),
                                 C.c_void_p, C.c_size_t, C.c_void_p]
+        lib.kf_find_autotune.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FindIn),
+                                         C.POINTER(FindOut), C.c_void_p, C.c_size_t, C.c_void_p,
+                                         C.POINTER(FindConfig)]
         lib.kf_fit_backward.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn), C.POINTER(FitOut),
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         _LIB = lib
@@ -117,6 +122,10 @@ def _dev(t, dtype, shape=None, name="tensor"):
 def _stream(stream):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+class FindConfig(C.Structure):
+    _fields_ = [("wide_window_bins", C.c_int32), ("blocks_per_cu", C.c_int32)]
 
 
 class Context:
@@ -159,6 +168,21 @@ class Context:
     def set_fallback_threshold(self, det_threshold: float):
         _check(_lib().kf_ctx_set_fallback_threshold(self._h, float(det_threshold)),
                "kf_ctx_set_fallback_threshold")
+
+    def set_find_config(self, wide_window_bins=None, blocks_per_cu=None):
+        """kf_ctx_set_find_config; fields left None keep their current value."""
+        cfg = self.find_config()
+        if wide_window_bins is not None:
+            cfg["wide_window_bins"] = int(wide_window_bins)
+        if blocks_per_cu is not None:
+            cfg["blocks_per_cu"] = int(blocks_per_cu)
+        c = FindConfig(cfg["wide_window_bins"], cfg["blocks_per_cu"])
+        _check(_lib().kf_ctx_set_find_config(self._h, C.byref(c)), "kf_ctx_set_find_config")
+
+    def find_config(self):
+        c = FindConfig()
+        _check(_lib().kf_ctx_get_find_config(self._h, C.byref(c)), "kf_ctx_get_find_config")
+        return {"wide_window_bins": c.wide_window_bins, "blocks_per_cu": c.blocks_per_cu}
 
     def workspace(self, op, inp, device):
         nb = C.c_size_t(0)
@@ -213,9 +237,11 @@ class Context:
         return out
 
     def find(self, hits, hit_off, seed_hits, seed_event, align=None, xX0=None, chi2_cut=30.0, nsigma=3.0,
-             keep=6, max_miss=3, refit=False, out=None, stream=None):
+             keep=6, max_miss=3, refit=False, out=None, stream=None, autotune=False):
         """kf_find.  hits [3][H] float32, hit_off [E][L+1] int64, seed_hits [3][S] int32,
-        seed_event [S] int32.  Returns a dict of the kf_find_out arrays."""
+        seed_event [S] int32.  Returns a dict of the kf_find_out arrays.  With
+        autotune=True the call is kf_find_autotune (synchronising; the chosen
+        configuration stays in the context and is in find_config())."""
         L = self.n_layers
         dev = hits.device
         H = hits.shape[1]
@@ -246,8 +272,12 @@ class Context:
                         "rf_state", "rf_cov", "rf_chi2", "rf_ndf", "rf_status")])
         ws = self.workspace(KF_OP_FIND, fin, dev)
         p = self._params(align, xX0)
-        _check(_lib().kf_find(self._h, C.byref(p), C.byref(fin), C.byref(fo), C.c_void_p(ws.data_ptr()),
-                              ws.numel(), _stream(stream)), "kf_find")
+        if autotune:
+            _check(_lib().kf_find_autotune(self._h, C.byref(p), C.byref(fin), C.byref(fo), C.c_void_p(ws.data_ptr()),
+                                           ws.numel(), _stream(stream), None), "kf_find_autotune")
+        else:
+            _check(_lib().kf_find(self._h, C.byref(p), C.byref(fin), C.byref(fo), C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), _stream(stream)), "kf_find")
         return out
 
     def fit_backward(self, hits, hit_mask, fwd, dchi2, align=None, xX0=None, stream=None):
@@ -275,5 +305,6 @@ class Context:
 
 def exported_symbols():
     """Names the header declares (for the load check)."""
-    return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_workspace_size", "kf_fit",
-            "kf_find", "kf_fit_backward", "kf_strerror"]
+    return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_ctx_set_find_config",
+            "kf_ctx_get_find_config", "kf_workspace_size", "kf_fit", "kf_find", "kf_find_autotune",
+            "kf_fit_backward", "kf_strerror"]

@@ -160,3 +160,56 @@ def test_find_empty_and_invalid():
     assert out["n_cand"].numel() == 0
     with pytest.raises(KfError):
         ctx.find(to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event), keep=9)
+
+
+def test_find_independent_of_launch_configuration():
+    """Wave-wide scans of wide windows, the persistent grid size and the autotuner's
+    choice change the time only: every output bit is the same."""
+    need_gpu()
+    from paper_1906_11744_amd import Context
+    geom, ev = synth.find_workload(3, n_tracks=3000)
+    ctx = Context(geom)
+    args = (to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event))
+    xX0 = to_dev(geom.xX0.astype(np.float32))
+    ref = None
+    for wide, per in [(1 << 30, 0), (16, 0), (0, 0), (4, 1), (0, 1)]:
+        ctx.set_find_config(wide_window_bins=wide, blocks_per_cu=per)
+        out = ctx.find(*args, xX0=xX0, refit=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        if ref is None:
+            ref = got
+        for k in ref:
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{k} wide={wide} per={per}")
+    out = ctx.find(*args, xX0=xX0, refit=True, autotune=True)
+    torch.cuda.synchronize()
+    print("autotuned:", ctx.find_config())
+    for k in ref:
+        np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k], err_msg=f"{k} autotuned")
+
+
+def test_find_batched_equals_per_event():
+    """Events in one call give the same candidates, bit for bit, as one call per event
+    (hit indices rebased to the event's slice)."""
+    need_gpu()
+    from paper_1906_11744_amd import Context
+    geom, ev = synth.find_workload(5, n_tracks=500, n_events=5)
+    ctx = Context(geom)
+    xX0 = to_dev(geom.xX0.astype(np.float32))
+    allout = ctx.find(to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event), xX0=xX0,
+                      refit=True)
+    torch.cuda.synchronize()
+    allout = {k: v.cpu().numpy() for k, v in allout.items()}
+    for e in range(ev.hit_off.shape[0]):
+        sel = np.nonzero(ev.seed_event == e)[0]
+        lo, hi = int(ev.hit_off[e, 0]), int(ev.hit_off[e, -1])
+        o = ctx.find(to_dev(np.ascontiguousarray(ev.hits[:, lo:hi])), to_dev(ev.hit_off[e:e + 1] - lo),
+                     to_dev((ev.seed_hits[:, sel] - lo).astype(np.int32)), to_dev(np.zeros(sel.size, np.int32)),
+                     xX0=xX0, refit=True)
+        torch.cuda.synchronize()
+        for k, v in o.items():
+            v = v.cpu().numpy()
+            ref = allout[k][..., sel]
+            if k == "hit_idx":
+                v = np.where(v >= 0, v + lo, v)
+            np.testing.assert_array_equal(v, ref, err_msg=f"event {e} {k}")
