@@ -242,18 +242,22 @@ def main():
                          "hbm_frac": nbytes / avg / 1e9 / PEAK_HBM_GBS},
         }
         if not args.no_cpu_baseline:
+            # the oracle over the whole workload, pass after pass, until 10 s have elapsed
             import oracle
-            sample = min(n, 200_000)
-            h = np.ascontiguousarray(ts.hits[:, :, :sample])
-            m = ts.hit_mask[:sample]
+            h = np.ascontiguousarray(ts.hits)
             t1 = time.perf_counter()
-            ref = oracle.fit(geom, h, m)
-            dt = time.perf_counter() - t1
-            ref_steps = int(np.where(ref["status"] & 16, 0, (ref["ndf"] + 5) // 2).sum())
+            passes, ref_steps = 0, 0
+            while True:
+                ref = oracle.fit(geom, h, ts.hit_mask)
+                passes += 1
+                ref_steps += int(np.where(ref["status"] & 16, 0, (ref["ndf"] + 5) // 2).sum())
+                dt = time.perf_counter() - t1
+                if dt >= 10.0:
+                    break
             res["cpu_baseline"] = {"value": ref_steps / dt, "unit": "steps/s", "cores": oracle.num_threads(),
                                    "kind": "oracle",
-                                   "sample": f"first {sample} tracks of the same workload, FP64 C++ oracle "
-                                             f"(OpenMP over tracks), {dt:.1f} s"}
+                                   "sample": f"{passes} pass(es) over all {n} tracks of the same workload, FP64 C++ "
+                                             f"oracle (OpenMP over tracks), {dt:.1f} s"}
         del hits, mask, out
     else:
         res = {"metric": "KF propagate+update steps/s (FP32 vs oracle tol)", "value": None, "unit": "steps/s",
