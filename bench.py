@@ -110,7 +110,10 @@ def bench_find(steps, warmup):
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
     out = kf.find(*args, xX0=xX0, autotune=True)
     avg, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
-    res["single_event_5000_tracks"] = {"events_per_s": 1.0 / avg, "ms_per_event": avg * 1e3,
+    kf.set_find_config(use_graph=1)
+    avg_g, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
+    res["single_event_5000_tracks"] = {"events_per_s": 1.0 / avg_g, "ms_per_event": avg_g * 1e3,
+                                       "ms_per_event_without_graph": avg * 1e3,
                                        "seeds": int(ev.seed_hits.shape[1]), "config": kf.find_config()}
     t0 = time.time()
     geom, ev = synth.find_workload(5)
@@ -120,6 +123,7 @@ def bench_find(steps, warmup):
     xX0 = t(geom.xX0.astype(np.float32))
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
     out = kf.find(*args, xX0=xX0, refit=True, autotune=True)
+    kf.set_find_config(use_graph=1)
     avg_b, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
     # per-event calls on the same data
     E = ev.hit_off.shape[0]
@@ -130,13 +134,15 @@ def bench_find(steps, warmup):
         per_event.append((t(ev.hits[:, lo:hi]), t(ev.hit_off[e:e + 1] - lo),
                           t((ev.seed_hits[:, sel] - lo).astype(np.int32)),
                           t(np.zeros(sel.shape[0], np.int32))))
+    cfg_batched = kf.find_config()
+    kf.set_find_config(use_graph=0)   # a graph per event would be captured anew at every call
     outs = [kf.find(*a, xX0=xX0, refit=True) for a in per_event]
 
     def loop():
         for a, o in zip(per_event, outs):
             kf.find(*a, xX0=xX0, refit=True, out=o)
     avg_l, _ = _time_launches(loop, max(3, steps // 4), warmup)
-    res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3, "config": kf.find_config(),
+    res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3, "config": cfg_batched,
                                 "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1])}
     res["per_event_loop_64_events"] = {"events_per_s": E / avg_l, "ms_total": avg_l * 1e3}
     res["batched_speedup"] = avg_l / avg_b

@@ -166,13 +166,23 @@ int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold);
  *     bins is scanned by all 64 lanes of its wave instead of its own lane (>= 0;
  *     default 16; 0 sends every window to the wave-wide scan).
  *   blocks_per_cu: persistent find workgroups per compute unit (0 = as many as fit;
- *     default 0). */
+ *     default 0).
+ *   use_graph: 1 = kf_find captures its launches (layer constants, binning, search,
+ *     refit) into a hipGraph on a stream of the context's own at the first call with
+ *     a given set of arguments (pointers, sizes, options, configuration, device) and
+ *     replays the instantiated graph on the caller's stream for every later call with
+ *     the same arguments; the four most recently used graphs are kept until the
+ *     context is destroyed.  Replays read the buffers' contents at replay time.  The
+ *     graph holds no memset nodes.  0 = plain launches (default).  A context is not
+ *     thread-safe. */
 typedef struct kf_find_config {
   int32_t wide_window_bins;
   int32_t blocks_per_cu;
+  int32_t use_graph;
 } kf_find_config;
 
-/* Set / read the context's kf_find configuration.  KF_E_INVALID for negative fields. */
+/* Set / read the context's kf_find configuration.  KF_E_INVALID for negative fields or
+ * use_graph other than 0 or 1. */
 int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg);
 int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg);
 
@@ -207,7 +217,7 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
 
 /* Autotuner of kf_find's configuration for inputs like `in`: runs kf_find (arguments
  * as for kf_find; `out` receives the usual results) under each candidate configuration
- * (wide_window_bins 4, 8, 16, 32, 64 x blocks_per_cu 0, 1), times two calls of each
+ * (wide_window_bins 4, 8, 16, 32, 64 x blocks_per_cu 0, 1; use_graph as set), times two calls of each
  * with HIP events on `stream`, keeps the fastest in the context and copies it to
  * *best (if not NULL).  Unlike every other call it SYNCHRONISES on `stream`.  On error
  * the previous configuration is kept and the error code returned. */

@@ -3,14 +3,29 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/kf.h"
 #include "kf_internal.h"
 
 struct kf_ctx {
+  struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
   kf_geometry g;
   float det_thr;
-  kf_find_config fcfg{16, 0};
+  kf_find_config fcfg{16, 0, 0};
+  hipStream_t cap_stream = nullptr;  // capture stream of the graph path
+  int cap_device = -1;
+  uint64_t tick = 0;
+  GraphEntry graphs[4];              // least recently used is replaced
+  ~kf_ctx() {
+    for (auto& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
   int grid_device = -1;   // device the occupancy figures below were taken on
   int grid_cus = 0;       // compute units
   int grid_per_cu = 0;    // find workgroups that fit on one compute unit
@@ -122,7 +137,9 @@ int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold) {
 }
 
 int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg) {
-  if (!ctx || !cfg || cfg->wide_window_bins < 0 || cfg->blocks_per_cu < 0) return KF_E_INVALID;
+  if (!ctx || !cfg || cfg->wide_window_bins < 0 || cfg->blocks_per_cu < 0 || cfg->use_graph < 0 ||
+      cfg->use_graph > 1)
+    return KF_E_INVALID;
   ctx->fcfg = *cfg;
   return KF_OK;
 }
@@ -193,8 +210,11 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   return kfi::launch_fit(a, st) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
-int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out, void* ws,
-            size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int check_find(kf_ctx* ctx, const kf_find_in* in, const kf_find_out* out, void* ws, size_t ws_bytes) {
   if (!ctx || !in || !out) return KF_E_INVALID;
   if (in->n_events < 0 || in->n_seeds < 0 || in->n_hits < 0) return KF_E_INVALID;
   if (in->keep < 1 || in->keep > KF_MAX_KEEP || in->max_miss < 1) return KF_E_INVALID;
@@ -210,11 +230,14 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
   if (in->n_hits >= (int64_t(1) << 28) - 2 || in->n_seeds >= (int64_t)INT32_MAX * 32) return KF_E_UNSUPPORTED;
   if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
   if ((int64_t)ctx->g.n_phi_bins * ctx->g.n_z_bins > 8192) return KF_E_UNSUPPORTED;  // LDS of the bin kernel
+  return check_ws(ws, ws_bytes, find_ws(ctx, in).total);
+}
+
+// The launches of one kf_find call (arguments already checked, n_seeds > 0).
+int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
+                 void* ws, hipStream_t st) {
   const FindWs w = find_ws(ctx, in);
-  int rc = check_ws(ws, ws_bytes, w.total);
-  if (rc != KF_OK) return rc;
   char* base = static_cast<char*>(ws);
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base + w.layers);
   const float* align = params ? params->align : nullptr;
   const float* xX0 = params ? params->xX0 : nullptr;
@@ -296,6 +319,112 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
   return KF_OK;
 }
 
+// Everything a captured kf_find depends on, field by field (no struct padding).
+std::vector<uint64_t> find_key(const kf_ctx* ctx, int dev, const kf_layer_params* params, const kf_find_in* in,
+                               const kf_find_out* out, void* ws, size_t ws_bytes) {
+  auto u = [](const void* p) { return (uint64_t)reinterpret_cast<uintptr_t>(p); };
+  auto f = [](float v) {
+    uint32_t b;
+    memcpy(&b, &v, 4);
+    return (uint64_t)b;
+  };
+  return {(uint64_t)dev,
+          u(params ? params->align : nullptr),
+          u(params ? params->xX0 : nullptr),
+          (uint64_t)in->n_events,
+          u(in->hit_off),
+          (uint64_t)in->n_hits,
+          u(in->hits),
+          (uint64_t)in->n_seeds,
+          u(in->seed_event),
+          u(in->seed_hits),
+          f(in->chi2_cut),
+          f(in->nsigma),
+          (uint64_t)in->keep,
+          (uint64_t)in->max_miss,
+          (uint64_t)(in->refit != 0),
+          u(out->n_cand),
+          u(out->hit_idx),
+          u(out->n_hits),
+          u(out->n_miss),
+          u(out->chi2),
+          u(out->state),
+          u(out->cov),
+          u(out->status),
+          u(in->refit ? out->rf_state : nullptr),
+          u(in->refit ? out->rf_cov : nullptr),
+          u(in->refit ? out->rf_chi2 : nullptr),
+          u(in->refit ? out->rf_ndf : nullptr),
+          u(in->refit ? out->rf_status : nullptr),
+          u(ws),
+          (uint64_t)ws_bytes,
+          (uint64_t)ctx->fcfg.wide_window_bins,
+          (uint64_t)ctx->fcfg.blocks_per_cu,
+          f(ctx->det_thr)};
+}
+
+// kf_find through a cached hipGraph: the call's launches are captured once on the
+// context's own stream and the instantiated graph is replayed on the caller's stream
+// for every later call with the same arguments.
+int find_graph(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out, void* ws,
+               size_t ws_bytes, hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return KF_E_HIP;
+  const std::vector<uint64_t> key = find_key(ctx, dev, params, in, out, ws, ws_bytes);
+  ++ctx->tick;
+  kf_ctx::GraphEntry* hit = nullptr;
+  for (auto& g : ctx->graphs)
+    if (g.exec && g.key == key) hit = &g;
+  if (!hit) {
+    int grid = 0;  // sizes the grid (and sets the kernel's LDS limit) outside the capture
+    if (persistent_grid(ctx, ctx->g.n_layers, &grid) != KF_OK) return KF_E_HIP;
+    if (ctx->cap_stream && ctx->cap_device != dev) {
+      (void)hipStreamDestroy(ctx->cap_stream);
+      ctx->cap_stream = nullptr;
+    }
+    if (!ctx->cap_stream) {
+      if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        ctx->cap_stream = nullptr;
+        return KF_E_HIP;
+      }
+      ctx->cap_device = dev;
+    }
+    if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return KF_E_HIP;
+    const int rc = enqueue_find(ctx, params, in, out, ws, ctx->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (rc != KF_OK || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc != KF_OK ? rc : KF_E_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return KF_E_HIP;
+    hit = &ctx->graphs[0];
+    for (auto& g : ctx->graphs)
+      if (!g.exec || g.used < hit->used) hit = &g;
+    if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
+    hit->exec = exec;
+    hit->key = key;
+  }
+  hit->used = ctx->tick;
+  return hipGraphLaunch(hit->exec, st) == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out, void* ws,
+            size_t ws_bytes, void* stream) {
+  const int rc = check_find(ctx, in, out, ws, ws_bytes);
+  if (rc != KF_OK || in->n_seeds == 0) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (ctx->fcfg.use_graph) return find_graph(ctx, params, in, out, ws, ws_bytes, st);
+  return enqueue_find(ctx, params, in, out, ws, st);
+}
+
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
@@ -356,7 +485,7 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
   int rc = KF_OK;
   for (int per : kPer) {
     for (int wide : kWide) {
-      ctx->fcfg = kf_find_config{wide, per};
+      ctx->fcfg = kf_find_config{wide, per, saved.use_graph};
       rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);  // warm-up, and validates the call
       if (rc != KF_OK) break;
       float ms = INFINITY;

@@ -125,7 +125,7 @@ def _stream(stream):
 
 
 class FindConfig(C.Structure):
-    _fields_ = [("wide_window_bins", C.c_int32), ("blocks_per_cu", C.c_int32)]
+    _fields_ = [("wide_window_bins", C.c_int32), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class Context:
@@ -169,20 +169,22 @@ class Context:
         _check(_lib().kf_ctx_set_fallback_threshold(self._h, float(det_threshold)),
                "kf_ctx_set_fallback_threshold")
 
-    def set_find_config(self, wide_window_bins=None, blocks_per_cu=None):
+    def set_find_config(self, wide_window_bins=None, blocks_per_cu=None, use_graph=None):
         """kf_ctx_set_find_config; fields left None keep their current value."""
         cfg = self.find_config()
         if wide_window_bins is not None:
             cfg["wide_window_bins"] = int(wide_window_bins)
         if blocks_per_cu is not None:
             cfg["blocks_per_cu"] = int(blocks_per_cu)
-        c = FindConfig(cfg["wide_window_bins"], cfg["blocks_per_cu"])
+        if use_graph is not None:
+            cfg["use_graph"] = int(use_graph)
+        c = FindConfig(cfg["wide_window_bins"], cfg["blocks_per_cu"], cfg["use_graph"])
         _check(_lib().kf_ctx_set_find_config(self._h, C.byref(c)), "kf_ctx_set_find_config")
 
     def find_config(self):
         c = FindConfig()
         _check(_lib().kf_ctx_get_find_config(self._h, C.byref(c)), "kf_ctx_get_find_config")
-        return {"wide_window_bins": c.wide_window_bins, "blocks_per_cu": c.blocks_per_cu}
+        return {"wide_window_bins": c.wide_window_bins, "blocks_per_cu": c.blocks_per_cu, "use_graph": c.use_graph}
 
     def workspace(self, op, inp, device):
         nb = C.c_size_t(0)

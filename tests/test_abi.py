@@ -77,11 +77,13 @@ def test_host_side_errors_before_launch():
 def test_find_config_roundtrip_and_validation():
     kf, lib = _lib()
     ctx = kf.Context(synth.workload_geometry(3))
-    assert ctx.find_config() == {"wide_window_bins": 16, "blocks_per_cu": 0}
-    ctx.set_find_config(wide_window_bins=0, blocks_per_cu=1)
-    assert ctx.find_config() == {"wide_window_bins": 0, "blocks_per_cu": 1}
+    assert ctx.find_config() == {"wide_window_bins": 16, "blocks_per_cu": 0, "use_graph": 0}
+    ctx.set_find_config(wide_window_bins=0, blocks_per_cu=1, use_graph=1)
+    assert ctx.find_config() == {"wide_window_bins": 0, "blocks_per_cu": 1, "use_graph": 1}
     with pytest.raises(kf.KfError):
         ctx.set_find_config(wide_window_bins=-1)
     with pytest.raises(kf.KfError):
         ctx.set_find_config(blocks_per_cu=-2)
-    assert ctx.find_config() == {"wide_window_bins": 0, "blocks_per_cu": 1}
+    with pytest.raises(kf.KfError):
+        ctx.set_find_config(use_graph=2)
+    assert ctx.find_config() == {"wide_window_bins": 0, "blocks_per_cu": 1, "use_graph": 1}

@@ -213,3 +213,33 @@ def test_find_batched_equals_per_event():
             if k == "hit_idx":
                 v = np.where(v >= 0, v + lo, v)
             np.testing.assert_array_equal(v, ref, err_msg=f"event {e} {k}")
+
+
+def test_find_graph_replays_match_eager():
+    """kf_find through a captured hipGraph: several replays, with eager work and
+    synchronisations between them and new contents in the same input buffers, each
+    equal to the eager call on the same contents."""
+    need_gpu()
+    from paper_1906_11744_amd import Context
+    geom, ev = synth.find_workload(5, n_tracks=600, n_events=4)
+    xX0 = to_dev(geom.xX0.astype(np.float32))
+    hits, hit_off = to_dev(ev.hits), to_dev(ev.hit_off)
+    seeds0, sev0 = to_dev(ev.seed_hits), to_dev(ev.seed_event)
+    S = ev.seed_hits.shape[1]
+    eager = Context(geom)
+    graph = Context(geom)
+    graph.set_find_config(use_graph=1)
+    seeds, sev = seeds0.clone(), sev0.clone()   # the graph's input buffers
+    out = None
+    gen = torch.Generator().manual_seed(5)
+    for rep in range(4):
+        perm = torch.randperm(S, generator=gen).to(seeds.device) if rep else torch.arange(S, device=seeds.device)
+        seeds.copy_(seeds0[:, perm])
+        sev.copy_(sev0[perm])
+        ref = eager.find(hits, hit_off, seeds.clone(), sev.clone(), xX0=xX0, refit=True)
+        torch.cuda.synchronize()
+        out = graph.find(hits, hit_off, seeds, sev, xX0=xX0, refit=True, out=out)
+        torch.cuda.synchronize()
+        _ = (hits * 2.0).sum().item()   # unrelated eager work between replays
+        for k in ref:
+            np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k].cpu().numpy(), err_msg=f"replay {rep} {k}")
