@@ -18,6 +18,13 @@ constexpr float kTwoPi = 6.28318530717958647692f;
 constexpr uint32_t ST_PROP_FAIL = 1u, ST_NEAR_TANGENT = 2u, ST_FP64 = 4u, ST_NONFINITE = 8u,
                    ST_BAD_INPUT = 16u, ST_TERM_MISSES = 32u;
 
+// Hardware reciprocal, square root and reciprocal square root (v_rcp_f32, v_sqrt_f32,
+// v_rsq_f32; about 1 ulp, no denormal fix-up: every operand on the path is a normal
+// number or the result is not used).
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hrsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // packed lower-triangular index
 __host__ __device__ constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
@@ -36,10 +43,11 @@ struct Model {
 };
 
 // A track candidate: state, covariance and the carried trigonometry of phi and theta.
-// The position is a compensated sum x[i] + xl[i] (i < 3): at 100 cm one float ulp is
-// 7.6e-6 cm, and rounding every step's increments into x alone random-walks the
-// trajectory by ~3e-5 cm over 17 layers, which a 1 m sagitta turns into ~2e-6/GeV of
-// curvature.  xl keeps each addition's rounding error.
+// The transverse position is a compensated sum x[i] + xl[i] (i < 2): at 100 cm one
+// float ulp is 7.6e-6 cm, and rounding every step's increments into x alone
+// random-walks the trajectory by ~3e-5 cm over 17 layers, which a 1 m sagitta turns
+// into ~2e-6/GeV of curvature.  xl keeps each addition's rounding error.  z has no
+// such lever (its error only tilts theta by ~1e-7): xl[2] is kept at 0.
 struct Trk {
   float x[6];   // x y z kappa phi theta
   float xl[3];  // low parts of x y z
@@ -116,14 +124,21 @@ __device__ __forceinline__ bool crossing(const Trk& k, const LayerK& ly, float k
   const float A = fmaf(2.f * w, b, fmaf(0.5f * w * w, c0, 2.f));
   const float D = fmaf(a, a, -0.5f * A * c0);
   if (!(c0 < 0.f) || !(D >= 0.f)) return false;
-  const float den = a + sqrtf(D);
+  const float den = a + hsqrt(D);
   if (!(den > 0.f)) return false;
-  const float sig = -c0 / (2.f * den);
+  const float sig = -0.5f * c0 * rcp(den);
   const float tau = w * sig;
   const float tau2 = tau * tau;
-  // atan(tau)/tau, exact at tau = 0
-  const float q = fabsf(tau) < 1e-2f ? fmaf(tau2, fmaf(tau2, 0.2f, -1.f / 3.f), 1.f) : atanf(tau) / tau;
-  const float f = 2.f * sig / (1.f + tau2);
+  // atan(tau)/tau, exact at tau = 0: its Taylor series to tau^12 below |tau| = 0.3
+  // (truncation < tau^14/15 = 3e-9), atanf beyond
+  float q;
+  if (fabsf(tau) < 0.3f) {
+    q = fmaf(tau2, fmaf(tau2, fmaf(tau2, fmaf(tau2, fmaf(tau2, fmaf(tau2, 1.f / 13.f, -1.f / 11.f), 1.f / 9.f),
+                                                      -1.f / 7.f), 0.2f), -1.f / 3.f), 1.f);
+  } else {
+    q = atanf(tau) / tau;
+  }
+  const float f = 2.f * sig * rcp(1.f + tau2);
   st.s = 2.f * sig * q;
   st.u = 2.f * tau * q;
   st.tau = tau;
@@ -138,7 +153,7 @@ __device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
   const float s = st.s, u = st.u;
   float F1, F2;  // d(displacement)/d(omega) = s^2 (F1 t + F2 n)
   const float tau2 = st.tau * st.tau;
-  const float inv1 = 1.f / (1.f + tau2);
+  const float inv1 = rcp(1.f + tau2);
   const float cu = (1.f - tau2) * inv1, su = 2.f * st.tau * inv1;
   if (fabsf(u) < 0.3f) {
     const float u2 = u * u;
@@ -150,7 +165,7 @@ __device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
     F2 = fmaf(u, su, -2.f * tau2 * inv1) * iu2;
   }
   const float ks2 = -kB * s * s;
-  const float rst = 1.f / k.st;
+  const float rst = rcp(k.st);
   const float a04 = -st.dy, a14 = st.dx;
   const float a03 = ks2 * fmaf(F1, k.cp, -F2 * k.sp);
   const float a13 = ks2 * fmaf(F1, k.sp, F2 * k.cp);
@@ -187,11 +202,11 @@ __device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
   // state
   add_pos(k.x[0], k.xl[0], st.dx);
   add_pos(k.x[1], k.xl[1], st.dy);
-  add_pos(k.x[2], k.xl[2], s * k.ct * rst);
+  k.x[2] = fmaf(s * rst, k.ct, k.x[2]);  // z needs no compensation (xl[2] stays 0)
   k.x[4] = wrap_pi(k.x[4] + u);
   const float cp = k.cp * cu - k.sp * su;
   const float sp = k.sp * cu + k.cp * su;
-  const float nrm = rsqrtf(fmaf(cp, cp, sp * sp));
+  const float nrm = hrsqrt(fmaf(cp, cp, sp * sp));
   k.cp = cp * nrm;
   k.sp = sp * nrm;
 }
@@ -208,7 +223,7 @@ __device__ __forceinline__ Frame frame_at(const Trk& k, const LayerK& ly) {
   Frame f;
   const float ex = rel_pos(k.x[0], k.xl[0], ly.cx), ey = rel_pos(k.x[1], k.xl[1], ly.cy);
   const float r2 = fmaf(ex, ex, ey * ey);
-  const float ir = rsqrtf(r2);
+  const float ir = hrsqrt(r2);
   f.rho = r2 * ir;
   f.rx = ex * ir;
   f.ry = ey * ir;
@@ -223,10 +238,10 @@ __device__ __forceinline__ void add_scattering(Trk& k, const Frame& f, float xX0
   const float kap = k.x[3];
   const float ks = kap * k.st;
   const float ks2 = ks * ks;
-  const float xe = xX0 / (k.st * fabsf(f.cosa));
+  const float xe = xX0 * rcp(k.st * fabsf(f.cosa));
   const float lg = fmaf(0.038f, __logf(xe), 1.f);
   const float th2 = 0.0136f * 0.0136f * ks2 * fmaf(mass2, ks2, 1.f) * xe * lg * lg;
-  const float rst = 1.f / k.st;
+  const float rst = rcp(k.st);
   const float cot = k.ct * rst;
   const float kc = kap * cot;
   k.C[tri(4, 4)] = fmaf(th2 * rst, rst, k.C[tri(4, 4)]);
@@ -250,9 +265,9 @@ struct Pred {
 
 __device__ __forceinline__ void prepare(const Trk& k, const Frame& f, const Model& md, Pred& p) {
   const float fx = -f.ry, fy = f.rx;
-  const float ica = 1.f / f.cosa;
+  const float ica = rcp(f.cosa);
   const float tana = fmaf(fx, k.cp, fy * k.sp) * ica;
-  const float cot = k.ct / k.st;
+  const float cot = k.ct * rcp(k.st);
   p.h1x = fmaf(-tana, f.rx, fx);
   p.h1y = fmaf(-tana, f.ry, fy);
   const float g = -cot * ica;
@@ -270,14 +285,14 @@ __device__ __forceinline__ void prepare(const Trk& k, const Frame& f, const Mode
   // equilibrated inverse: S~ = D^-1/2 S D^-1/2 has unit diagonal; its radial row is
   // (1, 0, 0), so det S~ = 1 - rho12^2.
   p.Si00 = 1.f / md.v_r;
-  const float d1 = rsqrtf(p.S11), d2 = rsqrtf(p.S22);
+  const float d1 = hrsqrt(p.S11), d2 = hrsqrt(p.S22);
   const float r12 = p.S12 * d1 * d2;
   const float det = fmaf(-r12, r12, 1.f);
   const bool good = p.S11 > 0.f && p.S22 > 0.f && det >= md.det_thr && md.det_thr <= 1.f &&
                     isfinite(det);
   p.fp64 = !good;
   if (good) {
-    const float idet = 1.f / det;
+    const float idet = rcp(det);
     p.Si11 = d1 * d1 * idet;
     p.Si22 = d2 * d2 * idet;
     p.Si12 = -r12 * d1 * d2 * idet;
@@ -312,9 +327,17 @@ __device__ __forceinline__ Resid residual(const Trk& k, const Frame& f, const La
   const float cr = fmaf(f.rx, dy, -f.ry * dx);
   const float d2 = fmaf(dx, dx, dy * dy);
   const float num = fmaf(2.f * f.rho, rd, d2);
-  const float rm = sqrtf(fmaf(f.rho, f.rho, num));
-  r.r0 = num / (rm + f.rho);
-  r.r1 = f.rho * atan2f(cr, f.rho + rd);
+  const float rm = hsqrt(fmaf(f.rho, f.rho, num));
+  r.r0 = num * rcp(rm + f.rho);
+  // angle of d about the axis seen from the prediction: atan(x), x = cr / (rho + rd),
+  // by its series to x^9 for |x| < 0.1 (truncation < x^11/11 = 1e-12), atan2f otherwise
+  const float den = f.rho + rd;
+  if (den > 0.f && fabsf(cr) < 0.1f * den) {
+    const float x = cr * rcp(den), x2 = x * x;
+    r.r1 = f.rho * (x * fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.f / 9.f, -1.f / 7.f), 0.2f), -1.f / 3.f), 1.f));
+  } else {
+    r.r1 = f.rho * atan2f(cr, den);
+  }
   r.r2 = (mz - k.x[2]) - k.xl[2];
   if (!p.fp64) {
     const float q = fmaf(r.r1 * r.r1, p.Si11, fmaf(2.f * r.r1 * r.r2, p.Si12, r.r2 * r.r2 * p.Si22));
@@ -342,7 +365,8 @@ __device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model&
   const float dphi = fmaf(K1[4], r1, K2[4] * r2);
   const float dth = fmaf(K1[5], r1, K2[5] * r2);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) add_pos(k.x[i], k.xl[i], fmaf(K1[i], r1, K2[i] * r2));
+  for (int i = 0; i < 2; ++i) add_pos(k.x[i], k.xl[i], fmaf(K1[i], r1, K2[i] * r2));
+  k.x[2] = fmaf(K1[2], r1, fmaf(K2[2], r2, k.x[2]));
 #pragma unroll
   for (int i = 3; i < 6; ++i) k.x[i] = fmaf(K1[i], r1, fmaf(K2[i], r2, k.x[i]));
   const float phin = wrap_pi(k.x[4]);

@@ -471,7 +471,7 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) k.x[q] = shfl_f(k.x[q], src);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) k.xl[q] = shfl_f(k.xl[q], src);
+      for (int q = 0; q < 2; ++q) k.xl[q] = shfl_f(k.xl[q], src);  // xl[2] is always 0
 #pragma unroll
       for (int q = 0; q < 21; ++q) k.C[q] = shfl_f(k.C[q], src);
       k.cp = shfl_f(k.cp, src);

@@ -64,7 +64,7 @@ struct GatherHits {
   }
 };
 
-template <class Src>
+template <bool kCkpt, class Src>
 __device__ __forceinline__ void fit_one(const FitArgs& a, int64_t i, uint32_t mask, const Src& src) {
   const int64_t n = a.n;
   const uint32_t need = a.seed_from_hits ? 7u : 1u;
@@ -127,7 +127,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int64_t i, uint32_t ma
         chi2 += r.chi2;
         ++nh;
       }
-      if (a.ckpt) store_ckpt(a.ckpt, n, i, l, k);
+      if (kCkpt) store_ckpt(a.ckpt, n, i, l, k);
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q)
@@ -142,11 +142,13 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int64_t i, uint32_t ma
   a.status[i] = status;
 }
 
+// kCkpt: also store the state and covariance after every processed layer (a.ckpt).
+template <bool kCkpt>
 __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   SoaHits src{a.hits, a.mask};
-  fit_one(a, i, a.mask[i], src);
+  fit_one<kCkpt>(a, i, a.mask[i], src);
 }
 
 // Fit of each seed's best finder candidate from its own hits (slot 0 of hit_idx).
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __re
   uint32_t mask = 0;
   for (int l = 0; l < a.nl; ++l) mask |= (idx0[(int64_t)l * a.n + i] >= 0 ? 1u : 0u) << l;
   GatherHits src{hits, H, idx0};
-  fit_one(a, i, mask, src);
+  fit_one<false>(a, i, mask, src);
 }
 
 hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream) {
@@ -170,7 +172,10 @@ hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const in
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream) {
   const int bs = 256;
   const int64_t nb = (a.n + bs - 1) / bs;
-  hipLaunchKernelGGL(fit_kernel, dim3((unsigned)nb), dim3(bs), 0, stream, a);
+  if (a.ckpt)
+    hipLaunchKernelGGL(fit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, a);
+  else
+    hipLaunchKernelGGL(fit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -171,7 +171,11 @@ def test_forced_fp64_fallback_matches():
     assert not np.any(out32["status"].cpu().numpy().view(np.uint32)[live] & 4 & ~(ref["status"][live] & 4))
     _compare(geom, ts.hits, ts.hit_mask, out64, ref, "forced FP64")
     d = np.abs(out64["state"].cpu().numpy() - out32["state"].cpu().numpy())
-    assert rel_state_err(out64["state"].cpu().numpy(), out32["state"].cpu().numpy().astype(np.float64)).max() < 1e-4
+    # the two GPU paths against each other, on the tracks the state bar covers (no
+    # near-tangent crossing, no propagation failure)
+    ok = live & ((ref["status"] & (oracle.ST_NEAR_TANGENT | oracle.ST_PROP_FAIL)) == 0)
+    rel = rel_state_err(out64["state"].cpu().numpy()[:, ok], out32["state"].cpu().numpy()[:, ok].astype(np.float64))
+    assert rel.max() < 1e-4
     assert np.isfinite(d).all()
 
 
