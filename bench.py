@@ -42,8 +42,8 @@ PEAK_HBM_GBS = 8000.0
 # runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean of 5 launches), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "dba0d043d2d0a82c", "tracks": 1_000_000,
-               "fetch_kib": 102694.2, "write_kib": 117187.5,
+FIT_TRAFFIC = {"sources": "99ddcc3026af2f69", "tracks": 1_000_000,
+               "fetch_kib": 102027.2, "write_kib": 117187.5,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
@@ -75,23 +75,24 @@ def algorithmic_bytes(n_tracks, n_layers, n_steps):
 
 
 def _time_launches(fn, steps, warmup):
-    """Average device time (s) of fn() over `steps` launches after `warmup`, from HIP
-    events on the current stream, plus the wall-clock seconds of the timed loop."""
+    """Mean device time (s) per call of fn() over `steps` back-to-back calls after
+    `warmup`, from one pair of HIP events on the current stream around the timed
+    region (the library launches on that stream), and the wall-clock seconds of the
+    same region."""
     import torch
     for _ in range(max(1, warmup)):
         fn()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        ev[k][0].record(stream)
+    e0.record(stream)
+    for _ in range(steps):
         fn()
-        ev[k][1].record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
-    return float(per.mean()), wall
+    return e0.elapsed_time(e1) * 1e-3 / steps, wall
 
 
 def bench_find(steps, warmup):

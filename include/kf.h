@@ -187,7 +187,8 @@ int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg);
 int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg);
 
 /* Workspace bytes needed by op (KF_OP_*) for the input `in` (a kf_fit_in or
- * kf_find_in; for KF_OP_FIT_BACKWARD the kf_fit_in of the forward call). */
+ * kf_find_in; for KF_OP_FIT_BACKWARD the kf_fit_in of the forward call).  0 for
+ * KF_OP_FIT (ws may then be NULL). */
 int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes);
 
 /* Batched Kalman fit, one track per GPU lane.  For every track: seed at layer 0,

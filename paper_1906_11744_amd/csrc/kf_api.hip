@@ -154,7 +154,7 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
   if (!ctx || !in || !bytes) return KF_E_INVALID;
   switch (op) {
     case KF_OP_FIT:
-      *bytes = fit_ws_bytes();
+      *bytes = 0;
       return KF_OK;
     case KF_OP_FIND:
       *bytes = find_ws(ctx, static_cast<const kf_find_in*>(in)).total;
@@ -181,14 +181,9 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   if (!in->seed_from_hits && (!in->seed_state || !in->seed_cov)) return KF_E_INVALID;
   if (in->seed_from_hits && !(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;  // no curvature from hits at B = 0
   if (in->n > (int64_t)INT32_MAX * 256) return KF_E_INVALID;
-  int rc = check_ws(ws, ws_bytes, fit_ws_bytes());
-  if (rc != KF_OK) return rc;
+  (void)ws;  // the fit needs no workspace
+  (void)ws_bytes;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(ws);
-  const float* align = params ? params->align : nullptr;
-  const float* xX0 = params ? params->xX0 : nullptr;
-  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
-    return KF_E_HIP;
   kfi::FitArgs a;
   a.n = in->n;
   a.nl = ctx->g.n_layers;
@@ -200,7 +195,10 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   a.mask = in->hit_mask;
   a.seed_state = in->seed_state;
   a.seed_cov = in->seed_cov;
-  a.layers = layers;
+  a.layers = nullptr;
+  a.align = params ? params->align : nullptr;
+  a.xX0 = params ? params->xX0 : nullptr;
+  for (int l = 0; l < 32; ++l) a.radius[l] = l < ctx->g.n_layers ? ctx->g.radius_cm[l] : 0.f;
   a.state = out->state;
   a.cov = out->cov;
   a.chi2 = out->chi2;

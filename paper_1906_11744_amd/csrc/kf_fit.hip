@@ -7,12 +7,12 @@ struct Radii {
   float r[32];
 };
 
-__global__ void layer_prep_kernel(int nl, Radii rad, const float* __restrict__ align, const float* __restrict__ xX0,
-                                  kfd::LayerK* __restrict__ out) {
-  const int l = threadIdx.x;
-  if (l >= nl) return;
+// Constants of layer l: radius, alignment (centre shift, z shift, cos/sin of the
+// rotation), material.  align / xX0 may be null (all zero).
+__device__ __forceinline__ kfd::LayerK make_layer(int l, const float* radius, const float* __restrict__ align,
+                                                  const float* __restrict__ xX0) {
   kfd::LayerK k;
-  k.r = rad.r[l];
+  k.r = radius[l];
   k.cx = align ? align[4 * l + 0] : 0.f;
   k.cy = align ? align[4 * l + 1] : 0.f;
   k.dz = align ? align[4 * l + 2] : 0.f;
@@ -20,7 +20,14 @@ __global__ void layer_prep_kernel(int nl, Radii rad, const float* __restrict__ a
   sincosf(dphi, &k.sphi, &k.cphi);
   k.xX0 = xX0 ? xX0[l] : 0.f;
   k.pad = 0.f;
-  out[l] = k;
+  return k;
+}
+
+__global__ void layer_prep_kernel(int nl, Radii rad, const float* __restrict__ align, const float* __restrict__ xX0,
+                                  kfd::LayerK* __restrict__ out) {
+  const int l = threadIdx.x;
+  if (l >= nl) return;
+  out[l] = make_layer(l, rad.r, align, xX0);
 }
 
 hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
@@ -65,14 +72,14 @@ struct GatherHits {
 };
 
 template <bool kCkpt, class Src>
-__device__ __forceinline__ void fit_one(const FitArgs& a, int64_t i, uint32_t mask, const Src& src) {
+__device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __restrict__ lays, int64_t i,
+                                        uint32_t mask, const Src& src) {
   const int64_t n = a.n;
   const uint32_t need = a.seed_from_hits ? 7u : 1u;
   uint32_t status = 0;
   kfd::Trk k;
   float chi2 = 0.f;
   int nh = 0;
-  const kfd::LayerK* __restrict__ lays = a.layers;
   auto hit = [&](int l, float& mx, float& my, float& mz) {
     float hx, hy, hz;
     src.get(i, n, l, hx, hy, hz);
@@ -143,12 +150,17 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int64_t i, uint32_t ma
 }
 
 // kCkpt: also store the state and covariance after every processed layer (a.ckpt).
+// The workgroup first builds the layer constants in LDS (one lane per layer), so that
+// one kf_fit call is one kernel.
 template <bool kCkpt>
 __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
+  __shared__ kfd::LayerK lays[32];
+  if ((int)threadIdx.x < a.nl) lays[threadIdx.x] = make_layer(threadIdx.x, a.radius, a.align, a.xX0);
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   SoaHits src{a.hits, a.mask};
-  fit_one<kCkpt>(a, i, a.mask[i], src);
+  fit_one<kCkpt>(a, lays, i, a.mask[i], src);
 }
 
 // Fit of each seed's best finder candidate from its own hits (slot 0 of hit_idx).
@@ -159,7 +171,7 @@ __global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __re
   uint32_t mask = 0;
   for (int l = 0; l < a.nl; ++l) mask |= (idx0[(int64_t)l * a.n + i] >= 0 ? 1u : 0u) << l;
   GatherHits src{hits, H, idx0};
-  fit_one<false>(a, i, mask, src);
+  fit_one<false>(a, a.layers, i, mask, src);
 }
 
 hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream) {

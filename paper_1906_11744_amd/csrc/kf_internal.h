@@ -20,7 +20,10 @@ struct FitArgs {
   const uint32_t* mask;
   const float* seed_state;
   const float* seed_cov;
-  const kfd::LayerK* layers;  // [nl], prepared on the device
+  const kfd::LayerK* layers;  // [nl], prepared on the device (refit), or
+  const float* align;         // computed by each fit workgroup from these (fit)
+  const float* xX0;
+  float radius[32];
   float* state;
   float* cov;
   float* chi2;

@@ -67,9 +67,15 @@ def test_host_side_errors_before_launch():
     assert lib.kf_fit(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -1
     fin = kf.FitIn(-1, None, None, None, None, 1)
     assert lib.kf_fit(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -1
-    nb = C.c_size_t(0)
+    nb = C.c_size_t(1)
     assert lib.kf_workspace_size(ctx._h, kf.KF_OP_FIT, C.byref(fin), C.byref(nb)) == 0
+    assert nb.value == 0   # the fit builds its layer table in LDS
+    fin = kf.FitIn(10, None, None, None, None, 1)
+    assert lib.kf_workspace_size(ctx._h, kf.KF_OP_FIT_BACKWARD, C.byref(fin), C.byref(nb)) == 0
     assert nb.value >= 256
+    fin = kf.FindIn(1, None, 100, None, 10, None, None, 30.0, 3.0, 6, 3, 0)
+    assert lib.kf_workspace_size(ctx._h, kf.KF_OP_FIND, C.byref(fin), C.byref(nb)) == 0
+    assert nb.value >= 100 * 20
     assert lib.kf_workspace_size(ctx._h, 99, C.byref(fin), C.byref(nb)) == -2
     assert lib.kf_strerror(-3).decode().startswith("workspace")
 
