@@ -25,16 +25,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 operations of one track (FMA = 2, each sqrt/rsqrt/division/
-# transcendental = 1), counted from the step as written with the known zeros removed:
-# propagation to the layer (crossing 47, fixed-arc transport of state and covariance
-# 180), scattering noise 27, measurement and update (frame 12, hit placement 9,
-# S and its inverse 85, residual and chi2 29, gain and Joseph update 345, chi2
-# accumulation 1).  The three-hit seed costs 60.
-FLOPS_PROPAGATE = 47 + 180
+# Algorithmic FP32 operations (FMA = 2, add/mul = 1, each reciprocal, square root,
+# logarithm or other transcendental = 1), counted from the formulas as the kernel
+# evaluates them with the known zeros of J and H removed:
+#   crossing 60, fixed-arc transport of state and covariance 194, frame 14,
+#   Highland scattering 27, S and its equilibrated inverse (with H and H C) 83,
+#   hit placement 9, residual and chi2 50, gain + state + Joseph covariance 356,
+#   chi2 accumulation 1; the three-hit seed 91.
+# A track with hits on layers 0..n-1 costs SEED + FIRST + (n - 1) * STEP.  The count
+# agrees with the hardware's SQ_INSTS_VALU_FLOPS_FP32 of the fit kernel to 1%.
+FLOPS_SEED = 91
+FLOPS_FIRST = 14 + 83 + 9 + 50 + 356 + 1          # update at the seed layer
+FLOPS_PROPAGATE = 60 + 194 + 14                    # crossing, transport, frame
 FLOPS_SCATTER = 27
-FLOPS_UPDATE = 12 + 9 + 85 + 29 + 345 + 1
-FLOPS_SEED = 60
+FLOPS_UPDATE = 83 + 9 + 50 + 356 + 1
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_HBM_GBS = 8000.0
 
@@ -64,7 +68,8 @@ def fit_traffic_bytes(n_tracks):
 def algorithmic_flops(n_hits_per_track, xX0_positive=True):
     n = np.asarray(n_hits_per_track, np.int64)
     n = n[n > 0]
-    per = FLOPS_SEED + FLOPS_UPDATE * n + (FLOPS_PROPAGATE + (FLOPS_SCATTER if xX0_positive else 0)) * (n - 1)
+    per = (FLOPS_SEED + FLOPS_FIRST +
+           (FLOPS_PROPAGATE + (FLOPS_SCATTER if xX0_positive else 0) + FLOPS_UPDATE) * (n - 1))
     return float(per.sum())
 
 

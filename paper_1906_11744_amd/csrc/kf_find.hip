@@ -114,6 +114,25 @@ enum : int { K_NONE = 0, K_HIT = 1, K_MISS = 2, K_CARRY = 3 };
 __device__ __forceinline__ bool key_lt(float c1, int h1, float c2, int h2) { return c1 < c2 || (c1 == c2 && h1 < h2); }
 
 __device__ __forceinline__ float shfl_f(float v, int src) { return __shfl(v, src, 64); }
+
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xF, 0xF, false);
+}
+
+// (hi, lo) <- the minimum of the 64-bit key over the lane's 8-lane group: xor 1 and
+// xor 2 inside each quad (quad_perm), then the mirrored lane of the other quad of the
+// half row (row_half_mirror).  Every lane of the group must be active.
+__device__ __forceinline__ void min_step(uint32_t& hi, uint32_t& lo, uint32_t ohi, uint32_t olo) {
+  const bool lt = ohi < hi || (ohi == hi && olo < lo);
+  hi = lt ? ohi : hi;
+  lo = lt ? olo : lo;
+}
+__device__ __forceinline__ void group_min8(uint32_t& hi, uint32_t& lo) {
+  min_step(hi, lo, dpp<0xB1>(hi), dpp<0xB1>(lo));
+  min_step(hi, lo, dpp<0x4E>(hi), dpp<0x4E>(lo));
+  min_step(hi, lo, dpp<0x141>(hi), dpp<0x141>(lo));
+}
 __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64); }
 
 }  // namespace
@@ -214,22 +233,20 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
       int nlist = 0;
       bool predicted = false;
       bool wide = false;
-      // One hit of the window: rectangle test, chi2 with the candidate's S^-1, and the
-      // sorted insertion of a passing branch into (bc, bi).  Slot t keeps its entry if
+      // One hit of the window (binned record and hit index): rectangle test, chi2 with
+      // the candidate's S^-1, and the sorted insertion of a passing branch into (bc, bi).  Slot t keeps its entry if
       // that entry precedes the new one, takes the new one if only the entry before it
       // does, and otherwise takes the entry before it: one select per slot, no element
       // moves under a lane mask (register-pair copies followed by a partial overwrite
       // of the same pair have lost the new element on gfx950).
-      auto consider = [&](int q, const kfd::Trk& kk, const kfd::Frame& ff, const kfd::Pred& pp, float php,
-                          float zpp, float wph, float wzz, float cbase) __attribute__((always_inline)) {
-        const float4 rec = a.brec[q];
+      auto consider = [&](const float4 rec, int hh, const kfd::Trk& kk, const kfd::Frame& ff, const kfd::Pred& pp,
+                          float php, float zpp, float wph, float wzz, float cbase) __attribute__((always_inline)) {
         const float dphi = kfd::wrap_pi(rec.w - php);
         const float dz = rec.z - zpp;
         if (!(fabsf(dphi) <= wph && fabsf(dz) <= wzz)) return;
         const kfd::Resid r = kfd::residual(kk, ff, ly, pp, rec.x, rec.y, rec.z);
         if (!(r.chi2 < a.chi2_cut)) return;
         const float cc = cbase + r.chi2;
-        const int hh = a.bidx[q];
         bool prev_lt = true;
         float oc = 0.f;
         int oh = 0;
@@ -308,7 +325,15 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
             for (int b = blo; b <= bhi; ++b) {
               const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
               const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
-              for (int q = q0; q < q1; ++q) consider(q, k, f, p, phip, zp, wphi, wz, c2);
+              // two records in flight per iteration
+              int q = q0;
+              for (; q + 1 < q1; q += 2) {
+                const float4 r0 = a.brec[q], r1 = a.brec[q + 1];
+                const int h0 = a.bidx[q], h1 = a.bidx[q + 1];
+                consider(r0, h0, k, f, p, phip, zp, wphi, wz, c2);
+                consider(r1, h1, k, f, p, phip, zp, wphi, wz, c2);
+              }
+              if (q < q1) consider(a.brec[q], a.bidx[q], k, f, p, phip, zp, wphi, wz, c2);
             }
           }
         } else {
@@ -363,7 +388,8 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
           for (int b = w.blo; b <= w.bhi; ++b) {
             const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
             const int q0 = boff[pb * a.nz + w.zlo], q1 = boff[pb * a.nz + w.zhi + 1];
-            for (int q = q0 + lane; q < q1; q += 64) consider(q, kc, fc, pc, w.phip, w.zp, w.wphi, w.wz, w.c2);
+            for (int q = q0 + lane; q < q1; q += 64)
+              consider(a.brec[q], a.bidx[q], kc, fc, pc, w.phip, w.zp, w.wphi, w.wz, w.c2);
           }
           // the candidate's list: kMaxList rounds of a 64-lane min over (chi2, hit) keys
           int hd = 0, cnt = 0;
@@ -407,28 +433,33 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
         }
         nlist = stn[tid];
       }
-      // ---- merge the group's branches: `keep` rounds of a 64-bit min over 8 lanes ----
-      // The list is not shifted when its head is taken (register-array moves); the
-      // head is an index resolved by a chain of selects.
+      // ---- merge the group's branches: `keep` rounds of an 8-lane minimum ----
+      // Each lane offers its best remaining branch as a 64-bit key: more hits, smaller
+      // total chi2, lower parent slot, with the branch kind in the two lowest bits (a
+      // lane offers one branch per round, so the kind never decides).  The minimum over
+      // the 8 lanes of a seed takes three DPP exchanges.  The key names the winner's
+      // slot, kind and total chi2; a winning hit's index is read afterwards from an LDS
+      // copy of the winner's sorted list, at the count of its earlier hit wins.  The
+      // list is never shifted: its head is an index resolved by a chain of selects.
+#pragma unroll
+      for (int t = 0; t < kMaxList; ++t) sti[t * 256 + tid] = bi[t];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       bool other_used = false;   // the miss (live) or carry (terminated) branch was taken
       int head = 0;
-      int my_par = slot, my_kind = K_NONE, my_hit = -2;
+      uint32_t wins = 0u;        // hit wins of every slot so far, 4 bits per slot
+      int my_par = slot, my_kind = K_NONE, my_entry = 0;
       float my_c = 0.f;
       int new_n = 0;
       for (int r = 0; r < a.keep; ++r) {
-        int hk = K_NONE, hh = -2, hn = 0;
-        float hc = 0.f;
+        int hk = K_NONE, hn = 0;
+        float hc = bc[0];
+#pragma unroll
+        for (int t = 1; t < kMaxList; ++t)
+          if (head == t) hc = bc[t];
         if (head < nlist) {
           hk = K_HIT;
-          hh = bi[0];
-          hc = bc[0];
-#pragma unroll
-          for (int t = 1; t < kMaxList; ++t) {
-            if (head == t) {
-              hh = bi[t];
-              hc = bc[t];
-            }
-          }
           hn = nh + 1;
         } else if (!other_used && mode == LIVE && predicted) {
           hk = K_MISS;
@@ -439,33 +470,28 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
           hc = c2;
           hn = nh;
         }
-        // 64-bit key built from two 32-bit halves chosen by selects
         const bool has = hk != K_NONE;
-        const uint32_t khi = has ? ((uint32_t)(255 - hn) << 8) | (__float_as_uint(hc) >> 24) : 0xffffffffu;
-        const uint32_t klo = has ? (__float_as_uint(hc) << 8) | (uint32_t)slot : 0xffffffffu;
-        unsigned long long key = ((unsigned long long)khi << 32) | klo;
-#pragma unroll
-        for (int m = 1; m < kGroup; m <<= 1) {
-          const unsigned long long o = __shfl_xor(key, m, kGroup);
-          key = o < key ? o : key;
-        }
-        if (key == ~0ull) break;
-        const int w = (int)(key & 7ull);
-        const int wk = shfl_i(hk, gbase + w);
-        const int wh = shfl_i(hh, gbase + w);
-        const float wc = shfl_f(hc, gbase + w);
+        uint32_t khi = has ? ((uint32_t)(255 - hn) << 8) | (__float_as_uint(hc) >> 24) : 0xffffffffu;
+        uint32_t klo = has ? (__float_as_uint(hc) << 8) | ((uint32_t)slot << 2) | (uint32_t)hk : 0xffffffffu;
+        group_min8(khi, klo);
+        if (khi == 0xffffffffu && klo == 0xffffffffu) break;
+        const int w = (int)((klo >> 2) & 7u);
+        const int wk = (int)(klo & 3u);
         if (slot == r) {
           my_par = w;
           my_kind = wk;
-          my_hit = wh;
-          my_c = wc;
+          my_c = __uint_as_float((khi << 24) | (klo >> 8));
+          my_entry = (int)((wins >> (4 * w)) & 15u);
         }
+        if (wk == K_HIT) wins += 1u << (4 * w);
         if (slot == w) {
           if (hk == K_HIT) ++head;
           else other_used = true;
         }
         ++new_n;
       }
+      int my_hit = -2;
+      if (my_kind == K_HIT) my_hit = sti[my_entry * 256 + (tid & ~(kGroup - 1)) + my_par];
       // ---- every surviving slot takes its parent's (predicted) candidate ----
       const int src = gbase + my_par;
 #pragma unroll
