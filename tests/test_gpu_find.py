@@ -11,6 +11,8 @@ Any other difference fails.  For identical candidates that never crossed a layer
 near-tangentially: state within 1e-4 (relative, floors as the fit), total chi2
 within 0.05 + 1e-4 chi2, counts and the PROP_FAIL / TERM_MISSES status bits exact.
 """
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 import torch
@@ -27,10 +29,12 @@ TOL_WIN = 1e-3       # relative to the window half width
 HARD = oracle.ST_PROP_FAIL | oracle.ST_TERM_MISSES
 
 
-def run_gpu(geom, ev, keep=6, max_miss=3, chi2_cut=30.0, nsigma=3.0, refit=False):
+def run_gpu(geom, ev, keep=6, max_miss=3, chi2_cut=30.0, nsigma=3.0, refit=False, graph=False):
     need_gpu()
     from paper_1906_11744_amd import Context
     ctx = Context(geom)
+    if graph:
+        ctx.set_find_config(use_graph=1)
     out = ctx.find(to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event),
                    xX0=to_dev(geom.xX0.astype(np.float32)), chi2_cut=chi2_cut, nsigma=nsigma, keep=keep,
                    max_miss=max_miss, refit=refit)
@@ -140,6 +144,27 @@ def test_find_batched_events_and_refit():
     np.testing.assert_array_equal(g["rf_ndf"][same], r["rf_ndf"][same])
     assert np.all(np.abs(g["rf_chi2"][ok] - r["rf_chi2"][ok]) < 0.05 + 1e-4 * r["rf_chi2"][ok])
     assert st["exact"] + st["reordered"] > 0.9 * ev.seed_hits.shape[1]
+
+
+def test_find_64_events_full_size_sampled():
+    """The 64-event batch (773 995 seeds, 15.7 M hits) in one graph-replayed call, as the
+    benchmark runs it; 3 000 seeds sampled across all events are checked against the
+    oracle run on the same hits."""
+    geom, ev = synth.find_workload(5)
+    g = run_gpu(geom, ev, refit=True, graph=True)
+    S = ev.seed_hits.shape[1]
+    sel = np.sort(np.random.default_rng(11).choice(S, 3000, replace=False))
+    sub = SimpleNamespace(hits=ev.hits, hit_off=ev.hit_off, seed_hits=np.ascontiguousarray(ev.seed_hits[:, sel]),
+                          seed_event=np.ascontiguousarray(ev.seed_event[sel]))
+    r = oracle_find(geom, sub, refit=True)
+    gs = {k: np.ascontiguousarray(v[..., sel]) for k, v in g.items()}
+    st = compare(geom, sub, gs, r, "64 events, 3000 sampled seeds")
+    assert st["exact"] + st["reordered"] >= 0.9 * sel.size
+    same = np.array([int(gs["n_cand"][s]) > 0 and np.array_equal(gs["hit_idx"][0, :, s], r["hit_idx"][0, :, s])
+                     for s in range(sel.size)])
+    ok = same & ((r["rf_status"] & (oracle.ST_NEAR_TANGENT | oracle.ST_PROP_FAIL)) == 0)
+    assert rel_state_err(gs["rf_state"][:, ok], r["rf_state"][:, ok]).max() < 1e-4
+    np.testing.assert_array_equal(gs["rf_ndf"][same], r["rf_ndf"][same])
 
 
 def test_find_is_deterministic():
