@@ -268,3 +268,14 @@ def test_find_graph_replays_match_eager():
         _ = (hits * 2.0).sum().item()   # unrelated eager work between replays
         for k in ref:
             np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k].cpu().numpy(), err_msg=f"replay {rep} {k}")
+
+
+def test_find_32_layers_and_8192_bins():
+    """The largest geometry kf_find accepts: 32 layers and 256 x 32 bins (LDS of the
+    binning and of the backpointers at their maximum)."""
+    geom = synth.barrel(32, 4.0, 110.0, B=3.8, xX0=0.01, eta_max=1.5, n_phi_bins=256, n_z_bins=32)
+    ev = synth.make_events(geom, [800], workload=6)
+    g = run_gpu(geom, ev, refit=True)
+    r = oracle_find(geom, ev, refit=True)
+    st = compare(geom, ev, g, r, "32 layers, 8192 bins")
+    assert st["exact"] + st["reordered"] >= 0.9 * ev.seed_hits.shape[1]

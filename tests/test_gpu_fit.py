@@ -238,3 +238,31 @@ def test_fit_is_deterministic():
     b = _run(geom, ts)
     for k in a:
         assert torch.equal(a[k], b[k]), k
+
+
+def test_fit_masks_with_gaps_and_seed_only_tracks():
+    """Hits missing on inner and middle layers (the track still crosses them: transport
+    and scattering without an update) and tracks with only the three seed hits."""
+    geom, ts = synth.fit_workload(2, n=3000)
+    rng = np.random.default_rng(7)
+    mask = ts.hit_mask.copy()
+    drop = rng.random((mask.size, geom.n_layers)) < 0.25
+    drop[:, :3] = False
+    for l in range(3, geom.n_layers):
+        mask[drop[:, l]] &= ~np.uint32(1 << l)
+    mask[rng.random(mask.size) < 0.05] &= np.uint32(7)
+    ts.hit_mask = mask
+    out = _run(geom, ts)
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, "masks with gaps")
+    ndf = out["ndf"].cpu().numpy()
+    assert np.all(ndf[mask == 7] == 1)
+
+
+def test_fit_32_layers_maximum():
+    """The largest layer count the ABI accepts."""
+    geom = synth.barrel(32, 4.0, 110.0, B=3.8, xX0=0.01, eta_max=1.5)
+    ts = synth.simulate(geom, synth.rng_for(6, 0), 2000, (0.5, 50.0), True, 1.5, keep_truth=False)
+    out = _run(geom, ts)
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask, records=True)
+    _compare(geom, ts.hits, ts.hit_mask, out, ref, "32 layers")
