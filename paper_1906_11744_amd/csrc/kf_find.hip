@@ -62,16 +62,37 @@ __global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
   const kfd::LayerK ly = a.layers[l];
   const float Z = a.zhalf[l];
   const float sphi = a.nphi / kfd::kTwoPi, sz = a.nz / (2.f * Z);
-  auto place_bin = [&](int64_t j, float4& rec) -> int {
+  auto place_bin = [&](float hx, float hy, float hz, float4& rec) -> int {
     float mx, my, mz;
-    kfd::place(ly, a.hits[j], a.hits[a.H + j], a.hits[2 * a.H + j], mx, my, mz);
+    kfd::place(ly, hx, hy, hz, mx, my, mz);
     const float ph = atan2f(my - ly.cy, mx - ly.cx);
     rec = make_float4(mx, my, mz, ph);
     return bin_index(ph, -kfd::kPi, sphi, a.nphi) * a.nz + bin_index(mz, -Z, sz, a.nz);
   };
-  for (int64_t j = beg + tid; j < end; j += 256) {
-    float4 rec;
-    atomicAdd(&cnt[place_bin(j, rec)], 1);
+  // Each lane takes hits beg + tid + 256 k; kU of them are loaded before any is
+  // binned, so that their loads are in flight together.  Out-of-slice slots read the
+  // slice's first hit and are skipped.
+  constexpr int kU = 4;
+  auto load_hits = [&](int64_t j0, float (&hx)[kU], float (&hy)[kU], float (&hz)[kU]) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t j = j0 + (int64_t)u * 256;
+      const int64_t jj = j < end ? j : beg;
+      hx[u] = a.hits[jj];
+      hy[u] = a.hits[a.H + jj];
+      hz[u] = a.hits[2 * a.H + jj];
+    }
+  };
+  for (int64_t j0 = beg + tid; j0 < end; j0 += 256 * kU) {
+    float hx[kU], hy[kU], hz[kU];
+    load_hits(j0, hx, hy, hz);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (j0 + (int64_t)u * 256 < end) {
+        float4 rec;
+        atomicAdd(&cnt[place_bin(hx[u], hy[u], hz[u], rec)], 1);
+      }
+    }
   }
   __syncthreads();
   // exclusive scan of nb counts: each thread a contiguous chunk, then the 256 chunk sums
@@ -97,12 +118,20 @@ __global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
   }
   if (tid == 0) out_off[nb] = (int)end;
   __syncthreads();
-  for (int64_t j = beg + tid; j < end; j += 256) {
-    float4 rec;
-    const int b = place_bin(j, rec);
-    const int p = atomicAdd(&cnt[b], 1);
-    a.brec[p] = rec;
-    a.bidx[p] = (int32_t)j;
+  for (int64_t j0 = beg + tid; j0 < end; j0 += 256 * kU) {
+    float hx[kU], hy[kU], hz[kU];
+    load_hits(j0, hx, hy, hz);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t j = j0 + (int64_t)u * 256;
+      if (j < end) {
+        float4 rec;
+        const int b = place_bin(hx[u], hy[u], hz[u], rec);
+        const int p = atomicAdd(&cnt[b], 1);
+        a.brec[p] = rec;
+        a.bidx[p] = (int32_t)j;
+      }
+    }
   }
 }
 
