@@ -139,6 +139,41 @@ def kalman_update(x, Cm, H, V, r):
     return x, Cm, chi2.value
 
 
+def rts_step(xf, Cf, J, xp, Cp, xs1, Cs1, wrap_idx=-1):
+    """One Rauch-Tung-Striebel step (dense, n <= 6): smoothed (x, C) at step l from the
+    filtered one at l and the prediction and smoothed estimate at l + 1."""
+    n = len(xf)
+    a = [np.ascontiguousarray(v, np.float64) for v in (xf, Cf, J, xp, Cp, xs1, Cs1)]
+    xs = np.zeros(n)
+    Cs = np.zeros((n, n))
+    ok = load().oracle_rts_step(n, *[_p(v) for v in a], _p(xs), _p(Cs), int(wrap_idx))
+    if not ok:
+        raise ValueError("singular predicted covariance")
+    return xs, Cs
+
+
+def smooth(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None):
+    """Forward fit plus RTS smoother of every track.  Returns state [L][6][n],
+    cov [L][21][n] (layers 0..lend, zero beyond), lend [n] (last layer with an update,
+    -1 if none) and the forward status [n]."""
+    dt = np.float64 if np.asarray(hits).dtype == np.float64 else np.float32
+    hits = np.ascontiguousarray(hits, dt)
+    mask = np.ascontiguousarray(mask, np.uint32)
+    L, _, n = hits.shape
+    from_hits = seed_state is None
+    ss = None if from_hits else np.ascontiguousarray(seed_state, dt)
+    sc = None if from_hits else np.ascontiguousarray(seed_cov, dt)
+    out = dict(state=np.zeros((L, 6, n)), cov=np.zeros((L, 21, n)), lend=np.zeros(n, np.int32),
+               status=np.zeros(n, np.uint32))
+    g = ogeom(geom)
+    xx = geom.xX0 if xX0 is None else xX0
+    fn = load().oracle_smooth_f64 if dt == np.float64 else load().oracle_smooth
+    fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(hits), _p(mask),
+                         int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]), _p(out["lend"]),
+                         _p(out["status"]))
+    return out
+
+
 def seed(geom, m0, m1, m2):
     st = np.zeros(6)
     cv = np.zeros(36)

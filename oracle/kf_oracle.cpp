@@ -1,5 +1,6 @@
-// FP64 oracle of the batched Kalman fit, the combinatorial track finder and the
-// gradient of the fit's total chi2 with respect to per-layer alignment and material.
+// FP64 oracle of the batched Kalman fit, the combinatorial track finder, the
+// gradient of the fit's total chi2 with respect to per-layer alignment and material,
+// and the fixed-interval (Rauch-Tung-Striebel) smoother over the fit.
 //
 // TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or call
 // this file: it exists so that tests, the smoke check and the CPU baseline of the
@@ -32,7 +33,9 @@
 // chi2/ndf of simulated tracks have unit scale; Jacobians agree with central
 // differences of the oracle's own maps; binned search = brute-force search;
 // dual-number gradient = central finite differences; global translation and
-// rotation leave the total chi2 unchanged.  Parity unpinned: the candidate score
+// rotation leave the total chi2 unchanged; RTS on a linear-Gaussian chain = the joint
+// posterior of all states, noiseless smoothed states = the helix at every layer to
+// second order, smoothed pulls have unit scale and C_s <= C_f.  Parity unpinned: the candidate score
 // and its tie rule, and the Highland variant, which are conventions.
 
 #include <omp.h>
@@ -1131,6 +1134,228 @@ void oracle_find(const OGeom* og, const double* align, const double* xX0, int32_
       rf_status[s] = tk.status;
     }
   }
+}
+
+}  // extern "C"
+
+// ==============================================================================
+// Fixed-interval smoother (Rauch-Tung-Striebel) over the forward fit
+// ==============================================================================
+// The paper's chain ends with a backward pass and a final fit of the built tracks
+// (Sec. 4.2, Sec. 5).  Read here as the textbook RTS smoother on the filter's own
+// linearisation: with the filtered state x_f(l), C_f(l) after layer l, the
+// prediction x_p(l+1), C_p(l+1) = J C_f(l) J^T + Q at layer l+1 (J the fixed-arc
+// transport Jacobian of that step) and the smoothed x_s(l+1), C_s(l+1),
+//   G      = C_f(l) J^T C_p(l+1)^-1,
+//   x_s(l) = x_f(l) + G (x_s(l+1) - x_p(l+1))      (azimuth difference wrapped),
+//   C_s(l) = C_f(l) + G (C_s(l+1) - C_p(l+1)) G^T,
+// from the last layer with a hit (x_s = x_f there) down to layer 0.  Layers without
+// a hit inside that range take part with their prediction as the filtered state.
+
+namespace {
+
+// Gauss-Jordan inverse with partial pivoting for n <= 6 (dense, row-major).
+bool invert_dense(int n, const double* A, double* Ai) {
+  double M[6][12];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < 2 * n; ++j) M[i][j] = j < n ? A[i * n + j] : (j - n == i ? 1.0 : 0.0);
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+    if (M[piv][c] == 0) return false;
+    if (piv != c)
+      for (int j = 0; j < 2 * n; ++j) std::swap(M[c][j], M[piv][j]);
+    double inv = 1.0 / M[c][c];
+    for (int j = 0; j < 2 * n; ++j) M[c][j] *= inv;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = M[r][c];
+      for (int j = 0; j < 2 * n; ++j) M[r][j] -= f * M[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Ai[i * n + j] = M[i][n + j];
+  return true;
+}
+
+// One RTS step for an n-dim state (n <= 6), dense row-major matrices.  wrap_idx >= 0
+// names a state component that is an angle (its difference is wrapped to (-pi, pi]).
+bool rts_step(int n, const double* xf, const double* Cf, const double* J, const double* xp, const double* Cp,
+              const double* xs1, const double* Cs1, double* xs, double* Cs, int wrap_idx) {
+  double Cpi[36], CJt[36], G[36], E[36], GE[36];
+  if (!invert_dense(n, Cp, Cpi)) return false;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double a = 0;
+      for (int k = 0; k < n; ++k) a += Cf[i * n + k] * J[j * n + k];
+      CJt[i * n + j] = a;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double a = 0;
+      for (int k = 0; k < n; ++k) a += CJt[i * n + k] * Cpi[k * n + j];
+      G[i * n + j] = a;
+    }
+  double d[6];
+  for (int i = 0; i < n; ++i) d[i] = xs1[i] - xp[i];
+  if (wrap_idx >= 0) d[wrap_idx] = wrap_pi(d[wrap_idx]);
+  for (int i = 0; i < n; ++i) {
+    double a = xf[i];
+    for (int k = 0; k < n; ++k) a += G[i * n + k] * d[k];
+    xs[i] = a;
+  }
+  if (wrap_idx >= 0) xs[wrap_idx] = wrap_pi(xs[wrap_idx]);
+  for (int i = 0; i < n * n; ++i) E[i] = Cs1[i] - Cp[i];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double a = 0;
+      for (int k = 0; k < n; ++k) a += G[i * n + k] * E[k * n + j];
+      GE[i * n + j] = a;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double a = Cf[i * n + j];
+      for (int k = 0; k < n; ++k) a += GE[i * n + k] * G[j * n + k];
+      Cs[i * n + j] = a;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) { double a = 0.5 * (Cs[i * n + j] + Cs[j * n + i]); Cs[i * n + j] = a; Cs[j * n + i] = a; }
+  return true;
+}
+
+// Forward fit of one track keeping, for every processed layer, the filtered state
+// and covariance and (from layer 1) the Jacobian and the prediction; then the RTS
+// pass.  Writes smoothed states/covariances for layers 0..lend (lend = last layer
+// with an update, -1 if none) and returns the forward status.
+uint32_t smooth_track(const Geo& g, const Layer<double>* lay, const double (*m)[3], uint32_t mask, bool from_hits,
+                      const double* seed_x, const double* seed_C, double (*xs)[6], double (*Cs)[36], int& lend) {
+  static thread_local double xf[32][6], Cf[32][36], xp[32][6], Cp[32][36], Jl[32][36];
+  Track<double> tk;
+  for (int i = 0; i < 6; ++i) { tk.x[i] = 0.0; for (int j = 0; j < 6; ++j) tk.C[i][j] = 0.0; }
+  tk.chi2 = 0.0; tk.n = 0; tk.status = 0;
+  lend = -1;
+  uint32_t need = from_hits ? 7u : 1u;
+  if ((mask & need) != need) return ST_BAD_INPUT;
+  if (from_hits) {
+    seed_from_hits(g, m[0], m[1], m[2], tk);
+  } else {
+    for (int i = 0; i < 6; ++i) tk.x[i] = seed_x[i];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) tk.C[i][j] = seed_C[i * 6 + j];
+  }
+  auto keep = [&](double (*xo)[6], double (*Co)[36], int l) {
+    for (int i = 0; i < 6; ++i) xo[l][i] = tk.x[i];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) Co[l][i * 6 + j] = tk.C[i][j];
+  };
+  if (!update_with_hit(g, lay[0], tk, m[0])) return tk.status;
+  keep(xf, Cf, 0);
+  lend = 0;
+  int last = 31 - __builtin_clz(mask);
+  if (last >= g.nl) last = g.nl - 1;
+  for (int l = 1; l <= last; ++l) {
+    // the prediction of predict(), with its Jacobian kept
+    double s;
+    if (!crossing_arc(tk.x, lay[l].cx, lay[l].cy, lay[l].r, g.kB, s)) { tk.status |= ST_PROP_FAIL; break; }
+    double xe[6], J[6][6];
+    helix_at(tk.x, s, g.kB, xe);
+    transport_jacobian(tk.x, xe, s, g.kB, J);
+    sandwich(J, tk.C);
+    for (int i = 0; i < 6; ++i) tk.x[i] = xe[i];
+    {
+      double ex = tk.x[0] - lay[l].cx, ey = tk.x[1] - lay[l].cy;
+      double ca = (ex * std::cos(tk.x[4]) + ey * std::sin(tk.x[4])) / std::sqrt(ex * ex + ey * ey);
+      if (std::fabs(ca) < 0.3) tk.status |= ST_NEAR_TANGENT;
+    }
+    add_scattering(g, lay[l], tk.x, tk.C);
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) Jl[l][i * 6 + j] = J[i][j];
+    keep(xp, Cp, l);
+    if (mask >> l & 1u) {
+      if (!update_with_hit(g, lay[l], tk, m[l])) break;
+      lend = l;
+    }
+    keep(xf, Cf, l);
+  }
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(tk.x[i])) tk.status |= ST_NONFINITE;
+  if (lend < 0) return tk.status;
+  for (int i = 0; i < 6; ++i) xs[lend][i] = xf[lend][i];
+  for (int i = 0; i < 36; ++i) Cs[lend][i] = Cf[lend][i];
+  for (int l = lend - 1; l >= 0; --l)
+    if (!rts_step(6, xf[l], Cf[l], Jl[l + 1], xp[l + 1], Cp[l + 1], xs[l + 1], Cs[l + 1], xs[l], Cs[l], 4)) {
+      tk.status |= ST_NONFINITE;
+      break;
+    }
+  return tk.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+// One RTS step for an n-dim state (n <= 6), dense row-major; returns 0 if C_p is
+// singular.  wrap_idx: index of an angle component or -1.
+int oracle_rts_step(int n, const double* xf, const double* Cf, const double* J, const double* xp, const double* Cp,
+                    const double* xs1, const double* Cs1, double* xs, double* Cs, int wrap_idx) {
+  return rts_step(n, xf, Cf, J, xp, Cp, xs1, Cs1, xs, Cs, wrap_idx) ? 1 : 0;
+}
+
+}  // extern "C"
+
+namespace {
+template <class HT>
+void smooth_batch(const OGeom* og, const double* align, const double* xX0, int64_t n, const HT* hits,
+                  const uint32_t* mask, int seed_from_hits_flag, const HT* seed_state, const HT* seed_cov,
+                  double* xs_out, double* Cs_out, int32_t* lend_out, uint32_t* status) {
+  Geo g = make_geo(og);
+  Layer<double> lay[32];
+  make_layers<double>(g, align, xX0, lay);
+  const int L = g.nl;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double m[32][3];
+    gather_hits(g, lay, hits, n, i, mask[i], m);
+    double sx[6], sC[36];
+    if (!seed_from_hits_flag) {
+      for (int k = 0; k < 6; ++k) sx[k] = (double)seed_state[(int64_t)k * n + i];
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) sC[a * 6 + b] = (double)seed_cov[(int64_t)tri(a, b) * n + i];
+    }
+    double xs[32][6], Cs[32][36];
+    int lend;
+    status[i] = smooth_track(g, lay, m, mask[i], seed_from_hits_flag != 0, sx, sC, xs, Cs, lend);
+    lend_out[i] = lend;
+    for (int l = 0; l < L; ++l) {
+      const bool have = l <= lend;
+      for (int k = 0; k < 6; ++k) xs_out[((int64_t)l * 6 + k) * n + i] = have ? xs[l][k] : 0.0;
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b <= a; ++b) Cs_out[((int64_t)l * 21 + tri(a, b)) * n + i] = have ? Cs[l][a * 6 + b] : 0.0;
+    }
+  }
+}
+}  // namespace
+
+extern "C" {
+
+// Batched smoother.  Inputs as oracle_fit.  Outputs in float64: xs [L][6][n],
+// Cs [L][21][n] (packed lower triangle) for layers 0..lend[i] (zero elsewhere),
+// lend [n] (last layer with an update, -1 if none), status [n] (the forward fit's).
+void oracle_smooth(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
+                   const uint32_t* mask, int seed_from_hits_flag, const float* seed_state, const float* seed_cov,
+                   double* xs_out, double* Cs_out, int32_t* lend_out, uint32_t* status) {
+  smooth_batch<float>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, xs_out, Cs_out,
+                      lend_out, status);
+}
+
+// As oracle_smooth with float64 hits and seeds.
+void oracle_smooth_f64(const OGeom* og, const double* align, const double* xX0, int64_t n, const double* hits,
+                       const uint32_t* mask, int seed_from_hits_flag, const double* seed_state,
+                       const double* seed_cov, double* xs_out, double* Cs_out, int32_t* lend_out,
+                       uint32_t* status) {
+  smooth_batch<double>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, xs_out, Cs_out,
+                       lend_out, status);
 }
 
 }  // extern "C"

@@ -1,0 +1,165 @@
+"""Pins of the oracle's fixed-interval (Rauch-Tung-Striebel) smoother.
+
+* Linear-Gaussian chain with process noise: the forward filter plus the RTS pass give,
+  at every step, the mean and covariance of the joint Gaussian of all states given all
+  measurements (the batch least-squares solution of the whole chain).
+* Noiseless hits, no material, a wrong seed with a diffuse prior: the smoothed state at
+  every layer is the generating helix there (the filtered state at the inner layers,
+  which has seen only a few hits, is not).
+* Smeared, scattered tracks: smoothed pulls at an inner and a middle layer have zero
+  mean and unit width; the smoothed covariance never exceeds the filtered one; at the
+  last updated layer the smoothed estimate is the filtered one.
+"""
+import math
+
+import numpy as np
+
+import oracle
+import physics
+import synth
+
+
+def _spd(rng, n, scale=1.0):
+    a = rng.normal(size=(n, n))
+    return scale * (a @ a.T + n * np.eye(n))
+
+
+def test_rts_equals_joint_gaussian_posterior(oracle_lib):
+    rng = np.random.default_rng(17)
+    n, m, K = 5, 2, 8                     # states x_0 .. x_K, a measurement at every step
+    F = np.eye(n) + 0.2 * rng.normal(size=(n, n))
+    Qs = [_spd(rng, n, 0.05) for _ in range(K)]
+    Hs = [rng.normal(size=(m, n)) for _ in range(K + 1)]
+    Vs = [_spd(rng, m, 0.1) for _ in range(K + 1)]
+    m0, P0 = rng.normal(size=n), _spd(rng, n)
+    xs_true = [m0 + np.linalg.cholesky(P0) @ rng.normal(size=n)]
+    for k in range(K):
+        xs_true.append(F @ xs_true[-1] + np.linalg.cholesky(Qs[k]) @ rng.normal(size=n))
+    ys = [H @ x + np.linalg.cholesky(V) @ rng.normal(size=m) for H, x, V in zip(Hs, xs_true, Vs)]
+    # forward filter (oracle's generic update), keeping filtered and predicted moments
+    xf, Cf, xp, Cp = [], [], [None], [None]
+    x, C = m0.copy(), P0.copy()
+    for k in range(K + 1):
+        if k > 0:
+            x, C = F @ x, F @ C @ F.T + Qs[k - 1]
+            xp.append(x.copy())
+            Cp.append(C.copy())
+        x, C, _ = oracle.kalman_update(x, C, Hs[k], Vs[k], ys[k] - Hs[k] @ x)
+        xf.append(x.copy())
+        Cf.append(C.copy())
+    # backward RTS pass
+    sx, sC = [None] * (K + 1), [None] * (K + 1)
+    sx[K], sC[K] = xf[K], Cf[K]
+    for k in range(K - 1, -1, -1):
+        sx[k], sC[k] = oracle.rts_step(xf[k], Cf[k], F, xp[k + 1], Cp[k + 1], sx[k + 1], sC[k + 1])
+    # joint Gaussian of (x_0..x_K): information matrix and vector
+    N = n * (K + 1)
+    Lam, eta = np.zeros((N, N)), np.zeros(N)
+    blk = lambda k: slice(k * n, (k + 1) * n)
+    P0i = np.linalg.inv(P0)
+    Lam[blk(0), blk(0)] += P0i
+    eta[blk(0)] += P0i @ m0
+    for k in range(K + 1):
+        Vi = np.linalg.inv(Vs[k])
+        Lam[blk(k), blk(k)] += Hs[k].T @ Vi @ Hs[k]
+        eta[blk(k)] += Hs[k].T @ Vi @ ys[k]
+    for k in range(K):
+        Qi = np.linalg.inv(Qs[k])
+        A = np.hstack([-F, np.eye(n)])             # x_{k+1} - F x_k
+        idx = np.r_[blk(k), blk(k + 1)]
+        Lam[np.ix_(idx, idx)] += A.T @ Qi @ A
+    cov = np.linalg.inv(Lam)
+    mean = cov @ eta
+    for k in range(K + 1):
+        np.testing.assert_allclose(sx[k], mean[blk(k)], rtol=1e-9, atol=1e-10)
+        np.testing.assert_allclose(sC[k], cov[blk(k), blk(k)], rtol=1e-8, atol=1e-11)
+    # the last step is the filtered estimate, and smoothing gains at the first step
+    np.testing.assert_array_equal(sx[K], xf[K])
+    assert np.trace(sC[0]) < 0.9 * np.trace(Cf[0])
+
+
+def _noiseless_smoothing_error(scale):
+    """Worst error of the smoothed states at layers 0, 3 and 8 (positions in cm, kappa
+    relative, angles in rad) and the filtered kappa error at layer 0, for noiseless
+    tracks without material fitted from a seed off by `scale` (diffuse prior)."""
+    geom = synth.workload_geometry(2)
+    geom.xX0[:] = 0.0
+    n = 200
+    rng = np.random.default_rng(23)
+    ts = synth.simulate(geom, synth.rng_for(94), n, (1.0, 50.0), True, 1.5, smear=False,
+                        scatter=False, hit_dtype=np.float64)
+    tr0 = ts.truth[0]
+    r0 = geom.radius[0]
+    seeds = np.zeros((6, n))
+    covs = np.zeros((21, n))
+    for i in range(n):
+        g = rng.normal(size=6)
+        a = math.atan2(tr0[1, i], tr0[0, i]) + scale * g[0] / r0
+        seeds[:, i] = [r0 * math.cos(a), r0 * math.sin(a), tr0[2, i] + scale * g[2],
+                       tr0[3, i] * (1 + scale * g[3]), tr0[4, i] + 0.1 * scale * g[4],
+                       tr0[5, i] + 0.1 * scale * g[5]]
+        w = np.array([1.0, 1.0, 1.0, abs(tr0[3, i]), 0.1, 0.1]) * 10.0
+        covs[:, i] = [(w[a_] ** 2 if a_ == b else 0.0) for a_ in range(6) for b in range(a_ + 1)]
+    sm = oracle.smooth(geom, ts.hits, ts.hit_mask, seed_state=seeds, seed_cov=covs)
+    ok = (sm["status"] & oracle.ST_PROP_FAIL) == 0
+    assert ok.mean() > 0.95
+    worst = 0.0
+    for l in (0, 3, 8):
+        tr = ts.truth[l]
+        xl, _ = physics.project_to_surface(sm["state"][l], oracle.unpack_cov(sm["cov"][l]),
+                                           np.full(n, geom.radius[l]), geom.k_B)
+        d = xl - tr
+        d[4] = (d[4] + math.pi) % (2 * math.pi) - math.pi
+        d[3] = d[3] / tr[3]
+        worst = max(worst, np.max(np.abs(d[:, ok])))
+    o = oracle.fit(geom, ts.hits, ts.hit_mask, seed_state=seeds, seed_cov=covs, records=True)
+    f0 = o["records"][:, 0, 3]
+    filt = np.max(np.abs(f0[ok] / tr0[3, ok] - 1.0))
+    return worst, filt
+
+
+def test_noiseless_smoothed_states_are_the_helix_at_every_layer(oracle_lib):
+    """The smoother works on the forward filter's linearisation, so what it leaves is
+    second order in the filter's error at that layer: with a seed off by 1e-4 it is
+    below 1e-7 at every layer while the filtered curvature at layer 0 is off by ~3e-4,
+    and ten times the seed error gives about a hundred times the smoothed error (a
+    wrong gain, Jacobian or sign would leave a first-order error instead)."""
+    small, filt = _noiseless_smoothing_error(1e-4)
+    large, _ = _noiseless_smoothing_error(1e-3)
+    assert small < 1e-7, small
+    assert filt > 1e-4, filt
+    assert large / small > 30.0, (large, small)
+
+
+def test_smoothed_pulls_covariance_and_last_layer(oracle_lib):
+    geom, ts = synth.fit_workload(2, n=6000, keep_truth=True)
+    n = ts.hits.shape[2]
+    ss = np.zeros((6, n), np.float32)
+    sc = np.zeros((21, n), np.float32)
+    for i in range(n):     # an uninformative seed, so that the hits alone set the scale
+        st, cv = oracle.seed(geom, ts.hits[0, :, i].astype(float), ts.hits[1, :, i].astype(float),
+                             ts.hits[2, :, i].astype(float))
+        ss[:, i] = st
+        sc[:, i] = [cv[a, b] * 1e3 for a in range(6) for b in range(a + 1)]
+    sm = oracle.smooth(geom, ts.hits, ts.hit_mask, seed_state=ss, seed_cov=sc)
+    o = oracle.fit(geom, ts.hits, ts.hit_mask, seed_state=ss, seed_cov=sc, records=True)
+    ok = (sm["status"] == 0) & (sm["lend"] == geom.n_layers - 1)
+    assert ok.mean() > 0.85
+    for l in (2, 8):
+        xl, Cl = physics.project_to_surface(sm["state"][l], oracle.unpack_cov(sm["cov"][l]),
+                                            np.full(n, geom.radius[l]), geom.k_B)
+        for p, v in physics.pulls(xl, Cl, ts.truth[l], idx=(2, 3, 4, 5)).items():
+            assert abs(v[ok].mean()) < 0.05, (l, p, v[ok].mean())
+            assert abs(v[ok].std() - 1.0) < 0.05, (l, p, v[ok].std())
+    # smoothing never adds uncertainty: C_f - C_s is positive semi-definite
+    for l in (0, 5, 12):
+        Cs = oracle.unpack_cov(sm["cov"][l][:, ok])
+        Cf = oracle.unpack_cov(o["records"][:, l, 6:].T[:, ok])
+        D = np.transpose(Cf - Cs, (2, 0, 1))
+        sc_ = np.sqrt(np.einsum("nii->ni", np.transpose(Cf, (2, 0, 1))))
+        Dn = D / sc_[:, :, None] / sc_[:, None, :]
+        assert np.linalg.eigvalsh(Dn).min() > -1e-9
+    # at the last updated layer the smoothed estimate is the filtered one
+    i = np.nonzero(ok)[0]
+    last = sm["lend"][i]
+    np.testing.assert_array_equal(sm["state"][last, :, i], o["state"][:, i].T)
