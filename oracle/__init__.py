@@ -174,6 +174,23 @@ def smooth(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=Non
     return out
 
 
+def smooth_filtered(geom, state, cov, lend, align=None, xX0=None):
+    """The RTS pass alone over given filtered estimates: state [L][6][n] and cov
+    [L][21][n] after each layer (any float type; read as float64), lend [n] the last
+    updated layer.  Returns state/cov as smooth() for layers first..lend (zero
+    elsewhere) and first [n] (the lowest layer reached, -1 if lend < 0)."""
+    state = np.ascontiguousarray(state, np.float64)
+    cov = np.ascontiguousarray(cov, np.float64)
+    lend = np.ascontiguousarray(lend, np.int32)
+    L, _, n = state.shape
+    out = dict(state=np.zeros((L, 6, n)), cov=np.zeros((L, 21, n)), first=np.zeros(n, np.int32))
+    g = ogeom(geom)
+    xx = geom.xX0 if xX0 is None else xX0
+    load().oracle_smooth_filtered(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(lend), _p(state),
+                                  _p(cov), _p(out["state"]), _p(out["cov"]), _p(out["first"]))
+    return out
+
+
 def seed(geom, m0, m1, m2):
     st = np.zeros(6)
     cv = np.zeros(36)
@@ -187,7 +204,8 @@ def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, 
     """Batched FP64 fit; seeds from hits 0-2 unless seed_state/seed_cov are given.
 
     hits [L][3][n] float32 (float64 hits select the float64-input entry), mask [n]
-    uint32.  Returns a dict of float64 outputs.
+    uint32.  Returns a dict of float64 outputs; records=True adds records [n][L][27],
+    the state and packed covariance after each processed layer (NaN beyond).
     """
     dt = np.float64 if np.asarray(hits).dtype == np.float64 else np.float32
     hits = np.ascontiguousarray(hits, dt)

@@ -516,13 +516,16 @@ bool update_with_hit(const Geo& g, const Layer<T>& ly, Track<T>& tk, const T m[3
 
 // Propagate to layer L: crossing, C <- J C J^T, then + Q of the layer's material.
 template <class T>
-bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk) {
+bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nullptr) {
   T s;
   if (!crossing_arc(tk.x, ly.cx, ly.cy, ly.r, g.kB, s)) { tk.status |= ST_PROP_FAIL; return false; }
   T xe[6];
   helix_at(tk.x, s, g.kB, xe);
   T J[6][6];
   transport_jacobian(tk.x, xe, s, g.kB, J);
+  if (J_out)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) J_out[i][j] = J[i][j];
   sandwich(J, tk.C);
   for (int i = 0; i < 6; ++i) tk.x[i] = xe[i];
   {  // crossing angle: |cos alpha| = |r_hat . t| below 0.3 marks a near-tangent crossing
@@ -575,7 +578,8 @@ inline int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1)
 // The fit of one track: seed at layer 0, update on hit 0, then for every later layer
 // up to the last hit: predict (crossing, transport, scattering) and, where the layer
 // has a hit, update.  m[l] are the placed hits, mask bit l marks a hit on layer l.
-// rec (optional) receives the filtered state and covariance after each update, [L][27].
+// rec (optional) receives the state and covariance after each processed layer, [L][27]
+// (after the update, or the prediction where the layer has no hit).
 template <class T>
 Track<T> fit_core(const Geo& g, const Layer<T>* lay, const T (*m)[3], uint32_t mask, bool from_hits,
                   const double* seed_x, const double* seed_C, double* rec) {
@@ -603,10 +607,9 @@ Track<T> fit_core(const Geo& g, const Layer<T>* lay, const T (*m)[3], uint32_t m
   if (last >= g.nl) last = g.nl - 1;
   for (int l = 1; l <= last; ++l) {
     if (!predict(g, lay[l], tk)) break;
-    if (mask >> l & 1u) {
+    if (mask >> l & 1u)
       if (!update_with_hit(g, lay[l], tk, m[l])) break;
-      record(l);
-    }
+    record(l);
   }
   for (int i = 0; i < 6; ++i)
     if (!std::isfinite(val(tk.x[i]))) tk.status |= ST_NONFINITE;
@@ -715,8 +718,8 @@ void oracle_seed(const OGeom* og, const double* m0, const double* m1, const doub
 // and xX0 [L] (either may be null: zero).  seed_from_hits != 0 builds each seed from
 // hits 0-2; otherwise seed_state [6][n] and seed_cov [21][n] are used.  Outputs in
 // float64: state [6][n], cov [21][n] (packed lower triangle, index i(i+1)/2 + j),
-// chi2 [n], ndf [n] = 2 n_hits - 5, status [n]; rec (optional) [n][L][27] filtered
-// state and covariance after each update (NaN elsewhere).
+// chi2 [n], ndf [n] = 2 n_hits - 5, status [n]; rec (optional) [n][L][27] state and
+// covariance after each processed layer (NaN elsewhere).
 }  // extern "C"
 
 namespace {
@@ -1255,20 +1258,8 @@ uint32_t smooth_track(const Geo& g, const Layer<double>* lay, const double (*m)[
   int last = 31 - __builtin_clz(mask);
   if (last >= g.nl) last = g.nl - 1;
   for (int l = 1; l <= last; ++l) {
-    // the prediction of predict(), with its Jacobian kept
-    double s;
-    if (!crossing_arc(tk.x, lay[l].cx, lay[l].cy, lay[l].r, g.kB, s)) { tk.status |= ST_PROP_FAIL; break; }
-    double xe[6], J[6][6];
-    helix_at(tk.x, s, g.kB, xe);
-    transport_jacobian(tk.x, xe, s, g.kB, J);
-    sandwich(J, tk.C);
-    for (int i = 0; i < 6; ++i) tk.x[i] = xe[i];
-    {
-      double ex = tk.x[0] - lay[l].cx, ey = tk.x[1] - lay[l].cy;
-      double ca = (ex * std::cos(tk.x[4]) + ey * std::sin(tk.x[4])) / std::sqrt(ex * ex + ey * ey);
-      if (std::fabs(ca) < 0.3) tk.status |= ST_NEAR_TANGENT;
-    }
-    add_scattering(g, lay[l], tk.x, tk.C);
+    double J[6][6];
+    if (!predict(g, lay[l], tk, J)) break;
     for (int i = 0; i < 6; ++i)
       for (int j = 0; j < 6; ++j) Jl[l][i * 6 + j] = J[i][j];
     keep(xp, Cp, l);
@@ -1291,9 +1282,68 @@ uint32_t smooth_track(const Geo& g, const Layer<double>* lay, const double (*m)[
   return tk.status;
 }
 
+// The RTS pass alone over filtered estimates supplied by the caller (x_f, C_f at
+// layers 0..lend, for instance another implementation's forward fit): the
+// prediction of layer l+1 from x_f(l), C_f(l) is made as in the forward fit, then the
+// step above.  Returns the lowest layer reached (lend if layer lend's predecessor
+// already fails, -1 if lend < 0).
+int smooth_from_filtered(const Geo& g, const Layer<double>* lay, int lend, const double (*xf)[6],
+                         const double (*Cf)[36], double (*xs)[6], double (*Cs)[36]) {
+  if (lend < 0) return -1;
+  for (int i = 0; i < 6; ++i) xs[lend][i] = xf[lend][i];
+  for (int i = 0; i < 36; ++i) Cs[lend][i] = Cf[lend][i];
+  int first = lend;
+  for (int l = lend - 1; l >= 0; --l) {
+    Track<double> tk;
+    for (int i = 0; i < 6; ++i) tk.x[i] = xf[l][i];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) tk.C[i][j] = Cf[l][i * 6 + j];
+    tk.chi2 = 0.0; tk.n = 0; tk.status = 0;
+    double J[6][6];
+    if (!predict(g, lay[l + 1], tk, J)) break;
+    double Cp[36];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) Cp[i * 6 + j] = tk.C[i][j];
+    if (!rts_step(6, xf[l], Cf[l], &J[0][0], tk.x, Cp, xs[l + 1], Cs[l + 1], xs[l], Cs[l], 4)) break;
+    first = l;
+  }
+  return first;
+}
+
 }  // namespace
 
 extern "C" {
+
+// The RTS pass alone (smooth_from_filtered) for a batch: xf [L][6][n] and Cf
+// [L][21][n] (packed lower triangle) hold the filtered estimates after each layer,
+// lend [n] the last updated layer (-1: none).  Outputs as oracle_smooth for layers
+// first[i]..lend[i] (zero elsewhere) and first [n] (-1 if lend < 0).
+void oracle_smooth_filtered(const OGeom* og, const double* align, const double* xX0, int64_t n,
+                            const int32_t* lend, const double* xf, const double* Cf, double* xs_out,
+                            double* Cs_out, int32_t* first_out) {
+  Geo g = make_geo(og);
+  Layer<double> lay[32];
+  make_layers<double>(g, align, xX0, lay);
+  const int L = g.nl;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double x[32][6], C[32][36], xs[32][6], Cs[32][36];
+    const int le = lend[i] < L ? lend[i] : L - 1;
+    for (int l = 0; l <= le; ++l) {
+      for (int k = 0; k < 6; ++k) x[l][k] = xf[((int64_t)l * 6 + k) * n + i];
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) C[l][a * 6 + b] = Cf[((int64_t)l * 21 + tri(a, b)) * n + i];
+    }
+    const int first = smooth_from_filtered(g, lay, le, x, C, xs, Cs);
+    first_out[i] = first;
+    for (int l = 0; l < L; ++l) {
+      const bool have = first >= 0 && l >= first && l <= le;
+      for (int k = 0; k < 6; ++k) xs_out[((int64_t)l * 6 + k) * n + i] = have ? xs[l][k] : 0.0;
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b <= a; ++b) Cs_out[((int64_t)l * 21 + tri(a, b)) * n + i] = have ? Cs[l][a * 6 + b] : 0.0;
+    }
+  }
+}
 
 // One RTS step for an n-dim state (n <= 6), dense row-major; returns 0 if C_p is
 // singular.  wrap_idx: index of an angle component or -1.

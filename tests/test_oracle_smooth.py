@@ -163,3 +163,30 @@ def test_smoothed_pulls_covariance_and_last_layer(oracle_lib):
     i = np.nonzero(ok)[0]
     last = sm["lend"][i]
     np.testing.assert_array_equal(sm["state"][last, :, i], o["state"][:, i].T)
+
+
+def test_rts_pass_over_given_filtered_estimates(oracle_lib):
+    """The RTS pass alone, fed the forward fit's per-layer records, reproduces the full
+    smoother (same arithmetic, so to rounding); layers outside first..lend stay zero."""
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    _, ts = synth.fit_workload(4, n=1500, align=a_true)
+    rng = np.random.default_rng(5)
+    mask = ts.hit_mask.copy()
+    for l in range(3, geom.n_layers):
+        mask[rng.random(mask.size) < 0.15] &= ~np.uint32(1 << l)
+    sm = oracle.smooth(geom, ts.hits, mask, align=a_true)
+    o = oracle.fit(geom, ts.hits, mask, align=a_true, records=True)
+    rec = np.transpose(o["records"], (1, 2, 0))            # [L][27][n]
+    r = oracle.smooth_filtered(geom, rec[:, :6], rec[:, 6:], sm["lend"], align=a_true)
+    ok = (sm["status"] & oracle.ST_PROP_FAIL) == 0
+    assert ok.mean() > 0.95 and (sm["lend"] >= 0).all()
+    np.testing.assert_array_equal(r["first"][ok], 0)
+    np.testing.assert_allclose(r["state"][..., ok], sm["state"][..., ok], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(r["cov"][..., ok], sm["cov"][..., ok], rtol=1e-10, atol=1e-16)
+    # lend = -1 gives nothing; lend = 0 gives layer 0 only, equal to the record
+    lend = np.where(np.arange(mask.size) % 2 == 0, -1, 0).astype(np.int32)
+    r0 = oracle.smooth_filtered(geom, rec[:, :6], rec[:, 6:], lend, align=a_true)
+    assert (r0["first"] == lend).all()
+    assert not r0["state"][1:].any() and not r0["state"][:, :, lend < 0].any()
+    np.testing.assert_array_equal(r0["state"][0][:, lend == 0], rec[0, :6][:, lend == 0])
