@@ -9,8 +9,9 @@ inflated prior.  Synthetic, seeded data (see synth/).
 One step = one kf_fit launch over all tracks (inputs resident in HBM).  The metric is
 Kalman propagate+update steps per second: every hit used by the filter is one step.
 The same JSON line also reports track finding (events/s for one event of 5 000 tracks
-and for 64 events of uneven pileup in one call versus one call per event) and the
-adjoint's cost relative to the forward fit on 1e5 tracks.  Prints one JSON line.
+and for 64 events of uneven pileup in one call versus one call per event), the
+adjoint's cost relative to the forward fit on 1e5 tracks, and the fixed-interval
+smoother over the 1e6-track fit.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -178,6 +179,36 @@ def bench_grad(steps, warmup):
             "backward_over_forward": t_b / t_f}
 
 
+def bench_smooth(steps, warmup, n_tracks):
+    """Fixed-interval smoother over the fit workload: the fit with checkpoints, then
+    kf_smooth of every track (the smoothed state and covariance of every layer)."""
+    import torch
+
+    import synth
+    from paper_1906_11744_amd import Context
+    dev = torch.device("cuda:0")
+    geom, ts = synth.fit_workload(2, n=n_tracks)
+    ctx = Context(geom)
+    hits = torch.from_numpy(np.ascontiguousarray(ts.hits)).to(dev)
+    mask = torch.from_numpy(ts.hit_mask.view(np.int32)).to(dev)
+    xX0 = torch.from_numpy(geom.xX0.astype(np.float32)).to(dev)
+    fwd = ctx.fit(hits, mask, xX0=xX0, ckpt=True)
+    out = ctx.smooth(hits, mask, fwd, xX0=xX0)
+    torch.cuda.synchronize()
+    layers = int((out["last"] - out["first"] + 1).clamp(min=0).sum().item())
+    t_f, _ = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
+    t_s, _ = _time_launches(lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=out), steps, warmup)
+    # HBM bytes of the smoother: a checkpoint (27 floats) read and an estimate (27
+    # floats) written per smoothed layer, mask/ndf/status read and first/last written
+    nbytes = layers * 2 * 27 * 4 + n_tracks * 5 * 4
+    gbs = nbytes / t_s / 1e9
+    return {"tracks": n_tracks, "smoothed_layers": layers, "forward_with_checkpoints_ms": t_f * 1e3,
+            "smooth_ms": t_s * 1e3, "smoothed_layers_per_s": layers / t_s,
+            "roofline": {"kernel": "smooth_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                         "algorithmic_bytes": nbytes}}
+
+
 def copy_calibration(steps):
     """A plain device copy of 1 GiB, `steps` times: the reference kernel whose HBM
     counters (FETCH_SIZE, WRITE_SIZE) calibrate those of the fit kernel."""
@@ -196,7 +227,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "copy"], default="all")
+    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "copy"], default="all")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the fit shards tracks across GPUs with no exchange, "
@@ -280,6 +311,8 @@ def main():
         res["find"] = bench_find(args.steps, args.warmup)
     if args.only in ("all", "grad"):
         res["adjoint"] = bench_grad(args.steps, args.warmup)
+    if args.only in ("all", "smooth"):
+        res["smooth"] = bench_smooth(args.steps, args.warmup, args.tracks)
     print(json.dumps(res), flush=True)
 
 

@@ -57,6 +57,7 @@ extern "C" {
 #define KF_OP_FIT 1
 #define KF_OP_FIND 2
 #define KF_OP_FIT_BACKWARD 3
+#define KF_OP_SMOOTH 4
 
 /* Detector and hit model, copied into the context at creation (host struct). */
 typedef struct kf_geometry {
@@ -187,8 +188,8 @@ int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg);
 int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg);
 
 /* Workspace bytes needed by op (KF_OP_*) for the input `in` (a kf_fit_in or
- * kf_find_in; for KF_OP_FIT_BACKWARD the kf_fit_in of the forward call).  0 for
- * KF_OP_FIT (ws may then be NULL). */
+ * kf_find_in; for KF_OP_FIT_BACKWARD and KF_OP_SMOOTH the kf_fit_in of the forward
+ * call).  0 for KF_OP_FIT (ws may then be NULL). */
 int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes);
 
 /* Batched Kalman fit, one track per GPU lane.  For every track: seed at layer 0,
@@ -232,6 +233,35 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
  * vector-Jacobian product of the fit as implemented by kf_fit. */
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream);
+
+/* Output of kf_smooth: state [L][6][n] and cov [L][21][n] (packed lower triangle) of
+ * every layer first[i]..last[i] of track i, zero on the other layers; last [n] = the
+ * last layer with an update (-1 for a track without one: all layers zero); first [n]
+ * = the innermost layer smoothed (0, unless a step failed: see kf_smooth). */
+typedef struct kf_smooth_out {
+  float* state;
+  float* cov;
+  int32_t* first;
+  int32_t* last;
+} kf_smooth_out;
+
+/* Fixed-interval (Rauch-Tung-Striebel) smoother over a fitted batch: the backward
+ * pass over the built tracks that ends the paper's chain (Sec. 4.2, Sec. 5), on the
+ * filter's own linearisation.  `in` and `params` are those of the forward kf_fit call
+ * and `fwd` its output, which must hold the checkpoints (fwd->ckpt).  For every track,
+ * from its last updated layer (smoothed = filtered there) down to layer 0: the step
+ * to the next layer out is predicted from the checkpoint as the fit does it (x_p,
+ * C_p = J C_f J^T + Q) and
+ *   G = C_f J^T C_p^-1,  x_s = x_f + G (x_s' - x_p),  C_s = C_f + G (C_s' - C_p) G^T,
+ * in float, except C_p's factorisation and the filtered-covariance term, which are
+ * formed in double in a cancellation-free arrangement.  If a step fails (the next
+ * layer is not reached from a checkpoint, or C_p is not positive definite) the
+ * smoothing of that track stops and `first` records where.  A track whose fit ended
+ * with BAD_INPUT has last = first = -1.  KF_E_INVALID for a NULL context, input or
+ * output array, n < 0, or fwd->ckpt NULL; KF_E_WORKSPACE for a short or misaligned
+ * workspace.  Workspace: kf_workspace_size(KF_OP_SMOOTH, in). */
+int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+              const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream);
 
 /* Static description of a return code. */
 const char* kf_strerror(int code);

@@ -159,6 +159,9 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
     case KF_OP_FIND:
       *bytes = find_ws(ctx, static_cast<const kf_find_in*>(in)).total;
       return KF_OK;
+    case KF_OP_SMOOTH:
+      *bytes = fit_ws_bytes();
+      return KF_OK;
     case KF_OP_FIT_BACKWARD: {
       const kf_fit_in* f = static_cast<const kf_fit_in*>(in);
       const size_t n = (size_t)(f->n > 0 ? f->n : 0);
@@ -464,6 +467,44 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   a.n_blocks = kfi::adjoint_blocks(in->n);
   a.part = reinterpret_cast<double*>(base + fit_ws_bytes());
   return kfi::launch_adjoint(a, dalign, dxX0, st) == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+              const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !in || !fwd || !out) return KF_E_INVALID;
+  if (in->n < 0) return KF_E_INVALID;
+  if (in->n == 0) return KF_OK;
+  if (!in->hit_mask || !fwd->ndf || !fwd->status || !fwd->ckpt || !out->state || !out->cov || !out->first ||
+      !out->last)
+    return KF_E_INVALID;
+  if (in->n > (int64_t)INT32_MAX * 64) return KF_E_INVALID;
+  int rc = check_ws(ws, ws_bytes, fit_ws_bytes());
+  if (rc != KF_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(ws);
+  const float* align = params ? params->align : nullptr;
+  const float* xX0 = params ? params->xX0 : nullptr;
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+    return KF_E_HIP;
+  const kfd::Model md = model_of(ctx);
+  kfi::SmoothArgs a;
+  a.n = in->n;
+  a.nl = ctx->g.n_layers;
+  a.k.kB = md.kB;
+  a.k.v_r = md.v_r;
+  a.k.v_rphi = md.v_rphi;
+  a.k.v_z = md.v_z;
+  a.k.mass2 = md.mass2;
+  a.mask = in->hit_mask;
+  a.ndf = fwd->ndf;
+  a.status = fwd->status;
+  a.ckpt = fwd->ckpt;
+  a.layers = layers;
+  a.state = out->state;
+  a.cov = out->cov;
+  a.first = out->first;
+  a.last = out->last;
+  return kfi::launch_smooth(a, st) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
 int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,

@@ -91,6 +91,23 @@ struct AdjArgs {
 int64_t adjoint_blocks(int64_t n);
 
 hipError_t launch_adjoint(const AdjArgs& a, float* dalign, float* dxX0, hipStream_t stream);
+
+struct SmoothArgs {
+  int64_t n;
+  int32_t nl;
+  kfa::Consts<float> k;
+  const uint32_t* mask;
+  const int32_t* ndf;
+  const uint32_t* status;
+  const float* ckpt;
+  const kfd::LayerK* layers;
+  float* state;    // [L][6][n]
+  float* cov;      // [L][21][n]
+  int32_t* first;  // [n]
+  int32_t* last;   // [n]
+};
+
+hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream);
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
 size_t find_lds_bytes(int nl);
 hipError_t find_max_blocks(int nl, int* blocks_per_cu);

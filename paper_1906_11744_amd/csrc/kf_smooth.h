@@ -1,0 +1,274 @@
+// One backward step of the fixed-interval (Rauch-Tung-Striebel) smoother over the
+// batched fit, templated on the scalar type and usable on host and device.
+//
+// The paper's tracking chain ends with a backward pass and a final fit of the built
+// tracks (Sec. 4.2, Sec. 5); here it is the smoother on the filter's own
+// linearisation.  From the filtered estimate (x_f, C_f) at layer l, the step to layer
+// l + 1 is predicted exactly as the fit does it (crossing, fixed-arc transport
+// J, Highland noise Q) to (x_p, C_p = J C_f J^T + Q); with the smoothed (x_s1, C_s1)
+// at l + 1,
+//   G   = C_f J^T C_p^-1,
+//   x_s = x_f + G (x_s1 - x_p)          (azimuth difference wrapped),
+//   C_s = C_f + G (C_s1 - C_p) G^T.
+// In float the textbook covariance update cancels: at the inner layers C_s is orders
+// of magnitude below C_f.  It is evaluated instead as the equivalent sum of
+// positive semi-definite terms
+//   C_s = M C_f M^T + G (Q + C_s1) G^T,   M = I - G J = J^-1 W J,   G = J^-1 (I - W),
+// with W = Q C_p^-1 (J^-1 = I - N + N^2 exactly, N the six off-diagonal transport
+// terms, since N^3 = 0), and the first term reduced to a 3x3 product in double (see
+// below).  Without material W = 0, G = J^-1 and C_s is C_s1 carried back through the
+// step.
+#pragma once
+
+#include "kf_adjoint.h"
+
+namespace kfs {
+
+using kfa::tri;
+
+template <class T>
+KFA_HD T wrap(T a) {
+  const T pi = T(3.14159265358979323846), two_pi = T(6.28318530717958647692);
+  if (a > pi) a -= two_pi;
+  if (a <= -pi) a += two_pi;
+  return a;
+}
+
+// J C J^T (J = I + N, the transport of the step) accumulated in double from a float
+// C: the transported covariance keeps what C itself holds, which the C_p^-1 block
+// below needs.
+template <class T>
+KFA_HD void transport_cov_f64(const kfa::Prop<T>& P, const T C[21], double Co[21]) {
+  const double a03 = P.a03, a04 = P.a04, a13 = P.a13, a14 = P.a14, a25 = P.a25, a43 = P.a43;
+  auto c = [&](int i, int j) { return (double)C[tri(i, j)]; };
+  double B[6][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    B[0][j] = c(0, j) + a03 * c(3, j) + a04 * c(4, j);
+    B[1][j] = c(1, j) + a13 * c(3, j) + a14 * c(4, j);
+    B[2][j] = c(2, j) + a25 * c(5, j);
+    B[3][j] = c(3, j);
+    B[4][j] = c(4, j) + a43 * c(3, j);
+    B[5][j] = c(5, j);
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    Co[tri(i, 0)] = B[i][0] + a03 * B[i][3] + a04 * B[i][4];
+    if (i >= 1) Co[tri(i, 1)] = B[i][1] + a13 * B[i][3] + a14 * B[i][4];
+    if (i >= 2) Co[tri(i, 2)] = B[i][2] + a25 * B[i][5];
+    if (i >= 3) Co[tri(i, 3)] = B[i][3];
+    if (i >= 4) Co[tri(i, 4)] = B[i][4] + a43 * B[i][3];
+    if (i >= 5) Co[tri(i, 5)] = B[i][5];
+  }
+}
+
+// The smoothed state is carried as its offset from the filtered one, ds = x_s - x_f:
+// offsets are small, so their float rounding is relative to the offset and does not
+// accumulate over the layers (a smoothed theta carried whole, rounded at every step,
+// would drift by ulps that the 100 cm lever arm turns into ~1e-4 cm in z).
+template <class T>
+KFA_HD void smoothed_state(const T xf[6], const T ds[6], T xs[6]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) xs[q] = xf[q] + ds[q];
+  xs[4] = wrap(xs[4]);
+}
+
+// One step in place: on entry (ds, Cs) is the smoothed estimate at layer l + 1 (ds its
+// offset from the filtered state xf1 there), on return the one at layer l (ds the
+// offset from xf).  xf, Cf: filtered estimate at l (packed lower C); ly1: the
+// constants of layer l + 1.  Returns false (ds, Cs unchanged) if layer l + 1 is not
+// reached from x_f or C_p is not positive definite.
+template <class T>
+KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::Lay<T>& ly1,
+                     const kfa::Consts<T>& k, T ds[6], T Cs[21]) {
+  using std::sqrt;
+  kfa::Prop<T> P;
+  T xp[6];
+  if (!kfa::propagate(xf, ly1, k, P, xp)) return false;
+  T Q[21];
+  const kfa::Frm<T> fr = kfa::frame(xp, ly1);
+  kfa::Scat<T> S;
+#pragma unroll
+  for (int q = 0; q < 21; ++q) Q[q] = T(0);
+  kfa::scatter(xp, fr, ly1, k, S, Q);  // Q alone: (kappa, phi, theta) block
+  // J = I + N and J^-1 = I - N + N^2, as dense 6x6
+  T N[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) N[i][j] = T(0);
+  N[0][3] = P.a03;
+  N[0][4] = P.a04;
+  N[1][3] = P.a13;
+  N[1][4] = P.a14;
+  N[2][5] = P.a25;
+  N[4][3] = P.a43;
+  T Ji[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) Ji[i][j] = (i == j ? T(1) : T(0)) - N[i][j];
+  Ji[0][3] += N[0][4] * N[4][3];
+  Ji[1][3] += N[1][4] * N[4][3];
+  // Only Q's (kappa, phi, theta) block Q3 is non-zero, so W = Q C_p^-1 has non-zero
+  // rows 3..5 only: W[3+a][i] = sum_b Q3[a][b] (C_p^-1)[3+b][i].  With R the same block
+  // of C_p^-1 and J C_f J^T = C_p - Q, the first term of C_s is
+  //   M C_f M^T = J^-1 W (C_p - Q) W^T J^-T = K T K^T,  T = Q3 R Q3 (I - R Q3),
+  // K = columns 3..5 of J^-1: a 3x3 product in place of the 6x6 sandwich of C_f,
+  // which at layers the fit saw through few hits (C_f orders of magnitude above C_s)
+  // would cancel.  C_p^-1's three columns come from a Cholesky factorisation of C_p
+  // equilibrated to unit diagonal, and R, T and W are formed, in double: C_p's
+  // condition number after equilibration can still reach ~1e5.
+  // C_p = J C_f J^T + Q in double (where the scattering dominates the filtered
+  // angles, I - R Q3 below recovers the part of J C_f J^T that a float C_p would
+  // round away), then factorised in place
+  double dsc[6], L[21];
+  transport_cov_f64(P, Cf, L);
+#pragma unroll
+  for (int q = 0; q < 21; ++q) L[q] += (double)Q[q];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    if (!(L[tri(i, i)] > 0.0)) return false;
+    dsc[i] = 1.0 / sqrt(L[tri(i, i)]);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double djj = L[tri(j, j)] * dsc[j] * dsc[j];
+#pragma unroll
+    for (int q = 0; q < j; ++q) djj -= L[tri(j, q)] * L[tri(j, q)];
+    if (!(djj > 0.0)) return false;
+    const double ljj = sqrt(djj);
+    L[tri(j, j)] = ljj;
+    const double inv = 1.0 / ljj;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double a = L[tri(i, j)] * dsc[i] * dsc[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) a -= L[tri(i, q)] * L[tri(j, q)];
+      L[tri(i, j)] = a * inv;
+    }
+  }
+  double Y[3][6];  // Y[b] = C_p^-1 e_(3+b)
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    double y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double a = i == 3 + b ? dsc[i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < i; ++q) a -= L[tri(i, q)] * y[q];
+      y[i] = a / L[tri(i, i)];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+      double a = y[i];
+#pragma unroll
+      for (int q = i + 1; q < 6; ++q) a -= L[tri(q, i)] * y[q];
+      y[i] = a / L[tri(i, i)];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Y[b][i] = y[i] * dsc[i];
+  }
+  double Q3[3][3], A[3][3], Tm[3][3], V[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Q3[a][b] = (double)Q[tri(3 + a, 3 + b)];
+  T W[6][6];  // rows 3..5 only
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double w = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) w += Q3[a][b] * Y[b][i];
+      W[3 + a][i] = (T)w;
+      if (i >= 3) A[a][i - 3] = w;  // Q3 R
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double v = a == b ? 1.0 : 0.0, t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        v -= Y[q][3 + a] * Q3[q][b];  // (I - R Q3)
+        t += A[a][q] * Q3[q][b];      // Q3 R Q3
+      }
+      V[a][b] = v;
+      Tm[a][b] = t;
+    }
+  double T3[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) t += Tm[a][q] * V[q][b];
+      T3[a][b] = t;
+    }
+  // G = J^-1 (I - W)
+  T G[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      T g = Ji[i][j];
+#pragma unroll
+      for (int q = 3; q < 6; ++q) g -= Ji[i][q] * W[q][j];
+      G[i][j] = g;
+    }
+  // state: x_s - x_f = G (x_s1 - x_p), with x_s1 - x_p = ds1 + (x_f1 - x_p) and x_f1 -
+  // x_p taken as the difference of the two filtered states less the step (exact or
+  // nearly so in float: the rounding of x_p's ~100 cm coordinates would otherwise cost
+  // ~4e-6 cm against differences of ~1e-3 cm)
+  T d[6];
+  d[0] = ds[0] + ((xf1[0] - xf[0]) - P.dx);
+  d[1] = ds[1] + ((xf1[1] - xf[1]) - P.dy);
+  d[2] = ds[2] + ((xf1[2] - xf[2]) - P.s * P.ct / P.st);
+  d[3] = ds[3] + (xf1[3] - xf[3]);
+  d[4] = ds[4] + (wrap(xf1[4] - xf[4]) - P.u);
+  d[5] = ds[5] + (xf1[5] - xf[5]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T a = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a += G[i][j] * d[j];
+    ds[i] = a;
+  }
+  // covariance: C_s = K T K^T + G (Q + C_s1) G^T
+  T KT[6][3], GE[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      T a = T(0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) a += Ji[i][3 + q] * (T)(0.5 * (T3[q][b] + T3[b][q]));
+      KT[i][b] = a;
+    }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      T b = T(0);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) b += G[i][q] * (Q[tri(q, j)] + Cs[tri(q, j)]);
+      GE[i][j] = b;
+    }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      T acc = T(0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc += KT[i][q] * Ji[j][3 + q];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) acc += GE[i][q] * G[j][q];
+      Cs[tri(i, j)] = acc;
+    }
+  return true;
+}
+
+}  // namespace kfs

@@ -1,0 +1,70 @@
+// Fixed-interval smoother over a fitted batch (kf_smooth): one track per lane walks
+// from its last updated layer inwards, reading the forward fit's checkpoint of each
+// layer and applying the step of kf_smooth.h.
+#include "kf_internal.h"
+#include "kf_smooth.h"
+
+namespace kfi {
+
+__global__ __launch_bounds__(64) void smooth_kernel(SmoothArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t n = a.n;
+  const int nl = a.nl;
+  const kfa::Lay<float>* lays = reinterpret_cast<const kfa::Lay<float>*>(a.layers);
+  const uint32_t st = a.status[i];
+  const int nh = (a.ndf[i] + 5) / 2;
+  int lend = (st & kfd::ST_BAD_INPUT) ? -1 : kfa::last_updated_layer(a.mask[i], nh, nl);
+  if (lend > nl - 1) lend = nl - 1;
+  auto put = [&](int l, const float x[6], const float C[21]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a.state[((int64_t)l * 6 + q) * n + i] = x[q];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) a.cov[((int64_t)l * 21 + q) * n + i] = C[q];
+  };
+  float zx[6], zC[21];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) zx[q] = 0.f;
+#pragma unroll
+  for (int q = 0; q < 21; ++q) zC[q] = 0.f;
+  for (int l = nl - 1; l > lend; --l) put(l, zx, zC);
+  int first = lend;
+  if (lend >= 0) {
+    // carried inwards: the smoothed covariance and the smoothed state's offset from
+    // the filtered one, with the filtered state of the layer outside
+    float xf1[6], ds[6], Cs[21];
+    const float* p = a.ckpt + (int64_t)lend * 27 * n + i;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) xf1[q] = p[q * n];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) ds[q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Cs[q] = p[(6 + q) * n];
+    put(lend, xf1, Cs);
+    for (int l = lend - 1; l >= 0; --l) {
+      float xf[6], Cf[21], xs[6];
+      const float* c = a.ckpt + (int64_t)l * 27 * n + i;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) xf[q] = c[q * n];
+#pragma unroll
+      for (int q = 0; q < 21; ++q) Cf[q] = c[(6 + q) * n];
+      if (!kfs::rts_step<float>(xf, Cf, xf1, lays[l + 1], a.k, ds, Cs)) break;
+      kfs::smoothed_state<float>(xf, ds, xs);
+      put(l, xs, Cs);
+      first = l;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) xf1[q] = xf[q];
+    }
+  }
+  for (int l = (lend < 0 ? nl : first) - 1; l >= 0; --l) put(l, zx, zC);
+  a.first[i] = lend < 0 ? -1 : first;
+  a.last[i] = lend;
+}
+
+hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream) {
+  const int64_t nb = (a.n + 63) / 64;
+  hipLaunchKernelGGL(smooth_kernel, dim3((unsigned)nb), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace kfi

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libkf.so")
 
 KF_MAX_LAYERS = 32
 KF_MAX_KEEP = 8
-KF_OP_FIT, KF_OP_FIND, KF_OP_FIT_BACKWARD = 1, 2, 3
+KF_OP_FIT, KF_OP_FIND, KF_OP_FIT_BACKWARD, KF_OP_SMOOTH = 1, 2, 3, 4
 
 ST_PROP_FAIL = 1
 ST_NEAR_TANGENT = 2
@@ -90,6 +90,8 @@ def _lib():
         lib.kf_find_autotune.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FindIn),
                                          C.POINTER(FindOut), C.c_void_p, C.c_size_t, C.c_void_p,
                                          C.POINTER(FindConfig)]
+        lib.kf_smooth.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn), C.POINTER(FitOut),
+                                  C.POINTER(SmoothOut), C.c_void_p, C.c_size_t, C.c_void_p]
         lib.kf_fit_backward.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn), C.POINTER(FitOut),
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         _LIB = lib
@@ -122,6 +124,10 @@ def _dev(t, dtype, shape=None, name="tensor"):
 def _stream(stream):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+class SmoothOut(C.Structure):
+    _fields_ = [("state", C.c_void_p), ("cov", C.c_void_p), ("first", C.c_void_p), ("last", C.c_void_p)]
 
 
 class FindConfig(C.Structure):
@@ -282,6 +288,33 @@ class Context:
                                   ws.numel(), _stream(stream)), "kf_find")
         return out
 
+    def smooth(self, hits, hit_mask, fwd, align=None, xX0=None, out=None, stream=None):
+        """kf_smooth: smoothed state [L][6][n] and cov [L][21][n] of every layer of a
+        fitted batch (fwd from fit(..., ckpt=True) with the same align/xX0), and the
+        per-track first/last smoothed layers."""
+        L = self.n_layers
+        n = hits.shape[2]
+        dev = hits.device
+        if fwd.get("ckpt") is None:
+            raise ValueError("the forward fit must be run with ckpt=True")
+        _dev(align, torch.float32, (L, 4), "align")
+        _dev(xX0, torch.float32, (L,), "xX0")
+        if out is None:
+            out = dict(state=torch.empty((L, 6, n), dtype=torch.float32, device=dev),
+                       cov=torch.empty((L, 21, n), dtype=torch.float32, device=dev),
+                       first=torch.empty(n, dtype=torch.int32, device=dev),
+                       last=torch.empty(n, dtype=torch.int32, device=dev))
+        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1)
+        fo = FitOut(fwd["state"].data_ptr(), fwd["cov"].data_ptr(), fwd["chi2"].data_ptr(),
+                    fwd["ndf"].data_ptr(), fwd["status"].data_ptr(), fwd["ckpt"].data_ptr())
+        so = SmoothOut(out["state"].data_ptr(), out["cov"].data_ptr(), out["first"].data_ptr(),
+                       out["last"].data_ptr())
+        ws = self.workspace(KF_OP_SMOOTH, fin, dev)
+        p = self._params(align, xX0)
+        _check(_lib().kf_smooth(self._h, C.byref(p), C.byref(fin), C.byref(fo), C.byref(so),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "kf_smooth")
+        return out
+
     def fit_backward(self, hits, hit_mask, fwd, dchi2, align=None, xX0=None, stream=None):
         """kf_fit_backward: dLoss/dalign [L][4] and dLoss/dxX0 [L] given dLoss/dchi2 [n]
         and the forward outputs (with checkpoints) of a seed-from-hits fit."""
@@ -309,4 +342,4 @@ def exported_symbols():
     """Names the header declares (for the load check)."""
     return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_ctx_set_find_config",
             "kf_ctx_get_find_config", "kf_workspace_size", "kf_fit", "kf_find", "kf_find_autotune",
-            "kf_fit_backward", "kf_strerror"]
+            "kf_smooth", "kf_fit_backward", "kf_strerror"]
