@@ -122,49 +122,61 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
   // C_p = J C_f J^T + Q in double (where the scattering dominates the filtered
   // angles, I - R Q3 below recovers the part of J C_f J^T that a float C_p would
   // round away), then factorised in place
-  double dsc[6], L[21];
+  // No correctly rounded division or square root is needed: the equilibration
+  // scale is any positive number near C_p's diagonal^-1/2 (it is undone exactly), and
+  // the pivots' inverse square roots are float estimates refined by two Newton steps
+  // in double (relative error ~1e-16).
+  double dsc[6], L[21], linv[6];
   transport_cov_f64(P, Cf, L);
 #pragma unroll
   for (int q = 0; q < 21; ++q) L[q] += (double)Q[q];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    if (!(L[tri(i, i)] > 0.0)) return false;
-    dsc[i] = 1.0 / sqrt(L[tri(i, i)]);
+    const double cii = L[tri(i, i)];
+    if (!(cii > 1e-30 && cii < 1e30)) return false;
+    dsc[i] = (double)(1.0f / sqrt((float)cii));
   }
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     double djj = L[tri(j, j)] * dsc[j] * dsc[j];
 #pragma unroll
     for (int q = 0; q < j; ++q) djj -= L[tri(j, q)] * L[tri(j, q)];
-    if (!(djj > 0.0)) return false;
-    const double ljj = sqrt(djj);
-    L[tri(j, j)] = ljj;
-    const double inv = 1.0 / ljj;
+    if (!(djj > 1e-30)) return false;  // not positive definite (to double rounding)
+    double r = (double)(1.0f / sqrt((float)djj));
+    r = r * (1.5 - 0.5 * djj * r * r);
+    r = r * (1.5 - 0.5 * djj * r * r);
+    L[tri(j, j)] = djj * r;
+    linv[j] = r;
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       double a = L[tri(i, j)] * dsc[i] * dsc[j];
 #pragma unroll
       for (int q = 0; q < j; ++q) a -= L[tri(i, q)] * L[tri(j, q)];
-      L[tri(i, j)] = a * inv;
+      L[tri(i, j)] = a * r;
     }
   }
-  double Y[3][6];  // Y[b] = C_p^-1 e_(3+b)
+  double Y[3][6];  // Y[b] = C_p^-1 e_(3+b); the forward sweep starts at row 3+b
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
+    const int c = 3 + b;
     double y[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      double a = i == 3 + b ? dsc[i] : 0.0;
+      if (i < c) {
+        y[i] = 0.0;
+        continue;
+      }
+      double a = i == c ? dsc[i] : 0.0;
 #pragma unroll
-      for (int q = 0; q < i; ++q) a -= L[tri(i, q)] * y[q];
-      y[i] = a / L[tri(i, i)];
+      for (int q = c; q < i; ++q) a -= L[tri(i, q)] * y[q];
+      y[i] = a * linv[i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
       double a = y[i];
 #pragma unroll
       for (int q = i + 1; q < 6; ++q) a -= L[tri(q, i)] * y[q];
-      y[i] = a / L[tri(i, i)];
+      y[i] = a * linv[i];
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) Y[b][i] = y[i] * dsc[i];

@@ -41,13 +41,24 @@ __global__ __launch_bounds__(64) void smooth_kernel(SmoothArgs a) {
 #pragma unroll
     for (int q = 0; q < 21; ++q) Cs[q] = p[(6 + q) * n];
     put(lend, xf1, Cs);
+    // the checkpoint of the next layer in is loaded one step ahead, so that its HBM
+    // latency overlaps the current step's arithmetic
+    float nx[6], nC[21];
+    auto load = [&](int l) {  // l = -1 (after the last step) re-reads layer 0: in bounds, unused
+      const float* c = a.ckpt + (int64_t)(l < 0 ? 0 : l) * 27 * n + i;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) nx[q] = c[q * n];
+#pragma unroll
+      for (int q = 0; q < 21; ++q) nC[q] = c[(6 + q) * n];
+    };
+    load(lend - 1);
     for (int l = lend - 1; l >= 0; --l) {
       float xf[6], Cf[21], xs[6];
-      const float* c = a.ckpt + (int64_t)l * 27 * n + i;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) xf[q] = c[q * n];
+      for (int q = 0; q < 6; ++q) xf[q] = nx[q];
 #pragma unroll
-      for (int q = 0; q < 21; ++q) Cf[q] = c[(6 + q) * n];
+      for (int q = 0; q < 21; ++q) Cf[q] = nC[q];
+      load(l - 1);
       if (!kfs::rts_step<float>(xf, Cf, xf1, lays[l + 1], a.k, ds, Cs)) break;
       kfs::smoothed_state<float>(xf, ds, xs);
       put(l, xs, Cs);
