@@ -57,13 +57,15 @@ struct Prop {
   T Ds;              // e' . t' (d|p - c|^2 / ds / 2)
 };
 
+// sin and cos of one angle (one range reduction for both in float)
+KFA_HD void sin_cos(float a, float& s, float& c) { sincosf(a, &s, &c); }
+KFA_HD void sin_cos(double a, double& s, double& c) { s = std::sin(a); c = std::cos(a); }
+
 template <class T>
 KFA_HD bool propagate(const T x[6], const Lay<T>& ly, const Consts<T>& k, Prop<T>& P, T xo[6]) {
   using std::atan; using std::cos; using std::sin; using std::sqrt; using std::fabs;
-  P.cp = cos(x[4]);
-  P.sp = sin(x[4]);
-  P.st = sin(x[5]);
-  P.ct = cos(x[5]);
+  sin_cos(x[4], P.sp, P.cp);
+  sin_cos(x[5], P.st, P.ct);
   const T ex = x[0] - ly.cx, ey = x[1] - ly.cy;
   const T a = ex * P.cp + ey * P.sp;
   const T b = ey * P.cp - ex * P.sp;
@@ -77,7 +79,19 @@ KFA_HD bool propagate(const T x[6], const Lay<T>& ly, const Consts<T>& k, Prop<T
   const T sig = -c0 / (T(2) * den);
   const T tau = w * sig;
   const T tau2 = tau * tau;
-  const T q = fabs(tau) < T(1e-2) ? T(1) + tau2 * (T(-1) / T(3) + tau2 * T(0.2)) : atan(tau) / tau;
+  // atan(tau)/tau by its Taylor series where the truncation is below the type's
+  // rounding: to tau^12 below |tau| = 0.3 in float (< 3e-9), to tau^4 below 1e-2 in
+  // double (< 2e-13); atan beyond
+  T q;
+  if constexpr (sizeof(T) == 4) {
+    if (fabs(tau) < T(0.3))
+      q = T(1) + tau2 * (T(-1) / T(3) + tau2 * (T(0.2) + tau2 * (T(-1) / T(7) + tau2 * (T(1) / T(9) +
+          tau2 * (T(-1) / T(11) + tau2 * (T(1) / T(13)))))));
+    else
+      q = atan(tau) / tau;
+  } else {
+    q = fabs(tau) < T(1e-2) ? T(1) + tau2 * (T(-1) / T(3) + tau2 * T(0.2)) : atan(tau) / tau;
+  }
   const T f = T(2) * sig / (T(1) + tau2);
   P.w = w;
   P.s = T(2) * sig * q;
@@ -663,17 +677,21 @@ KFA_HD void place(const Lay<T>& ly, T hx, T hy, T hz, T m[3]) {
 //   hit(l, h[3])     nominal hit on layer l;
 //   ckpt(l, x, C)    state and covariance after layer l of the forward fit;
 //   lstart           last layer the forward updated (all layers up to it processed);
+//   ltop             first layer index of the sweep (>= lstart): layers above lstart
+//                    are passed over, so that lanes of a wave that start the sweep at
+//                    the same ltop visit the same layer in every iteration;
 //   emit(l, g[5])    gradient contribution of layer l (d/d cx, cy, dz, dphi, xX0),
 //                    called once per layer from lstart down to 0, then for 1 and 2
 //                    again with the seed's share.
 // Returns false if a recomputed step fails (no contribution then).
 template <class T, class Hit, class Ckpt, class Emit>
-KFA_HD bool track_adjoint(int lstart, uint32_t mask, const Lay<T>* lays, const Consts<T>& k, const T Cs[21], T w,
-                          Hit hit, Ckpt ckpt, Emit emit) {
+KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lays, const Consts<T>& k,
+                          const T Cs[21], T w, Hit hit, Ckpt ckpt, Emit emit) {
   T xb[6] = {0, 0, 0, 0, 0, 0};
   T Cb[21];
   for (int q = 0; q < 21; ++q) Cb[q] = T(0);
-  for (int l = lstart; l >= 1; --l) {
+  for (int l = ltop; l >= 1; --l) {
+    if (l > lstart) continue;
     const Lay<T>& ly = lays[l];
     T x[6], C[21];
     ckpt(l - 1, x, C);

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) my[l * 5 + q] += g[q];
       };
-      if (!kfa::track_adjoint<float>(lstart, mask, lays, a.k, Cs, w, hit, ckpt, emit))
+      if (!kfa::track_adjoint<float>(lstart, nl - 1, mask, lays, a.k, Cs, w, hit, ckpt, emit))
         for (int o = 0; o < R; ++o) my[o] = 0.f;
     }
   }

@@ -1,6 +1,6 @@
-// Fixed-interval smoother over a fitted batch (kf_smooth): one track per lane walks
-// from its last updated layer inwards, reading the forward fit's checkpoint of each
-// layer and applying the step of kf_smooth.h.
+// Fixed-interval smoother over a fitted batch (kf_smooth): one track per lane, walked
+// from its last updated layer inwards over the forward fit's checkpoint of each layer
+// with the step of kf_smooth.h.
 #include "kf_internal.h"
 #include "kf_smooth.h"
 
@@ -16,58 +16,55 @@ __global__ __launch_bounds__(64) void smooth_kernel(SmoothArgs a) {
   const int nh = (a.ndf[i] + 5) / 2;
   int lend = (st & kfd::ST_BAD_INPUT) ? -1 : kfa::last_updated_layer(a.mask[i], nh, nl);
   if (lend > nl - 1) lend = nl - 1;
-  auto put = [&](int l, const float x[6], const float C[21]) {
+  // Every lane walks the same layer index, from the outermost layer in, so that each
+  // load and store of a wave covers one contiguous run of its array (lanes whose last
+  // updated layers differ would otherwise address different layers in one
+  // instruction).  A lane writes zeros above its last updated layer and below a
+  // failed step.  Carried inwards: the smoothed covariance and the smoothed state's
+  // offset from the filtered one, with the filtered state of the layer outside.
+  float xf1[6], ds[6], Cs[21];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) a.state[((int64_t)l * 6 + q) * n + i] = x[q];
+  for (int q = 0; q < 6; ++q) xf1[q] = ds[q] = 0.f;
 #pragma unroll
-    for (int q = 0; q < 21; ++q) a.cov[((int64_t)l * 21 + q) * n + i] = C[q];
-  };
-  float zx[6], zC[21];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) zx[q] = 0.f;
-#pragma unroll
-  for (int q = 0; q < 21; ++q) zC[q] = 0.f;
-  for (int l = nl - 1; l > lend; --l) put(l, zx, zC);
+  for (int q = 0; q < 21; ++q) Cs[q] = 0.f;
   int first = lend;
-  if (lend >= 0) {
-    // carried inwards: the smoothed covariance and the smoothed state's offset from
-    // the filtered one, with the filtered state of the layer outside
-    float xf1[6], ds[6], Cs[21];
-    const float* p = a.ckpt + (int64_t)lend * 27 * n + i;
+  bool live = false;
+  // the checkpoint of the next layer in is loaded one step ahead, so that its HBM
+  // latency overlaps the current step's arithmetic
+  float nx[6], nC[21];
+  auto load = [&](int l) {  // l = -1 (after the last step) re-reads layer 0: in bounds, unused
+    const float* c = a.ckpt + (int64_t)(l < 0 ? 0 : l) * 27 * n + i;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) xf1[q] = p[q * n];
+    for (int q = 0; q < 6; ++q) nx[q] = c[q * n];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) ds[q] = 0.f;
+    for (int q = 0; q < 21; ++q) nC[q] = c[(6 + q) * n];
+  };
+  load(nl - 1);
+  for (int l = nl - 1; l >= 0; --l) {
+    float xf[6], Cf[21], xs[6];
 #pragma unroll
-    for (int q = 0; q < 21; ++q) Cs[q] = p[(6 + q) * n];
-    put(lend, xf1, Cs);
-    // the checkpoint of the next layer in is loaded one step ahead, so that its HBM
-    // latency overlaps the current step's arithmetic
-    float nx[6], nC[21];
-    auto load = [&](int l) {  // l = -1 (after the last step) re-reads layer 0: in bounds, unused
-      const float* c = a.ckpt + (int64_t)(l < 0 ? 0 : l) * 27 * n + i;
+    for (int q = 0; q < 6; ++q) xf[q] = nx[q];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) nx[q] = c[q * n];
+    for (int q = 0; q < 21; ++q) Cf[q] = nC[q];
+    load(l - 1);
+    if (l == lend) {
+      live = true;
 #pragma unroll
-      for (int q = 0; q < 21; ++q) nC[q] = c[(6 + q) * n];
-    };
-    load(lend - 1);
-    for (int l = lend - 1; l >= 0; --l) {
-      float xf[6], Cf[21], xs[6];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) xf[q] = nx[q];
-#pragma unroll
-      for (int q = 0; q < 21; ++q) Cf[q] = nC[q];
-      load(l - 1);
-      if (!kfs::rts_step<float>(xf, Cf, xf1, lays[l + 1], a.k, ds, Cs)) break;
-      kfs::smoothed_state<float>(xf, ds, xs);
-      put(l, xs, Cs);
-      first = l;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) xf1[q] = xf[q];
+      for (int q = 0; q < 21; ++q) Cs[q] = Cf[q];
+    } else if (live) {
+      if (kfs::rts_step<float>(xf, Cf, xf1, lays[l + 1], a.k, ds, Cs))
+        first = l;
+      else
+        live = false;
     }
+    kfs::smoothed_state<float>(xf, ds, xs);  // ds = 0 at l == lend
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a.state[((int64_t)l * 6 + q) * n + i] = live ? xs[q] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) a.cov[((int64_t)l * 21 + q) * n + i] = live ? Cs[q] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) xf1[q] = xf[q];
   }
-  for (int l = (lend < 0 ? nl : first) - 1; l >= 0; --l) put(l, zx, zC);
   a.first[i] = lend < 0 ? -1 : first;
   a.last[i] = lend;
 }

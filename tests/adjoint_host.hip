@@ -83,7 +83,7 @@ extern "C" int adjoint_host_fp64(int nl, const double* radius, double B, double 
     auto emit = [&](int l, const T g[5]) {
       for (int q = 0; q < 5; ++q) gi[l * 5 + q] += g[q];
     };
-    if (!kfa::track_adjoint<T>(lupd, m, lays.data(), k, Cs, w ? w[i] : 1.0, hit, ckpt, emit)) return -1;
+    if (!kfa::track_adjoint<T>(lupd, nl - 1, m, lays.data(), k, Cs, w ? w[i] : 1.0, hit, ckpt, emit)) return -1;
     for (int q = 0; q < nl * 5; ++q) acc[q] += gi[q];
   }
   for (int l = 0; l < nl; ++l) {
