@@ -53,17 +53,33 @@ FIT_TRAFFIC = {"sources": "99ddcc3026af2f69", "tracks": 1_000_000,
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
 
-def fit_traffic_bytes(n_tracks):
-    """Measured HBM bytes per fit launch, or None if the kernel or workload differs."""
+# The same for one smooth_kernel launch on that workload (mean of 4 launches).
+SMOOTH_TRAFFIC = {"sources": "da16f4fd62d16e50", "tracks": 1_000_000,
+                  "fetch_kib": 906681.7, "write_kib": 1800781.2,
+                  "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
+SMOOTH_SOURCES = ("paper_1906_11744_amd/csrc/kf_smooth.hip", "paper_1906_11744_amd/csrc/kf_smooth.h",
+                  "paper_1906_11744_amd/csrc/kf_adjoint.h")
+
+
+def _traffic_bytes(table, sources, n_tracks):
     import hashlib
     h = hashlib.sha256()
-    for f in FIT_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != FIT_TRAFFIC["sources"] or n_tracks != FIT_TRAFFIC["tracks"]:
+    if h.hexdigest()[:16] != table["sources"] or n_tracks != table["tracks"]:
         return None
-    t = FIT_TRAFFIC
-    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    return 1024.0 * (table["fetch_kib"] * table["fetch_scale"] + table["write_kib"] * table["write_scale"])
+
+
+def fit_traffic_bytes(n_tracks):
+    """Measured HBM bytes per fit launch, or None if the kernel or workload differs."""
+    return _traffic_bytes(FIT_TRAFFIC, FIT_SOURCES, n_tracks)
+
+
+def smooth_traffic_bytes(n_tracks):
+    """Measured HBM bytes per smoother launch, or None if the kernel or workload differs."""
+    return _traffic_bytes(SMOOTH_TRAFFIC, SMOOTH_SOURCES, n_tracks)
 
 
 def algorithmic_flops(n_hits_per_track, xX0_positive=True):
@@ -198,14 +214,15 @@ def bench_smooth(steps, warmup, n_tracks):
     layers = int((out["last"] - out["first"] + 1).clamp(min=0).sum().item())
     t_f, _ = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
     t_s, _ = _time_launches(lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=out), steps, warmup)
-    # HBM bytes of the smoother: a checkpoint (27 floats) read and an estimate (27
-    # floats) written per smoothed layer, mask/ndf/status read and first/last written
-    nbytes = layers * 2 * 27 * 4 + n_tracks * 5 * 4
+    # HBM bytes the smoother must move: the checkpoint (27 floats) of every smoothed
+    # layer read, the whole output (27 floats on every layer, zeros included) written,
+    # mask/ndf/status read and first/last written
+    nbytes = layers * 27 * 4 + geom.n_layers * n_tracks * 27 * 4 + n_tracks * 5 * 4
     gbs = nbytes / t_s / 1e9
     return {"tracks": n_tracks, "smoothed_layers": layers, "forward_with_checkpoints_ms": t_f * 1e3,
             "smooth_ms": t_s * 1e3, "smoothed_layers_per_s": layers / t_s,
             "roofline": {"kernel": "smooth_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                         "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": smooth_traffic_bytes(n_tracks),
                          "algorithmic_bytes": nbytes}}
 
 
