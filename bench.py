@@ -44,18 +44,18 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of one fit_kernel launch on the 1e6-track workload, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean of 5 launches), each scaled by
+# runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean of 9 launches), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "99ddcc3026af2f69", "tracks": 1_000_000,
-               "fetch_kib": 102027.2, "write_kib": 117187.5,
+FIT_TRAFFIC = {"sources": "7c6bc0d41e5cc0ba", "tracks": 1_000_000,
+               "fetch_kib": 102031.6, "write_kib": 117187.5,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
 
-# The same for one smooth_kernel launch on that workload (mean of 4 launches).
-SMOOTH_TRAFFIC = {"sources": "da16f4fd62d16e50", "tracks": 1_000_000,
-                  "fetch_kib": 906681.7, "write_kib": 1800781.2,
+# The same for one smooth_kernel launch on that workload (mean of 7 launches).
+SMOOTH_TRAFFIC = {"sources": "c0f00b368f3292a3", "tracks": 1_000_000,
+                  "fetch_kib": 906638.5, "write_kib": 1800781.2,
                   "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 SMOOTH_SOURCES = ("paper_1906_11744_amd/csrc/kf_smooth.hip", "paper_1906_11744_amd/csrc/kf_smooth.h",
                   "paper_1906_11744_amd/csrc/kf_adjoint.h")
@@ -97,24 +97,79 @@ def algorithmic_bytes(n_tracks, n_layers, n_steps):
 
 
 def _time_launches(fn, steps, warmup):
-    """Mean device time (s) per call of fn() over `steps` back-to-back calls after
-    `warmup`, from one pair of HIP events on the current stream around the timed
-    region (the library launches on that stream), and the wall-clock seconds of the
-    same region."""
+    """Device time per call of fn() over `steps` back-to-back calls after `warmup`, on
+    the current stream (the library launches on it): the mean over calls of a HIP event
+    pair recorded around each call (the launch's own duration), the mean per call of one
+    event pair around the whole region (which adds the GPU's gap between consecutive
+    kernels), and the wall-clock seconds of the region."""
     import torch
     for _ in range(max(1, warmup)):
         fn()
     stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
+    for a, b in ev:
+        a.record(stream)
         fn()
+        b.record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) * 1e-3 / steps, wall
+    per_launch = sum(a.elapsed_time(b) for a, b in ev) * 1e-3 / steps
+    return per_launch, e0.elapsed_time(e1) * 1e-3 / steps, wall
+
+
+class _HipEvents:
+    """Raw hipEvent_t handles from the HIP runtime torch has loaded (one runtime per
+    process: both name the same soname), for kf_ctx_set_launch_events."""
+
+    def __init__(self, count):
+        import ctypes as C
+        self._C = C
+        self.hip = C.CDLL("libamdhip64.so.7")
+        self.ev = []
+        for _ in range(count):
+            e = C.c_void_p()
+            if self.hip.hipEventCreate(C.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev.append(e)
+
+    def elapsed_ms(self, a, b):
+        ms = self._C.c_float()
+        if self.hip.hipEventElapsedTime(self._C.byref(ms), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def close(self):
+        for e in self.ev:
+            self.hip.hipEventDestroy(e)
+        self.ev = []
+
+
+def _time_kernel(ctx, fn, steps, warmup):
+    """Mean duration (s) of the library kernel launched by each of `steps` back-to-back
+    calls of fn() (after `warmup`): the events of kf_ctx_set_launch_events, one pair per
+    call, bracket that kernel's own execution on the stream."""
+    import torch
+    for _ in range(max(1, warmup)):
+        fn()
+    he = _HipEvents(2 * steps)
+    torch.cuda.synchronize()
+    try:
+        for k in range(steps):
+            ctx.set_launch_events(he.ev[2 * k], he.ev[2 * k + 1])
+            fn()
+        ctx.set_launch_events(None, None)
+        torch.cuda.synchronize()
+        total = sum(he.elapsed_ms(he.ev[2 * k], he.ev[2 * k + 1]) for k in range(steps))
+    finally:
+        ctx.set_launch_events(None, None)
+        torch.cuda.synchronize()
+        he.close()
+    return total * 1e-3 / steps
 
 
 def bench_find(steps, warmup):
@@ -132,9 +187,9 @@ def bench_find(steps, warmup):
     xX0 = t(geom.xX0.astype(np.float32))
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
     out = kf.find(*args, xX0=xX0, autotune=True)
-    avg, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
+    avg, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
     kf.set_find_config(use_graph=1)
-    avg_g, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
+    avg_g, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
     res["single_event_5000_tracks"] = {"events_per_s": 1.0 / avg_g, "ms_per_event": avg_g * 1e3,
                                        "ms_per_event_without_graph": avg * 1e3,
                                        "seeds": int(ev.seed_hits.shape[1]), "config": kf.find_config()}
@@ -147,7 +202,7 @@ def bench_find(steps, warmup):
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
     out = kf.find(*args, xX0=xX0, refit=True, autotune=True)
     kf.set_find_config(use_graph=1)
-    avg_b, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
+    avg_b, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
     # per-event calls on the same data
     E = ev.hit_off.shape[0]
     per_event = []
@@ -164,7 +219,7 @@ def bench_find(steps, warmup):
     def loop():
         for a, o in zip(per_event, outs):
             kf.find(*a, xX0=xX0, refit=True, out=o)
-    avg_l, _ = _time_launches(loop, max(3, steps // 4), warmup)
+    avg_l, _, _ = _time_launches(loop, max(3, steps // 4), warmup)
     res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3, "config": cfg_batched,
                                 "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1])}
     res["per_event_loop_64_events"] = {"events_per_s": E / avg_l, "ms_total": avg_l * 1e3}
@@ -189,8 +244,8 @@ def bench_grad(steps, warmup):
     al, xX0 = t(np.zeros((geom.n_layers, 4), np.float32)), t(geom.xX0.astype(np.float32))
     fwd = kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True)
     w = torch.ones(ts.hits.shape[2], dtype=torch.float32, device=dev)
-    t_f, _ = _time_launches(lambda: kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
-    t_b, _ = _time_launches(lambda: kf.fit_backward(hits, mask, fwd, w, align=al, xX0=xX0), steps, warmup)
+    t_f, _, _ = _time_launches(lambda: kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
+    t_b, _, _ = _time_launches(lambda: kf.fit_backward(hits, mask, fwd, w, align=al, xX0=xX0), steps, warmup)
     return {"tracks": int(ts.hits.shape[2]), "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
             "backward_over_forward": t_b / t_f}
 
@@ -212,16 +267,18 @@ def bench_smooth(steps, warmup, n_tracks):
     out = ctx.smooth(hits, mask, fwd, xX0=xX0)
     torch.cuda.synchronize()
     layers = int((out["last"] - out["first"] + 1).clamp(min=0).sum().item())
-    t_f, _ = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
-    t_s, _ = _time_launches(lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=out), steps, warmup)
+    t_f, _, _ = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
+    t_s, _, _ = _time_launches(lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=out), steps, warmup)
+    t_k = _time_kernel(ctx, lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=out), steps, warmup)
     # HBM bytes the smoother must move: the checkpoint (27 floats) of every smoothed
     # layer read, the whole output (27 floats on every layer, zeros included) written,
     # mask/ndf/status read and first/last written
     nbytes = layers * 27 * 4 + geom.n_layers * n_tracks * 27 * 4 + n_tracks * 5 * 4
-    gbs = nbytes / t_s / 1e9
+    gbs = nbytes / t_k / 1e9
     return {"tracks": n_tracks, "smoothed_layers": layers, "forward_with_checkpoints_ms": t_f * 1e3,
             "smooth_ms": t_s * 1e3, "smoothed_layers_per_s": layers / t_s,
             "roofline": {"kernel": "smooth_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                         "avg_launch_ms": t_k * 1e3,
                          "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": smooth_traffic_bytes(n_tracks),
                          "algorithmic_bytes": nbytes}}
 
@@ -233,7 +290,7 @@ def copy_calibration(steps):
     n = 1 << 28
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
-    avg, _ = _time_launches(lambda: b.copy_(a), steps, 1)
+    avg, _, _ = _time_launches(lambda: b.copy_(a), steps, 1)
     return {"copy_bytes_each_way": 4 * n, "avg_ms": avg * 1e3, "GB_per_s": 8 * n / avg / 1e9}
 
 
@@ -275,7 +332,8 @@ def main():
         steps_per_launch = int(n_hits.sum())
         flops = algorithmic_flops(n_hits)
         nbytes = algorithmic_bytes(n, geom.n_layers, steps_per_launch)
-        avg, wall = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, out=out), args.steps, args.warmup)
+        _, avg_region, wall = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, out=out), args.steps, args.warmup)
+        avg = _time_kernel(ctx, lambda: ctx.fit(hits, mask, xX0=xX0, out=out), args.steps, args.warmup)
         value = steps_per_launch * args.steps / wall
         achieved_tflops = flops / avg / 1e12
         res = {
@@ -298,6 +356,7 @@ def main():
                          "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": fit_traffic_bytes(n),
                          "traffic_unit": "B per launch",
                          "kernel": "fit_kernel", "avg_launch_ms": avg * 1e3,
+                         "ms_per_call_with_kernel_gaps": avg_region * 1e3,
                          "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
                          "hbm_frac": nbytes / avg / 1e9 / PEAK_HBM_GBS},
         }

@@ -161,6 +161,15 @@ int kf_ctx_destroy(kf_ctx* ctx);
  * A threshold > 1 forces the FP64 path for every update. */
 int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold);
 
+/* Timing hook.  While start and stop (hipEvent_t, created by the caller) are both
+ * non-NULL, the main kernel of every kf_fit and kf_smooth call is launched with
+ * hipExtLaunchKernel so that the two events record the beginning and the end of that
+ * kernel's own execution on the stream (the measure a kernel trace reports, without
+ * the dispatch gaps between consecutive launches); hipEventElapsedTime(start, stop)
+ * then gives the duration of the last such launch.  NULL, NULL (the default) turns it
+ * off.  KF_E_INVALID for a NULL context or exactly one NULL event. */
+int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop);
+
 /* Launch configuration of kf_find, held by the context.  Outputs do not depend on it
  * (same bits for every valid configuration); only the time does.
  *   wide_window_bins: a candidate whose search window overlaps more than this many

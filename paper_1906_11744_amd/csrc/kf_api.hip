@@ -29,6 +29,7 @@ struct kf_ctx {
   int grid_device = -1;   // device the occupancy figures below were taken on
   int grid_cus = 0;       // compute units
   int grid_per_cu = 0;    // find workgroups that fit on one compute unit
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // timing hook (kf_ctx_set_launch_events)
 };
 
 namespace {
@@ -136,6 +137,13 @@ int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold) {
   return KF_OK;
 }
 
+int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop) {
+  if (!ctx || ((start == nullptr) != (stop == nullptr))) return KF_E_INVALID;
+  ctx->ev_start = reinterpret_cast<hipEvent_t>(start);
+  ctx->ev_stop = reinterpret_cast<hipEvent_t>(stop);
+  return KF_OK;
+}
+
 int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg) {
   if (!ctx || !cfg || cfg->wide_window_bins < 0 || cfg->blocks_per_cu < 0 || cfg->use_graph < 0 ||
       cfg->use_graph > 1)
@@ -208,7 +216,7 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   a.ndf = out->ndf;
   a.status = out->status;
   a.ckpt = out->ckpt;
-  return kfi::launch_fit(a, st) == hipSuccess ? KF_OK : KF_E_HIP;
+  return kfi::launch_fit(a, st, ctx->ev_start, ctx->ev_stop) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
 }  // extern "C"
@@ -504,7 +512,7 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
   a.cov = out->cov;
   a.first = out->first;
   a.last = out->last;
-  return kfi::launch_smooth(a, st) == hipSuccess ? KF_OK : KF_E_HIP;
+  return kfi::launch_smooth(a, st, ctx->ev_start, ctx->ev_stop) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
 int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,

@@ -181,13 +181,19 @@ hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const in
   return hipGetLastError();
 }
 
-hipError_t launch_fit(const FitArgs& a, hipStream_t stream) {
+hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int bs = 256;
   const int64_t nb = (a.n + bs - 1) / bs;
-  if (a.ckpt)
+  if (ev_start && ev_stop) {  // timing hook: the events bracket the kernel's own execution
+    if (a.ckpt)
+      hipExtLaunchKernelGGL(fit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
+    else
+      hipExtLaunchKernelGGL(fit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
+  } else if (a.ckpt) {
     hipLaunchKernelGGL(fit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, a);
-  else
+  } else {
     hipLaunchKernelGGL(fit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, a);
+  }
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Internal launch interface between the C ABI (kf_api.hip) and the kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -107,7 +108,8 @@ struct SmoothArgs {
   int32_t* last;   // [n]
 };
 
-hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream);
+hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
+                         hipEvent_t ev_stop = nullptr);
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
 size_t find_lds_bytes(int nl);
 hipError_t find_max_blocks(int nl, int* blocks_per_cu);
@@ -116,7 +118,8 @@ hipError_t launch_find(const FindArgs& a, int grid, hipStream_t stream);
 // Writes the per-layer constants (radius, alignment, its cos/sin, material).
 hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
                              kfd::LayerK* out, hipStream_t stream);
-hipError_t launch_fit(const FitArgs& a, hipStream_t stream);
+hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
+                      hipEvent_t ev_stop = nullptr);
 // Fit of each seed's rank-0 finder candidate: idx0 [L][n] hit indices into hits [3][H].
 hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream);
 

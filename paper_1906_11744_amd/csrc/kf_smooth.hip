@@ -69,9 +69,12 @@ __global__ __launch_bounds__(64) void smooth_kernel(SmoothArgs a) {
   a.last[i] = lend;
 }
 
-hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream) {
+hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int64_t nb = (a.n + 63) / 64;
-  hipLaunchKernelGGL(smooth_kernel, dim3((unsigned)nb), dim3(64), 0, stream, a);
+  if (ev_start && ev_stop)  // timing hook: the events bracket the kernel's own execution
+    hipExtLaunchKernelGGL(smooth_kernel, dim3((unsigned)nb), dim3(64), 0, stream, ev_start, ev_stop, 0, a);
+  else
+    hipLaunchKernelGGL(smooth_kernel, dim3((unsigned)nb), dim3(64), 0, stream, a);
   return hipGetLastError();
 }
 

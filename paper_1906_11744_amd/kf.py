@@ -80,6 +80,7 @@ def _lib():
         lib.kf_ctx_create.argtypes = [C.POINTER(Geometry), C.POINTER(C.c_void_p)]
         lib.kf_ctx_destroy.argtypes = [C.c_void_p]
         lib.kf_ctx_set_fallback_threshold.argtypes = [C.c_void_p, C.c_float]
+        lib.kf_ctx_set_launch_events.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         lib.kf_ctx_set_find_config.argtypes = [C.c_void_p, C.POINTER(FindConfig)]
         lib.kf_ctx_get_find_config.argtypes = [C.c_void_p, C.POINTER(FindConfig)]
         lib.kf_workspace_size.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]
@@ -174,6 +175,12 @@ class Context:
     def set_fallback_threshold(self, det_threshold: float):
         _check(_lib().kf_ctx_set_fallback_threshold(self._h, float(det_threshold)),
                "kf_ctx_set_fallback_threshold")
+
+    def set_launch_events(self, start=None, stop=None):
+        """kf_ctx_set_launch_events: hipEvent_t handles (ints or ctypes pointers) that the
+        main kernel of each kf_fit / kf_smooth call records around its own execution;
+        None, None turns the hook off."""
+        _check(_lib().kf_ctx_set_launch_events(self._h, start, stop), "kf_ctx_set_launch_events")
 
     def set_find_config(self, wide_window_bins=None, blocks_per_cu=None, use_graph=None):
         """kf_ctx_set_find_config; fields left None keep their current value."""
@@ -340,6 +347,7 @@ class Context:
 
 def exported_symbols():
     """Names the header declares (for the load check)."""
-    return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_ctx_set_find_config",
+    return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_ctx_set_launch_events",
+            "kf_ctx_set_find_config",
             "kf_ctx_get_find_config", "kf_workspace_size", "kf_fit", "kf_find", "kf_find_autotune",
             "kf_smooth", "kf_fit_backward", "kf_strerror"]

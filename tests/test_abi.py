@@ -93,3 +93,16 @@ def test_find_config_roundtrip_and_validation():
     with pytest.raises(kf.KfError):
         ctx.set_find_config(use_graph=2)
     assert ctx.find_config() == {"wide_window_bins": 0, "blocks_per_cu": 1, "use_graph": 1}
+
+
+def test_launch_event_hook_validation():
+    """kf_ctx_set_launch_events takes both events or neither (no device work here)."""
+    import ctypes as C
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    assert lib.kf_ctx_set_launch_events(None, None, None) == -1   # KF_E_INVALID
+    fake = C.c_void_p(0x1000)   # never dereferenced: only stored, and cleared again
+    assert lib.kf_ctx_set_launch_events(ctx._h, fake, None) == -1
+    assert lib.kf_ctx_set_launch_events(ctx._h, None, fake) == -1
+    assert lib.kf_ctx_set_launch_events(ctx._h, fake, fake) == 0
+    assert lib.kf_ctx_set_launch_events(ctx._h, None, None) == 0
