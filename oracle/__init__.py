@@ -290,3 +290,54 @@ def unpack_cov(c21):
             out[j, i] = c21[k]
             k += 1
     return out
+
+
+# Duplicate handling (Sec. 4.2).  The cuts are this project's readings (the paper
+# gives none); both the oracle and the library take them as arguments.
+SEED_CUTS = dict(psi_window=0.05, min_shared=2, min_shared_kin=1, kap_rel=0.1, kap_abs=0.15, theta=0.03,
+                 phi=0.02, z=0.5)
+TRACK_CUTS = dict(psi_window=0.05, shared_frac=0.5, kap_rel=0.1, kap_abs=0.01, theta=0.02)
+
+
+def clean_seeds(geom, ev, cuts=None, align=None, xX0=None):
+    """Seed cleaning of a synth.EventBatch's seeds: keep [S] (1 kept, 0 removed as the
+    duplicate of a lower-index seed) and sens [S] (a decision within float rounding of
+    a cut)."""
+    c = dict(SEED_CUTS, **(cuts or {}))
+    S = ev.seed_hits.shape[1]
+    H = ev.hits.shape[1]
+    keep = np.zeros(S, np.int32)
+    sens = np.zeros(S, np.uint8)
+    g = ogeom(geom)
+    xx = geom.xX0 if xX0 is None else xX0
+    off = np.ascontiguousarray(ev.hit_off, np.int64)
+    load().oracle_clean_seeds(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int32(off.shape[0]),
+                              _p(np.ascontiguousarray(ev.hits, np.float32)), C.c_int64(H), _p(off), C.c_int64(S),
+                              _p(np.ascontiguousarray(ev.seed_event, np.int32)),
+                              _p(np.ascontiguousarray(ev.seed_hits, np.int32)), C.c_double(c["psi_window"]),
+                              C.c_int32(c["min_shared"]), C.c_int32(c["min_shared_kin"]),
+                              C.c_double(c["kap_rel"]), C.c_double(c["kap_abs"]),
+                              C.c_double(c["theta"]), C.c_double(c["phi"]), C.c_double(c["z"]), _p(keep), _p(sens))
+    return keep, sens.astype(bool)
+
+
+def remove_duplicates(geom, hits, n_events, event, hit_idx, n_hits, chi2, state, cuts=None, align=None, xX0=None):
+    """Duplicate removal over built tracks: event [n], hit_idx [L][n] global hit indices
+    into hits [3][H] (< 0: none), n_hits [n], chi2 [n], state [6][n] (kappa and theta
+    used).  Priority: more hits, lower chi2, lower index.  Returns keep [n], sens [n]."""
+    c = dict(TRACK_CUTS, **(cuts or {}))
+    n = int(np.asarray(event).shape[0])
+    keep = np.zeros(n, np.int32)
+    sens = np.zeros(n, np.uint8)
+    g = ogeom(geom)
+    xx = geom.xX0 if xX0 is None else xX0
+    h = np.ascontiguousarray(hits, np.float32)
+    load().oracle_remove_duplicates(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int32(int(n_events)), _p(h),
+                                    C.c_int64(h.shape[1]), C.c_int64(n), _p(np.ascontiguousarray(event, np.int32)),
+                                    _p(np.ascontiguousarray(hit_idx, np.int32)),
+                                    _p(np.ascontiguousarray(n_hits, np.int32)),
+                                    _p(np.ascontiguousarray(chi2, np.float32)),
+                                    _p(np.ascontiguousarray(state, np.float32)), C.c_double(c["psi_window"]),
+                                    C.c_double(c["shared_frac"]), C.c_double(c["kap_rel"]), C.c_double(c["kap_abs"]),
+                                    C.c_double(c["theta"]), _p(keep), _p(sens))
+    return keep, sens.astype(bool)

@@ -1409,3 +1409,184 @@ void oracle_smooth_f64(const OGeom* og, const double* align, const double* xX0, 
 }
 
 }  // extern "C"
+
+
+// ==============================================================================
+// Duplicate handling (Sec. 4.2): seed cleaning before building, duplicate removal
+// after it.  The paper names the quantities (pT, eta and phi of the seeds or tracks,
+// and shared hits) but gives no cuts.  Read here as a pairwise duplicate relation
+// between two items of one event plus a priority order: an item is removed when an
+// item of higher priority in its event is its duplicate.  The relation is not made
+// transitive (an item that is itself removed still removes the ones below it), so the
+// result does not depend on the order in which pairs are examined.  Every relation
+// also requires |psi_i - psi_j| <= psi_window, psi the azimuth of the item's first
+// hit, which bounds the search.  Written brute force: every pair of an event.
+//
+// A decision is flagged float-sensitive when one of its comparisons lies within a
+// small margin of its cut and flipping that comparison alone would flip the decision.
+// ==============================================================================
+
+namespace {
+
+struct Cmp {
+  bool ok, near;
+};
+
+Cmp cmp_le(double a, double cut, double margin) { return {a <= cut, std::fabs(a - cut) <= margin}; }
+
+// c[0] && ... && c[n-1], and whether one near comparison could flip it
+Cmp all_of(const Cmp* c, int n) {
+  Cmp r{true, false};
+  int n_fail = 0;
+  for (int k = 0; k < n; ++k) n_fail += !c[k].ok;
+  r.ok = n_fail == 0;
+  for (int k = 0; k < n; ++k)
+    if (c[k].near && (n_fail == 0 || (n_fail == 1 && !c[k].ok))) r.near = true;
+  return r;
+}
+
+struct SeedPar {
+  double psi, z, kap, phi, theta;
+  int32_t h[3];
+  bool valid;
+};
+
+}  // namespace
+
+extern "C" {
+
+// Seed cleaning.  Seeds as for oracle_find (hit triplets on layers 0-2, global indices
+// into hits [3][H]; seed_event [S]).  A seed's kinematics are the three-hit helix at
+// its first hit (the fit's seed, on the placed hits).  Seeds i, j of one event are
+// duplicates when |dpsi| <= psi_window and either they share >= min_shared hits, or
+// they share >= min_shared_kin hits and |dkappa| <= kap_rel max|kappa| + kap_abs,
+// |dtheta|, |dphi| and |dz| (z at the first hit) are within their cuts.  Priority:
+// the lower index.  keep [S] = 1 / 0; sens [S] = 1 where a decision against a
+// higher-priority seed is float-sensitive; invalid seeds (event or hit index out of
+// range) are kept and take no part.
+void oracle_clean_seeds(const OGeom* og, const double* align, const double* xX0, int32_t n_events, const float* hits,
+                        int64_t H, const int64_t* hit_off, int64_t n_seeds, const int32_t* seed_event,
+                        const int32_t* seed_hits, double psi_window, int32_t min_shared, int32_t min_shared_kin,
+                        double kap_rel, double kap_abs, double theta_cut, double phi_cut, double z_cut, int32_t* keep,
+                        uint8_t* sens) {
+  Geo g = make_geo(og);
+  Layer<double> lay[32];
+  make_layers<double>(g, align, xX0, lay);
+  std::vector<SeedPar> P(n_seeds);
+  std::vector<std::vector<int64_t>> by_event(n_events > 0 ? n_events : 0);
+  for (int64_t i = 0; i < n_seeds; ++i) {
+    SeedPar& p = P[i];
+    keep[i] = 1;
+    sens[i] = 0;
+    p.valid = seed_event[i] >= 0 && seed_event[i] < n_events;
+    double m[3][3];
+    for (int l = 0; l < 3 && p.valid; ++l) {
+      const int32_t j = seed_hits[(int64_t)l * n_seeds + i];
+      p.h[l] = j;
+      const int64_t* off = hit_off + (int64_t)seed_event[i] * (g.nl + 1);
+      if (j < 0 || j >= H || j < off[l] || j >= off[l + 1]) {
+        p.valid = false;
+        break;
+      }
+      place_hit(lay[l], (double)hits[j], (double)hits[H + j], (double)hits[2 * H + j], m[l]);
+    }
+    if (!p.valid) continue;
+    Track<double> tk;
+    seed_from_hits(g, m[0], m[1], m[2], tk);
+    p.psi = std::atan2(m[0][1], m[0][0]);
+    p.z = tk.x[2];
+    p.kap = tk.x[3];
+    p.phi = tk.x[4];
+    p.theta = tk.x[5];
+    by_event[seed_event[i]].push_back(i);
+  }
+  for (auto& ev : by_event)
+    for (size_t a = 0; a < ev.size(); ++a) {
+      const int64_t i = ev[a];
+      const SeedPar& pi = P[i];
+      for (size_t b = 0; b < a; ++b) {  // j < i: higher priority
+        const int64_t j = ev[b];
+        const SeedPar& pj = P[j];
+        const Cmp w = cmp_le(std::fabs(wrap_pi(pi.psi - pj.psi)), psi_window, 1e-5);
+        int shared = 0;
+        for (int l = 0; l < 3; ++l) shared += pi.h[l] == pj.h[l];
+        Cmp d{shared >= min_shared, false};
+        if (!d.ok && shared >= min_shared_kin) {
+          const double kcut = kap_rel * std::max(std::fabs(pi.kap), std::fabs(pj.kap)) + kap_abs;
+          const Cmp c[4] = {cmp_le(std::fabs(pi.kap - pj.kap), kcut, 1e-3 * kcut),
+                            cmp_le(std::fabs(pi.theta - pj.theta), theta_cut, 1e-5),
+                            cmp_le(std::fabs(wrap_pi(pi.phi - pj.phi)), phi_cut, 1e-5),
+                            cmp_le(std::fabs(pi.z - pj.z), z_cut, 1e-4)};
+          d = all_of(c, 4);
+        }
+        const Cmp both[2] = {w, d};
+        const Cmp r = all_of(both, 2);
+        if (r.near) sens[i] = 1;
+        if (r.ok) keep[i] = 0;
+      }
+    }
+}
+
+// Duplicate removal over built tracks (for instance each seed's best finder candidate).
+// Item i: event [i], hits hit_idx [L][n] (global index, < 0 none), n_hits [i], chi2 [i],
+// kappa = state[3][i], theta = state[5][i] (state [6][n]).  psi: azimuth of the placed
+// hit on the item's lowest layer with a hit.  i, j are duplicates when |dpsi| <=
+// psi_window, they share at least shared_frac * min(n_hits) hits (the same hit on the
+// same layer) and |dkappa| <= kap_rel max|kappa| + kap_abs and |dtheta| <= theta_cut.
+// Priority: more hits, then lower chi2, then the lower index.  Items without hits are
+// kept and remove nothing.
+void oracle_remove_duplicates(const OGeom* og, const double* align, const double* xX0, int32_t n_events,
+                              const float* hits, int64_t H, int64_t n, const int32_t* event, const int32_t* hit_idx,
+                              const int32_t* n_hits, const float* chi2, const float* state, double psi_window,
+                              double shared_frac, double kap_rel, double kap_abs, double theta_cut, int32_t* keep,
+                              uint8_t* sens) {
+  Geo g = make_geo(og);
+  Layer<double> lay[32];
+  make_layers<double>(g, align, xX0, lay);
+  const int L = g.nl;
+  std::vector<double> psi(n, 0.0);
+  std::vector<std::vector<int64_t>> by_event(n_events > 0 ? n_events : 0);
+  for (int64_t i = 0; i < n; ++i) {
+    keep[i] = 1;
+    sens[i] = 0;
+    if (event[i] < 0 || event[i] >= n_events || n_hits[i] <= 0) continue;
+    int first = -1;
+    for (int l = 0; l < L && first < 0; ++l) {
+      const int32_t j = hit_idx[(int64_t)l * n + i];
+      if (j >= 0 && j < H) first = l;
+    }
+    if (first < 0) continue;
+    const int32_t j = hit_idx[(int64_t)first * n + i];
+    double m[3];
+    place_hit(lay[first], (double)hits[j], (double)hits[H + j], (double)hits[2 * H + j], m);
+    psi[i] = std::atan2(m[1], m[0]);
+    by_event[event[i]].push_back(i);
+  }
+  auto higher = [&](int64_t j, int64_t i) {  // priority of j above i
+    if (n_hits[j] != n_hits[i]) return n_hits[j] > n_hits[i];
+    if (chi2[j] != chi2[i]) return chi2[j] < chi2[i];
+    return j < i;
+  };
+  for (auto& ev : by_event)
+    for (int64_t i : ev)
+      for (int64_t j : ev) {
+        if (j == i || !higher(j, i)) continue;
+        int shared = 0;
+        for (int l = 0; l < L; ++l) {
+          const int32_t a = hit_idx[(int64_t)l * n + i];
+          shared += a >= 0 && a == hit_idx[(int64_t)l * n + j];
+        }
+        const double need = shared_frac * std::min(n_hits[i], n_hits[j]);
+        const double ki = state[3 * n + i], kj = state[3 * n + j];
+        const double kcut = kap_rel * std::max(std::fabs(ki), std::fabs(kj)) + kap_abs;
+        const Cmp c[4] = {cmp_le(std::fabs(wrap_pi(psi[i] - psi[j])), psi_window, 1e-5),
+                          {shared >= need, std::fabs(shared - need) < 1e-5},
+                          cmp_le(std::fabs(ki - kj), kcut, 1e-5 * kcut),
+                          cmp_le(std::fabs((double)state[5 * n + i] - (double)state[5 * n + j]), theta_cut, 1e-6)};
+        const Cmp r = all_of(c, 4);
+        if (r.near) sens[i] = 1;
+        if (r.ok) keep[i] = 0;
+      }
+}
+
+}  // extern "C"

@@ -414,3 +414,82 @@ def find_workload(k: int = 3, n_tracks: int | None = None, n_events: int | None 
         if n_tracks is not None:   # scaled-down copy of the same pileup mix
             nt = np.maximum(1, np.round(nt * (n_tracks / 12500.0))).astype(np.int64)
     return geom, make_events(geom, nt, workload=k)
+
+
+# --------------------------------------------------------------------------------------
+# injected duplicate seeds (tests of duplicate handling)
+# --------------------------------------------------------------------------------------
+
+def inject_duplicate_seeds(geom: Geometry, ev: EventBatch, frac: float = 0.1, workload: int = 6):
+    """A copy of `ev` with duplicates of a fraction `frac` of its seeds appended after
+    all the original seeds, as a detector with overlapping modules makes them: the same
+    track measured twice on a layer.  A duplicate replaces, in turn, hit 0, hit 1, hit 2,
+    hits 1 and 2, or all three hits of its original by a second measurement of the
+    same crossing (the
+    original hit moved along the cylinder by N(0, 2 sigma_rphi^2) in r*phi and
+    N(0, 2 sigma_z^2) in z, so that the pair differs as two independent measurements
+    do).  The new hits join their event's layer slices (after the existing hits there).
+
+    Returns (batch, dup_of): dup_of [S'] is the original seed of each injected seed and
+    -1 for the original seeds; seed_track of a duplicate is its original's track."""
+    rng = rng_for(workload)
+    S = ev.seed_hits.shape[1]
+    L = geom.n_layers
+    E = ev.hit_off.shape[0]
+    pick = np.nonzero(rng.random(S) < frac)[0]
+    variants = np.arange(pick.shape[0]) % 5          # 0, 1, 2: that hit; 3: hits 1, 2; 4: all
+    new = {}                                          # (event, layer) -> list of (x, y, z, track)
+    dup_hits = np.array(ev.seed_hits[:, pick], np.int64)
+    new_ref = []                                      # (k, l, event, position in new list)
+    for k, s in enumerate(pick):
+        e = int(ev.seed_event[s])
+        layers = [variants[k]] if variants[k] < 3 else ([1, 2] if variants[k] == 3 else [0, 1, 2])
+        for l in layers:
+            j = int(ev.seed_hits[l, s])
+            x, y, z = (float(ev.hits[q, j]) for q in range(3))
+            r = geom.radius[l]
+            ang = math.atan2(y, x) + rng.normal() * math.sqrt(2.0) * geom.sigma_rphi / r
+            zz = z + rng.normal() * math.sqrt(2.0) * geom.sigma_z
+            lst = new.setdefault((e, l), [])
+            new_ref.append((k, l, e, len(lst)))
+            lst.append((r * math.cos(ang), r * math.sin(ang), zz, int(ev.hit_track[j])))
+    # rebuild the hit arrays event by event, layer by layer, with the new hits at the
+    # end of each slice
+    old_to_new = np.empty(ev.hits.shape[1], np.int64)
+    hits, tracks, offs = [], [], np.zeros_like(ev.hit_off)
+    start_of_new = {}
+    pos = 0
+    for e in range(E):
+        for l in range(L):
+            a, b = int(ev.hit_off[e, l]), int(ev.hit_off[e, l + 1])
+            offs[e, l] = pos
+            old_to_new[a:b] = pos + np.arange(b - a)
+            hits.append(ev.hits[:, a:b])
+            tracks.append(ev.hit_track[a:b])
+            pos += b - a
+            extra = new.get((e, l), [])
+            start_of_new[(e, l)] = pos
+            if extra:
+                arr = np.array(extra, np.float64)
+                hits.append(arr[:, :3].T.astype(np.float32))
+                tracks.append(arr[:, 3].astype(np.int64))
+                pos += len(extra)
+        offs[e, L] = pos
+    seed_hits = old_to_new[ev.seed_hits].astype(np.int64)
+    dup = old_to_new[dup_hits]
+    for k, l, e, q in new_ref:
+        dup[l, k] = start_of_new[(e, l)] + q
+    track_hits = np.where(ev.track_hits >= 0, old_to_new[np.maximum(ev.track_hits, 0)], -1)
+    out = EventBatch(
+        hits=np.ascontiguousarray(np.concatenate(hits, axis=1)),
+        hit_off=offs,
+        hit_track=np.concatenate(tracks),
+        seed_hits=np.ascontiguousarray(np.concatenate([seed_hits, dup], axis=1).astype(np.int32)),
+        seed_event=np.concatenate([ev.seed_event, ev.seed_event[pick]]),
+        seed_track=np.concatenate([ev.seed_track, ev.seed_track[pick]]),
+        track_event=ev.track_event,
+        track_hits=track_hits,
+        n_tracks=ev.n_tracks,
+    )
+    dup_of = np.concatenate([np.full(S, -1, np.int64), pick.astype(np.int64)])
+    return out, dup_of
