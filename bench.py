@@ -283,6 +283,39 @@ def bench_smooth(steps, warmup, n_tracks):
                          "algorithmic_bytes": nbytes}}
 
 
+def bench_dedup(steps, warmup):
+    """Duplicate handling on the 64-event workload with 5% of its seeds duplicated
+    (second measurements of seed hits): seed cleaning over all seeds, then the finder
+    (with refit) over the kept seeds and duplicate removal over their rank-0 candidates."""
+    import torch
+
+    import synth
+    from paper_1906_11744_amd import Context
+    dev = torch.device("cuda:0")
+    geom, ev = synth.find_workload(5)
+    ev, _ = synth.inject_duplicate_seeds(geom, ev, 0.05)
+    ctx = Context(geom)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    hits, off, sh, se = t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event)
+    xX0 = t(geom.xX0.astype(np.float32))
+    keep = ctx.clean_seeds(hits, off, sh, se, xX0=xX0)
+    t_clean, _, _ = _time_launches(lambda: ctx.clean_seeds(hits, off, sh, se, xX0=xX0, out=keep), steps, warmup)
+    sel = torch.nonzero(keep == 1).flatten()
+    sh2, se2 = sh[:, sel].contiguous(), se[sel].contiguous()
+    out = ctx.find(hits, off, sh2, se2, xX0=xX0, refit=True)
+    hi, nh, c2 = out["hit_idx"][0].contiguous(), out["n_hits"][0].contiguous(), out["chi2"][0].contiguous()
+    E = int(off.shape[0])
+    kt = ctx.remove_duplicates(hits, E, se2, hi, nh, c2, out["rf_state"], xX0=xX0)
+    t_rm, _, _ = _time_launches(lambda: ctx.remove_duplicates(hits, E, se2, hi, nh, c2, out["rf_state"], xX0=xX0,
+                                                              out=kt), steps, warmup)
+    torch.cuda.synchronize()
+    S, S2 = int(sh.shape[1]), int(sh2.shape[1])
+    return {"events": E, "seeds": S, "seeds_removed_by_cleaning": S - S2,
+            "tracks_removed_after_building": int((kt == 0).sum().item()),
+            "clean_ms": t_clean * 1e3, "clean_seeds_per_s": S / t_clean,
+            "remove_ms": t_rm * 1e3, "remove_tracks_per_s": S2 / t_rm}
+
+
 def copy_calibration(steps):
     """A plain device copy of 1 GiB, `steps` times: the reference kernel whose HBM
     counters (FETCH_SIZE, WRITE_SIZE) calibrate those of the fit kernel."""
@@ -301,7 +334,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "copy"], default="all")
+    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "copy"], default="all")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the fit shards tracks across GPUs with no exchange, "
@@ -389,6 +422,8 @@ def main():
         res["adjoint"] = bench_grad(args.steps, args.warmup)
     if args.only in ("all", "smooth"):
         res["smooth"] = bench_smooth(args.steps, args.warmup, args.tracks)
+    if args.only in ("all", "dedup"):
+        res["dedup"] = bench_dedup(args.steps, args.warmup)
     print(json.dumps(res), flush=True)
 
 

@@ -58,6 +58,8 @@ extern "C" {
 #define KF_OP_FIND 2
 #define KF_OP_FIT_BACKWARD 3
 #define KF_OP_SMOOTH 4
+#define KF_OP_CLEAN_SEEDS 5
+#define KF_OP_REMOVE_DUPLICATES 6
 
 /* Detector and hit model, copied into the context at creation (host struct). */
 typedef struct kf_geometry {
@@ -198,7 +200,9 @@ int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg);
 
 /* Workspace bytes needed by op (KF_OP_*) for the input `in` (a kf_fit_in or
  * kf_find_in; for KF_OP_FIT_BACKWARD and KF_OP_SMOOTH the kf_fit_in of the forward
- * call).  0 for KF_OP_FIT (ws may then be NULL). */
+ * call; for KF_OP_CLEAN_SEEDS a kf_find_in; for KF_OP_REMOVE_DUPLICATES a
+ * kf_tracks_in; the last two also depend on the context's psi_window).  0 for
+ * KF_OP_FIT (ws may then be NULL). */
 int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes);
 
 /* Batched Kalman fit, one track per GPU lane.  For every track: seed at layer 0,
@@ -271,6 +275,74 @@ typedef struct kf_smooth_out {
  * workspace.  Workspace: kf_workspace_size(KF_OP_SMOOTH, in). */
 int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
               const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Duplicate handling (Sec. 4.2): seed cleaning before building and duplicate removal
+ * after it.  The paper names the quantities compared (pT, eta and phi of seeds or
+ * tracks, and shared hits) but no cuts; these are the context's (defaults below, set
+ * with kf_ctx_set_dedup_cuts).  Both calls read the relation as pairwise within an
+ * event with a priority order: an item is removed when an item of higher priority in
+ * its event is its duplicate.  It is not made transitive (a removed item still removes
+ * the items below it), so the result does not depend on evaluation order and is
+ * bit-deterministic.  Every duplicate pair lies within psi_window in psi, the azimuth
+ * of the item's first (placed) hit; the library bins each event's items in psi to
+ * bound the search.  Differences use the azimuth wrapped to (-pi, pi]. */
+typedef struct kf_dedup_cuts {
+  float psi_window;     /* rad; default 0.05 */
+  int32_t min_shared;   /* seeds: shared hits that alone make a duplicate; default 2 */
+  int32_t min_shared_kin; /* seeds: shared hits needed for the kinematic test; default 1 */
+  float seed_kap_rel, seed_kap_abs; /* |dkappa| <= rel * max|kappa| + abs; 0.1, 0.15 1/GeV */
+  float seed_theta, seed_phi, seed_z; /* |dtheta|, |dphi| (rad), |dz| (cm); 0.03, 0.02, 0.5 */
+  float trk_shared_frac; /* tracks: shared >= frac * min(n_hits); 0.5 */
+  float trk_kap_rel, trk_kap_abs; /* tracks: |dkappa| cut as for seeds; 0.1, 0.01 1/GeV */
+  float trk_theta;      /* tracks: |dtheta| (rad); 0.02 */
+} kf_dedup_cuts;
+
+/* Set / read the context's duplicate cuts.  KF_E_INVALID for a NULL argument, a
+ * non-positive psi_window, negative cuts or min_shared_kin > min_shared. */
+int kf_ctx_set_dedup_cuts(kf_ctx* ctx, const kf_dedup_cuts* cuts);
+int kf_ctx_get_dedup_cuts(const kf_ctx* ctx, kf_dedup_cuts* cuts);
+
+/* Seed cleaning.  Input: the events' hits and seeds of a kf_find_in (n_events,
+ * hit_off, n_hits, hits, n_seeds, seed_event, seed_hits; the other fields unused).  A
+ * seed takes part if its event is in range and each hit q lies in its event's slice of
+ * layer q; others are kept.  A seed's kinematics are the three-hit helix at its first
+ * placed hit (as kf_fit's seed): kappa, theta, phi, z.  Seeds i, j of one event are
+ * duplicates when |dpsi| <= psi_window and either they share >= min_shared hits (the
+ * same global index on the same layer), or they share >= min_shared_kin hits and
+ * |dkappa| <= seed_kap_rel * max(|kappa_i|, |kappa_j|) + seed_kap_abs, |dtheta| <=
+ * seed_theta, |dphi| <= seed_phi, |dz| <= seed_z.  Priority: the lower seed index.
+ * Output keep [n_seeds] int32: 1 kept, 0 removed.  KF_E_INVALID for a NULL context,
+ * input or array, negative counts; KF_E_WORKSPACE for a short workspace
+ * (kf_workspace_size(KF_OP_CLEAN_SEEDS, in)). */
+int kf_clean_seeds(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, int32_t* keep, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Built tracks for kf_remove_duplicates, e.g. each seed's rank-0 finder candidate:
+ * event [n]; hit_idx [L][n] global hit indices into hits [3][n_hits] (< 0: none);
+ * n_hits_trk [n]; chi2 [n]; state [6][n] (kappa and theta are compared; e.g. the
+ * refit's rf_state). */
+typedef struct kf_tracks_in {
+  int32_t n_events;
+  int64_t n_hits;
+  const float* hits;
+  int64_t n;
+  const int32_t* event;
+  const int32_t* hit_idx;
+  const int32_t* n_hits_trk;
+  const float* chi2;
+  const float* state;
+} kf_tracks_in;
+
+/* Duplicate removal over built tracks.  A track takes part if its event is in range,
+ * n_hits_trk > 0 and it has a hit index in [0, n_hits); psi is the azimuth of the placed
+ * hit on its lowest such layer.  Tracks i, j of one event are duplicates when |dpsi| <=
+ * psi_window, they share at least trk_shared_frac * min(n_hits_trk) hits (the same hit
+ * on the same layer), |dkappa| <= trk_kap_rel * max|kappa| + trk_kap_abs and |dtheta|
+ * <= trk_theta.  Priority: more hits, then lower chi2, then the lower index.  Output
+ * keep [n] int32.  Errors as kf_clean_seeds; workspace
+ * kf_workspace_size(KF_OP_REMOVE_DUPLICATES, in). */
+int kf_remove_duplicates(kf_ctx* ctx, const kf_layer_params* params, const kf_tracks_in* in, int32_t* keep,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /* Static description of a return code. */
 const char* kf_strerror(int code);

@@ -1500,7 +1500,9 @@ void oracle_clean_seeds(const OGeom* og, const double* align, const double* xX0,
     p.theta = tk.x[5];
     by_event[seed_event[i]].push_back(i);
   }
-  for (auto& ev : by_event)
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t e = 0; e < (int64_t)by_event.size(); ++e) {
+    const std::vector<int64_t>& ev = by_event[e];
     for (size_t a = 0; a < ev.size(); ++a) {
       const int64_t i = ev[a];
       const SeedPar& pi = P[i];
@@ -1525,6 +1527,7 @@ void oracle_clean_seeds(const OGeom* og, const double* align, const double* xX0,
         if (r.ok) keep[i] = 0;
       }
     }
+  }
 }
 
 // Duplicate removal over built tracks (for instance each seed's best finder candidate).
@@ -1567,9 +1570,10 @@ void oracle_remove_duplicates(const OGeom* og, const double* align, const double
     if (chi2[j] != chi2[i]) return chi2[j] < chi2[i];
     return j < i;
   };
-  for (auto& ev : by_event)
-    for (int64_t i : ev)
-      for (int64_t j : ev) {
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t e = 0; e < (int64_t)by_event.size(); ++e)
+    for (int64_t i : by_event[e])
+      for (int64_t j : by_event[e]) {
         if (j == i || !higher(j, i)) continue;
         int shared = 0;
         for (int l = 0; l < L; ++l) {

@@ -30,6 +30,7 @@ struct kf_ctx {
   int grid_cus = 0;       // compute units
   int grid_per_cu = 0;    // find workgroups that fit on one compute unit
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // timing hook (kf_ctx_set_launch_events)
+  kf_dedup_cuts dcuts{0.05f, 2, 1, 0.1f, 0.15f, 0.03f, 0.02f, 0.5f, 0.5f, 0.1f, 0.01f, 0.02f};
 };
 
 namespace {
@@ -88,6 +89,32 @@ FindWs find_ws(const kf_ctx* c, const kf_find_in* in) {
 
 // Persistent find grid: blocks_per_cu workgroups per compute unit, at most as many as
 // fit at once.
+// Workspace of duplicate handling: layer constants | par, spar [5][n] | sint [3][n] |
+// skey, bin [n] | cnt, cur [E * nb] | off [E * nb + 1] | order [n].
+struct DedupWs {
+  size_t layers, par, spar, sint, skey, bin, cnt, cur, off, order, total;
+  int64_t m;  // E * nb
+};
+
+DedupWs dedup_ws(const kf_ctx* c, int64_t n_items, int32_t n_events) {
+  DedupWs w;
+  const size_t n = (size_t)(n_items > 0 ? n_items : 0);
+  const int64_t E = n_events > 0 ? n_events : 0;
+  w.m = E * kfi::dedup_bins(c->dcuts.psi_window);
+  w.layers = 0;
+  w.par = w.layers + fit_ws_bytes();
+  w.spar = w.par + round_up(5 * n * sizeof(float));
+  w.sint = w.spar + round_up(5 * n * sizeof(float));
+  w.skey = w.sint + round_up(3 * n * 4);
+  w.bin = w.skey + round_up(n * 4);
+  w.cnt = w.bin + round_up(n * 4);
+  w.cur = w.cnt + round_up((size_t)w.m * 4);
+  w.off = w.cur + round_up((size_t)w.m * 4);
+  w.order = w.off + round_up(((size_t)w.m + 1) * 4);
+  w.total = w.order + round_up(n * 4);
+  return w;
+}
+
 int persistent_grid(kf_ctx* c, int nl, int* grid) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return KF_E_HIP;
@@ -158,6 +185,25 @@ int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg) {
   return KF_OK;
 }
 
+int kf_ctx_set_dedup_cuts(kf_ctx* ctx, const kf_dedup_cuts* c) {
+  if (!ctx || !c) return KF_E_INVALID;
+  const float f[] = {c->seed_kap_rel, c->seed_kap_abs, c->seed_theta, c->seed_phi, c->seed_z,
+                     c->trk_shared_frac, c->trk_kap_rel, c->trk_kap_abs, c->trk_theta};
+  for (float v : f)
+    if (!(v >= 0.f) || !isfinite(v)) return KF_E_INVALID;
+  if (!(c->psi_window > 0.f) || !isfinite(c->psi_window) || c->min_shared < 0 || c->min_shared_kin < 0 ||
+      c->min_shared_kin > c->min_shared)
+    return KF_E_INVALID;
+  ctx->dcuts = *c;
+  return KF_OK;
+}
+
+int kf_ctx_get_dedup_cuts(const kf_ctx* ctx, kf_dedup_cuts* c) {
+  if (!ctx || !c) return KF_E_INVALID;
+  *c = ctx->dcuts;
+  return KF_OK;
+}
+
 int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) {
   if (!ctx || !in || !bytes) return KF_E_INVALID;
   switch (op) {
@@ -175,6 +221,16 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
       const size_t n = (size_t)(f->n > 0 ? f->n : 0);
       *bytes = fit_ws_bytes() + round_up((size_t)ctx->g.n_layers * 5 * (size_t)kfi::adjoint_blocks((int64_t)n) *
                                          sizeof(double));
+      return KF_OK;
+    }
+    case KF_OP_CLEAN_SEEDS: {
+      const kf_find_in* f = static_cast<const kf_find_in*>(in);
+      *bytes = dedup_ws(ctx, f->n_seeds, f->n_events).total;
+      return KF_OK;
+    }
+    case KF_OP_REMOVE_DUPLICATES: {
+      const kf_tracks_in* t = static_cast<const kf_tracks_in*>(in);
+      *bytes = dedup_ws(ctx, t->n, t->n_events).total;
       return KF_OK;
     }
     default:
@@ -513,6 +569,91 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
   a.first = out->first;
   a.last = out->last;
   return kfi::launch_smooth(a, st, ctx->ev_start, ctx->ev_stop) == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+}  // extern "C"
+
+namespace {
+
+int run_dedup(kf_ctx* ctx, const kf_layer_params* params, kfi::DedupArgs& a, bool seeds, void* ws, size_t ws_bytes,
+              void* stream) {
+  const DedupWs w = dedup_ws(ctx, a.n, a.n_events);
+  if (w.m >= (int64_t)INT32_MAX) return KF_E_INVALID;
+  const int rc = check_ws(ws, ws_bytes, w.total);
+  if (rc != KF_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base + w.layers);
+  const float* align = params ? params->align : nullptr;
+  const float* xX0 = params ? params->xX0 : nullptr;
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+    return KF_E_HIP;
+  const kf_dedup_cuts& c = ctx->dcuts;
+  a.c = kfi::DedupCuts{c.psi_window, c.min_shared, c.min_shared_kin, c.seed_kap_rel, c.seed_kap_abs,
+                       c.seed_theta, c.seed_phi, c.seed_z, c.trk_shared_frac, c.trk_kap_rel, c.trk_kap_abs,
+                       c.trk_theta};
+  a.nl = ctx->g.n_layers;
+  a.nb = kfi::dedup_bins(c.psi_window);
+  a.md = model_of(ctx);
+  a.layers = layers;
+  a.par = reinterpret_cast<float*>(base + w.par);
+  a.spar = reinterpret_cast<float*>(base + w.spar);
+  a.sint = reinterpret_cast<int32_t*>(base + w.sint);
+  a.skey = reinterpret_cast<int32_t*>(base + w.skey);
+  a.bin = reinterpret_cast<int32_t*>(base + w.bin);
+  a.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
+  a.cur = reinterpret_cast<int32_t*>(base + w.cur);
+  a.off = reinterpret_cast<int32_t*>(base + w.off);
+  a.order = reinterpret_cast<int32_t*>(base + w.order);
+  return kfi::launch_dedup(a, seeds, st) == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_clean_seeds(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, int32_t* keep, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!ctx || !in) return KF_E_INVALID;
+  if (in->n_seeds < 0 || in->n_events < 0 || in->n_hits < 0) return KF_E_INVALID;
+  if (in->n_seeds == 0) return KF_OK;
+  if (!keep) return KF_E_INVALID;
+  if (in->n_seeds > (int64_t)INT32_MAX - 1) return KF_E_INVALID;
+  if (!in->seed_event || !in->seed_hits || (in->n_events > 0 && !in->hit_off) || (in->n_hits > 0 && !in->hits))
+    return KF_E_INVALID;
+  kfi::DedupArgs a{};
+  a.n = in->n_seeds;
+  a.n_events = in->n_events;
+  a.hits = in->hits;
+  a.H = in->n_hits;
+  a.hit_off = in->hit_off;
+  a.seed_event = in->seed_event;
+  a.seed_hits = in->seed_hits;
+  a.keep = keep;
+  return run_dedup(ctx, params, a, true, ws, ws_bytes, stream);
+}
+
+int kf_remove_duplicates(kf_ctx* ctx, const kf_layer_params* params, const kf_tracks_in* in, int32_t* keep,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !in) return KF_E_INVALID;
+  if (in->n < 0 || in->n_events < 0 || in->n_hits < 0) return KF_E_INVALID;
+  if (in->n == 0) return KF_OK;
+  if (!keep) return KF_E_INVALID;
+  if (in->n > (int64_t)INT32_MAX - 1) return KF_E_INVALID;
+  if (!in->event || !in->hit_idx || !in->n_hits_trk || !in->chi2 || !in->state || (in->n_hits > 0 && !in->hits))
+    return KF_E_INVALID;
+  kfi::DedupArgs a{};
+  a.n = in->n;
+  a.n_events = in->n_events;
+  a.hits = in->hits;
+  a.H = in->n_hits;
+  a.event = in->event;
+  a.hit_idx = in->hit_idx;
+  a.n_hits = in->n_hits_trk;
+  a.chi2 = in->chi2;
+  a.state = in->state;
+  a.keep = keep;
+  return run_dedup(ctx, params, a, false, ws, ws_bytes, stream);
 }
 
 int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,

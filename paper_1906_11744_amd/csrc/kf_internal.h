@@ -108,6 +108,48 @@ struct SmoothArgs {
   int32_t* last;   // [n]
 };
 
+// Cuts of the duplicate relations (kf_dedup_cuts of kf.h, copied).
+struct DedupCuts {
+  float psi_window;
+  int32_t min_shared, min_shared_kin;
+  float seed_kap_rel, seed_kap_abs, seed_theta, seed_phi, seed_z;
+  float trk_shared_frac, trk_kap_rel, trk_kap_abs, trk_theta;
+};
+
+struct DedupArgs {
+  int64_t n;        // items (seeds or tracks)
+  int32_t nl, n_events, nb;
+  DedupCuts c;
+  kfd::Model md;
+  const kfd::LayerK* layers;
+  const float* hits;  // [3][H]
+  int64_t H;
+  // seeds
+  const int64_t* hit_off;
+  const int32_t* seed_event;
+  const int32_t* seed_hits;  // [3][n]
+  // tracks
+  const int32_t* event;
+  const int32_t* hit_idx;  // [L][n]
+  const int32_t* n_hits;
+  const float* chi2;
+  const float* state;  // [6][n]
+  // workspace
+  float* par;      // [5][n]
+  float* spar;     // [5][n] par in sorted (bin) order
+  int32_t* sint;   // [3][n] in sorted order: a seed's hits, or a track's hit count (row 0)
+  int32_t* skey;   // [n] event * nb + bin of each sorted place
+  int32_t* bin;    // [n], -1: takes no part
+  int32_t* cnt;    // [n_events * nb]
+  int32_t* off;    // [n_events * nb + 1]
+  int32_t* cur;    // [n_events * nb]
+  int32_t* order;  // [n]
+  int32_t* keep;   // [n] output
+};
+
+int dedup_bins(float psi_window);
+hipError_t launch_dedup(const DedupArgs& a, bool seeds, hipStream_t stream);
+
 hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
                          hipEvent_t ev_stop = nullptr);
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream);

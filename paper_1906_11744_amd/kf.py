@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libkf.so")
 KF_MAX_LAYERS = 32
 KF_MAX_KEEP = 8
 KF_OP_FIT, KF_OP_FIND, KF_OP_FIT_BACKWARD, KF_OP_SMOOTH = 1, 2, 3, 4
+KF_OP_CLEAN_SEEDS, KF_OP_REMOVE_DUPLICATES = 5, 6
 
 ST_PROP_FAIL = 1
 ST_NEAR_TANGENT = 2
@@ -67,6 +68,19 @@ class FindOut(C.Structure):
                 ("rf_chi2", C.c_void_p), ("rf_ndf", C.c_void_p), ("rf_status", C.c_void_p)]
 
 
+class DedupCuts(C.Structure):
+    _fields_ = [("psi_window", C.c_float), ("min_shared", C.c_int32), ("min_shared_kin", C.c_int32),
+                ("seed_kap_rel", C.c_float), ("seed_kap_abs", C.c_float), ("seed_theta", C.c_float),
+                ("seed_phi", C.c_float), ("seed_z", C.c_float), ("trk_shared_frac", C.c_float),
+                ("trk_kap_rel", C.c_float), ("trk_kap_abs", C.c_float), ("trk_theta", C.c_float)]
+
+
+class TracksIn(C.Structure):
+    _fields_ = [("n_events", C.c_int32), ("n_hits", C.c_int64), ("hits", C.c_void_p), ("n", C.c_int64),
+                ("event", C.c_void_p), ("hit_idx", C.c_void_p), ("n_hits_trk", C.c_void_p),
+                ("chi2", C.c_void_p), ("state", C.c_void_p)]
+
+
 _LIB = None
 
 
@@ -91,6 +105,12 @@ def _lib():
         lib.kf_find_autotune.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FindIn),
                                          C.POINTER(FindOut), C.c_void_p, C.c_size_t, C.c_void_p,
                                          C.POINTER(FindConfig)]
+        lib.kf_ctx_set_dedup_cuts.argtypes = [C.c_void_p, C.POINTER(DedupCuts)]
+        lib.kf_ctx_get_dedup_cuts.argtypes = [C.c_void_p, C.POINTER(DedupCuts)]
+        lib.kf_clean_seeds.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FindIn), C.c_void_p,
+                                       C.c_void_p, C.c_size_t, C.c_void_p]
+        lib.kf_remove_duplicates.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(TracksIn), C.c_void_p,
+                                             C.c_void_p, C.c_size_t, C.c_void_p]
         lib.kf_smooth.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn), C.POINTER(FitOut),
                                   C.POINTER(SmoothOut), C.c_void_p, C.c_size_t, C.c_void_p]
         lib.kf_fit_backward.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn), C.POINTER(FitOut),
@@ -295,6 +315,74 @@ class Context:
                                   ws.numel(), _stream(stream)), "kf_find")
         return out
 
+    def dedup_cuts(self):
+        """kf_ctx_get_dedup_cuts as a dict."""
+        c = DedupCuts()
+        _check(_lib().kf_ctx_get_dedup_cuts(self._h, C.byref(c)), "kf_ctx_get_dedup_cuts")
+        return {f: getattr(c, f) for f, _ in DedupCuts._fields_}
+
+    def set_dedup_cuts(self, **kw):
+        """kf_ctx_set_dedup_cuts; fields not given keep their current value."""
+        cur = self.dedup_cuts()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise TypeError(f"unknown cut(s) {sorted(unknown)}")
+        cur.update(kw)
+        _check(_lib().kf_ctx_set_dedup_cuts(self._h, C.byref(DedupCuts(**cur))), "kf_ctx_set_dedup_cuts")
+
+    def clean_seeds(self, hits, hit_off, seed_hits, seed_event, align=None, xX0=None, out=None, stream=None):
+        """kf_clean_seeds: keep [S] int32 (1 kept, 0 the duplicate of a lower-index seed)."""
+        L = self.n_layers
+        dev = seed_hits.device
+        H = hits.shape[1]
+        E = hit_off.shape[0]
+        S = seed_hits.shape[1]
+        _dev(hits, torch.float32, (3, H), "hits")
+        _dev(hit_off, torch.int64, (E, L + 1), "hit_off")
+        _dev(seed_hits, torch.int32, (3, S), "seed_hits")
+        _dev(seed_event, torch.int32, (S,), "seed_event")
+        _dev(align, torch.float32, (L, 4), "align")
+        _dev(xX0, torch.float32, (L,), "xX0")
+        if out is None:
+            out = torch.empty(S, dtype=torch.int32, device=dev)
+        _dev(out, torch.int32, (S,), "out")
+        fin = FindIn(E, hit_off.data_ptr(), H, hits.data_ptr(), S, seed_event.data_ptr(), seed_hits.data_ptr(),
+                     0.0, 0.0, 1, 1, 0)
+        ws = self.workspace(KF_OP_CLEAN_SEEDS, fin, dev)
+        p = self._params(align, xX0)
+        _check(_lib().kf_clean_seeds(self._h, C.byref(p), C.byref(fin), C.c_void_p(out.data_ptr()),
+                                     C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "kf_clean_seeds")
+        return out
+
+    def remove_duplicates(self, hits, n_events, event, hit_idx, n_hits, chi2, state, align=None, xX0=None,
+                          out=None, stream=None):
+        """kf_remove_duplicates over built tracks: event [n] int32, hit_idx [L][n] int32,
+        n_hits [n] int32, chi2 [n] float32, state [6][n] float32 (kappa, theta compared).
+        Returns keep [n] int32."""
+        L = self.n_layers
+        dev = event.device
+        H = hits.shape[1]
+        n = event.shape[0]
+        _dev(hits, torch.float32, (3, H), "hits")
+        _dev(event, torch.int32, (n,), "event")
+        _dev(hit_idx, torch.int32, (L, n), "hit_idx")
+        _dev(n_hits, torch.int32, (n,), "n_hits")
+        _dev(chi2, torch.float32, (n,), "chi2")
+        _dev(state, torch.float32, (6, n), "state")
+        _dev(align, torch.float32, (L, 4), "align")
+        _dev(xX0, torch.float32, (L,), "xX0")
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=dev)
+        _dev(out, torch.int32, (n,), "out")
+        tin = TracksIn(int(n_events), H, hits.data_ptr(), n, event.data_ptr(), hit_idx.data_ptr(),
+                       n_hits.data_ptr(), chi2.data_ptr(), state.data_ptr())
+        ws = self.workspace(KF_OP_REMOVE_DUPLICATES, tin, dev)
+        p = self._params(align, xX0)
+        _check(_lib().kf_remove_duplicates(self._h, C.byref(p), C.byref(tin), C.c_void_p(out.data_ptr()),
+                                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+               "kf_remove_duplicates")
+        return out
+
     def smooth(self, hits, hit_mask, fwd, align=None, xX0=None, out=None, stream=None):
         """kf_smooth: smoothed state [L][6][n] and cov [L][21][n] of every layer of a
         fitted batch (fwd from fit(..., ckpt=True) with the same align/xX0), and the
@@ -350,4 +438,5 @@ def exported_symbols():
     return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_ctx_set_launch_events",
             "kf_ctx_set_find_config",
             "kf_ctx_get_find_config", "kf_workspace_size", "kf_fit", "kf_find", "kf_find_autotune",
-            "kf_smooth", "kf_fit_backward", "kf_strerror"]
+            "kf_smooth", "kf_fit_backward", "kf_ctx_set_dedup_cuts", "kf_ctx_get_dedup_cuts", "kf_clean_seeds",
+            "kf_remove_duplicates", "kf_strerror"]

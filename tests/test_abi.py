@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 import synth
@@ -106,3 +107,25 @@ def test_launch_event_hook_validation():
     assert lib.kf_ctx_set_launch_events(ctx._h, None, fake) == -1
     assert lib.kf_ctx_set_launch_events(ctx._h, fake, fake) == 0
     assert lib.kf_ctx_set_launch_events(ctx._h, None, None) == 0
+
+
+def test_dedup_cuts_defaults_roundtrip_and_validation():
+    """The library's default duplicate cuts are the oracle's; set/get round-trips; bad
+    cuts are refused (host only)."""
+    import oracle
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    c = ctx.dedup_cuts()
+    s, t = oracle.SEED_CUTS, oracle.TRACK_CUTS
+    assert c["psi_window"] == np.float32(s["psi_window"]) == np.float32(t["psi_window"])
+    assert (c["min_shared"], c["min_shared_kin"]) == (s["min_shared"], s["min_shared_kin"])
+    for k_lib, v in (("seed_kap_rel", s["kap_rel"]), ("seed_kap_abs", s["kap_abs"]), ("seed_theta", s["theta"]),
+                     ("seed_phi", s["phi"]), ("seed_z", s["z"]), ("trk_shared_frac", t["shared_frac"]),
+                     ("trk_kap_rel", t["kap_rel"]), ("trk_kap_abs", t["kap_abs"]), ("trk_theta", t["theta"])):
+        assert c[k_lib] == np.float32(v), k_lib
+    ctx.set_dedup_cuts(psi_window=0.1, min_shared=3)
+    assert ctx.dedup_cuts()["psi_window"] == np.float32(0.1) and ctx.dedup_cuts()["min_shared"] == 3
+    for bad in (dict(psi_window=0.0), dict(seed_theta=-1.0), dict(min_shared=0, min_shared_kin=1)):
+        with pytest.raises(kf.KfError):
+            ctx.set_dedup_cuts(**bad)
+    assert ctx.dedup_cuts()["psi_window"] == np.float32(0.1)
