@@ -156,10 +156,15 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(DedupArgs a, const int3
 }
 
 // Visit the sorted places of bins b-1, b, b+1 (wrapped, each bin once) of the bin
-// `key` belongs to; f(q) returns true to stop.  Consecutive lanes hold consecutive
-// places, mostly of one bin, so their loops run over the same places.
-template <class F>
-__device__ __forceinline__ bool for_neighbours(const DedupArgs& a, int32_t key, F f) {
+// `key` belongs to.  Consecutive lanes hold consecutive places, mostly of one bin, so
+// their loops run over the same places.  The places come in chunks of 8 whose azimuth,
+// row `r2` of the sorted quantities and item index are loaded together (loads in
+// flight together, not one by one); pre(psi_q, x_q, j) is the cheap first test,
+// full(q, j) the rest of the relation; the walk stops at the first place that passes
+// both.
+template <class Pre, class Full>
+__device__ __forceinline__ bool for_neighbours(const DedupArgs& a, int32_t key, int r2, Pre pre, Full full) {
+  constexpr int kChunk = 8;
   const int b = key % a.nb;
   const int64_t e0 = (int64_t)key - b;
   const int nd = a.nb >= 3 ? 3 : a.nb;
@@ -168,8 +173,20 @@ __device__ __forceinline__ bool for_neighbours(const DedupArgs& a, int32_t key, 
     if (bb >= a.nb) bb -= a.nb;
     if (bb < 0) bb += a.nb;
     const int32_t s1 = a.off[e0 + bb + 1];
-    for (int32_t q = a.off[e0 + bb]; q < s1; ++q)
-      if (f(q)) return true;
+    for (int32_t q0 = a.off[e0 + bb]; q0 < s1; q0 += kChunk) {
+      float ps[kChunk], xs[kChunk];
+      int32_t jj[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) {
+        const int32_t q = q0 + k < s1 ? q0 + k : s1 - 1;  // in range; repeats are tested once
+        ps[k] = a.spar[q];
+        xs[k] = a.spar[(int64_t)r2 * a.n + q];
+        jj[k] = a.order[q];
+      }
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k)
+        if (q0 + k < s1 && pre(ps[k], xs[k], jj[k]) && full(q0 + k, jj[k])) return true;
+    }
   }
   return false;
 }
@@ -186,19 +203,22 @@ __global__ __launch_bounds__(kBlock) void clean_decide_kernel(DedupArgs a, int64
 #pragma unroll
   for (int l = 0; l < 3; ++l) h[l] = a.sint[l * n + s];
   const DedupCuts c = a.c;
-  const bool dup = for_neighbours(a, a.skey[s], [&](int32_t q) {
-    if (a.order[q] >= i) return false;  // priority: the lower index
-    if (!(fabsf(kfd::wrap_pi(psi - a.spar[q])) <= c.psi_window)) return false;
-    int shared = 0;
+  const bool dup = for_neighbours(
+      a, a.skey[s], 0,
+      [&](float psi_q, float, int32_t j) {  // priority (the lower index), then the window
+        return j < i && fabsf(kfd::wrap_pi(psi - psi_q)) <= c.psi_window;
+      },
+      [&](int32_t q, int32_t) {
+        int shared = 0;
 #pragma unroll
-    for (int l = 0; l < 3; ++l) shared += a.sint[l * n + q] == h[l];
-    if (shared >= c.min_shared) return true;
-    if (shared < c.min_shared_kin) return false;
-    const float kj = a.spar[n + q];
-    const float kcut = c.seed_kap_rel * fmaxf(fabsf(kap), fabsf(kj)) + c.seed_kap_abs;
-    return fabsf(kap - kj) <= kcut && fabsf(th - a.spar[2 * n + q]) <= c.seed_theta &&
-           fabsf(kfd::wrap_pi(ph - a.spar[3 * n + q])) <= c.seed_phi && fabsf(z - a.spar[4 * n + q]) <= c.seed_z;
-  });
+        for (int l = 0; l < 3; ++l) shared += a.sint[l * n + q] == h[l];
+        if (shared >= c.min_shared) return true;
+        if (shared < c.min_shared_kin) return false;
+        const float kj = a.spar[n + q];
+        const float kcut = c.seed_kap_rel * fmaxf(fabsf(kap), fabsf(kj)) + c.seed_kap_abs;
+        return fabsf(kap - kj) <= kcut && fabsf(th - a.spar[2 * n + q]) <= c.seed_theta &&
+               fabsf(kfd::wrap_pi(ph - a.spar[3 * n + q])) <= c.seed_phi && fabsf(z - a.spar[4 * n + q]) <= c.seed_z;
+      });
   a.keep[i] = dup ? 0 : 1;
 }
 
@@ -210,24 +230,26 @@ __global__ __launch_bounds__(kBlock) void remove_decide_kernel(DedupArgs a, int6
   const float psi = a.spar[s], kap = a.spar[n + s], th = a.spar[2 * n + s], c2 = a.spar[3 * n + s];
   const int32_t nh = a.sint[s];
   const DedupCuts c = a.c;
-  const bool dup = for_neighbours(a, a.skey[s], [&](int32_t q) {
-    const int32_t j = a.order[q];
-    if (j == i) return false;
-    const int32_t nj = a.sint[q];
-    const float cj = a.spar[3 * n + q];
-    const bool higher = nj != nh ? nj > nh : (cj != c2 ? cj < c2 : j < i);
-    if (!higher) return false;
-    if (!(fabsf(kfd::wrap_pi(psi - a.spar[q])) <= c.psi_window)) return false;
-    const float kj = a.spar[n + q];
-    const float kcut = c.trk_kap_rel * fmaxf(fabsf(kap), fabsf(kj)) + c.trk_kap_abs;
-    if (!(fabsf(kap - kj) <= kcut) || !(fabsf(th - a.spar[2 * n + q]) <= c.trk_theta)) return false;
-    int shared = 0;
-    for (int l = 0; l < a.nl; ++l) {
-      const int32_t hi = a.hit_idx[(int64_t)l * n + i];
-      shared += hi >= 0 && hi == a.hit_idx[(int64_t)l * n + j];
-    }
-    return (float)shared >= c.trk_shared_frac * (float)(nj < nh ? nj : nh);
-  });
+  const bool dup = for_neighbours(
+      a, a.skey[s], 2,
+      [&](float psi_q, float th_q, int32_t j) {  // the window and theta reject nearly all
+        return j != i && fabsf(kfd::wrap_pi(psi - psi_q)) <= c.psi_window && fabsf(th - th_q) <= c.trk_theta;
+      },
+      [&](int32_t q, int32_t j) {
+        const int32_t nj = a.sint[q];
+        const float cj = a.spar[3 * n + q];
+        const bool higher = nj != nh ? nj > nh : (cj != c2 ? cj < c2 : j < i);
+        if (!higher) return false;
+        const float kj = a.spar[n + q];
+        const float kcut = c.trk_kap_rel * fmaxf(fabsf(kap), fabsf(kj)) + c.trk_kap_abs;
+        if (!(fabsf(kap - kj) <= kcut)) return false;
+        int shared = 0;
+        for (int l = 0; l < a.nl; ++l) {
+          const int32_t hi = a.hit_idx[(int64_t)l * n + i];
+          shared += hi >= 0 && hi == a.hit_idx[(int64_t)l * n + j];
+        }
+        return (float)shared >= c.trk_shared_frac * (float)(nj < nh ? nj : nh);
+      });
   a.keep[i] = dup ? 0 : 1;
 }
 
