@@ -316,6 +316,36 @@ def bench_dedup(steps, warmup):
             "remove_ms": t_rm * 1e3, "remove_tracks_per_s": S2 / t_rm}
 
 
+def cpu_scaling():
+    """The oracle's finder over several events at once (its OpenMP loop runs over every
+    seed of every event, so all events are in flight together) against the number of
+    threads: the CPU reference point for the finder, the analogue of the paper's scan of
+    events in flight.  8 events of the 64-event mix scaled to ~1 250 tracks each."""
+    import os
+
+    import oracle
+    import synth
+    geom, ev = synth.find_workload(5, n_tracks=1250, n_events=8)
+    n_cpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = [t for t in (1, 2, 4, 8, 16, 32, 64) if t <= n_cpu]
+    rows = []
+    try:
+        for t in threads:
+            oracle.set_num_threads(t)
+            t0 = time.perf_counter()
+            oracle.find(geom, ev)
+            dt = time.perf_counter() - t0
+            rows.append({"threads": t, "s": dt, "events_per_s": ev.n_tracks.shape[0] / dt})
+            print(f"# cpu scaling: {t} threads {dt:.2f} s", file=sys.stderr, flush=True)
+    finally:
+        oracle.set_num_threads(0)
+    base = rows[0]["s"]
+    for r in rows:
+        r["speedup"] = base / r["s"]
+    return {"events": int(ev.n_tracks.shape[0]), "seeds": int(ev.seed_hits.shape[1]),
+            "tracks_per_event_mean": float(ev.n_tracks.mean()), "scan": rows}
+
+
 def copy_calibration(steps):
     """A plain device copy of 1 GiB, `steps` times: the reference kernel whose HBM
     counters (FETCH_SIZE, WRITE_SIZE) calibrate those of the fit kernel."""
@@ -334,7 +364,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "copy"], default="all")
+    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "cpu_scaling", "copy"],
+                    default="all")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the fit shards tracks across GPUs with no exchange, "
@@ -424,6 +455,8 @@ def main():
         res["smooth"] = bench_smooth(args.steps, args.warmup, args.tracks)
     if args.only in ("all", "dedup"):
         res["dedup"] = bench_dedup(args.steps, args.warmup)
+    if args.only in ("all", "cpu_scaling") and not args.no_cpu_baseline:
+        res["cpu_finder_scaling"] = cpu_scaling()
     print(json.dumps(res), flush=True)
 
 

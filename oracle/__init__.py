@@ -60,6 +60,11 @@ def num_threads() -> int:
     return int(load().oracle_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (n < 1: all processors)."""
+    load().oracle_set_num_threads(C.c_int(int(n)))
+
+
 def ogeom(geom) -> OGeom:
     g = OGeom()
     g.n_layers = geom.n_layers

@@ -647,8 +647,10 @@ Track<T> fit_track_i(const Geo& g, const Layer<T>* lay, const HT* hits, int64_t 
 // ==============================================================================
 extern "C" {
 
-// Threads the OpenMP loops of the batch entries use.
+// Threads the OpenMP loops of the batch entries use, and a setter (for the CPU
+// scaling study; n < 1 restores the default).
 int oracle_num_threads() { return omp_get_max_threads(); }
+void oracle_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
 
 // Crossing of one state with the cylinder |p - c| = r: writes the propagated state
 // and the transverse arc; returns 1 on success, 0 if the layer is not reached.
