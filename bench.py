@@ -40,7 +40,8 @@ FLOPS_FIRST = 14 + 83 + 9 + 50 + 356 + 1          # update at the seed layer
 FLOPS_PROPAGATE = 60 + 194 + 14                    # crossing, transport, frame
 FLOPS_SCATTER = 27
 FLOPS_UPDATE = 83 + 9 + 50 + 356 + 1
-PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk, packed FP32)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # the same without packed FP32 (64 FMA lanes per CU per clock)
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of one fit_kernel launch on the 1e6-track workload, from two rocprofv3 --pmc
@@ -422,7 +423,9 @@ def main():
                          "kernel": "fit_kernel", "avg_launch_ms": avg * 1e3,
                          "ms_per_call_with_kernel_gaps": avg_region * 1e3,
                          "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
-                         "hbm_frac": nbytes / avg / 1e9 / PEAK_HBM_GBS},
+                         "hbm_frac": nbytes / avg / 1e9 / PEAK_HBM_GBS,
+                         "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                         "frac_unpacked": achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS},
         }
         if not args.no_cpu_baseline:
             # the oracle over the whole workload, pass after pass, until 10 s have elapsed
