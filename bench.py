@@ -36,10 +36,11 @@ sys.path.insert(0, ROOT)
 # A track with hits on layers 0..n-1 costs SEED + FIRST + (n - 1) * STEP.  The count
 # agrees with the hardware's SQ_INSTS_VALU_FLOPS_FP32 of the fit kernel to 1%.
 FLOPS_SEED = 91
-FLOPS_FIRST = 14 + 83 + 9 + 50 + 356 + 1          # update at the seed layer
+FLOPS_PLACE = 9                                    # a hit placed on a layer its alignment moves
+FLOPS_FIRST = 14 + 83 + FLOPS_PLACE + 50 + 356 + 1  # update at the seed layer
 FLOPS_PROPAGATE = 60 + 194 + 14                    # crossing, transport, frame
 FLOPS_SCATTER = 27
-FLOPS_UPDATE = 83 + 9 + 50 + 356 + 1
+FLOPS_UPDATE = 83 + FLOPS_PLACE + 50 + 356 + 1
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk, packed FP32)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # the same without packed FP32 (64 FMA lanes per CU per clock)
 PEAK_HBM_GBS = 8000.0
@@ -48,8 +49,8 @@ PEAK_HBM_GBS = 8000.0
 # runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean of 9 launches), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "7c6bc0d41e5cc0ba", "tracks": 1_000_000,
-               "fetch_kib": 102031.6, "write_kib": 117187.5,
+FIT_TRAFFIC = {"sources": "e986ef33b68ffe1a", "tracks": 1_000_000,
+               "fetch_kib": 102018.9, "write_kib": 117187.5,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
@@ -83,11 +84,14 @@ def smooth_traffic_bytes(n_tracks):
     return _traffic_bytes(SMOOTH_TRAFFIC, SMOOTH_SOURCES, n_tracks)
 
 
-def algorithmic_flops(n_hits_per_track, xX0_positive=True):
+def algorithmic_flops(n_hits_per_track, xX0_positive=True, aligned=False):
+    """Flops per launch; without alignment the hit placement is the identity, which the
+    kernel skips, and is not counted."""
     n = np.asarray(n_hits_per_track, np.int64)
     n = n[n > 0]
-    per = (FLOPS_SEED + FLOPS_FIRST +
-           (FLOPS_PROPAGATE + (FLOPS_SCATTER if xX0_positive else 0) + FLOPS_UPDATE) * (n - 1))
+    place = 0 if aligned else FLOPS_PLACE
+    per = (FLOPS_SEED + FLOPS_FIRST - place +
+           (FLOPS_PROPAGATE + (FLOPS_SCATTER if xX0_positive else 0) + FLOPS_UPDATE - place) * (n - 1))
     return float(per.sum())
 
 

@@ -30,7 +30,8 @@ __host__ __device__ constexpr int tri(int i, int j) { return i >= j ? i * (i + 1
 
 // Per-layer constants of one launch (uniform across lanes).
 struct LayerK {
-  float r, cx, cy, dz, cphi, sphi, xX0, pad;
+  float r, cx, cy, dz, cphi, sphi, xX0;
+  float moved;  // 1 if the alignment moves the layer (any of cx, cy, dz, its rotation), else 0
 };
 
 // Constants of the hit model and the field.
@@ -203,7 +204,7 @@ __device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
   add_pos(k.x[0], k.xl[0], st.dx);
   add_pos(k.x[1], k.xl[1], st.dy);
   k.x[2] = fmaf(s * rst, k.ct, k.x[2]);  // z needs no compensation (xl[2] stays 0)
-  k.x[4] = wrap_pi(k.x[4] + u);
+  k.x[4] += u;  // wrapped where it is stored: the step uses (cp, sp), not phi
   const float cp = k.cp * cu - k.sp * su;
   const float sp = k.sp * cu + k.cp * su;
   const float nrm = hrsqrt(fmaf(cp, cp, sp * sp));
@@ -370,9 +371,7 @@ __device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model&
   k.x[2] = fmaf(K1[2], r1, fmaf(K2[2], r2, k.x[2]));
 #pragma unroll
   for (int i = 3; i < 6; ++i) k.x[i] = fmaf(K1[i], r1, fmaf(K2[i], r2, k.x[i]));
-  const float phin = wrap_pi(k.x[4]);
-  k.x[4] = phin;
-  rotate_small(k.cp, k.sp, dphi, phin);
+  rotate_small(k.cp, k.sp, dphi, k.x[4]);
   rotate_small(k.ct, k.st, dth, k.x[5]);
   float* C = k.C;
   // M[i][j] for the lower triangle and for columns 0..2 of every row
@@ -401,9 +400,15 @@ __device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model&
 // Place a nominal-frame hit on its (aligned) layer.
 __device__ __forceinline__ void place(const LayerK& ly, float hx, float hy, float hz, float& mx, float& my,
                                       float& mz) {
-  mx = ly.cx + fmaf(ly.cphi, hx, -ly.sphi * hy);
-  my = ly.cy + fmaf(ly.sphi, hx, ly.cphi * hy);
-  mz = hz + ly.dz;
+  if (ly.moved != 0.f) {  // (the identity transform gives the same bits)
+    mx = ly.cx + fmaf(ly.cphi, hx, -ly.sphi * hy);
+    my = ly.cy + fmaf(ly.sphi, hx, ly.cphi * hy);
+    mz = hz + ly.dz;
+  } else {
+    mx = hx;
+    my = hy;
+    mz = hz;
+  }
 }
 
 // Seed: the helix through three placed hits (signed Menger curvature, chord angles),

@@ -596,7 +596,8 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
         a.status[at(slot, 1)] = have ? st : 0u;
 #pragma unroll
         for (int q = 0; q < 6; ++q)
-          a.state[((int64_t)slot * 6 + q) * S + s] = have ? (q < 3 ? k.x[q] + k.xl[q] : k.x[q]) : 0.f;
+          a.state[((int64_t)slot * 6 + q) * S + s] =
+              have ? (q < 3 ? k.x[q] + k.xl[q] : (q == 4 ? kfd::wrap_pi(k.x[q]) : k.x[q])) : 0.f;
 #pragma unroll
         for (int q = 0; q < 21; ++q) a.cov[((int64_t)slot * 21 + q) * S + s] = have ? k.C[q] : 0.f;
       }

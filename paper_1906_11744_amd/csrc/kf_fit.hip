@@ -19,7 +19,7 @@ __device__ __forceinline__ kfd::LayerK make_layer(int l, const float* radius, co
   const float dphi = align ? align[4 * l + 3] : 0.f;
   sincosf(dphi, &k.sphi, &k.cphi);
   k.xX0 = xX0 ? xX0[l] : 0.f;
-  k.pad = 0.f;
+  k.moved = (k.cx != 0.f || k.cy != 0.f || k.dz != 0.f || dphi != 0.f) ? 1.f : 0.f;
   return k;
 }
 
@@ -41,7 +41,7 @@ hipError_t launch_layer_prep(int nl, const float* radius_host, const float* alig
 __device__ __forceinline__ void store_ckpt(float* ck, int64_t n, int64_t i, int l, const kfd::Trk& k) {
   float* p = ck + (int64_t)l * 27 * n + i;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) p[q * n] = q < 3 ? k.x[q] + k.xl[q] : k.x[q];
+  for (int q = 0; q < 6; ++q) p[q * n] = q < 3 ? k.x[q] + k.xl[q] : (q == 4 ? kfd::wrap_pi(k.x[q]) : k.x[q]);
 #pragma unroll
   for (int q = 0; q < 21; ++q) p[(6 + q) * n] = k.C[q];
 }
@@ -141,7 +141,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       if (!isfinite(k.x[q])) status |= kfd::ST_NONFINITE;
   }
 #pragma unroll
-  for (int q = 0; q < 6; ++q) a.state[q * n + i] = q < 3 ? k.x[q] + k.xl[q] : k.x[q];
+  for (int q = 0; q < 6; ++q) a.state[q * n + i] = q < 3 ? k.x[q] + k.xl[q] : (q == 4 ? kfd::wrap_pi(k.x[q]) : k.x[q]);
 #pragma unroll
   for (int q = 0; q < 21; ++q) a.cov[q * n + i] = k.C[q];
   a.chi2[i] = chi2;
