@@ -129,3 +129,33 @@ def test_dedup_cuts_defaults_roundtrip_and_validation():
         with pytest.raises(kf.KfError):
             ctx.set_dedup_cuts(**bad)
     assert ctx.dedup_cuts()["psi_window"] == np.float32(0.1)
+
+
+def test_dedup_calls_reject_bad_arguments_before_launch():
+    """kf_clean_seeds / kf_remove_duplicates: empty input is a no-op; NULL context,
+    input or arrays and negative counts are refused before anything is launched."""
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    keep = C.c_void_p(0x1000)    # never dereferenced on these paths
+    fin = kf.FindIn(1, None, 0, None, 0, None, None, 0.0, 0.0, 1, 1, 0)
+    assert lib.kf_clean_seeds(ctx._h, None, C.byref(fin), None, None, 0, None) == 0     # n_seeds = 0
+    fin = kf.FindIn(1, None, 0, None, 5, None, None, 0.0, 0.0, 1, 1, 0)
+    assert lib.kf_clean_seeds(ctx._h, None, C.byref(fin), keep, None, 0, None) == -1    # missing arrays
+    assert lib.kf_clean_seeds(None, None, C.byref(fin), keep, None, 0, None) == -1
+    fin = kf.FindIn(-1, None, 0, None, 5, None, None, 0.0, 0.0, 1, 1, 0)
+    assert lib.kf_clean_seeds(ctx._h, None, C.byref(fin), keep, None, 0, None) == -1    # n_events < 0
+    tin = kf.TracksIn(1, 0, None, 0, None, None, None, None, None)
+    assert lib.kf_remove_duplicates(ctx._h, None, C.byref(tin), None, None, 0, None) == 0
+    tin = kf.TracksIn(1, 0, None, 3, None, None, None, None, None)
+    assert lib.kf_remove_duplicates(ctx._h, None, C.byref(tin), keep, None, 0, None) == -1
+    tin = kf.TracksIn(1, -2, None, 3, None, None, None, None, None)
+    assert lib.kf_remove_duplicates(ctx._h, None, C.byref(tin), keep, None, 0, None) == -1
+    assert lib.kf_remove_duplicates(ctx._h, None, None, keep, None, 0, None) == -1
+    # workspace sizes grow with the items and the events
+    nb = C.c_size_t(0)
+    fin = kf.FindIn(64, None, 0, None, 1000, None, None, 0.0, 0.0, 1, 1, 0)
+    assert lib.kf_workspace_size(ctx._h, kf.KF_OP_CLEAN_SEEDS, C.byref(fin), C.byref(nb)) == 0
+    small = nb.value
+    fin = kf.FindIn(64, None, 0, None, 100000, None, None, 0.0, 0.0, 1, 1, 0)
+    assert lib.kf_workspace_size(ctx._h, kf.KF_OP_CLEAN_SEEDS, C.byref(fin), C.byref(nb)) == 0
+    assert nb.value > small + 100000 * 40
