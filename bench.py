@@ -101,30 +101,71 @@ def algorithmic_bytes(n_tracks, n_layers, n_steps):
     return float(n_steps * 12 + n_tracks * (4 + 24 + 84 + 12))
 
 
-def _time_launches(fn, steps, warmup):
-    """Device time per call of fn() over `steps` back-to-back calls after `warmup`, on
-    the current stream (the library launches on it): the mean over calls of a HIP event
-    pair recorded around each call (the launch's own duration), the mean per call of one
-    event pair around the whole region (which adds the GPU's gap between consecutive
-    kernels), and the wall-clock seconds of the region."""
+# The GPU lowers its clocks within milliseconds of going idle and needs some tens of
+# milliseconds of sustained load to raise them again (measured on the fit: ~235 us per
+# launch cold, ~204 us after ~200 back-to-back launches).  Every timed function is
+# first run back to back for this long, untimed, before its warm-up steps.
+SETTLE_S = 0.2
+
+
+def _settle(fn, seconds=SETTLE_S):
+    """Run fn() back to back until `seconds` of wall clock have passed (synchronising
+    every few calls so the host does not run ahead of the GPU); returns the calls made."""
     import torch
+    t0 = time.perf_counter()
+    calls = 0
+    while True:
+        for _ in range(4):
+            fn()
+        calls += 4
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            return calls
+
+
+class Timing(tuple):
+    """(region, per_launch, wall): seconds per call of a back-to-back region bracketed by
+    one event pair, seconds per call from an event pair around each call, and wall-clock
+    seconds per call of the region."""
+    __slots__ = ()
+
+    def __new__(cls, region, per_launch, wall):
+        return super().__new__(cls, (region, per_launch, wall))
+
+    region = property(lambda self: self[0])
+    per_launch = property(lambda self: self[1])
+    wall = property(lambda self: self[2])
+
+
+def _time_launches(fn, steps, warmup):
+    """Time `steps` back-to-back calls of fn() on the current stream (the library
+    launches on it), after the clocks have settled and `warmup` untimed calls: one HIP
+    event pair around the whole region (device time, including the GPU's gap between
+    consecutive calls) and the host's wall clock around it, both between two
+    synchronisations; then a second pass with an event pair around each call."""
+    import torch
+    _settle(fn)
     for _ in range(max(1, warmup)):
         fn()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    region = e0.elapsed_time(e1) * 1e-3 / steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for a, b in ev:
         a.record(stream)
         fn()
         b.record(stream)
-    e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     per_launch = sum(a.elapsed_time(b) for a, b in ev) * 1e-3 / steps
-    return per_launch, e0.elapsed_time(e1) * 1e-3 / steps, wall
+    return Timing(region, per_launch, wall / steps)
 
 
 class _HipEvents:
@@ -159,9 +200,10 @@ def _time_kernel(ctx, fn, steps, warmup):
     calls of fn() (after `warmup`): the events of kf_ctx_set_launch_events, one pair per
     call, bracket that kernel's own execution on the stream."""
     import torch
+    he = _HipEvents(2 * steps)
+    _settle(fn)
     for _ in range(max(1, warmup)):
         fn()
-    he = _HipEvents(2 * steps)
     torch.cuda.synchronize()
     try:
         for k in range(steps):
@@ -365,8 +407,8 @@ def copy_calibration(steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "cpu_scaling", "copy"],
@@ -401,9 +443,9 @@ def main():
         steps_per_launch = int(n_hits.sum())
         flops = algorithmic_flops(n_hits)
         nbytes = algorithmic_bytes(n, geom.n_layers, steps_per_launch)
-        _, avg_region, wall = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, out=out), args.steps, args.warmup)
+        tm = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, out=out), args.steps, args.warmup)
         avg = _time_kernel(ctx, lambda: ctx.fit(hits, mask, xX0=xX0, out=out), args.steps, args.warmup)
-        value = steps_per_launch * args.steps / wall
+        value = steps_per_launch / tm.wall
         achieved_tflops = flops / avg / 1e12
         res = {
             "metric": "KF propagate+update steps/s (FP32 vs oracle tol)",
@@ -412,7 +454,7 @@ def main():
             "n_gpus": 1,
             "steps": args.steps,
             "warmup": args.warmup,
-            "ms_per_step": wall / args.steps * 1e3,
+            "ms_per_step": tm.wall * 1e3,
             "higher_is_better": True,
             "scaling": "weak",
             "vs_baseline": None,
@@ -425,7 +467,8 @@ def main():
                          "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": fit_traffic_bytes(n),
                          "traffic_unit": "B per launch",
                          "kernel": "fit_kernel", "avg_launch_ms": avg * 1e3,
-                         "ms_per_call_with_kernel_gaps": avg_region * 1e3,
+                         "ms_per_call_with_kernel_gaps": tm.region * 1e3,
+                         "ms_per_call_with_per_call_events": tm.per_launch * 1e3,
                          "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
                          "hbm_frac": nbytes / avg / 1e9 / PEAK_HBM_GBS,
                          "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
