@@ -268,10 +268,26 @@ def bench_find(steps, warmup):
             kf.find(*a, xX0=xX0, refit=True, out=o)
     avg_l, _, _ = _time_launches(loop, max(3, steps // 4), warmup)
     res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3, "config": cfg_batched,
-                                "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1])}
+                                "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1]),
+                                "fp64_fallback": _fallback_rates(out)}
     res["per_event_loop_64_events"] = {"events_per_s": E / avg_l, "ms_total": avg_l * 1e3}
     res["batched_speedup"] = avg_l / avg_b
     return res
+
+
+def _fallback_rates(out):
+    """Share of the finder's candidates (every kept rank, counted where a candidate
+    exists) and of the refitted best candidates whose status carries the FP64-fallback
+    bit (at least one update took S^-1 and chi2 in FP64)."""
+    n_cand = out["n_cand"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    live = np.arange(st.shape[0])[:, None] < n_cand[None, :]
+    r = {"find_candidates": float(((st & 4) != 0)[live].mean()) if live.any() else 0.0,
+         "find_rank0": float(((st[0] & 4) != 0)[n_cand > 0].mean()) if (n_cand > 0).any() else 0.0}
+    if out.get("rf_status") is not None:
+        rs = out["rf_status"].cpu().numpy()
+        r["refit"] = float(((rs & 4) != 0)[n_cand > 0].mean()) if (n_cand > 0).any() else 0.0
+    return r
 
 
 def bench_grad(steps, warmup):
@@ -463,6 +479,7 @@ def main():
             "config": {"workload": "fit: 1e6 tracks x 17 barrel layers (4-110 cm), B=3.8 T, x/X0=0.02, "
                                    "pT log-uniform 0.5-50 GeV, |eta|<1.5, seeds from first 3 hits (10x cov)",
                        "tracks": n, "layers": geom.n_layers, "kalman_steps_per_launch": steps_per_launch},
+            "fp64_fallback_tracks": float(((status & 4) != 0).mean()),
             "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": fit_traffic_bytes(n),
                          "traffic_unit": "B per launch",
