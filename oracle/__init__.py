@@ -196,6 +196,21 @@ def smooth_filtered(geom, state, cov, lend, align=None, xX0=None):
     return out
 
 
+def material_step(geom, l, state, cov, material, xX0=0.0, align=None):
+    """The material of layer l applied to a state at its crossing (Sec. 3): multiple
+    scattering with the layer's x/X0 (the map's value at the crossing's z if
+    material[0] is a map [L][nz], else xX0), then the mean ionisation loss
+    material[1] * x_eff / beta^2.  Returns (state, cov) or None if the particle stops."""
+    g = ogeom(geom)
+    x = np.array(state, np.float64)
+    Cm = np.array(cov, np.float64).reshape(36)
+    xmap = None if material[0] is None else np.ascontiguousarray(material[0], np.float64)
+    nz = 0 if xmap is None else int(xmap.shape[1])
+    ok = load().oracle_material_step(C.byref(g), int(l), _p(_f64(align)), C.c_double(xX0), _p(xmap), C.c_int(nz),
+                                     C.c_double(float(material[1])), _p(x), _p(Cm))
+    return (x, Cm.reshape(6, 6)) if ok else None
+
+
 def seed(geom, m0, m1, m2):
     st = np.zeros(6)
     cv = np.zeros(36)
@@ -205,12 +220,14 @@ def seed(geom, m0, m1, m2):
     return st, cv.reshape(6, 6)
 
 
-def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, records=False):
+def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, records=False, material=None):
     """Batched FP64 fit; seeds from hits 0-2 unless seed_state/seed_cov are given.
 
     hits [L][3][n] float32 (float64 hits select the float64-input entry), mask [n]
     uint32.  Returns a dict of float64 outputs; records=True adds records [n][L][27],
     the state and packed covariance after each processed layer (NaN beyond).
+    material = (xX0_map [L][nz] or None, eloss GeV per X0): the material model of
+    Sec. 3 (float32 hits only), see material_step.
     """
     dt = np.float64 if np.asarray(hits).dtype == np.float64 else np.float32
     hits = np.ascontiguousarray(hits, dt)
@@ -224,10 +241,20 @@ def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, 
     rec = np.zeros((n, L, 27)) if records else None
     g = ogeom(geom)
     xx = geom.xX0 if xX0 is None else xX0
-    fn = load().oracle_fit_f64 if dt == np.float64 else load().oracle_fit
-    fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(hits), _p(mask),
-                      int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]), _p(out["chi2"]),
-                      _p(out["ndf"]), _p(out["status"]), _p(rec))
+    if material is not None:
+        if dt != np.float32:
+            raise TypeError("the material model takes float32 hits")
+        xmap = None if material[0] is None else np.ascontiguousarray(material[0], np.float64)
+        nz = 0 if xmap is None else int(xmap.shape[1])
+        load().oracle_fit_material(C.byref(g), _p(_f64(align)), _p(_f64(xx)), _p(xmap), C.c_int(nz),
+                                   C.c_double(float(material[1])), C.c_int64(n), _p(hits), _p(mask),
+                                   int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]),
+                                   _p(out["chi2"]), _p(out["ndf"]), _p(out["status"]), _p(rec))
+    else:
+        fn = load().oracle_fit_f64 if dt == np.float64 else load().oracle_fit
+        fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(hits), _p(mask),
+           int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]), _p(out["chi2"]),
+           _p(out["ndf"]), _p(out["status"]), _p(rec))
     if records:
         out["records"] = rec
     return out

@@ -35,7 +35,10 @@
 // dual-number gradient = central finite differences; global translation and
 // rotation leave the total chi2 unchanged; RTS on a linear-Gaussian chain = the joint
 // posterior of all states, noiseless smoothed states = the helix at every layer to
-// second order, smoothed pulls have unit scale and C_s <= C_f.  Parity unpinned: the candidate score
+// second order, smoothed pulls have unit scale and C_s <= C_f; a material map of
+// constant rows without energy loss is the per-layer model bit for bit, one material
+// step matches its definition (covariance row by central differences), and tracks
+// simulated through the map with energy loss give unit pulls.  Parity unpinned: the candidate score
 // and its tie rule, and the Highland variant, which are conventions.
 
 #include <omp.h>
@@ -45,6 +48,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -136,6 +140,7 @@ template <class T>
 struct Layer {
   T cx, cy, dz, cphi, sphi, xX0;  // alignment (centre, z shift, rotation) and x/X0
   double r;
+  int idx;  // layer index (row of a material map)
 };
 
 struct Geo {
@@ -143,6 +148,13 @@ struct Geo {
   double kB, srphi, sz, sr, mass;
   double radius[32], zhalf[32];
   int nphi, nz;
+  // Material beyond one x/X0 per layer (Sec. 3: material arrays indexed in r and z,
+  // multiple scattering and energy loss): map [nl][map_nz] of x/X0 at the centres of
+  // map_nz equal z bins over each layer's [-zhalf, zhalf] (null: the layer's xX0), and
+  // the mean ionisation loss per radiation length at minimum ionisation (0: none).
+  const double* map = nullptr;
+  int map_nz = 0;
+  double eloss = 0.0;
 };
 
 Geo make_geo(const OGeom* g) {
@@ -167,6 +179,7 @@ void make_layers(const Geo& g, const T* align /*[L][4]*/, const T* xX0, Layer<T>
     lay[l].sphi = sin(dphi);
     lay[l].xX0 = xX0 ? xX0[l] : T(0.0);
     lay[l].r = g.radius[l];
+    lay[l].idx = l;
   }
 }
 
@@ -348,6 +361,57 @@ void add_scattering(const Geo& g, const Layer<T>& ly, const T x[6], T C[6][6]) {
   C[3][3] += x[3] * x[3] * cot * cot * th2;
   C[3][5] -= x[3] * cot * th2;
   C[5][3] -= x[3] * cot * th2;
+}
+
+// x/X0 of layer l at z (the layer's own frame) from the material map: linear
+// interpolation between the centres of the map's equal z bins over [-Z_L, Z_L],
+// constant beyond the outer centres.
+double map_xX0(const Geo& g, int l, double z) {
+  const double* m = g.map + (int64_t)l * g.map_nz;
+  const int nz = g.map_nz;
+  if (nz == 1) return m[0];
+  const double Z = g.zhalf[l];
+  const double u = (z + Z) / (2.0 * Z) * nz - 0.5;
+  if (u <= 0.0) return m[0];
+  if (u >= nz - 1) return m[nz - 1];
+  int k = (int)std::floor(u);
+  if (k > nz - 2) k = nz - 2;
+  const double t = u - k;
+  return m[k] + t * (m[k + 1] - m[k]);
+}
+
+// The material of a thin layer at the predicted state (Sec. 3), in FP64 only:
+// multiple scattering with the layer's x/X0 there (the map, else the layer's
+// constant), then the mean ionisation loss dE = eloss * x_eff / beta^2 (x_eff the
+// path length of the scattering term, beta at the incoming momentum): the energy
+// drops to E - dE at fixed direction, so kappa becomes kappa * p / p'.  The
+// covariance follows kappa' as a function of (kappa, theta), differentiated here by
+// dual numbers; the path-length factor enters the mean only.  False if the particle
+// is left without kinetic energy.
+bool material_step(const Geo& g, const Layer<double>& ly, double x[6], double C[6][6]) {
+  Layer<double> lm = ly;
+  if (g.map) lm.xX0 = map_xX0(g, ly.idx, x[2] - ly.dz);
+  add_scattering(g, lm, x, C);
+  if (!(g.eloss > 0.0) || !(lm.xX0 > 0.0)) return true;
+  const double ex = x[0] - ly.cx, ey = x[1] - ly.cy;
+  const double cpsi = std::sin(x[5]) * std::fabs((ex * std::cos(x[4]) + ey * std::sin(x[4])) / std::sqrt(ex * ex + ey * ey));
+  const double xe = lm.xX0 / cpsi;
+  const double m2 = g.mass * g.mass;
+  Dual<2> kap(x[3]), th(x[5]);
+  kap.d[0] = 1.0;
+  th.d[1] = 1.0;
+  const Dual<2> p = 1.0 / (fabs(kap) * sin(th));
+  const Dual<2> E2 = p * p + m2;
+  const Dual<2> E1 = sqrt(E2) - g.eloss * xe * E2 / (p * p);
+  if (!(E1.v > g.mass)) return false;
+  const Dual<2> k1 = kap * p / sqrt(E1 * E1 - m2);
+  double A[6][6] = {};
+  for (int i = 0; i < 6; ++i) A[i][i] = 1.0;
+  A[3][3] = k1.d[0];
+  A[3][5] = k1.d[1];
+  sandwich(A, C);
+  x[3] = k1.v;
+  return true;
 }
 
 // Gauss-Jordan inverse with partial pivoting (n <= 4); returns false if singular.
@@ -533,7 +597,16 @@ bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nul
     double ca = (ex * std::cos(val(tk.x[4])) + ey * std::sin(val(tk.x[4]))) / std::sqrt(ex * ex + ey * ey);
     if (std::fabs(ca) < 0.3) tk.status |= ST_NEAR_TANGENT;
   }
-  add_scattering(g, ly, tk.x, tk.C);
+  if (g.map || g.eloss > 0.0) {
+    if constexpr (std::is_same<T, double>::value) {
+      if (!material_step(g, ly, tk.x, tk.C)) { tk.status |= ST_PROP_FAIL; return false; }
+    } else {
+      tk.status |= ST_BAD_INPUT;  // the material model is not differentiated
+      return false;
+    }
+  } else {
+    add_scattering(g, ly, tk.x, tk.C);
+  }
   return true;
 }
 
@@ -728,8 +801,12 @@ namespace {
 template <class HT>
 void fit_batch(const OGeom* og, const double* align, const double* xX0, int64_t n, const HT* hits,
                const uint32_t* mask, int seed_from_hits_flag, const HT* seed_state, const HT* seed_cov,
-               double* state, double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec) {
+               double* state, double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec,
+               const double* map = nullptr, int map_nz = 0, double eloss = 0.0) {
   Geo g = make_geo(og);
+  g.map = map;
+  g.map_nz = map_nz;
+  g.eloss = eloss;
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
 #pragma omp parallel for schedule(static)
@@ -757,6 +834,41 @@ void oracle_fit(const OGeom* og, const double* align, const double* xX0, int64_t
                 double* state, double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec) {
   fit_batch<float>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, state, cov, chi2, ndf,
                    status, rec);
+}
+
+// As oracle_fit with the material model of Sec. 3: map [L][map_nz] of x/X0 (null: the
+// per-layer xX0) and the mean ionisation loss per radiation length eloss (0: none).
+void oracle_fit_material(const OGeom* og, const double* align, const double* xX0, const double* map, int map_nz,
+                         double eloss, int64_t n, const float* hits, const uint32_t* mask, int seed_from_hits_flag,
+                         const float* seed_state, const float* seed_cov, double* state, double* cov, double* chi2,
+                         int32_t* ndf, uint32_t* status, double* rec) {
+  fit_batch<float>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, state, cov, chi2, ndf,
+                   status, rec, map, map_nz, eloss);
+}
+
+// One material step on a state at its crossing with layer l (align [4] and xX0 of
+// that layer, either may be null): x [6] and C [36] in, updated in place.  Returns 0
+// if the particle stops.
+int oracle_material_step(const OGeom* og, int l, const double* align, double xX0, const double* map, int map_nz,
+                         double eloss, double* x, double* C) {
+  Geo g = make_geo(og);
+  g.map = map;
+  g.map_nz = map_nz;
+  g.eloss = eloss;
+  Layer<double> lay[32];
+  double al[32 * 4] = {};
+  double xx[32] = {};
+  if (align)
+    for (int q = 0; q < 4; ++q) al[4 * l + q] = align[q];
+  xx[l] = xX0;
+  make_layers<double>(g, al, xx, lay);
+  double Cm[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) Cm[i][j] = C[i * 6 + j];
+  const bool ok = material_step(g, lay[l], x, Cm);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) C[i * 6 + j] = Cm[i][j];
+  return ok ? 1 : 0;
 }
 
 // As oracle_fit with float64 hits and seeds (for noiseless checks finer than float32).

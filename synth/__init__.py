@@ -34,6 +34,10 @@ K_B_PER_TESLA = 0.299792458e-2   # GeV / (cm T)
 M_PION = 0.13957039              # GeV
 HIGHLAND_A = 0.0136              # GeV
 HIGHLAND_B = 0.038
+# Mean ionisation loss of a minimum-ionising particle per radiation length of silicon:
+# (dE/dx)_min = 1.664 MeV cm^2/g times X0 = 21.82 g/cm^2 (PDG tables of atomic and
+# nuclear properties of materials).
+ELOSS_SI_GEV_PER_X0 = 0.0363
 
 
 @dataclasses.dataclass
@@ -187,15 +191,19 @@ class TrackSample:
 
 def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max=1.0,
              align=None, smear=True, scatter=True, keep_truth=True, particles=None,
-             hit_dtype=np.float32):
+             hit_dtype=np.float32, material=None):
     """Simulate n prompt tracks through every layer in turn.
 
     At each layer: exact crossing (first_crossing), record the unsmeared point,
     smear it along the cylinder (sigma_rphi in r*phi, sigma_z in z), then apply a
     Gaussian multiple-scattering kick with the Highland width for the crossing's
-    path length (x/X0 / cos psi, cos psi = sin(theta) |r_hat . t|).  The momentum
-    magnitude is conserved (no energy loss).  A track that cannot reach a layer
-    stops there; later layers have no hit.
+    path length (x/X0 / cos psi, cos psi = sin(theta) |r_hat . t|).  Without
+    `material` the layer's x/X0 is geom.xX0 and the momentum magnitude is conserved.
+    With material = (xX0_map [L][nz], eloss) the layer's x/X0 is the map
+    interpolated at the crossing's z (material_at), and after the kick the energy
+    drops by the mean ionisation loss eloss * x_eff / beta^2 (x_eff the same path
+    length, beta at the incoming momentum); a particle left without kinetic energy
+    stops.  A track that cannot reach a layer stops there; later layers have no hit.
     """
     L = geom.n_layers
     if particles is None:
@@ -245,17 +253,23 @@ def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max
         mask |= np.where(reach, np.uint32(1) << np.uint32(l), np.uint32(0)).astype(np.uint32)
         if keep_truth:
             truth_hit[l] = np.where(reach, np.stack([x, y, z]), np.nan)
-        # multiple scattering at the crossing
+        # multiple scattering (and, with a material model, energy loss) at the crossing
         k1 = rng.standard_normal(n)
         k2 = rng.standard_normal(n)
-        xx = geom.xX0[l]
-        if scatter and xx > 0:
+        if material is None:
+            xx = np.full(n, geom.xX0[l])
+            eloss = 0.0
+        else:
+            xx = material_at(geom, material[0], l, z - dz)
+            eloss = float(material[1])
+        if scatter and np.any(xx > 0):
             st, ct = np.sin(theta), np.cos(theta)
             rhx, rhy = (x - dx) / r, (y - dy) / r
             cpsi = st * np.abs(rhx * np.cos(phi) + rhy * np.sin(phi))
             p = np.abs(1.0 / kappa) / st
             beta = p / np.sqrt(p * p + geom.mass ** 2)
-            th0 = highland_theta0(p, beta, xx / cpsi)
+            xe = np.where(xx > 0, xx / cpsi, 1.0)
+            th0 = np.where(xx > 0, highland_theta0(p, beta, xe), 0.0)
             a = k1 * th0
             b = k2 * th0
             cp, sp = np.cos(phi), np.sin(phi)
@@ -266,7 +280,14 @@ def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max
             dn /= np.linalg.norm(dn, axis=0)
             th_new = np.arccos(np.clip(dn[2], -1.0, 1.0))
             ph_new = np.arctan2(dn[1], dn[0])
-            pt_new = p * np.sin(th_new)
+            p_new = p
+            if eloss > 0:
+                m2 = geom.mass ** 2
+                e_new = np.sqrt(p * p + m2) - np.where(xx > 0, eloss * xe / (beta * beta), 0.0)
+                stopped = reach & (e_new * e_new <= m2)
+                p_new = np.sqrt(np.maximum(e_new * e_new - m2, 1e-300))
+                alive = alive & ~stopped
+            pt_new = p_new * np.sin(th_new)
             theta = np.where(reach, th_new, theta)
             phi = np.where(reach, ph_new, phi)
             kappa = np.where(reach, q / pt_new, kappa)
@@ -274,6 +295,48 @@ def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max
             truth[l] = np.where(reach, np.stack([x, y, z, kappa, phi, theta]), np.nan)
     return TrackSample(hits=hits, hit_mask=mask, truth=truth, truth_hit=truth_hit,
                        pt=pt, phi=phi0, eta=eta, q=q)
+
+
+# --------------------------------------------------------------------------------------
+# material beyond one x/X0 per layer
+# --------------------------------------------------------------------------------------
+
+def material_map(geom: Geometry, nz: int = 16, workload: int = 7):
+    """x/X0 at normal incidence at nz equally spaced z-bin centres of every layer,
+    [L][nz]: the layer's own geom.xX0 (0.02 if it has none) rising as (1 + 1.5 (z/Z_L)^2)
+    towards the ends (cables and supports), 0.01 more in the central bin (a service
+    ring), and a seeded +-20% variation per bin."""
+    rng = np.random.Generator(np.random.Philox(key=[BASE_SEED + workload, 2 ** 31 - 2]))
+    L = geom.n_layers
+    zc = (np.arange(nz) + 0.5) / nz * 2.0 - 1.0          # bin centres in units of Z_L
+    base = np.where(geom.xX0 > 0, geom.xX0, 0.02)
+    m = base[:, None] * (1.0 + 1.5 * zc[None, :] ** 2) * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, (L, nz)))
+    m[:, nz // 2] += 0.01
+    return m
+
+
+def material_at(geom: Geometry, xmap, l, z):
+    """x/X0 of layer l at z (cm, in the layer's own frame): linear interpolation
+    between the bin centres of xmap[l] over [-Z_L, Z_L], constant beyond the outer
+    centres."""
+    xmap = np.asarray(xmap, np.float64)
+    nz = xmap.shape[1]
+    if nz == 1:
+        return np.full(np.shape(z), xmap[l, 0])
+    u = (np.asarray(z, np.float64) + geom.zhalf[l]) / (2.0 * geom.zhalf[l]) * nz - 0.5
+    u = np.clip(u, 0.0, nz - 1.0)
+    k = np.minimum(np.floor(u).astype(np.int64), nz - 2)
+    t = u - k
+    return xmap[l, k] * (1.0 - t) + xmap[l, k + 1] * t
+
+
+def material_workload(n: int = 100_000, event: int = 0, nz: int = 16, eloss: float = ELOSS_SI_GEV_PER_X0):
+    """The 17-layer fit workload (pT log-uniform 0.5..50 GeV, |eta| < 1.5) through a
+    material map with energy loss: returns (geom, ts, (xmap, eloss))."""
+    geom = workload_geometry(2)
+    xmap = material_map(geom, nz)
+    ts = simulate(geom, rng_for(7, event), n, (0.5, 50.0), True, 1.5, material=(xmap, eloss))
+    return geom, ts, (xmap, eloss)
 
 
 # --------------------------------------------------------------------------------------

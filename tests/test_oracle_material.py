@@ -1,0 +1,128 @@
+"""Pins of the oracle's material model (Sec. 3: material arrays indexed in r and z for
+multiple scattering and energy loss), no GPU.
+
+* A map whose every bin holds the layer's own x/X0, without energy loss, is the
+  per-layer model: the fit is bit-identical to the plain one.
+* One material step against the definitions written out here in numpy: the map is
+  interpolated as the generator does it (synth.material_at, written separately from
+  the oracle's lookup), kappa' = kappa p / p' with E' = E - eloss x_eff / beta^2, the
+  other parameters unchanged, and the covariance A (C + Q) A^T with Q the oracle's
+  scattering term at the interpolated x/X0 and A's kappa row taken by central
+  differences of that closed form (the oracle takes it by dual numbers).
+* Simulated tracks through the map with energy loss (the generator's own model):
+  the fitted parameters' pulls have zero mean and unit width; leaving the energy loss
+  out biases the curvature of low-momentum tracks by ~2 sigma, and replacing the map
+  by one x/X0 per layer widens the pulls, so both parts of the model are seen.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import physics
+import synth
+
+
+def test_constant_map_without_loss_is_the_layer_model(oracle_lib):
+    geom, ts = synth.fit_workload(2, n=3000)
+    ref = oracle.fit(geom, ts.hits, ts.hit_mask)
+    for nz in (1, 8):
+        xmap = np.repeat(geom.xX0[:, None], nz, axis=1)
+        o = oracle.fit(geom, ts.hits, ts.hit_mask, material=(xmap, 0.0))
+        for k in ("state", "cov", "chi2", "ndf", "status"):
+            assert np.array_equal(o[k], ref[k]), (nz, k)
+    o = oracle.fit(geom, ts.hits, ts.hit_mask, material=(None, 0.0))
+    assert np.array_equal(o["state"], ref["state"]) and np.array_equal(o["cov"], ref["cov"])
+
+
+def _kappa_after_loss(kap, th, xe, eloss, mass):
+    p = 1.0 / (abs(kap) * math.sin(th))
+    e = math.sqrt(p * p + mass * mass)
+    e1 = e - eloss * xe * (e * e) / (p * p)
+    if e1 <= mass:
+        return None
+    return kap * p / math.sqrt(e1 * e1 - mass * mass)
+
+
+def test_material_step_against_its_definition(oracle_lib):
+    geom = synth.workload_geometry(2)
+    xmap = synth.material_map(geom, 12)
+    eloss = synth.ELOSS_SI_GEV_PER_X0
+    rng = np.random.default_rng(5)
+    align = np.array([0.01, -0.02, 0.3, 0.0])
+    checked = 0
+    for _ in range(200):
+        l = int(rng.integers(1, geom.n_layers))
+        r = geom.radius[l]
+        a = rng.uniform(-math.pi, math.pi)
+        z_loc = rng.uniform(-1.3, 1.3) * geom.zhalf[l]          # beyond the outer centres too
+        x = np.array([align[0] + r * math.cos(a), align[1] + r * math.sin(a), z_loc + align[2],
+                      rng.choice([-1, 1]) / (0.5 * 100 ** rng.random()),
+                      a + rng.uniform(-0.8, 0.8), rng.uniform(0.5, math.pi - 0.5)])
+        A0 = rng.standard_normal((6, 6))
+        C0 = A0 @ A0.T * 1e-4 + np.eye(6) * 1e-5
+        out = oracle.material_step(geom, l, x, C0, (xmap, eloss), align=align)
+        xx = float(synth.material_at(geom, xmap, l, np.array([z_loc]))[0])
+        cpsi = math.sin(x[5]) * abs(math.cos(x[4] - a))
+        xe = xx / cpsi
+        k1 = _kappa_after_loss(x[3], x[5], xe, eloss, geom.mass)
+        assert out is not None and k1 is not None
+        xs, Cs = out
+        assert abs(xs[3] - k1) <= 1e-12 * abs(k1)
+        assert np.array_equal(np.delete(xs, 3), np.delete(x, 3))
+        # covariance: A (C + Q) A^T, A's kappa row by central differences
+        Q = oracle.scattering(geom, x, align[:2], xx)
+        hk, ht = 1e-6 * abs(x[3]), 1e-6
+        dk = (_kappa_after_loss(x[3] + hk, x[5], xe, eloss, geom.mass) -
+              _kappa_after_loss(x[3] - hk, x[5], xe, eloss, geom.mass)) / (2 * hk)
+        dt = (_kappa_after_loss(x[3], x[5] + ht, xe, eloss, geom.mass) -
+              _kappa_after_loss(x[3], x[5] - ht, xe, eloss, geom.mass)) / (2 * ht)
+        A = np.eye(6)
+        A[3, 3], A[3, 5] = dk, dt
+        Cref = A @ (C0 + Q) @ A.T
+        d = np.sqrt(np.diag(Cref))
+        assert np.max(np.abs(Cs - Cref) / np.outer(d, d)) < 1e-8
+        checked += 1
+    assert checked == 200
+
+
+def test_material_step_stops_a_particle_without_energy(oracle_lib):
+    geom = synth.workload_geometry(2)
+    l = 5
+    r = geom.radius[l]
+    x = np.array([r, 0.0, 0.0, 1.0 / 0.05, 0.0, math.pi / 2])        # pT = 50 MeV
+    assert oracle.material_step(geom, l, x, np.eye(6) * 1e-4, (None, 10.0), xX0=0.02) is None
+    assert oracle.material_step(geom, l, x, np.eye(6) * 1e-4, (None, 0.01), xX0=0.02) is not None
+
+
+def _pulls(geom, ts, o):
+    n = ts.hits.shape[2]
+    last = np.array([int(m).bit_length() - 1 for m in ts.hit_mask])
+    ok = (o["status"] & (oracle.ST_PROP_FAIL | oracle.ST_NEAR_TANGENT)) == 0
+    tr = ts.truth[last, :, np.arange(n)].T
+    xp, Cp = physics.project_to_surface(o["state"], oracle.unpack_cov(o["cov"]), geom.radius[last], geom.k_B)
+    return physics.pulls(xp, Cp, tr), tr, ok
+
+
+@pytest.mark.parametrize("part", ["full", "no_loss", "layer_xX0"])
+def test_material_model_pulls(oracle_lib, part):
+    geom, ts, mat = synth.material_workload(30000)
+    m = {"full": mat, "no_loss": (mat[0], 0.0), "layer_xX0": (None, mat[1])}[part]
+    o = oracle.fit(geom, ts.hits, ts.hit_mask, material=m)
+    pl, tr, ok = _pulls(geom, ts, o)
+    assert ok.mean() > 0.95
+    low = ok & (ts.pt < 1.0)
+    kq = pl[3][low] * np.sign(tr[3][low])
+    widths = [pl[p][ok].std() for p in (3, 4, 5)]
+    means = [pl[p][ok].mean() for p in (3, 4, 5)]
+    print(f"[{part}] pull means {np.round(means, 3)} widths {np.round(widths, 3)}; "
+          f"pT < 1 GeV signed kappa pull mean {kq.mean():+.3f} (n={low.sum()})")
+    if part == "full":
+        assert max(abs(v) for v in means) < 0.03
+        assert max(abs(w - 1.0) for w in widths) < 0.03
+        assert abs(kq.mean()) < 0.15
+    elif part == "no_loss":
+        assert kq.mean() < -1.0          # |kappa| underestimated where the momentum has dropped
+    else:
+        assert min(widths) > 1.08        # scattering underestimated where the map exceeds 0.02
