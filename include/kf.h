@@ -37,6 +37,7 @@ extern "C" {
 
 #define KF_MAX_LAYERS 32
 #define KF_MAX_KEEP 8
+#define KF_MAX_MAP_BINS 64
 
 /* return codes */
 #define KF_OK 0
@@ -171,6 +172,30 @@ int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold);
  * then gives the duration of the last such launch.  NULL, NULL (the default) turns it
  * off.  KF_E_INVALID for a NULL context or exactly one NULL event. */
 int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop);
+
+/* Material model of kf_fit beyond one x/X0 per layer (Sec. 3: two-dimensional
+ * arrays of radiation lengths indexed in r and z account for multiple scattering and
+ * energy loss).
+ *   xX0_map: DEVICE pointer, [n_layers][nz] float32, owned by the caller and read by
+ *     every later kf_fit until the setting changes (keep it alive and unchanged while
+ *     set).  Row l holds x/X0 at normal incidence at the centres of nz equal bins over
+ *     the layer's [-zhalf_cm[l], zhalf_cm[l]] in its own (aligned) frame; the value at
+ *     a crossing is interpolated linearly in z between the centres and held constant
+ *     beyond the outer ones.  It replaces kf_layer_params.xX0.  NULL keeps the
+ *     per-layer xX0.  1 <= nz <= KF_MAX_MAP_BINS.
+ *   eloss_gev_per_x0: mean ionisation loss of a minimum-ionising particle per
+ *     radiation length (GeV, >= 0; 0.0363 for silicon; 0 = no loss).  At each crossed
+ *     layer after the seed layer, after the scattering term, the energy drops by
+ *     eloss * x_eff / beta^2 (x_eff = x/X0 / (sin theta |cos alpha|), the scattering
+ *     term's path length; beta at the incoming momentum) at fixed direction:
+ *     kappa <- kappa p / p', and the covariance follows kappa' as a function of
+ *     (kappa, theta).  A particle left without kinetic energy stops there
+ *     (KF_ST_PROP_FAIL).  No straggling term.
+ * While a map or a nonzero loss is set, kf_find, kf_find_autotune, kf_smooth and
+ * kf_fit_backward return KF_E_UNSUPPORTED (they model one x/X0 per layer and no
+ * loss).  KF_E_INVALID for a NULL context, a negative or non-finite loss, nz out of
+ * range with a map, or a geometry with a zhalf_cm that is not positive. */
+int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float eloss_gev_per_x0);
 
 /* Launch configuration of kf_find, held by the context.  Outputs do not depend on it
  * (same bits for every valid configuration); only the time does.

@@ -31,6 +31,10 @@ struct kf_ctx {
   int grid_per_cu = 0;    // find workgroups that fit on one compute unit
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // timing hook (kf_ctx_set_launch_events)
   kf_dedup_cuts dcuts{0.05f, 2, 1, 0.1f, 0.15f, 0.03f, 0.02f, 0.5f, 0.5f, 0.1f, 0.01f, 0.02f};
+  const float* mat_map = nullptr;  // material model (kf_ctx_set_material)
+  int32_t mat_nz = 0;
+  float eloss = 0.f;
+  bool material() const { return mat_map != nullptr || eloss > 0.f; }
 };
 
 namespace {
@@ -171,6 +175,19 @@ int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop) {
   return KF_OK;
 }
 
+int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float eloss_gev_per_x0) {
+  if (!ctx || !isfinite(eloss_gev_per_x0) || eloss_gev_per_x0 < 0.f) return KF_E_INVALID;
+  if (xX0_map) {
+    if (nz < 1 || nz > KF_MAX_MAP_BINS) return KF_E_INVALID;
+    for (int l = 0; l < ctx->g.n_layers; ++l)
+      if (!(ctx->g.zhalf_cm[l] > 0.f) || !isfinite(ctx->g.zhalf_cm[l])) return KF_E_INVALID;
+  }
+  ctx->mat_map = xX0_map;
+  ctx->mat_nz = xX0_map ? nz : 0;
+  ctx->eloss = eloss_gev_per_x0;
+  return KF_OK;
+}
+
 int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg) {
   if (!ctx || !cfg || cfg->wide_window_bins < 0 || cfg->blocks_per_cu < 0 || cfg->use_graph < 0 ||
       cfg->use_graph > 1)
@@ -266,6 +283,10 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   a.align = params ? params->align : nullptr;
   a.xX0 = params ? params->xX0 : nullptr;
   for (int l = 0; l < 32; ++l) a.radius[l] = l < ctx->g.n_layers ? ctx->g.radius_cm[l] : 0.f;
+  a.mat_map = ctx->mat_map;
+  a.mat_nz = ctx->mat_nz;
+  a.eloss = ctx->eloss;
+  for (int l = 0; l < 32; ++l) a.zhalf[l] = l < ctx->g.n_layers ? ctx->g.zhalf_cm[l] : 0.f;
   a.state = out->state;
   a.cov = out->cov;
   a.chi2 = out->chi2;
@@ -281,6 +302,7 @@ namespace {
 
 int check_find(kf_ctx* ctx, const kf_find_in* in, const kf_find_out* out, void* ws, size_t ws_bytes) {
   if (!ctx || !in || !out) return KF_E_INVALID;
+  if (ctx->material()) return KF_E_UNSUPPORTED;  // the finder models one x/X0 per layer
   if (in->n_events < 0 || in->n_seeds < 0 || in->n_hits < 0) return KF_E_INVALID;
   if (in->keep < 1 || in->keep > KF_MAX_KEEP || in->max_miss < 1) return KF_E_INVALID;
   if (!(in->chi2_cut > 0.f) || !(in->nsigma > 0.f)) return KF_E_INVALID;
@@ -495,6 +517,7 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
   if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
+  if (ctx->material()) return KF_E_UNSUPPORTED;  // the adjoint differentiates the per-layer model
   if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
   if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
     return KF_E_INVALID;
@@ -537,6 +560,7 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
               const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !in || !fwd || !out) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
+  if (ctx->material()) return KF_E_UNSUPPORTED;  // the smoother's step assumes kappa is transported unchanged
   if (in->n == 0) return KF_OK;
   if (!in->hit_mask || !fwd->ndf || !fwd->status || !fwd->ckpt || !out->state || !out->cov || !out->first ||
       !out->last)

@@ -32,6 +32,7 @@ __host__ __device__ constexpr int tri(int i, int j) { return i >= j ? i * (i + 1
 struct LayerK {
   float r, cx, cy, dz, cphi, sphi, xX0;
   float moved;  // 1 if the alignment moves the layer (any of cx, cy, dz, its rotation), else 0
+  float zs, zo; // material map: fractional bin u = z * zs + zo of a z in the layer's frame
 };
 
 // Constants of the hit model and the field.
@@ -249,6 +250,57 @@ __device__ __forceinline__ void add_scattering(Trk& k, const Frame& f, float xX0
   k.C[tri(5, 5)] += th2;
   k.C[tri(3, 3)] = fmaf(kc * kc, th2, k.C[tri(3, 3)]);
   k.C[tri(5, 3)] = fmaf(-kc, th2, k.C[tri(5, 3)]);
+}
+
+// x/X0 of a layer at z (its own frame) from its row of the material map: nz values at
+// the centres of nz equal bins over [-Z, Z], interpolated linearly, constant beyond
+// the outer centres (u = (z + Z) nz / 2Z - 1/2 is the position in units of bins).
+__device__ __forceinline__ float map_xX0(const float* __restrict__ row, int nz, const LayerK& ly, float z) {
+  if (nz == 1) return row[0];
+  const float u = fminf(fmaxf(fmaf(z - ly.dz, ly.zs, ly.zo), 0.f), (float)(nz - 1));
+  const int b = min((int)u, nz - 2);
+  const float t = u - (float)b;
+  const float v0 = row[b];
+  return fmaf(t, row[b + 1] - v0, v0);
+}
+
+// Mean ionisation loss of a thin layer after its scattering (Sec. 3: energy loss from
+// the material arrays): dE = eloss * x_eff / beta^2 with the scattering term's path
+// length x_eff and beta at the incoming momentum p = 1 / (|kappa| sin theta); the
+// energy drops to E' = E - dE at fixed direction, so kappa' = kappa p / p'.  The
+// covariance follows kappa'(kappa, theta): C <- A C A^T with A = I but for the kappa
+// row (D at kappa, T at theta), where, with W = p X / p'^3 and
+// X = dE (m^2/E + E') + 2 eloss x_eff m^2 E' / p^2 (a sum of positive terms: the
+// derivative written this way does not cancel),
+//   D = dkappa'/dkappa = p/p' + W,   T = dkappa'/dtheta = kappa cot(theta) W.
+// False if the particle is left without kinetic energy.
+__device__ __forceinline__ bool energy_loss(Trk& k, const Frame& f, float xX0, float eloss, float mass2) {
+  const float kap = k.x[3];
+  const float ks = fabsf(kap) * k.st;          // 1 / p
+  const float p = rcp(ks);
+  const float c = eloss * xX0 * rcp(k.st * fabsf(f.cosa));
+  const float ib2 = fmaf(mass2, ks * ks, 1.f); // 1 / beta^2
+  const float E = p * hsqrt(ib2);
+  const float dE = c * ib2;
+  const float E1 = E - dE;
+  const float q2 = fmaf(E1, E1, -mass2);       // p'^2
+  if (!(E1 > 0.f) || !(q2 > 0.f)) return false;
+  const float ip1 = hrsqrt(q2);                // 1 / p'
+  const float X = fmaf(dE, fmaf(mass2, rcp(E), E1), 2.f * c * mass2 * E1 * ks * ks);
+  const float W = p * X * (ip1 * ip1 * ip1);
+  const float g = p * ip1;
+  const float D = g + W;
+  const float T = kap * (k.ct * rcp(k.st)) * W;
+  float* C = k.C;
+  const float c53 = C[tri(5, 3)], c55 = C[tri(5, 5)], c33 = C[tri(3, 3)];
+  C[tri(3, 0)] = fmaf(D, C[tri(3, 0)], T * C[tri(5, 0)]);
+  C[tri(3, 1)] = fmaf(D, C[tri(3, 1)], T * C[tri(5, 1)]);
+  C[tri(3, 2)] = fmaf(D, C[tri(3, 2)], T * C[tri(5, 2)]);
+  C[tri(4, 3)] = fmaf(D, C[tri(4, 3)], T * C[tri(5, 4)]);
+  C[tri(5, 3)] = fmaf(D, c53, T * c55);
+  C[tri(3, 3)] = fmaf(D * D, c33, T * fmaf(2.f * D, c53, T * c55));
+  k.x[3] = kap * g;
+  return true;
 }
 
 // What a prediction needs for every hit of a layer: the projection rows

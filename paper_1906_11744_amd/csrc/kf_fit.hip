@@ -8,10 +8,14 @@ struct Radii {
 };
 
 // Constants of layer l: radius, alignment (centre shift, z shift, cos/sin of the
-// rotation), material.  align / xX0 may be null (all zero).
+// rotation), material.  align / xX0 may be null (all zero); zhalf / nz place the
+// bins of a material map (nz = 0: none).
 __device__ __forceinline__ kfd::LayerK make_layer(int l, const float* radius, const float* __restrict__ align,
-                                                  const float* __restrict__ xX0) {
+                                                  const float* __restrict__ xX0, const float* zhalf = nullptr,
+                                                  int nz = 0) {
   kfd::LayerK k;
+  k.zs = (nz > 1) ? (float)nz / (2.f * zhalf[l]) : 0.f;
+  k.zo = 0.5f * (float)nz - 0.5f;
   k.r = radius[l];
   k.cx = align ? align[4 * l + 0] : 0.f;
   k.cy = align ? align[4 * l + 1] : 0.f;
@@ -71,7 +75,7 @@ struct GatherHits {
   }
 };
 
-template <bool kCkpt, class Src>
+template <bool kCkpt, bool kMat, class Src>
 __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __restrict__ lays, int64_t i,
                                         uint32_t mask, const Src& src) {
   const int64_t n = a.n;
@@ -122,7 +126,20 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       }
       const kfd::Frame f = kfd::frame_at(k, ly);
       if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
-      if (l > 0 && ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+      if (kMat) {  // the material map at the crossing's z and the energy loss
+        if (l > 0) {
+          const float xx = a.mat_map ? kfd::map_xX0(a.mat_map + l * a.mat_nz, a.mat_nz, ly, k.x[2]) : ly.xX0;
+          if (xx > 0.f) {
+            kfd::add_scattering(k, f, xx, a.md.mass2);
+            if (a.eloss > 0.f && !kfd::energy_loss(k, f, xx, a.eloss, a.md.mass2)) {
+              status |= kfd::ST_PROP_FAIL;
+              break;
+            }
+          }
+        }
+      } else if (l > 0 && ly.xX0 > 0.f) {
+        kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+      }
       if ((mask >> l) & 1u) {
         kfd::Pred p;
         kfd::prepare(k, f, a.md, p);
@@ -150,17 +167,19 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
 }
 
 // kCkpt: also store the state and covariance after every processed layer (a.ckpt).
+// kMat: the material model (map and energy loss) instead of one x/X0 per layer.
 // The workgroup first builds the layer constants in LDS (one lane per layer), so that
 // one kf_fit call is one kernel.
-template <bool kCkpt>
+template <bool kCkpt, bool kMat>
 __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
   __shared__ kfd::LayerK lays[32];
-  if ((int)threadIdx.x < a.nl) lays[threadIdx.x] = make_layer(threadIdx.x, a.radius, a.align, a.xX0);
+  if ((int)threadIdx.x < a.nl)
+    lays[threadIdx.x] = make_layer(threadIdx.x, a.radius, a.align, a.xX0, a.zhalf, kMat ? a.mat_nz : 0);
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   SoaHits src{a.hits, a.mask};
-  fit_one<kCkpt>(a, lays, i, a.mask[i], src);
+  fit_one<kCkpt, kMat>(a, lays, i, a.mask[i], src);
 }
 
 // Fit of each seed's best finder candidate from its own hits (slot 0 of hit_idx).
@@ -171,7 +190,7 @@ __global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __re
   uint32_t mask = 0;
   for (int l = 0; l < a.nl; ++l) mask |= (idx0[(int64_t)l * a.n + i] >= 0 ? 1u : 0u) << l;
   GatherHits src{hits, H, idx0};
-  fit_one<false>(a, a.layers, i, mask, src);
+  fit_one<false, false>(a, a.layers, i, mask, src);
 }
 
 hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream) {
@@ -181,18 +200,25 @@ hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const in
   return hipGetLastError();
 }
 
+template <bool kCkpt, bool kMat>
+void launch_fit_variant(const FitArgs& a, unsigned nb, unsigned bs, hipStream_t stream, hipEvent_t ev_start,
+                        hipEvent_t ev_stop) {
+  if (ev_start && ev_stop)  // timing hook: the events bracket the kernel's own execution
+    hipExtLaunchKernelGGL((fit_kernel<kCkpt, kMat>), dim3(nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
+  else
+    hipLaunchKernelGGL((fit_kernel<kCkpt, kMat>), dim3(nb), dim3(bs), 0, stream, a);
+}
+
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  const int bs = 256;
-  const int64_t nb = (a.n + bs - 1) / bs;
-  if (ev_start && ev_stop) {  // timing hook: the events bracket the kernel's own execution
-    if (a.ckpt)
-      hipExtLaunchKernelGGL(fit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
-    else
-      hipExtLaunchKernelGGL(fit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
-  } else if (a.ckpt) {
-    hipLaunchKernelGGL(fit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, a);
+  const unsigned bs = 256;
+  const unsigned nb = (unsigned)((a.n + bs - 1) / bs);
+  const bool mat = a.mat_map != nullptr || a.eloss > 0.f;
+  if (a.ckpt) {
+    if (mat) launch_fit_variant<true, true>(a, nb, bs, stream, ev_start, ev_stop);
+    else launch_fit_variant<true, false>(a, nb, bs, stream, ev_start, ev_stop);
   } else {
-    hipLaunchKernelGGL(fit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, a);
+    if (mat) launch_fit_variant<false, true>(a, nb, bs, stream, ev_start, ev_stop);
+    else launch_fit_variant<false, false>(a, nb, bs, stream, ev_start, ev_stop);
   }
   return hipGetLastError();
 }

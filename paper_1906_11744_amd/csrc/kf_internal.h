@@ -25,6 +25,12 @@ struct FitArgs {
   const float* align;         // computed by each fit workgroup from these (fit)
   const float* xX0;
   float radius[32];
+  // material model beyond one x/X0 per layer (fit only): map [nl][mat_nz] of x/X0 at
+  // z-bin centres over [-zhalf, zhalf] (null: xX0), mean loss per radiation length
+  const float* mat_map = nullptr;
+  int32_t mat_nz = 0;
+  float eloss = 0.f;
+  float zhalf[32] = {};
   float* state;
   float* cov;
   float* chi2;

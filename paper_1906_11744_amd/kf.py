@@ -185,6 +185,7 @@ class Context:
         _check(_lib().kf_ctx_create(C.byref(g), C.byref(h)), "kf_ctx_create")
         self._h = h
         self._ws = None
+        self._material = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -201,6 +202,22 @@ class Context:
         main kernel of each kf_fit / kf_smooth call records around its own execution;
         None, None turns the hook off."""
         _check(_lib().kf_ctx_set_launch_events(self._h, start, stop), "kf_ctx_set_launch_events")
+
+    def set_material(self, xX0_map=None, eloss=0.0):
+        """kf_ctx_set_material: xX0_map [L][nz] float32 CUDA tensor (x/X0 at the z-bin
+        centres of each layer; None keeps the per-layer xX0) and the mean ionisation
+        loss per radiation length in GeV (0: none).  The context keeps a reference to
+        the map while it is set."""
+        if xX0_map is None:
+            _check(_lib().kf_ctx_set_material(self._h, None, 0, C.c_float(float(eloss))), "kf_ctx_set_material")
+            self._material = None
+            return
+        _dev(xX0_map, torch.float32, None, "xX0_map")
+        if xX0_map.dim() != 2 or xX0_map.shape[0] != self.n_layers:
+            raise ValueError(f"xX0_map must be [{self.n_layers}][nz], got {tuple(xX0_map.shape)}")
+        _check(_lib().kf_ctx_set_material(self._h, C.c_void_p(xX0_map.data_ptr()), int(xX0_map.shape[1]),
+                                          C.c_float(float(eloss))), "kf_ctx_set_material")
+        self._material = xX0_map
 
     def set_find_config(self, wide_window_bins=None, blocks_per_cu=None, use_graph=None):
         """kf_ctx_set_find_config; fields left None keep their current value."""
@@ -436,7 +453,7 @@ class Context:
 def exported_symbols():
     """Names the header declares (for the load check)."""
     return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_ctx_set_launch_events",
-            "kf_ctx_set_find_config",
+            "kf_ctx_set_material", "kf_ctx_set_find_config",
             "kf_ctx_get_find_config", "kf_workspace_size", "kf_fit", "kf_find", "kf_find_autotune",
             "kf_smooth", "kf_fit_backward", "kf_ctx_set_dedup_cuts", "kf_ctx_get_dedup_cuts", "kf_clean_seeds",
             "kf_remove_duplicates", "kf_strerror"]

@@ -159,3 +159,36 @@ def test_dedup_calls_reject_bad_arguments_before_launch():
     fin = kf.FindIn(64, None, 0, None, 100000, None, None, 0.0, 0.0, 1, 1, 0)
     assert lib.kf_workspace_size(ctx._h, kf.KF_OP_CLEAN_SEEDS, C.byref(fin), C.byref(nb)) == 0
     assert nb.value > small + 100000 * 40
+
+
+def test_material_setting_validation_and_the_calls_it_excludes():
+    """kf_ctx_set_material stores its arguments (no device work here); while a map or
+    a loss is set, the finder, the smoother and the adjoint refuse before launching,
+    and clearing the setting lets their own validation run again."""
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    fake = C.c_void_p(0x1000)   # never dereferenced: no kf_fit is called here
+    assert lib.kf_ctx_set_material(None, None, 0, C.c_float(0.0)) == -1
+    assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(-1.0)) == -1
+    assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(float("nan"))) == -1
+    assert lib.kf_ctx_set_material(ctx._h, fake, 0, C.c_float(0.0)) == -1
+    assert lib.kf_ctx_set_material(ctx._h, fake, 65, C.c_float(0.0)) == -1
+    fin = kf.FindIn(1, fake, 100, fake, 10, fake, fake, 30.0, 3.0, 6, 3, 0)
+    fo = kf.FindOut(*([fake] * 13))
+    p = kf.LayerParams()
+    fit_in = kf.FitIn(10, fake, fake, None, None, 1)
+    fit_out = kf.FitOut(fake, fake, fake, fake, fake, fake)
+    so = kf.SmoothOut(fake, fake, fake, fake)
+
+    def codes():
+        return (lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None),
+                lib.kf_smooth(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), C.byref(so), None, 0, None),
+                lib.kf_fit_backward(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), fake, fake, fake,
+                                    None, 0, None))
+    # without a material setting each call stops at its missing workspace instead
+    assert codes() == (-3, -3, -3)
+    for args in ((fake, 1, 0.0), (fake, 64, 0.0363), (None, 0, 0.0363)):
+        assert lib.kf_ctx_set_material(ctx._h, args[0], args[1], C.c_float(args[2])) == 0
+        assert codes() == (-2, -2, -2), args
+    assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
+    assert codes() == (-3, -3, -3)
