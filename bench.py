@@ -46,18 +46,18 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6  # the same without packed FP32 (64 FMA lanes p
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of one fit_kernel launch on the 1e6-track workload, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean of 9 launches), each scaled by
+# runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean over every launch of the run), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "e986ef33b68ffe1a", "tracks": 1_000_000,
-               "fetch_kib": 102018.9, "write_kib": 117187.5,
+FIT_TRAFFIC = {"sources": "6db829028da8a411", "tracks": 1_000_000,
+               "fetch_kib": 101933.0, "write_kib": 117187.5,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
 
-# The same for one smooth_kernel launch on that workload (mean of 7 launches).
-SMOOTH_TRAFFIC = {"sources": "c0f00b368f3292a3", "tracks": 1_000_000,
-                  "fetch_kib": 906638.5, "write_kib": 1800781.2,
+# The same for one smooth_kernel launch on that workload.
+SMOOTH_TRAFFIC = {"sources": "1974d8e7b6eb5506", "tracks": 1_000_000,
+                  "fetch_kib": 907275.0, "write_kib": 1800781.3,
                   "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 SMOOTH_SOURCES = ("paper_1906_11744_amd/csrc/kf_smooth.hip", "paper_1906_11744_amd/csrc/kf_smooth.h",
                   "paper_1906_11744_amd/csrc/kf_adjoint.h")
@@ -309,8 +309,53 @@ def bench_grad(steps, warmup):
     w = torch.ones(ts.hits.shape[2], dtype=torch.float32, device=dev)
     t_f, _, _ = _time_launches(lambda: kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True, out=fwd), steps, warmup)
     t_b, _, _ = _time_launches(lambda: kf.fit_backward(hits, mask, fwd, w, align=al, xX0=xX0), steps, warmup)
-    return {"tracks": int(ts.hits.shape[2]), "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
-            "backward_over_forward": t_b / t_f}
+    n = int(ts.hits.shape[2])
+    ndf = fwd["ndf"].cpu().numpy()
+    status = fwd["status"].cpu().numpy().view(np.uint32)
+    n_steps = int(np.where(status & 16, 0, (ndf + 5) // 2).sum())
+    # bytes each must move: the forward reads 12 B of hit per step and the mask, writes
+    # the outputs (120 B per track) and a 27-float checkpoint per step; the adjoint
+    # reads the checkpoint and the hit of every step and 16 B per track (mask, status,
+    # ndf, dLoss/dchi2); its gradient output is negligible
+    b_f = 120.0 * n_steps + 124.0 * n
+    b_b = 120.0 * n_steps + 16.0 * n
+    return {"tracks": n, "kalman_steps": n_steps, "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
+            "backward_over_forward": t_b / t_f,
+            "forward_algorithmic_bytes": b_f, "forward_GB_per_s": b_f / t_f / 1e9,
+            "backward_algorithmic_bytes": b_b, "backward_GB_per_s": b_b / t_b / 1e9}
+
+
+def bench_material(steps, warmup):
+    """The fit with the material model (kf_ctx_set_material): 1e6 tracks simulated
+    through a 16-bin x/X0 map per layer with the mean energy loss of silicon, fitted
+    with that model; the same tracks fitted with one x/X0 per layer for comparison."""
+    import torch
+
+    import synth
+    from paper_1906_11744_amd import Context
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    geom, ts, (xmap, eloss) = synth.material_workload(1_000_000)
+    print(f"# generated 1e6 tracks through the material map in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = Context(geom)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    hits, mask = t(ts.hits), t(ts.hit_mask.view(np.int32))
+    xX0 = t(geom.xX0.astype(np.float32))
+    dmap = t(xmap.astype(np.float32))
+    ctx.set_material(dmap, eloss)
+    out = ctx.fit(hits, mask, xX0=xX0)
+    ndf = out["ndf"].cpu().numpy()
+    status = out["status"].cpu().numpy().view(np.uint32)
+    n_steps = int(np.where(status & 16, 0, (ndf + 5) // 2).sum())
+    fn = lambda: ctx.fit(hits, mask, xX0=xX0, out=out)
+    tm = _time_launches(fn, steps, warmup)
+    t_k = _time_kernel(ctx, fn, steps, warmup)
+    ctx.set_material(None, 0.0)
+    t_k0 = _time_kernel(ctx, fn, steps, warmup)
+    return {"tracks": int(ts.hits.shape[2]), "kalman_steps": n_steps, "map_bins": int(xmap.shape[1]),
+            "eloss_gev_per_x0": eloss, "steps_per_s": n_steps / tm.wall, "ms_per_call": tm.wall * 1e3,
+            "kernel_ms": t_k * 1e3, "kernel_ms_one_xX0_per_layer": t_k0 * 1e3,
+            "material_cost_ratio": t_k / t_k0}
 
 
 def bench_smooth(steps, warmup, n_tracks):
@@ -427,7 +472,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "cpu_scaling", "copy"],
+    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "material", "cpu_scaling", "copy"],
                     default="all")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -522,6 +567,8 @@ def main():
         res["smooth"] = bench_smooth(args.steps, args.warmup, args.tracks)
     if args.only in ("all", "dedup"):
         res["dedup"] = bench_dedup(args.steps, args.warmup)
+    if args.only in ("all", "material"):
+        res["material"] = bench_material(args.steps, args.warmup)
     if args.only in ("all", "cpu_scaling") and not args.no_cpu_baseline:
         res["cpu_finder_scaling"] = cpu_scaling()
     print(json.dumps(res), flush=True)
