@@ -220,14 +220,17 @@ def seed(geom, m0, m1, m2):
     return st, cv.reshape(6, 6)
 
 
-def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, records=False, material=None):
+def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, records=False, material=None,
+        field=None):
     """Batched FP64 fit; seeds from hits 0-2 unless seed_state/seed_cov are given.
 
     hits [L][3][n] float32 (float64 hits select the float64-input entry), mask [n]
     uint32.  Returns a dict of float64 outputs; records=True adds records [n][L][27],
     the state and packed covariance after each processed layer (NaN beyond).
     material = (xX0_map [L][nz] or None, eloss GeV per X0): the material model of
-    Sec. 3 (float32 hits only), see material_step.
+    Sec. 3, see material_step.  field = (c_r, c_z): the field B_z(r, z) =
+    B (1 + c_r r^2 + c_z z^2) (cm), each step the helix of the field at its start and the
+    seed's curvature converted with the field at hit 0.
     """
     dt = np.float64 if np.asarray(hits).dtype == np.float64 else np.float32
     hits = np.ascontiguousarray(hits, dt)
@@ -241,15 +244,17 @@ def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, 
     rec = np.zeros((n, L, 27)) if records else None
     g = ogeom(geom)
     xx = geom.xX0 if xX0 is None else xX0
-    if material is not None:
-        if dt != np.float32:
-            raise TypeError("the material model takes float32 hits")
+    if material is not None or field is not None:
+        material = (None, 0.0) if material is None else material
+        field = (0.0, 0.0) if field is None else field
         xmap = None if material[0] is None else np.ascontiguousarray(material[0], np.float64)
         nz = 0 if xmap is None else int(xmap.shape[1])
-        load().oracle_fit_material(C.byref(g), _p(_f64(align)), _p(_f64(xx)), _p(xmap), C.c_int(nz),
-                                   C.c_double(float(material[1])), C.c_int64(n), _p(hits), _p(mask),
-                                   int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]),
-                                   _p(out["chi2"]), _p(out["ndf"]), _p(out["status"]), _p(rec))
+        fn = load().oracle_fit_model_f64 if dt == np.float64 else load().oracle_fit_model
+        fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), _p(xmap), C.c_int(nz),
+                                C.c_double(float(material[1])), C.c_double(float(field[0])),
+                                C.c_double(float(field[1])), C.c_int64(n), _p(hits), _p(mask),
+                                int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]),
+                                _p(out["chi2"]), _p(out["ndf"]), _p(out["status"]), _p(rec))
     else:
         fn = load().oracle_fit_f64 if dt == np.float64 else load().oracle_fit
         fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(hits), _p(mask),

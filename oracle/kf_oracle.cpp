@@ -38,7 +38,9 @@
 // second order, smoothed pulls have unit scale and C_s <= C_f; a material map of
 // constant rows without energy loss is the per-layer model bit for bit, one material
 // step matches its definition (covariance row by central differences), and tracks
-// simulated through the map with energy loss give unit pulls.  Parity unpinned: the candidate score
+// simulated through the map with energy loss give unit pulls; a field with zero
+// coefficients is the uniform one bit for bit, noiseless tracks in a non-uniform field
+// return the generating state, and its pulls have unit scale.  Parity unpinned: the candidate score
 // and its tie rule, and the Highland variant, which are conventions.
 
 #include <omp.h>
@@ -155,7 +157,16 @@ struct Geo {
   const double* map = nullptr;
   int map_nz = 0;
   double eloss = 0.0;
+  // Parameterised field (Sec. 3): B_z(r, z) = B (1 + fr r^2 + fz z^2), cm, global frame;
+  // each step is the helix of the field at its starting point.
+  double fr = 0.0, fz = 0.0;
 };
+
+// k_B of the field at (x, y, z).
+double kB_at(const Geo& g, double x, double y, double z) {
+  if (g.fr == 0.0 && g.fz == 0.0) return g.kB;
+  return g.kB * (1.0 + g.fr * (x * x + y * y) + g.fz * z * z);
+}
 
 Geo make_geo(const OGeom* g) {
   Geo o;
@@ -582,11 +593,12 @@ bool update_with_hit(const Geo& g, const Layer<T>& ly, Track<T>& tk, const T m[3
 template <class T>
 bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nullptr) {
   T s;
-  if (!crossing_arc(tk.x, ly.cx, ly.cy, ly.r, g.kB, s)) { tk.status |= ST_PROP_FAIL; return false; }
+  const double kB = kB_at(g, val(tk.x[0]), val(tk.x[1]), val(tk.x[2]));  // the field at the step's start
+  if (!crossing_arc(tk.x, ly.cx, ly.cy, ly.r, kB, s)) { tk.status |= ST_PROP_FAIL; return false; }
   T xe[6];
-  helix_at(tk.x, s, g.kB, xe);
+  helix_at(tk.x, s, kB, xe);
   T J[6][6];
-  transport_jacobian(tk.x, xe, s, g.kB, J);
+  transport_jacobian(tk.x, xe, s, kB, J);
   if (J_out)
     for (int i = 0; i < 6; ++i)
       for (int j = 0; j < 6; ++j) J_out[i][j] = J[i][j];
@@ -611,7 +623,8 @@ bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nul
 }
 
 // Three-hit helix seed at hit 0 (signed Menger curvature, chord angles), with the
-// diagonal prior covariance inflated ten times in variance.
+// diagonal prior covariance inflated ten times in variance.  Curvature is turned into
+// kappa with the field at hit 0.
 template <class T>
 void seed_from_hits(const Geo& g, const T m0[3], const T m1[3], const T m2[3], Track<T>& tk) {
   using std::asin; using std::atan2; using std::sqrt;
@@ -631,12 +644,13 @@ void seed_from_hits(const Geo& g, const T m0[3], const T m1[3], const T m2[3], T
   else s02 = lc * asin(qc) / qc;
   T theta = atan2(s02, m2[2] - m0[2]);
   tk.x[0] = m0[0]; tk.x[1] = m0[1]; tk.x[2] = m0[2];
-  tk.x[3] = -w / g.kB;
+  const double kB0 = kB_at(g, val(m0[0]), val(m0[1]), val(m0[2]));
+  tk.x[3] = -w / kB0;
   tk.x[4] = wrap_pi(phi0);
   tk.x[5] = theta;
   double dr = g.radius[2] - g.radius[0];
   double sphi = std::sqrt(2.0) * g.srphi / dr, sth = std::sqrt(2.0) * g.sz / dr;
-  double skap = 8.0 * std::sqrt(1.5) * g.srphi / (dr * dr * g.kB);
+  double skap = 8.0 * std::sqrt(1.5) * g.srphi / (dr * dr * kB0);
   double d[6] = {g.srphi * g.srphi, g.srphi * g.srphi, g.sz * g.sz, skap * skap, sphi * sphi, sth * sth};
   for (int i = 0; i < 6; ++i)
     for (int j = 0; j < 6; ++j) tk.C[i][j] = T(i == j ? 10.0 * d[i] : 0.0);
@@ -802,11 +816,14 @@ template <class HT>
 void fit_batch(const OGeom* og, const double* align, const double* xX0, int64_t n, const HT* hits,
                const uint32_t* mask, int seed_from_hits_flag, const HT* seed_state, const HT* seed_cov,
                double* state, double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec,
-               const double* map = nullptr, int map_nz = 0, double eloss = 0.0) {
+               const double* map = nullptr, int map_nz = 0, double eloss = 0.0, double fr = 0.0,
+               double fz = 0.0) {
   Geo g = make_geo(og);
   g.map = map;
   g.map_nz = map_nz;
   g.eloss = eloss;
+  g.fr = fr;
+  g.fz = fz;
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
 #pragma omp parallel for schedule(static)
@@ -836,14 +853,24 @@ void oracle_fit(const OGeom* og, const double* align, const double* xX0, int64_t
                    status, rec);
 }
 
-// As oracle_fit with the material model of Sec. 3: map [L][map_nz] of x/X0 (null: the
-// per-layer xX0) and the mean ionisation loss per radiation length eloss (0: none).
-void oracle_fit_material(const OGeom* og, const double* align, const double* xX0, const double* map, int map_nz,
-                         double eloss, int64_t n, const float* hits, const uint32_t* mask, int seed_from_hits_flag,
-                         const float* seed_state, const float* seed_cov, double* state, double* cov, double* chi2,
-                         int32_t* ndf, uint32_t* status, double* rec) {
+// As oracle_fit with the detector model of Sec. 3: map [L][map_nz] of x/X0 (null: the
+// per-layer xX0), the mean ionisation loss per radiation length eloss (0: none) and
+// the field B_z(r, z) = B (1 + fr r^2 + fz z^2) (0, 0: uniform).
+void oracle_fit_model(const OGeom* og, const double* align, const double* xX0, const double* map, int map_nz,
+                      double eloss, double fr, double fz, int64_t n, const float* hits, const uint32_t* mask,
+                      int seed_from_hits_flag, const float* seed_state, const float* seed_cov, double* state,
+                      double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec) {
   fit_batch<float>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, state, cov, chi2, ndf,
-                   status, rec, map, map_nz, eloss);
+                   status, rec, map, map_nz, eloss, fr, fz);
+}
+
+// The same with float64 hits and seeds (noiseless checks finer than float32).
+void oracle_fit_model_f64(const OGeom* og, const double* align, const double* xX0, const double* map, int map_nz,
+                          double eloss, double fr, double fz, int64_t n, const double* hits, const uint32_t* mask,
+                          int seed_from_hits_flag, const double* seed_state, const double* seed_cov, double* state,
+                          double* cov, double* chi2, int32_t* ndf, uint32_t* status, double* rec) {
+  fit_batch<double>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, state, cov, chi2, ndf,
+                    status, rec, map, map_nz, eloss, fr, fz);
 }
 
 // One material step on a state at its crossing with layer l (align [4] and xX0 of

@@ -191,7 +191,7 @@ class TrackSample:
 
 def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max=1.0,
              align=None, smear=True, scatter=True, keep_truth=True, particles=None,
-             hit_dtype=np.float32, material=None):
+             hit_dtype=np.float32, material=None, field=None):
     """Simulate n prompt tracks through every layer in turn.
 
     At each layer: exact crossing (first_crossing), record the unsmeared point,
@@ -203,7 +203,10 @@ def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max
     interpolated at the crossing's z (material_at), and after the kick the energy
     drops by the mean ionisation loss eloss * x_eff / beta^2 (x_eff the same path
     length, beta at the incoming momentum); a particle left without kinetic energy
-    stops.  A track that cannot reach a layer stops there; later layers have no hit.
+    stops.  With field = (c_r, c_z) the field is B_z(r, z) = B (1 + c_r r^2 + c_z z^2)
+    (cm, global frame) and each step from one layer to the next is the helix of the
+    field at the step's starting point.  A track that cannot reach a layer stops there;
+    later layers have no hit.
     """
     L = geom.n_layers
     if particles is None:
@@ -229,7 +232,10 @@ def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max
     for l in range(L):
         dx, dy, dz, dphi = align[l]
         r = geom.radius[l]
-        omega = -kB * kappa
+        if field is None:
+            omega = -kB * kappa
+        else:
+            omega = -kB * (1.0 + field[0] * (x * x + y * y) + field[1] * z * z) * kappa
         s, qx, qy = first_crossing(x, y, phi, omega, dx, dy, r)
         reach = alive & np.isfinite(s)
         alive = reach
@@ -337,6 +343,20 @@ def material_workload(n: int = 100_000, event: int = 0, nz: int = 16, eloss: flo
     xmap = material_map(geom, nz)
     ts = simulate(geom, rng_for(7, event), n, (0.5, 50.0), True, 1.5, material=(xmap, eloss))
     return geom, ts, (xmap, eloss)
+
+
+# A solenoid-like field falling off away from the centre: 1.2% lower at r = 110 cm and
+# 16% lower at |z| = 200 cm (coefficients of B_z(r, z) = B (1 + c_r r^2 + c_z z^2), cm^-2).
+FIELD_SOLENOID = (-1.0e-6, -4.0e-6)
+
+
+def field_workload(n: int = 100_000, event: int = 0, field=FIELD_SOLENOID, material=True):
+    """The 17-layer fit workload in the field B_z(r, z) (and, with material=True, through
+    the material map with silicon's energy loss): returns (geom, ts, field, material or None)."""
+    geom = workload_geometry(2)
+    mat = (material_map(geom, 16), ELOSS_SI_GEV_PER_X0) if material else None
+    ts = simulate(geom, rng_for(9, event), n, (0.5, 50.0), True, 1.5, material=mat, field=field)
+    return geom, ts, field, mat
 
 
 # --------------------------------------------------------------------------------------
