@@ -197,6 +197,19 @@ int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop);
  * range with a map, or a geometry with a zhalf_cm that is not positive. */
 int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float eloss_gev_per_x0);
 
+/* Parameterised magnetic field of kf_fit (Sec. 3: a constant or parameterised field):
+ * B_z(r, z) = B_tesla (1 + c_r r^2 + c_z z^2), r = sqrt(x^2 + y^2) and z in cm in the
+ * global frame (coefficients in cm^-2).  Each step from one layer to the next is the
+ * helix of the field at the step's starting point (the filtered position on the
+ * previous layer): its crossing and its transport Jacobian use that field, which the
+ * Jacobian treats as constant over the step.  A seed built from hits converts the
+ * three-hit curvature into kappa with the field at hit 0.  0, 0 (the default) is the
+ * uniform field.  While either coefficient is nonzero, kf_find, kf_find_autotune,
+ * kf_smooth and kf_fit_backward return KF_E_UNSUPPORTED, as with a material model.
+ * KF_E_INVALID for a NULL context or a non-finite coefficient; KF_E_UNSUPPORTED for a
+ * nonzero coefficient when B_tesla is 0. */
+int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z);
+
 /* Launch configuration of kf_find, held by the context.  Outputs do not depend on it
  * (same bits for every valid configuration); only the time does.
  *   wide_window_bins: a candidate whose search window overlaps more than this many

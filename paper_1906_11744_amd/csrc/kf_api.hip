@@ -34,7 +34,9 @@ struct kf_ctx {
   const float* mat_map = nullptr;  // material model (kf_ctx_set_material)
   int32_t mat_nz = 0;
   float eloss = 0.f;
-  bool material() const { return mat_map != nullptr || eloss > 0.f; }
+  float fr = 0.f, fz = 0.f;        // parameterised field (kf_ctx_set_field)
+  // the detector model beyond one x/X0 per layer and a uniform field: the fit only
+  bool material() const { return mat_map != nullptr || eloss > 0.f || fr != 0.f || fz != 0.f; }
 };
 
 namespace {
@@ -188,6 +190,14 @@ int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float elo
   return KF_OK;
 }
 
+int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z) {
+  if (!ctx || !isfinite(c_r) || !isfinite(c_z)) return KF_E_INVALID;
+  if (!(ctx->g.B_tesla != 0.f) && (c_r != 0.f || c_z != 0.f)) return KF_E_UNSUPPORTED;
+  ctx->fr = c_r;
+  ctx->fz = c_z;
+  return KF_OK;
+}
+
 int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg) {
   if (!ctx || !cfg || cfg->wide_window_bins < 0 || cfg->blocks_per_cu < 0 || cfg->use_graph < 0 ||
       cfg->use_graph > 1)
@@ -286,6 +296,8 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   a.mat_map = ctx->mat_map;
   a.mat_nz = ctx->mat_nz;
   a.eloss = ctx->eloss;
+  a.fr = ctx->fr;
+  a.fz = ctx->fz;
   for (int l = 0; l < 32; ++l) a.zhalf[l] = l < ctx->g.n_layers ? ctx->g.zhalf_cm[l] : 0.f;
   a.state = out->state;
   a.cov = out->cov;
@@ -302,7 +314,7 @@ namespace {
 
 int check_find(kf_ctx* ctx, const kf_find_in* in, const kf_find_out* out, void* ws, size_t ws_bytes) {
   if (!ctx || !in || !out) return KF_E_INVALID;
-  if (ctx->material()) return KF_E_UNSUPPORTED;  // the finder models one x/X0 per layer
+  if (ctx->material()) return KF_E_UNSUPPORTED;  // the finder models one x/X0 per layer, a uniform field
   if (in->n_events < 0 || in->n_seeds < 0 || in->n_hits < 0) return KF_E_INVALID;
   if (in->keep < 1 || in->keep > KF_MAX_KEEP || in->max_miss < 1) return KF_E_INVALID;
   if (!(in->chi2_cut > 0.f) || !(in->nsigma > 0.f)) return KF_E_INVALID;
@@ -517,7 +529,7 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
   if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
-  if (ctx->material()) return KF_E_UNSUPPORTED;  // the adjoint differentiates the per-layer model
+  if (ctx->material()) return KF_E_UNSUPPORTED;  // the adjoint differentiates the per-layer, uniform-field model
   if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
   if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
     return KF_E_INVALID;

@@ -75,7 +75,13 @@ struct GatherHits {
   }
 };
 
-template <bool kCkpt, bool kMat, class Src>
+// k_B of the parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2) at (x, y, z); exactly
+// the uniform k_B when both coefficients are zero.
+__device__ __forceinline__ float field_kB(const FitArgs& a, float x, float y, float z) {
+  return a.md.kB * fmaf(a.fz, z * z, fmaf(a.fr, fmaf(x, x, y * y), 1.f));
+}
+
+template <bool kCkpt, bool kModel, class Src>
 __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __restrict__ lays, int64_t i,
                                         uint32_t mask, const Src& src) {
   const int64_t n = a.n;
@@ -103,7 +109,9 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       float m1x, m1y, m1z, m2x, m2y, m2z;
       hit(1, m1x, m1y, m1z);
       hit(2, m2x, m2y, m2z);
-      kfd::seed_from_three(k, a.md, m0x, m0y, m0z, m1x, m1y, m2x, m2y, m2z, a.srphi, a.sz);
+      kfd::Model md0 = a.md;
+      if (kModel) md0.kB = field_kB(a, m0x, m0y, m0z);  // curvature to kappa in the field at hit 0
+      kfd::seed_from_three(k, md0, m0x, m0y, m0z, m1x, m1y, m2x, m2y, m2z, a.srphi, a.sz);
     } else {
 #pragma unroll
       for (int q = 0; q < 6; ++q) k.x[q] = a.seed_state[q * n + i];
@@ -117,16 +125,18 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
     for (int l = 0; l <= last; ++l) {
       const kfd::LayerK ly = lays[l];
       if (l > 0) {
+        // the step is the helix of the field at its starting point
+        const float kB = kModel ? field_kB(a, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2]) : a.md.kB;
         kfd::Step st;
-        if (!kfd::crossing(k, ly, a.md.kB, st)) {
+        if (!kfd::crossing(k, ly, kB, st)) {
           status |= kfd::ST_PROP_FAIL;
           break;
         }
-        kfd::transport(k, st, a.md.kB);
+        kfd::transport(k, st, kB);
       }
       const kfd::Frame f = kfd::frame_at(k, ly);
       if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
-      if (kMat) {  // the material map at the crossing's z and the energy loss
+      if (kModel) {  // the material map at the crossing's z and the energy loss
         if (l > 0) {
           const float xx = a.mat_map ? kfd::map_xX0(a.mat_map + l * a.mat_nz, a.mat_nz, ly, k.x[2]) : ly.xX0;
           if (xx > 0.f) {
@@ -167,19 +177,20 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
 }
 
 // kCkpt: also store the state and covariance after every processed layer (a.ckpt).
-// kMat: the material model (map and energy loss) instead of one x/X0 per layer.
+// kModel: the detector model (material map, energy loss, parameterised field) instead of
+// one x/X0 per layer and a uniform field.
 // The workgroup first builds the layer constants in LDS (one lane per layer), so that
 // one kf_fit call is one kernel.
-template <bool kCkpt, bool kMat>
+template <bool kCkpt, bool kModel>
 __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
   __shared__ kfd::LayerK lays[32];
   if ((int)threadIdx.x < a.nl)
-    lays[threadIdx.x] = make_layer(threadIdx.x, a.radius, a.align, a.xX0, a.zhalf, kMat ? a.mat_nz : 0);
+    lays[threadIdx.x] = make_layer(threadIdx.x, a.radius, a.align, a.xX0, a.zhalf, kModel ? a.mat_nz : 0);
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   SoaHits src{a.hits, a.mask};
-  fit_one<kCkpt, kMat>(a, lays, i, a.mask[i], src);
+  fit_one<kCkpt, kModel>(a, lays, i, a.mask[i], src);
 }
 
 // Fit of each seed's best finder candidate from its own hits (slot 0 of hit_idx).
@@ -200,19 +211,19 @@ hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const in
   return hipGetLastError();
 }
 
-template <bool kCkpt, bool kMat>
+template <bool kCkpt, bool kModel>
 void launch_fit_variant(const FitArgs& a, unsigned nb, unsigned bs, hipStream_t stream, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
   if (ev_start && ev_stop)  // timing hook: the events bracket the kernel's own execution
-    hipExtLaunchKernelGGL((fit_kernel<kCkpt, kMat>), dim3(nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
+    hipExtLaunchKernelGGL((fit_kernel<kCkpt, kModel>), dim3(nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
   else
-    hipLaunchKernelGGL((fit_kernel<kCkpt, kMat>), dim3(nb), dim3(bs), 0, stream, a);
+    hipLaunchKernelGGL((fit_kernel<kCkpt, kModel>), dim3(nb), dim3(bs), 0, stream, a);
 }
 
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const unsigned bs = 256;
   const unsigned nb = (unsigned)((a.n + bs - 1) / bs);
-  const bool mat = a.mat_map != nullptr || a.eloss > 0.f;
+  const bool mat = a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f;
   if (a.ckpt) {
     if (mat) launch_fit_variant<true, true>(a, nb, bs, stream, ev_start, ev_stop);
     else launch_fit_variant<true, false>(a, nb, bs, stream, ev_start, ev_stop);

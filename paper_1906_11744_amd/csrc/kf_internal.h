@@ -25,12 +25,14 @@ struct FitArgs {
   const float* align;         // computed by each fit workgroup from these (fit)
   const float* xX0;
   float radius[32];
-  // material model beyond one x/X0 per layer (fit only): map [nl][mat_nz] of x/X0 at
+  // detector model beyond one x/X0 per layer and a uniform field (fit only): map [nl][mat_nz] of x/X0 at
   // z-bin centres over [-zhalf, zhalf] (null: xX0), mean loss per radiation length
   const float* mat_map = nullptr;
   int32_t mat_nz = 0;
   float eloss = 0.f;
   float zhalf[32] = {};
+  // parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2) (fit only; 0, 0: uniform)
+  float fr = 0.f, fz = 0.f;
   float* state;
   float* cov;
   float* chi2;

@@ -219,6 +219,11 @@ class Context:
                                           C.c_float(float(eloss))), "kf_ctx_set_material")
         self._material = xX0_map
 
+    def set_field(self, c_r=0.0, c_z=0.0):
+        """kf_ctx_set_field: B_z(r, z) = B (1 + c_r r^2 + c_z z^2) (cm^-2); 0, 0 is the
+        uniform field."""
+        _check(_lib().kf_ctx_set_field(self._h, C.c_float(float(c_r)), C.c_float(float(c_z))), "kf_ctx_set_field")
+
     def set_find_config(self, wide_window_bins=None, blocks_per_cu=None, use_graph=None):
         """kf_ctx_set_find_config; fields left None keep their current value."""
         cfg = self.find_config()
@@ -453,7 +458,7 @@ class Context:
 def exported_symbols():
     """Names the header declares (for the load check)."""
     return ["kf_ctx_create", "kf_ctx_destroy", "kf_ctx_set_fallback_threshold", "kf_ctx_set_launch_events",
-            "kf_ctx_set_material", "kf_ctx_set_find_config",
+            "kf_ctx_set_material", "kf_ctx_set_field", "kf_ctx_set_find_config",
             "kf_ctx_get_find_config", "kf_workspace_size", "kf_fit", "kf_find", "kf_find_autotune",
             "kf_smooth", "kf_fit_backward", "kf_ctx_set_dedup_cuts", "kf_ctx_get_dedup_cuts", "kf_clean_seeds",
             "kf_remove_duplicates", "kf_strerror"]

@@ -192,3 +192,25 @@ def test_material_setting_validation_and_the_calls_it_excludes():
         assert codes() == (-2, -2, -2), args
     assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
     assert codes() == (-3, -3, -3)
+
+
+def test_field_setting_validation_and_the_calls_it_excludes():
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    assert lib.kf_ctx_set_field(None, C.c_float(0.0), C.c_float(0.0)) == -1
+    assert lib.kf_ctx_set_field(ctx._h, C.c_float(float("inf")), C.c_float(0.0)) == -1
+    assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(float("nan"))) == -1
+    fake = C.c_void_p(0x1000)
+    fin = kf.FindIn(1, fake, 100, fake, 10, fake, fake, 30.0, 3.0, 6, 3, 0)
+    fo = kf.FindOut(*([fake] * 13))
+    p = kf.LayerParams()
+    assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -3
+    assert lib.kf_ctx_set_field(ctx._h, C.c_float(-1e-6), C.c_float(-4e-6)) == 0
+    assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -2
+    assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(0.0)) == 0
+    assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -3
+    g0 = synth.workload_geometry(2)
+    g0.B = 0.0
+    ctx0 = kf.Context(g0)
+    assert lib.kf_ctx_set_field(ctx0._h, C.c_float(0.0), C.c_float(-4e-6)) == -2
+    assert lib.kf_ctx_set_field(ctx0._h, C.c_float(0.0), C.c_float(0.0)) == 0
