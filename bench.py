@@ -326,36 +326,42 @@ def bench_grad(steps, warmup):
 
 
 def bench_material(steps, warmup):
-    """The fit with the material model (kf_ctx_set_material): 1e6 tracks simulated
-    through a 16-bin x/X0 map per layer with the mean energy loss of silicon, fitted
-    with that model; the same tracks fitted with one x/X0 per layer for comparison."""
+    """The fit with the detector model of Sec. 3: 1e6 tracks simulated through a 16-bin
+    x/X0 map per layer with the mean energy loss of silicon, in the field B_z(r, z),
+    fitted with the whole model (kf_ctx_set_material + kf_ctx_set_field); the same
+    tracks fitted with the material model alone and with one x/X0 per layer in a
+    uniform field, for the cost of each part."""
     import torch
 
     import synth
     from paper_1906_11744_amd import Context
     dev = torch.device("cuda:0")
     t0 = time.time()
-    geom, ts, (xmap, eloss) = synth.material_workload(1_000_000)
-    print(f"# generated 1e6 tracks through the material map in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    geom, ts, fld, (xmap, eloss) = synth.field_workload(1_000_000, material=True)
+    print(f"# generated 1e6 tracks through the material map and field in {time.time() - t0:.1f} s", file=sys.stderr,
+          flush=True)
     ctx = Context(geom)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     hits, mask = t(ts.hits), t(ts.hit_mask.view(np.int32))
     xX0 = t(geom.xX0.astype(np.float32))
     dmap = t(xmap.astype(np.float32))
     ctx.set_material(dmap, eloss)
+    ctx.set_field(*fld)
     out = ctx.fit(hits, mask, xX0=xX0)
     ndf = out["ndf"].cpu().numpy()
     status = out["status"].cpu().numpy().view(np.uint32)
     n_steps = int(np.where(status & 16, 0, (ndf + 5) // 2).sum())
     fn = lambda: ctx.fit(hits, mask, xX0=xX0, out=out)
     tm = _time_launches(fn, steps, warmup)
-    t_k = _time_kernel(ctx, fn, steps, warmup)
+    t_full = _time_kernel(ctx, fn, steps, warmup)
+    ctx.set_field(0.0, 0.0)
+    t_mat = _time_kernel(ctx, fn, steps, warmup)
     ctx.set_material(None, 0.0)
-    t_k0 = _time_kernel(ctx, fn, steps, warmup)
+    t_plain = _time_kernel(ctx, fn, steps, warmup)
     return {"tracks": int(ts.hits.shape[2]), "kalman_steps": n_steps, "map_bins": int(xmap.shape[1]),
-            "eloss_gev_per_x0": eloss, "steps_per_s": n_steps / tm.wall, "ms_per_call": tm.wall * 1e3,
-            "kernel_ms": t_k * 1e3, "kernel_ms_one_xX0_per_layer": t_k0 * 1e3,
-            "material_cost_ratio": t_k / t_k0}
+            "eloss_gev_per_x0": eloss, "field_c_r_c_z": list(fld), "steps_per_s": n_steps / tm.wall,
+            "ms_per_call": tm.wall * 1e3, "kernel_ms": t_full * 1e3, "kernel_ms_material_only": t_mat * 1e3,
+            "kernel_ms_one_xX0_per_layer_uniform_field": t_plain * 1e3, "model_cost_ratio": t_full / t_plain}
 
 
 def bench_smooth(steps, warmup, n_tracks):
