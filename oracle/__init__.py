@@ -286,9 +286,15 @@ def fit_grad(geom, hits, mask, align, xX0, weight=None):
     return ga, gx
 
 
+class OModel(C.Structure):
+    _fields_ = [("map", C.c_void_p), ("nz", C.c_int32), ("pad", C.c_int32), ("eloss", C.c_double),
+                ("fr", C.c_double), ("fz", C.c_double)]
+
+
 def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, refit=False,
-         align=None, xX0=None, tol_abs=0.05, tol_rel=1e-4, tol_win=5e-3):
-    """FP64 combinatorial search of every seed of a synth.EventBatch."""
+         align=None, xX0=None, tol_abs=0.05, tol_rel=1e-4, tol_win=5e-3, material=None, field=None):
+    """FP64 combinatorial search of every seed of a synth.EventBatch; material and
+    field as for fit() (the detector model in every prediction and in the refit)."""
     L = geom.n_layers
     S = ev.seed_hits.shape[1]
     H = ev.hits.shape[1]
@@ -305,7 +311,15 @@ def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, r
                  rf_ndf=np.zeros(S, np.int32), rf_status=np.zeros(S, np.uint32))
     g = ogeom(geom)
     xx = geom.xX0 if xX0 is None else xX0
-    load().oracle_find(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int32(off.shape[0]), _p(off),
+    model, xmap = None, None
+    if material is not None or field is not None:
+        material = (None, 0.0) if material is None else material
+        field = (0.0, 0.0) if field is None else field
+        xmap = None if material[0] is None else np.ascontiguousarray(material[0], np.float64)
+        model = OModel(None if xmap is None else xmap.ctypes.data, 0 if xmap is None else int(xmap.shape[1]), 0,
+                       float(material[1]), float(field[0]), float(field[1]))
+    load().oracle_find(C.byref(g), _p(_f64(align)), _p(_f64(xx)), None if model is None else C.byref(model),
+                       C.c_int32(off.shape[0]), _p(off),
                        C.c_int64(H), _p(hits), C.c_int64(S), _p(sev), _p(sh), C.c_double(chi2_cut),
                        C.c_double(nsigma), C.c_int32(keep), C.c_int32(max_miss), C.c_int32(int(brute)),
                        C.c_double(tol_abs), C.c_double(tol_rel), C.c_double(tol_win),

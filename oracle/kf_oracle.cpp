@@ -1010,7 +1010,7 @@ struct FindCfg {
 // Relative margin by which the helix of state x clears (> 0) or misses (< 0) the
 // cylinder of layer ly: its circle reaches |centre - axis| + R from the axis.
 double reach_margin(const Geo& g, const Layer<double>& ly, const double x[6]) {
-  double w = -g.kB * x[3];
+  double w = -kB_at(g, x[0], x[1], x[2]) * x[3];
   if (w == 0) return 1.0;
   double R = 1.0 / std::fabs(w);
   double cx = x[0] - std::sin(x[4]) / w - ly.cx, cy = x[1] + std::cos(x[4]) / w - ly.cy;
@@ -1100,6 +1100,9 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
       if (std::fabs(reach_margin(g, ly, cd.tk.x)) < 1e-4) ambig |= 1u << L;
       Track<double> p = cd.tk;
       if (!predict(g, ly, p)) {
+        // no crossing (the state is untouched), or the particle stops in the layer's
+        // material (it ends with the prediction transported to the layer)
+        cd.tk = p;
         cd.term = true;
         cd.tk.status |= ST_PROP_FAIL;
         br.push_back({(int)k, 2, -1, cd.tk.n, cd.tk.chi2, 0.0});
@@ -1222,7 +1225,15 @@ extern "C" {
 //   n_hits, n_miss [keep][S]; chi2 [keep][S]; state [keep][6][S]; cov [keep][21][S];
 //   status [keep][S]; ambig [S] (bit L: an FP32-sensitive decision on layer L);
 //   rf_* [S]: refit of rank 0 (may be null).
-void oracle_find(const OGeom* og, const double* align, const double* xX0, int32_t n_events, const int64_t* hit_off,
+// The detector model of Sec. 3 for the finder (null: one x/X0 per layer, uniform field).
+struct OModel {
+  const double* map;  // [L][nz] x/X0 at z-bin centres, or null
+  int32_t nz, pad;
+  double eloss, fr, fz;
+};
+
+void oracle_find(const OGeom* og, const double* align, const double* xX0, const OModel* model, int32_t n_events,
+                 const int64_t* hit_off,
                  int64_t n_hits_total, const float* hits, int64_t n_seeds, const int32_t* seed_event,
                  const int32_t* seed_hits, double chi2_cut, double nsigma, int32_t keep, int32_t max_miss,
                  int32_t brute, double tol_abs, double tol_rel, double tol_win, int32_t* n_cand, int32_t* hit_idx,
@@ -1230,6 +1241,13 @@ void oracle_find(const OGeom* og, const double* align, const double* xX0, int32_
                  uint32_t* ambig, double* rf_state, double* rf_cov, double* rf_chi2, int32_t* rf_ndf,
                  uint32_t* rf_status) {
   Geo g = make_geo(og);
+  if (model) {
+    g.map = model->map;
+    g.map_nz = model->nz;
+    g.eloss = model->eloss;
+    g.fr = model->fr;
+    g.fz = model->fz;
+  }
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
   const int L = g.nl;

@@ -28,7 +28,7 @@ struct kf_ctx {
   }
   int grid_device = -1;   // device the occupancy figures below were taken on
   int grid_cus = 0;       // compute units
-  int grid_per_cu = 0;    // find workgroups that fit on one compute unit
+  int grid_per_cu[2] = {0, 0};  // find workgroups that fit on one compute unit (plain, model variant)
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // timing hook (kf_ctx_set_launch_events)
   kf_dedup_cuts dcuts{0.05f, 2, 1, 0.1f, 0.15f, 0.03f, 0.02f, 0.5f, 0.5f, 0.1f, 0.01f, 0.02f};
   const float* mat_map = nullptr;  // material model (kf_ctx_set_material)
@@ -125,15 +125,18 @@ int persistent_grid(kf_ctx* c, int nl, int* grid) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return KF_E_HIP;
   if (c->grid_device != dev) {
-    int cus = 0, per = 0;
+    int cus = 0, per = 0, per_model = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return KF_E_HIP;
-    if (kfi::find_max_blocks(nl, &per) != hipSuccess) return KF_E_HIP;
+    if (kfi::find_max_blocks(nl, false, &per) != hipSuccess) return KF_E_HIP;
+    if (kfi::find_max_blocks(nl, true, &per_model) != hipSuccess) return KF_E_HIP;
     c->grid_cus = cus;
-    c->grid_per_cu = per > 0 ? per : 1;
+    c->grid_per_cu[0] = per > 0 ? per : 1;
+    c->grid_per_cu[1] = per_model > 0 ? per_model : 1;
     c->grid_device = dev;
   }
+  const int have = c->grid_per_cu[c->material() ? 1 : 0];
   const int want = c->fcfg.blocks_per_cu;
-  *grid = c->grid_cus * (want > 0 && want < c->grid_per_cu ? want : c->grid_per_cu);
+  *grid = c->grid_cus * (want > 0 && want < have ? want : have);
   return KF_OK;
 }
 
@@ -314,7 +317,6 @@ namespace {
 
 int check_find(kf_ctx* ctx, const kf_find_in* in, const kf_find_out* out, void* ws, size_t ws_bytes) {
   if (!ctx || !in || !out) return KF_E_INVALID;
-  if (ctx->material()) return KF_E_UNSUPPORTED;  // the finder models one x/X0 per layer, a uniform field
   if (in->n_events < 0 || in->n_seeds < 0 || in->n_hits < 0) return KF_E_INVALID;
   if (in->keep < 1 || in->keep > KF_MAX_KEEP || in->max_miss < 1) return KF_E_INVALID;
   if (!(in->chi2_cut > 0.f) || !(in->nsigma > 0.f)) return KF_E_INVALID;
@@ -340,7 +342,8 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base + w.layers);
   const float* align = params ? params->align : nullptr;
   const float* xX0 = params ? params->xX0 : nullptr;
-  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st, ctx->g.zhalf_cm,
+                             ctx->mat_nz) != hipSuccess)
     return KF_E_HIP;
   kfi::BinArgs b;
   b.nl = ctx->g.n_layers;
@@ -381,6 +384,11 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   f.bidx = b.bidx;
   f.boff = b.boff;
   for (int l = 0; l < 32; ++l) f.zhalf[l] = b.zhalf[l];
+  f.mat_map = ctx->mat_map;
+  f.mat_nz = ctx->mat_nz;
+  f.eloss = ctx->eloss;
+  f.fr = ctx->fr;
+  f.fz = ctx->fz;
   f.counter = b.counter;
   f.n_cand = out->n_cand;
   f.hit_idx = out->hit_idx;
@@ -413,6 +421,11 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
     a.ndf = out->rf_ndf;
     a.status = out->rf_status;
     a.ckpt = nullptr;
+    a.mat_map = ctx->mat_map;
+    a.mat_nz = ctx->mat_nz;
+    a.eloss = ctx->eloss;
+    a.fr = ctx->fr;
+    a.fz = ctx->fz;
     if (kfi::launch_refit(a, in->hits, in->n_hits, out->hit_idx, st) != hipSuccess) return KF_E_HIP;
   }
   return KF_OK;
@@ -457,6 +470,11 @@ std::vector<uint64_t> find_key(const kf_ctx* ctx, int dev, const kf_layer_params
           u(in->refit ? out->rf_status : nullptr),
           u(ws),
           (uint64_t)ws_bytes,
+          u(ctx->mat_map),
+          (uint64_t)ctx->mat_nz,
+          f(ctx->eloss),
+          f(ctx->fr),
+          f(ctx->fz),
           (uint64_t)ctx->fcfg.wide_window_bins,
           (uint64_t)ctx->fcfg.blocks_per_cu,
           f(ctx->det_thr)};

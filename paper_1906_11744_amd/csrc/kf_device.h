@@ -303,6 +303,24 @@ __device__ __forceinline__ bool energy_loss(Trk& k, const Frame& f, float xX0, f
   return true;
 }
 
+// k_B of the parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2) at (x, y, z), for a
+// step that starts there; exactly kB when both coefficients are zero.
+__device__ __forceinline__ float field_kB(float kB, float fr, float fz, float x, float y, float z) {
+  return kB * fmaf(fz, z * z, fmaf(fr, fmaf(x, x, y * y), 1.f));
+}
+
+// The material of a layer crossed after the seed layer under the detector model: x/X0
+// from the map row (null: the layer's constant), its scattering term, then the mean
+// energy loss.  False if the particle stops in it (the state then holds the
+// transported prediction with the scattering term added).
+__device__ __forceinline__ bool apply_material(Trk& k, const Frame& f, const LayerK& ly, const float* row, int nz,
+                                               float eloss, float mass2) {
+  const float xx = row ? map_xX0(row, nz, ly, k.x[2]) : ly.xX0;
+  if (!(xx > 0.f)) return true;
+  add_scattering(k, f, xx, mass2);
+  return !(eloss > 0.f) || energy_loss(k, f, xx, eloss, mass2);
+}
+
 // What a prediction needs for every hit of a layer: the projection rows
 // h1 = phi_hat - tan(alpha) r_hat, h2 = (-cot(theta)/cos(alpha) r_hat, 1), the
 // products HC (rows 1, 2 of H C) and S^-1 (S = H C H^T + V is block diagonal: its

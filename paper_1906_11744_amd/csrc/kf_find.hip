@@ -166,6 +166,10 @@ __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64
 
 }  // namespace
 
+// kModel: the detector model (material map, energy loss, parameterised field) in every
+// prediction, as the fit's model variant takes it; false: one x/X0 per layer and a
+// uniform field.
+template <bool kModel>
 __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
   // LDS: wide-window slots [256] x 128 B, stashed branch lists (chi2 [8][256],
   // hit [8][256], count [256]), backpointers [nl][256] of every (layer, slot):
@@ -220,24 +224,38 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
       for (int q = 0; q < 3; ++q)
         kfd::place(a.layers[q], a.hits[sh[q]], a.hits[a.H + sh[q]], a.hits[2 * a.H + sh[q]], m[q][0], m[q][1],
                    m[q][2]);
-      kfd::seed_from_three(k, a.md, m[0][0], m[0][1], m[0][2], m[1][0], m[1][1], m[2][0], m[2][1], m[2][2],
+      kfd::Model md0 = a.md;
+      if (kModel) md0.kB = kfd::field_kB(a.md.kB, a.fr, a.fz, m[0][0], m[0][1], m[0][2]);  // kappa at hit 0
+      kfd::seed_from_three(k, md0, m[0][0], m[0][1], m[0][2], m[1][0], m[1][1], m[2][0], m[2][1], m[2][2],
                            a.srphi, a.sz);
       kfd::init_trig(k);
       bool ok = true;
       for (int q = 0; q < 3 && ok; ++q) {
         const kfd::LayerK ly = a.layers[q];
         if (q > 0) {
+          const float kB =
+              kModel ? kfd::field_kB(a.md.kB, a.fr, a.fz, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2]) : a.md.kB;
           kfd::Step stp;
-          ok = kfd::crossing(k, ly, a.md.kB, stp);
+          ok = kfd::crossing(k, ly, kB, stp);
           if (!ok) {
             st |= kfd::ST_PROP_FAIL;
             break;
           }
-          kfd::transport(k, stp, a.md.kB);
+          kfd::transport(k, stp, kB);
         }
         const kfd::Frame f = kfd::frame_at(k, ly);
-        if (q > 0 && ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
-        if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
+        if (kModel) {
+          if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
+          if (q > 0 && !kfd::apply_material(k, f, ly, a.mat_map ? a.mat_map + q * a.mat_nz : nullptr, a.mat_nz,
+                                            a.eloss, a.md.mass2)) {
+            ok = false;
+            st |= kfd::ST_PROP_FAIL;
+            break;
+          }
+        } else {
+          if (q > 0 && ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+          if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
+        }
         kfd::Pred p;
         kfd::prepare(k, f, a.md, p);
         if (p.fp64) st |= kfd::ST_FP64;
@@ -293,13 +311,23 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
         nlist = nlist < kMaxList ? nlist + 1 : kMaxList;
       };
       if (mode == LIVE) {
+        const float kB =
+            kModel ? kfd::field_kB(a.md.kB, a.fr, a.fz, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2]) : a.md.kB;
         kfd::Step stp;
-        if (kfd::crossing(k, ly, a.md.kB, stp)) {
-          predicted = true;
-          kfd::transport(k, stp, a.md.kB);
-          const kfd::Frame f = kfd::frame_at(k, ly);
+        bool reach = kfd::crossing(k, ly, kB, stp);
+        kfd::Frame f;
+        if (reach) {
+          kfd::transport(k, stp, kB);
+          f = kfd::frame_at(k, ly);
           if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
-          if (ly.xX0 > 0.f) kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+          if (kModel)  // a particle that stops in the layer's material ends there, transported
+            reach = kfd::apply_material(k, f, ly, a.mat_map ? a.mat_map + l * a.mat_nz : nullptr, a.mat_nz, a.eloss,
+                                        a.md.mass2);
+          else if (ly.xX0 > 0.f)
+            kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
+        }
+        if (reach) {
+          predicted = true;
           kfd::Pred p;
           kfd::prepare(k, f, a.md, p);
           const float phip = atan2f(f.ry, f.rx), zp = k.x[2] + k.xl[2];
@@ -619,16 +647,24 @@ size_t find_lds_bytes(int nl) {
   return (size_t)256 * kWideStride + (size_t)(2 * kMaxList + 1) * 256 * 4 + (size_t)nl * 256 * sizeof(int32_t);
 }
 
-hipError_t find_max_blocks(int nl, int* blocks_per_cu) {
+template <bool kModel>
+hipError_t find_max_blocks_variant(int nl, int* blocks_per_cu) {
   // more than 64 KiB of dynamic LDS per workgroup (gfx950 has 160 KiB per CU)
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(find_kernel),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(find_kernel<kModel>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)find_lds_bytes(nl));
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel, 256, find_lds_bytes(nl));
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel<kModel>, 256, find_lds_bytes(nl));
+}
+
+hipError_t find_max_blocks(int nl, bool model, int* blocks_per_cu) {
+  return model ? find_max_blocks_variant<true>(nl, blocks_per_cu) : find_max_blocks_variant<false>(nl, blocks_per_cu);
 }
 
 hipError_t launch_find(const FindArgs& a, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(find_kernel, dim3((unsigned)grid), dim3(256), find_lds_bytes(a.nl), stream, a);
+  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
+    hipLaunchKernelGGL(find_kernel<true>, dim3((unsigned)grid), dim3(256), find_lds_bytes(a.nl), stream, a);
+  else
+    hipLaunchKernelGGL(find_kernel<false>, dim3((unsigned)grid), dim3(256), find_lds_bytes(a.nl), stream, a);
   return hipGetLastError();
 }
 

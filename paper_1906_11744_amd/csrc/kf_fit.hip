@@ -27,18 +27,22 @@ __device__ __forceinline__ kfd::LayerK make_layer(int l, const float* radius, co
   return k;
 }
 
-__global__ void layer_prep_kernel(int nl, Radii rad, const float* __restrict__ align, const float* __restrict__ xX0,
-                                  kfd::LayerK* __restrict__ out) {
+__global__ void layer_prep_kernel(int nl, Radii rad, Radii zh, int map_nz, const float* __restrict__ align,
+                                  const float* __restrict__ xX0, kfd::LayerK* __restrict__ out) {
   const int l = threadIdx.x;
   if (l >= nl) return;
-  out[l] = make_layer(l, rad.r, align, xX0);
+  out[l] = make_layer(l, rad.r, align, xX0, zh.r, map_nz);
 }
 
 hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
-                             kfd::LayerK* out, hipStream_t stream) {
-  Radii rad;
-  for (int l = 0; l < 32; ++l) rad.r[l] = l < nl ? radius_host[l] : 0.f;
-  hipLaunchKernelGGL(layer_prep_kernel, dim3(1), dim3(32), 0, stream, nl, rad, align, xX0, out);
+                             kfd::LayerK* out, hipStream_t stream, const float* zhalf_host, int map_nz) {
+  Radii rad, zh;
+  for (int l = 0; l < 32; ++l) {
+    rad.r[l] = l < nl ? radius_host[l] : 0.f;
+    zh.r[l] = (zhalf_host && l < nl) ? zhalf_host[l] : 1.f;
+  }
+  if (!zhalf_host) map_nz = 0;
+  hipLaunchKernelGGL(layer_prep_kernel, dim3(1), dim3(32), 0, stream, nl, rad, zh, map_nz, align, xX0, out);
   return hipGetLastError();
 }
 
@@ -75,12 +79,6 @@ struct GatherHits {
   }
 };
 
-// k_B of the parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2) at (x, y, z); exactly
-// the uniform k_B when both coefficients are zero.
-__device__ __forceinline__ float field_kB(const FitArgs& a, float x, float y, float z) {
-  return a.md.kB * fmaf(a.fz, z * z, fmaf(a.fr, fmaf(x, x, y * y), 1.f));
-}
-
 template <bool kCkpt, bool kModel, class Src>
 __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __restrict__ lays, int64_t i,
                                         uint32_t mask, const Src& src) {
@@ -110,7 +108,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       hit(1, m1x, m1y, m1z);
       hit(2, m2x, m2y, m2z);
       kfd::Model md0 = a.md;
-      if (kModel) md0.kB = field_kB(a, m0x, m0y, m0z);  // curvature to kappa in the field at hit 0
+      if (kModel) md0.kB = kfd::field_kB(a.md.kB, a.fr, a.fz, m0x, m0y, m0z);  // curvature to kappa at hit 0
       kfd::seed_from_three(k, md0, m0x, m0y, m0z, m1x, m1y, m2x, m2y, m2z, a.srphi, a.sz);
     } else {
 #pragma unroll
@@ -126,7 +124,8 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       const kfd::LayerK ly = lays[l];
       if (l > 0) {
         // the step is the helix of the field at its starting point
-        const float kB = kModel ? field_kB(a, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2]) : a.md.kB;
+        const float kB = kModel ? kfd::field_kB(a.md.kB, a.fr, a.fz, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2])
+                                : a.md.kB;
         kfd::Step st;
         if (!kfd::crossing(k, ly, kB, st)) {
           status |= kfd::ST_PROP_FAIL;
@@ -137,15 +136,10 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       const kfd::Frame f = kfd::frame_at(k, ly);
       if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
       if (kModel) {  // the material map at the crossing's z and the energy loss
-        if (l > 0) {
-          const float xx = a.mat_map ? kfd::map_xX0(a.mat_map + l * a.mat_nz, a.mat_nz, ly, k.x[2]) : ly.xX0;
-          if (xx > 0.f) {
-            kfd::add_scattering(k, f, xx, a.md.mass2);
-            if (a.eloss > 0.f && !kfd::energy_loss(k, f, xx, a.eloss, a.md.mass2)) {
-              status |= kfd::ST_PROP_FAIL;
-              break;
-            }
-          }
+        if (l > 0 && !kfd::apply_material(k, f, ly, a.mat_map ? a.mat_map + l * a.mat_nz : nullptr, a.mat_nz, a.eloss,
+                                          a.md.mass2)) {
+          status |= kfd::ST_PROP_FAIL;
+          break;
         }
       } else if (l > 0 && ly.xX0 > 0.f) {
         kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
@@ -194,6 +188,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a) {
 }
 
 // Fit of each seed's best finder candidate from its own hits (slot 0 of hit_idx).
+template <bool kModel>
 __global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __restrict__ hits, int64_t H,
                                                     const int32_t* __restrict__ idx0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,13 +196,16 @@ __global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __re
   uint32_t mask = 0;
   for (int l = 0; l < a.nl; ++l) mask |= (idx0[(int64_t)l * a.n + i] >= 0 ? 1u : 0u) << l;
   GatherHits src{hits, H, idx0};
-  fit_one<false, false>(a, a.layers, i, mask, src);
+  fit_one<false, kModel>(a, a.layers, i, mask, src);
 }
 
 hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream) {
   const int bs = 256;
   const int64_t nb = (a.n + bs - 1) / bs;
-  hipLaunchKernelGGL(refit_kernel, dim3((unsigned)nb), dim3(bs), 0, stream, a, hits, H, idx0);
+  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
+    hipLaunchKernelGGL(refit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, a, hits, H, idx0);
+  else
+    hipLaunchKernelGGL(refit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, a, hits, H, idx0);
   return hipGetLastError();
 }
 

@@ -69,6 +69,11 @@ struct FindArgs {
   const int32_t* bidx;
   const int32_t* boff;
   float zhalf[32];
+  // detector model (as in FitArgs): material map [nl][mat_nz] or null, loss, field
+  const float* mat_map = nullptr;
+  int32_t mat_nz = 0;
+  float eloss = 0.f;
+  float fr = 0.f, fz = 0.f;
   int32_t* counter;
   int32_t* n_cand;
   int32_t* hit_idx;
@@ -162,12 +167,15 @@ hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_
                          hipEvent_t ev_stop = nullptr);
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
 size_t find_lds_bytes(int nl);
-hipError_t find_max_blocks(int nl, int* blocks_per_cu);
+// model: the finder variant with the detector model (material map, energy loss, field)
+hipError_t find_max_blocks(int nl, bool model, int* blocks_per_cu);
 hipError_t launch_find(const FindArgs& a, int grid, hipStream_t stream);
 
-// Writes the per-layer constants (radius, alignment, its cos/sin, material).
+// Writes the per-layer constants (radius, alignment, its cos/sin, material; with
+// zhalf_host and map_nz > 0 also the placement of the material map's z bins).
 hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
-                             kfd::LayerK* out, hipStream_t stream);
+                             kfd::LayerK* out, hipStream_t stream, const float* zhalf_host = nullptr,
+                             int map_nz = 0);
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
                       hipEvent_t ev_stop = nullptr);
 // Fit of each seed's rank-0 finder candidate: idx0 [L][n] hit indices into hits [3][H].

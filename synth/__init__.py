@@ -419,11 +419,12 @@ class EventBatch:
 
 def make_events(geom: Geometry, n_tracks_per_event, workload=3, noise_frac=0.2,
                 pt_range=(0.5, 50.0), pt_log=True, eta_max=1.5, scatter=True, smear=True,
-                first_event=0):
+                first_event=0, material=None, field=None):
     """Events for the finder: simulated tracks plus noise hits, shuffled per layer.
 
     Noise: round(noise_frac * true hits on L) hits uniform in phi in [-pi, pi) and in
     z in [-Z_L, Z_L], on the cylinder.  Seeds are the true triplets on layers 0-2.
+    material / field: as for simulate().
     """
     L = geom.n_layers
     all_hits, offs, tr_ids, seeds, seed_ev, seed_tr = [], [], [], [], [], []
@@ -433,7 +434,7 @@ def make_events(geom: Geometry, n_tracks_per_event, workload=3, noise_frac=0.2,
     for e, nt in enumerate(n_tracks_per_event):
         rng = rng_for(workload, first_event + e)
         ts = simulate(geom, rng, int(nt), pt_range, pt_log, eta_max, keep_truth=False,
-                      smear=smear, scatter=scatter)
+                      smear=smear, scatter=scatter, material=material, field=field)
         off = np.zeros(L + 1, dtype=np.int64)
         ev_hits = []
         ev_trk = []

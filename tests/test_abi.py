@@ -163,8 +163,9 @@ def test_dedup_calls_reject_bad_arguments_before_launch():
 
 def test_material_setting_validation_and_the_calls_it_excludes():
     """kf_ctx_set_material stores its arguments (no device work here); while a map or
-    a loss is set, the finder, the smoother and the adjoint refuse before launching,
-    and clearing the setting lets their own validation run again."""
+    a loss is set, the smoother and the adjoint refuse before launching (the finder
+    takes the model and goes on to its own checks), and clearing the setting lets
+    their own validation run again."""
     kf, lib = _lib()
     ctx = kf.Context(synth.workload_geometry(2))
     fake = C.c_void_p(0x1000)   # never dereferenced: no kf_fit is called here
@@ -189,7 +190,7 @@ def test_material_setting_validation_and_the_calls_it_excludes():
     assert codes() == (-3, -3, -3)
     for args in ((fake, 1, 0.0), (fake, 64, 0.0363), (None, 0, 0.0363)):
         assert lib.kf_ctx_set_material(ctx._h, args[0], args[1], C.c_float(args[2])) == 0
-        assert codes() == (-2, -2, -2), args
+        assert codes() == (-3, -2, -2), args
     assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
     assert codes() == (-3, -3, -3)
 
@@ -201,14 +202,16 @@ def test_field_setting_validation_and_the_calls_it_excludes():
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(float("inf")), C.c_float(0.0)) == -1
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(float("nan"))) == -1
     fake = C.c_void_p(0x1000)
-    fin = kf.FindIn(1, fake, 100, fake, 10, fake, fake, 30.0, 3.0, 6, 3, 0)
-    fo = kf.FindOut(*([fake] * 13))
     p = kf.LayerParams()
-    assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -3
+    fit_in = kf.FitIn(10, fake, fake, None, None, 1)
+    fit_out = kf.FitOut(fake, fake, fake, fake, fake, fake)
+    so = kf.SmoothOut(fake, fake, fake, fake)
+    smooth = lambda: lib.kf_smooth(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), C.byref(so), None, 0, None)
+    assert smooth() == -3
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(-1e-6), C.c_float(-4e-6)) == 0
-    assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -2
+    assert smooth() == -2
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(0.0)) == 0
-    assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -3
+    assert smooth() == -3
     g0 = synth.workload_geometry(2)
     g0.B = 0.0
     ctx0 = kf.Context(g0)

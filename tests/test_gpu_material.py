@@ -10,7 +10,9 @@ the state bar as there.  Cases: tracks simulated through the map with energy los
 follows each layer's z shift), 20 000 tracks sampled from the 1e6-track call, a
 loss large enough to stop slow particles, each part of the model alone, and a map of
 constant rows without loss, which is the per-layer model; tracks stepped through the
-parameterised field, alone and with the material model."""
+parameterised field, alone and with the material model; and the finder (search and
+refit) on events simulated with the whole model, under the finder's own parity rule
+(tests/test_gpu_find.py)."""
 import numpy as np
 import pytest
 import torch
@@ -161,22 +163,55 @@ def test_constant_map_without_loss_is_the_layer_model():
     assert cov_err(g["cov"], plain["cov"].astype(np.float64))[ok].max() < 1e-6
 
 
-def test_material_excludes_find_smooth_and_adjoint():
+def test_material_excludes_smooth_and_adjoint():
     need_gpu()
     from paper_1906_11744_amd import Context, kf
     geom, ev = synth.find_workload(3, n_tracks=50)
     ctx = Context(geom)
     ctx.set_material(None, 0.0363)
     t = lambda a: to_dev(np.ascontiguousarray(a))
-    with pytest.raises(kf.KfError) as e:
-        ctx.find(t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
-    assert e.value.code == -2
     _, ts = synth.fit_workload(2, n=100)
     fwd = ctx.fit(to_dev(ts.hits), mask_dev(ts.hit_mask), ckpt=True)
-    with pytest.raises(kf.KfError):
+    with pytest.raises(kf.KfError) as e:
         ctx.smooth(to_dev(ts.hits), mask_dev(ts.hit_mask), fwd)
+    assert e.value.code == -2
     with pytest.raises(kf.KfError):
         ctx.fit_backward(to_dev(ts.hits), mask_dev(ts.hit_mask), fwd, torch.ones(100, device="cuda"))
     ctx.set_material(None, 0.0)
     ctx.find(t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("loss_scale", [1.0, 40.0])
+def test_finder_with_the_detector_model(loss_scale):
+    """One event of 2 000 tracks (20% noise) simulated through the map with energy loss
+    in the field; kf_find with refit under the same model against the oracle's finder;
+    with 40 times the loss, candidates whose particle stops end at that layer."""
+    from test_gpu_find import compare, oracle_find
+    need_gpu()
+    from paper_1906_11744_amd import Context
+    geom = synth.workload_geometry(2)
+    xmap = synth.material_map(geom, 16)
+    mat = (xmap, synth.ELOSS_SI_GEV_PER_X0 * loss_scale)
+    fld = synth.FIELD_SOLENOID
+    ev = synth.make_events(geom, [2000], workload=10, material=(xmap, synth.ELOSS_SI_GEV_PER_X0), field=fld)
+    ctx = Context(geom)
+    ctx.set_material(to_dev(xmap.astype(np.float32)), mat[1])
+    ctx.set_field(*fld)
+    t = lambda a: to_dev(np.ascontiguousarray(a))
+    out = ctx.find(t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event),
+                   xX0=t(geom.xX0.astype(np.float32)), refit=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    r = oracle_find(geom, ev, refit=True, material=_oracle_material(mat), field=_oracle_field(fld))
+    stats = compare(geom, ev, g, r, f"finder with map, loss x {loss_scale:g} and field")
+    assert stats["exact"] + stats["reordered"] > 0.97 * ev.seed_hits.shape[1]
+    stops = ((r["status"][0] & oracle.ST_PROP_FAIL) != 0).sum()
+    print(f"oracle rank-0 candidates ending with PROP_FAIL: {stops}")
+    # the refit of each seed's best candidate under the same model
+    ok = (r["n_cand"] > 0) & ((r["rf_status"] & (oracle.ST_PROP_FAIL | oracle.ST_NEAR_TANGENT)) == 0)
+    same = np.array([np.array_equal(g["hit_idx"][0, :, s], r["hit_idx"][0, :, s]) for s in range(ok.size)])
+    sel = ok & same
+    rel = rel_state_err(g["rf_state"][:, sel], r["rf_state"][:, sel])
+    print(f"refit: n={sel.sum()} max rel state err {rel.max():.2e}")
+    assert rel.max() < 1e-4
