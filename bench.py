@@ -49,8 +49,8 @@ PEAK_HBM_GBS = 8000.0
 # runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean over every launch of the run), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "6db829028da8a411", "tracks": 1_000_000,
-               "fetch_kib": 101933.0, "write_kib": 117187.5,
+FIT_TRAFFIC = {"sources": "2465c930467a6e29", "tracks": 1_000_000,
+               "fetch_kib": 101938.2, "write_kib": 117187.5,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
@@ -358,10 +358,25 @@ def bench_material(steps, warmup):
     t_mat = _time_kernel(ctx, fn, steps, warmup)
     ctx.set_material(None, 0.0)
     t_plain = _time_kernel(ctx, fn, steps, warmup)
-    return {"tracks": int(ts.hits.shape[2]), "kalman_steps": n_steps, "map_bins": int(xmap.shape[1]),
-            "eloss_gev_per_x0": eloss, "field_c_r_c_z": list(fld), "steps_per_s": n_steps / tm.wall,
-            "ms_per_call": tm.wall * 1e3, "kernel_ms": t_full * 1e3, "kernel_ms_material_only": t_mat * 1e3,
-            "kernel_ms_one_xX0_per_layer_uniform_field": t_plain * 1e3, "model_cost_ratio": t_full / t_plain}
+    res = {"tracks": int(ts.hits.shape[2]), "kalman_steps": n_steps, "map_bins": int(xmap.shape[1]),
+           "eloss_gev_per_x0": eloss, "field_c_r_c_z": list(fld), "steps_per_s": n_steps / tm.wall,
+           "ms_per_call": tm.wall * 1e3, "kernel_ms": t_full * 1e3, "kernel_ms_material_only": t_mat * 1e3,
+           "kernel_ms_one_xX0_per_layer_uniform_field": t_plain * 1e3, "model_cost_ratio": t_full / t_plain}
+    # the finder on one event of 5 000 tracks simulated with the whole model
+    ev = synth.make_events(geom, [5000], workload=10, material=(xmap, eloss), field=fld)
+    args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
+    ctx.set_material(dmap, eloss)
+    ctx.set_field(*fld)
+    ctx.set_find_config(use_graph=1)
+    fout = ctx.find(*args, xX0=xX0)
+    t_fm = _time_launches(lambda: ctx.find(*args, xX0=xX0, out=fout), steps, warmup).region
+    ctx.set_material(None, 0.0)
+    ctx.set_field(0.0, 0.0)
+    fout = ctx.find(*args, xX0=xX0)
+    t_fp = _time_launches(lambda: ctx.find(*args, xX0=xX0, out=fout), steps, warmup).region
+    res["find_one_event_5000_tracks"] = {"events_per_s": 1.0 / t_fm, "ms_per_event": t_fm * 1e3,
+                                         "ms_per_event_one_xX0_per_layer_uniform_field": t_fp * 1e3}
+    return res
 
 
 def bench_smooth(steps, warmup, n_tracks):

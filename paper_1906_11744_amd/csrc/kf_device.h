@@ -316,9 +316,12 @@ __device__ __forceinline__ float field_kB(float kB, float fr, float fz, float x,
 __device__ __forceinline__ bool apply_material(Trk& k, const Frame& f, const LayerK& ly, const float* row, int nz,
                                                float eloss, float mass2) {
   const float xx = row ? map_xX0(row, nz, ly, k.x[2]) : ly.xX0;
-  if (!(xx > 0.f)) return true;
-  add_scattering(k, f, xx, mass2);
-  return !(eloss > 0.f) || energy_loss(k, f, xx, eloss, mass2);
+  bool ok = true;
+  if (xx > 0.f) {
+    add_scattering(k, f, xx, mass2);
+    if (eloss > 0.f) ok = energy_loss(k, f, xx, eloss, mass2);
+  }
+  return ok;
 }
 
 // What a prediction needs for every hit of a layer: the projection rows

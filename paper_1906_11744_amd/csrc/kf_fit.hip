@@ -136,10 +136,15 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       const kfd::Frame f = kfd::frame_at(k, ly);
       if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
       if (kModel) {  // the material map at the crossing's z and the energy loss
-        if (l > 0 && !kfd::apply_material(k, f, ly, a.mat_map ? a.mat_map + l * a.mat_nz : nullptr, a.mat_nz, a.eloss,
-                                          a.md.mass2)) {
-          status |= kfd::ST_PROP_FAIL;
-          break;
+        if (l > 0) {
+          const float xx = a.mat_map ? kfd::map_xX0(a.mat_map + l * a.mat_nz, a.mat_nz, ly, k.x[2]) : ly.xX0;
+          if (xx > 0.f) {
+            kfd::add_scattering(k, f, xx, a.md.mass2);
+            if (a.eloss > 0.f && !kfd::energy_loss(k, f, xx, a.eloss, a.md.mass2)) {
+              status |= kfd::ST_PROP_FAIL;
+              break;
+            }
+          }
         }
       } else if (l > 0 && ly.xX0 > 0.f) {
         kfd::add_scattering(k, f, ly.xX0, a.md.mass2);
