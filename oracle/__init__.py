@@ -34,6 +34,24 @@ class OGeom(C.Structure):
                 ("radius", C.c_double * 32), ("zhalf", C.c_double * 32)]
 
 
+class OModel(C.Structure):
+    """The detector model of Sec. 3 (material map, energy loss, field)."""
+    _fields_ = [("map", C.c_void_p), ("nz", C.c_int32), ("pad", C.c_int32), ("eloss", C.c_double),
+                ("fr", C.c_double), ("fz", C.c_double)]
+
+
+def _model(material, field):
+    """(OModel or None, the float64 map it points to, kept alive by the caller)."""
+    if material is None and field is None:
+        return None, None
+    material = (None, 0.0) if material is None else material
+    field = (0.0, 0.0) if field is None else field
+    xmap = None if material[0] is None else np.ascontiguousarray(material[0], np.float64)
+    m = OModel(None if xmap is None else xmap.ctypes.data, 0 if xmap is None else int(xmap.shape[1]), 0,
+               float(material[1]), float(field[0]), float(field[1]))
+    return m, xmap
+
+
 def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
@@ -157,10 +175,11 @@ def rts_step(xf, Cf, J, xp, Cp, xs1, Cs1, wrap_idx=-1):
     return xs, Cs
 
 
-def smooth(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None):
+def smooth(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, material=None, field=None):
     """Forward fit plus RTS smoother of every track.  Returns state [L][6][n],
     cov [L][21][n] (layers 0..lend, zero beyond), lend [n] (last layer with an update,
-    -1 if none) and the forward status [n]."""
+    -1 if none) and the forward status [n].  material / field: the detector model as
+    for fit() (each step's linearisation then includes the energy loss)."""
     dt = np.float64 if np.asarray(hits).dtype == np.float64 else np.float32
     hits = np.ascontiguousarray(hits, dt)
     mask = np.ascontiguousarray(mask, np.uint32)
@@ -173,13 +192,15 @@ def smooth(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=Non
     g = ogeom(geom)
     xx = geom.xX0 if xX0 is None else xX0
     fn = load().oracle_smooth_f64 if dt == np.float64 else load().oracle_smooth
-    fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(hits), _p(mask),
+    model, _keep = _model(material, field)
+    fn(C.byref(g), _p(_f64(align)), _p(_f64(xx)), None if model is None else C.byref(model), C.c_int64(n),
+       _p(hits), _p(mask),
                          int(from_hits), _p(ss), _p(sc), _p(out["state"]), _p(out["cov"]), _p(out["lend"]),
                          _p(out["status"]))
     return out
 
 
-def smooth_filtered(geom, state, cov, lend, align=None, xX0=None):
+def smooth_filtered(geom, state, cov, lend, align=None, xX0=None, material=None, field=None):
     """The RTS pass alone over given filtered estimates: state [L][6][n] and cov
     [L][21][n] after each layer (any float type; read as float64), lend [n] the last
     updated layer.  Returns state/cov as smooth() for layers first..lend (zero
@@ -191,7 +212,9 @@ def smooth_filtered(geom, state, cov, lend, align=None, xX0=None):
     out = dict(state=np.zeros((L, 6, n)), cov=np.zeros((L, 21, n)), first=np.zeros(n, np.int32))
     g = ogeom(geom)
     xx = geom.xX0 if xX0 is None else xX0
-    load().oracle_smooth_filtered(C.byref(g), _p(_f64(align)), _p(_f64(xx)), C.c_int64(n), _p(lend), _p(state),
+    model, _keep = _model(material, field)
+    load().oracle_smooth_filtered(C.byref(g), _p(_f64(align)), _p(_f64(xx)), None if model is None else C.byref(model),
+                                  C.c_int64(n), _p(lend), _p(state),
                                   _p(cov), _p(out["state"]), _p(out["cov"]), _p(out["first"]))
     return out
 
@@ -286,11 +309,6 @@ def fit_grad(geom, hits, mask, align, xX0, weight=None):
     return ga, gx
 
 
-class OModel(C.Structure):
-    _fields_ = [("map", C.c_void_p), ("nz", C.c_int32), ("pad", C.c_int32), ("eloss", C.c_double),
-                ("fr", C.c_double), ("fz", C.c_double)]
-
-
 def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, refit=False,
          align=None, xX0=None, tol_abs=0.05, tol_rel=1e-4, tol_win=5e-3, material=None, field=None):
     """FP64 combinatorial search of every seed of a synth.EventBatch; material and
@@ -311,13 +329,7 @@ def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, r
                  rf_ndf=np.zeros(S, np.int32), rf_status=np.zeros(S, np.uint32))
     g = ogeom(geom)
     xx = geom.xX0 if xX0 is None else xX0
-    model, xmap = None, None
-    if material is not None or field is not None:
-        material = (None, 0.0) if material is None else material
-        field = (0.0, 0.0) if field is None else field
-        xmap = None if material[0] is None else np.ascontiguousarray(material[0], np.float64)
-        model = OModel(None if xmap is None else xmap.ctypes.data, 0 if xmap is None else int(xmap.shape[1]), 0,
-                       float(material[1]), float(field[0]), float(field[1]))
+    model, _keep = _model(material, field)
     load().oracle_find(C.byref(g), _p(_f64(align)), _p(_f64(xx)), None if model is None else C.byref(model),
                        C.c_int32(off.shape[0]), _p(off),
                        C.c_int64(H), _p(hits), C.c_int64(S), _p(sev), _p(sh), C.c_double(chi2_cut),

@@ -399,7 +399,10 @@ double map_xX0(const Geo& g, int l, double z) {
 // covariance follows kappa' as a function of (kappa, theta), differentiated here by
 // dual numbers; the path-length factor enters the mean only.  False if the particle
 // is left without kinetic energy.
-bool material_step(const Geo& g, const Layer<double>& ly, double x[6], double C[6][6]) {
+bool material_step(const Geo& g, const Layer<double>& ly, double x[6], double C[6][6], double (*A_out)[6] = nullptr) {
+  if (A_out)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) A_out[i][j] = i == j ? 1.0 : 0.0;
   Layer<double> lm = ly;
   if (g.map) lm.xX0 = map_xX0(g, ly.idx, x[2] - ly.dz);
   add_scattering(g, lm, x, C);
@@ -422,6 +425,9 @@ bool material_step(const Geo& g, const Layer<double>& ly, double x[6], double C[
   A[3][5] = k1.d[1];
   sandwich(A, C);
   x[3] = k1.v;
+  if (A_out)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) A_out[i][j] = A[i][j];
   return true;
 }
 
@@ -611,7 +617,13 @@ bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nul
   }
   if (g.map || g.eloss > 0.0) {
     if constexpr (std::is_same<T, double>::value) {
-      if (!material_step(g, ly, tk.x, tk.C)) { tk.status |= ST_PROP_FAIL; return false; }
+      double A[6][6];
+      if (!material_step(g, ly, tk.x, tk.C, A)) { tk.status |= ST_PROP_FAIL; return false; }
+      if (J_out) {  // the step's linearisation is A J: the loss maps kappa after the transport
+        double row[6];
+        for (int j = 0; j < 6; ++j) row[j] = A[3][3] * J_out[3][j] + A[3][5] * J_out[5][j];
+        for (int j = 0; j < 6; ++j) J_out[3][j] = row[j];
+      }
     } else {
       tk.status |= ST_BAD_INPUT;  // the material model is not differentiated
       return false;
@@ -1232,6 +1244,21 @@ struct OModel {
   double eloss, fr, fz;
 };
 
+}  // extern "C"
+
+namespace {
+void set_model(Geo& g, const OModel* model) {
+  if (!model) return;
+  g.map = model->map;
+  g.map_nz = model->nz;
+  g.eloss = model->eloss;
+  g.fr = model->fr;
+  g.fz = model->fz;
+}
+}  // namespace
+
+extern "C" {
+
 void oracle_find(const OGeom* og, const double* align, const double* xX0, const OModel* model, int32_t n_events,
                  const int64_t* hit_off,
                  int64_t n_hits_total, const float* hits, int64_t n_seeds, const int32_t* seed_event,
@@ -1241,13 +1268,7 @@ void oracle_find(const OGeom* og, const double* align, const double* xX0, const 
                  uint32_t* ambig, double* rf_state, double* rf_cov, double* rf_chi2, int32_t* rf_ndf,
                  uint32_t* rf_status) {
   Geo g = make_geo(og);
-  if (model) {
-    g.map = model->map;
-    g.map_nz = model->nz;
-    g.eloss = model->eloss;
-    g.fr = model->fr;
-    g.fz = model->fz;
-  }
+  set_model(g, model);
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
   const int L = g.nl;
@@ -1477,10 +1498,11 @@ extern "C" {
 // [L][21][n] (packed lower triangle) hold the filtered estimates after each layer,
 // lend [n] the last updated layer (-1: none).  Outputs as oracle_smooth for layers
 // first[i]..lend[i] (zero elsewhere) and first [n] (-1 if lend < 0).
-void oracle_smooth_filtered(const OGeom* og, const double* align, const double* xX0, int64_t n,
+void oracle_smooth_filtered(const OGeom* og, const double* align, const double* xX0, const OModel* model, int64_t n,
                             const int32_t* lend, const double* xf, const double* Cf, double* xs_out,
                             double* Cs_out, int32_t* first_out) {
   Geo g = make_geo(og);
+  set_model(g, model);
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
   const int L = g.nl;
@@ -1515,10 +1537,11 @@ int oracle_rts_step(int n, const double* xf, const double* Cf, const double* J, 
 
 namespace {
 template <class HT>
-void smooth_batch(const OGeom* og, const double* align, const double* xX0, int64_t n, const HT* hits,
-                  const uint32_t* mask, int seed_from_hits_flag, const HT* seed_state, const HT* seed_cov,
-                  double* xs_out, double* Cs_out, int32_t* lend_out, uint32_t* status) {
+void smooth_batch(const OGeom* og, const double* align, const double* xX0, const OModel* model, int64_t n,
+                  const HT* hits, const uint32_t* mask, int seed_from_hits_flag, const HT* seed_state,
+                  const HT* seed_cov, double* xs_out, double* Cs_out, int32_t* lend_out, uint32_t* status) {
   Geo g = make_geo(og);
+  set_model(g, model);
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
   const int L = g.nl;
@@ -1551,20 +1574,20 @@ extern "C" {
 // Batched smoother.  Inputs as oracle_fit.  Outputs in float64: xs [L][6][n],
 // Cs [L][21][n] (packed lower triangle) for layers 0..lend[i] (zero elsewhere),
 // lend [n] (last layer with an update, -1 if none), status [n] (the forward fit's).
-void oracle_smooth(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
-                   const uint32_t* mask, int seed_from_hits_flag, const float* seed_state, const float* seed_cov,
-                   double* xs_out, double* Cs_out, int32_t* lend_out, uint32_t* status) {
-  smooth_batch<float>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, xs_out, Cs_out,
-                      lend_out, status);
+void oracle_smooth(const OGeom* og, const double* align, const double* xX0, const OModel* model, int64_t n,
+                   const float* hits, const uint32_t* mask, int seed_from_hits_flag, const float* seed_state,
+                   const float* seed_cov, double* xs_out, double* Cs_out, int32_t* lend_out, uint32_t* status) {
+  smooth_batch<float>(og, align, xX0, model, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, xs_out,
+                      Cs_out, lend_out, status);
 }
 
 // As oracle_smooth with float64 hits and seeds.
-void oracle_smooth_f64(const OGeom* og, const double* align, const double* xX0, int64_t n, const double* hits,
-                       const uint32_t* mask, int seed_from_hits_flag, const double* seed_state,
+void oracle_smooth_f64(const OGeom* og, const double* align, const double* xX0, const OModel* model, int64_t n,
+                       const double* hits, const uint32_t* mask, int seed_from_hits_flag, const double* seed_state,
                        const double* seed_cov, double* xs_out, double* Cs_out, int32_t* lend_out,
                        uint32_t* status) {
-  smooth_batch<double>(og, align, xX0, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, xs_out, Cs_out,
-                       lend_out, status);
+  smooth_batch<double>(og, align, xX0, model, n, hits, mask, seed_from_hits_flag, seed_state, seed_cov, xs_out,
+                       Cs_out, lend_out, status);
 }
 
 }  // extern "C"

@@ -190,3 +190,33 @@ def test_rts_pass_over_given_filtered_estimates(oracle_lib):
     assert (r0["first"] == lend).all()
     assert not r0["state"][1:].any() and not r0["state"][:, :, lend < 0].any()
     np.testing.assert_array_equal(r0["state"][0][:, lend == 0], rec[0, :6][:, lend == 0])
+
+
+def test_smoothed_pulls_under_the_detector_model(oracle_lib):
+    """Tracks simulated through the material map with energy loss in the field
+    B_z(r, z), smoothed under the same model (each step's linearisation includes the
+    loss): the smoothed parameters at inner layers have unit pulls; smoothing under a
+    model without the loss biases the smoothed curvature of slow tracks at the inner
+    layers, where the momentum is highest."""
+    geom, ts, fld, mat = synth.field_workload(8000, material=True)
+    n = ts.hits.shape[2]
+    res = {}
+    for lab, m in (("model", mat), ("no loss", (mat[0], 0.0))):
+        sm = oracle.smooth(geom, ts.hits, ts.hit_mask, material=m, field=fld)
+        ok = (sm["status"] == 0) & (sm["lend"] == geom.n_layers - 1)
+        assert ok.mean() > 0.8
+        slow = ok & (ts.pt < 1.0)
+        for l in (2, 8):
+            xl, Cl = physics.project_to_surface(sm["state"][l], oracle.unpack_cov(sm["cov"][l]),
+                                                np.full(n, geom.radius[l]), geom.k_B * (1 + fld[0] * geom.radius[l] ** 2))
+            pl = physics.pulls(xl, Cl, ts.truth[l], idx=(3, 4, 5))
+            kq = pl[3][slow] * np.sign(ts.truth[l][3][slow])
+            res[(lab, l)] = ([(round(float(v[ok].mean()), 3), round(float(v[ok].std()), 3)) for v in pl.values()],
+                             round(float(kq.mean()), 3))
+    print(res)
+    for l in (2, 8):
+        pulls, kq = res[("model", l)]
+        for mean, width in pulls:
+            assert abs(mean) < 0.05 and abs(width - 1.0) < 0.05, (l, pulls)
+        assert abs(kq) < 0.15, (l, kq)
+    assert res[("no loss", 2)][1] > 0.6   # |kappa| overestimated at the inner layers without the loss (~1 sigma)
