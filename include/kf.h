@@ -193,11 +193,13 @@ int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop);
  *     (KF_ST_PROP_FAIL).  No straggling term.
  * kf_find (and kf_find_autotune) take the same model in every prediction of the
  * search and in the refit; a candidate whose particle stops ends there
- * (KF_ST_PROP_FAIL), holding its prediction transported to that layer.  While a map
- * or a nonzero loss is set, kf_smooth and kf_fit_backward return KF_E_UNSUPPORTED
- * (they model one x/X0 per layer and no loss).  KF_E_INVALID for a NULL context, a
- * negative or non-finite loss, nz out of range with a map, or a geometry with a
- * zhalf_cm that is not positive. */
+ * (KF_ST_PROP_FAIL), holding its prediction transported to that layer.  kf_smooth
+ * takes it in every step (the step's linearisation then includes the loss; the
+ * batch must have been fitted under the same setting).  While a map or a nonzero
+ * loss is set, kf_fit_backward returns KF_E_UNSUPPORTED (it differentiates one x/X0
+ * per layer and no loss).  KF_E_INVALID for a NULL context, a negative or non-finite
+ * loss, nz out of range with a map, or a geometry with a zhalf_cm that is not
+ * positive. */
 int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float eloss_gev_per_x0);
 
 /* Parameterised magnetic field of kf_fit (Sec. 3: a constant or parameterised field):
@@ -207,9 +209,9 @@ int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float elo
  * previous layer): its crossing and its transport Jacobian use that field, which the
  * Jacobian treats as constant over the step.  A seed built from hits converts the
  * three-hit curvature into kappa with the field at hit 0.  0, 0 (the default) is the
- * uniform field.  kf_find takes the same field in the search and the refit.  While
- * either coefficient is nonzero, kf_smooth and kf_fit_backward return
- * KF_E_UNSUPPORTED, as with a material model.
+ * uniform field.  kf_find and kf_smooth take the same field.  While either
+ * coefficient is nonzero, kf_fit_backward returns KF_E_UNSUPPORTED, as with a
+ * material model.
  * KF_E_INVALID for a NULL context or a non-finite coefficient; KF_E_UNSUPPORTED for a
  * nonzero coefficient when B_tesla is 0. */
 int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z);

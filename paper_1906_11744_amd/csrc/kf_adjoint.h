@@ -31,7 +31,7 @@ KFA_HD constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j
 // Per-layer constants; the float layout is that of the fit kernels' layer table.
 template <class T>
 struct Lay {
-  T r, cx, cy, dz, cphi, sphi, xX0, pad, zs, zo;  // pad, zs, zo: fields of the fit's table this code does not use
+  T r, cx, cy, dz, cphi, sphi, xX0, pad, zs, zo;  // pad: unused here; zs, zo: the material map's z bins (smoother)
 };
 
 template <class T>

@@ -590,7 +590,6 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
               const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !in || !fwd || !out) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
-  if (ctx->material()) return KF_E_UNSUPPORTED;  // the smoother's step assumes kappa is transported unchanged
   if (in->n == 0) return KF_OK;
   if (!in->hit_mask || !fwd->ndf || !fwd->status || !fwd->ckpt || !out->state || !out->cov || !out->first ||
       !out->last)
@@ -602,7 +601,8 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(ws);
   const float* align = params ? params->align : nullptr;
   const float* xX0 = params ? params->xX0 : nullptr;
-  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st, ctx->g.zhalf_cm,
+                             ctx->mat_nz) != hipSuccess)
     return KF_E_HIP;
   const kfd::Model md = model_of(ctx);
   kfi::SmoothArgs a;
@@ -622,6 +622,11 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
   a.cov = out->cov;
   a.first = out->first;
   a.last = out->last;
+  a.mat_map = ctx->mat_map;
+  a.mat_nz = ctx->mat_nz;
+  a.eloss = ctx->eloss;
+  a.fr = ctx->fr;
+  a.fz = ctx->fz;
   return kfi::launch_smooth(a, st, ctx->ev_start, ctx->ev_stop) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 

@@ -119,6 +119,11 @@ struct SmoothArgs {
   float* cov;      // [L][21][n]
   int32_t* first;  // [n]
   int32_t* last;   // [n]
+  // detector model (as in FitArgs): material map [nl][mat_nz] or null, loss, field
+  const float* mat_map = nullptr;
+  int32_t mat_nz = 0;
+  float eloss = 0.f;
+  float fr = 0.f, fz = 0.f;
 };
 
 // Cuts of the duplicate relations (kf_dedup_cuts of kf.h, copied).

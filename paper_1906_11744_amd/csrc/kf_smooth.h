@@ -73,24 +73,89 @@ KFA_HD void smoothed_state(const T xf[6], const T ds[6], T xs[6]) {
   xs[4] = wrap(xs[4]);
 }
 
+// The detector model of one step (Sec. 3), as the fit takes it: the material map's
+// row of the layer stepped to (null: that layer's x/X0), the mean ionisation loss per
+// radiation length and the field B_z(r, z) = B (1 + fr r^2 + fz z^2).
+template <class T>
+struct StepModel {
+  const float* row;
+  int nz;
+  T eloss, fr, fz;
+};
+
+// x/X0 of a layer at z (global) from its map row: linear between the centres of nz
+// equal bins over [-Z, Z] of the layer's frame (u = (z - dz) zs + zo, in bins),
+// constant beyond the outer centres.
+template <class T>
+KFA_HD T map_value(const float* row, int nz, const kfa::Lay<T>& ly, T z) {
+  if (nz == 1) return (T)row[0];
+  T u = (z - ly.dz) * ly.zs + ly.zo;
+  u = u < T(0) ? T(0) : (u > T(nz - 1) ? T(nz - 1) : u);
+  int b = (int)u;
+  if (b > nz - 2) b = nz - 2;
+  const T t = u - (T)b;
+  const T v0 = (T)row[b];
+  return v0 + t * ((T)row[b + 1] - v0);
+}
+
+// The mean energy loss at a predicted state as a map of kappa: kappa' = g kappa with
+// g = p / p', and its derivatives D = dkappa'/dkappa, Tt = dkappa'/dtheta (the path
+// length x/X0 / (sin theta |cos alpha|) held fixed), written without cancellation:
+// with W = p X / p'^3 and X = dE (m^2/E + E') + 2 eloss x_eff m^2 E' / p^2,
+// D = p/p' + W and Tt = kappa cot(theta) W.  False if the particle stops.
+template <class T>
+KFA_HD bool loss_map(T kap, T st, T ct, T cosa, T xx, T eloss, T mass2, T& g, T& D, T& Tt) {
+  using std::fabs; using std::sqrt;
+  const T ks = fabs(kap) * st;
+  const T p = T(1) / ks;
+  const T c = eloss * xx / (st * fabs(cosa));
+  const T ib2 = T(1) + mass2 * ks * ks;
+  const T E = p * sqrt(ib2);
+  const T dE = c * ib2;
+  const T E1 = E - dE;
+  const T q2 = E1 * E1 - mass2;
+  if (!(E1 > T(0)) || !(q2 > T(0))) return false;
+  const T ip1 = T(1) / sqrt(q2);
+  const T X = dE * (mass2 / E + E1) + T(2) * c * mass2 * E1 * ks * ks;
+  const T W = p * X * (ip1 * ip1 * ip1);
+  g = p * ip1;
+  D = g + W;
+  Tt = kap * (ct / st) * W;
+  return true;
+}
+
 // One step in place: on entry (ds, Cs) is the smoothed estimate at layer l + 1 (ds its
 // offset from the filtered state xf1 there), on return the one at layer l (ds the
 // offset from xf).  xf, Cf: filtered estimate at l (packed lower C); ly1: the
-// constants of layer l + 1.  Returns false (ds, Cs unchanged) if layer l + 1 is not
-// reached from x_f or C_p is not positive definite.
+// constants of layer l + 1; sm: the detector model of the step (null: one x/X0 per
+// layer, uniform field).  Returns false (ds, Cs unchanged) if layer l + 1 is not
+// reached from x_f, the particle stops in its material, or C_p is not positive
+// definite.
+// With energy loss the step's linearisation is A J, A the identity but for the kappa
+// row (D, Tt of loss_map), and C_p = A (J C_f J^T + Q) A^T, so the gain is
+// G = C_f J^T (J C_f J^T + Q)^-1 A^-1: the step below, written for A = I, applies
+// unchanged to A^-1 (x_s1 - x_p) and A^-1 C_s1 A^-T.
 template <class T>
 KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::Lay<T>& ly1,
-                     const kfa::Consts<T>& k, T ds[6], T Cs[21]) {
+                     const kfa::Consts<T>& k0, T ds[6], T Cs[21], const StepModel<T>* sm = nullptr) {
   using std::sqrt;
+  kfa::Consts<T> k = k0;
+  if (sm) k.kB = k0.kB * (T(1) + sm->fr * (xf[0] * xf[0] + xf[1] * xf[1]) + sm->fz * xf[2] * xf[2]);
   kfa::Prop<T> P;
   T xp[6];
   if (!kfa::propagate(xf, ly1, k, P, xp)) return false;
+  kfa::Lay<T> lym = ly1;
+  if (sm && sm->row) lym.xX0 = map_value<T>(sm->row, sm->nz, ly1, xp[2]);
+  T gl = T(1), Dl = T(1), Tl = T(0);
+  const bool loss = sm && sm->eloss > T(0) && lym.xX0 > T(0);
   T Q[21];
-  const kfa::Frm<T> fr = kfa::frame(xp, ly1);
+  const kfa::Frm<T> fr = kfa::frame(xp, lym);
+  if (loss && !loss_map<T>(xp[3], P.st, P.ct, fr.rx * P.cpe + fr.ry * P.spe, lym.xX0, sm->eloss, k.mass2, gl, Dl, Tl))
+    return false;
   kfa::Scat<T> S;
 #pragma unroll
   for (int q = 0; q < 21; ++q) Q[q] = T(0);
-  kfa::scatter(xp, fr, ly1, k, S, Q);  // Q alone: (kappa, phi, theta) block
+  kfa::scatter(xp, fr, lym, k, S, Q);  // Q alone: (kappa, phi, theta) block
   // J = I + N and J^-1 = I - N + N^2, as dense 6x6
   T N[6][6];
 #pragma unroll
@@ -239,9 +304,19 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
   d[0] = ds[0] + ((xf1[0] - xf[0]) - P.dx);
   d[1] = ds[1] + ((xf1[1] - xf[1]) - P.dy);
   d[2] = ds[2] + ((xf1[2] - xf[2]) - P.s * P.ct / P.st);
-  d[3] = ds[3] + (xf1[3] - xf[3]);
+  d[3] = ds[3] + (xf1[3] - gl * xf[3]);  // x_p's kappa: the loss scales the filtered one
   d[4] = ds[4] + (wrap(xf1[4] - xf[4]) - P.u);
   d[5] = ds[5] + (xf1[5] - xf[5]);
+  if (loss) {  // back through the loss: d <- A^-1 d, C_s1 <- A^-1 C_s1 A^-T
+    const T iD = T(1) / Dl, a = Tl * iD;
+    d[3] = iD * d[3] - a * d[5];
+    const T c33 = Cs[tri(3, 3)], c53 = Cs[tri(5, 3)], c55 = Cs[tri(5, 5)];
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j != 3) Cs[tri(3, j)] = iD * Cs[tri(3, j)] - a * Cs[tri(5, j)];
+    Cs[tri(5, 3)] = iD * c53 - a * c55;
+    Cs[tri(3, 3)] = iD * iD * c33 - T(2) * iD * a * c53 + a * a * c55;
+  }
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     T a = T(0);

@@ -6,6 +6,8 @@
 
 namespace kfi {
 
+// kModel: each step under the detector model (material map, energy loss, field).
+template <bool kModel>
 __global__ __launch_bounds__(64) void smooth_kernel(SmoothArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (i >= a.n) return;
@@ -52,7 +54,8 @@ __global__ __launch_bounds__(64) void smooth_kernel(SmoothArgs a) {
 #pragma unroll
       for (int q = 0; q < 21; ++q) Cs[q] = Cf[q];
     } else if (live) {
-      if (kfs::rts_step<float>(xf, Cf, xf1, lays[l + 1], a.k, ds, Cs))
+      kfs::StepModel<float> sm{a.mat_map ? a.mat_map + (l + 1) * a.mat_nz : nullptr, a.mat_nz, a.eloss, a.fr, a.fz};
+      if (kfs::rts_step<float>(xf, Cf, xf1, lays[l + 1], a.k, ds, Cs, kModel ? &sm : nullptr))
         first = l;
       else
         live = false;
@@ -69,12 +72,21 @@ __global__ __launch_bounds__(64) void smooth_kernel(SmoothArgs a) {
   a.last[i] = lend;
 }
 
-hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  const int64_t nb = (a.n + 63) / 64;
+template <bool kModel>
+void launch_smooth_variant(const SmoothArgs& a, unsigned nb, hipStream_t stream, hipEvent_t ev_start,
+                           hipEvent_t ev_stop) {
   if (ev_start && ev_stop)  // timing hook: the events bracket the kernel's own execution
-    hipExtLaunchKernelGGL(smooth_kernel, dim3((unsigned)nb), dim3(64), 0, stream, ev_start, ev_stop, 0, a);
+    hipExtLaunchKernelGGL((smooth_kernel<kModel>), dim3(nb), dim3(64), 0, stream, ev_start, ev_stop, 0, a);
   else
-    hipLaunchKernelGGL(smooth_kernel, dim3((unsigned)nb), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((smooth_kernel<kModel>), dim3(nb), dim3(64), 0, stream, a);
+}
+
+hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const unsigned nb = (unsigned)((a.n + 63) / 64);
+  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
+    launch_smooth_variant<true>(a, nb, stream, ev_start, ev_stop);
+  else
+    launch_smooth_variant<false>(a, nb, stream, ev_start, ev_stop);
   return hipGetLastError();
 }
 

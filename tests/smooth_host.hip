@@ -7,10 +7,13 @@
 
 #include "../paper_1906_11744_amd/csrc/kf_smooth.h"
 
+// map [nl][nz] (float32, null: none), zhalf [nl], eloss, fr, fz: the detector model;
+// use_model = 0 runs the plain step.
 template <class T>
 static int smooth_host(int nl, const double* radius, double B, double srphi, double sz, double sr, double mass,
                        const double* align, const double* xX0, long n, const double* rec, const int* lend,
-                       double* xs_out, double* Cs_out) {
+                       double* xs_out, double* Cs_out, int use_model = 0, const float* map = nullptr, int nz = 0,
+                       const double* zhalf = nullptr, double eloss = 0.0, double fr = 0.0, double fz = 0.0) {
   kfa::Consts<T> k;
   k.kB = (T)(0.299792458e-2 * B);
   k.v_r = (T)(sr * sr);
@@ -27,6 +30,8 @@ static int smooth_host(int nl, const double* radius, double B, double srphi, dou
     lays[l].sphi = (T)std::sin(align[4 * l + 3]);
     lays[l].xX0 = (T)xX0[l];
     lays[l].pad = 0;
+    lays[l].zs = (map && nz > 1) ? (T)((double)nz / (2.0 * zhalf[l])) : T(0);
+    lays[l].zo = (T)(0.5 * nz - 0.5);
   }
   int bad = 0;
   for (long i = 0; i < n; ++i) {
@@ -46,7 +51,8 @@ static int smooth_host(int nl, const double* radius, double B, double srphi, dou
       T xf[6], Cf[21];
       for (int q = 0; q < 6; ++q) xf[q] = (T)r[(long)l * 27 + q];
       for (int q = 0; q < 21; ++q) Cf[q] = (T)r[(long)l * 27 + 6 + q];
-      if (!kfs::rts_step<T>(xf, Cf, xf1, lays[l + 1], k, ds, Cs1)) {
+      kfs::StepModel<T> sm{map ? map + (long)(l + 1) * nz : nullptr, nz, (T)eloss, (T)fr, (T)fz};
+      if (!kfs::rts_step<T>(xf, Cf, xf1, lays[l + 1], k, ds, Cs1, use_model ? &sm : nullptr)) {
         ++bad;
         break;
       }
@@ -68,4 +74,20 @@ extern "C" int smooth_host_f64(int nl, const double* radius, double B, double sr
                                double mass, const double* align, const double* xX0, long n, const double* rec,
                                const int* lend, double* xs_out, double* Cs_out) {
   return smooth_host<double>(nl, radius, B, srphi, sz, sr, mass, align, xX0, n, rec, lend, xs_out, Cs_out);
+}
+
+extern "C" int smooth_host_model_f32(int nl, const double* radius, double B, double srphi, double sz, double sr,
+                                     double mass, const double* align, const double* xX0, long n, const double* rec,
+                                     const int* lend, double* xs_out, double* Cs_out, const float* map, int nz,
+                                     const double* zhalf, double eloss, double fr, double fz) {
+  return smooth_host<float>(nl, radius, B, srphi, sz, sr, mass, align, xX0, n, rec, lend, xs_out, Cs_out, 1, map, nz,
+                            zhalf, eloss, fr, fz);
+}
+
+extern "C" int smooth_host_model_f64(int nl, const double* radius, double B, double srphi, double sz, double sr,
+                                     double mass, const double* align, const double* xX0, long n, const double* rec,
+                                     const int* lend, double* xs_out, double* Cs_out, const float* map, int nz,
+                                     const double* zhalf, double eloss, double fr, double fz) {
+  return smooth_host<double>(nl, radius, B, srphi, sz, sr, mass, align, xX0, n, rec, lend, xs_out, Cs_out, 1, map, nz,
+                             zhalf, eloss, fr, fz);
 }

@@ -163,9 +163,9 @@ def test_dedup_calls_reject_bad_arguments_before_launch():
 
 def test_material_setting_validation_and_the_calls_it_excludes():
     """kf_ctx_set_material stores its arguments (no device work here); while a map or
-    a loss is set, the smoother and the adjoint refuse before launching (the finder
-    takes the model and goes on to its own checks), and clearing the setting lets
-    their own validation run again."""
+    a loss is set, the adjoint refuses before launching (the finder and the smoother
+    take the model and go on to their own checks), and clearing the setting lets its
+    own validation run again."""
     kf, lib = _lib()
     ctx = kf.Context(synth.workload_geometry(2))
     fake = C.c_void_p(0x1000)   # never dereferenced: no kf_fit is called here
@@ -190,7 +190,7 @@ def test_material_setting_validation_and_the_calls_it_excludes():
     assert codes() == (-3, -3, -3)
     for args in ((fake, 1, 0.0), (fake, 64, 0.0363), (None, 0, 0.0363)):
         assert lib.kf_ctx_set_material(ctx._h, args[0], args[1], C.c_float(args[2])) == 0
-        assert codes() == (-3, -2, -2), args
+        assert codes() == (-3, -3, -2), args
     assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
     assert codes() == (-3, -3, -3)
 
@@ -206,12 +206,13 @@ def test_field_setting_validation_and_the_calls_it_excludes():
     fit_in = kf.FitIn(10, fake, fake, None, None, 1)
     fit_out = kf.FitOut(fake, fake, fake, fake, fake, fake)
     so = kf.SmoothOut(fake, fake, fake, fake)
-    smooth = lambda: lib.kf_smooth(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), C.byref(so), None, 0, None)
-    assert smooth() == -3
+    back = lambda: lib.kf_fit_backward(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), fake, fake, fake,
+                                       None, 0, None)
+    assert back() == -3
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(-1e-6), C.c_float(-4e-6)) == 0
-    assert smooth() == -2
+    assert back() == -2
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(0.0)) == 0
-    assert smooth() == -3
+    assert back() == -3
     g0 = synth.workload_geometry(2)
     g0.B = 0.0
     ctx0 = kf.Context(g0)

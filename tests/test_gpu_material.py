@@ -163,7 +163,49 @@ def test_constant_map_without_loss_is_the_layer_model():
     assert cov_err(g["cov"], plain["cov"].astype(np.float64))[ok].max() < 1e-6
 
 
-def test_material_excludes_smooth_and_adjoint():
+def test_smoother_under_the_detector_model():
+    """kf_smooth after a checkpointing fit, both under the whole model (map, loss,
+    field), against the oracle's RTS pass over the GPU's own checkpoints (the step:
+    1e-4 / 1e-4) and against the oracle's own fit and smoother (end to end: 2e-4 /
+    5e-4, the bars of the plain smoother and for the same reasons)."""
+    from gpu_common import cov_err as _ce
+    need_gpu()
+    from paper_1906_11744_amd import Context
+    geom, ts, fld, mat = synth.field_workload(3000, material=True)
+    ctx = Context(geom)
+    ctx.set_material(to_dev(np.asarray(mat[0], np.float32)), mat[1])
+    ctx.set_field(*fld)
+    hits, mask = to_dev(ts.hits), mask_dev(ts.hit_mask)
+    x = to_dev(geom.xX0.astype(np.float32))
+    fwd = ctx.fit(hits, mask, xX0=x, ckpt=True)
+    out = ctx.smooth(hits, mask, fwd, xX0=x)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    ck = fwd["ckpt"].cpu().numpy()
+    m, f = _oracle_material(mat), _oracle_field(fld)
+    r = oracle.smooth(geom, ts.hits, ts.hit_mask, material=m, field=f)
+    s = oracle.smooth_filtered(geom, ck[:, :6], ck[:, 6:], g["last"], material=m, field=f)
+    lend = r["lend"]
+    ok = (r["status"] & (oracle.ST_NEAR_TANGENT | oracle.ST_PROP_FAIL)) == 0
+    np.testing.assert_array_equal(g["last"][ok], lend[ok])
+    assert np.all(g["first"][ok & (lend >= 0)] == 0)
+    np.testing.assert_array_equal(s["first"][ok], g["first"][ok])
+    wx = wc = ex = ec = 0.0
+    for l in range(geom.n_layers):
+        sel = ok & (lend >= l)
+        if not sel.any():
+            continue
+        wx = max(wx, rel_state_err(g["state"][l][:, sel], s["state"][l][:, sel]).max())
+        wc = max(wc, _ce(g["cov"][l][:, sel], s["cov"][l][:, sel]).max())
+        ex = max(ex, rel_state_err(g["state"][l][:, sel], r["state"][l][:, sel]).max())
+        ec = max(ec, _ce(g["cov"][l][:, sel], r["cov"][l][:, sel]).max())
+    print(f"[smoother under the detector model] n={ok.sum()} step: state {wx:.2e} cov {wc:.2e}; "
+          f"end to end: state {ex:.2e} cov {ec:.2e}")
+    assert wx < 1e-4 and wc < 1e-4
+    assert ex < 2e-4 and ec < 5e-4
+
+
+def test_material_excludes_the_adjoint():
     need_gpu()
     from paper_1906_11744_amd import Context, kf
     geom, ev = synth.find_workload(3, n_tracks=50)
@@ -173,10 +215,8 @@ def test_material_excludes_smooth_and_adjoint():
     _, ts = synth.fit_workload(2, n=100)
     fwd = ctx.fit(to_dev(ts.hits), mask_dev(ts.hit_mask), ckpt=True)
     with pytest.raises(kf.KfError) as e:
-        ctx.smooth(to_dev(ts.hits), mask_dev(ts.hit_mask), fwd)
-    assert e.value.code == -2
-    with pytest.raises(kf.KfError):
         ctx.fit_backward(to_dev(ts.hits), mask_dev(ts.hit_mask), fwd, torch.ones(100, device="cuda"))
+    assert e.value.code == -2
     ctx.set_material(None, 0.0)
     ctx.find(t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
     torch.cuda.synchronize()

@@ -82,3 +82,45 @@ def test_library_step_against_oracle_pass(host_smooth, kind):
         print(f"[{fn}, {kind}] max rel state err {wx:.2e}, max cov err {wc:.2e}")
     assert worst["smooth_host_f64"][0] < 1e-9 and worst["smooth_host_f64"][1] < 1e-7
     assert worst["smooth_host_f32"][0] < 1e-4 and worst["smooth_host_f32"][1] < 1e-4
+
+
+def test_library_step_under_the_detector_model(host_smooth):
+    """The same check under the detector model (16-bin material map, silicon's energy
+    loss, the field B_z(r, z)): the oracle's pass takes each step's linearisation as
+    A J with the loss's kappa row in A; the library's step maps the next layer's
+    smoothed estimate back through A^-1 and applies the plain form."""
+    geom, ts, fld, mat = synth.field_workload(3000, material=True)
+    xmap32 = np.ascontiguousarray(mat[0], np.float32)
+    m = (xmap32.astype(np.float64), float(np.float32(mat[1])))
+    align = np.zeros((geom.n_layers, 4))
+    sm = oracle.smooth(geom, ts.hits, ts.hit_mask, material=m, field=fld)
+    o = oracle.fit(geom, ts.hits, ts.hit_mask, records=True, material=m, field=fld)
+    lend = np.ascontiguousarray(sm["lend"], np.int32)
+    rec = np.ascontiguousarray(o["records"].astype(np.float32).astype(np.float64))
+    recT = np.transpose(rec, (1, 2, 0))
+    ref = oracle.smooth_filtered(geom, recT[:, :6], recT[:, 6:], lend, material=m, field=fld)
+    ok = ((sm["status"] & (oracle.ST_NEAR_TANGENT | oracle.ST_PROP_FAIL)) == 0) & (ref["first"] == 0)
+    assert ok.mean() > 0.9
+    L, n = geom.n_layers, lend.size
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    f64 = lambda a: np.ascontiguousarray(a, np.float64)
+    worst = {}
+    for fn in ("smooth_host_model_f64", "smooth_host_model_f32"):
+        xs, Cs = np.zeros((L, 6, n)), np.zeros((L, 21, n))
+        bad = getattr(host_smooth, fn)(C.c_int(L), p(f64(geom.radius)), C.c_double(geom.B), C.c_double(geom.sigma_rphi),
+                                       C.c_double(geom.sigma_z), C.c_double(geom.sigma_r), C.c_double(geom.mass),
+                                       p(f64(align)), p(f64(geom.xX0)), C.c_long(n), p(rec), p(lend), p(xs), p(Cs),
+                                       p(xmap32), C.c_int(xmap32.shape[1]), p(f64(geom.zhalf)), C.c_double(m[1]),
+                                       C.c_double(fld[0]), C.c_double(fld[1]))
+        assert bad == 0
+        wx, wc = 0.0, 0.0
+        for l in range(L):
+            sel = ok & (lend >= l)
+            if not sel.any():
+                continue
+            wx = max(wx, rel_state_err(xs[l][:, sel], ref["state"][l][:, sel]).max())
+            wc = max(wc, cov_err(Cs[l][:, sel], ref["cov"][l][:, sel]).max())
+        worst[fn] = (wx, wc)
+        print(f"[{fn}] max rel state err {wx:.2e}, max cov err {wc:.2e}")
+    assert worst["smooth_host_model_f64"][0] < 1e-9 and worst["smooth_host_model_f64"][1] < 1e-7
+    assert worst["smooth_host_model_f32"][0] < 1e-4 and worst["smooth_host_model_f32"][1] < 1e-4
