@@ -56,8 +56,8 @@ FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csr
 
 
 # The same for one smooth_kernel launch on that workload.
-SMOOTH_TRAFFIC = {"sources": "1974d8e7b6eb5506", "tracks": 1_000_000,
-                  "fetch_kib": 907275.0, "write_kib": 1800781.3,
+SMOOTH_TRAFFIC = {"sources": "b634566cde116de5", "tracks": 1_000_000,
+                  "fetch_kib": 907966.7, "write_kib": 1800781.3,
                   "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 SMOOTH_SOURCES = ("paper_1906_11744_amd/csrc/kf_smooth.hip", "paper_1906_11744_amd/csrc/kf_smooth.h",
                   "paper_1906_11744_amd/csrc/kf_adjoint.h")
@@ -376,6 +376,17 @@ def bench_material(steps, warmup):
     t_fp = _time_launches(lambda: ctx.find(*args, xX0=xX0, out=fout), steps, warmup).region
     res["find_one_event_5000_tracks"] = {"events_per_s": 1.0 / t_fm, "ms_per_event": t_fm * 1e3,
                                          "ms_per_event_one_xX0_per_layer_uniform_field": t_fp * 1e3}
+    # the smoother over the 1e6-track fit under the whole model, against the plain model
+    ctx.set_material(dmap, eloss)
+    ctx.set_field(*fld)
+    fwd = ctx.fit(hits, mask, xX0=xX0, ckpt=True)
+    sout = ctx.smooth(hits, mask, fwd, xX0=xX0)
+    t_sm = _time_kernel(ctx, lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=sout), steps, warmup)
+    ctx.set_material(None, 0.0)
+    ctx.set_field(0.0, 0.0)
+    fwd = ctx.fit(hits, mask, xX0=xX0, ckpt=True, out=fwd)
+    t_sp = _time_kernel(ctx, lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=sout), steps, warmup)
+    res["smooth_1e6_tracks"] = {"kernel_ms": t_sm * 1e3, "kernel_ms_one_xX0_per_layer_uniform_field": t_sp * 1e3}
     return res
 
 
