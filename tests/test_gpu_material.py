@@ -108,11 +108,12 @@ def test_material_1e6_tracks_sampled():
     _compare(g, ref, "1e6 tracks with map + loss (sample)", idx=idx)
 
 
-@pytest.mark.parametrize("part", ["map_only", "loss_only", "one_bin_map"])
+@pytest.mark.parametrize("part", ["map_only", "loss_only", "one_bin_map", "max_bins_map"])
 def test_material_parts(part):
     geom, ts, mat = synth.material_workload(3000)
     m = {"map_only": (mat[0], 0.0), "loss_only": (None, mat[1]),
-         "one_bin_map": (mat[0][:, :1].copy(), mat[1])}[part]
+         "one_bin_map": (mat[0][:, :1].copy(), mat[1]),
+         "max_bins_map": (synth.material_map(geom, 64), mat[1])}[part]   # KF_MAX_MAP_BINS
     g = _fit(geom, ts, m)
     ref = oracle.fit(geom, ts.hits, ts.hit_mask, material=_oracle_material(m))
     _compare(g, ref, part)
