@@ -1,19 +1,24 @@
 /*
  * kf.h -- C ABI of the MI355X (gfx950) batched Kalman-filter track fit, combinatorial
- * track finder and adjoint of the fit.
+ * track finder, adjoint of the fit, fixed-interval smoother and duplicate handling.
  *
  * The method: charged-particle tracks are fitted and built with the Kalman filter,
  * layer by layer, on symmetric 6x6 covariances, with search windows and candidate
  * scores for building and radiation lengths of every layer for multiple scattering
- * (paper, Sec. 2 and Sec. 3; window sizes and scores, Sec. 4.3).  The paper prints no
- * formulas; the library implements the readings stated with each call below.
+ * (paper, Sec. 2 and Sec. 3; window sizes and scores, Sec. 4.3); the chain ends with
+ * duplicate removal and a backward pass (Sec. 4.2, Sec. 5).  Beyond one x/X0 per layer
+ * and a uniform field, a context can carry the detector model of Sec. 3 (a material
+ * map in (layer, z), energy loss, a parameterised field: kf_ctx_set_material,
+ * kf_ctx_set_field).  The paper prints no formulas; the library implements the
+ * readings stated with each call below.
  *
  * Conventions for every call
  *   - Array arguments are DEVICE pointers owned by the caller, float32 structure of
  *     arrays ("[A][B][n]" means element (a, b, i) is at (a * B + b) * n + i).
  *   - Track state (x, y, z, kappa = q/pT, phi, theta) in cm, 1/GeV, rad; the field is
- *     uniform along +z; omega = -0.299792458e-2 * B * kappa is the signed turning rate
- *     per unit transverse arc length.
+ *     along +z, uniform unless kf_ctx_set_field parameterises it; omega =
+ *     -0.299792458e-2 * B * kappa is the signed turning rate per unit transverse arc
+ *     length.
  *   - Covariances are packed lower triangles: element (i >= j) at i * (i + 1) / 2 + j.
  *   - Layer L is an infinite cylinder of radius radius_cm[L]; its alignment
  *     align[L] = (dx, dy, dz, dphi) moves its axis to (dx, dy), shifts its hits by dz
