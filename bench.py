@@ -568,6 +568,17 @@ def main():
                          "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                          "frac_unpacked": achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS},
         }
+        # the small configuration (1 000 tracks, 10 layers, no material): 16 waves on
+        # 1 024 SIMDs, so a launch is latency-bound; reported per call, not as a roofline
+        g1, ts1 = synth.fit_workload(1)
+        ctx1 = Context(g1)
+        h1 = torch.from_numpy(np.ascontiguousarray(ts1.hits)).to(dev)
+        m1 = torch.from_numpy(ts1.hit_mask.view(np.int32)).to(dev)
+        o1 = ctx1.fit(h1, m1)
+        tm1 = _time_launches(lambda: ctx1.fit(h1, m1, out=o1), args.steps, args.warmup)
+        t1 = _time_kernel(ctx1, lambda: ctx1.fit(h1, m1, out=o1), args.steps, args.warmup)
+        res["fit_1000_tracks_10_layers"] = {"us_per_call": tm1.region * 1e6, "us_kernel": t1 * 1e6,
+                                            "us_per_call_with_per_call_events": tm1.per_launch * 1e6}
         if not args.no_cpu_baseline:
             # the oracle over the whole workload, pass after pass, until 10 s have elapsed
             import oracle
