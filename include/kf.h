@@ -214,9 +214,10 @@ int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float elo
  * previous layer): its crossing and its transport Jacobian use that field, which the
  * Jacobian treats as constant over the step.  A seed built from hits converts the
  * three-hit curvature into kappa with the field at hit 0.  0, 0 (the default) is the
- * uniform field.  kf_find and kf_smooth take the same field.  While either
- * coefficient is nonzero, kf_fit_backward returns KF_E_UNSUPPORTED, as with a
- * material model.
+ * uniform field.  kf_find and kf_smooth take the same field.  kf_fit_backward takes
+ * it too: its gradient holds each step's field (and the seed's) at its value, the
+ * derivative of the fit with those fields fixed; the field's own change under the
+ * parameters is left out.
  * KF_E_INVALID for a NULL context or a non-finite coefficient; KF_E_UNSUPPORTED for a
  * nonzero coefficient when B_tesla is 0. */
 int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z);
@@ -292,7 +293,9 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
  * given dchi2 [n] = dLoss/dchi2_i, accumulates dLoss/dalign [L][4] and dLoss/dxX0 [L]
  * (overwritten, float32) by a reverse sweep over each track's layers that recomputes
  * every step from its checkpoint.  The paper has no differentiation; this is the
- * vector-Jacobian product of the fit as implemented by kf_fit. */
+ * vector-Jacobian product of the fit as implemented by kf_fit.  Under a parameterised
+ * field (kf_ctx_set_field) each step's field is held at its value; KF_E_UNSUPPORTED
+ * while a material map or an energy loss is set (kf_ctx_set_material). */
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream);
 

@@ -288,24 +288,28 @@ def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, 
     return out
 
 
-def total_chi2(geom, hits, mask, align, xX0, weight=None):
+def total_chi2(geom, hits, mask, align, xX0, weight=None, field=None):
     hits = np.ascontiguousarray(hits, np.float32)
     mask = np.ascontiguousarray(mask, np.uint32)
     g = ogeom(geom)
+    fr, fz = (0.0, 0.0) if field is None else (float(field[0]), float(field[1]))
     return load().oracle_total_chi2(C.byref(g), _p(_f64(align)), _p(_f64(xX0)), C.c_int64(hits.shape[2]),
-                                    _p(hits), _p(mask), _p(_f64(weight)))
+                                    _p(hits), _p(mask), _p(_f64(weight)), C.c_double(fr), C.c_double(fz))
 
 
-def fit_grad(geom, hits, mask, align, xX0, weight=None):
-    """FP64 gradient of sum_i weight_i chi2_i w.r.t. align [L][4] and xX0 [L] (dual numbers)."""
+def fit_grad(geom, hits, mask, align, xX0, weight=None, field=None):
+    """FP64 gradient of sum_i weight_i chi2_i w.r.t. align [L][4] and xX0 [L] (dual
+    numbers).  field = (c_r, c_z): the parameterised field, each step's value held
+    fixed in the derivative."""
     hits = np.ascontiguousarray(hits, np.float32)
     mask = np.ascontiguousarray(mask, np.uint32)
     L = hits.shape[0]
     ga = np.zeros((L, 4))
     gx = np.zeros(L)
     g = ogeom(geom)
+    fr, fz = (0.0, 0.0) if field is None else (float(field[0]), float(field[1]))
     load().oracle_fit_grad(C.byref(g), _p(_f64(align)), _p(_f64(xX0)), C.c_int64(hits.shape[2]), _p(hits),
-                           _p(mask), _p(_f64(weight)), _p(ga), _p(gx))
+                           _p(mask), _p(_f64(weight)), _p(ga), _p(gx), C.c_double(fr), C.c_double(fz))
     return ga, gx
 
 

@@ -921,8 +921,10 @@ void oracle_fit_f64(const OGeom* og, const double* align, const double* xX0, int
 // Weighted total chi2, sum_i weight[i] * chi2_i (weight may be null: all ones),
 // summed in track order, seeds built from hits.  For central finite differences.
 double oracle_total_chi2(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
-                         const uint32_t* mask, const double* weight) {
+                         const uint32_t* mask, const double* weight, double fr, double fz) {
   Geo g = make_geo(og);
+  g.fr = fr;
+  g.fz = fz;
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
   std::vector<double> c(n);
@@ -939,10 +941,16 @@ double oracle_total_chi2(const OGeom* og, const double* align, const double* xX0
 // Gradient of sum_i weight[i] chi2_i with respect to align [L][4] and xX0 [L], by
 // forward-mode dual numbers through the whole fit (seeds built from the placed
 // hits), one layer's five parameters per pass.
+// fr, fz: the parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2).  Each step's field
+// (at its start; the seed's at hit 0) enters as a value, not as a function of the
+// parameters: the gradient holds the field seen by each step fixed.
 void oracle_fit_grad(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
-                     const uint32_t* mask, const double* weight, double* g_align, double* g_xX0) {
+                     const uint32_t* mask, const double* weight, double* g_align, double* g_xX0, double fr,
+                     double fz) {
   using D = Dual<5>;
   Geo g = make_geo(og);
+  g.fr = fr;
+  g.fz = fz;
   for (int pl = 0; pl < g.nl; ++pl) {
     D al[32 * 4], xx[32];
     for (int l = 0; l < g.nl; ++l) {

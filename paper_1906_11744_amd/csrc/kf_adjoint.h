@@ -666,6 +666,21 @@ KFA_HD void seed_cov(T srphi, T sz, T dr02, T kB, T C[21]) {
   C[tri(5, 5)] = T(10) * sth * sth;
 }
 
+// The parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2) (Sec. 3), with what the
+// seed covariance needs to follow it.  Each step takes the field at its start and the
+// seed at its first hit; the sweep holds these values fixed, so the gradient omits the
+// field's own change under the parameters.
+template <class T>
+struct FieldK {
+  T fr, fz;
+  T srphi, sz, dr02;
+};
+
+template <class T>
+KFA_HD T field_kB(const Consts<T>& k, const FieldK<T>& f, T x, T y, T z) {
+  return k.kB * (T(1) + f.fr * (x * x + y * y) + f.fz * z * z);
+}
+
 template <class T>
 KFA_HD void place(const Lay<T>& ly, T hx, T hy, T hz, T m[3]) {
   m[0] = ly.cx + ly.cphi * hx - ly.sphi * hy;
@@ -682,11 +697,13 @@ KFA_HD void place(const Lay<T>& ly, T hx, T hy, T hz, T m[3]) {
 //                    the same ltop visit the same layer in every iteration;
 //   emit(l, g[5])    gradient contribution of layer l (d/d cx, cy, dz, dphi, xX0),
 //                    called once per layer from lstart down to 0, then for 1 and 2
-//                    again with the seed's share.
+//                    again with the seed's share;
+//   fk               null: the uniform field of k, with seed covariance Cs; else the
+//                    parameterised field (Cs is then recomputed for the seed's field).
 // Returns false if a recomputed step fails (no contribution then).
 template <class T, class Hit, class Ckpt, class Emit>
 KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lays, const Consts<T>& k,
-                          const T Cs[21], T w, Hit hit, Ckpt ckpt, Emit emit) {
+                          const T Cs[21], T w, Hit hit, Ckpt ckpt, Emit emit, const FieldK<T>* fk = nullptr) {
   T xb[6] = {0, 0, 0, 0, 0, 0};
   T Cb[21];
   for (int q = 0; q < 21; ++q) Cb[q] = T(0);
@@ -695,14 +712,16 @@ KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lay
     const Lay<T>& ly = lays[l];
     T x[6], C[21];
     ckpt(l - 1, x, C);
+    Consts<T> ks = k;
+    if (fk) ks.kB = field_kB(k, *fk, x[0], x[1], x[2]);  // the field at the step's start
     Prop<T> P;
     T xp[6];
-    if (!propagate(x, ly, k, P, xp)) return false;
+    if (!propagate(x, ly, ks, P, xp)) return false;
     T B[6][6], Cp[21];
     transport_cov(P, C, B, Cp);
     const Frm<T> fr = frame(xp, ly);
     Scat<T> Q;
-    scatter(xp, fr, ly, k, Q, Cp);
+    scatter(xp, fr, ly, ks, Q, Cp);
     T g[5] = {0, 0, 0, 0, 0};
     if ((mask >> l) & 1u) {
       T h[3], m[3];
@@ -712,13 +731,13 @@ KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lay
       T xu[6], Cu[21];
       for (int q = 0; q < 6; ++q) xu[q] = xp[q];
       for (int q = 0; q < 21; ++q) Cu[q] = Cp[q];
-      update(xu, Cu, ly, k, m[0], m[1], m[2], U);
+      update(xu, Cu, ly, ks, m[0], m[1], m[2], U);
       T mb[3] = {0, 0, 0};
       update_adj(xp, Cp, U, w, xb, Cb, mb[0], mb[1], mb[2], g[0], g[1]);
       place_adj(ly, h[0], h[1], mb[0], mb[1], mb[2], g);
     }
-    scatter_adj(xp, fr, ly, k, Q, Cb, xb, g[0], g[1], g[4]);
-    propagate_adj(x, C, B, P, k, xb, Cb, g[0], g[1]);
+    scatter_adj(xp, fr, ly, ks, Q, Cb, xb, g[0], g[1], g[4]);
+    propagate_adj(x, C, B, P, ks, xb, Cb, g[0], g[1]);
     emit(l, g);
   }
   // seed and the layer-0 update
@@ -727,18 +746,26 @@ KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lay
     hit(l, h[l]);
     place(lays[l], h[l][0], h[l][1], h[l][2], m[l]);
   }
+  Consts<T> k0 = k;
+  T Cf[21];
+  const T* C0 = Cs;
+  if (fk) {  // curvature from the field at the first hit, and the seed covariance with it
+    k0.kB = field_kB(k, *fk, m[0][0], m[0][1], m[0][2]);
+    seed_cov(fk->srphi, fk->sz, fk->dr02, k0.kB, Cf);
+    C0 = Cf;
+  }
   Seed<T> E;
   T xs[6];
-  seed(m[0], m[1], m[2], k, E, xs);
+  seed(m[0], m[1], m[2], k0, E, xs);
   Upd<T> U;
   T xu[6], Cu[21];
   for (int q = 0; q < 6; ++q) xu[q] = xs[q];
-  for (int q = 0; q < 21; ++q) Cu[q] = Cs[q];
-  update(xu, Cu, lays[0], k, m[0][0], m[0][1], m[0][2], U);
+  for (int q = 0; q < 21; ++q) Cu[q] = C0[q];
+  update(xu, Cu, lays[0], k0, m[0][0], m[0][1], m[0][2], U);
   T g0[5] = {0, 0, 0, 0, 0};
   T mb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  update_adj(xs, Cs, U, w, xb, Cb, mb[0][0], mb[0][1], mb[0][2], g0[0], g0[1]);
-  seed_adj(E, k, xb, mb[0], mb[1], mb[2]);
+  update_adj(xs, C0, U, w, xb, Cb, mb[0][0], mb[0][1], mb[0][2], g0[0], g0[1]);
+  seed_adj(E, k0, xb, mb[0], mb[1], mb[2]);
   place_adj(lays[0], h[0][0], h[0][1], mb[0][0], mb[0][1], mb[0][2], g0);
   emit(0, g0);
   for (int l = 1; l < 3; ++l) {

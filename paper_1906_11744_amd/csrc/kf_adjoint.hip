@@ -17,6 +17,7 @@ constexpr int kAdjBlock = 64;
 
 __host__ __device__ inline int adj_row_stride(int nl) { return 5 * nl + ((5 * nl) % 2 == 0 ? 1 : 0); }
 
+template <bool kField>
 __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
   extern __shared__ float red[];
   const int R = 5 * a.nl;
@@ -55,7 +56,9 @@ __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) my[l * 5 + q] += g[q];
       };
-      if (!kfa::track_adjoint<float>(lstart, nl - 1, mask, lays, a.k, Cs, w, hit, ckpt, emit))
+      const kfa::FieldK<float> fk{a.fr, a.fz, a.srphi, a.sz, a.dr02};
+      if (!kfa::track_adjoint<float>(lstart, nl - 1, mask, lays, a.k, Cs, w, hit, ckpt, emit,
+                                     kField ? &fk : nullptr))
         for (int o = 0; o < R; ++o) my[o] = 0.f;
     }
   }
@@ -94,7 +97,10 @@ int64_t adjoint_blocks(int64_t n) { return (n + kAdjBlock - 1) / kAdjBlock; }
 hipError_t launch_adjoint(const AdjArgs& a, float* dalign, float* dxX0, hipStream_t stream) {
   if (a.n_blocks > 0) {
     const size_t lds = (size_t)kAdjBlock * adj_row_stride(a.nl) * sizeof(float);
-    hipLaunchKernelGGL(fit_adjoint_kernel, dim3((unsigned)a.n_blocks), dim3(kAdjBlock), lds, stream, a);
+    if (a.fr != 0.f || a.fz != 0.f)
+      hipLaunchKernelGGL((fit_adjoint_kernel<true>), dim3((unsigned)a.n_blocks), dim3(kAdjBlock), lds, stream, a);
+    else
+      hipLaunchKernelGGL((fit_adjoint_kernel<false>), dim3((unsigned)a.n_blocks), dim3(kAdjBlock), lds, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -547,7 +547,9 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
   if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
-  if (ctx->material()) return KF_E_UNSUPPORTED;  // the adjoint differentiates the per-layer, uniform-field model
+  // the adjoint differentiates the per-layer material model; the field enters with each
+  // step's value held fixed
+  if (ctx->mat_map != nullptr || ctx->eloss > 0.f) return KF_E_UNSUPPORTED;
   if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
   if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
     return KF_E_INVALID;
@@ -574,6 +576,8 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   a.srphi = ctx->g.sigma_rphi_cm;
   a.sz = ctx->g.sigma_z_cm;
   a.dr02 = md.dr02;
+  a.fr = ctx->fr;
+  a.fz = ctx->fz;
   a.hits = in->hits;
   a.mask = in->hit_mask;
   a.ndf = fwd->ndf;

@@ -90,6 +90,7 @@ struct AdjArgs {
   int32_t nl;
   kfa::Consts<float> k;
   float srphi, sz, dr02;
+  float fr = 0.f, fz = 0.f;  // parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2)
   const float* hits;
   const uint32_t* mask;
   const int32_t* ndf;

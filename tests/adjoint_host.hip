@@ -2,13 +2,16 @@
 // CPU test that checks the hand-derived reverse sweep against the oracle's forward-
 // mode dual-number gradient.  Runs the same forward steps in double, checkpoints
 // every layer, and accumulates sum_i w_i d chi2_i / d(align, xX0) in track order.
+// fr, fz != 0: the parameterised field B (1 + fr r^2 + fz z^2), each step in the field
+// at its start and the seed's curvature in the field at its first hit.
 #include <vector>
 
 #include "../paper_1906_11744_amd/csrc/kf_adjoint.h"
 
 extern "C" int adjoint_host_fp64(int nl, const double* radius, double B, double srphi, double sz, double sr,
                                  double mass, const double* align, const double* xX0, long n, const float* hits,
-                                 const uint32_t* mask, const double* w, double* g_align, double* g_xX0) {
+                                 const uint32_t* mask, const double* w, double* g_align, double* g_xX0,
+                                 double fr, double fz) {
   using T = double;
   kfa::Consts<T> k;
   k.kB = 0.299792458e-2 * B;
@@ -29,6 +32,8 @@ extern "C" int adjoint_host_fp64(int nl, const double* radius, double B, double 
   }
   T Cs[21];
   kfa::seed_cov<T>(srphi, sz, radius[2] - radius[0], k.kB, Cs);
+  const kfa::FieldK<T> fk{fr, fz, srphi, sz, radius[2] - radius[0]};
+  const bool field = fr != 0.0 || fz != 0.0;
   std::vector<T> acc(nl * 5, 0.0);
   std::vector<T> ck(nl * 27);
   for (long i = 0; i < n; ++i) {
@@ -45,8 +50,10 @@ extern "C" int adjoint_host_fp64(int nl, const double* radius, double B, double 
     }
     kfa::Seed<T> E;
     T x[6], C[21];
-    kfa::seed(pm[0], pm[1], pm[2], k, E, x);
-    for (int q = 0; q < 21; ++q) C[q] = Cs[q];
+    kfa::Consts<T> k0 = k;
+    if (field) k0.kB = kfa::field_kB(k, fk, pm[0][0], pm[0][1], pm[0][2]);
+    kfa::seed(pm[0], pm[1], pm[2], k0, E, x);
+    kfa::seed_cov<T>(srphi, sz, radius[2] - radius[0], k0.kB, C);
     kfa::Upd<T> U;
     kfa::update(x, C, lays[0], k, pm[0][0], pm[0][1], pm[0][2], U);
     for (int q = 0; q < 6; ++q) ck[q] = x[q];
@@ -55,9 +62,11 @@ extern "C" int adjoint_host_fp64(int nl, const double* radius, double B, double 
     if (last > nl - 1) last = nl - 1;
     int lupd = 0;
     for (int l = 1; l <= last; ++l) {
+      kfa::Consts<T> ks = k;
+      if (field) ks.kB = kfa::field_kB(k, fk, x[0], x[1], x[2]);
       kfa::Prop<T> P;
       T xp[6];
-      if (!kfa::propagate(x, lays[l], k, P, xp)) break;
+      if (!kfa::propagate(x, lays[l], ks, P, xp)) break;
       T Bm[6][6], Cp[21];
       kfa::transport_cov(P, C, Bm, Cp);
       const kfa::Frm<T> fr = kfa::frame(xp, lays[l]);
@@ -83,7 +92,9 @@ extern "C" int adjoint_host_fp64(int nl, const double* radius, double B, double 
     auto emit = [&](int l, const T g[5]) {
       for (int q = 0; q < 5; ++q) gi[l * 5 + q] += g[q];
     };
-    if (!kfa::track_adjoint<T>(lupd, nl - 1, m, lays.data(), k, Cs, w ? w[i] : 1.0, hit, ckpt, emit)) return -1;
+    if (!kfa::track_adjoint<T>(lupd, nl - 1, m, lays.data(), k, Cs, w ? w[i] : 1.0, hit, ckpt, emit,
+                               field ? &fk : nullptr))
+      return -1;
     for (int q = 0; q < nl * 5; ++q) acc[q] += gi[q];
   }
   for (int l = 0; l < nl; ++l) {

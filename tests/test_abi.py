@@ -210,7 +210,10 @@ def test_field_setting_validation_and_the_calls_it_excludes():
                                        None, 0, None)
     assert back() == -3
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(-1e-6), C.c_float(-4e-6)) == 0
-    assert back() == -2
+    assert back() == -3           # the adjoint takes the field: it stops at the workspace
+    assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0363)) == 0
+    assert back() == -2           # but not the energy loss
+    assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(0.0)) == 0
     assert back() == -3
     g0 = synth.workload_geometry(2)

@@ -25,7 +25,7 @@ def host_adjoint(tmp_path_factory):
     return lib
 
 
-def run_host(lib, geom, ts, align, xX0, w=None):
+def run_host(lib, geom, ts, align, xX0, w=None, field=(0.0, 0.0)):
     L = geom.n_layers
     n = ts.hits.shape[2]
     ga = np.zeros((L, 4))
@@ -38,7 +38,8 @@ def run_host(lib, geom, ts, align, xX0, w=None):
     ww = None if w is None else f64(w)
     rc = lib.adjoint_host_fp64(C.c_int(L), p(rad), C.c_double(geom.B), C.c_double(geom.sigma_rphi),
                                C.c_double(geom.sigma_z), C.c_double(geom.sigma_r), C.c_double(geom.mass), p(al),
-                               p(xx), C.c_long(n), p(hits), p(mask), None if ww is None else p(ww), p(ga), p(gx))
+                               p(xx), C.c_long(n), p(hits), p(mask), None if ww is None else p(ww), p(ga), p(gx),
+                               C.c_double(field[0]), C.c_double(field[1]))
     assert rc == 0
     return ga, gx
 
@@ -65,3 +66,23 @@ def test_host_adjoint_no_material(host_adjoint):
     ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, np.zeros(geom.n_layers))
     scale = np.abs(ra).max()
     np.testing.assert_allclose(ga, ra, rtol=1e-9, atol=1e-10 * scale)
+
+
+@pytest.mark.parametrize("at_truth", [False, True])
+def test_host_adjoint_in_the_field_equals_dual_gradient(host_adjoint, at_truth):
+    """Tracks simulated in the parameterised field, fitted in it: the reverse sweep with
+    each step's field held at its start value equals the oracle's dual-number gradient,
+    which reads the field as a value in the same places."""
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    fld = synth.FIELD_SOLENOID
+    ts = synth.simulate(geom, synth.rng_for(77), 60, (0.5, 50.0), True, 1.5, align=a_true, field=fld)
+    align = a_true if at_truth else np.zeros_like(a_true)
+    w = np.random.default_rng(4).uniform(0.5, 1.5, ts.hits.shape[2])
+    ga, gx = run_host(host_adjoint, geom, ts, align, geom.xX0, w, field=fld)
+    ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w, field=fld)
+    ua, _ = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w)
+    scale = max(np.abs(ra).max(), np.abs(rx).max())
+    assert np.abs(ua - ra).max() > 1e-2 * scale          # the field matters at this size
+    np.testing.assert_allclose(ga, ra, rtol=1e-9, atol=1e-10 * scale)
+    np.testing.assert_allclose(gx, rx, rtol=1e-9, atol=1e-10 * scale)

@@ -23,10 +23,12 @@ def _case(n, at_truth):
     return geom, ts, align
 
 
-def _gpu_grad(geom, ts, align, w):
+def _gpu_grad(geom, ts, align, w, field=None):
     need_gpu()
     from paper_1906_11744_amd import Context
     kf = Context(geom)
+    if field is not None:
+        kf.set_field(*field)
     hits, mask = to_dev(ts.hits), mask_dev(ts.hit_mask)
     a = to_dev(np.asarray(align, np.float32))
     x = to_dev(geom.xX0.astype(np.float32))
@@ -68,6 +70,26 @@ def test_gradient_full_size_1e5_tracks():
     ga, gx, _ = _gpu_grad(geom, ts, align, w)
     ra, rx = oracle.fit_grad(geom, np.ascontiguousarray(ts.hits[:, :, idx]), ts.hit_mask[idx], align, geom.xX0)
     _check(ga, gx, ra, rx, "1e5 tracks, 2000 weighted")
+
+
+@pytest.mark.parametrize("at_truth", [False, True])
+def test_gradient_in_the_field_matches_fp64_reference(at_truth):
+    """Tracks simulated in the parameterised field B (1 + c_r r^2 + c_z z^2), fitted and
+    differentiated in it: each step's field enters at its value, as in the oracle; the
+    gradient taken in the uniform field differs from the reference by far more than
+    the tolerance."""
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    fld = synth.FIELD_SOLENOID
+    ts = synth.simulate(geom, synth.rng_for(78), 2000, (0.5, 50.0), True, 1.5, align=a_true, field=fld)
+    align = a_true if at_truth else np.zeros_like(a_true)
+    w = np.random.default_rng(6).uniform(0.5, 1.5, ts.hits.shape[2])
+    ga, gx, _ = _gpu_grad(geom, ts, align, w, field=fld)
+    ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w, field=fld)
+    _check(ga, gx, ra, rx, f"field, 2000 tracks, align {'true' if at_truth else 'zero'}")
+    ua, ux = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w)
+    r, u = np.concatenate([ra.ravel(), rx]), np.concatenate([ua.ravel(), ux])
+    assert np.linalg.norm(u - r) / np.linalg.norm(r) > 1e-2
 
 
 def test_backward_is_deterministic():

@@ -487,3 +487,60 @@ def test_gradient_global_symmetries(oracle_lib):
     ga, gx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0)
     for k in range(3):
         assert abs(ga[:, k].sum()) <= 1e-8 * np.abs(ga[:, k]).sum()
+
+
+
+def _field_grad_case(at_truth):
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    ts = synth.simulate(geom, synth.rng_for(77), 24, (0.5, 50.0), True, 1.5, align=a_true, field=synth.FIELD_SOLENOID)
+    return geom, ts, (a_true if at_truth else np.zeros_like(a_true))
+
+
+@pytest.mark.parametrize("at_truth", [False, True])
+def test_field_gradient_against_central_differences(oracle_lib, at_truth):
+    """In the parameterised field (Sec. 3) the gradient holds each step's field at its
+    value.  The derivative it leaves out is the field's change when a parameter moves a
+    step's start point: with |fr| r^2 and |fz| z^2 at the percent level over the
+    geometry, that term is below 1e-3 of the gradient's scale (at most 2e-4 measured over
+    every component), while the gradient taken in the uniform field misses the central
+    differences by several percent of it."""
+    geom, ts, align = _field_grad_case(at_truth)
+    fld = synth.FIELD_SOLENOID
+    xX0 = geom.xX0.copy()
+    ga, gx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, xX0, field=fld)
+    ua, ux = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, xX0)
+    h = 1e-6
+    scale = max(np.abs(ga).max(), np.abs(gx).max())
+    worst, worst_u = 0.0, 0.0
+    rng = np.random.default_rng(2)
+    comps = [(l, k) for l in range(geom.n_layers) for k in range(5)]
+    for (l, k) in [comps[j] for j in rng.choice(len(comps), 30, replace=False)]:
+        ap, am = align.copy(), align.copy()
+        xp, xm = xX0.copy(), xX0.copy()
+        if k < 4:
+            ap[l, k] += h
+            am[l, k] -= h
+            g, u = ga[l, k], ua[l, k]
+        else:
+            xp[l] += h
+            xm[l] -= h
+            g, u = gx[l], ux[l]
+        fd = (oracle.total_chi2(geom, ts.hits, ts.hit_mask, ap, xp, field=fld) -
+              oracle.total_chi2(geom, ts.hits, ts.hit_mask, am, xm, field=fld)) / (2 * h)
+        worst = max(worst, abs(fd - g) / scale)
+        worst_u = max(worst_u, abs(fd - u) / scale)
+    print(f"max |fd - g| / scale: held field {worst:.2e}, uniform field {worst_u:.2e}")
+    assert worst < 1e-3 and worst_u > 2e-2
+
+
+def test_field_gradient_shift_invariance(oracle_lib):
+    """With each step's field held at its value, moving every hit and every surface by
+    one common shift (x, y, z) or, at zero misalignment, rotating all of them about the
+    beam axis leaves the total chi2 unchanged, so the per-layer derivatives sum to zero
+    even though the field itself is not shift-invariant."""
+    for at_truth in (False, True):
+        geom, ts, align = _field_grad_case(at_truth)
+        ga, _ = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, field=synth.FIELD_SOLENOID)
+        for k in range(3 if at_truth else 4):
+            assert abs(ga[:, k].sum()) <= 1e-8 * np.abs(ga[:, k]).sum(), (at_truth, k, ga[:, k].sum())
