@@ -292,7 +292,8 @@ def _fallback_rates(out):
 
 def bench_grad(steps, warmup):
     """Differentiable fit: 1e5 misaligned tracks; forward (fit with checkpoints) and the
-    adjoint (kf_fit_backward), each timed alone."""
+    adjoint (kf_fit_backward), each timed alone, in the uniform field and under the
+    parameterised one."""
     import torch
 
     import synth
@@ -319,8 +320,15 @@ def bench_grad(steps, warmup):
     # ndf, dLoss/dchi2); its gradient output is negligible
     b_f = 120.0 * n_steps + 124.0 * n
     b_b = 120.0 * n_steps + 16.0 * n
+    # the same inputs under the parameterised field (every step evaluates its field)
+    kfb = Context(geom)
+    kfb.set_field(*synth.FIELD_SOLENOID)
+    fwdb = kfb.fit(hits, mask, align=al, xX0=xX0, ckpt=True)
+    t_fb, _, _ = _time_launches(lambda: kfb.fit(hits, mask, align=al, xX0=xX0, ckpt=True, out=fwdb), steps, warmup)
+    t_bb, _, _ = _time_launches(lambda: kfb.fit_backward(hits, mask, fwdb, w, align=al, xX0=xX0), steps, warmup)
     return {"tracks": n, "kalman_steps": n_steps, "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
             "backward_over_forward": t_b / t_f,
+            "field_forward_ms": t_fb * 1e3, "field_backward_ms": t_bb * 1e3,
             "forward_algorithmic_bytes": b_f, "forward_GB_per_s": b_f / t_f / 1e9,
             "backward_algorithmic_bytes": b_b, "backward_GB_per_s": b_b / t_b / 1e9}
 
