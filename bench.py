@@ -56,8 +56,8 @@ FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csr
 
 
 # The same for one smooth_kernel launch on that workload.
-SMOOTH_TRAFFIC = {"sources": "6da3ad5dac1f2d89", "tracks": 1_000_000,
-                  "fetch_kib": 902508.1, "write_kib": 1800781.3,
+SMOOTH_TRAFFIC = {"sources": "d1de2197c326dcae", "tracks": 1_000_000,
+                  "fetch_kib": 902506.5, "write_kib": 1800781.3,
                   "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 SMOOTH_SOURCES = ("paper_1906_11744_amd/csrc/kf_smooth.hip", "paper_1906_11744_amd/csrc/kf_smooth.h",
                   "paper_1906_11744_amd/csrc/kf_adjoint.h")

@@ -294,8 +294,9 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
  * (overwritten, float32) by a reverse sweep over each track's layers that recomputes
  * every step from its checkpoint.  The paper has no differentiation; this is the
  * vector-Jacobian product of the fit as implemented by kf_fit.  Under a parameterised
- * field (kf_ctx_set_field) each step's field is held at its value; KF_E_UNSUPPORTED
- * while a material map or an energy loss is set (kf_ctx_set_material). */
+ * field (kf_ctx_set_field) each step's field is held at its value (the forward call
+ * must have run under the same field); KF_E_UNSUPPORTED while a material map or an
+ * energy loss is set (kf_ctx_set_material). */
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream);
 

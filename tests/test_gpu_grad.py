@@ -92,6 +92,25 @@ def test_gradient_in_the_field_matches_fp64_reference(at_truth):
     assert np.linalg.norm(u - r) / np.linalg.norm(r) > 1e-2
 
 
+def test_gradient_in_the_field_full_size_1e5_tracks():
+    """The differentiable-fit workload's size under the parameterised field, in one
+    launch as timed: weight 1 on 2 000 sampled tracks and 0 elsewhere gives the
+    oracle's gradient of those tracks alone."""
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    fld = synth.FIELD_SOLENOID
+    ts = synth.simulate(geom, synth.rng_for(79), 100_000, (0.5, 50.0), True, 1.5, align=a_true, field=fld)
+    align = np.zeros_like(a_true)
+    n = ts.hits.shape[2]
+    idx = np.sort(np.random.default_rng(10).choice(n, 2000, replace=False))
+    w = np.zeros(n)
+    w[idx] = 1.0
+    ga, gx, _ = _gpu_grad(geom, ts, align, w, field=fld)
+    ra, rx = oracle.fit_grad(geom, np.ascontiguousarray(ts.hits[:, :, idx]), ts.hit_mask[idx], align, geom.xX0,
+                             field=fld)
+    _check(ga, gx, ra, rx, "field, 1e5 tracks, 2000 weighted")
+
+
 def test_backward_is_deterministic():
     geom, ts, align = _case(20000, True)
     w = np.ones(ts.hits.shape[2])
