@@ -299,8 +299,8 @@ def total_chi2(geom, hits, mask, align, xX0, weight=None, field=None):
 
 def fit_grad(geom, hits, mask, align, xX0, weight=None, field=None):
     """FP64 gradient of sum_i weight_i chi2_i w.r.t. align [L][4] and xX0 [L] (dual
-    numbers).  field = (c_r, c_z): the parameterised field, each step's value held
-    fixed in the derivative."""
+    numbers).  field = (c_r, c_z): the parameterised field; the derivative includes the
+    field's change where a parameter moves a step's start point or the seed's first hit."""
     hits = np.ascontiguousarray(hits, np.float32)
     mask = np.ascontiguousarray(mask, np.uint32)
     L = hits.shape[0]

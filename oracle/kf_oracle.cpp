@@ -150,7 +150,7 @@ struct Geo {
   double kB, srphi, sz, sr, mass;
   double radius[32], zhalf[32];
   int nphi, nz;
-  // Material beyond one x/X0 per layer (Sec. 3: material arrays indexed in r and z,
+  // Material beyond one x/X0 per layer (Sec. 3: a per-layer table of x/X0 over z,
   // multiple scattering and energy loss): map [nl][map_nz] of x/X0 at the centres of
   // map_nz equal z bins over each layer's [-zhalf, zhalf] (null: the layer's xX0), and
   // the mean ionisation loss per radiation length at minimum ionisation (0: none).
@@ -162,9 +162,12 @@ struct Geo {
   double fr = 0.0, fz = 0.0;
 };
 
-// k_B of the field at (x, y, z).
-double kB_at(const Geo& g, double x, double y, double z) {
-  if (g.fr == 0.0 && g.fz == 0.0) return g.kB;
+// k_B of the field at (x, y, z).  Templated on the scalar type: with dual numbers the
+// field's dependence on the point (which moves with the alignment parameters) is part
+// of the derivative, so the gradient below is that of the total chi2 as computed.
+template <class T>
+T kB_at(const Geo& g, const T& x, const T& y, const T& z) {
+  if (g.fr == 0.0 && g.fz == 0.0) return T(g.kB);
   return g.kB * (1.0 + g.fr * (x * x + y * y) + g.fz * z * z);
 }
 
@@ -210,7 +213,7 @@ void place_hit(const Layer<T>& ly, double hx, double hy, double hz, T m[3]) {
 
 // Position and direction after a transverse arc s.
 template <class T>
-void helix_at(const T x[6], const T& s, double kB, T out[6]) {
+void helix_at(const T x[6], const T& s, const T& kB, T out[6]) {
   using std::cos; using std::sin;
   T w = -kB * x[3];
   T u = w * s;
@@ -238,7 +241,7 @@ void helix_at(const T x[6], const T& s, double kB, T out[6]) {
 // along the helix until it changes sign, bisect the bracket, then polish with
 // Newton steps (which also settle the derivative parts of dual numbers).
 template <class T>
-T crossing_residual(const T x[6], const T& s, const T& cx, const T& cy, double r, double kB, T* fp) {
+T crossing_residual(const T x[6], const T& s, const T& cx, const T& cy, double r, const T& kB, T* fp) {
   using std::cos; using std::sin;
   T p[6];
   helix_at(x, s, kB, p);
@@ -248,11 +251,11 @@ T crossing_residual(const T x[6], const T& s, const T& cx, const T& cy, double r
 }
 
 template <class T>
-bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, double kB, T& s) {
+bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, const T& kB, T& s) {
   T ex = x[0] - cx, ey = x[1] - cy;
   double c0 = val(ex * ex + ey * ey) - r * r;
   if (!(c0 < 0)) return false;
-  double w = -kB * val(x[3]);
+  double w = -val(kB) * val(x[3]);
   double smax = w != 0 ? kPi / std::fabs(w) : 4.0 * r;
   double h = 0.125 * r;
   if (w != 0) h = std::min(h, 0.125 / std::fabs(w));
@@ -306,7 +309,7 @@ bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, double kB, T
 // end state xe).  J = I plus six terms: d(x,y)/dphi, d(x,y)/dkappa, dz/dtheta,
 // dphi/dkappa.
 template <class T>
-void transport_jacobian(const T x[6], const T xe[6], const T& s, double kB, T J[6][6]) {
+void transport_jacobian(const T x[6], const T xe[6], const T& s, const T& kB, T J[6][6]) {
   using std::cos; using std::sin;
   for (int i = 0; i < 6; ++i)
     for (int j = 0; j < 6; ++j) J[i][j] = T(i == j ? 1.0 : 0.0);
@@ -329,7 +332,7 @@ void transport_jacobian(const T x[6], const T xe[6], const T& s, double kB, T J[
   J[1][3] = -kB * s2 * (F1 * ty + F2 * tx);
   T st = sin(x[5]);
   J[2][5] = -s / (st * st);
-  J[4][3] = T(-kB) * s;
+  J[4][3] = -kB * s;
 }
 
 template <class T>
@@ -599,7 +602,7 @@ bool update_with_hit(const Geo& g, const Layer<T>& ly, Track<T>& tk, const T m[3
 template <class T>
 bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nullptr) {
   T s;
-  const double kB = kB_at(g, val(tk.x[0]), val(tk.x[1]), val(tk.x[2]));  // the field at the step's start
+  const T kB = kB_at<T>(g, tk.x[0], tk.x[1], tk.x[2]);  // the field at the step's start
   if (!crossing_arc(tk.x, ly.cx, ly.cy, ly.r, kB, s)) { tk.status |= ST_PROP_FAIL; return false; }
   T xe[6];
   helix_at(tk.x, s, kB, xe);
@@ -656,16 +659,17 @@ void seed_from_hits(const Geo& g, const T m0[3], const T m1[3], const T m2[3], T
   else s02 = lc * asin(qc) / qc;
   T theta = atan2(s02, m2[2] - m0[2]);
   tk.x[0] = m0[0]; tk.x[1] = m0[1]; tk.x[2] = m0[2];
-  const double kB0 = kB_at(g, val(m0[0]), val(m0[1]), val(m0[2]));
+  const T kB0 = kB_at<T>(g, m0[0], m0[1], m0[2]);
   tk.x[3] = -w / kB0;
   tk.x[4] = wrap_pi(phi0);
   tk.x[5] = theta;
   double dr = g.radius[2] - g.radius[0];
   double sphi = std::sqrt(2.0) * g.srphi / dr, sth = std::sqrt(2.0) * g.sz / dr;
-  double skap = 8.0 * std::sqrt(1.5) * g.srphi / (dr * dr * kB0);
-  double d[6] = {g.srphi * g.srphi, g.srphi * g.srphi, g.sz * g.sz, skap * skap, sphi * sphi, sth * sth};
+  const T skap = 8.0 * std::sqrt(1.5) * g.srphi / (dr * dr * kB0);
+  const T d[6] = {T(g.srphi * g.srphi), T(g.srphi * g.srphi), T(g.sz * g.sz), skap * skap, T(sphi * sphi),
+                  T(sth * sth)};
   for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) tk.C[i][j] = T(i == j ? 10.0 * d[i] : 0.0);
+    for (int j = 0; j < 6; ++j) tk.C[i][j] = i == j ? 10.0 * d[i] : T(0.0);
   tk.chi2 = 0.0;
   tk.n = 0;
   tk.status = 0;
@@ -942,8 +946,9 @@ double oracle_total_chi2(const OGeom* og, const double* align, const double* xX0
 // forward-mode dual numbers through the whole fit (seeds built from the placed
 // hits), one layer's five parameters per pass.
 // fr, fz: the parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2).  Each step's field
-// (at its start; the seed's at hit 0) enters as a value, not as a function of the
-// parameters: the gradient holds the field seen by each step fixed.
+// is taken at its start and the seed's at hit 0, points that move with the parameters;
+// the dual numbers carry that dependence, so this is the exact derivative of the total
+// chi2 that oracle_total_chi2 evaluates.
 void oracle_fit_grad(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
                      const uint32_t* mask, const double* weight, double* g_align, double* g_xX0, double fr,
                      double fz) {
@@ -1030,7 +1035,7 @@ struct FindCfg {
 // Relative margin by which the helix of state x clears (> 0) or misses (< 0) the
 // cylinder of layer ly: its circle reaches |centre - axis| + R from the axis.
 double reach_margin(const Geo& g, const Layer<double>& ly, const double x[6]) {
-  double w = -kB_at(g, x[0], x[1], x[2]) * x[3];
+  double w = -kB_at<double>(g, x[0], x[1], x[2]) * x[3];
   if (w == 0) return 1.0;
   double R = 1.0 / std::fabs(w);
   double cx = x[0] - std::sin(x[4]) / w - ly.cx, cy = x[1] + std::cos(x[4]) / w - ly.cy;

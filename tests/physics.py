@@ -58,3 +58,46 @@ def pulls(est, cov, truth, idx=(3, 4, 5)):
             d = (d + np.pi) % (2 * np.pi) - np.pi
         out[p] = d / np.sqrt(cov[p, p])
     return out
+
+
+# determinants of the equilibrated S on both sides of the 1e-2 fallback threshold
+FALLBACK_DETS = [0.5, 0.02, 0.0105, 0.0101, 0.0099, 0.0095, 0.002]
+
+
+def correlated_seeds(geom, dets):
+    """External seeds on layer 0 whose first update has an innovation covariance S of a
+    chosen conditioning: for each target d, a radial track (phi = 0, theta = pi/2) at
+    (r_0, 0, 0) with a prior whose (y, z) block gives the measured rows of S the
+    correlation rho = sqrt(1 - d).  There the crossing-point projection is H = rows
+    (y) and (z) of the position, so S = diag(sigma_r^2, C_yy + sigma_rphi^2,
+    C_zz + sigma_z^2) + C_yz off the diagonal, and the determinant of S scaled to unit
+    diagonal is exactly 1 - rho^2 = d.  Returns hits [L][3][n], mask [n] (layer 0 only),
+    seed_state [6][n] and seed_cov [21][n] (packed lower triangle), float32."""
+    d = np.asarray(dets, np.float64)
+    n = d.size
+    L = geom.n_layers
+    r0 = float(geom.radius[0])
+    vr, vz = geom.sigma_rphi ** 2, geom.sigma_z ** 2
+    a, b = 999.0 * vr, 999.0 * vz          # |rho| can reach 999/1000
+    rho = np.sqrt(1.0 - d)
+    cyz = rho * np.sqrt((a + vr) * (b + vz))
+    full = np.zeros((6, 6, n))
+    for i, v in enumerate([1e-4, a, b, 1e-4, 1e-6, 1e-6]):
+        full[i, i] = v
+    full[1, 2] = full[2, 1] = cyz
+    cov = np.zeros((21, n))
+    k = 0
+    for i in range(6):
+        for j in range(i + 1):
+            cov[k] = full[i, j]
+            k += 1
+    state = np.zeros((6, n))
+    state[0] = r0
+    state[3] = 0.5
+    state[5] = 0.5 * np.pi
+    hits = np.zeros((L, 3, n), np.float32)
+    hits[0, 0] = r0
+    hits[0, 1] = 0.003
+    hits[0, 2] = -0.02
+    mask = np.ones(n, np.uint32)
+    return hits, mask, state.astype(np.float32), cov.astype(np.float32)

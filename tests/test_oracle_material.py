@@ -1,4 +1,4 @@
-"""Pins of the oracle's material model (Sec. 3: material arrays indexed in r and z for
+"""Pins of the oracle's material model (Sec. 3: x/X0 as a function of layer and z for
 multiple scattering and energy loss), no GPU.
 
 * A map whose every bin holds the layer's own x/X0, without energy loss, is the
