@@ -178,9 +178,9 @@ int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold);
  * off.  KF_E_INVALID for a NULL context or exactly one NULL event. */
 int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop);
 
-/* Material model of kf_fit beyond one x/X0 per layer (Sec. 3: two-dimensional
- * arrays of radiation lengths indexed in r and z account for multiple scattering and
- * energy loss).
+/* Material model of kf_fit beyond one x/X0 per layer (Sec. 3): a table of x/X0 per
+ * layer and z bin, looked up at each crossing, feeding both the scattering term and a
+ * mean energy loss.
  *   xX0_map: DEVICE pointer, [n_layers][nz] float32, owned by the caller and read by
  *     every later kf_fit until the setting changes (keep it alive and unchanged while
  *     set).  Row l holds x/X0 at normal incidence at the centres of nz equal bins over
@@ -215,9 +215,8 @@ int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float elo
  * Jacobian treats as constant over the step.  A seed built from hits converts the
  * three-hit curvature into kappa with the field at hit 0.  0, 0 (the default) is the
  * uniform field.  kf_find and kf_smooth take the same field.  kf_fit_backward takes
- * it too: its gradient holds each step's field (and the seed's) at its value, the
- * derivative of the fit with those fields fixed; the field's own change under the
- * parameters is left out.
+ * it too, including the field's change where a parameter moves a step's start point
+ * or the seed's first hit (the exact derivative of the fit's total chi2).
  * KF_E_INVALID for a NULL context or a non-finite coefficient; KF_E_UNSUPPORTED for a
  * nonzero coefficient when B_tesla is 0. */
 int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z);
@@ -293,10 +292,12 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
  * given dchi2 [n] = dLoss/dchi2_i, accumulates dLoss/dalign [L][4] and dLoss/dxX0 [L]
  * (overwritten, float32) by a reverse sweep over each track's layers that recomputes
  * every step from its checkpoint.  The paper has no differentiation; this is the
- * vector-Jacobian product of the fit as implemented by kf_fit.  Under a parameterised
- * field (kf_ctx_set_field) each step's field is held at its value (the forward call
- * must have run under the same field); KF_E_UNSUPPORTED while a material map or an
- * energy loss is set (kf_ctx_set_material). */
+ * vector-Jacobian product of the fit as implemented by kf_fit: every S^-1 is recomputed
+ * as the forward formed it (equilibrated, in FP64 below the context's fallback
+ * threshold).  Under a parameterised field (kf_ctx_set_field; the forward call must
+ * have run under the same field) the field at each step's start and at the seed's
+ * first hit is differentiated with those points; KF_E_UNSUPPORTED while a material
+ * map or an energy loss is set (kf_ctx_set_material). */
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream);
 

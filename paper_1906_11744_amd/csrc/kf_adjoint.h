@@ -37,6 +37,9 @@ struct Lay {
 template <class T>
 struct Consts {
   T kB, v_r, v_rphi, v_z, mass2;
+  // float S^-1: below this determinant of the equilibrated S (unit diagonal) the
+  // inverse is formed in double, as the forward fit does (> 1 forces it everywhere)
+  T det_thr = T(1e-2);
 };
 
 // ---------------------------------------------------------------------------------
@@ -240,10 +243,30 @@ KFA_HD T update(T x[6], T C[21], const Lay<T>& ly, const Consts<T>& k, T mx, T m
   const T S11 = U.A1[0] * U.h1x + U.A1[1] * U.h1y + k.v_rphi;
   const T S12 = U.A1[0] * U.h2x + U.A1[1] * U.h2y + U.A1[2];
   const T S22 = U.A2[0] * U.h2x + U.A2[1] * U.h2y + U.A2[2] + k.v_z;
-  const T det = S11 * S22 - S12 * S12;
-  U.Si11 = S22 / det;
-  U.Si22 = S11 / det;
-  U.Si12 = -S12 / det;
+  if constexpr (sizeof(T) == 4) {
+    // the forward fit's inverse: equilibrated to unit diagonal, with its condition check
+    // and the FP64 path, so that the sweep differentiates the S^-1 the fit used
+    const T d1 = T(1) / sqrt(S11), d2 = T(1) / sqrt(S22);
+    const T r12 = S12 * d1 * d2;
+    const T det = T(1) - r12 * r12;
+    if (det >= k.det_thr) {
+      const T idet = T(1) / det;
+      U.Si11 = d1 * d1 * idet;
+      U.Si22 = d2 * d2 * idet;
+      U.Si12 = -r12 * d1 * d2 * idet;
+    } else {
+      const double s11 = S11, s12 = S12, s22 = S22;
+      const double dd = s11 * s22 - s12 * s12;
+      U.Si11 = (T)(s22 / dd);
+      U.Si22 = (T)(s11 / dd);
+      U.Si12 = (T)(-s12 / dd);
+    }
+  } else {
+    const T det = S11 * S22 - S12 * S12;
+    U.Si11 = S22 / det;
+    U.Si22 = S11 / det;
+    U.Si12 = -S12 / det;
+  }
   U.Si00 = T(1) / k.v_r;
   U.dx = mx - x[0];
   U.dy = my - x[1];
@@ -520,10 +543,12 @@ KFA_HD void scatter_adj(const T x[6], const Frm<T>& f, const Lay<T>& ly, const C
 }
 
 // Adjoint of the propagation step: in xb/Cb the adjoints at the end, out at the start;
-// adds the adjoint of the layer axis.
+// adds the adjoint of the layer axis and, if kBb is given, returns the adjoint of the
+// step's k_B (which enters through omega = -k_B kappa, the arc that omega fixes, and
+// the Jacobian's d(x, y)/dkappa and dphi/dkappa).
 template <class T>
 KFA_HD void propagate_adj(const T x[6], const T C[21], const T B[6][6], const Prop<T>& P, const Consts<T>& k,
-                          T xb[6], T Cb[21], T& cxb, T& cyb) {
+                          T xb[6], T Cb[21], T& cxb, T& cyb, T* kBb = nullptr) {
   // J-bar = 2 Cb' J C = 2 Cb' B (only the six variable entries)
   auto jb = [&](int i, int j) {
     T s = 0;
@@ -563,9 +588,10 @@ KFA_HD void propagate_adj(const T x[6], const T C[21], const T B[6][6], const Pr
   // a04 = -dy, a14 = dx
   const T dxb = b14, dyb = -b04;
   phb += -P.dy * dxb + P.dx * dyb;
+  const T s2 = P.s * P.s;
+  const T vx = P.F1 * P.cp - P.F2 * P.sp, vy = P.F1 * P.sp + P.F2 * P.cp;  // F1 t + F2 n
+  T kBx = 0;  // explicit k_B of the Jacobian terms (a03, a13, a43)
   {
-    const T s2 = P.s * P.s;
-    const T vx = P.F1 * P.cp - P.F2 * P.sp, vy = P.F1 * P.sp + P.F2 * P.cp;  // F1 t + F2 n
     wb += s2 * (vx * dxb + vy * dyb);
     sb += P.cpe * dxb + P.spe * dyb;
     // (a03, a13) = -kB s^2 (F1 t + F2 n)
@@ -574,10 +600,12 @@ KFA_HD void propagate_adj(const T x[6], const T C[21], const T B[6][6], const Pr
     const T F1b = -k.kB * s2 * vt, F2b = -k.kB * s2 * vn;
     sb += -T(2) * k.kB * P.s * (P.F1 * vt + P.F2 * vn);
     ub += F1b * P.F1d + F2b * P.F2d;
+    kBx += -s2 * (P.F1 * vt + P.F2 * vn);
   }
   sb += -b25 / (P.st * P.st);
   thb += b25 * T(2) * P.s * P.ct / (P.st * P.st * P.st);
   sb += -k.kB * b43;
+  kBx += -P.s * b43;
   // u = omega s
   wb += P.s * ub;
   sb += P.w * ub;
@@ -592,6 +620,13 @@ KFA_HD void propagate_adj(const T x[6], const T C[21], const T B[6][6], const Pr
   xb[3] += -k.kB * wb;
   xb[4] += phb;
   xb[5] += thb;
+  if (kBb) {
+    // every kappa term above is -kB times an omega adjoint: the end state's (x, y) and
+    // phi at fixed arc, the Jacobian's displacement and turning terms (wb), and the
+    // arc's implicit dependence; k_B takes -kappa times the same sum
+    const T wall = s2 * (vx * xe0 + vy * xe1) + P.s * xe4 + wb - s2 * (P.ex * vx + P.ey * vy) * is;
+    *kBb += -x[3] * wall + kBx;
+  }
 }
 
 // Adjoint of the seed: state adjoint -> adjoints of the three placed hits.
@@ -668,8 +703,8 @@ KFA_HD void seed_cov(T srphi, T sz, T dr02, T kB, T C[21]) {
 
 // The parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2) (Sec. 3), with what the
 // seed covariance needs to follow it.  Each step takes the field at its start and the
-// seed at its first hit; the sweep holds these values fixed, so the gradient omits the
-// field's own change under the parameters.
+// seed at its first hit; those points move with the parameters, and the sweep carries
+// the field's change with them (field_adj).
 template <class T>
 struct FieldK {
   T fr, fz;
@@ -679,6 +714,15 @@ struct FieldK {
 template <class T>
 KFA_HD T field_kB(const Consts<T>& k, const FieldK<T>& f, T x, T y, T z) {
   return k.kB * (T(1) + f.fr * (x * x + y * y) + f.fz * z * z);
+}
+
+// Adjoint of field_kB at (x, y, z): adds kBb dk_B/d(x, y, z).
+template <class T>
+KFA_HD void field_adj(const Consts<T>& k, const FieldK<T>& f, T x, T y, T z, T kBb, T& xb, T& yb, T& zb) {
+  const T g = T(2) * k.kB * kBb;
+  xb += g * f.fr * x;
+  yb += g * f.fr * y;
+  zb += g * f.fz * z;
 }
 
 template <class T>
@@ -737,7 +781,9 @@ KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lay
       place_adj(ly, h[0], h[1], mb[0], mb[1], mb[2], g);
     }
     scatter_adj(xp, fr, ly, ks, Q, Cb, xb, g[0], g[1], g[4]);
-    propagate_adj(x, C, B, P, ks, xb, Cb, g[0], g[1]);
+    T kBb = 0;
+    propagate_adj(x, C, B, P, ks, xb, Cb, g[0], g[1], fk ? &kBb : nullptr);
+    if (fk) field_adj(k, *fk, x[0], x[1], x[2], kBb, xb[0], xb[1], xb[2]);  // the step's start point
     emit(l, g);
   }
   // seed and the layer-0 update
@@ -765,6 +811,12 @@ KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lay
   T g0[5] = {0, 0, 0, 0, 0};
   T mb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   update_adj(xs, C0, U, w, xb, Cb, mb[0][0], mb[0][1], mb[0][2], g0[0], g0[1]);
+  if (fk) {
+    // the seed's k_B at hit 0: kappa = -omega / k_B and the prior's C[kappa][kappa],
+    // which scales as 1 / k_B^2
+    const T kBb = -(xb[3] * xs[3] + T(2) * Cb[tri(3, 3)] * C0[tri(3, 3)]) / k0.kB;
+    field_adj(k, *fk, m[0][0], m[0][1], m[0][2], kBb, mb[0][0], mb[0][1], mb[0][2]);
+  }
   seed_adj(E, k0, xb, mb[0], mb[1], mb[2]);
   place_adj(lays[0], h[0][0], h[0][1], mb[0][0], mb[0][1], mb[0][2], g0);
   emit(0, g0);

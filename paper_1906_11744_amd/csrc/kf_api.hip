@@ -547,8 +547,8 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
   if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
-  // the adjoint differentiates the per-layer material model; the field enters with each
-  // step's value held fixed
+  // the adjoint differentiates the per-layer material model and the field (with the
+  // points each step and the seed take it at)
   if (ctx->mat_map != nullptr || ctx->eloss > 0.f) return KF_E_UNSUPPORTED;
   if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
   if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
@@ -573,6 +573,7 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   a.k.v_rphi = md.v_rphi;
   a.k.v_z = md.v_z;
   a.k.mass2 = md.mass2;
+  a.k.det_thr = md.det_thr;
   a.srphi = ctx->g.sigma_rphi_cm;
   a.sz = ctx->g.sigma_z_cm;
   a.dr02 = md.dr02;

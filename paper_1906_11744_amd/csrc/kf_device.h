@@ -265,7 +265,7 @@ __device__ __forceinline__ float map_xX0(const float* __restrict__ row, int nz, 
 }
 
 // Mean ionisation loss of a thin layer after its scattering (Sec. 3: energy loss from
-// the material arrays): dE = eloss * x_eff / beta^2 with the scattering term's path
+// the material description): dE = eloss * x_eff / beta^2 with the scattering term's path
 // length x_eff and beta at the incoming momentum p = 1 / (|kappa| sin theta); the
 // energy drops to E' = E - dE at fixed direction, so kappa' = kappa p / p'.  The
 // covariance follows kappa'(kappa, theta): C <- A C A^T with A = I but for the kappa

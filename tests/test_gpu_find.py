@@ -4,13 +4,20 @@ Comparison rule, per seed:
   * the ordered candidate lists (hit index on every layer) are identical, or
   * they hold the same candidates and every swapped pair has equal hit counts and
     oracle total chi2 within TOL_CHI2 (a near-tie; only the rank labels differ), or
-  * the oracle logged an FP32-sensitive decision for the seed (a chi2 within TOL_CHI2
-    of the cut, a hit within TOL_WIN of a window edge, or the last kept and first
-    dropped branch within TOL_CHI2) -- counted and reported, bounded in number.
+  * they differ, and the first decision where they part is one the oracle logged as
+    FP32-sensitive (a chi2 within TOL_CHI2 of the cut, a hit within TOL_WIN of a
+    window edge, the last kept and first dropped branch within TOL_CHI2, or a helix
+    grazing the layer).  The final lists cannot show where the decisions first
+    differed (a divergence on one layer changes which earlier prefixes survive), so
+    that layer is found directly: both finders are run again on the differing seeds
+    with the detector cut after layer L, for L = 3, 4, ..., and the first L whose
+    candidates differ must carry the oracle's flag for that layer.  Such seeds are
+    counted and reported, bounded in number.
 Any other difference fails.  For identical candidates that never crossed a layer
 near-tangentially: state within 1e-4 (relative, floors as the fit), total chi2
 within 0.05 + 1e-4 chi2, counts and the PROP_FAIL / TERM_MISSES status bits exact.
 """
+import dataclasses
 from types import SimpleNamespace
 
 import numpy as np
@@ -29,12 +36,21 @@ TOL_WIN = 1e-3       # relative to the window half width
 HARD = oracle.ST_PROP_FAIL | oracle.ST_TERM_MISSES
 
 
-def run_gpu(geom, ev, keep=6, max_miss=3, chi2_cut=30.0, nsigma=3.0, refit=False, graph=False):
+def run_gpu(geom, ev, keep=6, max_miss=3, chi2_cut=30.0, nsigma=3.0, refit=False, graph=False, material=None,
+            field=None):
+    """kf_find on the GPU; material = (x/X0 map [L][nz] or None, loss) and field = (c_r, c_z)
+    set the detector model."""
     need_gpu()
     from paper_1906_11744_amd import Context
     ctx = Context(geom)
     if graph:
         ctx.set_find_config(use_graph=1)
+    keep_alive = None
+    if material is not None:
+        keep_alive = None if material[0] is None else to_dev(np.asarray(material[0], np.float32))
+        ctx.set_material(keep_alive, material[1])
+    if field is not None:
+        ctx.set_field(*field)
     out = ctx.find(to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event),
                    xX0=to_dev(geom.xX0.astype(np.float32)), chi2_cut=chi2_cut, nsigma=nsigma, keep=keep,
                    max_miss=max_miss, refit=refit)
@@ -42,41 +58,83 @@ def run_gpu(geom, ev, keep=6, max_miss=3, chi2_cut=30.0, nsigma=3.0, refit=False
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def compare(geom, ev, g, r, label):
+def oracle_find(geom, ev, material=None, field=None, **kw):
+    """The oracle's finder on what the GPU reads: a material map and loss rounded to
+    float32, and the field coefficients too."""
+    if material is not None:
+        material = (None if material[0] is None else np.asarray(material[0], np.float32).astype(np.float64),
+                    float(np.float32(material[1])))
+    if field is not None:
+        field = tuple(float(np.float32(c)) for c in field)
+    return oracle.find(geom, ev, tol_abs=TOL_CHI2, tol_rel=TOL_CHI2_REL, tol_win=TOL_WIN, material=material,
+                       field=field, **kw)
+
+
+def _match(g, r, s):
+    """('exact' | 'reordered', [(gpu slot, oracle slot)]) if seed s's candidate lists
+    agree up to near-tie reorderings, else (None, None)."""
+    ng, no = int(g["n_cand"][s]), int(r["n_cand"][s])
+    hg = [tuple(g["hit_idx"][k, :, s]) for k in range(ng)]
+    ho = [tuple(r["hit_idx"][k, :, s]) for k in range(no)]
+    if hg == ho:
+        return "exact", [(k, k) for k in range(ng)]
+    if sorted(hg) != sorted(ho):
+        return None, None
+    pos = {h: k for k, h in enumerate(ho)}
+    perm = [pos[h] for h in hg]
+    for a in range(ng):
+        for b in range(a + 1, ng):
+            if perm[a] > perm[b]:   # GPU ranks a above b, the oracle the other way
+                ca, cb = r["chi2"][perm[a], s], r["chi2"][perm[b], s]
+                same_n = r["n_hits"][perm[a], s] == r["n_hits"][perm[b], s]
+                if not (same_n and abs(ca - cb) <= TOL_CHI2 + TOL_CHI2_REL * max(ca, cb)):
+                    return None, None
+    return "reordered", [(k, perm[k]) for k in range(ng)]
+
+
+def first_divergence(geom, ev, seeds, opts):
+    """{seed: first layer L whose decisions differ} for seeds of `ev` whose final
+    candidates differ: both finders run on those seeds with the geometry cut after
+    layer L (every candidate then survives to the output), L = 3, 4, ...  None if no
+    cut shows a difference."""
+    seeds = np.asarray(seeds, np.int64)
+    first = {int(s): None for s in seeds}
+    sh = np.ascontiguousarray(ev.seed_hits[:, seeds])
+    se = np.ascontiguousarray(ev.seed_event[seeds])
+    pending = list(range(seeds.size))
+    run = {k: v for k, v in opts.items() if k in ("keep", "max_miss", "chi2_cut", "nsigma", "field")}
+    for L in range(3, geom.n_layers):
+        n = L + 1
+        gt = dataclasses.replace(geom, radius=geom.radius[:n], zhalf=geom.zhalf[:n], xX0=geom.xX0[:n])
+        if opts.get("material") is not None:
+            xmap, eloss = opts["material"]
+            run["material"] = (None if xmap is None else np.ascontiguousarray(np.asarray(xmap)[:n]), eloss)
+        sub = SimpleNamespace(hits=ev.hits, hit_off=np.ascontiguousarray(ev.hit_off[:, :n + 1]), seed_hits=sh,
+                              seed_event=se)
+        g = run_gpu(gt, sub, **run)
+        r = oracle_find(gt, sub, **run)
+        for j in pending:
+            if _match(g, r, j)[0] is None:
+                first[int(seeds[j])] = L
+        pending = [j for j in pending if first[int(seeds[j])] is None]
+        if not pending:
+            break
+    return first
+
+
+def compare(geom, ev, g, r, label, **opts):
     S = ev.seed_hits.shape[1]
     stats = dict(exact=0, reordered=0, ambiguous=0, unexplained=[])
     max_rel = 0.0
     max_dchi = 0.0
     status_g = g["status"].view(np.uint32)
+    differ = []
     for s in range(S):
-        ng, no = int(g["n_cand"][s]), int(r["n_cand"][s])
-        hg = [tuple(g["hit_idx"][k, :, s]) for k in range(ng)]
-        ho = [tuple(r["hit_idx"][k, :, s]) for k in range(no)]
-        if hg == ho:
-            stats["exact"] += 1
-            pairs = [(k, k) for k in range(ng)]
-        elif sorted(hg) == sorted(ho):
-            pos = {h: k for k, h in enumerate(ho)}
-            perm = [pos[h] for h in hg]
-            ok = True
-            for a in range(ng):
-                for b in range(a + 1, ng):
-                    if perm[a] > perm[b]:   # GPU ranks a above b, oracle the other way
-                        ca, cb = r["chi2"][perm[a], s], r["chi2"][perm[b], s]
-                        same_n = r["n_hits"][perm[a], s] == r["n_hits"][perm[b], s]
-                        if not (same_n and abs(ca - cb) <= TOL_CHI2 + TOL_CHI2_REL * max(ca, cb)):
-                            ok = False
-            if not ok and r["ambig"][s] == 0:
-                stats["unexplained"].append(s)
-                continue
-            stats["reordered"] += 1
-            pairs = [(k, perm[k]) for k in range(ng)]
-        else:
-            if r["ambig"][s] != 0:
-                stats["ambiguous"] += 1
-            else:
-                stats["unexplained"].append(s)
+        kind, pairs = _match(g, r, s)
+        if kind is None:
+            differ.append(s)
             continue
+        stats[kind] += 1
         for kg, ko in pairs:
             assert g["n_hits"][kg, s] == r["n_hits"][ko, s]
             assert g["n_miss"][kg, s] == r["n_miss"][ko, s]
@@ -89,20 +147,19 @@ def compare(geom, ev, g, r, label):
             max_dchi = max(max_dchi, dchi)
             assert rel < 1e-4, (label, s, kg, rel, g["state"][kg, :, s], r["state"][ko, :, s], r["n_miss"][ko, s])
             assert dchi < 0.05 + 1e-4 * r["chi2"][ko, s], (label, s, kg, dchi)
+    where = first_divergence(geom, ev, differ, opts) if differ else {}
+    for s in differ:
+        L = where[s]
+        if L is not None and (int(r["ambig"][s]) >> L) & 1:
+            stats["ambiguous"] += 1
+        else:
+            stats["unexplained"].append((s, L, int(r["ambig"][s])))
     print(f"[{label}] seeds {S}: identical {stats['exact']}, reordered near-ties {stats['reordered']}, "
-          f"differ at flagged decisions {stats['ambiguous']} (flagged seeds {(r['ambig'] != 0).sum()}), "
+          f"first divergence at a flagged decision {stats['ambiguous']} (flagged seeds {(r['ambig'] != 0).sum()}), "
           f"unexplained {len(stats['unexplained'])}; max rel state err {max_rel:.2e}, max |dchi2| {max_dchi:.2e}")
-    if stats["unexplained"]:
-        bad = np.array(stats["unexplained"])
-        np.savez_compressed(f"gpurun_out/find_unexplained_{label.replace(' ', '_').replace(',', '')}.npz", seeds=bad,
-                            **{f"gpu_{k}": v[..., bad] for k, v in g.items()},
-                            **{f"orc_{k}": v[..., bad] for k, v in r.items()})
-    assert not stats["unexplained"], (label, stats["unexplained"][:20])
+    assert not stats["unexplained"], (label, "(seed, first divergent layer, oracle flags)",
+                                      stats["unexplained"][:20])
     return stats
-
-
-def oracle_find(geom, ev, **kw):
-    return oracle.find(geom, ev, tol_abs=TOL_CHI2, tol_rel=TOL_CHI2_REL, tol_win=TOL_WIN, **kw)
 
 
 def test_find_one_event_5000_tracks():
@@ -119,7 +176,7 @@ def test_find_small_events_and_options(n_tracks, keep, max_miss):
     geom, ev = synth.find_workload(3, n_tracks=n_tracks)
     g = run_gpu(geom, ev, keep=keep, max_miss=max_miss)
     r = oracle_find(geom, ev, keep=keep, max_miss=max_miss)
-    compare(geom, ev, g, r, f"{n_tracks} tracks keep={keep} max_miss={max_miss}")
+    compare(geom, ev, g, r, f"{n_tracks} tracks keep={keep} max_miss={max_miss}", keep=keep, max_miss=max_miss)
 
 
 def test_find_wide_windows_wrap():
@@ -127,7 +184,7 @@ def test_find_wide_windows_wrap():
     geom, ev = synth.find_workload(3, n_tracks=120)
     g = run_gpu(geom, ev, nsigma=300.0, chi2_cut=50.0)
     r = oracle_find(geom, ev, nsigma=300.0, chi2_cut=50.0)
-    compare(geom, ev, g, r, "wide windows")
+    compare(geom, ev, g, r, "wide windows", nsigma=300.0, chi2_cut=50.0)
 
 
 def test_find_batched_events_and_refit():

@@ -180,6 +180,24 @@ def test_forced_fp64_fallback_matches():
     assert np.isfinite(d).all()
 
 
+def test_fallback_flag_at_known_correlation():
+    """Updates whose S has measured rows of a constructed correlation rho (determinant
+    of the equilibrated S = 1 - rho^2, on both sides of the 1e-2 threshold): the FP32
+    condition check sends exactly those below the threshold to FP64, as the oracle
+    flags them, and the chi2 of the FP64 path matches the oracle's."""
+    geom = synth.workload_geometry(2)
+    hits, mask, st, cov = physics.correlated_seeds(geom, physics.FALLBACK_DETS)
+    ts = type("T", (), dict(hits=hits, hit_mask=mask))
+    out = _run(geom, ts, seeds=(st, cov))
+    ref = oracle.fit(geom, hits, mask, seed_state=st, seed_cov=cov)
+    got = (out["status"].cpu().numpy().view(np.uint32) & 4) != 0
+    expect = np.array(physics.FALLBACK_DETS) < 1e-2
+    np.testing.assert_array_equal(got, expect)
+    np.testing.assert_array_equal(got, (ref["status"] & oracle.ST_ILLCOND) != 0)
+    c2 = out["chi2"].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(c2 - ref["chi2"]) < 0.05 + 1e-4 * ref["chi2"]), (c2, ref["chi2"])
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_noiseless_hits_return_generating_helix(k):
     """Noiseless hits and no material, seeds from the hits: the FP32 fit ends on the

@@ -23,12 +23,14 @@ def _case(n, at_truth):
     return geom, ts, align
 
 
-def _gpu_grad(geom, ts, align, w, field=None):
+def _gpu_grad(geom, ts, align, w, field=None, det_threshold=None):
     need_gpu()
     from paper_1906_11744_amd import Context
     kf = Context(geom)
     if field is not None:
         kf.set_field(*field)
+    if det_threshold is not None:
+        kf.set_fallback_threshold(det_threshold)
     hits, mask = to_dev(ts.hits), mask_dev(ts.hit_mask)
     a = to_dev(np.asarray(align, np.float32))
     x = to_dev(geom.xX0.astype(np.float32))
@@ -75,9 +77,10 @@ def test_gradient_full_size_1e5_tracks():
 @pytest.mark.parametrize("at_truth", [False, True])
 def test_gradient_in_the_field_matches_fp64_reference(at_truth):
     """Tracks simulated in the parameterised field B (1 + c_r r^2 + c_z z^2), fitted and
-    differentiated in it: each step's field enters at its value, as in the oracle; the
-    gradient taken in the uniform field differs from the reference by far more than
-    the tolerance."""
+    differentiated in it: the reverse sweep carries the field's change with each step's
+    start point and the seed's first hit, and the reference is the oracle's exact
+    dual-number gradient; the gradient taken in the uniform field differs from it by far
+    more than the tolerance."""
     geom = synth.workload_geometry(2)
     a_true = synth.misalignment(geom.n_layers)
     fld = synth.FIELD_SOLENOID
@@ -109,6 +112,21 @@ def test_gradient_in_the_field_full_size_1e5_tracks():
     ra, rx = oracle.fit_grad(geom, np.ascontiguousarray(ts.hits[:, :, idx]), ts.hit_mask[idx], align, geom.xX0,
                              field=fld)
     _check(ga, gx, ra, rx, "field, 1e5 tracks, 2000 weighted")
+
+
+@pytest.mark.parametrize("at_truth", [False, True])
+def test_gradient_with_forced_fp64_inverse(at_truth):
+    """A fallback threshold above 1 sends every update's S^-1 to FP64 in the forward fit;
+    the reverse sweep then recomputes each S^-1 by the same FP64 path, and the gradient
+    still equals the FP64 reference."""
+    geom, ts, align = _case(2000, at_truth)
+    w = np.random.default_rng(7).uniform(0.5, 1.5, ts.hits.shape[2])
+    ga, gx, fwd = _gpu_grad(geom, ts, align, w, det_threshold=2.0)
+    st = fwd["status"].cpu().numpy().view(np.uint32)
+    fitted = (st & (oracle.ST_BAD_INPUT | oracle.ST_PROP_FAIL)) == 0
+    assert np.all(st[fitted] & oracle.ST_ILLCOND)
+    ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w)
+    _check(ga, gx, ra, rx, f"forced FP64 S^-1, align {'true' if at_truth else 'zero'}")
 
 
 def test_backward_is_deterministic():

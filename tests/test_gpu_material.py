@@ -244,8 +244,8 @@ def test_finder_with_the_detector_model(loss_scale):
                    xX0=t(geom.xX0.astype(np.float32)), refit=True)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items()}
-    r = oracle_find(geom, ev, refit=True, material=_oracle_material(mat), field=_oracle_field(fld))
-    stats = compare(geom, ev, g, r, f"finder with map, loss x {loss_scale:g} and field")
+    r = oracle_find(geom, ev, refit=True, material=mat, field=fld)
+    stats = compare(geom, ev, g, r, f"finder with map, loss x {loss_scale:g} and field", material=mat, field=fld)
     assert stats["exact"] + stats["reordered"] > 0.97 * ev.seed_hits.shape[1]
     stops = ((r["status"][0] & oracle.ST_PROP_FAIL) != 0).sum()
     print(f"oracle rank-0 candidates ending with PROP_FAIL: {stops}")
