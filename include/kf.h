@@ -50,6 +50,7 @@ extern "C" {
 #define KF_E_UNSUPPORTED (-2) /* valid request the library does not implement */
 #define KF_E_WORKSPACE (-3)   /* workspace missing, too small or misaligned */
 #define KF_E_HIP (-4)         /* the HIP runtime reported an error at launch */
+#define KF_E_SCRATCH (-5)     /* request larger than the library's static scratch */
 
 /* per-track status bits */
 #define KF_ST_PROP_FAIL 1u     /* the helix does not reach a layer it must cross; the fit stops there */
@@ -300,6 +301,25 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
  * map or an energy loss is set (kf_ctx_set_material). */
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream);
+
+/* kf_fit_backward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * reverse sweep and the same bits as kf_fit_backward, with its workspace (the layer
+ * table and the per-block FP64 partials, kf_workspace_size(KF_OP_FIT_BACKWARD, in)
+ * bytes) taken from a scratch array that the library holds in every GPU's memory
+ * instead of from a caller's `ws`.  The scratch is kf_static_scratch_bytes() = 16 MiB
+ * per GPU, held from the first call on that GPU until the process ends (17 layers:
+ * up to ~1.5e6 tracks; 32 layers: ~8e5).  A larger request returns KF_E_SCRATCH
+ * before anything is launched; other errors as kf_fit_backward.  The call allocates
+ * nothing.  Every call on one GPU shares that GPU's scratch, whatever the context or
+ * stream: calls that may overlap on one GPU (different streams, threads) race and
+ * must be serialised by the caller.  The scratch keeps the last call's contents;
+ * nothing in it needs clearing (every byte is written before it is read). */
+int kf_fit_backward_static(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+                           const float* dchi2, float* dalign, float* dxX0, void* stream);
+
+/* Bytes of the static scratch of kf_fit_backward_static (per GPU). */
+size_t kf_static_scratch_bytes(void);
 
 /* Output of kf_smooth: state [L][6][n] and cov [L][21][n] (packed lower triangle) of
  * every layer first[i]..last[i] of track i, zero on the other layers; last [n] = the

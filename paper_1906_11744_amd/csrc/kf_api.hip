@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -72,6 +73,12 @@ bool valid_geometry(const kf_geometry* g) {
 
 // Workspace of a fit: the per-layer constants.
 size_t fit_ws_bytes() { return round_up(sizeof(kfd::LayerK) * KF_MAX_LAYERS); }
+
+// Workspace of the adjoint: the layer table, then [L][5][blocks] FP64 partials.
+size_t backward_ws_bytes(const kf_ctx* ctx, int64_t n) {
+  return fit_ws_bytes() + round_up((size_t)ctx->g.n_layers * 5 * (size_t)kfi::adjoint_blocks(n > 0 ? n : 0) *
+                                   sizeof(double));
+}
 
 // Workspace of a find: layer constants | binned records [H] float4 | binned indices [H]
 // | bin offsets [E][L][nbins + 1] | tile counter.
@@ -248,9 +255,7 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
       return KF_OK;
     case KF_OP_FIT_BACKWARD: {
       const kf_fit_in* f = static_cast<const kf_fit_in*>(in);
-      const size_t n = (size_t)(f->n > 0 ? f->n : 0);
-      *bytes = fit_ws_bytes() + round_up((size_t)ctx->g.n_layers * 5 * (size_t)kfi::adjoint_blocks((int64_t)n) *
-                                         sizeof(double));
+      *bytes = backward_ws_bytes(ctx, f->n);
       return KF_OK;
     }
     case KF_OP_CLEAN_SEEDS: {
@@ -542,8 +547,13 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
   return enqueue_find(ctx, params, in, out, ws, st);
 }
 
-int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
-                    const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks of the adjoint (everything but the workspace).
+int check_backward(const kf_ctx* ctx, const kf_fit_in* in, const kf_fit_out* fwd, const float* dchi2,
+                   const float* dalign, const float* dxX0) {
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
   if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
@@ -553,12 +563,13 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
   if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
     return KF_E_INVALID;
-  size_t need = 0;
-  kf_workspace_size(ctx, KF_OP_FIT_BACKWARD, in, &need);
-  int rc = check_ws(ws, ws_bytes, need);
-  if (rc != KF_OK) return rc;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
+  return KF_OK;
+}
+
+// The adjoint's launches with its scratch at `base` (layer table, then the per-block
+// FP64 partials; every byte is written before it is read, nothing needs clearing).
+int enqueue_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+                     const float* dchi2, float* dalign, float* dxX0, char* base, hipStream_t st) {
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base);
   const float* align = params ? params->align : nullptr;
   const float* xX0 = params ? params->xX0 : nullptr;
@@ -590,6 +601,58 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
   a.part = reinterpret_cast<double*>(base + fit_ws_bytes());
   return kfi::launch_adjoint(a, dalign, dxX0, st) == hipSuccess ? KF_OK : KF_E_HIP;
 }
+
+// Scratch of kf_fit_backward_static: one copy per GPU in the code object's device
+// memory, alive until the process ends.  Host code never passes `scratch` itself (its
+// host-side name is not a device address): each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return KF_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KF_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+                    const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_backward(ctx, in, fwd, dchi2, dalign, dxX0);
+  if (rc != KF_OK) return rc;
+  rc = check_ws(ws, ws_bytes, backward_ws_bytes(ctx, in->n));
+  if (rc != KF_OK) return rc;
+  return enqueue_backward(ctx, params, in, fwd, dchi2, dalign, dxX0, static_cast<char*>(ws),
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+int kf_fit_backward_static(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
+                           const float* dchi2, float* dalign, float* dxX0, void* stream) {
+  int rc = check_backward(ctx, in, fwd, dchi2, dalign, dxX0);
+  if (rc != KF_OK) return rc;
+  if (backward_ws_bytes(ctx, in->n) > kStaticScratchBytes) return KF_E_SCRATCH;
+  void* base = nullptr;
+  rc = static_scratch(&base);
+  if (rc != KF_OK) return rc;
+  return enqueue_backward(ctx, params, in, fwd, dchi2, dalign, dxX0, static_cast<char*>(base),
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t kf_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
 int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
               const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream) {
@@ -772,6 +835,7 @@ const char* kf_strerror(int code) {
     case KF_E_UNSUPPORTED: return "unsupported request";
     case KF_E_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
     case KF_E_HIP: return "HIP runtime error at launch";
+    case KF_E_SCRATCH: return "request exceeds the library's static scratch (kf_static_scratch_bytes)";
     default: return "unknown error code";
   }
 }

@@ -115,6 +115,10 @@ def _lib():
                                   C.POINTER(SmoothOut), C.c_void_p, C.c_size_t, C.c_void_p]
         lib.kf_fit_backward.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn), C.POINTER(FitOut),
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        lib.kf_fit_backward_static.argtypes = [C.c_void_p, C.POINTER(LayerParams), C.POINTER(FitIn),
+                                               C.POINTER(FitOut), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.kf_static_scratch_bytes.restype = C.c_size_t
+        lib.kf_static_scratch_bytes.argtypes = []
         _LIB = lib
     return _LIB
 
@@ -454,6 +458,36 @@ class Context:
                                       C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "kf_fit_backward")
         return da, dx
 
+    def fit_backward_static(self, hits, hit_mask, fwd, dchi2, align=None, xX0=None, out=None, stream=None):
+        """kf_fit_backward_static: as fit_backward, with the library's static per-GPU
+        scratch instead of a workspace.  out = (dalign [L][4], dxX0 [L]) float32 device
+        tensors to write (allocated here if None; pass them to allocate nothing)."""
+        L = self.n_layers
+        n = hits.shape[2]
+        dev = hits.device
+        _dev(hits, torch.float32, (L, 3, n), "hits")
+        _dev(dchi2, torch.float32, (n,), "dchi2")
+        if fwd.get("ckpt") is None:
+            raise ValueError("the forward fit must be run with ckpt=True")
+        if out is None:
+            out = (torch.empty((L, 4), dtype=torch.float32, device=dev), torch.empty(L, dtype=torch.float32, device=dev))
+        da, dx = out
+        _dev(da, torch.float32, (L, 4), "dalign")
+        _dev(dx, torch.float32, (L,), "dxX0")
+        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1)
+        fo = FitOut(fwd["state"].data_ptr(), fwd["cov"].data_ptr(), fwd["chi2"].data_ptr(),
+                    fwd["ndf"].data_ptr(), fwd["status"].data_ptr(), fwd["ckpt"].data_ptr())
+        p = self._params(align, xX0)
+        _check(_lib().kf_fit_backward_static(self._h, C.byref(p), C.byref(fin), C.byref(fo),
+                                             C.c_void_p(dchi2.data_ptr()), C.c_void_p(da.data_ptr()),
+                                             C.c_void_p(dx.data_ptr()), _stream(stream)), "kf_fit_backward_static")
+        return da, dx
+
+
+def static_scratch_bytes() -> int:
+    """Per-GPU bytes of the scratch behind Context.fit_backward_static."""
+    return int(_lib().kf_static_scratch_bytes())
+
 
 def exported_symbols():
     """Names the header declares (for the load check)."""
@@ -461,4 +495,4 @@ def exported_symbols():
             "kf_ctx_set_material", "kf_ctx_set_field", "kf_ctx_set_find_config",
             "kf_ctx_get_find_config", "kf_workspace_size", "kf_fit", "kf_find", "kf_find_autotune",
             "kf_smooth", "kf_fit_backward", "kf_ctx_set_dedup_cuts", "kf_ctx_get_dedup_cuts", "kf_clean_seeds",
-            "kf_remove_duplicates", "kf_strerror"]
+            "kf_remove_duplicates", "kf_strerror", "kf_fit_backward_static", "kf_static_scratch_bytes"]

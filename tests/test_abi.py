@@ -20,7 +20,7 @@ def _lib():
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "kf.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(kf_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(kf_\w+)\s*\(", src, flags=re.M)))
 
 
 def test_header_declares_the_three_calls():
@@ -221,3 +221,25 @@ def test_field_setting_validation_and_the_calls_it_excludes():
     ctx0 = kf.Context(g0)
     assert lib.kf_ctx_set_field(ctx0._h, C.c_float(0.0), C.c_float(-4e-6)) == -2
     assert lib.kf_ctx_set_field(ctx0._h, C.c_float(0.0), C.c_float(0.0)) == 0
+
+
+def test_static_backward_rejects_requests_beyond_its_scratch():
+    """kf_fit_backward_static checks the size on the host and returns KF_E_SCRATCH
+    before anything is launched (the pointers below are never dereferenced); a request
+    that fits passes that check (and would launch: not run here)."""
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    assert lib.kf_static_scratch_bytes() == 16 << 20
+    fake = C.c_void_p(256)
+    ws = C.c_size_t()
+    for n, fits in [(2_000_000, False), (1_500_000, True)]:
+        fin = kf.FitIn(n, fake, fake, None, None, 1)
+        assert lib.kf_workspace_size(ctx._h, kf.KF_OP_FIT_BACKWARD, C.byref(fin), C.byref(ws)) == 0
+        assert (ws.value <= lib.kf_static_scratch_bytes()) == fits
+    fin = kf.FitIn(2_000_000, fake, fake, None, None, 1)
+    fo = kf.FitOut(fake, fake, fake, fake, fake, fake)
+    p = kf.LayerParams(None, None)
+    rc = lib.kf_fit_backward_static(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), fake, fake, fake, None)
+    assert rc == -5 and b"static scratch" in lib.kf_strerror(rc)
+    # argument errors come first, as for kf_fit_backward
+    assert lib.kf_fit_backward_static(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), fake, None, fake, None) == -1
