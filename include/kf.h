@@ -43,6 +43,7 @@ extern "C" {
 #define KF_MAX_LAYERS 32
 #define KF_MAX_KEEP 8
 #define KF_MAX_MAP_BINS 64
+#define KF_MAX_FIND_BINS 32768 /* phi x z bins of kf_find's hit binning */
 
 /* return codes */
 #define KF_OK 0
@@ -80,7 +81,7 @@ typedef struct kf_geometry {
   float mass_gev;                /* particle mass in the Highland beta */
   int32_t n_phi_bins;            /* finder bins in phi over [-pi, pi): 1 .. 1024 */
   int32_t n_z_bins;              /* finder bins in z over [-Z, Z]: 1 .. 256; kf_find needs */
-                                 /* n_phi_bins * n_z_bins <= 8192 */
+                                 /* n_phi_bins * n_z_bins <= KF_MAX_FIND_BINS */
 } kf_geometry;
 
 typedef struct kf_ctx kf_ctx;
@@ -224,6 +225,17 @@ int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z);
 
 /* Launch configuration of kf_find, held by the context.  Outputs do not depend on it
  * (same bits for every valid configuration); only the time does.
+ *   n_phi_bins, n_z_bins: the tiling of each (event, layer)'s hits into bins over
+ *     [-pi, pi) x [-Z, Z] that the search walks (0 = the geometry's n_phi_bins,
+ *     n_z_bins).  Every window is covered by the bins it overlaps, and the hits tested
+ *     inside it and their order of preference do not depend on the tiling, so finer
+ *     bins change only how many hits outside the window are looked at.  1 .. 1024 and
+ *     1 .. 256, product at most KF_MAX_FIND_BINS.
+ *   lanes_per_seed: the lanes of a 64-lane wave that hold one seed's candidates (one
+ *     candidate per lane): 4, 6 or 8, at least the call's keep (a call with keep above
+ *     it returns KF_E_INVALID); 0 (the default) = the fewest of these that hold keep.
+ *     A wave works on 64 / lanes_per_seed seeds at once, so the candidates per wave are
+ *     that times keep: with keep = 6, 60 at 6 lanes per seed and 48 at 8.
  *   wide_window_bins: a candidate whose search window overlaps more than this many
  *     bins is scanned by all 64 lanes of its wave instead of its own lane (>= 0;
  *     default 16; 0 sends every window to the wave-wide scan).
@@ -241,10 +253,13 @@ typedef struct kf_find_config {
   int32_t wide_window_bins;
   int32_t blocks_per_cu;
   int32_t use_graph;
+  int32_t n_phi_bins;
+  int32_t n_z_bins;
+  int32_t lanes_per_seed;
 } kf_find_config;
 
-/* Set / read the context's kf_find configuration.  KF_E_INVALID for negative fields or
- * use_graph other than 0 or 1. */
+/* Set / read the context's kf_find configuration.  KF_E_INVALID for negative fields,
+ * use_graph other than 0 or 1, or a bin tiling out of range. */
 int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg);
 int kf_ctx_get_find_config(const kf_ctx* ctx, kf_find_config* cfg);
 
@@ -281,11 +296,14 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
             void* ws, size_t ws_bytes, void* stream);
 
 /* Autotuner of kf_find's configuration for inputs like `in`: runs kf_find (arguments
- * as for kf_find; `out` receives the usual results) under each candidate configuration
- * (wide_window_bins 4, 8, 16, 32, 64 x blocks_per_cu 0, 1; use_graph as set), times two calls of each
- * with HIP events on `stream`, keeps the fastest in the context and copies it to
- * *best (if not NULL).  Unlike every other call it SYNCHRONISES on `stream`.  On error
- * the previous configuration is kept and the error code returned. */
+ * as for kf_find; `out` receives the usual results) under candidate configurations,
+ * times two calls of each with HIP events on `stream` (after one untimed call), keeps
+ * the fastest in the context and copies it to *best (if not NULL).  The candidates:
+ * the bin tiling (the geometry's, and phi x z = 256 x 32, 128 x 64, 256 x 64, 512 x 32,
+ * 512 x 64, 256 x 128, 1024 x 32) crossed with wide_window_bins 8, 32, 128 (lanes per
+ * seed 0); then, from the best, each other lanes_per_seed of 4, 6, 8 that holds keep;
+ * then wide_window_bins 4, 16, 64; then blocks_per_cu 0, 12; use_graph as set.  Unlike every other call it SYNCHRONISES on `stream`.  On error the previous
+ * configuration is kept and the error code returned. */
 int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
                      void* ws, size_t ws_bytes, void* stream, kf_find_config* best);
 

@@ -17,7 +17,7 @@ struct kf_ctx {
   };
   kf_geometry g;
   float det_thr;
-  kf_find_config fcfg{16, 0, 0};
+  kf_find_config fcfg{16, 0, 0, 0, 0, 0};
   hipStream_t cap_stream = nullptr;  // capture stream of the graph path
   int cap_device = -1;
   uint64_t tick = 0;
@@ -29,7 +29,7 @@ struct kf_ctx {
   }
   int grid_device = -1;   // device the occupancy figures below were taken on
   int grid_cus = 0;       // compute units
-  int grid_per_cu[2] = {0, 0};  // find workgroups that fit on one compute unit (plain, model variant)
+  int grid_per_cu[2][3] = {};  // find workgroups that fit on one compute unit ([plain, model][4, 6, 8 lanes])
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // timing hook (kf_ctx_set_launch_events)
   kf_dedup_cuts dcuts{0.05f, 2, 1, 0.1f, 0.15f, 0.03f, 0.02f, 0.5f, 0.5f, 0.1f, 0.01f, 0.02f};
   const float* mat_map = nullptr;  // material model (kf_ctx_set_material)
@@ -81,22 +81,52 @@ size_t backward_ws_bytes(const kf_ctx* ctx, int64_t n) {
 }
 
 // Workspace of a find: layer constants | binned records [H] float4 | binned indices [H]
-// | bin offsets [E][L][nbins + 1] | tile counter.
+// | bin offsets [E][L][nbins + 1] | tile counter | backpointers of the persistent
+// workgroups' current tiles.
 struct FindWs {
-  size_t layers, brec, bidx, boff, counter, total;
+  size_t layers, brec, bidx, boff, counter, bp, total;
 };
+
+int64_t find_tiles(const kf_find_in* in, int lanes_per_seed) {
+  const int64_t t = kfi::find_tile_seeds(lanes_per_seed);
+  return in->n_seeds > 0 ? (in->n_seeds + t - 1) / t : 0;
+}
+
+// Persistent find workgroups at most: as many as tiles of the largest grouping (8 lanes
+// per seed, the fewest seeds per tile), and kMaxFindGrid.
+int64_t find_grid_cap(const kf_find_in* in) {
+  const int64_t t = find_tiles(in, 8);
+  return t < kfi::kMaxFindGrid ? t : kfi::kMaxFindGrid;
+}
+
+// Lanes per seed of a find call: the configuration's, else the fewest of 4, 6, 8 that
+// hold `keep` candidates; 0 if the configuration's is below keep.
+int find_group(const kf_ctx* c, int keep) {
+  if (c->fcfg.lanes_per_seed > 0) return c->fcfg.lanes_per_seed >= keep ? c->fcfg.lanes_per_seed : 0;
+  return keep <= 4 ? 4 : (keep <= 6 ? 6 : 8);
+}
+
+int group_index(int lanes_per_seed) { return lanes_per_seed == 4 ? 0 : (lanes_per_seed == 6 ? 1 : 2); }
+
+// The bin tiling kf_find walks: the configuration's, else the geometry's.
+void find_bins(const kf_ctx* c, int* nphi, int* nz) {
+  *nphi = c->fcfg.n_phi_bins > 0 ? c->fcfg.n_phi_bins : c->g.n_phi_bins;
+  *nz = c->fcfg.n_z_bins > 0 ? c->fcfg.n_z_bins : c->g.n_z_bins;
+}
 
 FindWs find_ws(const kf_ctx* c, const kf_find_in* in) {
   FindWs w;
   const size_t H = (size_t)(in->n_hits > 0 ? in->n_hits : 0);
-  const size_t nb = (size_t)c->g.n_phi_bins * c->g.n_z_bins + 1;
+  // bin offsets for the largest tiling, so that one workspace serves every configuration
+  const size_t nb = (size_t)KF_MAX_FIND_BINS + 1;
   const size_t E = (size_t)(in->n_events > 0 ? in->n_events : 0);
   w.layers = 0;
   w.brec = w.layers + fit_ws_bytes();
   w.bidx = w.brec + round_up(H * 16);
   w.boff = w.bidx + round_up(H * 4);
   w.counter = w.boff + round_up(E * c->g.n_layers * nb * 4);
-  w.total = w.counter + kAlign;
+  w.bp = w.counter + kAlign;
+  w.total = w.bp + round_up(kfi::find_bp_bytes(c->g.n_layers, find_grid_cap(in)));
   return w;
 }
 
@@ -128,20 +158,23 @@ DedupWs dedup_ws(const kf_ctx* c, int64_t n_items, int32_t n_events) {
   return w;
 }
 
-int persistent_grid(kf_ctx* c, int nl, int* grid) {
+int persistent_grid(kf_ctx* c, int nl, int lanes_per_seed, int* grid) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return KF_E_HIP;
   if (c->grid_device != dev) {
-    int cus = 0, per = 0, per_model = 0;
+    int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return KF_E_HIP;
-    if (kfi::find_max_blocks(nl, false, &per) != hipSuccess) return KF_E_HIP;
-    if (kfi::find_max_blocks(nl, true, &per_model) != hipSuccess) return KF_E_HIP;
+    for (int m = 0; m < 2; ++m)
+      for (int gi = 0; gi < 3; ++gi) {
+        int per = 0;
+        if (kfi::find_max_blocks(nl, m == 1, gi == 0 ? 4 : (gi == 1 ? 6 : 8), &per) != hipSuccess) return KF_E_HIP;
+        c->grid_per_cu[m][gi] = per > 0 ? per : 1;
+      }
+    if (kfi::prepare_bin(KF_MAX_FIND_BINS) != hipSuccess) return KF_E_HIP;
     c->grid_cus = cus;
-    c->grid_per_cu[0] = per > 0 ? per : 1;
-    c->grid_per_cu[1] = per_model > 0 ? per_model : 1;
     c->grid_device = dev;
   }
-  const int have = c->grid_per_cu[c->material() ? 1 : 0];
+  const int have = c->grid_per_cu[c->material() ? 1 : 0][group_index(lanes_per_seed)];
   const int want = c->fcfg.blocks_per_cu;
   *grid = c->grid_cus * (want > 0 && want < have ? want : have);
   return KF_OK;
@@ -210,8 +243,13 @@ int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z) {
 
 int kf_ctx_set_find_config(kf_ctx* ctx, const kf_find_config* cfg) {
   if (!ctx || !cfg || cfg->wide_window_bins < 0 || cfg->blocks_per_cu < 0 || cfg->use_graph < 0 ||
-      cfg->use_graph > 1)
+      cfg->use_graph > 1 || cfg->n_phi_bins < 0 || cfg->n_phi_bins > 1024 || cfg->n_z_bins < 0 ||
+      cfg->n_z_bins > 256 || !(cfg->lanes_per_seed == 0 || cfg->lanes_per_seed == 4 || cfg->lanes_per_seed == 6 ||
+                               cfg->lanes_per_seed == 8))
     return KF_E_INVALID;
+  const int nphi = cfg->n_phi_bins > 0 ? cfg->n_phi_bins : ctx->g.n_phi_bins;
+  const int nz = cfg->n_z_bins > 0 ? cfg->n_z_bins : ctx->g.n_z_bins;
+  if ((int64_t)nphi * nz > KF_MAX_FIND_BINS) return KF_E_INVALID;
   ctx->fcfg = *cfg;
   return KF_OK;
 }
@@ -324,6 +362,7 @@ int check_find(kf_ctx* ctx, const kf_find_in* in, const kf_find_out* out, void* 
   if (!ctx || !in || !out) return KF_E_INVALID;
   if (in->n_events < 0 || in->n_seeds < 0 || in->n_hits < 0) return KF_E_INVALID;
   if (in->keep < 1 || in->keep > KF_MAX_KEEP || in->max_miss < 1) return KF_E_INVALID;
+  if (find_group(ctx, in->keep) == 0) return KF_E_INVALID;  // configured lanes per seed below keep
   if (!(in->chi2_cut > 0.f) || !(in->nsigma > 0.f)) return KF_E_INVALID;
   if (in->n_seeds == 0) return KF_OK;
   if (in->n_events == 0 || !in->hit_off || !in->hits || !in->seed_event || !in->seed_hits) return KF_E_INVALID;
@@ -335,13 +374,18 @@ int check_find(kf_ctx* ctx, const kf_find_in* in, const kf_find_out* out, void* 
   // hit indices travel as (index + 2) << 3 in 32-bit backpointers
   if (in->n_hits >= (int64_t(1) << 28) - 2 || in->n_seeds >= (int64_t)INT32_MAX * 32) return KF_E_UNSUPPORTED;
   if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
-  if ((int64_t)ctx->g.n_phi_bins * ctx->g.n_z_bins > 8192) return KF_E_UNSUPPORTED;  // LDS of the bin kernel
+  int nphi = 0, nz = 0;
+  find_bins(ctx, &nphi, &nz);
+  if ((int64_t)nphi * nz > KF_MAX_FIND_BINS) return KF_E_UNSUPPORTED;  // LDS of the bin kernel
   return check_ws(ws, ws_bytes, find_ws(ctx, in).total);
 }
 
 // The launches of one kf_find call (arguments already checked, n_seeds > 0).
 int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
                  void* ws, hipStream_t st) {
+  const int group = find_group(ctx, in->keep);
+  int grid = 0;  // (also readies the kernels' LDS limits before the first launch)
+  if (persistent_grid(ctx, ctx->g.n_layers, group, &grid) != KF_OK) return KF_E_HIP;
   const FindWs w = find_ws(ctx, in);
   char* base = static_cast<char*>(ws);
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base + w.layers);
@@ -352,8 +396,7 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
     return KF_E_HIP;
   kfi::BinArgs b;
   b.nl = ctx->g.n_layers;
-  b.nphi = ctx->g.n_phi_bins;
-  b.nz = ctx->g.n_z_bins;
+  find_bins(ctx, &b.nphi, &b.nz);
   b.n_events = in->n_events;
   b.H = in->n_hits;
   b.hit_off = in->hit_off;
@@ -380,7 +423,8 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   f.sz = ctx->g.sigma_z_cm;
   f.n_seeds = in->n_seeds;
   f.H = in->n_hits;
-  f.n_tiles = (in->n_seeds + 31) / 32;
+  f.n_tiles = find_tiles(in, group);
+  f.bp = reinterpret_cast<int32_t*>(base + w.bp);
   f.hits = in->hits;
   f.seed_event = in->seed_event;
   f.seed_hits = in->seed_hits;
@@ -403,10 +447,9 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   f.state = out->state;
   f.cov = out->cov;
   f.status = out->status;
-  int grid = 0;
-  if (persistent_grid(ctx, b.nl, &grid) != KF_OK) return KF_E_HIP;
+  if ((int64_t)grid > find_grid_cap(in)) grid = (int)find_grid_cap(in);
   if ((int64_t)grid > f.n_tiles) grid = (int)f.n_tiles;
-  if (kfi::launch_find(f, grid, st) != hipSuccess) return KF_E_HIP;
+  if (kfi::launch_find(f, group, grid, st) != hipSuccess) return KF_E_HIP;
   if (in->refit) {
     kfi::FitArgs a;
     a.n = in->n_seeds;
@@ -482,6 +525,9 @@ std::vector<uint64_t> find_key(const kf_ctx* ctx, int dev, const kf_layer_params
           f(ctx->fz),
           (uint64_t)ctx->fcfg.wide_window_bins,
           (uint64_t)ctx->fcfg.blocks_per_cu,
+          (uint64_t)ctx->fcfg.n_phi_bins,
+          (uint64_t)ctx->fcfg.n_z_bins,
+          (uint64_t)ctx->fcfg.lanes_per_seed,
           f(ctx->det_thr)};
 }
 
@@ -499,7 +545,7 @@ int find_graph(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in,
     if (g.exec && g.key == key) hit = &g;
   if (!hit) {
     int grid = 0;  // sizes the grid (and sets the kernel's LDS limit) outside the capture
-    if (persistent_grid(ctx, ctx->g.n_layers, &grid) != KF_OK) return KF_E_HIP;
+    if (persistent_grid(ctx, ctx->g.n_layers, find_group(ctx, in->keep), &grid) != KF_OK) return KF_E_HIP;
     if (ctx->cap_stream && ctx->cap_device != dev) {
       (void)hipStreamDestroy(ctx->cap_stream);
       ctx->cap_stream = nullptr;
@@ -786,8 +832,11 @@ int kf_remove_duplicates(kf_ctx* ctx, const kf_layer_params* params, const kf_tr
 int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
                      void* ws, size_t ws_bytes, void* stream, kf_find_config* best) {
   if (!ctx) return KF_E_INVALID;
-  static const int kWide[] = {4, 8, 16, 32, 64};
-  static const int kPer[] = {0, 1};
+  static const int kTiles[][2] = {{0, 0}, {256, 32}, {128, 64}, {256, 64}, {512, 32}, {512, 64}, {256, 128}, {1024, 32}};
+  static const int kWideCoarse[] = {8, 32, 128};
+  static const int kWideFine[] = {4, 16, 64};
+  static const int kPer[] = {0, 12};
+  static const int kLanes[] = {4, 6, 8};
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -798,32 +847,45 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
   kf_find_config pick = saved;
   float best_ms = INFINITY;
   int rc = KF_OK;
-  for (int per : kPer) {
-    for (int wide : kWide) {
-      ctx->fcfg = kf_find_config{wide, per, saved.use_graph};
-      rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);  // warm-up, and validates the call
-      if (rc != KF_OK) break;
-      float ms = INFINITY;
-      for (int rep = 0; rep < 2 && rc == KF_OK; ++rep) {
-        if (hipEventRecord(e0, st) != hipSuccess) rc = KF_E_HIP;
-        if (rc == KF_OK) rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);
-        if (rc == KF_OK && hipEventRecord(e1, st) != hipSuccess) rc = KF_E_HIP;
-        if (rc == KF_OK && hipEventSynchronize(e1) != hipSuccess) rc = KF_E_HIP;
-        float t = 0.f;
-        if (rc == KF_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = KF_E_HIP;
-        if (rc == KF_OK && t < ms) ms = t;
-      }
-      if (rc != KF_OK) break;
-      if (ms < best_ms) {
-        best_ms = ms;
-        pick = ctx->fcfg;
-      }
+  // times one configuration (one untimed call, then the faster of two); configurations
+  // the context rejects (a tiling beyond the bin limit for this geometry) are skipped
+  auto trial = [&](kf_find_config cfg) {
+    if (rc != KF_OK) return;
+    if (kf_ctx_set_find_config(ctx, &cfg) != KF_OK) return;
+    rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);
+    float ms = INFINITY;
+    for (int rep = 0; rep < 2 && rc == KF_OK; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) rc = KF_E_HIP;
+      if (rc == KF_OK) rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);
+      if (rc == KF_OK && hipEventRecord(e1, st) != hipSuccess) rc = KF_E_HIP;
+      if (rc == KF_OK && hipEventSynchronize(e1) != hipSuccess) rc = KF_E_HIP;
+      float t = 0.f;
+      if (rc == KF_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = KF_E_HIP;
+      if (rc == KF_OK && t < ms) ms = t;
     }
-    if (rc != KF_OK) break;
-  }
+    if (rc == KF_OK && ms < best_ms) {
+      best_ms = ms;
+      pick = cfg;
+    }
+  };
+  for (const auto& t : kTiles)
+    for (int wide : kWideCoarse) trial(kf_find_config{wide, 0, saved.use_graph, t[0], t[1], 0});
+  const kf_find_config stage1 = pick;
+  for (int g : kLanes)
+    if (in && g >= in->keep && g != find_group(ctx, in->keep))
+      trial(kf_find_config{stage1.wide_window_bins, 0, saved.use_graph, stage1.n_phi_bins, stage1.n_z_bins, g});
+  const kf_find_config stage2 = pick;
+  for (int wide : kWideFine)
+    trial(kf_find_config{wide, 0, saved.use_graph, stage2.n_phi_bins, stage2.n_z_bins, stage2.lanes_per_seed});
+  const kf_find_config stage3 = pick;
+  for (int per : kPer)
+    if (per != stage3.blocks_per_cu) trial(kf_find_config{stage3.wide_window_bins, per, saved.use_graph,
+                                                          stage3.n_phi_bins, stage3.n_z_bins,
+                                                          stage3.lanes_per_seed});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->fcfg = rc == KF_OK ? pick : saved;
+  ctx->fcfg = rc == KF_OK && best_ms < INFINITY ? pick : saved;
+  if (rc == KF_OK && best_ms == INFINITY) rc = KF_E_INVALID;
   if (rc == KF_OK && best) *best = pick;
   return rc;
 }

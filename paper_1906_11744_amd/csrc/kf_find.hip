@@ -3,39 +3,31 @@
 //  * bin_kernel: one workgroup per (event, layer) slice; places every hit on its
 //    (aligned) layer and counting-sorts it into n_phi x n_z bins in LDS.  Binned
 //    records are (x, y, z, phi about the layer axis) plus the caller's hit index.
-//  * find_kernel: persistent workgroups pull tiles of 32 seeds from a counter.  A
-//    seed owns a group of 8 lanes; lane k holds candidate k (state and packed
-//    covariance in registers).  Per layer every live candidate predicts, scans the
-//    bins its window overlaps keeping its best `keep` hit branches in registers, the
-//    group merges all branches with min-reductions of 64-bit score keys over lane
-//    shuffles, and each surviving slot pulls its parent's predicted state by shuffle
-//    and applies its update.  Backpointers (parent slot and hit, one dword per layer
-//    and slot) live in LDS; candidates' hit lists are rebuilt from them at the end.
+//  * find_kernel: persistent one-wave workgroups pull tiles of 8 seeds from a counter.
+//    A seed owns a group of 8 lanes; lane k holds candidate k (state in registers).
+//    Per layer every live candidate predicts, parks its predicted covariance in LDS,
+//    scans the bins its window overlaps keeping its best hit branches in registers,
+//    the group merges all branches with min-reductions of 64-bit score keys over DPP
+//    lane exchanges, and each surviving slot pulls its parent's predicted state (the
+//    covariance from LDS, the rest by lane shuffles) and applies its update.
+//    Backpointers (parent slot and hit, one dword per layer and slot) go to a small
+//    per-workgroup buffer in global memory; candidates' hit lists are rebuilt from
+//    them at the end of the tile.
 #include "kf_internal.h"
 
 namespace kfi {
 
 namespace {
 
-constexpr int kGroup = 8;        // lanes per seed (>= keep)
-constexpr int kTileSeeds = 32;   // seeds per 256-lane workgroup
-constexpr int kMaxList = 8;      // hit branches kept per candidate
+constexpr int kWave = 64;     // one wave per find workgroup
+constexpr int kMaxList = 8;   // hit branches kept per candidate
+// A seed's candidates sit in a group of G consecutive lanes (G = 4, 6 or 8, >= keep);
+// a wave holds kWave / G seeds (the tile) and leaves the kWave % G lanes after them idle.
 
 // A candidate whose window overlaps more than FindArgs::wide_bins bins is scanned by
-// its whole wave: its window and the quantities its chi2 needs go to LDS, the 64
-// lanes split its hits, and their sorted lists are merged into the candidate's.
-constexpr int kWideStride = 128;  // bytes reserved per lane slot
-struct alignas(8) WideWin {
-  float phip, zp, wphi, wz;
-  int32_t blo, bhi, zlo, zhi, e;
-  float c2;
-  float x[3], xl[3];
-  float rho, rx, ry;
-  float Si00, Si11, Si12, Si22;
-  int32_t fp64;
-  double dSi11, dSi12, dSi22;
-};
-static_assert(sizeof(WideWin) <= kWideStride, "WideWin layout");
+// its whole wave: the lanes read its window and the quantities its chi2 needs from
+// the candidate's lane (readlane), split its hits, and their sorted lists are merged
+// into the candidate's.
 
 __device__ __forceinline__ int bin_index(float v, float lo, float scale, int nb) {
   const int b = (int)floorf((v - lo) * scale);
@@ -157,10 +149,30 @@ __device__ __forceinline__ void min_step(uint32_t& hi, uint32_t& lo, uint32_t oh
   hi = lt ? ohi : hi;
   lo = lt ? olo : lo;
 }
-__device__ __forceinline__ void group_min8(uint32_t& hi, uint32_t& lo) {
-  min_step(hi, lo, dpp<0xB1>(hi), dpp<0xB1>(lo));
-  min_step(hi, lo, dpp<0x4E>(hi), dpp<0x4E>(lo));
-  min_step(hi, lo, dpp<0x141>(hi), dpp<0x141>(lo));
+// The minimum over the lane's G-lane group.  G = 8: xor 1 and xor 2 inside each quad
+// (quad_perm), then the mirrored lane of the other quad of the half row
+// (row_half_mirror); G = 4: the two quad steps.  Other G (<= 8): rotations by 1, 2 and 4
+// inside the group by lane shuffles, which together cover every lane of it; the idle
+// lanes after the last group of a wave keep their own key.
+template <int G>
+__device__ __forceinline__ void group_min(uint32_t& hi, uint32_t& lo, int gbase, int slot) {
+  if constexpr (G == 8) {
+    min_step(hi, lo, dpp<0xB1>(hi), dpp<0xB1>(lo));
+    min_step(hi, lo, dpp<0x4E>(hi), dpp<0x4E>(lo));
+    min_step(hi, lo, dpp<0x141>(hi), dpp<0x141>(lo));
+  } else if constexpr (G == 4) {
+    min_step(hi, lo, dpp<0xB1>(hi), dpp<0xB1>(lo));
+    min_step(hi, lo, dpp<0x4E>(hi), dpp<0x4E>(lo));
+  } else {
+    const bool whole = gbase + G <= kWave;
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+      const int src = whole ? gbase + (slot + d) % G : gbase + slot;
+      const uint32_t ohi = (uint32_t)__shfl((int)hi, src, kWave);
+      const uint32_t olo = (uint32_t)__shfl((int)lo, src, kWave);
+      min_step(hi, lo, ohi, olo);
+    }
+  }
 }
 __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64); }
 
@@ -169,35 +181,39 @@ __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64
 // kModel: the detector model (material map, energy loss, parameterised field) in every
 // prediction, as the fit's model variant takes it; false: one x/X0 per layer and a
 // uniform field.
-template <bool kModel>
-__global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
-  // LDS: wide-window slots [256] x 128 B, stashed branch lists (chi2 [8][256],
-  // hit [8][256], count [256]), backpointers [nl][256] of every (layer, slot):
-  // ((hit + 2) << 3) | parent slot, hit >= -2.
+template <bool kModel, int G>
+__global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
+  constexpr int kTileSeeds = kWave / G;
+  // LDS: the predicted covariance of every lane, sC [21][64] (a survivor reads its
+  // parent's), and branch lists saved around wide-window scans (chi2 [8][64], hit
+  // [8][64], count [64]).
   extern __shared__ __align__(16) unsigned char lds[];
-  WideWin* const ww = reinterpret_cast<WideWin*>(lds);
-  float* const stc = reinterpret_cast<float*>(lds + 256 * kWideStride);
-  int32_t* const sti = reinterpret_cast<int32_t*>(stc + kMaxList * 256);
-  int32_t* const stn = sti + kMaxList * 256;
-  int32_t* const bp = stn + 256;
-  __shared__ int tile_sh;
-  const int tid = threadIdx.x;
-  const int slot = tid & (kGroup - 1);
-  const int grp = tid / kGroup;
-  const int lane = __lane_id();
-  const int gbase = lane & ~(kGroup - 1);
+  float* const sC = reinterpret_cast<float*>(lds);
+  float* const stc = sC + 21 * kWave;
+  int32_t* const sti = reinterpret_cast<int32_t*>(stc + kMaxList * kWave);
+  int32_t* const stn = sti + kMaxList * kWave;
+  const int lane = threadIdx.x;
+  const int slot = lane % G;
+  const int grp = lane / G;
+  const int gbase = grp * G;
   const int nl = a.nl;
   const int64_t S = a.n_seeds;
   const int nb_all = a.nphi * a.nz;
   const float kphi = a.nphi / kfd::kTwoPi;
+  // backpointers of this workgroup's tile, [nl][64]: ((hit + 2) << 3) | parent slot
+  int32_t* const bp = a.bp + (int64_t)blockIdx.x * nl * kWave;
+  auto wave_sync = []() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
   for (;;) {
-    __syncthreads();
-    if (tid == 0) tile_sh = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int64_t tile = tile_sh;
+    int claim = 0;
+    if (lane == 0) claim = atomicAdd(a.counter, 1);
+    const int64_t tile = __builtin_amdgcn_readfirstlane(claim);
     if (tile >= a.n_tiles) break;
     const int64_t s = tile * kTileSeeds + grp;
-    const bool active = s < S;
+    const bool active = grp < kTileSeeds && s < S;
     // ---------------- seed and its refit over hits 0..2 ----------------
     kfd::Trk k;
     float c2 = 0.f;
@@ -280,6 +296,17 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
       int nlist = 0;
       bool predicted = false;
       bool wide = false;
+      // the prediction's window and what its chi2 needs (read by the wave for a wide
+      // window)
+      float phip = 0.f, zp = 0.f, wphi = 0.f, wz = 0.f;
+      int blo = 0, bhi = -1, zlo = 0, zhi = -1;
+      kfd::Frame f;
+      f.rho = f.rx = f.ry = 0.f;
+      f.cosa = 1.f;
+      kfd::Pred p;
+      p.Si00 = p.Si11 = p.Si12 = p.Si22 = 0.f;
+      p.fp64 = false;
+      p.dSi11 = p.dSi12 = p.dSi22 = 0.0;
       // One hit of the window (binned record and hit index): rectangle test, chi2 with
       // the candidate's S^-1, and the sorted insertion of a passing branch into (bc, bi).  Slot t keeps its entry if
       // that entry precedes the new one, takes the new one if only the entry before it
@@ -315,7 +342,6 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
             kModel ? kfd::field_kB(a.md.kB, a.fr, a.fz, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2]) : a.md.kB;
         kfd::Step stp;
         bool reach = kfd::crossing(k, ly, kB, stp);
-        kfd::Frame f;
         if (reach) {
           kfd::transport(k, stp, kB);
           f = kfd::frame_at(k, ly);
@@ -328,17 +354,19 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
         }
         if (reach) {
           predicted = true;
-          kfd::Pred p;
           kfd::prepare(k, f, a.md, p);
-          const float phip = atan2f(f.ry, f.rx), zp = k.x[2] + k.xl[2];
-          const float wphi = a.nsigma * sqrtf(p.S11) / f.rho;
-          const float wz = a.nsigma * sqrtf(p.S22);
+          phip = atan2f(f.ry, f.rx);
+          zp = k.x[2] + k.xl[2];
+          wphi = a.nsigma * sqrtf(p.S11) / f.rho;
+          wz = a.nsigma * sqrtf(p.S22);
           const float Z = a.zhalf[l];
           const float kz = a.nz / (2.f * Z);
           const float zq = fmaf(wz, 1e-4f, wz) + 1e-6f;
-          const int zlo = bin_index(zp - zq, -Z, kz, a.nz), zhi = bin_index(zp + zq, -Z, kz, a.nz);
+          zlo = bin_index(zp - zq, -Z, kz, a.nz);
+          zhi = bin_index(zp + zq, -Z, kz, a.nz);
           const float wq = fmaf(wphi, 1e-4f, wphi) + 1e-6f;
-          int blo = 0, bhi = a.nphi - 1;
+          blo = 0;
+          bhi = a.nphi - 1;
           if (wq < kfd::kPi) {
             blo = (int)floorf((phip - wq + kfd::kPi) * kphi);
             bhi = (int)floorf((phip + wq + kfd::kPi) * kphi);
@@ -347,55 +375,29 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
               bhi = a.nphi - 1;
             }
           }
-          if ((bhi - blo + 1) * (zhi - zlo + 1) > a.wide_bins) {
-            wide = true;
-            WideWin w;
-            w.phip = phip;
-            w.zp = zp;
-            w.wphi = wphi;
-            w.wz = wz;
-            w.blo = blo;
-            w.bhi = bhi;
-            w.zlo = zlo;
-            w.zhi = zhi;
-            w.e = e;
-            w.c2 = c2;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              w.x[q] = k.x[q];
-              w.xl[q] = k.xl[q];
-            }
-            w.rho = f.rho;
-            w.rx = f.rx;
-            w.ry = f.ry;
-            w.Si00 = p.Si00;
-            w.Si11 = p.Si11;
-            w.Si12 = p.Si12;
-            w.Si22 = p.Si22;
-            w.fp64 = p.fp64 ? 1 : 0;
-            w.dSi11 = p.dSi11;
-            w.dSi12 = p.dSi12;
-            w.dSi22 = p.dSi22;
-            ww[tid] = w;
-          } else {
-            const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
-            for (int b = blo; b <= bhi; ++b) {
-              const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
-              const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
-              // two records in flight per iteration
-              int q = q0;
-              for (; q + 1 < q1; q += 2) {
-                const float4 r0 = a.brec[q], r1 = a.brec[q + 1];
-                const int h0 = a.bidx[q], h1 = a.bidx[q + 1];
-                consider(r0, h0, k, f, p, phip, zp, wphi, wz, c2);
-                consider(r1, h1, k, f, p, phip, zp, wphi, wz, c2);
-              }
-              if (q < q1) consider(a.brec[q], a.bidx[q], k, f, p, phip, zp, wphi, wz, c2);
-            }
-          }
+          wide = (bhi - blo + 1) * (zhi - zlo + 1) > a.wide_bins;
         } else {
           mode = TERM;
           st |= kfd::ST_PROP_FAIL;
+        }
+      }
+      // every lane parks its (predicted, or carried) covariance for its children
+#pragma unroll
+      for (int q = 0; q < 21; ++q) sC[q * kWave + lane] = k.C[q];
+      if (predicted && !wide) {
+        const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
+        for (int b = blo; b <= bhi; ++b) {
+          const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
+          const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
+          // two records in flight per iteration
+          int q = q0;
+          for (; q + 1 < q1; q += 2) {
+            const float4 r0 = a.brec[q], r1 = a.brec[q + 1];
+            const int h0 = a.bidx[q], h1 = a.bidx[q + 1];
+            consider(r0, h0, k, f, p, phip, zp, wphi, wz, c2);
+            consider(r1, h1, k, f, p, phip, zp, wphi, wz, c2);
+          }
+          if (q < q1) consider(a.brec[q], a.bidx[q], k, f, p, phip, zp, wphi, wz, c2);
         }
       }
       // ---- wide windows: each is scanned by the whole wave ----
@@ -403,50 +405,56 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
       if (wide_m != 0ull) {
 #pragma unroll
         for (int t = 0; t < kMaxList; ++t) {
-          stc[t * 256 + tid] = bc[t];
-          sti[t * 256 + tid] = bi[t];
+          stc[t * kWave + lane] = bc[t];
+          sti[t * kWave + lane] = bi[t];
         }
-        stn[tid] = nlist;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int wbase = tid & ~63;
+        stn[lane] = nlist;
+        wave_sync();
         while (wide_m != 0ull) {
           const int c = __ffsll((unsigned long long)wide_m) - 1;
           wide_m &= wide_m - 1ull;
-          const WideWin w = ww[wbase + c];
+          auto rdf = [c](float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c)); };
+          auto rdi = [c](int v) { return __builtin_amdgcn_readlane(v, c); };
+          auto rdd = [c](double v) {
+            const uint64_t u = __double_as_longlong(v);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, c);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), c);
+            return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+          };
           kfd::Trk kc;
-          kfd::Frame fc;
-          kfd::Pred pc;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            kc.x[q] = w.x[q];
-            kc.xl[q] = w.xl[q];
+            kc.x[q] = rdf(k.x[q]);
+            kc.xl[q] = rdf(k.xl[q]);
           }
-          fc.rho = w.rho;
-          fc.rx = w.rx;
-          fc.ry = w.ry;
+          kfd::Frame fc;
+          fc.rho = rdf(f.rho);
+          fc.rx = rdf(f.rx);
+          fc.ry = rdf(f.ry);
           fc.cosa = 1.f;
-          pc.Si00 = w.Si00;
-          pc.Si11 = w.Si11;
-          pc.Si12 = w.Si12;
-          pc.Si22 = w.Si22;
-          pc.fp64 = w.fp64 != 0;
-          pc.dSi11 = w.dSi11;
-          pc.dSi12 = w.dSi12;
-          pc.dSi22 = w.dSi22;
+          kfd::Pred pc;
+          pc.Si00 = rdf(p.Si00);
+          pc.Si11 = rdf(p.Si11);
+          pc.Si12 = rdf(p.Si12);
+          pc.Si22 = rdf(p.Si22);
+          pc.fp64 = rdi(p.fp64 ? 1 : 0) != 0;
+          pc.dSi11 = rdd(p.dSi11);
+          pc.dSi12 = rdd(p.dSi12);
+          pc.dSi22 = rdd(p.dSi22);
+          const float wphip = rdf(phip), wzp = rdf(zp), wwphi = rdf(wphi), wwz = rdf(wz), wc2 = rdf(c2);
+          const int wblo = rdi(blo), wbhi = rdi(bhi), wzlo = rdi(zlo), wzhi = rdi(zhi), we = rdi(e);
 #pragma unroll
           for (int t = 0; t < kMaxList; ++t) {
             bc[t] = INFINITY;
             bi[t] = 0x7fffffff;
           }
           nlist = 0;
-          const int32_t* boff = a.boff + ((int64_t)w.e * nl + l) * (nb_all + 1);
-          for (int b = w.blo; b <= w.bhi; ++b) {
+          const int32_t* boff = a.boff + ((int64_t)we * nl + l) * (nb_all + 1);
+          for (int b = wblo; b <= wbhi; ++b) {
             const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
-            const int q0 = boff[pb * a.nz + w.zlo], q1 = boff[pb * a.nz + w.zhi + 1];
-            for (int q = q0 + lane; q < q1; q += 64)
-              consider(a.brec[q], a.bidx[q], kc, fc, pc, w.phip, w.zp, w.wphi, w.wz, w.c2);
+            const int q0 = boff[pb * a.nz + wzlo], q1 = boff[pb * a.nz + wzhi + 1];
+            for (int q = q0 + lane; q < q1; q += kWave)
+              consider(a.brec[q], a.bidx[q], kc, fc, pc, wphip, wzp, wwphi, wwz, wc2);
           }
           // the candidate's list: kMaxList rounds of a 64-lane min over (chi2, hit) keys
           int hd = 0, cnt = 0;
@@ -473,48 +481,44 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
             if (key == ~0ull) break;
             if (mine == key) ++hd;
             if (lane == c) {
-              stc[r * 256 + tid] = __uint_as_float((uint32_t)(key >> 32));
-              sti[r * 256 + tid] = (int32_t)(uint32_t)(key & 0xffffffffull);
+              stc[r * kWave + lane] = __uint_as_float((uint32_t)(key >> 32));
+              sti[r * kWave + lane] = (int32_t)(uint32_t)(key & 0xffffffffull);
             }
             ++cnt;
           }
-          if (lane == c) stn[tid] = cnt;
+          if (lane == c) stn[lane] = cnt;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
 #pragma unroll
         for (int t = 0; t < kMaxList; ++t) {
-          bc[t] = stc[t * 256 + tid];
-          bi[t] = sti[t * 256 + tid];
+          bc[t] = stc[t * kWave + lane];
+          bi[t] = sti[t * kWave + lane];
         }
-        nlist = stn[tid];
+        nlist = stn[lane];
       }
       // ---- merge the group's branches: `keep` rounds of an 8-lane minimum ----
       // Each lane offers its best remaining branch as a 64-bit key: more hits, smaller
       // total chi2, lower parent slot, with the branch kind in the two lowest bits (a
       // lane offers one branch per round, so the kind never decides).  The minimum over
       // the 8 lanes of a seed takes three DPP exchanges.  The key names the winner's
-      // slot, kind and total chi2; a winning hit's index is read afterwards from an LDS
-      // copy of the winner's sorted list, at the count of its earlier hit wins.  The
-      // list is never shifted: its head is an index resolved by a chain of selects.
-#pragma unroll
-      for (int t = 0; t < kMaxList; ++t) sti[t * 256 + tid] = bi[t];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // slot, kind and total chi2; the slot that the round fills takes the winner's hit
+      // index by one lane shuffle.  The list is never shifted: its head is an index
+      // resolved by a chain of selects.
       bool other_used = false;   // the miss (live) or carry (terminated) branch was taken
       int head = 0;
-      uint32_t wins = 0u;        // hit wins of every slot so far, 4 bits per slot
-      int my_par = slot, my_kind = K_NONE, my_entry = 0;
+      int my_par = slot, my_kind = K_NONE, my_hit = -2;
       float my_c = 0.f;
       int new_n = 0;
       for (int r = 0; r < a.keep; ++r) {
         int hk = K_NONE, hn = 0;
         float hc = bc[0];
+        int hx = bi[0];
 #pragma unroll
         for (int t = 1; t < kMaxList; ++t)
-          if (head == t) hc = bc[t];
+          if (head == t) {
+            hc = bc[t];
+            hx = bi[t];
+          }
         if (head < nlist) {
           hk = K_HIT;
           hn = nh + 1;
@@ -530,33 +534,32 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
         const bool has = hk != K_NONE;
         uint32_t khi = has ? ((uint32_t)(255 - hn) << 8) | (__float_as_uint(hc) >> 24) : 0xffffffffu;
         uint32_t klo = has ? (__float_as_uint(hc) << 8) | ((uint32_t)slot << 2) | (uint32_t)hk : 0xffffffffu;
-        group_min8(khi, klo);
+        group_min<G>(khi, klo, gbase, slot);
         if (khi == 0xffffffffu && klo == 0xffffffffu) break;
         const int w = (int)((klo >> 2) & 7u);
         const int wk = (int)(klo & 3u);
+        const int whit = shfl_i(hx, gbase + w);
         if (slot == r) {
           my_par = w;
           my_kind = wk;
           my_c = __uint_as_float((khi << 24) | (klo >> 8));
-          my_entry = (int)((wins >> (4 * w)) & 15u);
+          my_hit = whit;
         }
-        if (wk == K_HIT) wins += 1u << (4 * w);
         if (slot == w) {
           if (hk == K_HIT) ++head;
           else other_used = true;
         }
         ++new_n;
       }
-      int my_hit = -2;
-      if (my_kind == K_HIT) my_hit = sti[my_entry * 256 + (tid & ~(kGroup - 1)) + my_par];
       // ---- every surviving slot takes its parent's (predicted) candidate ----
       const int src = gbase + my_par;
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < 21; ++q) k.C[q] = sC[q * kWave + src];
 #pragma unroll
       for (int q = 0; q < 6; ++q) k.x[q] = shfl_f(k.x[q], src);
 #pragma unroll
       for (int q = 0; q < 2; ++q) k.xl[q] = shfl_f(k.xl[q], src);  // xl[2] is always 0
-#pragma unroll
-      for (int q = 0; q < 21; ++q) k.C[q] = shfl_f(k.C[q], src);
       k.cp = shfl_f(k.cp, src);
       k.sp = shfl_f(k.sp, src);
       k.ct = shfl_f(k.ct, src);
@@ -566,18 +569,19 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
       nm = shfl_i(nm, src);
       mode = shfl_i(mode, src);
       st = (uint32_t)shfl_i((int)st, src);
+      wave_sync();  // every lane has read sC before the next layer overwrites it
       if (active) {
         if (slot < new_n) {
           if (my_kind == K_HIT) {
-            const kfd::Frame f = kfd::frame_at(k, ly);
-            if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
-            kfd::Pred p;
-            kfd::prepare(k, f, a.md, p);
-            if (p.fp64) st |= kfd::ST_FP64;
+            const kfd::Frame fu = kfd::frame_at(k, ly);
+            if (fabsf(fu.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
+            kfd::Pred pu;
+            kfd::prepare(k, fu, a.md, pu);
+            if (pu.fp64) st |= kfd::ST_FP64;
             float mx, my, mz;
             kfd::place(ly, a.hits[my_hit], a.hits[a.H + my_hit], a.hits[2 * a.H + my_hit], mx, my, mz);
-            const kfd::Resid r = kfd::residual(k, f, ly, p, mx, my, mz);
-            kfd::apply_update(k, p, a.md, r.r1, r.r2);
+            const kfd::Resid r = kfd::residual(k, fu, ly, pu, mx, my, mz);
+            kfd::apply_update(k, pu, a.md, r.r1, r.r2);
             c2 = my_c;
             nh += 1;
           } else if (my_kind == K_MISS) {
@@ -590,33 +594,41 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
           } else {
             my_hit = -2;
           }
-          bp[l * 256 + tid] = ((my_hit + 2) << 3) | my_par;
+          bp[l * kWave + lane] = ((my_hit + 2) << 3) | my_par;
         } else {
           mode = EMPTY;
         }
       }
       ncand = new_n;
     }
-    __syncthreads();
+    // the tile's backpointers, written by the lanes of this wave, are read back below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     // ---------------- outputs ----------------
+    // The output rows' strides are rebuilt here from an opaque copy of the seed count,
+    // so that the compiler does not keep ~30 precomputed row addresses live through the
+    // whole tile loop.
+    int64_t So = S;
+    asm volatile("" : "+s"(So));
     if (active) {
       const int keep = a.keep;
       if (slot < keep) {
         const bool have = slot < ncand;
-        auto at = [&](int kk, int64_t inner) { return ((int64_t)kk * inner) * S + s; };
+        auto at = [&](int kk, int64_t inner) { return ((int64_t)kk * inner) * So + s; };
         int cur = slot;
         for (int l = nl - 1; l >= 0; --l) {
           int h = -2;
           if (have) {
             if (l >= 3) {
-              const int v = bp[l * 256 + grp * kGroup + cur];
+              const int v = bp[l * kWave + gbase + cur];
               h = (v >> 3) - 2;
-              cur = v & (kGroup - 1);
+              cur = v & 7;
             } else {
               h = sh[l];
             }
           }
-          a.hit_idx[((int64_t)slot * nl + l) * S + s] = h;
+          a.hit_idx[((int64_t)slot * nl + l) * So + s] = h;
         }
         a.n_hits[at(slot, 1)] = have ? nh : 0;
         a.n_miss[at(slot, 1)] = have ? nm : 0;
@@ -624,17 +636,26 @@ __global__ __launch_bounds__(256, 2) void find_kernel(FindArgs a) {
         a.status[at(slot, 1)] = have ? st : 0u;
 #pragma unroll
         for (int q = 0; q < 6; ++q)
-          a.state[((int64_t)slot * 6 + q) * S + s] =
+          a.state[((int64_t)slot * 6 + q) * So + s] =
               have ? (q < 3 ? k.x[q] + k.xl[q] : (q == 4 ? kfd::wrap_pi(k.x[q]) : k.x[q])) : 0.f;
 #pragma unroll
-        for (int q = 0; q < 21; ++q) a.cov[((int64_t)slot * 21 + q) * S + s] = have ? k.C[q] : 0.f;
+        for (int q = 0; q < 21; ++q) a.cov[((int64_t)slot * 21 + q) * So + s] = have ? k.C[q] : 0.f;
       }
       if (slot == 0) {
         a.n_cand[s] = ncand;
         if (bad) a.status[s] = kfd::ST_BAD_INPUT;
       }
     }
+    // the next tile overwrites the backpointers only after every lane has read them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
+}
+
+hipError_t prepare_bin(int nbins) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (nbins + 1) * (int)sizeof(int));
 }
 
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream) {
@@ -643,29 +664,47 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+int find_tile_seeds(int lanes_per_seed) { return kWave / lanes_per_seed; }
+
 size_t find_lds_bytes(int nl) {
-  return (size_t)256 * kWideStride + (size_t)(2 * kMaxList + 1) * 256 * 4 + (size_t)nl * 256 * sizeof(int32_t);
+  (void)nl;
+  return (size_t)(21 + 2 * kMaxList + 1) * kWave * 4;
+}
+
+size_t find_bp_bytes(int nl, int64_t grid) { return (size_t)grid * nl * kWave * sizeof(int32_t); }
+
+namespace {
+
+template <bool kModel, int G>
+hipError_t max_blocks(int nl, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel<kModel, G>, kWave,
+                                                      find_lds_bytes(nl));
 }
 
 template <bool kModel>
-hipError_t find_max_blocks_variant(int nl, int* blocks_per_cu) {
-  // more than 64 KiB of dynamic LDS per workgroup (gfx950 has 160 KiB per CU)
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(find_kernel<kModel>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)find_lds_bytes(nl));
-  if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel<kModel>, 256, find_lds_bytes(nl));
-}
-
-hipError_t find_max_blocks(int nl, bool model, int* blocks_per_cu) {
-  return model ? find_max_blocks_variant<true>(nl, blocks_per_cu) : find_max_blocks_variant<false>(nl, blocks_per_cu);
-}
-
-hipError_t launch_find(const FindArgs& a, int grid, hipStream_t stream) {
-  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
-    hipLaunchKernelGGL(find_kernel<true>, dim3((unsigned)grid), dim3(256), find_lds_bytes(a.nl), stream, a);
-  else
-    hipLaunchKernelGGL(find_kernel<false>, dim3((unsigned)grid), dim3(256), find_lds_bytes(a.nl), stream, a);
+hipError_t launch_group(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream) {
+  const dim3 g((unsigned)grid), b(kWave);
+  const size_t lds = find_lds_bytes(a.nl);
+  if (lanes_per_seed == 4) hipLaunchKernelGGL((find_kernel<kModel, 4>), g, b, lds, stream, a);
+  else if (lanes_per_seed == 6) hipLaunchKernelGGL((find_kernel<kModel, 6>), g, b, lds, stream, a);
+  else hipLaunchKernelGGL((find_kernel<kModel, 8>), g, b, lds, stream, a);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t find_max_blocks(int nl, bool model, int lanes_per_seed, int* blocks_per_cu) {
+  switch (lanes_per_seed) {
+    case 4: return model ? max_blocks<true, 4>(nl, blocks_per_cu) : max_blocks<false, 4>(nl, blocks_per_cu);
+    case 6: return model ? max_blocks<true, 6>(nl, blocks_per_cu) : max_blocks<false, 6>(nl, blocks_per_cu);
+    default: return model ? max_blocks<true, 8>(nl, blocks_per_cu) : max_blocks<false, 8>(nl, blocks_per_cu);
+  }
+}
+
+hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream) {
+  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
+    return launch_group<true>(a, lanes_per_seed, grid, stream);
+  return launch_group<false>(a, lanes_per_seed, grid, stream);
 }
 
 }  // namespace kfi

@@ -75,6 +75,7 @@ struct FindArgs {
   float eloss = 0.f;
   float fr = 0.f, fz = 0.f;
   int32_t* counter;
+  int32_t* bp;       // [grid][nl][64] backpointers of each workgroup's current tile
   int32_t* n_cand;
   int32_t* hit_idx;
   int32_t* n_hits;
@@ -172,10 +173,15 @@ hipError_t launch_dedup(const DedupArgs& a, bool seeds, hipStream_t stream);
 hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
                          hipEvent_t ev_stop = nullptr);
 hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
+hipError_t prepare_bin(int nbins);  // allows the bin kernel's LDS for nbins bins
 size_t find_lds_bytes(int nl);
-// model: the finder variant with the detector model (material map, energy loss, field)
-hipError_t find_max_blocks(int nl, bool model, int* blocks_per_cu);
-hipError_t launch_find(const FindArgs& a, int grid, hipStream_t stream);
+int find_tile_seeds(int lanes_per_seed);        // seeds per find tile (one workgroup)
+constexpr int kMaxFindGrid = 4096;              // persistent find workgroups at most
+size_t find_bp_bytes(int nl, int64_t grid);     // backpointer buffer of `grid` workgroups
+// model: the finder variant with the detector model (material map, energy loss, field);
+// lanes_per_seed: 4, 6 or 8 lanes hold one seed's candidates
+hipError_t find_max_blocks(int nl, bool model, int lanes_per_seed, int* blocks_per_cu);
+hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream);
 
 // Writes the per-layer constants (radius, alignment, its cos/sin, material; with
 // zhalf_host and map_nz > 0 also the placement of the material map's z bins).

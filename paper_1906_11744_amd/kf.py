@@ -156,7 +156,11 @@ class SmoothOut(C.Structure):
 
 
 class FindConfig(C.Structure):
-    _fields_ = [("wide_window_bins", C.c_int32), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32)]
+    _fields_ = [("wide_window_bins", C.c_int32), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
+                ("n_phi_bins", C.c_int32), ("n_z_bins", C.c_int32), ("lanes_per_seed", C.c_int32)]
+
+
+FIND_CONFIG_KEYS = ("wide_window_bins", "blocks_per_cu", "use_graph", "n_phi_bins", "n_z_bins", "lanes_per_seed")
 
 
 class Context:
@@ -228,22 +232,22 @@ class Context:
         uniform field."""
         _check(_lib().kf_ctx_set_field(self._h, C.c_float(float(c_r)), C.c_float(float(c_z))), "kf_ctx_set_field")
 
-    def set_find_config(self, wide_window_bins=None, blocks_per_cu=None, use_graph=None):
-        """kf_ctx_set_find_config; fields left None keep their current value."""
+    def set_find_config(self, **kw):
+        """kf_ctx_set_find_config; keys of FIND_CONFIG_KEYS (wide_window_bins,
+        blocks_per_cu, use_graph, n_phi_bins, n_z_bins, lanes_per_seed), others keep their value."""
         cfg = self.find_config()
-        if wide_window_bins is not None:
-            cfg["wide_window_bins"] = int(wide_window_bins)
-        if blocks_per_cu is not None:
-            cfg["blocks_per_cu"] = int(blocks_per_cu)
-        if use_graph is not None:
-            cfg["use_graph"] = int(use_graph)
-        c = FindConfig(cfg["wide_window_bins"], cfg["blocks_per_cu"], cfg["use_graph"])
+        for k, v in kw.items():
+            if k not in FIND_CONFIG_KEYS:
+                raise TypeError(f"unknown find configuration field {k}")
+            if v is not None:
+                cfg[k] = int(v)
+        c = FindConfig(*[cfg[k] for k in FIND_CONFIG_KEYS])
         _check(_lib().kf_ctx_set_find_config(self._h, C.byref(c)), "kf_ctx_set_find_config")
 
     def find_config(self):
         c = FindConfig()
         _check(_lib().kf_ctx_get_find_config(self._h, C.byref(c)), "kf_ctx_get_find_config")
-        return {"wide_window_bins": c.wide_window_bins, "blocks_per_cu": c.blocks_per_cu, "use_graph": c.use_graph}
+        return {k: int(getattr(c, k)) for k in FIND_CONFIG_KEYS}
 
     def workspace(self, op, inp, device):
         nb = C.c_size_t(0)

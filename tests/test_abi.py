@@ -84,16 +84,32 @@ def test_host_side_errors_before_launch():
 def test_find_config_roundtrip_and_validation():
     kf, lib = _lib()
     ctx = kf.Context(synth.workload_geometry(3))
-    assert ctx.find_config() == {"wide_window_bins": 16, "blocks_per_cu": 0, "use_graph": 0}
-    ctx.set_find_config(wide_window_bins=0, blocks_per_cu=1, use_graph=1)
-    assert ctx.find_config() == {"wide_window_bins": 0, "blocks_per_cu": 1, "use_graph": 1}
+    base = {"wide_window_bins": 16, "blocks_per_cu": 0, "use_graph": 0, "n_phi_bins": 0, "n_z_bins": 0,
+            "lanes_per_seed": 0}
+    assert ctx.find_config() == base
+    ctx.set_find_config(wide_window_bins=0, blocks_per_cu=1, use_graph=1, n_phi_bins=512, n_z_bins=64,
+                        lanes_per_seed=6)
+    want = {"wide_window_bins": 0, "blocks_per_cu": 1, "use_graph": 1, "n_phi_bins": 512, "n_z_bins": 64,
+            "lanes_per_seed": 6}
+    assert ctx.find_config() == want
     with pytest.raises(kf.KfError):
         ctx.set_find_config(wide_window_bins=-1)
     with pytest.raises(kf.KfError):
         ctx.set_find_config(blocks_per_cu=-2)
     with pytest.raises(kf.KfError):
         ctx.set_find_config(use_graph=2)
-    assert ctx.find_config() == {"wide_window_bins": 0, "blocks_per_cu": 1, "use_graph": 1}
+    with pytest.raises(kf.KfError):        # 1024 x 64 bins: beyond KF_MAX_FIND_BINS
+        ctx.set_find_config(n_phi_bins=1024)
+    with pytest.raises(kf.KfError):
+        ctx.set_find_config(n_z_bins=257)
+    with pytest.raises(kf.KfError):        # 512 x 128 bins
+        ctx.set_find_config(n_phi_bins=512, n_z_bins=128)
+    for bad in (5, 7, 16, -1):
+        with pytest.raises(kf.KfError):
+            ctx.set_find_config(lanes_per_seed=bad)
+    assert ctx.find_config() == want
+    ctx.set_find_config(n_phi_bins=1024, n_z_bins=32)   # 32 768 bins: the limit
+    assert ctx.find_config()["n_phi_bins"] == 1024
 
 
 def test_launch_event_hook_validation():

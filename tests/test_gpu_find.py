@@ -245,8 +245,9 @@ def test_find_empty_and_invalid():
 
 
 def test_find_independent_of_launch_configuration():
-    """Wave-wide scans of wide windows, the persistent grid size and the autotuner's
-    choice change the time only: every output bit is the same."""
+    """Wave-wide scans of wide windows, the persistent grid size, the bin tiling the
+    search walks and the autotuner's choice change the time only: every output bit is
+    the same."""
     need_gpu()
     from paper_1906_11744_amd import Context
     geom, ev = synth.find_workload(3, n_tracks=3000)
@@ -254,15 +255,19 @@ def test_find_independent_of_launch_configuration():
     args = (to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event))
     xX0 = to_dev(geom.xX0.astype(np.float32))
     ref = None
-    for wide, per in [(1 << 30, 0), (16, 0), (0, 0), (4, 1), (0, 1)]:
-        ctx.set_find_config(wide_window_bins=wide, blocks_per_cu=per)
+    for wide, per, nphi, nz, g in [(1 << 30, 0, 0, 0, 8), (16, 0, 0, 0, 0), (0, 0, 0, 0, 6), (4, 1, 0, 0, 8),
+                                   (0, 1, 0, 0, 0), (16, 0, 256, 32, 8), (32, 0, 512, 64, 6),
+                                   (8, 12, 1024, 32, 0), (128, 0, 256, 128, 8), (1 << 30, 0, 1, 1, 0),
+                                   (16, 0, 7, 3, 6)]:
+        ctx.set_find_config(wide_window_bins=wide, blocks_per_cu=per, n_phi_bins=nphi, n_z_bins=nz, lanes_per_seed=g)
         out = ctx.find(*args, xX0=xX0, refit=True)
         torch.cuda.synchronize()
         got = {k: v.cpu().numpy() for k, v in out.items()}
         if ref is None:
             ref = got
         for k in ref:
-            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{k} wide={wide} per={per}")
+            np.testing.assert_array_equal(got[k], ref[k],
+                                          err_msg=f"{k} wide={wide} per={per} bins={nphi}x{nz} lanes={g}")
     out = ctx.find(*args, xX0=xX0, refit=True, autotune=True)
     torch.cuda.synchronize()
     print("autotuned:", ctx.find_config())
