@@ -296,8 +296,9 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
             void* ws, size_t ws_bytes, void* stream);
 
 /* Autotuner of kf_find's configuration for inputs like `in`: runs kf_find (arguments
- * as for kf_find; `out` receives the usual results) under candidate configurations,
- * times two calls of each with HIP events on `stream` (after one untimed call), keeps
+ * as for kf_find; `out` receives the usual results) under candidate configurations:
+ * after running the call until 100 ms of it have elapsed (the GPU's clock settles), it
+ * times three calls of each with HIP events on `stream` (after one untimed call), keeps
  * the fastest in the context and copies it to *best (if not NULL).  The candidates:
  * the bin tiling (the geometry's, and phi x z = 256 x 32, 128 x 64, 256 x 64, 512 x 32,
  * 512 x 64, 256 x 128, 1024 x 32) crossed with wide_window_bins 8, 32, 128 (lanes per

@@ -84,7 +84,7 @@ size_t backward_ws_bytes(const kf_ctx* ctx, int64_t n) {
 // | bin offsets [E][L][nbins + 1] | tile counter | backpointers of the persistent
 // workgroups' current tiles.
 struct FindWs {
-  size_t layers, brec, bidx, boff, counter, bp, total;
+  size_t layers, brec, bidx, boff, counter, bp, bpos, rpos, rmask, total;
 };
 
 int64_t find_tiles(const kf_find_in* in, int lanes_per_seed) {
@@ -126,7 +126,15 @@ FindWs find_ws(const kf_ctx* c, const kf_find_in* in) {
   w.boff = w.bidx + round_up(H * 4);
   w.counter = w.boff + round_up(E * c->g.n_layers * nb * 4);
   w.bp = w.counter + kAlign;
-  w.total = w.bp + round_up(kfi::find_bp_bytes(c->g.n_layers, find_grid_cap(in)));
+  // with a refit: placed hits of the workgroups' tiles, of every seed's rank-0
+  // candidate, and that candidate's layers
+  const size_t S = (size_t)(in->n_seeds > 0 ? in->n_seeds : 0);
+  const size_t L = (size_t)c->g.n_layers;
+  const size_t grid = (size_t)find_grid_cap(in);
+  w.bpos = w.bp + round_up(kfi::find_bp_bytes(c->g.n_layers, find_grid_cap(in)));
+  w.rpos = w.bpos + (in->refit ? round_up(grid * L * 3 * 64 * sizeof(float)) : 0);
+  w.rmask = w.rpos + (in->refit ? round_up(L * 3 * S * sizeof(float)) : 0);
+  w.total = w.rmask + (in->refit ? round_up(S * sizeof(uint32_t)) : 0);
   return w;
 }
 
@@ -425,6 +433,11 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   f.H = in->n_hits;
   f.n_tiles = find_tiles(in, group);
   f.bp = reinterpret_cast<int32_t*>(base + w.bp);
+  if (in->refit) {
+    f.bpos = reinterpret_cast<float*>(base + w.bpos);
+    f.rpos = reinterpret_cast<float*>(base + w.rpos);
+    f.rmask = reinterpret_cast<uint32_t*>(base + w.rmask);
+  }
   f.hits = in->hits;
   f.seed_event = in->seed_event;
   f.seed_hits = in->seed_hits;
@@ -474,7 +487,7 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
     a.eloss = ctx->eloss;
     a.fr = ctx->fr;
     a.fz = ctx->fz;
-    if (kfi::launch_refit(a, in->hits, in->n_hits, out->hit_idx, st) != hipSuccess) return KF_E_HIP;
+    if (kfi::launch_refit(a, f.rpos, f.rmask, st) != hipSuccess) return KF_E_HIP;
   }
   return KF_OK;
 }
@@ -847,14 +860,29 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
   kf_find_config pick = saved;
   float best_ms = INFINITY;
   int rc = KF_OK;
-  // times one configuration (one untimed call, then the faster of two); configurations
+  // the GPU's clock drops when it idles and takes tens of milliseconds of work to
+  // return: the first configurations would be timed on a slow clock.  Run the call until
+  // 100 ms of it have elapsed (at least 4 calls, at most 200) before timing anything.
+  {
+    float total = 0.f;
+    for (int rep = 0; rep < 200 && rc == KF_OK && (rep < 4 || total < 100.f); ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) rc = KF_E_HIP;
+      if (rc == KF_OK) rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);
+      if (rc == KF_OK && hipEventRecord(e1, st) != hipSuccess) rc = KF_E_HIP;
+      if (rc == KF_OK && hipEventSynchronize(e1) != hipSuccess) rc = KF_E_HIP;
+      float t = 0.f;
+      if (rc == KF_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = KF_E_HIP;
+      total += t;
+    }
+  }
+  // times one configuration (one untimed call, then the fastest of three); configurations
   // the context rejects (a tiling beyond the bin limit for this geometry) are skipped
   auto trial = [&](kf_find_config cfg) {
     if (rc != KF_OK) return;
     if (kf_ctx_set_find_config(ctx, &cfg) != KF_OK) return;
     rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);
     float ms = INFINITY;
-    for (int rep = 0; rep < 2 && rc == KF_OK; ++rep) {
+    for (int rep = 0; rep < 3 && rc == KF_OK; ++rep) {
       if (hipEventRecord(e0, st) != hipSuccess) rc = KF_E_HIP;
       if (rc == KF_OK) rc = kf_find(ctx, params, in, out, ws, ws_bytes, stream);
       if (rc == KF_OK && hipEventRecord(e1, st) != hipSuccess) rc = KF_E_HIP;

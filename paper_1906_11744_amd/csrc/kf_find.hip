@@ -184,6 +184,9 @@ __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64
 template <bool kModel, int G>
 __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
   constexpr int kTileSeeds = kWave / G;
+  // at most G branches of one parent can survive (keep <= G), so a candidate keeps its
+  // best G hit branches
+  constexpr int kList = G;
   // LDS: the predicted covariance of every lane, sC [21][64] (a survivor reads its
   // parent's), and branch lists saved around wide-window scans (chi2 [8][64], hit
   // [8][64], count [64]).
@@ -200,8 +203,10 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
   const int64_t S = a.n_seeds;
   const int nb_all = a.nphi * a.nz;
   const float kphi = a.nphi / kfd::kTwoPi;
-  // backpointers of this workgroup's tile, [nl][64]: ((hit + 2) << 3) | parent slot
+  // backpointers of this workgroup's tile, [nl][64]: ((hit + 2) << 3) | parent slot;
+  // with a refit, the placed hit of each (layer, lane) that took one, [nl][3][64]
   int32_t* const bp = a.bp + (int64_t)blockIdx.x * nl * kWave;
+  float* const bpos = a.bpos ? a.bpos + (int64_t)blockIdx.x * nl * 3 * kWave : nullptr;
   auto wave_sync = []() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -240,6 +245,12 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       for (int q = 0; q < 3; ++q)
         kfd::place(a.layers[q], a.hits[sh[q]], a.hits[a.H + sh[q]], a.hits[2 * a.H + sh[q]], m[q][0], m[q][1],
                    m[q][2]);
+      if (bpos) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) bpos[(q * 3 + c) * kWave + lane] = m[q][c];
+      }
       kfd::Model md0 = a.md;
       if (kModel) md0.kB = kfd::field_kB(a.md.kB, a.fr, a.fz, m[0][0], m[0][1], m[0][2]);  // kappa at hit 0
       kfd::seed_from_three(k, md0, m[0][0], m[0][1], m[0][2], m[1][0], m[1][1], m[2][0], m[2][1], m[2][2],
@@ -286,10 +297,10 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
     // ---------------- layers 3 .. L-1 ----------------
     for (int l = 3; l < nl; ++l) {
       const kfd::LayerK ly = a.layers[l];
-      float bc[kMaxList];
-      int bi[kMaxList];
+      float bc[kList];
+      int bi[kList];
 #pragma unroll
-      for (int q = 0; q < kMaxList; ++q) {
+      for (int q = 0; q < kList; ++q) {
         bc[q] = INFINITY;
         bi[q] = 0x7fffffff;
       }
@@ -325,7 +336,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         float oc = 0.f;
         int oh = 0;
 #pragma unroll
-        for (int t = 0; t < kMaxList; ++t) {
+        for (int t = 0; t < kList; ++t) {
           const bool lt = t < nlist && key_lt(bc[t], bi[t], cc, hh);
           const float ct = bc[t];
           const int ht = bi[t];
@@ -335,7 +346,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
           oc = ct;
           oh = ht;
         }
-        nlist = nlist < kMaxList ? nlist + 1 : kMaxList;
+        nlist = nlist < kList ? nlist + 1 : kList;
       };
       if (mode == LIVE) {
         const float kB =
@@ -404,7 +415,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       unsigned long long wide_m = __ballot(wide);
       if (wide_m != 0ull) {
 #pragma unroll
-        for (int t = 0; t < kMaxList; ++t) {
+        for (int t = 0; t < kList; ++t) {
           stc[t * kWave + lane] = bc[t];
           sti[t * kWave + lane] = bi[t];
         }
@@ -444,7 +455,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
           const float wphip = rdf(phip), wzp = rdf(zp), wwphi = rdf(wphi), wwz = rdf(wz), wc2 = rdf(c2);
           const int wblo = rdi(blo), wbhi = rdi(bhi), wzlo = rdi(zlo), wzhi = rdi(zhi), we = rdi(e);
 #pragma unroll
-          for (int t = 0; t < kMaxList; ++t) {
+          for (int t = 0; t < kList; ++t) {
             bc[t] = INFINITY;
             bi[t] = 0x7fffffff;
           }
@@ -456,13 +467,13 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
             for (int q = q0 + lane; q < q1; q += kWave)
               consider(a.brec[q], a.bidx[q], kc, fc, pc, wphip, wzp, wwphi, wwz, wc2);
           }
-          // the candidate's list: kMaxList rounds of a 64-lane min over (chi2, hit) keys
+          // the candidate's list: kList rounds of a 64-lane min over (chi2, hit) keys
           int hd = 0, cnt = 0;
-          for (int r = 0; r < kMaxList; ++r) {
+          for (int r = 0; r < kList; ++r) {
             float hc = bc[0];
             int hx = bi[0];
 #pragma unroll
-            for (int t = 1; t < kMaxList; ++t) {
+            for (int t = 1; t < kList; ++t) {
               if (hd == t) {
                 hc = bc[t];
                 hx = bi[t];
@@ -490,7 +501,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         }
         wave_sync();
 #pragma unroll
-        for (int t = 0; t < kMaxList; ++t) {
+        for (int t = 0; t < kList; ++t) {
           bc[t] = stc[t * kWave + lane];
           bi[t] = sti[t * kWave + lane];
         }
@@ -514,7 +525,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         float hc = bc[0];
         int hx = bi[0];
 #pragma unroll
-        for (int t = 1; t < kMaxList; ++t)
+        for (int t = 1; t < kList; ++t)
           if (head == t) {
             hc = bc[t];
             hx = bi[t];
@@ -580,6 +591,11 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
             if (pu.fp64) st |= kfd::ST_FP64;
             float mx, my, mz;
             kfd::place(ly, a.hits[my_hit], a.hits[a.H + my_hit], a.hits[2 * a.H + my_hit], mx, my, mz);
+            if (bpos) {
+              bpos[(l * 3 + 0) * kWave + lane] = mx;
+              bpos[(l * 3 + 1) * kWave + lane] = my;
+              bpos[(l * 3 + 2) * kWave + lane] = mz;
+            }
             const kfd::Resid r = kfd::residual(k, fu, ly, pu, mx, my, mz);
             kfd::apply_update(k, pu, a.md, r.r1, r.r2);
             c2 = my_c;
@@ -617,11 +633,14 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         const bool have = slot < ncand;
         auto at = [&](int kk, int64_t inner) { return ((int64_t)kk * inner) * So + s; };
         int cur = slot;
+        const bool rank0 = slot == 0 && bpos != nullptr;
+        uint32_t rmask = 0;
         for (int l = nl - 1; l >= 0; --l) {
           int h = -2;
+          int at_lane = gbase + cur;  // the lane of this candidate's ancestor on layer l
           if (have) {
             if (l >= 3) {
-              const int v = bp[l * kWave + gbase + cur];
+              const int v = bp[l * kWave + at_lane];
               h = (v >> 3) - 2;
               cur = v & 7;
             } else {
@@ -629,7 +648,13 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
             }
           }
           a.hit_idx[((int64_t)slot * nl + l) * So + s] = h;
+          if (rank0 && h >= 0) {  // the rank-0 candidate's placed hits, for the refit
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a.rpos[((int64_t)l * 3 + c) * So + s] = bpos[(l * 3 + c) * kWave + at_lane];
+            rmask |= 1u << l;
+          }
         }
+        if (rank0) a.rmask[s] = rmask;
         a.n_hits[at(slot, 1)] = have ? nh : 0;
         a.n_miss[at(slot, 1)] = have ? nm : 0;
         a.chi2[at(slot, 1)] = have ? c2 : 0.f;

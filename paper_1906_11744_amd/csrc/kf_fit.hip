@@ -56,6 +56,7 @@ __device__ __forceinline__ void store_ckpt(float* ck, int64_t n, int64_t i, int 
 
 // Hits of track i in the [L][3][n] layout, mask from the caller.
 struct SoaHits {
+  static constexpr bool kPlaced = false;
   const float* hits;
   const uint32_t* mask;
   __device__ void get(int64_t i, int64_t n, int l, float& hx, float& hy, float& hz) const {
@@ -66,16 +67,16 @@ struct SoaHits {
   }
 };
 
-// Hits of seed i's rank-0 finder candidate: global indices hit_idx[l][i] into [3][H].
-struct GatherHits {
-  const float* hits;
-  int64_t H;
-  const int32_t* idx;  // [L][n] (slot 0 of the finder's hit_idx)
+// Hits of seed i's rank-0 finder candidate, already placed on their layers by the
+// finder: pos [L][3][n].
+struct PlacedHits {
+  static constexpr bool kPlaced = true;
+  const float* pos;
   __device__ void get(int64_t i, int64_t n, int l, float& hx, float& hy, float& hz) const {
-    const int32_t j = idx[(int64_t)l * n + i];
-    hx = hits[j];
-    hy = hits[H + j];
-    hz = hits[2 * H + j];
+    const float* h = pos + (int64_t)l * 3 * n + i;
+    hx = h[0];
+    hy = h[n];
+    hz = h[2 * n];
   }
 };
 
@@ -89,9 +90,13 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
   float chi2 = 0.f;
   int nh = 0;
   auto hit = [&](int l, float& mx, float& my, float& mz) {
-    float hx, hy, hz;
-    src.get(i, n, l, hx, hy, hz);
-    kfd::place(lays[l], hx, hy, hz, mx, my, mz);
+    if constexpr (Src::kPlaced) {
+      src.get(i, n, l, mx, my, mz);
+    } else {
+      float hx, hy, hz;
+      src.get(i, n, l, hx, hy, hz);
+      kfd::place(lays[l], hx, hy, hz, mx, my, mz);
+    }
   };
   if ((mask & need) != need) {
     status = kfd::ST_BAD_INPUT;
@@ -194,25 +199,25 @@ __global__ __launch_bounds__(256, 5) void fit_kernel(FitArgs a) {
   fit_one<kCkpt, kModel>(a, lays, i, a.mask[i], src);
 }
 
-// Fit of each seed's best finder candidate from its own hits (slot 0 of hit_idx).
+// Fit of each seed's best finder candidate from its own hits, which the finder left
+// placed on their layers in pos [L][3][n] with their layers in mask [n]: one coalesced
+// 4-byte load per coordinate instead of a gather from the event's hit arrays.
 template <bool kModel>
-__global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __restrict__ hits, int64_t H,
-                                                    const int32_t* __restrict__ idx0) {
+__global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __restrict__ pos,
+                                                    const uint32_t* __restrict__ mask) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  uint32_t mask = 0;
-  for (int l = 0; l < a.nl; ++l) mask |= (idx0[(int64_t)l * a.n + i] >= 0 ? 1u : 0u) << l;
-  GatherHits src{hits, H, idx0};
-  fit_one<false, kModel>(a, a.layers, i, mask, src);
+  PlacedHits src{pos};
+  fit_one<false, kModel>(a, a.layers, i, mask[i], src);
 }
 
-hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream) {
+hipError_t launch_refit(const FitArgs& a, const float* pos, const uint32_t* mask, hipStream_t stream) {
   const int bs = 256;
   const int64_t nb = (a.n + bs - 1) / bs;
   if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
-    hipLaunchKernelGGL(refit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, a, hits, H, idx0);
+    hipLaunchKernelGGL(refit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, a, pos, mask);
   else
-    hipLaunchKernelGGL(refit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, a, hits, H, idx0);
+    hipLaunchKernelGGL(refit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, a, pos, mask);
   return hipGetLastError();
 }
 

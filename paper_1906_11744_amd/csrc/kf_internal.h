@@ -76,6 +76,12 @@ struct FindArgs {
   float fr = 0.f, fz = 0.f;
   int32_t* counter;
   int32_t* bp;       // [grid][nl][64] backpointers of each workgroup's current tile
+  // with a refit: placed hit positions [grid][nl][3][64] of each workgroup's current tile
+  // (per layer and lane, where the lane's candidate took a hit), and for every seed its
+  // rank-0 candidate's placed hits rpos [nl][3][S] and their layers rmask [S]
+  float* bpos = nullptr;
+  float* rpos = nullptr;
+  uint32_t* rmask = nullptr;
   int32_t* n_cand;
   int32_t* hit_idx;
   int32_t* n_hits;
@@ -190,7 +196,8 @@ hipError_t launch_layer_prep(int nl, const float* radius_host, const float* alig
                              int map_nz = 0);
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
                       hipEvent_t ev_stop = nullptr);
-// Fit of each seed's rank-0 finder candidate: idx0 [L][n] hit indices into hits [3][H].
-hipError_t launch_refit(const FitArgs& a, const float* hits, int64_t H, const int32_t* idx0, hipStream_t stream);
+// Fit of each seed's rank-0 finder candidate from the placed hits the finder recorded:
+// pos [L][3][n] (placed on their layers) on the layers of mask [n].
+hipError_t launch_refit(const FitArgs& a, const float* pos, const uint32_t* mask, hipStream_t stream);
 
 }  // namespace kfi
