@@ -142,9 +142,9 @@ typedef struct kf_find_in {  /* n_hits < 2^28 - 2 */
  * n_cand [S]; hit_idx [keep][L][S] global hit index, -1 missing layer, -2 not reached;
  * n_hits, n_miss [keep][S]; chi2 [keep][S]; state [keep][6][S]; cov [keep][21][S];
  * status [keep][S]; rf_* (only with refit): the fit of the rank-0 candidate's hits,
- * seeded from its first three, as kf_fit_out.  A seed whose event or hit indices are
- * out of range gets n_cand 0 and status[0][s] = KF_ST_BAD_INPUT; hit_off slices are
- * clamped to [0, n_hits]. */
+ * seeded from its first three, as kf_fit_out.  A seed whose event is out of range, or
+ * whose hit q is not in its event's slice of layer q, gets n_cand 0 and status[0][s] =
+ * KF_ST_BAD_INPUT; hit_off slices are clamped to [0, n_hits]. */
 typedef struct kf_find_out {
   int32_t* n_cand;
   int32_t* hit_idx;

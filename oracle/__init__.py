@@ -316,7 +316,10 @@ def fit_grad(geom, hits, mask, align, xX0, weight=None, field=None):
 def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, refit=False,
          align=None, xX0=None, tol_abs=0.05, tol_rel=1e-4, tol_win=5e-3, material=None, field=None):
     """FP64 combinatorial search of every seed of a synth.EventBatch; material and
-    field as for fit() (the detector model in every prediction and in the refit)."""
+    field as for fit() (the detector model in every prediction and in the refit).
+    The result's "work" counts what the search did: predictions that reached their
+    layer, hits inside a window (each given a chi2), updates of surviving hit branches,
+    and seed refits (one per seed)."""
     L = geom.n_layers
     S = ev.seed_hits.shape[1]
     H = ev.hits.shape[1]
@@ -327,7 +330,7 @@ def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, r
     o = dict(n_cand=np.zeros(S, np.int32), hit_idx=np.zeros((keep, L, S), np.int32),
              n_hits=np.zeros((keep, S), np.int32), n_miss=np.zeros((keep, S), np.int32),
              chi2=np.zeros((keep, S)), state=np.zeros((keep, 6, S)), cov=np.zeros((keep, 21, S)),
-             status=np.zeros((keep, S), np.uint32), ambig=np.zeros(S, np.uint32))
+             status=np.zeros((keep, S), np.uint32), ambig=np.zeros(S, np.uint32), work=np.zeros(4, np.int64))
     if refit:
         o.update(rf_state=np.zeros((6, S)), rf_cov=np.zeros((21, S)), rf_chi2=np.zeros(S),
                  rf_ndf=np.zeros(S, np.int32), rf_status=np.zeros(S, np.uint32))
@@ -342,7 +345,7 @@ def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, r
                        _p(o["n_cand"]), _p(o["hit_idx"]), _p(o["n_hits"]), _p(o["n_miss"]), _p(o["chi2"]),
                        _p(o["state"]), _p(o["cov"]), _p(o["status"]), _p(o["ambig"]),
                        _p(o.get("rf_state")), _p(o.get("rf_cov")), _p(o.get("rf_chi2")),
-                       _p(o.get("rf_ndf")), _p(o.get("rf_status")))
+                       _p(o.get("rf_ndf")), _p(o.get("rf_status")), _p(o["work"]))
     return o
 
 

@@ -1095,9 +1095,14 @@ double hit_chi2(const Layer<double>& ly, const double x[6], const double Si[9], 
 // candidates lies within the FP32 tolerance of its threshold: a helix grazing the
 // layer (reach margin below 1e-4), a chi2 near the cut, a hit near a window edge, or
 // the last kept and first dropped branch scores near a tie.
+// work (optional) counts what the search does for the seed: [0] predictions that reach
+// their layer, [1] hits inside a window (each gets a chi2), [2] updates of surviving
+// hit branches, [3] the seed refit (1 per seed).
 std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCfg& o, const EventView& ev,
-                            const std::vector<BinnedLayer>& bl, const int32_t sh[3], uint32_t& ambig) {
+                            const std::vector<BinnedLayer>& bl, const int32_t sh[3], uint32_t& ambig,
+                            int64_t* work = nullptr) {
   ambig = 0;
+  int64_t wk[4] = {0, 0, 0, 1};
   std::vector<Cand> cands;
   Cand c0;
   c0.hist.assign(g.nl, -2);
@@ -1134,6 +1139,7 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
         continue;
       }
       pred[k] = p;
+      ++wk[0];
       // S at the prediction: the frame and H belong to the prediction, so S is shared
       // by every hit of the window.
       Meas<double> me;
@@ -1174,6 +1180,7 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
         double c = hit_chi2(ly, p.x, Si, mh);
         if (near_edge && c < o.chi2_cut + tol(o.chi2_cut)) ambig |= 1u << L;
         if (!inside) return;
+        ++wk[1];
         if (std::fabs(c - o.chi2_cut) <= tol(o.chi2_cut)) ambig |= 1u << L;
         if (c < o.chi2_cut) br.push_back({(int)k, 0, j, cd.tk.n + 1, cd.tk.chi2 + c, c});
       };
@@ -1226,6 +1233,7 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
         double mh[3];
         place_global(ly, ev, b.hit, mh);
         if (!update_with_hit(g, ly, nc.tk, mh)) nc.term = true;
+        ++wk[2];
         nc.tk.chi2 = b.chi2tot;
         nc.hist[L] = (int32_t)b.hit;
       }
@@ -1233,6 +1241,8 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
     }
     cands.swap(next);
   }
+  if (work)
+    for (int q = 0; q < 4; ++q) work[q] += wk[q];
   return cands;
 }
 
@@ -1279,7 +1289,7 @@ void oracle_find(const OGeom* og, const double* align, const double* xX0, const 
                  int32_t brute, double tol_abs, double tol_rel, double tol_win, int32_t* n_cand, int32_t* hit_idx,
                  int32_t* n_hits, int32_t* n_miss, double* chi2, double* state, double* cov, uint32_t* status,
                  uint32_t* ambig, double* rf_state, double* rf_cov, double* rf_chi2, int32_t* rf_ndf,
-                 uint32_t* rf_status) {
+                 uint32_t* rf_status, int64_t* work) {
   Geo g = make_geo(og);
   set_model(g, model);
   Layer<double> lay[32];
@@ -1299,7 +1309,13 @@ void oracle_find(const OGeom* og, const double* align, const double* xX0, const 
     EventView ev{hits, n_hits_total, hit_off + (int64_t)e * (L + 1)};
     int32_t sh[3] = {seed_hits[s], seed_hits[S + s], seed_hits[2 * S + s]};
     uint32_t amb = 0;
-    std::vector<Cand> cs = find_seed(g, lay, o, ev, bins[e], sh, amb);
+    int64_t wk[4] = {0, 0, 0, 0};
+    std::vector<Cand> cs = find_seed(g, lay, o, ev, bins[e], sh, amb, work ? wk : nullptr);
+    if (work)
+      for (int q = 0; q < 4; ++q) {
+#pragma omp atomic
+        work[q] += wk[q];
+      }
     ambig[s] = amb;
     n_cand[s] = (int32_t)cs.size();
     for (int k = 0; k < keep; ++k) {

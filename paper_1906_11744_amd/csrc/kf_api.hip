@@ -84,7 +84,7 @@ size_t backward_ws_bytes(const kf_ctx* ctx, int64_t n) {
 // | bin offsets [E][L][nbins + 1] | tile counter | backpointers of the persistent
 // workgroups' current tiles.
 struct FindWs {
-  size_t layers, brec, bidx, boff, counter, bp, bpos, rpos, rmask, total;
+  size_t layers, brec, hpos, bidx, boff, counter, bp, bpos, rpos, rmask, total;
 };
 
 int64_t find_tiles(const kf_find_in* in, int lanes_per_seed) {
@@ -122,7 +122,8 @@ FindWs find_ws(const kf_ctx* c, const kf_find_in* in) {
   const size_t E = (size_t)(in->n_events > 0 ? in->n_events : 0);
   w.layers = 0;
   w.brec = w.layers + fit_ws_bytes();
-  w.bidx = w.brec + round_up(H * 16);
+  w.hpos = w.brec + round_up(H * 16);
+  w.bidx = w.hpos + round_up(H * 16);
   w.boff = w.bidx + round_up(H * 4);
   w.counter = w.boff + round_up(E * c->g.n_layers * nb * 4);
   w.bp = w.counter + kAlign;
@@ -412,6 +413,7 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   b.layers = layers;
   for (int l = 0; l < 32; ++l) b.zhalf[l] = l < ctx->g.n_layers ? ctx->g.zhalf_cm[l] : 1.f;
   b.brec = reinterpret_cast<float4*>(base + w.brec);
+  b.hpos = reinterpret_cast<float4*>(base + w.hpos);
   b.bidx = reinterpret_cast<int32_t*>(base + w.bidx);
   b.boff = reinterpret_cast<int32_t*>(base + w.boff);
   b.counter = reinterpret_cast<int32_t*>(base + w.counter);
@@ -439,10 +441,12 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
     f.rmask = reinterpret_cast<uint32_t*>(base + w.rmask);
   }
   f.hits = in->hits;
+  f.hit_off = in->hit_off;
   f.seed_event = in->seed_event;
   f.seed_hits = in->seed_hits;
   f.layers = layers;
   f.brec = b.brec;
+  f.hpos = b.hpos;
   f.bidx = b.bidx;
   f.boff = b.boff;
   for (int l = 0; l < 32; ++l) f.zhalf[l] = b.zhalf[l];

@@ -2,7 +2,9 @@
 //
 //  * bin_kernel: one workgroup per (event, layer) slice; places every hit on its
 //    (aligned) layer and counting-sorts it into n_phi x n_z bins in LDS.  Binned
-//    records are (x, y, z, phi about the layer axis) plus the caller's hit index.
+//    records are (x, y, z, phi about the layer axis) plus the caller's hit index; the
+//    same records are also written in the caller's hit order, so that a hit known by
+//    its index is one 16-byte load away.
 //  * find_kernel: persistent one-wave workgroups pull tiles of 8 seeds from a counter.
 //    A seed owns a group of 8 lanes; lane k holds candidate k (state in registers).
 //    Per layer every live candidate predicts, parks its predicted covariance in LDS,
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
         const int p = atomicAdd(&cnt[b], 1);
         a.brec[p] = rec;
         a.bidx[p] = (int32_t)j;
+        a.hpos[j] = rec;
       }
     }
   }
@@ -232,8 +235,15 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) sh[q] = a.seed_hits[q * S + s];
       bad = e < 0 || e >= a.n_events;
+      // hit q must lie in its event's slice of layer q (clamped to the hit array)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) bad = bad || sh[q] < 0 || (int64_t)sh[q] >= a.H;
+      for (int q = 0; q < 3; ++q) {
+        int64_t lo = bad ? 0 : a.hit_off[(int64_t)e * (nl + 1) + q];
+        int64_t hi = bad ? 0 : a.hit_off[(int64_t)e * (nl + 1) + q + 1];
+        lo = lo < 0 ? 0 : (lo > a.H ? a.H : lo);
+        hi = hi < lo ? lo : (hi > a.H ? a.H : hi);
+        bad = bad || (int64_t)sh[q] < lo || (int64_t)sh[q] >= hi;
+      }
       if (bad) {
         e = 0;
         sh[0] = sh[1] = sh[2] = 0;
@@ -242,9 +252,12 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
     if (active && !bad) {
       float m[3][3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        kfd::place(a.layers[q], a.hits[sh[q]], a.hits[a.H + sh[q]], a.hits[2 * a.H + sh[q]], m[q][0], m[q][1],
-                   m[q][2]);
+      for (int q = 0; q < 3; ++q) {
+        const float4 h = a.hpos[sh[q]];  // placed on its layer by the binning
+        m[q][0] = h.x;
+        m[q][1] = h.y;
+        m[q][2] = h.z;
+      }
       if (bpos) {
 #pragma unroll
         for (int q = 0; q < 3; ++q)
@@ -589,8 +602,8 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
             kfd::Pred pu;
             kfd::prepare(k, fu, a.md, pu);
             if (pu.fp64) st |= kfd::ST_FP64;
-            float mx, my, mz;
-            kfd::place(ly, a.hits[my_hit], a.hits[a.H + my_hit], a.hits[2 * a.H + my_hit], mx, my, mz);
+            const float4 h = a.hpos[my_hit];  // placed on its layer by the binning
+            const float mx = h.x, my = h.y, mz = h.z;
             if (bpos) {
               bpos[(l * 3 + 0) * kWave + lane] = mx;
               bpos[(l * 3 + 1) * kWave + lane] = my;

@@ -49,6 +49,7 @@ struct BinArgs {
   const kfd::LayerK* layers;
   float zhalf[32];
   float4* brec;            // [H] binned (x, y, z, phi) of placed hits
+  float4* hpos;            // [H] the same records in the caller's hit order
   int32_t* bidx;           // [H] caller's index of each binned hit
   int32_t* boff;           // [E][L][nbins + 1] absolute start of every bin
   int32_t* counter;        // find tile queue, zeroed here
@@ -61,11 +62,13 @@ struct FindArgs {
   kfd::Model md;
   float srphi, sz;
   int64_t n_seeds, H, n_tiles;
+  const int64_t* hit_off;  // [E][L+1]
   const float* hits;
   const int32_t* seed_event;
   const int32_t* seed_hits;
   const kfd::LayerK* layers;
   const float4* brec;
+  const float4* hpos;  // [H] placed (x, y, z, phi) of every hit in the caller's order
   const int32_t* bidx;
   const int32_t* boff;
   float zhalf[32];

@@ -244,6 +244,37 @@ def test_find_empty_and_invalid():
         ctx.find(to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event), keep=9)
 
 
+def test_find_flags_malformed_seeds():
+    """Seeds whose event is out of range, or whose hit q is outside the event's slice of
+    layer q (out of the hit array, on another layer, in another event), get no candidate
+    and BAD_INPUT; the well-formed seeds beside them are found as without them."""
+    need_gpu()
+    from paper_1906_11744_amd import Context
+    geom, ev = synth.find_workload(5, n_tracks=300, n_events=3)
+    S = ev.seed_hits.shape[1]
+    good = np.arange(0, S, 3)
+    sh = ev.seed_hits[:, good].copy()
+    se = ev.seed_event[good].copy()
+    e1 = int(np.nonzero(ev.seed_event == 1)[0][0])
+    bad = [(sh[:, 0], 7),                                        # event out of range
+           (np.array([sh[0, 0], sh[1, 0], ev.hits.shape[1]]), se[0]),   # hit index beyond the array
+           (np.array([sh[1, 0], sh[0, 0], sh[2, 0]]), se[0]),   # hits 0 and 1 swapped: wrong layers
+           (np.array([sh[0, 0], ev.seed_hits[1, e1], sh[2, 0]]), se[0] if ev.seed_event[e1] != se[0] else 0)]
+    bsh = np.stack([b[0] for b in bad], axis=1).astype(np.int32)
+    bse = np.array([b[1] for b in bad], np.int32)
+    ctx = Context(geom)
+    xX0 = to_dev(geom.xX0.astype(np.float32))
+    mixed = ctx.find(to_dev(ev.hits), to_dev(ev.hit_off), to_dev(np.concatenate([sh, bsh], axis=1)),
+                     to_dev(np.concatenate([se, bse])), xX0=xX0)
+    plain = ctx.find(to_dev(ev.hits), to_dev(ev.hit_off), to_dev(sh), to_dev(se), xX0=xX0)
+    torch.cuda.synchronize()
+    n = good.size
+    assert np.all(mixed["n_cand"].cpu().numpy()[n:] == 0)
+    assert np.all(mixed["status"].cpu().numpy().view(np.uint32)[0, n:] == oracle.ST_BAD_INPUT)
+    for k in plain:
+        np.testing.assert_array_equal(mixed[k].cpu().numpy()[..., :n], plain[k].cpu().numpy(), err_msg=k)
+
+
 def test_find_independent_of_launch_configuration():
     """Wave-wide scans of wide windows, the persistent grid size, the bin tiling the
     search walks and the autotuner's choice change the time only: every output bit is
