@@ -41,6 +41,20 @@ FLOPS_FIRST = 14 + 83 + FLOPS_PLACE + 50 + 356 + 1  # update at the seed layer
 FLOPS_PROPAGATE = 60 + 194 + 14                    # crossing, transport, frame
 FLOPS_SCATTER = 27
 FLOPS_UPDATE = 83 + FLOPS_PLACE + 50 + 356 + 1
+# The finder's algorithmic work, per operation of its algorithm (counts of each on the
+# benchmark workloads are the oracle's, in tests/golden/find_work.json):
+#   a prediction that reaches its layer: crossing, transport, frame, scattering, S and its
+#     inverse, the window's half widths (2 square roots, a division, 3 products, 2 adds);
+#   a hit inside a window: rectangle test (4) and its residual and chi2 (50);
+#   an update of a surviving hit branch: gain, state and Joseph covariance (its residual
+#     and S^-1 were formed by the scan and the prediction);
+#   a seed refit: the three-hit seed, the update at layer 0, then two predictions and
+#     updates (no alignment: no hit placement).
+FLOPS_FIND_PREDICT = 60 + 194 + 14 + 27 + 83 + 8
+FLOPS_FIND_WINDOW_HIT = 4 + 50
+FLOPS_FIND_UPDATE = 356
+FLOPS_FIND_SEED = 91 + (14 + 83 + 50 + 356 + 1) + 2 * (60 + 194 + 14 + 27 + 83 + 50 + 356 + 1)
+FIND_WORK = os.path.join(ROOT, "tests", "golden", "find_work.json")
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk, packed FP32)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # the same without packed FP32 (64 FMA lanes per CU per clock)
 PEAK_HBM_GBS = 8000.0
@@ -72,6 +86,27 @@ def _traffic_bytes(table, sources, n_tracks):
     if h.hexdigest()[:16] != table["sources"] or n_tracks != table["tracks"]:
         return None
     return 1024.0 * (table["fetch_kib"] * table["fetch_scale"] + table["write_kib"] * table["write_scale"])
+
+
+# The same for one find_kernel launch on the 64-event batch (773 995 seeds) in its
+# benchmarked configuration; valid only while the finder's sources hash to `sources`.
+FIND_TRAFFIC = {"sources": None, "tracks": 773995, "fetch_kib": 0.0, "write_kib": 0.0,
+                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
+FIND_SOURCES = ("paper_1906_11744_amd/csrc/kf_find.hip", "paper_1906_11744_amd/csrc/kf_device.h",
+                "paper_1906_11744_amd/csrc/kf_internal.h")
+
+
+def find_traffic_bytes(n_seeds):
+    """Measured HBM bytes per search-kernel launch on the 64-event batch, or None."""
+    if FIND_TRAFFIC["sources"] is None:
+        return None
+    return _traffic_bytes(FIND_TRAFFIC, FIND_SOURCES, n_seeds)
+
+
+def find_algorithmic_flops(work):
+    """Flops of the finder's algorithm for the operation counts `work` (find_work.json)."""
+    return float(work["predictions"] * FLOPS_FIND_PREDICT + work["window_hits"] * FLOPS_FIND_WINDOW_HIT +
+                 work["updates"] * FLOPS_FIND_UPDATE + work["seed_refits"] * FLOPS_FIND_SEED)
 
 
 def fit_traffic_bytes(n_tracks):
@@ -185,8 +220,9 @@ class _HipEvents:
 
     def elapsed_ms(self, a, b):
         ms = self._C.c_float()
-        if self.hip.hipEventElapsedTime(self._C.byref(ms), a, b) != 0:
-            raise RuntimeError("hipEventElapsedTime failed")
+        rc = self.hip.hipEventElapsedTime(self._C.byref(ms), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
         return ms.value
 
     def close(self):
@@ -270,6 +306,22 @@ def bench_find(steps, warmup):
     res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3, "config": cfg_batched,
                                 "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1]),
                                 "fp64_fallback": _fallback_rates(out)}
+    # the search kernel alone, on its own launch events (plain launches, the tuned
+    # configuration), against the algorithmic flops of what the search does
+    with open(FIND_WORK) as fh:
+        work = json.load(fh)["batched_64_events"]
+    if work["seeds"] == int(ev.seed_hits.shape[1]) and work["hits"] == int(ev.hits.shape[1]):
+        kf.set_find_config(**dict(cfg_batched, use_graph=0))
+        t_k = _time_kernel(kf, lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
+        flops = find_algorithmic_flops(work)
+        ach = flops / t_k / 1e12
+        res["batched_64_events"]["roofline"] = {
+            "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP32_TFLOPS, "traffic": find_traffic_bytes(work["seeds"]),
+            "traffic_unit": "B per launch", "kernel": "find_kernel", "avg_launch_ms": t_k * 1e3,
+            "algorithmic_flops_per_launch": flops, "work": {k: work[k] for k in
+                                                            ("predictions", "window_hits", "updates", "seed_refits")},
+            "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS, "frac_unpacked": ach / PEAK_FP32_UNPACKED_TFLOPS}
     res["per_event_loop_64_events"] = {"events_per_s": E / avg_l, "ms_total": avg_l * 1e3}
     res["batched_speedup"] = avg_l / avg_b
     return res
@@ -464,6 +516,64 @@ def bench_dedup(steps, warmup):
             "remove_ms": t_rm * 1e3, "remove_tracks_per_s": S2 / t_rm}
 
 
+def _cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo) and its logical CPUs."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs on the host)"
+    except OSError:
+        pass
+    return None
+
+
+def _cpu_more(geom, ts):
+    """More of the oracle on the host, each on a bounded sample: the fit on one thread
+    (20 000 tracks of the fit workload, passes until 3 s), and the finder with every
+    thread on the one-event workload (5 000 tracks) and on the first 24 000 seeds of the
+    64-event batch (every event's hits), scaled to events by the batch's seeds per event."""
+    import oracle
+    import synth
+    out = {}
+    sub_hits = np.ascontiguousarray(ts.hits[:, :, :20000])
+    sub_mask = np.ascontiguousarray(ts.hit_mask[:20000])
+    try:
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        passes, st = 0, 0
+        while True:
+            r = oracle.fit(geom, sub_hits, sub_mask)
+            passes += 1
+            st += int(np.where(r["status"] & 16, 0, (r["ndf"] + 5) // 2).sum())
+            dt = time.perf_counter() - t0
+            if dt >= 3.0:
+                break
+        out["one_thread_value"] = st / dt
+        out["one_thread_sample"] = f"{passes} pass(es) over 20 000 tracks of the workload, 1 thread, {dt:.1f} s"
+    finally:
+        oracle.set_num_threads(0)
+    g3, ev3 = synth.find_workload(3)
+    t0 = time.perf_counter()
+    oracle.find(g3, ev3)
+    dt = time.perf_counter() - t0
+    out["find_one_event_5000_tracks"] = {"events_per_s": 1.0 / dt, "threads": oracle.num_threads()}
+    g5, ev5 = synth.find_workload(5)
+    from types import SimpleNamespace
+    k = 24000
+    sub = SimpleNamespace(hits=ev5.hits, hit_off=ev5.hit_off, seed_hits=np.ascontiguousarray(ev5.seed_hits[:, :k]),
+                          seed_event=np.ascontiguousarray(ev5.seed_event[:k]))
+    t0 = time.perf_counter()
+    oracle.find(g5, sub)
+    dt = time.perf_counter() - t0
+    per_event = ev5.seed_hits.shape[1] / ev5.hit_off.shape[0]
+    out["find_64_events"] = {"events_per_s": k / dt / per_event, "seeds_per_s": k / dt,
+                             "threads": oracle.num_threads(),
+                             "sample": f"first {k} of {ev5.seed_hits.shape[1]} seeds (binning of all 64 events "
+                                       f"included), {dt:.1f} s"}
+    return out
+
+
 def cpu_scaling():
     """The oracle's finder over several events at once (its OpenMP loop runs over every
     seed of every event, so all events are in flight together) against the number of
@@ -603,7 +713,9 @@ def main():
             res["cpu_baseline"] = {"value": ref_steps / dt, "unit": "steps/s", "cores": oracle.num_threads(),
                                    "kind": "oracle",
                                    "sample": f"{passes} pass(es) over all {n} tracks of the same workload, FP64 C++ "
-                                             f"oracle (OpenMP over tracks), {dt:.1f} s"}
+                                             f"oracle (OpenMP over tracks), {dt:.1f} s",
+                                   "cpu_model": _cpu_model()}
+            res["cpu_baseline"].update(_cpu_more(geom, ts))
         del hits, mask, out
     else:
         res = {"metric": "KF propagate+update steps/s (FP32 vs oracle tol)", "value": None, "unit": "steps/s",

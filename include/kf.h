@@ -172,7 +172,8 @@ int kf_ctx_destroy(kf_ctx* ctx);
 int kf_ctx_set_fallback_threshold(kf_ctx* ctx, float det_threshold);
 
 /* Timing hook.  While start and stop (hipEvent_t, created by the caller) are both
- * non-NULL, the main kernel of every kf_fit and kf_smooth call is launched with
+ * non-NULL, the main kernel of every kf_fit and kf_smooth call, and the search kernel of
+ * every kf_find call made without a graph (use_graph 0), is launched with
  * hipExtLaunchKernel so that the two events record the beginning and the end of that
  * kernel's own execution on the stream (the measure a kernel trace reports, without
  * the dispatch gaps between consecutive launches); hipEventElapsedTime(start, stop)

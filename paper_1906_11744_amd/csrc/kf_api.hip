@@ -389,9 +389,10 @@ int check_find(kf_ctx* ctx, const kf_find_in* in, const kf_find_out* out, void* 
   return check_ws(ws, ws_bytes, find_ws(ctx, in).total);
 }
 
-// The launches of one kf_find call (arguments already checked, n_seeds > 0).
+// The launches of one kf_find call (arguments already checked, n_seeds > 0); timed:
+// the search kernel records the context's launch events (never inside a capture).
 int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
-                 void* ws, hipStream_t st) {
+                 void* ws, hipStream_t st, bool timed) {
   const int group = find_group(ctx, in->keep);
   int grid = 0;  // (also readies the kernels' LDS limits before the first launch)
   if (persistent_grid(ctx, ctx->g.n_layers, group, &grid) != KF_OK) return KF_E_HIP;
@@ -466,7 +467,9 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   f.status = out->status;
   if ((int64_t)grid > find_grid_cap(in)) grid = (int)find_grid_cap(in);
   if ((int64_t)grid > f.n_tiles) grid = (int)f.n_tiles;
-  if (kfi::launch_find(f, group, grid, st) != hipSuccess) return KF_E_HIP;
+  if (kfi::launch_find(f, group, grid, st, timed ? ctx->ev_start : nullptr, timed ? ctx->ev_stop : nullptr) !=
+      hipSuccess)
+    return KF_E_HIP;
   if (in->refit) {
     kfi::FitArgs a;
     a.n = in->n_seeds;
@@ -575,7 +578,7 @@ int find_graph(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in,
       ctx->cap_device = dev;
     }
     if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return KF_E_HIP;
-    const int rc = enqueue_find(ctx, params, in, out, ws, ctx->cap_stream);
+    const int rc = enqueue_find(ctx, params, in, out, ws, ctx->cap_stream, false);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
     if (rc != KF_OK || ec != hipSuccess) {
@@ -607,7 +610,7 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
   if (rc != KF_OK || in->n_seeds == 0) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (ctx->fcfg.use_graph) return find_graph(ctx, params, in, out, ws, ws_bytes, st);
-  return enqueue_find(ctx, params, in, out, ws, st);
+  return enqueue_find(ctx, params, in, out, ws, st, true);
 }
 
 }  // extern "C"

@@ -719,13 +719,22 @@ hipError_t max_blocks(int nl, int* blocks_per_cu) {
                                                       find_lds_bytes(nl));
 }
 
-template <bool kModel>
-hipError_t launch_group(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream) {
+template <bool kModel, int G>
+void launch_variant(const FindArgs& a, int grid, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const dim3 g((unsigned)grid), b(kWave);
   const size_t lds = find_lds_bytes(a.nl);
-  if (lanes_per_seed == 4) hipLaunchKernelGGL((find_kernel<kModel, 4>), g, b, lds, stream, a);
-  else if (lanes_per_seed == 6) hipLaunchKernelGGL((find_kernel<kModel, 6>), g, b, lds, stream, a);
-  else hipLaunchKernelGGL((find_kernel<kModel, 8>), g, b, lds, stream, a);
+  if (ev_start && ev_stop)  // timing hook: the events bracket the kernel's own execution
+    hipExtLaunchKernelGGL((find_kernel<kModel, G>), g, b, lds, stream, ev_start, ev_stop, 0, a);
+  else
+    hipLaunchKernelGGL((find_kernel<kModel, G>), g, b, lds, stream, a);
+}
+
+template <bool kModel>
+hipError_t launch_group(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream, hipEvent_t ev_start,
+                        hipEvent_t ev_stop) {
+  if (lanes_per_seed == 4) launch_variant<kModel, 4>(a, grid, stream, ev_start, ev_stop);
+  else if (lanes_per_seed == 6) launch_variant<kModel, 6>(a, grid, stream, ev_start, ev_stop);
+  else launch_variant<kModel, 8>(a, grid, stream, ev_start, ev_stop);
   return hipGetLastError();
 }
 
@@ -739,10 +748,11 @@ hipError_t find_max_blocks(int nl, bool model, int lanes_per_seed, int* blocks_p
   }
 }
 
-hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream) {
+hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream, hipEvent_t ev_start,
+                       hipEvent_t ev_stop) {
   if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
-    return launch_group<true>(a, lanes_per_seed, grid, stream);
-  return launch_group<false>(a, lanes_per_seed, grid, stream);
+    return launch_group<true>(a, lanes_per_seed, grid, stream, ev_start, ev_stop);
+  return launch_group<false>(a, lanes_per_seed, grid, stream, ev_start, ev_stop);
 }
 
 }  // namespace kfi

@@ -190,7 +190,8 @@ size_t find_bp_bytes(int nl, int64_t grid);     // backpointer buffer of `grid` 
 // model: the finder variant with the detector model (material map, energy loss, field);
 // lanes_per_seed: 4, 6 or 8 lanes hold one seed's candidates
 hipError_t find_max_blocks(int nl, bool model, int lanes_per_seed, int* blocks_per_cu);
-hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream);
+hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream,
+                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Writes the per-layer constants (radius, alignment, its cos/sin, material; with
 // zhalf_host and map_nz > 0 also the placement of the material map's z bins).
