@@ -31,7 +31,9 @@ class OGeom(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("n_phi_bins", C.c_int32), ("n_z_bins", C.c_int32),
                 ("pad", C.c_int32), ("B", C.c_double), ("sigma_rphi", C.c_double),
                 ("sigma_z", C.c_double), ("sigma_r", C.c_double), ("mass", C.c_double),
-                ("radius", C.c_double * 32), ("zhalf", C.c_double * 32)]
+                ("radius", C.c_double * 32), ("zhalf", C.c_double * 32),
+                ("disk_z", C.c_double * 32), ("disk_rmin", C.c_double * 32), ("disk_rmax", C.c_double * 32),
+                ("cyl_zmax", C.c_double * 32)]
 
 
 class OModel(C.Structure):
@@ -96,6 +98,10 @@ def ogeom(geom) -> OGeom:
     for i in range(geom.n_layers):
         g.radius[i] = geom.radius[i]
         g.zhalf[i] = geom.zhalf[i]
+        g.disk_z[i] = geom.disk_z[i]
+        g.disk_rmin[i] = geom.disk_rmin[i]
+        g.disk_rmax[i] = geom.disk_rmax[i]
+        g.cyl_zmax[i] = geom.cyl_zmax[i]
     return g
 
 
@@ -114,6 +120,26 @@ def propagate(state, center, r, B):
     ok = load().oracle_propagate(_p(st), C.c_double(center[0]), C.c_double(center[1]), C.c_double(r),
                                  C.c_double(B), _p(out), C.byref(s))
     return (out, s.value) if ok else (None, None)
+
+
+def propagate_disk(state, zd, B):
+    """Crossing with the plane z = zd: (state, arc) or (None, None)."""
+    out = np.zeros(6)
+    s = C.c_double(0)
+    st = np.ascontiguousarray(state, np.float64)
+    ok = load().oracle_propagate_disk(_p(st), C.c_double(zd), C.c_double(B), _p(out), C.byref(s))
+    return (out, s.value) if ok else (None, None)
+
+
+def measurement_disk(state, center, zd, m):
+    """H (3x6) and residual on the disk plane z = zd centred at `center`."""
+    H = np.zeros(18)
+    r = np.zeros(3)
+    st = np.ascontiguousarray(state, np.float64)
+    mm = np.ascontiguousarray(m, np.float64)
+    load().oracle_measurement_disk(_p(st), C.c_double(center[0]), C.c_double(center[1]), C.c_double(zd), _p(mm),
+                                   _p(H), _p(r))
+    return H.reshape(3, 6), r
 
 
 def transport_jacobian(state, s, B):
@@ -139,12 +165,13 @@ def measurement(state, center, m):
     return H.reshape(3, 6), r
 
 
-def scattering(geom, state, center, xX0):
+def scattering(geom, state, center, xX0, zd=0.0):
+    """Q (6x6) at a state on a cylinder centred at `center`, or on the disk z = zd."""
     Q = np.zeros(36)
     g = ogeom(geom)
     st = np.ascontiguousarray(state, np.float64)
     load().oracle_scattering(C.byref(g), _p(st), C.c_double(center[0]), C.c_double(center[1]),
-                             C.c_double(xX0), _p(Q))
+                             C.c_double(xX0), C.c_double(zd), _p(Q))
     return Q.reshape(6, 6)
 
 

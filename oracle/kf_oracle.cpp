@@ -121,6 +121,10 @@ struct OGeom {
   double B, sigma_rphi, sigma_z, sigma_r, mass;
   double radius[32];
   double zhalf[32];
+  // endcap disks: layer l is the plane z = disk_z[l] (!= 0) active for radii
+  // disk_rmin[l] .. disk_rmax[l]; other layers are cylinders active for |z| <= cyl_zmax[l]
+  // (0: unbounded)
+  double disk_z[32], disk_rmin[32], disk_rmax[32], cyl_zmax[32];
 };
 }
 
@@ -142,13 +146,19 @@ template <class T>
 struct Layer {
   T cx, cy, dz, cphi, sphi, xX0;  // alignment (centre, z shift, rotation) and x/X0
   double r;
-  int idx;  // layer index (row of a material map)
+  int idx = 0;  // layer index (row of a material map)
+  // a disk: the plane z = zd + dz, active for rmin <= rho <= rmax (rho about its axis);
+  // a cylinder: active for |z - dz| <= zmax (0: unbounded)
+  bool disk = false;
+  double zd = 0, rmin = 0, rmax = 0, zmax = 0;
+  bool bounded() const { return disk || zmax > 0; }
 };
 
 struct Geo {
   int nl;
   double kB, srphi, sz, sr, mass;
   double radius[32], zhalf[32];
+  double disk_z[32], disk_rmin[32], disk_rmax[32], cyl_zmax[32];
   int nphi, nz;
   // Material beyond one x/X0 per layer (Sec. 3: a per-layer table of x/X0 over z,
   // multiple scattering and energy loss): map [nl][map_nz] of x/X0 at the centres of
@@ -176,7 +186,14 @@ Geo make_geo(const OGeom* g) {
   o.nl = g->n_layers;
   o.kB = 0.299792458e-2 * g->B;
   o.srphi = g->sigma_rphi; o.sz = g->sigma_z; o.sr = g->sigma_r; o.mass = g->mass;
-  for (int l = 0; l < 32; ++l) { o.radius[l] = g->radius[l]; o.zhalf[l] = g->zhalf[l]; }
+  for (int l = 0; l < 32; ++l) {
+    o.radius[l] = g->radius[l];
+    o.zhalf[l] = g->zhalf[l];
+    o.disk_z[l] = g->disk_z[l];
+    o.disk_rmin[l] = g->disk_rmin[l];
+    o.disk_rmax[l] = g->disk_rmax[l];
+    o.cyl_zmax[l] = g->cyl_zmax[l];
+  }
   o.nphi = g->n_phi_bins; o.nz = g->n_z_bins;
   return o;
 }
@@ -194,6 +211,11 @@ void make_layers(const Geo& g, const T* align /*[L][4]*/, const T* xX0, Layer<T>
     lay[l].xX0 = xX0 ? xX0[l] : T(0.0);
     lay[l].r = g.radius[l];
     lay[l].idx = l;
+    lay[l].disk = g.disk_z[l] != 0.0;
+    lay[l].zd = g.disk_z[l];
+    lay[l].rmin = g.disk_rmin[l];
+    lay[l].rmax = g.disk_rmax[l];
+    lay[l].zmax = lay[l].disk ? 0.0 : g.cyl_zmax[l];
   }
 }
 
@@ -305,6 +327,19 @@ bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, const T& kB,
   return true;
 }
 
+// Transverse arc to the plane of a disk: z(s) = z + s cot(theta) = zp gives s = (zp - z)
+// tan(theta).  The plane must lie ahead (s > 0) and be reached within half a turn.
+template <class T>
+bool plane_arc(const T x[6], const Layer<T>& ly, const T& kB, T& s) {
+  using std::cos; using std::sin;
+  const T ct = cos(x[5]);
+  if (val(ct) == 0) return false;
+  s = (ly.zd + ly.dz - x[2]) * sin(x[5]) / ct;
+  if (!(val(s) > 0)) return false;
+  const double w = -val(kB) * val(x[3]);
+  return std::fabs(w * val(s)) < kPi;
+}
+
 // Transport Jacobian of the helix map at fixed transverse arc s (start state x,
 // end state xe).  J = I plus six terms: d(x,y)/dphi, d(x,y)/dkappa, dz/dtheta,
 // dphi/dkappa.
@@ -363,7 +398,9 @@ void add_scattering(const Geo& g, const Layer<T>& ly, const T x[6], T C[6][6]) {
   T ex = x[0] - ly.cx, ey = x[1] - ly.cy;
   T rho = sqrt(ex * ex + ey * ey);
   T st = sin(x[5]), ct = cos(x[5]);
-  T cpsi = st * fabs((ex * cos(x[4]) + ey * sin(x[4])) / rho);
+  // cosine of the angle between the track and the surface normal: r_hat on a cylinder,
+  // z on a disk
+  T cpsi = ly.disk ? fabs(ct) : st * fabs((ex * cos(x[4]) + ey * sin(x[4])) / rho);
   T p = 1.0 / (fabs(x[3]) * st);
   T beta = p / sqrt(p * p + g.mass * g.mass);
   T xe = ly.xX0 / cpsi;
@@ -407,11 +444,13 @@ bool material_step(const Geo& g, const Layer<double>& ly, double x[6], double C[
     for (int i = 0; i < 6; ++i)
       for (int j = 0; j < 6; ++j) A_out[i][j] = i == j ? 1.0 : 0.0;
   Layer<double> lm = ly;
-  if (g.map) lm.xX0 = map_xX0(g, ly.idx, x[2] - ly.dz);
+  if (g.map && !ly.disk) lm.xX0 = map_xX0(g, ly.idx, x[2] - ly.dz);
   add_scattering(g, lm, x, C);
   if (!(g.eloss > 0.0) || !(lm.xX0 > 0.0)) return true;
   const double ex = x[0] - ly.cx, ey = x[1] - ly.cy;
-  const double cpsi = std::sin(x[5]) * std::fabs((ex * std::cos(x[4]) + ey * std::sin(x[4])) / std::sqrt(ex * ex + ey * ey));
+  const double cpsi = ly.disk ? std::fabs(std::cos(x[5]))
+                              : std::sin(x[5]) * std::fabs((ex * std::cos(x[4]) + ey * std::sin(x[4])) /
+                                                           std::sqrt(ex * ex + ey * ey));
   const double xe = lm.xX0 / cpsi;
   const double m2 = g.mass * g.mass;
   Dual<2> kap(x[3]), th(x[5]);
@@ -535,9 +574,42 @@ struct Meas {
   T rho, phip, cosa;
 };
 
+// On a disk the frame is the same about the disk's axis, with the plane's normal z:
+// residual (z_m - z_p, rho_p * wrap(phi_m - phi_p), rho_m - rho_p) and H the projection
+// along the state's tangent onto the plane (a position offset d moves to
+// d - t3 d_z / cot(theta)): row 0 = 0 (the normal), row 1 = (phi_hat, -(phi_hat . t) /
+// cot theta), row 2 = (r_hat, -(r_hat . t) / cot theta); cos alpha = cos theta.
+template <class T>
+void measurement_disk(const Layer<T>& ly, const T x[6], const T m[3], Meas<T>& o) {
+  using std::atan2; using std::cos; using std::sin; using std::sqrt;
+  T ex = x[0] - ly.cx, ey = x[1] - ly.cy;
+  T rho = sqrt(ex * ex + ey * ey);
+  T rx = ex / rho, ry = ey / rho;
+  T fx = -ry, fy = rx;
+  T tx = cos(x[4]), ty = sin(x[4]);
+  T cot = cos(x[5]) / sin(x[5]);
+  for (int i = 0; i < 18; ++i) o.H[i] = 0.0;
+  o.H[6 + 0] = fx;
+  o.H[6 + 1] = fy;
+  o.H[6 + 2] = -(fx * tx + fy * ty) / cot;
+  o.H[12 + 0] = rx;
+  o.H[12 + 1] = ry;
+  o.H[12 + 2] = -(rx * tx + ry * ty) / cot;
+  T mx = m[0] - ly.cx, my = m[1] - ly.cy;
+  T rhom = sqrt(mx * mx + my * my);
+  T phim = atan2(my, mx), phip = atan2(ey, ex);
+  o.r[0] = m[2] - x[2];
+  o.r[1] = rho * wrap_pi(phim - phip);
+  o.r[2] = rhom - rho;
+  o.rho = rho;
+  o.phip = phip;
+  o.cosa = cos(x[5]);
+}
+
 template <class T>
 void measurement(const Layer<T>& ly, const T x[6], const T m[3], Meas<T>& o) {
   using std::atan2; using std::cos; using std::sin; using std::sqrt;
+  if (ly.disk) { measurement_disk(ly, x, m, o); return; }
   T ex = x[0] - ly.cx, ey = x[1] - ly.cy;
   T rho = sqrt(ex * ex + ey * ey);
   T rx = ex / rho, ry = ey / rho;
@@ -603,7 +675,8 @@ template <class T>
 bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nullptr) {
   T s;
   const T kB = kB_at<T>(g, tk.x[0], tk.x[1], tk.x[2]);  // the field at the step's start
-  if (!crossing_arc(tk.x, ly.cx, ly.cy, ly.r, kB, s)) { tk.status |= ST_PROP_FAIL; return false; }
+  const bool crossed = ly.disk ? plane_arc(tk.x, ly, kB, s) : crossing_arc(tk.x, ly.cx, ly.cy, ly.r, kB, s);
+  if (!crossed) { tk.status |= ST_PROP_FAIL; return false; }
   T xe[6];
   helix_at(tk.x, s, kB, xe);
   T J[6][6];
@@ -613,9 +686,11 @@ bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nul
       for (int j = 0; j < 6; ++j) J_out[i][j] = J[i][j];
   sandwich(J, tk.C);
   for (int i = 0; i < 6; ++i) tk.x[i] = xe[i];
-  {  // crossing angle: |cos alpha| = |r_hat . t| below 0.3 marks a near-tangent crossing
+  {  // crossing angle: |cos alpha| = |r_hat . t| (a disk: |cos theta|) below 0.3 marks a
+     // near-tangent crossing
     double ex = val(tk.x[0]) - val(ly.cx), ey = val(tk.x[1]) - val(ly.cy);
-    double ca = (ex * std::cos(val(tk.x[4])) + ey * std::sin(val(tk.x[4]))) / std::sqrt(ex * ex + ey * ey);
+    double ca = ly.disk ? std::cos(val(tk.x[5]))
+                        : (ex * std::cos(val(tk.x[4])) + ey * std::sin(val(tk.x[4]))) / std::sqrt(ex * ex + ey * ey);
     if (std::fabs(ca) < 0.3) tk.status |= ST_NEAR_TANGENT;
   }
   if (g.map || g.eloss > 0.0) {
@@ -709,6 +784,10 @@ Track<T> fit_core(const Geo& g, const Layer<T>* lay, const T (*m)[3], uint32_t m
   int last = 31 - __builtin_clz(mask);
   if (last >= g.nl) last = g.nl - 1;
   for (int l = 1; l <= last; ++l) {
+    // a bounded surface (a disk, or a cylinder of finite length) without a hit is one
+    // the track did not cross: it is passed over (no material); one with a hit was
+    // crossed.  Unbounded cylinders are crossed in turn, with or without a hit.
+    if (lay[l].bounded() && !(mask >> l & 1u)) { record(l); continue; }
     if (!predict(g, lay[l], tk)) break;
     if (mask >> l & 1u)
       if (!update_with_hit(g, lay[l], tk, m[l])) break;
@@ -791,10 +870,41 @@ void oracle_measurement(const double* state, double cx, double cy, const double*
   for (int i = 0; i < 3; ++i) r[i] = me.r[i];
 }
 
-// Multiple-scattering covariance Q (row-major 6x6) at a state on a layer.
-void oracle_scattering(const OGeom* og, const double* state, double cx, double cy, double xX0, double* Q) {
+// The same on the plane z = zd of a disk centred at (cx, cy): H and the residual
+// (z_m - z_p, rho_p dphi, rho_m - rho_p).
+void oracle_measurement_disk(const double* state, double cx, double cy, double zd, const double* m, double* H,
+                             double* r) {
+  Layer<double> ly{cx, cy, 0.0, 1.0, 0.0, 0.0, 0.0};
+  ly.disk = true;
+  ly.zd = zd;
+  Meas<double> me;
+  measurement(ly, state, m, me);
+  for (int i = 0; i < 18; ++i) H[i] = me.H[i];
+  for (int i = 0; i < 3; ++i) r[i] = me.r[i];
+}
+
+// Crossing of one state with the plane z = zd: the propagated state and the transverse
+// arc; 1 on success, 0 if the plane is behind or beyond half a turn.
+int oracle_propagate_disk(const double* state, double zd, double B, double* out, double* s_out) {
+  const double kB = 0.299792458e-2 * B;
+  Layer<double> ly{0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0};
+  ly.disk = true;
+  ly.zd = zd;
+  double s;
+  if (!plane_arc<double>(state, ly, kB, s)) return 0;
+  helix_at<double>(state, s, kB, out);
+  *s_out = s;
+  return 1;
+}
+
+// Multiple-scattering covariance Q (row-major 6x6) at a state on a layer: a cylinder
+// centred at (cx, cy), or (zd != 0) the disk in the plane z = zd.
+void oracle_scattering(const OGeom* og, const double* state, double cx, double cy, double xX0, double zd,
+                       double* Q) {
   Geo g = make_geo(og);
   Layer<double> ly{cx, cy, 0.0, 1.0, 0.0, xX0, 0.0};
+  ly.disk = zd != 0.0;
+  ly.zd = zd;
   double C[6][6] = {};
   add_scattering(g, ly, state, C);
   for (int i = 0; i < 6; ++i)
@@ -1009,7 +1119,7 @@ struct Cand {
 
 struct Branch {
   int parent;
-  int kind;      // 0 hit, 1 miss, 2 carry (terminated parent)
+  int kind;      // 0 hit, 1 miss, 2 carry (terminated parent), 3 pass (a bounded surface not crossed)
   int64_t hit;
   int nhits;
   double chi2tot, chi2h;
@@ -1064,9 +1174,11 @@ void bin_layer(const Geo& g, const Layer<double>& ly, int l, const EventView& ev
     double m[3];
     place_global(ly, ev, B.begin + j, m);
     ph[j] = std::atan2(m[1] - val(ly.cy), m[0] - val(ly.cx));
-    zz[j] = m[2];
+    // the bins' second coordinate: z on a cylinder, the radius about the axis on a disk
+    zz[j] = ly.disk ? std::hypot(m[0] - val(ly.cx), m[1] - val(ly.cy)) : m[2];
+    const double lo2 = ly.disk ? ly.rmin : -g.zhalf[l], span2 = ly.disk ? ly.rmax - ly.rmin : 2 * g.zhalf[l];
     int bp = clamp_bin(bin_floor(ph[j], -kPi, 2 * kPi, nphi), nphi);
-    int bz = clamp_bin(bin_floor(zz[j], -g.zhalf[l], 2 * g.zhalf[l], nz), nz);
+    int bz = clamp_bin(bin_floor(zz[j], lo2, span2, nz), nz);
     bin[j] = bp * nz + bz;
   }
   B.off.assign(nb + 1, 0);
@@ -1127,9 +1239,26 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
       Cand& cd = cands[k];
       if (cd.term) { br.push_back({(int)k, 2, -1, cd.tk.n, cd.tk.chi2, 0.0}); continue; }
       // reaching the layer at all is FP32-sensitive for a helix that grazes it
-      if (std::fabs(reach_margin(g, ly, cd.tk.x)) < 1e-4) ambig |= 1u << L;
+      if (!ly.disk && std::fabs(reach_margin(g, ly, cd.tk.x)) < 1e-4) ambig |= 1u << L;
       Track<double> p = cd.tk;
-      if (!predict(g, ly, p)) {
+      if (ly.bounded()) {
+        // a bounded surface that the candidate does not reach, or reaches outside its
+        // active area, is passed over: the candidate goes on unchanged (no miss).  A
+        // crossing within 0.01 cm of the area's edge is an FP32-sensitive decision.
+        bool cross = predict(g, ly, p);
+        if (cross) {
+          const double c2 = ly.disk ? std::hypot(p.x[0] - ly.cx, p.x[1] - ly.cy) : std::fabs(p.x[2] - ly.dz);
+          const double lo = ly.disk ? ly.rmin : -1.0, hi = ly.disk ? ly.rmax : ly.zmax;
+          if (std::fabs(c2 - hi) < 0.01 || (ly.disk && std::fabs(c2 - lo) < 0.01)) ambig |= 1u << L;
+          cross = c2 <= hi && (!ly.disk || c2 >= lo);
+        } else if (ly.disk && std::fabs(std::cos(cd.tk.x[5])) < 1e-6) {
+          ambig |= 1u << L;  // a track along the plane: which side it heads to is FP32-sensitive
+        }
+        if (!cross) {
+          br.push_back({(int)k, 3, -1, cd.tk.n, cd.tk.chi2, 0.0});
+          continue;
+        }
+      } else if (!predict(g, ly, p)) {
         // no crossing (the state is untouched), or the particle stops in the layer's
         // material (it ends with the prediction transported to the layer)
         cd.tk = p;
@@ -1167,7 +1296,8 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
       }
       double wphi = o.nsigma * std::sqrt(S[4]) / me.rho;
       double wz = o.nsigma * std::sqrt(S[8]);
-      double phip = me.phip, zp = p.x[2];
+      // the window's second coordinate: z on a cylinder, the radius on a disk
+      double phip = me.phip, zp = ly.disk ? me.rho : p.x[2];
       auto consider = [&](int64_t j, double phih, double zh) {
         double dphi = wrap_pi(phih - phip), dz = zh - zp;
         double ephi = std::fabs(dphi) - wphi, ez = std::fabs(dz) - wz;
@@ -1188,14 +1318,16 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
         for (int64_t j = B.begin; j < B.end; ++j) {
           double mh[3];
           place_global(ly, ev, j, mh);
-          consider(j, std::atan2(mh[1] - ly.cy, mh[0] - ly.cx), mh[2]);
+          consider(j, std::atan2(mh[1] - ly.cy, mh[0] - ly.cx),
+                   ly.disk ? std::hypot(mh[0] - ly.cx, mh[1] - ly.cy) : mh[2]);
         }
       } else {
         // every bin that can hold a hit within (1 + tol_win) of the window, and more
         double wq = (1.0 + 2 * o.tol_win) * wphi + 1e-6;
         double zq = (1.0 + 2 * o.tol_win) * wz + 1e-6;
-        int zlo = clamp_bin(bin_floor(zp - zq, -g.zhalf[L], 2 * g.zhalf[L], nz), nz);
-        int zhi = clamp_bin(bin_floor(zp + zq, -g.zhalf[L], 2 * g.zhalf[L], nz), nz);
+        const double lo2 = ly.disk ? ly.rmin : -g.zhalf[L], span2 = ly.disk ? ly.rmax - ly.rmin : 2 * g.zhalf[L];
+        int zlo = clamp_bin(bin_floor(zp - zq, lo2, span2, nz), nz);
+        int zhi = clamp_bin(bin_floor(zp + zq, lo2, span2, nz), nz);
         int64_t blo = 0, bhi = nphi - 1;
         if (wq < kPi) {
           blo = bin_floor(phip - wq, -kPi, 2 * kPi, nphi);
@@ -1228,6 +1360,8 @@ std::vector<Cand> find_seed(const Geo& g, const Layer<double>* lay, const FindCf
         nc.nmiss += 1;
         nc.hist[L] = -1;
         if (nc.nmiss >= o.max_miss) { nc.term = true; nc.tk.status |= ST_TERM_MISSES; }
+      } else if (b.kind == 3) {
+        nc.hist[L] = -2;  // a bounded surface passed over: unchanged, no miss
       } else if (b.kind == 0) {
         nc.tk = pred[b.parent];
         double mh[3];

@@ -53,6 +53,13 @@ class Geometry:
     mass: float = M_PION          # GeV, used in beta of the Highland formula
     n_phi_bins: int = 128
     n_z_bins: int = 32
+    # Endcap disks (Sec. 3): layer l is the plane z = disk_z[l] (!= 0), active for radii
+    # disk_rmin[l] .. disk_rmax[l] (its finder bins run over that radial range); other
+    # layers are cylinders, active for |z| <= cyl_zmax[l] (0: unbounded).
+    disk_z: np.ndarray | None = None
+    disk_rmin: np.ndarray | None = None
+    disk_rmax: np.ndarray | None = None
+    cyl_zmax: np.ndarray | None = None
 
     def __post_init__(self):
         self.radius = np.asarray(self.radius, dtype=np.float64)
@@ -60,6 +67,17 @@ class Geometry:
         if self.xX0 is None:
             self.xX0 = np.zeros_like(self.radius)
         self.xX0 = np.asarray(self.xX0, dtype=np.float64)
+        for f in ("disk_z", "disk_rmin", "disk_rmax", "cyl_zmax"):
+            v = getattr(self, f)
+            setattr(self, f, np.zeros_like(self.radius) if v is None else np.asarray(v, dtype=np.float64))
+
+    @property
+    def is_disk(self) -> np.ndarray:
+        return self.disk_z != 0.0
+
+    @property
+    def has_disks(self) -> bool:
+        return bool(np.any(self.is_disk))
 
     @property
     def n_layers(self) -> int:
@@ -81,6 +99,33 @@ def barrel(n_layers: int, r_min: float, r_max: float, B: float = 3.8,
     r = r_min + (r_max - r_min) * np.arange(n_layers) / (n_layers - 1)
     z = 1.1 * r * math.sinh(eta_max)
     return Geometry(radius=r, zhalf=z, B=B, xX0=np.full(n_layers, xX0), **kw)
+
+
+# eta regions of the seeds (Sec. 2: seeds are processed in regions of pseudorapidity):
+# barrel, transition and endcap on each side, by the seed's |eta| (of its third hit)
+ETA_REGION_EDGES = (0.9, 1.7)
+
+
+def barrel_endcap(n_barrel: int = 17, r_min: float = 4.0, r_max: float = 110.0, zmax: float = 120.0,
+                  disk_z=(130.0, 155.0, 180.0, 205.0, 230.0, 255.0, 280.0), disk_rmin: float = 20.0,
+                  disk_rmax: float = 110.0, B: float = 3.8, xX0: float = 0.0, **kw) -> Geometry:
+    """Barrel cylinders at radii r_min..r_max (evenly spaced), active for |z| <= zmax,
+    then endcap disks at +disk_z, then at -disk_z, active for disk_rmin <= r <= disk_rmax.
+    The cylinders' finder bins in z run over [-zmax, zmax]; the disks' over their radii."""
+    nd = len(disk_z)
+    r = r_min + (r_max - r_min) * np.arange(n_barrel) / (n_barrel - 1)
+    L = n_barrel + 2 * nd
+    radius = np.concatenate([r, np.full(2 * nd, disk_rmax)])
+    dz = np.concatenate([np.zeros(n_barrel), np.asarray(disk_z, float), -np.asarray(disk_z, float)])
+    return Geometry(radius=radius, zhalf=np.full(L, zmax), B=B, xX0=np.full(L, xX0), disk_z=dz,
+                    disk_rmin=np.where(dz != 0, disk_rmin, 0.0), disk_rmax=np.where(dz != 0, disk_rmax, 0.0),
+                    cyl_zmax=np.where(dz == 0, zmax, 0.0), **kw)
+
+
+def eta_region(eta) -> np.ndarray:
+    """Region of each |eta|: 0 barrel, 1 transition, 2 endcap (ETA_REGION_EDGES)."""
+    a = np.abs(np.asarray(eta, np.float64))
+    return (a >= ETA_REGION_EDGES[0]).astype(np.int32) + (a >= ETA_REGION_EDGES[1]).astype(np.int32)
 
 
 def rng_for(workload: int, event: int = 0) -> np.random.Generator:
@@ -208,6 +253,9 @@ def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max
     field at the step's starting point.  A track that cannot reach a layer stops there;
     later layers have no hit.
     """
+    if geom.has_disks:
+        return _simulate_with_disks(geom, rng, n, pt_range, pt_log, eta_max, align, smear, scatter, keep_truth,
+                                    particles, hit_dtype)
     L = geom.n_layers
     if particles is None:
         pt, phi0, eta, q = sample_particles(rng, n, pt_range, pt_log, eta_max)
@@ -301,6 +349,141 @@ def simulate(geom: Geometry, rng, n, pt_range=(0.5, 10.0), pt_log=False, eta_max
             truth[l] = np.where(reach, np.stack([x, y, z, kappa, phi, theta]), np.nan)
     return TrackSample(hits=hits, hit_mask=mask, truth=truth, truth_hit=truth_hit,
                        pt=pt, phi=phi0, eta=eta, q=q)
+
+
+def helix_step(x, y, phi, omega, s):
+    """Transverse position and azimuth after a transverse arc s along the helix (the
+    chord of the circle of curvature omega, written to stay exact as omega -> 0)."""
+    u = omega * s
+    small = np.abs(u) < 1e-6
+    us = np.where(small, 1.0, u)
+    A = np.where(small, 1.0 - u * u / 6.0, np.sin(us) / us)       # sin(u)/u
+    Bn = np.where(small, 0.5 * u, (1.0 - np.cos(us)) / us)       # (1 - cos u)/u
+    tx, ty = np.cos(phi), np.sin(phi)
+    return x + s * (A * tx - Bn * ty), y + s * (A * ty + Bn * tx), phi + u
+
+
+def _simulate_with_disks(geom, rng, n, pt_range, pt_log, eta_max, align, smear, scatter, keep_truth, particles,
+                         hit_dtype):
+    """simulate() for a geometry with endcap disks.  A particle visits the cylinders in
+    turn, then the disks on its side of z (the sign of cot theta) in turn.  A surface it
+    crosses outside its active area (|z| > cyl_zmax of a bounded cylinder; a radius
+    outside a disk's range), or does not reach within half a turn, is passed over: no
+    hit, no material.  An unbounded cylinder that is not reached stops the particle.
+    A disk hit is smeared along the disk: sigma_z in r, sigma_rphi in r*phi; the
+    scattering path length on a disk is x/X0 / |cos theta|.  Uniform field, one x/X0
+    per layer."""
+    L = geom.n_layers
+    if particles is None:
+        pt, phi0, eta, q = sample_particles(rng, n, pt_range, pt_log, eta_max)
+    else:
+        pt, phi0, eta, q = (np.asarray(a, np.float64) for a in particles)
+        n = pt.shape[0]
+    if align is None:
+        align = np.zeros((L, 4))
+    align = np.asarray(align, np.float64)
+    theta = 2.0 * np.arctan(np.exp(-eta))
+    kappa = q / pt
+    phi = phi0.copy()
+    x = np.zeros(n)
+    y = np.zeros(n)
+    z = np.zeros(n)
+    alive = np.ones(n, dtype=bool)
+    hits = np.full((L, 3, n), np.nan, dtype=hit_dtype)
+    mask = np.zeros(n, dtype=np.uint32)
+    truth = np.full((L, 6, n), np.nan) if keep_truth else None
+    truth_hit = np.full((L, 3, n), np.nan) if keep_truth else None
+    kB = geom.k_B
+    for l in range(L):
+        dx, dy, dz, dphi = align[l]
+        omega = -kB * kappa
+        cot = np.cos(theta) / np.sin(theta)
+        if geom.is_disk[l]:
+            zp = geom.disk_z[l] + dz
+            side = np.sign(geom.disk_z[l]) == np.sign(cot)
+            s = np.where(side & (cot != 0), (zp - z) / np.where(cot != 0, cot, 1.0), -1.0)
+            ok = alive & side & (s > 0) & (np.abs(omega * s) < math.pi)
+            s = np.where(ok, s, 0.0)
+            qx, qy, qphi = helix_step(x, y, phi, omega, s)
+            rr = np.hypot(qx - dx, qy - dy)
+            reach = ok & (rr >= geom.disk_rmin[l]) & (rr <= geom.disk_rmax[l])
+            znew = np.full(n, zp)
+        else:
+            r = geom.radius[l]
+            s, qx, qy = first_crossing(x, y, phi, omega, dx, dy, r)
+            got = alive & np.isfinite(s)
+            s = np.where(got, s, 0.0)
+            znew = z + s * cot
+            qphi = phi + omega * s
+            if geom.cyl_zmax[l] > 0:
+                reach = got & (np.abs(znew - dz) <= geom.cyl_zmax[l])
+            else:
+                reach = got
+                alive = got
+        x = np.where(reach, qx, x)
+        y = np.where(reach, qy, y)
+        z = np.where(reach, znew, z)
+        phi = np.where(reach, np.mod(qphi + math.pi, 2.0 * math.pi) - math.pi, phi)
+        g1 = rng.standard_normal(n)
+        g2 = rng.standard_normal(n)
+        if not smear:
+            g1[:] = 0.0
+            g2[:] = 0.0
+        ang = np.arctan2(y - dy, x - dx)
+        if geom.is_disk[l]:
+            rr = np.hypot(x - dx, y - dy)
+            rm = rr + g2 * geom.sigma_z
+            loc = ang + g1 * geom.sigma_rphi / np.maximum(rr, 1e-9) - dphi
+            hx, hy, hz = rm * np.cos(loc), rm * np.sin(loc), np.full(n, geom.disk_z[l])
+        else:
+            r = geom.radius[l]
+            loc = ang + g1 * geom.sigma_rphi / r - dphi
+            hx, hy, hz = r * np.cos(loc), r * np.sin(loc), z + g2 * geom.sigma_z - dz
+        hits[l, 0] = np.where(reach, hx, np.nan)
+        hits[l, 1] = np.where(reach, hy, np.nan)
+        hits[l, 2] = np.where(reach, hz, np.nan)
+        mask |= np.where(reach, np.uint32(1) << np.uint32(l), np.uint32(0)).astype(np.uint32)
+        if keep_truth:
+            truth_hit[l] = np.where(reach, np.stack([x, y, z]), np.nan)
+        k1 = rng.standard_normal(n)
+        k2 = rng.standard_normal(n)
+        xx = geom.xX0[l]
+        if scatter and xx > 0:
+            st, ct = np.sin(theta), np.cos(theta)
+            cp, sp = np.cos(phi), np.sin(phi)
+            if geom.is_disk[l]:
+                cpsi = np.abs(ct)
+            else:
+                r = geom.radius[l]
+                cpsi = st * np.abs((x - dx) / r * cp + (y - dy) / r * sp)
+            p = np.abs(1.0 / kappa) / st
+            beta = p / np.sqrt(p * p + geom.mass ** 2)
+            th0 = highland_theta0(p, beta, xx / np.maximum(cpsi, 1e-12))
+            a = k1 * th0
+            b = k2 * th0
+            d0 = np.stack([st * cp, st * sp, ct])
+            e1 = np.stack([ct * cp, ct * sp, -st])
+            e2 = np.stack([-sp, cp, np.zeros(n)])
+            dn = d0 + a * e1 + b * e2
+            dn /= np.linalg.norm(dn, axis=0)
+            th_new = np.arccos(np.clip(dn[2], -1.0, 1.0))
+            ph_new = np.arctan2(dn[1], dn[0])
+            theta = np.where(reach, th_new, theta)
+            phi = np.where(reach, ph_new, phi)
+            kappa = np.where(reach, q / (p * np.sin(th_new)), kappa)
+        if keep_truth:
+            truth[l] = np.where(reach, np.stack([x, y, z, kappa, phi, theta]), np.nan)
+    return TrackSample(hits=hits, hit_mask=mask, truth=truth, truth_hit=truth_hit,
+                       pt=pt, phi=phi0, eta=eta, q=q)
+
+
+def endcap_workload(n: int = 100_000, event: int = 0, eta_max: float = 2.5, workload: int = 11):
+    """Tracks through the barrel-and-endcap geometry (barrel_endcap, x/X0 = 0.02 per
+    layer), pT log-uniform 0.5-50 GeV, |eta| < eta_max, hits smeared and scattered.
+    Tracks with hits on layers 0-2 can be fitted from three-hit seeds."""
+    geom = barrel_endcap(xX0=0.02)
+    ts = simulate(geom, rng_for(workload, event), n, (0.5, 50.0), True, eta_max)
+    return geom, ts
 
 
 # --------------------------------------------------------------------------------------
@@ -445,9 +628,13 @@ def make_events(geom: Geometry, n_tracks_per_event, workload=3, noise_frac=0.2,
             h = ts.hits[l][:, idx].astype(np.float32)
             nn = int(round(noise_frac * idx.shape[0]))
             ph = rng.uniform(-math.pi, math.pi, nn)
-            zz = rng.uniform(-geom.zhalf[l], geom.zhalf[l], nn)
-            rr = geom.radius[l]
-            hn = np.stack([rr * np.cos(ph), rr * np.sin(ph), zz]).astype(np.float32)
+            if geom.is_disk[l]:   # on the disk: uniform in phi and in its radii
+                rr = rng.uniform(geom.disk_rmin[l], geom.disk_rmax[l], nn)
+                hn = np.stack([rr * np.cos(ph), rr * np.sin(ph), np.full(nn, geom.disk_z[l])]).astype(np.float32)
+            else:
+                zz = rng.uniform(-geom.zhalf[l], geom.zhalf[l], nn)
+                rr = geom.radius[l]
+                hn = np.stack([rr * np.cos(ph), rr * np.sin(ph), zz]).astype(np.float32)
             hl = np.concatenate([h, hn], axis=1)
             tl = np.concatenate([idx.astype(np.int64) + tid_base, np.full(nn, -1, np.int64)])
             perm = rng.permutation(hl.shape[1])
@@ -464,6 +651,13 @@ def make_events(geom: Geometry, n_tracks_per_event, workload=3, noise_frac=0.2,
         offs.append(off + base)
         ok = (pos_of[0] >= 0) & (pos_of[1] >= 0) & (pos_of[2] >= 0)
         sidx = np.nonzero(ok)[0]
+        if geom.has_disks:
+            # seeds grouped by eta region (of the seed's third hit) within the event, the
+            # order in which they are processed (Sec. 2)
+            p2 = pos_of[2, sidx] - base
+            zz = np.concatenate(ev_hits, axis=1)[2, p2].astype(np.float64)
+            rr = np.hypot(*np.concatenate(ev_hits, axis=1)[:2, p2].astype(np.float64))
+            sidx = sidx[np.argsort(eta_region(np.arcsinh(zz / rr)), kind="stable")]
         seeds.append(pos_of[:3, sidx].astype(np.int32))
         seed_ev.append(np.full(sidx.shape[0], e, np.int32))
         seed_tr.append(sidx.astype(np.int64) + tid_base)
@@ -482,6 +676,13 @@ def make_events(geom: Geometry, n_tracks_per_event, workload=3, noise_frac=0.2,
         track_hits=np.concatenate(track_hits, axis=1),
         n_tracks=np.asarray(n_tracks_per_event, dtype=np.int64),
     )
+
+
+def endcap_find_workload(n_tracks: int = 5000, n_events: int = 1, eta_max: float = 2.5, workload: int = 12):
+    """Events of n_tracks tracks each in the barrel-and-endcap geometry (x/X0 = 0.02 per
+    layer), |eta| < eta_max, 20% noise per layer, seeds grouped by eta region."""
+    geom = barrel_endcap(xX0=0.02)
+    return geom, make_events(geom, [n_tracks] * n_events, workload=workload, eta_max=eta_max)
 
 
 def find_workload(k: int = 3, n_tracks: int | None = None, n_events: int | None = None):

@@ -49,6 +49,25 @@ def project_to_surface(x, Cm, r, kB, cx=0.0, cy=0.0):
     return xp, Cp
 
 
+def project_to_plane(x, Cm, zd, kB):
+    """As project_to_surface for the plane z = zd of a disk: the arc to the plane is
+    s = (zd - z) tan(theta), and a z offset returns to the plane with a = e_z / cot."""
+    x = np.array(x, np.float64)
+    zd = np.broadcast_to(np.asarray(zd, np.float64), x[2].shape)
+    cot = 1 / np.tan(x[5])
+    s = (zd - x[2]) / cot
+    px, py, pz, ph = helix_point(x, s, kB)
+    xp = x.copy()
+    xp[0], xp[1], xp[2], xp[4] = px, py, zd, (ph + np.pi) % (2 * np.pi) - np.pi
+    n = x.shape[1]
+    z0 = np.zeros(n)
+    g = np.stack([np.cos(ph), np.sin(ph), cot, z0, -kB * x[3], z0])
+    a = np.stack([z0, z0, 1 / cot, z0, z0, z0])
+    Pi = np.eye(6)[:, :, None] - g[:, None, :] * a[None, :, :]
+    Cp = np.einsum('ijn,jkn,lkn->iln', Pi, Cm, Pi)
+    return xp, Cp
+
+
 def pulls(est, cov, truth, idx=(3, 4, 5)):
     """Pulls of state components; phi differences are wrapped."""
     out = {}
