@@ -20,9 +20,11 @@
  *     -0.299792458e-2 * B * kappa is the signed turning rate per unit transverse arc
  *     length.
  *   - Covariances are packed lower triangles: element (i >= j) at i * (i + 1) / 2 + j.
- *   - Layer L is an infinite cylinder of radius radius_cm[L]; its alignment
- *     align[L] = (dx, dy, dz, dphi) moves its axis to (dx, dy), shifts its hits by dz
- *     and rotates them by dphi about the axis.  Hits are given in the nominal frame.
+ *   - Layer L is an infinite cylinder of radius radius_cm[L] unless the geometry makes
+ *     it a disk or bounds it (kf_geometry, endcap fields); its alignment
+ *     align[L] = (dx, dy, dz, dphi) moves its axis to (dx, dy), shifts its hits (and a
+ *     disk's plane) by dz and rotates them by dphi about the axis.  Hits are given in
+ *     the nominal frame.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream) and
  *     never synchronise (kf_find_autotune excepted).  The library allocates no device memory per call: scratch
  *     space is the caller's `ws` of at least kf_workspace_size() bytes, 256-byte
@@ -73,7 +75,7 @@ extern "C" {
 typedef struct kf_geometry {
   int32_t n_layers;              /* 3 .. KF_MAX_LAYERS */
   float B_tesla;                 /* uniform field along +z; 0 allowed with external seeds */
-  float radius_cm[KF_MAX_LAYERS];  /* strictly increasing, > 0 */
+  float radius_cm[KF_MAX_LAYERS];  /* > 0, strictly increasing over the cylinders */
   float zhalf_cm[KF_MAX_LAYERS];   /* z range [-Z, Z] of the finder's z bins (> 0) */
   float sigma_rphi_cm;           /* hit resolution along the layer (r*phi) */
   float sigma_z_cm;              /* hit resolution along z */
@@ -82,6 +84,29 @@ typedef struct kf_geometry {
   int32_t n_phi_bins;            /* finder bins in phi over [-pi, pi): 1 .. 1024 */
   int32_t n_z_bins;              /* finder bins in z over [-Z, Z]: 1 .. 256; kf_find needs */
                                  /* n_phi_bins * n_z_bins <= KF_MAX_FIND_BINS */
+  /* Endcap disks and bounded barrel layers (Sec. 3: barrel and endcap regions); all
+   * zero (as a zero-initialised struct has them) keeps every layer an infinite
+   * cylinder.
+   *   disk_z_cm[L] != 0: layer L is the disk in the plane z = disk_z_cm[L] (+ its
+   *     alignment dz), active for disk_rmin_cm[L] <= rho <= disk_rmax_cm[L] about its
+   *     axis (0 <= rmin < rmax).  Its hit is measured as (z, rho * phi, rho): the
+   *     residual (z_m - z_p, rho_p * dphi, rho_m - rho_p) with variances (sigma_r^2,
+   *     sigma_rphi^2, sigma_z^2), H the projection along the state's tangent onto the
+   *     plane; its scattering path is x/X0 / |cos theta|.  radius_cm[L] and zhalf_cm[L]
+   *     are not used (they must still be > 0); the finder bins it in phi and in rho
+   *     over [rmin, rmax] (n_z_bins of them).
+   *   cyl_zmax_cm[L] > 0 (cylinders only): layer L is active for |z - dz| <= zmax.
+   * A disk or bounded cylinder (a bounded surface) is crossed where the track has a hit
+   * on it and passed over where it has none: no propagation, no material, no miss.
+   * The finder passes over a bounded surface that a candidate does not reach, or
+   * reaches outside its active area.  Layers 0-2 (the seed layers) must be cylinders,
+   * and cylinder radii must increase with L (disks may sit anywhere after layer 2).
+   * kf_fit_backward, kf_smooth, the material model and the parameterised field return
+   * KF_E_UNSUPPORTED for a geometry with bounded surfaces. */
+  float disk_z_cm[KF_MAX_LAYERS];
+  float disk_rmin_cm[KF_MAX_LAYERS];
+  float disk_rmax_cm[KF_MAX_LAYERS];
+  float cyl_zmax_cm[KF_MAX_LAYERS];
 } kf_geometry;
 
 typedef struct kf_ctx kf_ctx;
@@ -139,7 +164,8 @@ typedef struct kf_find_in {  /* n_hits < 2^28 - 2 */
 } kf_find_in;
 
 /* Finder output (slot k < keep, unused slots: hit_idx -2, counts 0, values 0):
- * n_cand [S]; hit_idx [keep][L][S] global hit index, -1 missing layer, -2 not reached;
+ * n_cand [S]; hit_idx [keep][L][S] global hit index, -1 missing layer, -2 not reached
+ * (or a bounded surface passed over);
  * n_hits, n_miss [keep][S]; chi2 [keep][S]; state [keep][6][S]; cov [keep][21][S];
  * status [keep][S]; rf_* (only with refit): the fit of the rank-0 candidate's hits,
  * seeded from its first three, as kf_fit_out.  A seed whose event is out of range, or
@@ -278,7 +304,9 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes);
  * crossing angle), and where the layer has a hit: S = H C H^T + V in the local
  * cylindrical frame (H: the state's tangent line projected onto the layer), S^-1 by an
  * equilibrated inverse with the FP64 fallback above, chi2, gain K = C H^T S^-1 and
- * the Joseph-form update.  Paper: Sec. 2 (Kalman filter on 6x6 covariances), Sec. 3
+ * the Joseph-form update.  A bounded surface (disk, bounded cylinder) without a hit
+ * is passed over; on a disk the crossing is that with its plane and the frame is the
+ * plane's (kf_geometry).  Paper: Sec. 2 (Kalman filter on 6x6 covariances), Sec. 3
  * (geometry, material), Sec. 5 (the fitting step). */
 int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* out,
            void* ws, size_t ws_bytes, void* stream);
@@ -292,7 +320,10 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
  * candidate compete, and the best `keep` branches per seed survive, ranked by (more
  * hits, smaller total chi2, parent rank, smaller hit index, missing-hit branch last).
  * Survivors with a hit are updated.  A candidate stops at its max_miss-th missing
- * layer or when propagation fails and is carried unchanged. */
+ * layer or when propagation fails and is carried unchanged.  On a bounded surface a
+ * candidate that does not reach it, or reaches it outside its active area, offers one
+ * branch that passes it over (unchanged, no miss) instead of a missing-hit branch; on a
+ * disk the window's second coordinate is rho (|drho| <= nsigma sqrt(S_rho)). */
 int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
             void* ws, size_t ws_bytes, void* stream);
 

@@ -32,6 +32,7 @@ KFA_HD constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j
 template <class T>
 struct Lay {
   T r, cx, cy, dz, cphi, sphi, xX0, pad, zs, zo;  // pad: unused here; zs, zo: the material map's z bins (smoother)
+  T endcap[5];  // endcap surface fields of the forward table: unused (cylinders only here)
 };
 
 template <class T>

@@ -29,7 +29,7 @@ struct kf_ctx {
   }
   int grid_device = -1;   // device the occupancy figures below were taken on
   int grid_cus = 0;       // compute units
-  int grid_per_cu[2][3] = {};  // find workgroups that fit on one compute unit ([plain, model][4, 6, 8 lanes])
+  int grid_per_cu[3][3] = {};  // find workgroups that fit on one compute unit ([variant][4, 6, 8 lanes])
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // timing hook (kf_ctx_set_launch_events)
   kf_dedup_cuts dcuts{0.05f, 2, 1, 0.1f, 0.15f, 0.03f, 0.02f, 0.5f, 0.5f, 0.1f, 0.01f, 0.02f};
   const float* mat_map = nullptr;  // material model (kf_ctx_set_material)
@@ -38,6 +38,19 @@ struct kf_ctx {
   float fr = 0.f, fz = 0.f;        // parameterised field (kf_ctx_set_field)
   // the detector model beyond one x/X0 per layer and a uniform field: the fit only
   bool material() const { return mat_map != nullptr || eloss > 0.f || fr != 0.f || fz != 0.f; }
+  bool bounded = false;            // the geometry has a disk or a bounded cylinder
+  // the kernel variant of kf_find and the refit (kfi::Variant)
+  int variant() const { return material() ? kfi::kModelV : (bounded ? kfi::kBoundedV : kfi::kPlain); }
+  kfi::Surfaces surfaces() const {
+    kfi::Surfaces s = {};
+    for (int l = 0; l < g.n_layers; ++l) {
+      s.disk_z[l] = g.disk_z_cm[l];
+      s.rmin[l] = g.disk_rmin_cm[l];
+      s.rmax[l] = g.disk_rmax_cm[l];
+      s.zmax[l] = g.cyl_zmax_cm[l];
+    }
+    return s;
+  }
 };
 
 namespace {
@@ -61,9 +74,19 @@ kfd::Model model_of(const kf_ctx* c) {
 bool valid_geometry(const kf_geometry* g) {
   if (!g) return false;
   if (g->n_layers < 3 || g->n_layers > KF_MAX_LAYERS) return false;
+  float last_r = 0.f;  // radius of the previous cylinder
   for (int l = 0; l < g->n_layers; ++l) {
-    if (!(g->radius_cm[l] > 0.f) || !(g->zhalf_cm[l] > 0.f)) return false;
-    if (l > 0 && !(g->radius_cm[l] > g->radius_cm[l - 1])) return false;
+    if (!(g->radius_cm[l] > 0.f) || !(g->zhalf_cm[l] > 0.f) || !isfinite(g->radius_cm[l]) ||
+        !isfinite(g->zhalf_cm[l]))
+      return false;
+    const float zd = g->disk_z_cm[l], r0 = g->disk_rmin_cm[l], r1 = g->disk_rmax_cm[l], zm = g->cyl_zmax_cm[l];
+    if (!isfinite(zd) || !isfinite(r0) || !isfinite(r1) || !(zm >= 0.f) || !isfinite(zm)) return false;
+    if (zd != 0.f) {  // a disk: after the seed layers, 0 <= rmin < rmax, no z bound
+      if (l < 3 || !(r0 >= 0.f) || !(r1 > r0) || zm != 0.f) return false;
+    } else {          // a cylinder: no radii of a disk, radius above the previous cylinder's
+      if (r0 != 0.f || r1 != 0.f || !(g->radius_cm[l] > last_r)) return false;
+      last_r = g->radius_cm[l];
+    }
   }
   if (!(g->sigma_rphi_cm > 0.f) || !(g->sigma_z_cm > 0.f) || !(g->sigma_r_cm > 0.f)) return false;
   if (!(g->mass_gev >= 0.f) || !isfinite(g->B_tesla)) return false;
@@ -173,17 +196,17 @@ int persistent_grid(kf_ctx* c, int nl, int lanes_per_seed, int* grid) {
   if (c->grid_device != dev) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return KF_E_HIP;
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < 3; ++m)
       for (int gi = 0; gi < 3; ++gi) {
         int per = 0;
-        if (kfi::find_max_blocks(nl, m == 1, gi == 0 ? 4 : (gi == 1 ? 6 : 8), &per) != hipSuccess) return KF_E_HIP;
+        if (kfi::find_max_blocks(nl, m, gi == 0 ? 4 : (gi == 1 ? 6 : 8), &per) != hipSuccess) return KF_E_HIP;
         c->grid_per_cu[m][gi] = per > 0 ? per : 1;
       }
     if (kfi::prepare_bin(KF_MAX_FIND_BINS) != hipSuccess) return KF_E_HIP;
     c->grid_cus = cus;
     c->grid_device = dev;
   }
-  const int have = c->grid_per_cu[c->material() ? 1 : 0][group_index(lanes_per_seed)];
+  const int have = c->grid_per_cu[c->variant()][group_index(lanes_per_seed)];
   const int want = c->fcfg.blocks_per_cu;
   *grid = c->grid_cus * (want > 0 && want < have ? want : have);
   return KF_OK;
@@ -207,6 +230,8 @@ int kf_ctx_create(const kf_geometry* geom, kf_ctx** ctx) {
   if (!c) return KF_E_INVALID;
   c->g = *geom;
   c->det_thr = 1e-2f;
+  for (int l = 0; l < geom->n_layers; ++l)
+    if (geom->disk_z_cm[l] != 0.f || geom->cyl_zmax_cm[l] > 0.f) c->bounded = true;
   *ctx = c;
   return KF_OK;
 }
@@ -231,6 +256,7 @@ int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop) {
 
 int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float eloss_gev_per_x0) {
   if (!ctx || !isfinite(eloss_gev_per_x0) || eloss_gev_per_x0 < 0.f) return KF_E_INVALID;
+  if (ctx->bounded && (xX0_map || eloss_gev_per_x0 > 0.f)) return KF_E_UNSUPPORTED;
   if (xX0_map) {
     if (nz < 1 || nz > KF_MAX_MAP_BINS) return KF_E_INVALID;
     for (int l = 0; l < ctx->g.n_layers; ++l)
@@ -245,6 +271,7 @@ int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float elo
 int kf_ctx_set_field(kf_ctx* ctx, float c_r, float c_z) {
   if (!ctx || !isfinite(c_r) || !isfinite(c_z)) return KF_E_INVALID;
   if (!(ctx->g.B_tesla != 0.f) && (c_r != 0.f || c_z != 0.f)) return KF_E_UNSUPPORTED;
+  if (ctx->bounded && (c_r != 0.f || c_z != 0.f)) return KF_E_UNSUPPORTED;
   ctx->fr = c_r;
   ctx->fz = c_z;
   return KF_OK;
@@ -354,6 +381,8 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   a.fr = ctx->fr;
   a.fz = ctx->fz;
   for (int l = 0; l < 32; ++l) a.zhalf[l] = l < ctx->g.n_layers ? ctx->g.zhalf_cm[l] : 0.f;
+  a.sf = ctx->surfaces();
+  a.bounded = ctx->bounded ? 1 : 0;
   a.state = out->state;
   a.cov = out->cov;
   a.chi2 = out->chi2;
@@ -401,8 +430,9 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base + w.layers);
   const float* align = params ? params->align : nullptr;
   const float* xX0 = params ? params->xX0 : nullptr;
+  const kfi::Surfaces sf = ctx->surfaces();
   if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st, ctx->g.zhalf_cm,
-                             ctx->mat_nz) != hipSuccess)
+                             ctx->mat_nz, &sf) != hipSuccess)
     return KF_E_HIP;
   kfi::BinArgs b;
   b.nl = ctx->g.n_layers;
@@ -456,6 +486,7 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   f.eloss = ctx->eloss;
   f.fr = ctx->fr;
   f.fz = ctx->fz;
+  f.bounded = ctx->bounded ? 1 : 0;
   f.counter = b.counter;
   f.n_cand = out->n_cand;
   f.hit_idx = out->hit_idx;
@@ -494,6 +525,7 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
     a.eloss = ctx->eloss;
     a.fr = ctx->fr;
     a.fz = ctx->fz;
+    a.bounded = ctx->bounded ? 1 : 0;  // (the surfaces are in the prepared layers)
     if (kfi::launch_refit(a, f.rpos, f.rmask, st) != hipSuccess) return KF_E_HIP;
   }
   return KF_OK;
@@ -626,7 +658,7 @@ int check_backward(const kf_ctx* ctx, const kf_fit_in* in, const kf_fit_out* fwd
   // the adjoint differentiates the per-layer material model and the field (with the
   // points each step and the seed take it at)
   if (ctx->mat_map != nullptr || ctx->eloss > 0.f) return KF_E_UNSUPPORTED;
-  if (!(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;
+  if (!(ctx->g.B_tesla != 0.f) || ctx->bounded) return KF_E_UNSUPPORTED;  // cylinders only
   if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
     return KF_E_INVALID;
   return KF_OK;
@@ -724,6 +756,7 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
               const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !in || !fwd || !out) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
+  if (ctx->bounded) return KF_E_UNSUPPORTED;  // the smoother is for cylinders only
   if (in->n == 0) return KF_OK;
   if (!in->hit_mask || !fwd->ndf || !fwd->status || !fwd->ckpt || !out->state || !out->cov || !out->first ||
       !out->last)

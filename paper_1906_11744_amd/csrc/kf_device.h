@@ -33,6 +33,10 @@ struct LayerK {
   float r, cx, cy, dz, cphi, sphi, xX0;
   float moved;  // 1 if the alignment moves the layer (any of cx, cy, dz, its rotation), else 0
   float zs, zo; // material map: fractional bin u = z * zs + zo of a z in the layer's frame
+  // Endcap geometry.  disk = 1: the plane z = zp (its nominal z plus dz), active for
+  // lo <= rho <= hi about the axis.  A cylinder with hi > 0 is active for |z - dz| <= hi.
+  // bounded = 1 for a disk or a bounded cylinder (passed over where a track has no hit).
+  float disk, bounded, zp, lo, hi;
 };
 
 // Constants of the hit model and the field.
@@ -213,15 +217,58 @@ __device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
   k.sp = sp * nrm;
 }
 
+// Propagation to the plane z = ly.zp of a disk: transverse arc s = (zp - z) tan(theta),
+// which must be positive (the plane ahead) with |u| = |omega s| < pi; then tau = tan(u/2)
+// and the displacement 2 sigma / (1 + tau^2) (t + tau n) with sigma = tau / omega =
+// (s/2) tan(u/2) / (u/2) (its series below |u/2| = 0.1, truncation < 1e-12), the same
+// Step as a cylinder crossing.
+__device__ __forceinline__ bool plane_crossing(const Trk& k, const LayerK& ly, float kB, Step& st) {
+  if (k.ct == 0.f) return false;
+  const float s = (ly.zp - k.x[2]) * k.st * rcp(k.ct);
+  if (!(s > 0.f)) return false;
+  const float u = -kB * k.x[3] * s;
+  if (!(fabsf(u) < kPi)) return false;
+  const float v = 0.5f * u;
+  float tq;  // tan(v) / v
+  if (fabsf(v) < 0.1f) {
+    const float v2 = v * v;
+    tq = fmaf(v2, fmaf(v2, fmaf(v2, fmaf(v2, 62.f / 2835.f, 17.f / 315.f), 2.f / 15.f), 1.f / 3.f), 1.f);
+  } else {
+    tq = tanf(v) / v;
+  }
+  const float tau = v * tq;
+  const float f = s * tq * rcp(fmaf(tau, tau, 1.f));
+  st.s = s;
+  st.u = u;
+  st.tau = tau;
+  st.dx = f * fmaf(-tau, k.sp, k.cp);
+  st.dy = f * fmaf(tau, k.cp, k.sp);
+  return true;
+}
+
+// Whether the crossing of a step lies in a bounded surface's active area: a disk's
+// radii, a bounded cylinder's |z - dz| <= hi (the same positions transport() reaches).
+__device__ __forceinline__ bool in_area(const Trk& k, const LayerK& ly, const Step& st, bool disk) {
+  if (disk) {
+    const float px = rel_pos(k.x[0], k.xl[0], ly.cx) + st.dx, py = rel_pos(k.x[1], k.xl[1], ly.cy) + st.dy;
+    const float rho = hsqrt(fmaf(px, px, py * py));
+    return rho >= ly.lo && rho <= ly.hi;
+  }
+  const float z = fmaf(st.s * rcp(k.st), k.ct, k.x[2]);
+  return fabsf(z - ly.dz) <= ly.hi;
+}
+
 // ---------------------------------------------------------------------------------
 // local cylindrical frame at the prediction and the measurement model
 // ---------------------------------------------------------------------------------
 struct Frame {
   float rho, rx, ry;  // radius about the layer axis and radial unit vector
-  float cosa;         // r_hat . t
+  float cosa;         // cosine of the angle between the track and the surface normal:
+                      // r_hat . t on a cylinder, cos(theta) on a disk
+  float cpsi;         // the same for the 3-D direction (the material's path is xX0 / cpsi)
 };
 
-__device__ __forceinline__ Frame frame_at(const Trk& k, const LayerK& ly) {
+__device__ __forceinline__ Frame frame_at(const Trk& k, const LayerK& ly, bool disk = false) {
   Frame f;
   const float ex = rel_pos(k.x[0], k.xl[0], ly.cx), ey = rel_pos(k.x[1], k.xl[1], ly.cy);
   const float r2 = fmaf(ex, ex, ey * ey);
@@ -229,18 +276,25 @@ __device__ __forceinline__ Frame frame_at(const Trk& k, const LayerK& ly) {
   f.rho = r2 * ir;
   f.rx = ex * ir;
   f.ry = ey * ir;
-  f.cosa = fmaf(f.rx, k.cp, f.ry * k.sp);
+  if (disk) {
+    f.cosa = k.ct;
+    f.cpsi = fabsf(k.ct);
+  } else {
+    f.cosa = fmaf(f.rx, k.cp, f.ry * k.sp);
+    f.cpsi = k.st * fabsf(f.cosa);
+  }
   return f;
 }
 
 // Highland multiple scattering of a thin layer, added to (kappa, phi, theta):
-// theta0^2 = (0.0136/(beta p))^2 x (1 + 0.038 ln x)^2, x = xX0 / (sin(theta) |cos alpha|),
+// theta0^2 = (0.0136/(beta p))^2 x (1 + 0.038 ln x)^2, x = xX0 / cpsi (a cylinder:
+// sin(theta) |cos alpha|; a disk: |cos theta|),
 // 1/(beta p) = |kappa| sin(theta) sqrt(1 + m^2 kappa^2 sin^2(theta)).
 __device__ __forceinline__ void add_scattering(Trk& k, const Frame& f, float xX0, float mass2) {
   const float kap = k.x[3];
   const float ks = kap * k.st;
   const float ks2 = ks * ks;
-  const float xe = xX0 * rcp(k.st * fabsf(f.cosa));
+  const float xe = xX0 * rcp(f.cpsi);
   const float lg = fmaf(0.038f, __logf(xe), 1.f);
   const float th2 = 0.0136f * 0.0136f * ks2 * fmaf(mass2, ks2, 1.f) * xe * lg * lg;
   const float rst = rcp(k.st);
@@ -278,7 +332,7 @@ __device__ __forceinline__ bool energy_loss(Trk& k, const Frame& f, float xX0, f
   const float kap = k.x[3];
   const float ks = fabsf(kap) * k.st;          // 1 / p
   const float p = rcp(ks);
-  const float c = eloss * xX0 * rcp(k.st * fabsf(f.cosa));
+  const float c = eloss * xX0 * rcp(f.cpsi);
   const float ib2 = fmaf(mass2, ks * ks, 1.f); // 1 / beta^2
   const float E = p * hsqrt(ib2);
   const float dE = c * ib2;
@@ -327,9 +381,12 @@ __device__ __forceinline__ bool apply_material(Trk& k, const Frame& f, const Lay
 // What a prediction needs for every hit of a layer: the projection rows
 // h1 = phi_hat - tan(alpha) r_hat, h2 = (-cot(theta)/cos(alpha) r_hat, 1), the
 // products HC (rows 1, 2 of H C) and S^-1 (S = H C H^T + V is block diagonal: its
-// radial entry is the regulariser alone).
+// radial entry is the regulariser alone).  On a disk the rows project onto the plane
+// along the tangent: h1 = (phi_hat, -(phi_hat . t) / cot(theta)), h2 = (r_hat,
+// -(r_hat . t) / cot(theta)) for (rho * phi, rho), and the regulariser's row is z.
 struct Pred {
   float h1x, h1y, h2x, h2y;
+  float h1z, h2z;  // z components on a disk (a cylinder's are 0 and 1)
   float HC1[6], HC2[6];
   float S11, S12, S22;
   float Si00, Si11, Si12, Si22;
@@ -337,25 +394,45 @@ struct Pred {
   double dSi11, dSi12, dSi22;
 };
 
-__device__ __forceinline__ void prepare(const Trk& k, const Frame& f, const Model& md, Pred& p) {
+__device__ __forceinline__ void prepare(const Trk& k, const Frame& f, const Model& md, Pred& p, bool disk = false) {
   const float fx = -f.ry, fy = f.rx;
-  const float ica = rcp(f.cosa);
-  const float tana = fmaf(fx, k.cp, fy * k.sp) * ica;
-  const float cot = k.ct * rcp(k.st);
-  p.h1x = fmaf(-tana, f.rx, fx);
-  p.h1y = fmaf(-tana, f.ry, fy);
-  const float g = -cot * ica;
-  p.h2x = g * f.rx;
-  p.h2y = g * f.ry;
   const float* C = k.C;
+  if (disk) {
+    const float icot = k.st * rcp(k.ct);
+    p.h1x = fx;
+    p.h1y = fy;
+    p.h1z = -fmaf(fx, k.cp, fy * k.sp) * icot;
+    p.h2x = f.rx;
+    p.h2y = f.ry;
+    p.h2z = -fmaf(f.rx, k.cp, f.ry * k.sp) * icot;
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    p.HC1[j] = fmaf(p.h1x, C[tri(0, j)], p.h1y * C[tri(1, j)]);
-    p.HC2[j] = fmaf(p.h2x, C[tri(0, j)], fmaf(p.h2y, C[tri(1, j)], C[tri(2, j)]));
+    for (int j = 0; j < 6; ++j) {
+      p.HC1[j] = fmaf(p.h1x, C[tri(0, j)], fmaf(p.h1y, C[tri(1, j)], p.h1z * C[tri(2, j)]));
+      p.HC2[j] = fmaf(p.h2x, C[tri(0, j)], fmaf(p.h2y, C[tri(1, j)], p.h2z * C[tri(2, j)]));
+    }
+    p.S11 = fmaf(p.HC1[0], p.h1x, fmaf(p.HC1[1], p.h1y, fmaf(p.HC1[2], p.h1z, md.v_rphi)));
+    p.S12 = fmaf(p.HC1[0], p.h2x, fmaf(p.HC1[1], p.h2y, p.HC1[2] * p.h2z));
+    p.S22 = fmaf(p.HC2[0], p.h2x, fmaf(p.HC2[1], p.h2y, fmaf(p.HC2[2], p.h2z, md.v_z)));
+  } else {
+    const float ica = rcp(f.cosa);
+    const float tana = fmaf(fx, k.cp, fy * k.sp) * ica;
+    const float cot = k.ct * rcp(k.st);
+    p.h1x = fmaf(-tana, f.rx, fx);
+    p.h1y = fmaf(-tana, f.ry, fy);
+    const float g = -cot * ica;
+    p.h2x = g * f.rx;
+    p.h2y = g * f.ry;
+    p.h1z = 0.f;
+    p.h2z = 1.f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      p.HC1[j] = fmaf(p.h1x, C[tri(0, j)], p.h1y * C[tri(1, j)]);
+      p.HC2[j] = fmaf(p.h2x, C[tri(0, j)], fmaf(p.h2y, C[tri(1, j)], C[tri(2, j)]));
+    }
+    p.S11 = fmaf(p.HC1[0], p.h1x, fmaf(p.HC1[1], p.h1y, md.v_rphi));
+    p.S12 = fmaf(p.HC1[0], p.h2x, fmaf(p.HC1[1], p.h2y, p.HC1[2]));
+    p.S22 = fmaf(p.HC2[0], p.h2x, fmaf(p.HC2[1], p.h2y, p.HC2[2] + md.v_z));
   }
-  p.S11 = fmaf(p.HC1[0], p.h1x, fmaf(p.HC1[1], p.h1y, md.v_rphi));
-  p.S12 = fmaf(p.HC1[0], p.h2x, fmaf(p.HC1[1], p.h2y, p.HC1[2]));
-  p.S22 = fmaf(p.HC2[0], p.h2x, fmaf(p.HC2[1], p.h2y, p.HC2[2] + md.v_z));
   // equilibrated inverse: S~ = D^-1/2 S D^-1/2 has unit diagonal; its radial row is
   // (1, 0, 0), so det S~ = 1 - rho12^2.
   p.Si00 = 1.f / md.v_r;
@@ -384,7 +461,8 @@ __device__ __forceinline__ void prepare(const Trk& k, const Frame& f, const Mode
 }
 
 // Residual of a placed hit m in the prediction's frame: (rho_m - rho_p,
-// rho_p * angle(r_hat, m - c), z_m - z_p), and its chi2.  Everything is formed from
+// rho_p * angle(r_hat, m - c), z_m - z_p) on a cylinder, (z_m - z_p, rho_p * angle,
+// rho_m - rho_p) on a disk, and its chi2.  Everything is formed from
 // the small offset d = m - p (p: the predicted point, hi + lo parts): since r_hat is
 // parallel to p - c, r_hat x (m - c) = r_hat x d, and
 // rho_m - rho_p = (2 rho_p r_hat.d + |d|^2) / (rho_m + rho_p).  Products of the
@@ -394,7 +472,7 @@ struct Resid {
 };
 
 __device__ __forceinline__ Resid residual(const Trk& k, const Frame& f, const LayerK& ly, const Pred& p, float mx,
-                                          float my, float mz) {
+                                          float my, float mz, bool disk = false) {
   (void)ly;
   Resid r;
   const float dx = (mx - k.x[0]) - k.xl[0], dy = (my - k.x[1]) - k.xl[1];
@@ -414,6 +492,11 @@ __device__ __forceinline__ Resid residual(const Trk& k, const Frame& f, const La
     r.r1 = f.rho * atan2f(cr, den);
   }
   r.r2 = (mz - k.x[2]) - k.xl[2];
+  if (disk) {  // the radial difference measures rho, the z difference is the regulariser's
+    const float t = r.r0;
+    r.r0 = r.r2;
+    r.r2 = t;
+  }
   if (!p.fp64) {
     const float q = fmaf(r.r1 * r.r1, p.Si11, fmaf(2.f * r.r1 * r.r2, p.Si12, r.r2 * r.r2 * p.Si22));
     r.chi2 = fmaf(r.r0 * r.r0, p.Si00, q);
@@ -430,7 +513,8 @@ __device__ __forceinline__ Resid residual(const Trk& k, const Frame& f, const La
 // x += K r, C <- (I - K H) C (I - K H)^T + K V K^T.  With M = (I - K H) C =
 // C - K (H C) and v_a = M h_a^T, C' = M - (v_1 k_1^T + v_2 k_2^T) + K V K^T, lower
 // triangle only.
-__device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model& md, float r1, float r2) {
+__device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model& md, float r1, float r2,
+                                             bool disk = false) {
   float K1[6], K2[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -459,8 +543,10 @@ __device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model&
   float w1[6], w2[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float v1 = fmaf(M[i][0], p.h1x, M[i][1] * p.h1y);
-    const float v2 = fmaf(M[i][0], p.h2x, fmaf(M[i][1], p.h2y, M[i][2]));
+    const float v1 = disk ? fmaf(M[i][0], p.h1x, fmaf(M[i][1], p.h1y, M[i][2] * p.h1z))
+                          : fmaf(M[i][0], p.h1x, M[i][1] * p.h1y);
+    const float v2 = disk ? fmaf(M[i][0], p.h2x, fmaf(M[i][1], p.h2y, M[i][2] * p.h2z))
+                          : fmaf(M[i][0], p.h2x, fmaf(M[i][1], p.h2y, M[i][2]));
     w1[i] = fmaf(md.v_rphi, K1[i], -v1);
     w2[i] = fmaf(md.v_z, K2[i], -v2);
   }

@@ -54,14 +54,19 @@ __global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
   beg = beg < 0 ? 0 : (beg > a.H ? a.H : beg);
   end = end < beg ? beg : (end > a.H ? a.H : end);
   const kfd::LayerK ly = a.layers[l];
+  // the bins' second coordinate: z over [-Z, Z] on a cylinder, rho over [lo, hi] on a disk
+  const bool disk = ly.disk != 0.f;
   const float Z = a.zhalf[l];
-  const float sphi = a.nphi / kfd::kTwoPi, sz = a.nz / (2.f * Z);
+  const float lo2 = disk ? ly.lo : -Z;
+  const float sphi = a.nphi / kfd::kTwoPi, sz = a.nz / (disk ? ly.hi - ly.lo : 2.f * Z);
   auto place_bin = [&](float hx, float hy, float hz, float4& rec) -> int {
     float mx, my, mz;
     kfd::place(ly, hx, hy, hz, mx, my, mz);
-    const float ph = atan2f(my - ly.cy, mx - ly.cx);
+    const float ex = mx - ly.cx, ey = my - ly.cy;
+    const float ph = atan2f(ey, ex);
     rec = make_float4(mx, my, mz, ph);
-    return bin_index(ph, -kfd::kPi, sphi, a.nphi) * a.nz + bin_index(mz, -Z, sz, a.nz);
+    const float c2 = disk ? sqrtf(fmaf(ex, ex, ey * ey)) : mz;
+    return bin_index(ph, -kfd::kPi, sphi, a.nphi) * a.nz + bin_index(c2, lo2, sz, a.nz);
   };
   // Each lane takes hits beg + tid + 256 k; kU of them are loaded before any is
   // binned, so that their loads are in flight together.  Out-of-slice slots read the
@@ -181,11 +186,15 @@ __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64
 
 }  // namespace
 
-// kModel: the detector model (material map, energy loss, parameterised field) in every
-// prediction, as the fit's model variant takes it; false: one x/X0 per layer and a
-// uniform field.
-template <bool kModel, int G>
+// kVar (a Variant): the detector model (material map, energy loss, parameterised field)
+// in every prediction, as the fit's model variant takes it; or bounded surfaces: a
+// candidate that misses a disk or a bounded cylinder (or meets it outside its active
+// area) passes it over, and a disk's window runs over (phi, rho) of its plane; or
+// neither.
+template <int kVar, int G>
 __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
+  constexpr bool kModel = kVar == kModelV;
+  constexpr bool kBounded = kVar == kBoundedV;
   constexpr int kTileSeeds = kWave / G;
   // at most G branches of one parent can survive (keep <= G), so a candidate keeps its
   // best G hit branches
@@ -310,6 +319,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
     // ---------------- layers 3 .. L-1 ----------------
     for (int l = 3; l < nl; ++l) {
       const kfd::LayerK ly = a.layers[l];
+      const bool disk = kBounded && ly.disk != 0.f;
       float bc[kList];
       int bi[kList];
 #pragma unroll
@@ -319,6 +329,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       }
       int nlist = 0;
       bool predicted = false;
+      bool passed = false;  // a bounded surface this live candidate passes over
       bool wide = false;
       // the prediction's window and what its chi2 needs (read by the wave for a wide
       // window)
@@ -326,7 +337,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       int blo = 0, bhi = -1, zlo = 0, zhi = -1;
       kfd::Frame f;
       f.rho = f.rx = f.ry = 0.f;
-      f.cosa = 1.f;
+      f.cosa = f.cpsi = 1.f;
       kfd::Pred p;
       p.Si00 = p.Si11 = p.Si12 = p.Si22 = 0.f;
       p.fp64 = false;
@@ -340,9 +351,15 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       auto consider = [&](const float4 rec, int hh, const kfd::Trk& kk, const kfd::Frame& ff, const kfd::Pred& pp,
                           float php, float zpp, float wph, float wzz, float cbase) __attribute__((always_inline)) {
         const float dphi = kfd::wrap_pi(rec.w - php);
-        const float dz = rec.z - zpp;
+        float dz;
+        if (disk) {  // the window's second coordinate: the hit's radius about the axis
+          const float ex = rec.x - ly.cx, ey = rec.y - ly.cy;
+          dz = sqrtf(fmaf(ex, ex, ey * ey)) - zpp;
+        } else {
+          dz = rec.z - zpp;
+        }
         if (!(fabsf(dphi) <= wph && fabsf(dz) <= wzz)) return;
-        const kfd::Resid r = kfd::residual(kk, ff, ly, pp, rec.x, rec.y, rec.z);
+        const kfd::Resid r = kfd::residual(kk, ff, ly, pp, rec.x, rec.y, rec.z, disk);
         if (!(r.chi2 < a.chi2_cut)) return;
         const float cc = cbase + r.chi2;
         bool prev_lt = true;
@@ -365,10 +382,20 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         const float kB =
             kModel ? kfd::field_kB(a.md.kB, a.fr, a.fz, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2]) : a.md.kB;
         kfd::Step stp;
-        bool reach = kfd::crossing(k, ly, kB, stp);
+        bool reach;
+        if (kBounded) {
+          reach = disk ? kfd::plane_crossing(k, ly, kB, stp) : kfd::crossing(k, ly, kB, stp);
+          if (ly.bounded != 0.f) {  // missed, or met outside the active area: passed over
+            if (reach) reach = kfd::in_area(k, ly, stp, disk);
+            passed = !reach;
+          }
+        } else {
+          reach = kfd::crossing(k, ly, kB, stp);
+        }
         if (reach) {
           kfd::transport(k, stp, kB);
-          f = kfd::frame_at(k, ly);
+          if (disk) k.x[2] = ly.zp;
+          f = kfd::frame_at(k, ly, disk);
           if (fabsf(f.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
           if (kModel)  // a particle that stops in the layer's material ends there, transported
             reach = kfd::apply_material(k, f, ly, a.mat_map ? a.mat_map + l * a.mat_nz : nullptr, a.mat_nz, a.eloss,
@@ -378,16 +405,17 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         }
         if (reach) {
           predicted = true;
-          kfd::prepare(k, f, a.md, p);
+          kfd::prepare(k, f, a.md, p, disk);
           phip = atan2f(f.ry, f.rx);
-          zp = k.x[2] + k.xl[2];
+          zp = disk ? f.rho : k.x[2] + k.xl[2];
           wphi = a.nsigma * sqrtf(p.S11) / f.rho;
           wz = a.nsigma * sqrtf(p.S22);
           const float Z = a.zhalf[l];
-          const float kz = a.nz / (2.f * Z);
+          const float lo2 = disk ? ly.lo : -Z;
+          const float kz = a.nz / (disk ? ly.hi - ly.lo : 2.f * Z);
           const float zq = fmaf(wz, 1e-4f, wz) + 1e-6f;
-          zlo = bin_index(zp - zq, -Z, kz, a.nz);
-          zhi = bin_index(zp + zq, -Z, kz, a.nz);
+          zlo = bin_index(zp - zq, lo2, kz, a.nz);
+          zhi = bin_index(zp + zq, lo2, kz, a.nz);
           const float wq = fmaf(wphi, 1e-4f, wphi) + 1e-6f;
           blo = 0;
           bhi = a.nphi - 1;
@@ -400,7 +428,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
             }
           }
           wide = (bhi - blo + 1) * (zhi - zlo + 1) > a.wide_bins;
-        } else {
+        } else if (!passed) {
           mode = TERM;
           st |= kfd::ST_PROP_FAIL;
         }
@@ -455,7 +483,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
           fc.rho = rdf(f.rho);
           fc.rx = rdf(f.rx);
           fc.ry = rdf(f.ry);
-          fc.cosa = 1.f;
+          fc.cosa = fc.cpsi = 1.f;
           kfd::Pred pc;
           pc.Si00 = rdf(p.Si00);
           pc.Si11 = rdf(p.Si11);
@@ -550,7 +578,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
           hk = K_MISS;
           hc = c2;
           hn = nh;
-        } else if (!other_used && mode == TERM) {
+        } else if (!other_used && (mode == TERM || passed)) {
           hk = K_CARRY;
           hc = c2;
           hn = nh;
@@ -597,10 +625,10 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       if (active) {
         if (slot < new_n) {
           if (my_kind == K_HIT) {
-            const kfd::Frame fu = kfd::frame_at(k, ly);
+            const kfd::Frame fu = kfd::frame_at(k, ly, disk);
             if (fabsf(fu.cosa) < 0.3f) st |= kfd::ST_NEAR_TANGENT;
             kfd::Pred pu;
-            kfd::prepare(k, fu, a.md, pu);
+            kfd::prepare(k, fu, a.md, pu, disk);
             if (pu.fp64) st |= kfd::ST_FP64;
             const float4 h = a.hpos[my_hit];  // placed on its layer by the binning
             const float mx = h.x, my = h.y, mz = h.z;
@@ -609,8 +637,8 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
               bpos[(l * 3 + 1) * kWave + lane] = my;
               bpos[(l * 3 + 2) * kWave + lane] = mz;
             }
-            const kfd::Resid r = kfd::residual(k, fu, ly, pu, mx, my, mz);
-            kfd::apply_update(k, pu, a.md, r.r1, r.r2);
+            const kfd::Resid r = kfd::residual(k, fu, ly, pu, mx, my, mz, disk);
+            kfd::apply_update(k, pu, a.md, r.r1, r.r2, disk);
             c2 = my_c;
             nh += 1;
           } else if (my_kind == K_MISS) {
@@ -713,46 +741,61 @@ size_t find_bp_bytes(int nl, int64_t grid) { return (size_t)grid * nl * kWave * 
 
 namespace {
 
-template <bool kModel, int G>
+template <int kVar, int G>
 hipError_t max_blocks(int nl, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel<kModel, G>, kWave,
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, find_kernel<kVar, G>, kWave,
                                                       find_lds_bytes(nl));
 }
 
-template <bool kModel, int G>
+template <int kVar>
+hipError_t max_blocks_group(int nl, int lanes_per_seed, int* blocks_per_cu) {
+  if (lanes_per_seed == 4) return max_blocks<kVar, 4>(nl, blocks_per_cu);
+  if (lanes_per_seed == 6) return max_blocks<kVar, 6>(nl, blocks_per_cu);
+  return max_blocks<kVar, 8>(nl, blocks_per_cu);
+}
+
+template <int kVar, int G>
 void launch_variant(const FindArgs& a, int grid, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const dim3 g((unsigned)grid), b(kWave);
   const size_t lds = find_lds_bytes(a.nl);
   if (ev_start && ev_stop)  // timing hook: the events bracket the kernel's own execution
-    hipExtLaunchKernelGGL((find_kernel<kModel, G>), g, b, lds, stream, ev_start, ev_stop, 0, a);
+    hipExtLaunchKernelGGL((find_kernel<kVar, G>), g, b, lds, stream, ev_start, ev_stop, 0, a);
   else
-    hipLaunchKernelGGL((find_kernel<kModel, G>), g, b, lds, stream, a);
+    hipLaunchKernelGGL((find_kernel<kVar, G>), g, b, lds, stream, a);
 }
 
-template <bool kModel>
+template <int kVar>
 hipError_t launch_group(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
-  if (lanes_per_seed == 4) launch_variant<kModel, 4>(a, grid, stream, ev_start, ev_stop);
-  else if (lanes_per_seed == 6) launch_variant<kModel, 6>(a, grid, stream, ev_start, ev_stop);
-  else launch_variant<kModel, 8>(a, grid, stream, ev_start, ev_stop);
+  if (lanes_per_seed == 4) launch_variant<kVar, 4>(a, grid, stream, ev_start, ev_stop);
+  else if (lanes_per_seed == 6) launch_variant<kVar, 6>(a, grid, stream, ev_start, ev_stop);
+  else launch_variant<kVar, 8>(a, grid, stream, ev_start, ev_stop);
   return hipGetLastError();
+}
+
+// The variant of a launch (the API refuses the detector model with bounded surfaces).
+int find_variant(const FindArgs& a) {
+  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f) return kModelV;
+  return a.bounded ? kBoundedV : kPlain;
 }
 
 }  // namespace
 
-hipError_t find_max_blocks(int nl, bool model, int lanes_per_seed, int* blocks_per_cu) {
-  switch (lanes_per_seed) {
-    case 4: return model ? max_blocks<true, 4>(nl, blocks_per_cu) : max_blocks<false, 4>(nl, blocks_per_cu);
-    case 6: return model ? max_blocks<true, 6>(nl, blocks_per_cu) : max_blocks<false, 6>(nl, blocks_per_cu);
-    default: return model ? max_blocks<true, 8>(nl, blocks_per_cu) : max_blocks<false, 8>(nl, blocks_per_cu);
+hipError_t find_max_blocks(int nl, int variant, int lanes_per_seed, int* blocks_per_cu) {
+  switch (variant) {
+    case kModelV: return max_blocks_group<kModelV>(nl, lanes_per_seed, blocks_per_cu);
+    case kBoundedV: return max_blocks_group<kBoundedV>(nl, lanes_per_seed, blocks_per_cu);
+    default: return max_blocks_group<kPlain>(nl, lanes_per_seed, blocks_per_cu);
   }
 }
 
 hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream, hipEvent_t ev_start,
                        hipEvent_t ev_stop) {
-  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
-    return launch_group<true>(a, lanes_per_seed, grid, stream, ev_start, ev_stop);
-  return launch_group<false>(a, lanes_per_seed, grid, stream, ev_start, ev_stop);
+  switch (find_variant(a)) {
+    case kModelV: return launch_group<kModelV>(a, lanes_per_seed, grid, stream, ev_start, ev_stop);
+    case kBoundedV: return launch_group<kBoundedV>(a, lanes_per_seed, grid, stream, ev_start, ev_stop);
+    default: return launch_group<kPlain>(a, lanes_per_seed, grid, stream, ev_start, ev_stop);
+  }
 }
 
 }  // namespace kfi

@@ -8,11 +8,13 @@ struct Radii {
 };
 
 // Constants of layer l: radius, alignment (centre shift, z shift, cos/sin of the
-// rotation), material.  align / xX0 may be null (all zero); zhalf / nz place the
-// bins of a material map (nz = 0: none).
+// rotation), material, endcap surface.  align / xX0 may be null (all zero); zhalf / nz
+// place the bins of a material map (nz = 0: none); zd, rmin, rmax, zmax: the layer's
+// Surfaces entries (all 0: an infinite cylinder).
 __device__ __forceinline__ kfd::LayerK make_layer(int l, const float* radius, const float* __restrict__ align,
                                                   const float* __restrict__ xX0, const float* zhalf = nullptr,
-                                                  int nz = 0) {
+                                                  int nz = 0, float zd = 0.f, float rmin = 0.f, float rmax = 0.f,
+                                                  float zmax = 0.f) {
   kfd::LayerK k;
   k.zs = (nz > 1) ? (float)nz / (2.f * zhalf[l]) : 0.f;
   k.zo = 0.5f * (float)nz - 0.5f;
@@ -24,25 +26,33 @@ __device__ __forceinline__ kfd::LayerK make_layer(int l, const float* radius, co
   sincosf(dphi, &k.sphi, &k.cphi);
   k.xX0 = xX0 ? xX0[l] : 0.f;
   k.moved = (k.cx != 0.f || k.cy != 0.f || k.dz != 0.f || dphi != 0.f) ? 1.f : 0.f;
+  k.disk = zd != 0.f ? 1.f : 0.f;
+  k.bounded = (zd != 0.f || zmax > 0.f) ? 1.f : 0.f;
+  k.zp = zd != 0.f ? zd + k.dz : 0.f;
+  k.lo = zd != 0.f ? rmin : 0.f;
+  k.hi = zd != 0.f ? rmax : zmax;
   return k;
 }
 
 __global__ void layer_prep_kernel(int nl, Radii rad, Radii zh, int map_nz, const float* __restrict__ align,
-                                  const float* __restrict__ xX0, kfd::LayerK* __restrict__ out) {
+                                  const float* __restrict__ xX0, kfd::LayerK* __restrict__ out, Surfaces sf) {
   const int l = threadIdx.x;
   if (l >= nl) return;
-  out[l] = make_layer(l, rad.r, align, xX0, zh.r, map_nz);
+  out[l] = make_layer(l, rad.r, align, xX0, zh.r, map_nz, sf.disk_z[l], sf.rmin[l], sf.rmax[l], sf.zmax[l]);
 }
 
 hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
-                             kfd::LayerK* out, hipStream_t stream, const float* zhalf_host, int map_nz) {
+                             kfd::LayerK* out, hipStream_t stream, const float* zhalf_host, int map_nz,
+                             const Surfaces* sf) {
   Radii rad, zh;
   for (int l = 0; l < 32; ++l) {
     rad.r[l] = l < nl ? radius_host[l] : 0.f;
     zh.r[l] = (zhalf_host && l < nl) ? zhalf_host[l] : 1.f;
   }
   if (!zhalf_host) map_nz = 0;
-  hipLaunchKernelGGL(layer_prep_kernel, dim3(1), dim3(32), 0, stream, nl, rad, zh, map_nz, align, xX0, out);
+  const Surfaces none = {};
+  hipLaunchKernelGGL(layer_prep_kernel, dim3(1), dim3(32), 0, stream, nl, rad, zh, map_nz, align, xX0, out,
+                     sf ? *sf : none);
   return hipGetLastError();
 }
 
@@ -80,9 +90,13 @@ struct PlacedHits {
   }
 };
 
-template <bool kCkpt, bool kModel, class Src>
+// kVar: a Variant.  Bounded surfaces: a layer without a hit is passed over, a disk is
+// reached on its plane and measured in its frame.
+template <bool kCkpt, int kVar, class Src>
 __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __restrict__ lays, int64_t i,
                                         uint32_t mask, const Src& src) {
+  constexpr bool kModel = kVar == kModelV;
+  constexpr bool kBounded = kVar == kBoundedV;
   const int64_t n = a.n;
   const uint32_t need = a.seed_from_hits ? 7u : 1u;
   uint32_t status = 0;
@@ -127,18 +141,24 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
     if (last > a.nl - 1) last = a.nl - 1;
     for (int l = 0; l <= last; ++l) {
       const kfd::LayerK ly = lays[l];
+      if (kBounded && ly.bounded != 0.f && !((mask >> l) & 1u)) {  // passed over
+        if (kCkpt) store_ckpt(a.ckpt, n, i, l, k);
+        continue;
+      }
+      const bool disk = kBounded && ly.disk != 0.f;  // (layer 0 is a cylinder)
       if (l > 0) {
         // the step is the helix of the field at its starting point
         const float kB = kModel ? kfd::field_kB(a.md.kB, a.fr, a.fz, k.x[0] + k.xl[0], k.x[1] + k.xl[1], k.x[2])
                                 : a.md.kB;
         kfd::Step st;
-        if (!kfd::crossing(k, ly, kB, st)) {
+        if (!(disk ? kfd::plane_crossing(k, ly, kB, st) : kfd::crossing(k, ly, kB, st))) {
           status |= kfd::ST_PROP_FAIL;
           break;
         }
         kfd::transport(k, st, kB);
+        if (disk) k.x[2] = ly.zp;  // on the plane exactly
       }
-      const kfd::Frame f = kfd::frame_at(k, ly);
+      const kfd::Frame f = kfd::frame_at(k, ly, disk);
       if (fabsf(f.cosa) < 0.3f) status |= kfd::ST_NEAR_TANGENT;
       if (kModel) {  // the material map at the crossing's z and the energy loss
         if (l > 0) {
@@ -156,12 +176,12 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       }
       if ((mask >> l) & 1u) {
         kfd::Pred p;
-        kfd::prepare(k, f, a.md, p);
+        kfd::prepare(k, f, a.md, p, disk);
         if (p.fp64) status |= kfd::ST_FP64;
         float mx, my, mz;
         hit(l, mx, my, mz);
-        const kfd::Resid r = kfd::residual(k, f, ly, p, mx, my, mz);
-        kfd::apply_update(k, p, a.md, r.r1, r.r2);
+        const kfd::Resid r = kfd::residual(k, f, ly, p, mx, my, mz, disk);
+        kfd::apply_update(k, p, a.md, r.r1, r.r2, disk);
         chi2 += r.chi2;
         ++nh;
       }
@@ -180,67 +200,88 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
   a.status[i] = status;
 }
 
-// kCkpt: also store the state and covariance after every processed layer (a.ckpt).
-// kModel: the detector model (material map, energy loss, parameterised field) instead of
-// one x/X0 per layer and a uniform field.
+// kCkpt: also store the state and covariance after every processed layer (a.ckpt; a
+// layer passed over stores the state unchanged).  kVar: a Variant, the detector model
+// (material map, energy loss, parameterised field) or bounded surfaces instead of
+// infinite cylinders with one x/X0 per layer and a uniform field.
 // The workgroup first builds the layer constants in LDS (one lane per layer), so that
 // one kf_fit call is one kernel.  Five waves per SIMD (at most 96 VGPRs; the compiler
 // spills two 8-byte values of the FP64-fallback path) hide more latency than the four
 // that 112 VGPRs allow: 3% faster on the 1e6-track fit; six would spill ~30 registers.
-template <bool kCkpt, bool kModel>
-__global__ __launch_bounds__(256, 5) void fit_kernel(FitArgs a) {
+// The bounded-surface variant carries both surface types' algebra and takes four.
+template <bool kCkpt, int kVar>
+__global__ __launch_bounds__(256, kVar == kBoundedV ? 4 : 5) void fit_kernel(FitArgs a) {
   __shared__ kfd::LayerK lays[32];
-  if ((int)threadIdx.x < a.nl)
-    lays[threadIdx.x] = make_layer(threadIdx.x, a.radius, a.align, a.xX0, a.zhalf, kModel ? a.mat_nz : 0);
+  const int t = threadIdx.x;
+  if (t < a.nl) {
+    if (kVar == kBoundedV)
+      lays[t] = make_layer(t, a.radius, a.align, a.xX0, a.zhalf, 0, a.sf.disk_z[t], a.sf.rmin[t], a.sf.rmax[t],
+                           a.sf.zmax[t]);
+    else
+      lays[t] = make_layer(t, a.radius, a.align, a.xX0, a.zhalf, kVar == kModelV ? a.mat_nz : 0);
+  }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   SoaHits src{a.hits, a.mask};
-  fit_one<kCkpt, kModel>(a, lays, i, a.mask[i], src);
+  fit_one<kCkpt, kVar>(a, lays, i, a.mask[i], src);
 }
 
 // Fit of each seed's best finder candidate from its own hits, which the finder left
 // placed on their layers in pos [L][3][n] with their layers in mask [n]: one coalesced
 // 4-byte load per coordinate instead of a gather from the event's hit arrays.
-template <bool kModel>
+template <int kVar>
 __global__ __launch_bounds__(256) void refit_kernel(FitArgs a, const float* __restrict__ pos,
                                                     const uint32_t* __restrict__ mask) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   PlacedHits src{pos};
-  fit_one<false, kModel>(a, a.layers, i, mask[i], src);
+  fit_one<false, kVar>(a, a.layers, i, mask[i], src);
 }
+
+namespace {
+// The variant of a launch (the API refuses the detector model with bounded surfaces).
+int variant_of(const FitArgs& a) {
+  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f) return kModelV;
+  return a.bounded ? kBoundedV : kPlain;
+}
+}  // namespace
 
 hipError_t launch_refit(const FitArgs& a, const float* pos, const uint32_t* mask, hipStream_t stream) {
   const int bs = 256;
-  const int64_t nb = (a.n + bs - 1) / bs;
-  if (a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f)
-    hipLaunchKernelGGL(refit_kernel<true>, dim3((unsigned)nb), dim3(bs), 0, stream, a, pos, mask);
-  else
-    hipLaunchKernelGGL(refit_kernel<false>, dim3((unsigned)nb), dim3(bs), 0, stream, a, pos, mask);
+  const dim3 g((unsigned)((a.n + bs - 1) / bs)), b(bs);
+  switch (variant_of(a)) {
+    case kModelV: hipLaunchKernelGGL(refit_kernel<kModelV>, g, b, 0, stream, a, pos, mask); break;
+    case kBoundedV: hipLaunchKernelGGL(refit_kernel<kBoundedV>, g, b, 0, stream, a, pos, mask); break;
+    default: hipLaunchKernelGGL(refit_kernel<kPlain>, g, b, 0, stream, a, pos, mask); break;
+  }
   return hipGetLastError();
 }
 
-template <bool kCkpt, bool kModel>
+template <bool kCkpt, int kVar>
 void launch_fit_variant(const FitArgs& a, unsigned nb, unsigned bs, hipStream_t stream, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
   if (ev_start && ev_stop)  // timing hook: the events bracket the kernel's own execution
-    hipExtLaunchKernelGGL((fit_kernel<kCkpt, kModel>), dim3(nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
+    hipExtLaunchKernelGGL((fit_kernel<kCkpt, kVar>), dim3(nb), dim3(bs), 0, stream, ev_start, ev_stop, 0, a);
   else
-    hipLaunchKernelGGL((fit_kernel<kCkpt, kModel>), dim3(nb), dim3(bs), 0, stream, a);
+    hipLaunchKernelGGL((fit_kernel<kCkpt, kVar>), dim3(nb), dim3(bs), 0, stream, a);
+}
+
+template <bool kCkpt>
+void launch_fit_ckpt(const FitArgs& a, unsigned nb, unsigned bs, hipStream_t stream, hipEvent_t ev_start,
+                     hipEvent_t ev_stop) {
+  switch (variant_of(a)) {
+    case kModelV: launch_fit_variant<kCkpt, kModelV>(a, nb, bs, stream, ev_start, ev_stop); break;
+    case kBoundedV: launch_fit_variant<kCkpt, kBoundedV>(a, nb, bs, stream, ev_start, ev_stop); break;
+    default: launch_fit_variant<kCkpt, kPlain>(a, nb, bs, stream, ev_start, ev_stop); break;
+  }
 }
 
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const unsigned bs = 256;
   const unsigned nb = (unsigned)((a.n + bs - 1) / bs);
-  const bool mat = a.mat_map != nullptr || a.eloss > 0.f || a.fr != 0.f || a.fz != 0.f;
-  if (a.ckpt) {
-    if (mat) launch_fit_variant<true, true>(a, nb, bs, stream, ev_start, ev_stop);
-    else launch_fit_variant<true, false>(a, nb, bs, stream, ev_start, ev_stop);
-  } else {
-    if (mat) launch_fit_variant<false, true>(a, nb, bs, stream, ev_start, ev_stop);
-    else launch_fit_variant<false, false>(a, nb, bs, stream, ev_start, ev_stop);
-  }
+  if (a.ckpt) launch_fit_ckpt<true>(a, nb, bs, stream, ev_start, ev_stop);
+  else launch_fit_ckpt<false>(a, nb, bs, stream, ev_start, ev_stop);
   return hipGetLastError();
 }
 

@@ -10,6 +10,17 @@
 
 namespace kfi {
 
+// Endcap surfaces per layer (kf_geometry's fields; all zero: every layer an infinite
+// cylinder): a disk's plane z (0: a cylinder) and radii, a cylinder's |z| bound (0: none).
+struct Surfaces {
+  float disk_z[32], rmin[32], rmax[32], zmax[32];
+};
+
+// Kernel variants: one x/X0 per layer and a uniform field; the detector model (material
+// map, energy loss, parameterised field); bounded surfaces (disks, bounded cylinders)
+// with one x/X0 per layer and a uniform field.
+enum Variant : int { kPlain = 0, kModelV = 1, kBoundedV = 2 };
+
 // Everything a fit launch needs, by value.
 struct FitArgs {
   int64_t n;
@@ -33,6 +44,9 @@ struct FitArgs {
   float zhalf[32] = {};
   // parameterised field B_z(r, z) = B (1 + fr r^2 + fz z^2) (fit only; 0, 0: uniform)
   float fr = 0.f, fz = 0.f;
+  // endcap surfaces (fit only: the refit reads them from the prepared layers)
+  Surfaces sf = {};
+  int32_t bounded = 0;  // the geometry has a disk or a bounded cylinder
   float* state;
   float* cov;
   float* chi2;
@@ -77,6 +91,7 @@ struct FindArgs {
   int32_t mat_nz = 0;
   float eloss = 0.f;
   float fr = 0.f, fz = 0.f;
+  int32_t bounded = 0;  // the geometry has a disk or a bounded cylinder
   int32_t* counter;
   int32_t* bp;       // [grid][nl][64] backpointers of each workgroup's current tile
   // with a refit: placed hit positions [grid][nl][3][64] of each workgroup's current tile
@@ -187,17 +202,18 @@ size_t find_lds_bytes(int nl);
 int find_tile_seeds(int lanes_per_seed);        // seeds per find tile (one workgroup)
 constexpr int kMaxFindGrid = 4096;              // persistent find workgroups at most
 size_t find_bp_bytes(int nl, int64_t grid);     // backpointer buffer of `grid` workgroups
-// model: the finder variant with the detector model (material map, energy loss, field);
-// lanes_per_seed: 4, 6 or 8 lanes hold one seed's candidates
-hipError_t find_max_blocks(int nl, bool model, int lanes_per_seed, int* blocks_per_cu);
+// variant: a Variant (plain, detector model, bounded surfaces); lanes_per_seed: 4, 6 or
+// 8 lanes hold one seed's candidates
+hipError_t find_max_blocks(int nl, int variant, int lanes_per_seed, int* blocks_per_cu);
 hipError_t launch_find(const FindArgs& a, int lanes_per_seed, int grid, hipStream_t stream,
                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Writes the per-layer constants (radius, alignment, its cos/sin, material; with
-// zhalf_host and map_nz > 0 also the placement of the material map's z bins).
+// zhalf_host and map_nz > 0 also the placement of the material map's z bins; with sf
+// the endcap surfaces).
 hipError_t launch_layer_prep(int nl, const float* radius_host, const float* align, const float* xX0,
                              kfd::LayerK* out, hipStream_t stream, const float* zhalf_host = nullptr,
-                             int map_nz = 0);
+                             int map_nz = 0, const Surfaces* sf = nullptr);
 hipError_t launch_fit(const FitArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
                       hipEvent_t ev_stop = nullptr);
 // Fit of each seed's rank-0 finder candidate from the placed hits the finder recorded:

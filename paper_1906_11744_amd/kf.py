@@ -37,7 +37,9 @@ class Geometry(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("B_tesla", C.c_float),
                 ("radius_cm", C.c_float * KF_MAX_LAYERS), ("zhalf_cm", C.c_float * KF_MAX_LAYERS),
                 ("sigma_rphi_cm", C.c_float), ("sigma_z_cm", C.c_float), ("sigma_r_cm", C.c_float),
-                ("mass_gev", C.c_float), ("n_phi_bins", C.c_int32), ("n_z_bins", C.c_int32)]
+                ("mass_gev", C.c_float), ("n_phi_bins", C.c_int32), ("n_z_bins", C.c_int32),
+                ("disk_z_cm", C.c_float * KF_MAX_LAYERS), ("disk_rmin_cm", C.c_float * KF_MAX_LAYERS),
+                ("disk_rmax_cm", C.c_float * KF_MAX_LAYERS), ("cyl_zmax_cm", C.c_float * KF_MAX_LAYERS)]
 
 
 class LayerParams(C.Structure):
@@ -165,7 +167,8 @@ FIND_CONFIG_KEYS = ("wide_window_bins", "blocks_per_cu", "use_graph", "n_phi_bin
 
 class Context:
     """A kf_ctx for one detector geometry (anything with the attributes of
-    synth.Geometry, or keyword arguments)."""
+    synth.Geometry, or keyword arguments; disk_z, disk_rmin, disk_rmax and cyl_zmax
+    describe endcap disks and bounded cylinders, all zero when absent)."""
 
     def __init__(self, geom=None, **kw):
         g = Geometry()
@@ -174,6 +177,9 @@ class Context:
             for k in ("radius", "zhalf", "B", "sigma_rphi", "sigma_z", "sigma_r", "mass", "n_phi_bins",
                       "n_z_bins"):
                 src.setdefault(k, getattr(geom, k))
+            for k in ("disk_z", "disk_rmin", "disk_rmax", "cyl_zmax"):
+                if getattr(geom, k, None) is not None:
+                    src.setdefault(k, getattr(geom, k))
         radius = [float(v) for v in src["radius"]]
         zhalf = [float(v) for v in src["zhalf"]]
         g.n_layers = len(radius)
@@ -187,6 +193,9 @@ class Context:
         g.mass_gev = float(src.get("mass", 0.13957039))
         g.n_phi_bins = int(src.get("n_phi_bins", 128))
         g.n_z_bins = int(src.get("n_z_bins", 32))
+        for k in ("disk_z", "disk_rmin", "disk_rmax", "cyl_zmax"):
+            for i, v in enumerate(src.get(k, ())):
+                getattr(g, k + "_cm")[i] = float(v)
         self.geometry = g
         self.n_layers = g.n_layers
         h = C.c_void_p()

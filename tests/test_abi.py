@@ -259,3 +259,47 @@ def test_static_backward_rejects_requests_beyond_its_scratch():
     assert rc == -5 and b"static scratch" in lib.kf_strerror(rc)
     # argument errors come first, as for kf_fit_backward
     assert lib.kf_fit_backward_static(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), fake, None, fake, None) == -1
+
+
+def test_endcap_geometry_validation_and_the_calls_it_excludes():
+    """Disks and bounded cylinders: the seed layers must be cylinders, a disk needs
+    0 <= rmin < rmax and no z bound, cylinder radii increase over the cylinders only;
+    with bounded surfaces the material model, the field, the smoother and the adjoint
+    refuse before launching, while kf_find goes on to its own checks."""
+    kf, lib = _lib()
+    geom = synth.barrel_endcap(xX0=0.02)
+    ctx = kf.Context(geom)
+    assert ctx.n_layers == 31
+    for field, l, v in [("disk_z", 1, 50.0),          # a disk among the seed layers
+                        ("disk_rmin", 20, 120.0),     # rmin above rmax
+                        ("disk_rmin", 20, -1.0),
+                        ("cyl_zmax", 20, 10.0),       # a z bound on a disk
+                        ("disk_rmax", 3, 10.0),       # disk radii on a cylinder
+                        ("cyl_zmax", 3, -5.0)]:
+        bad = synth.barrel_endcap(xX0=0.02)
+        getattr(bad, field)[l] = v
+        with pytest.raises(kf.KfError) as e:
+            kf.Context(bad)
+        assert e.value.code == -1, (field, l)
+    bad = synth.barrel_endcap(xX0=0.02)
+    bad.radius[16] = bad.radius[15]       # two cylinders at one radius
+    with pytest.raises(kf.KfError):
+        kf.Context(bad)
+    fake = C.c_void_p(0x1000)   # never dereferenced
+    assert lib.kf_ctx_set_material(ctx._h, fake, 16, C.c_float(0.0)) == -2
+    assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0363)) == -2
+    assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
+    assert lib.kf_ctx_set_field(ctx._h, C.c_float(-1e-6), C.c_float(0.0)) == -2
+    assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(0.0)) == 0
+    p = kf.LayerParams()
+    fit_in = kf.FitIn(10, fake, fake, None, None, 1)
+    fit_out = kf.FitOut(fake, fake, fake, fake, fake, fake)
+    so = kf.SmoothOut(fake, fake, fake, fake)
+    assert lib.kf_smooth(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), C.byref(so), None, 0, None) == -2
+    assert lib.kf_fit_backward(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), fake, fake, fake,
+                               None, 0, None) == -2
+    assert lib.kf_fit_backward_static(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), fake, fake, fake,
+                                      None) == -2
+    fin = kf.FindIn(1, fake, 100, fake, 10, fake, fake, 30.0, 3.0, 6, 3, 0)
+    fo = kf.FindOut(*([fake] * 13))
+    assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -3

@@ -105,7 +105,9 @@ def first_divergence(geom, ev, seeds, opts):
     run = {k: v for k, v in opts.items() if k in ("keep", "max_miss", "chi2_cut", "nsigma", "field")}
     for L in range(3, geom.n_layers):
         n = L + 1
-        gt = dataclasses.replace(geom, radius=geom.radius[:n], zhalf=geom.zhalf[:n], xX0=geom.xX0[:n])
+        gt = dataclasses.replace(geom, radius=geom.radius[:n], zhalf=geom.zhalf[:n], xX0=geom.xX0[:n],
+                                 disk_z=geom.disk_z[:n], disk_rmin=geom.disk_rmin[:n], disk_rmax=geom.disk_rmax[:n],
+                                 cyl_zmax=geom.cyl_zmax[:n])
         if opts.get("material") is not None:
             xmap, eloss = opts["material"]
             run["material"] = (None if xmap is None else np.ascontiguousarray(np.asarray(xmap)[:n]), eloss)
