@@ -60,6 +60,7 @@ struct Trk {
   float C[21];
   float cp, sp; // cos, sin of phi
   float ct, st; // cos, sin of theta
+  float rst;    // 1 / sin(theta), kept with them (every step needs it; one reciprocal per update)
 };
 
 // x + d as a compensated sum (Knuth's two-sum; the rounding error goes to lo).  lo is
@@ -86,6 +87,7 @@ __device__ __forceinline__ float wrap_pi(float a) {
 __device__ __forceinline__ void init_trig(Trk& t) {
   sincosf(t.x[4], &t.sp, &t.cp);
   sincosf(t.x[5], &t.st, &t.ct);
+  t.rst = rcp(t.st);
 }
 
 // Rotate (c, s) = (cos a, sin a) to a + d; small d by its Taylor series, otherwise
@@ -117,6 +119,7 @@ __device__ __forceinline__ void rotate_small(float& c, float& s, float d, float 
 struct Step {
   float s;      // transverse arc
   float tau;    // tan(u/2)
+  float inv1;   // 1 / (1 + tau^2)
   float dx, dy; // transverse displacement
   float u;      // turning angle
 };
@@ -144,7 +147,8 @@ __device__ __forceinline__ bool crossing(const Trk& k, const LayerK& ly, float k
   } else {
     q = atanf(tau) / tau;
   }
-  const float f = 2.f * sig * rcp(1.f + tau2);
+  st.inv1 = rcp(1.f + tau2);
+  const float f = 2.f * sig * st.inv1;
   st.s = 2.f * sig * q;
   st.u = 2.f * tau * q;
   st.tau = tau;
@@ -159,7 +163,7 @@ __device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
   const float s = st.s, u = st.u;
   float F1, F2;  // d(displacement)/d(omega) = s^2 (F1 t + F2 n)
   const float tau2 = st.tau * st.tau;
-  const float inv1 = rcp(1.f + tau2);
+  const float inv1 = st.inv1;
   const float cu = (1.f - tau2) * inv1, su = 2.f * st.tau * inv1;
   if (fabsf(u) < 0.3f) {
     const float u2 = u * u;
@@ -171,7 +175,7 @@ __device__ __forceinline__ void transport(Trk& k, const Step& st, float kB) {
     F2 = fmaf(u, su, -2.f * tau2 * inv1) * iu2;
   }
   const float ks2 = -kB * s * s;
-  const float rst = rcp(k.st);
+  const float rst = k.rst;
   const float a04 = -st.dy, a14 = st.dx;
   const float a03 = ks2 * fmaf(F1, k.cp, -F2 * k.sp);
   const float a13 = ks2 * fmaf(F1, k.sp, F2 * k.cp);
@@ -237,7 +241,8 @@ __device__ __forceinline__ bool plane_crossing(const Trk& k, const LayerK& ly, f
     tq = tanf(v) / v;
   }
   const float tau = v * tq;
-  const float f = s * tq * rcp(fmaf(tau, tau, 1.f));
+  st.inv1 = rcp(fmaf(tau, tau, 1.f));
+  const float f = s * tq * st.inv1;
   st.s = s;
   st.u = u;
   st.tau = tau;
@@ -254,7 +259,7 @@ __device__ __forceinline__ bool in_area(const Trk& k, const LayerK& ly, const St
     const float rho = hsqrt(fmaf(px, px, py * py));
     return rho >= ly.lo && rho <= ly.hi;
   }
-  const float z = fmaf(st.s * rcp(k.st), k.ct, k.x[2]);
+  const float z = fmaf(st.s * k.rst, k.ct, k.x[2]);
   return fabsf(z - ly.dz) <= ly.hi;
 }
 
@@ -265,7 +270,9 @@ struct Frame {
   float rho, rx, ry;  // radius about the layer axis and radial unit vector
   float cosa;         // cosine of the angle between the track and the surface normal:
                       // r_hat . t on a cylinder, cos(theta) on a disk
-  float cpsi;         // the same for the 3-D direction (the material's path is xX0 / cpsi)
+  float ica;          // 1 / cosa (cylinders)
+  float icpsi;        // 1 / the same cosine for the 3-D direction (the material's path is
+                      // xX0 * icpsi): 1 / (sin(theta) |cosa|) on a cylinder, 1 / |cos theta| on a disk
 };
 
 __device__ __forceinline__ Frame frame_at(const Trk& k, const LayerK& ly, bool disk = false) {
@@ -278,26 +285,29 @@ __device__ __forceinline__ Frame frame_at(const Trk& k, const LayerK& ly, bool d
   f.ry = ey * ir;
   if (disk) {
     f.cosa = k.ct;
-    f.cpsi = fabsf(k.ct);
+    f.ica = 1.f;
+    f.icpsi = rcp(fabsf(k.ct));
   } else {
     f.cosa = fmaf(f.rx, k.cp, f.ry * k.sp);
-    f.cpsi = k.st * fabsf(f.cosa);
+    f.ica = rcp(f.cosa);
+    f.icpsi = k.rst * fabsf(f.ica);
   }
   return f;
 }
 
 // Highland multiple scattering of a thin layer, added to (kappa, phi, theta):
-// theta0^2 = (0.0136/(beta p))^2 x (1 + 0.038 ln x)^2, x = xX0 / cpsi (a cylinder:
-// sin(theta) |cos alpha|; a disk: |cos theta|),
+// theta0^2 = (0.0136/(beta p))^2 x (1 + 0.038 ln x)^2, x = xX0 icpsi (a cylinder:
+// 1 / (sin(theta) |cos alpha|); a disk: 1 / |cos theta|),
 // 1/(beta p) = |kappa| sin(theta) sqrt(1 + m^2 kappa^2 sin^2(theta)).
 __device__ __forceinline__ void add_scattering(Trk& k, const Frame& f, float xX0, float mass2) {
   const float kap = k.x[3];
   const float ks = kap * k.st;
   const float ks2 = ks * ks;
-  const float xe = xX0 * rcp(f.cpsi);
-  const float lg = fmaf(0.038f, __logf(xe), 1.f);
+  const float xe = xX0 * f.icpsi;
+  // 0.038 ln x as 0.038 ln(2) log2(x): the hardware base-2 logarithm (v_log_f32, ~1 ulp)
+  const float lg = fmaf(0.038f * 0.69314718f, __builtin_amdgcn_logf(xe), 1.f);
   const float th2 = 0.0136f * 0.0136f * ks2 * fmaf(mass2, ks2, 1.f) * xe * lg * lg;
-  const float rst = rcp(k.st);
+  const float rst = k.rst;
   const float cot = k.ct * rst;
   const float kc = kap * cot;
   k.C[tri(4, 4)] = fmaf(th2 * rst, rst, k.C[tri(4, 4)]);
@@ -332,7 +342,7 @@ __device__ __forceinline__ bool energy_loss(Trk& k, const Frame& f, float xX0, f
   const float kap = k.x[3];
   const float ks = fabsf(kap) * k.st;          // 1 / p
   const float p = rcp(ks);
-  const float c = eloss * xX0 * rcp(f.cpsi);
+  const float c = eloss * xX0 * f.icpsi;
   const float ib2 = fmaf(mass2, ks * ks, 1.f); // 1 / beta^2
   const float E = p * hsqrt(ib2);
   const float dE = c * ib2;
@@ -344,7 +354,7 @@ __device__ __forceinline__ bool energy_loss(Trk& k, const Frame& f, float xX0, f
   const float W = p * X * (ip1 * ip1 * ip1);
   const float g = p * ip1;
   const float D = g + W;
-  const float T = kap * (k.ct * rcp(k.st)) * W;
+  const float T = kap * (k.ct * k.rst) * W;
   float* C = k.C;
   const float c53 = C[tri(5, 3)], c55 = C[tri(5, 5)], c33 = C[tri(3, 3)];
   C[tri(3, 0)] = fmaf(D, C[tri(3, 0)], T * C[tri(5, 0)]);
@@ -414,9 +424,9 @@ __device__ __forceinline__ void prepare(const Trk& k, const Frame& f, const Mode
     p.S12 = fmaf(p.HC1[0], p.h2x, fmaf(p.HC1[1], p.h2y, p.HC1[2] * p.h2z));
     p.S22 = fmaf(p.HC2[0], p.h2x, fmaf(p.HC2[1], p.h2y, fmaf(p.HC2[2], p.h2z, md.v_z)));
   } else {
-    const float ica = rcp(f.cosa);
+    const float ica = f.ica;
     const float tana = fmaf(fx, k.cp, fy * k.sp) * ica;
-    const float cot = k.ct * rcp(k.st);
+    const float cot = k.ct * k.rst;
     p.h1x = fmaf(-tana, f.rx, fx);
     p.h1y = fmaf(-tana, f.ry, fy);
     const float g = -cot * ica;
@@ -530,6 +540,7 @@ __device__ __forceinline__ void apply_update(Trk& k, const Pred& p, const Model&
   for (int i = 3; i < 6; ++i) k.x[i] = fmaf(K1[i], r1, fmaf(K2[i], r2, k.x[i]));
   rotate_small(k.cp, k.sp, dphi, k.x[4]);
   rotate_small(k.ct, k.st, dth, k.x[5]);
+  k.rst = rcp(k.st);
   float* C = k.C;
   // M[i][j] for the lower triangle and for columns 0..2 of every row
   float M[6][6];

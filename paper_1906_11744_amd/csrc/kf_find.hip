@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       int blo = 0, bhi = -1, zlo = 0, zhi = -1;
       kfd::Frame f;
       f.rho = f.rx = f.ry = 0.f;
-      f.cosa = f.cpsi = 1.f;
+      f.cosa = f.ica = f.icpsi = 1.f;
       kfd::Pred p;
       p.Si00 = p.Si11 = p.Si12 = p.Si22 = 0.f;
       p.fp64 = false;
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
           fc.rho = rdf(f.rho);
           fc.rx = rdf(f.rx);
           fc.ry = rdf(f.ry);
-          fc.cosa = fc.cpsi = 1.f;
+          fc.cosa = fc.ica = fc.icpsi = 1.f;
           kfd::Pred pc;
           pc.Si00 = rdf(p.Si00);
           pc.Si11 = rdf(p.Si11);
@@ -616,6 +616,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       k.sp = shfl_f(k.sp, src);
       k.ct = shfl_f(k.ct, src);
       k.st = shfl_f(k.st, src);
+      k.rst = shfl_f(k.rst, src);
       c2 = shfl_f(c2, src);
       nh = shfl_i(nh, src);
       nm = shfl_i(nm, src);

@@ -141,6 +141,10 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
     if (last > a.nl - 1) last = a.nl - 1;
     for (int l = 0; l <= last; ++l) {
       const kfd::LayerK ly = lays[l];
+      // the layer's hit is loaded before the step, so that its latency hides behind it
+      // (hits [L][3][n] is read in full; a layer without a hit ignores its values)
+      float phx, phy, phz;
+      src.get(i, n, l, phx, phy, phz);
       if (kBounded && ly.bounded != 0.f && !((mask >> l) & 1u)) {  // passed over
         if (kCkpt) store_ckpt(a.ckpt, n, i, l, k);
         continue;
@@ -178,8 +182,8 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
         kfd::Pred p;
         kfd::prepare(k, f, a.md, p, disk);
         if (p.fp64) status |= kfd::ST_FP64;
-        float mx, my, mz;
-        hit(l, mx, my, mz);
+        float mx = phx, my = phy, mz = phz;
+        if constexpr (!Src::kPlaced) kfd::place(ly, phx, phy, phz, mx, my, mz);
         const kfd::Resid r = kfd::residual(k, f, ly, p, mx, my, mz, disk);
         kfd::apply_update(k, p, a.md, r.r1, r.r2, disk);
         chi2 += r.chi2;
