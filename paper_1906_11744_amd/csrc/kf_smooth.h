@@ -15,8 +15,7 @@
 // positive semi-definite terms
 //   C_s = M C_f M^T + G (Q + C_s1) G^T,   M = I - G J = J^-1 W J,   G = J^-1 (I - W),
 // with W = Q C_p^-1 (J^-1 = I - N + N^2 exactly, N the six off-diagonal transport
-// terms, since N^3 = 0), and the first term reduced to a 3x3 product in double (see
-// below).  Without material W = 0, G = J^-1 and C_s is C_s1 carried back through the
+// terms, since N^3 = 0), and the first term reduced to a 3x3 product (see below).  Without material W = 0, G = J^-1 and C_s is C_s1 carried back through the
 // step.
 #pragma once
 
@@ -34,14 +33,14 @@ KFA_HD T wrap(T a) {
   return a;
 }
 
-// J C J^T (J = I + N, the transport of the step) accumulated in double from a float
-// C: the transported covariance keeps what C itself holds, which the C_p^-1 block
-// below needs.
-template <class T>
-KFA_HD void transport_cov_f64(const kfa::Prop<T>& P, const T C[21], double Co[21]) {
-  const double a03 = P.a03, a04 = P.a04, a13 = P.a13, a14 = P.a14, a25 = P.a25, a43 = P.a43;
-  auto c = [&](int i, int j) { return (double)C[tri(i, j)]; };
-  double B[6][6];
+// J C J^T (J = I + N, the transport of the step) accumulated in the precision U from
+// C: in double the transported covariance keeps what a float C itself holds, which
+// the C_p^-1 block below can need.
+template <class U, class T>
+KFA_HD void transport_cov_u(const kfa::Prop<T>& P, const T C[21], U Co[21]) {
+  const U a03 = P.a03, a04 = P.a04, a13 = P.a13, a14 = P.a14, a25 = P.a25, a43 = P.a43;
+  auto c = [&](int i, int j) { return (U)C[tri(i, j)]; };
+  U B[6][6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     B[0][j] = c(0, j) + a03 * c(3, j) + a04 * c(4, j);
@@ -124,6 +123,112 @@ KFA_HD bool loss_map(T kap, T st, T ct, T cosa, T xx, T eloss, T mass2, T& g, T&
   return true;
 }
 
+// C_p = J C_f J^T + Q factorised, and what the step needs of C_p^-1, formed in the
+// precision U: W = Q C_p^-1 (rows 3..5; Q is non-zero in its (kappa, phi, theta) block
+// Q3 only) and T3 = Q3 R Q3 (I - R Q3), R the (3..5, 3..5) block of C_p^-1.  pivot
+// receives the smallest pivot of the factorisation of C_p equilibrated to unit
+// diagonal, or the smallest diagonal element of I - R Q3 if that is smaller; false if
+// C_p is not positive definite (to U's rounding).
+template <class U, class T>
+KFA_HD bool cp_terms(const kfa::Prop<T>& P, const T Cf[21], const T Q[21], T W[6][6], T T3[3][3], T& pivot) {
+  using std::sqrt;
+  U dsc[6], L[21], linv[6];
+  transport_cov_u<U>(P, Cf, L);
+#pragma unroll
+  for (int q = 0; q < 21; ++q) L[q] += (U)Q[q];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const U cii = L[tri(i, i)];
+    if (!(cii > U(1e-30) && cii < U(1e30))) return false;
+    dsc[i] = (U)(1.0f / sqrt((float)cii));
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    U djj = L[tri(j, j)] * dsc[j] * dsc[j];
+#pragma unroll
+    for (int q = 0; q < j; ++q) djj -= L[tri(j, q)] * L[tri(j, q)];
+    if (!(djj > U(1e-30))) return false;  // not positive definite (to U's rounding)
+    pivot = j == 0 ? (T)djj : (pivot < (T)djj ? pivot : (T)djj);
+    U r = (U)(1.0f / sqrt((float)djj));
+    r = r * (U(1.5) - U(0.5) * djj * r * r);
+    r = r * (U(1.5) - U(0.5) * djj * r * r);
+    L[tri(j, j)] = djj * r;
+    linv[j] = r;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      U a = L[tri(i, j)] * dsc[i] * dsc[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) a -= L[tri(i, q)] * L[tri(j, q)];
+      L[tri(i, j)] = a * r;
+    }
+  }
+  U Y[3][6];  // Y[b] = C_p^-1 e_(3+b); the forward sweep starts at row 3+b
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int c = 3 + b;
+    U y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i < c) {
+        y[i] = U(0);
+        continue;
+      }
+      U a = i == c ? dsc[i] : U(0);
+#pragma unroll
+      for (int q = c; q < i; ++q) a -= L[tri(i, q)] * y[q];
+      y[i] = a * linv[i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+      U a = y[i];
+#pragma unroll
+      for (int q = i + 1; q < 6; ++q) a -= L[tri(q, i)] * y[q];
+      y[i] = a * linv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Y[b][i] = y[i] * dsc[i];
+  }
+  U Q3[3][3], A[3][3], Tm[3][3], V[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Q3[a][b] = (U)Q[tri(3 + a, 3 + b)];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      U w = U(0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) w += Q3[a][b] * Y[b][i];
+      W[3 + a][i] = (T)w;
+      if (i >= 3) A[a][i - 3] = w;  // Q3 R
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      U v = a == b ? U(1) : U(0), t = U(0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        v -= Y[q][3 + a] * Q3[q][b];  // (I - R Q3)
+        t += A[a][q] * Q3[q][b];      // Q3 R Q3
+      }
+      V[a][b] = v;
+      Tm[a][b] = t;
+      if (a == b) pivot = pivot < (T)v ? pivot : (T)v;
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      U t = U(0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) t += Tm[a][q] * V[q][b];
+      T3[a][b] = (T)t;
+    }
+  return true;
+}
+
 // One step in place: on entry (ds, Cs) is the smoothed estimate at layer l + 1 (ds its
 // offset from the filtered state xf1 there), on return the one at layer l (ds the
 // offset from xf).  xf, Cf: filtered estimate at l (packed lower C); ly1: the
@@ -135,7 +240,7 @@ KFA_HD bool loss_map(T kap, T st, T ct, T cosa, T xx, T eloss, T mass2, T& g, T&
 // row (D, Tt of loss_map), and C_p = A (J C_f J^T + Q) A^T, so the gain is
 // G = C_f J^T (J C_f J^T + Q)^-1 A^-1: the step below, written for A = I, applies
 // unchanged to A^-1 (x_s1 - x_p) and A^-1 C_s1 A^-T.
-template <class T>
+template <class T, bool kF32 = false>
 KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::Lay<T>& ly1,
                      const kfa::Consts<T>& k0, T ds[6], T Cs[21], const StepModel<T>* sm = nullptr) {
   using std::sqrt;
@@ -182,109 +287,24 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
   // K = columns 3..5 of J^-1: a 3x3 product in place of the 6x6 sandwich of C_f,
   // which at layers the fit saw through few hits (C_f orders of magnitude above C_s)
   // would cancel.  C_p^-1's three columns come from a Cholesky factorisation of C_p
-  // equilibrated to unit diagonal, and R, T and W are formed, in double: C_p's
-  // condition number after equilibration can still reach ~1e5.
-  // C_p = J C_f J^T + Q in double (where the scattering dominates the filtered
-  // angles, I - R Q3 below recovers the part of J C_f J^T that a float C_p would
-  // round away), then factorised in place
-  // No correctly rounded division or square root is needed: the equilibration
-  // scale is any positive number near C_p's diagonal^-1/2 (it is undone exactly), and
-  // the pivots' inverse square roots are float estimates refined by two Newton steps
-  // in double (relative error ~1e-16).
-  double dsc[6], L[21], linv[6];
-  transport_cov_f64(P, Cf, L);
-#pragma unroll
-  for (int q = 0; q < 21; ++q) L[q] += (double)Q[q];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const double cii = L[tri(i, i)];
-    if (!(cii > 1e-30 && cii < 1e30)) return false;
-    dsc[i] = (double)(1.0f / sqrt((float)cii));
-  }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    double djj = L[tri(j, j)] * dsc[j] * dsc[j];
-#pragma unroll
-    for (int q = 0; q < j; ++q) djj -= L[tri(j, q)] * L[tri(j, q)];
-    if (!(djj > 1e-30)) return false;  // not positive definite (to double rounding)
-    double r = (double)(1.0f / sqrt((float)djj));
-    r = r * (1.5 - 0.5 * djj * r * r);
-    r = r * (1.5 - 0.5 * djj * r * r);
-    L[tri(j, j)] = djj * r;
-    linv[j] = r;
-#pragma unroll
-    for (int i = j + 1; i < 6; ++i) {
-      double a = L[tri(i, j)] * dsc[i] * dsc[j];
-#pragma unroll
-      for (int q = 0; q < j; ++q) a -= L[tri(i, q)] * L[tri(j, q)];
-      L[tri(i, j)] = a * r;
-    }
-  }
-  double Y[3][6];  // Y[b] = C_p^-1 e_(3+b); the forward sweep starts at row 3+b
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int c = 3 + b;
-    double y[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      if (i < c) {
-        y[i] = 0.0;
-        continue;
-      }
-      double a = i == c ? dsc[i] : 0.0;
-#pragma unroll
-      for (int q = c; q < i; ++q) a -= L[tri(i, q)] * y[q];
-      y[i] = a * linv[i];
-    }
-#pragma unroll
-    for (int i = 5; i >= 0; --i) {
-      double a = y[i];
-#pragma unroll
-      for (int q = i + 1; q < 6; ++q) a -= L[tri(q, i)] * y[q];
-      y[i] = a * linv[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) Y[b][i] = y[i] * dsc[i];
-  }
-  double Q3[3][3], A[3][3], Tm[3][3], V[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) Q3[a][b] = (double)Q[tri(3 + a, 3 + b)];
+  // equilibrated to unit diagonal (cp_terms), formed in double from C_p = J C_f J^T +
+  // Q accumulated in double: C_p's condition number after equilibration can reach ~1e5,
+  // and where the scattering dominates the filtered angles I - R Q3 recovers the part
+  // of J C_f J^T that a float C_p would round away.  kF32: the block in float instead,
+  // formed again in double where its condition check fails: the factorisation's
+  // smallest pivot (the fraction of a component's variance left once the earlier
+  // components are known) or the smallest diagonal element of I - R Q3 below
+  // k0.det_thr.  (That variant meets the 1e-4 bar at det_thr 1e-2 with a tenth of the
+  // steps in double; in 64-lane waves nearly every wave then runs both paths.)  No
+  // correctly rounded division or square root is needed: the equilibration scale is
+  // any positive number near C_p's diagonal^-1/2 (it is undone exactly), and the
+  // pivots' inverse square roots are float estimates refined by two Newton steps.
   T W[6][6];  // rows 3..5 only
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      double w = 0.0;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) w += Q3[a][b] * Y[b][i];
-      W[3 + a][i] = (T)w;
-      if (i >= 3) A[a][i - 3] = w;  // Q3 R
-    }
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      double v = a == b ? 1.0 : 0.0, t = 0.0;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        v -= Y[q][3 + a] * Q3[q][b];  // (I - R Q3)
-        t += A[a][q] * Q3[q][b];      // Q3 R Q3
-      }
-      V[a][b] = v;
-      Tm[a][b] = t;
-    }
-  double T3[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      double t = 0.0;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) t += Tm[a][q] * V[q][b];
-      T3[a][b] = t;
-    }
+  T T3[3][3];
+  T piv = T(0);
+  if (!kF32 || !cp_terms<T, T>(P, Cf, Q, W, T3, piv) || !(piv >= k0.det_thr)) {
+    if (!cp_terms<double, T>(P, Cf, Q, W, T3, piv)) return false;
+  }
   // G = J^-1 (I - W)
   T G[6][6];
 #pragma unroll
@@ -332,7 +352,7 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
     for (int b = 0; b < 3; ++b) {
       T a = T(0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) a += Ji[i][3 + q] * (T)(0.5 * (T3[q][b] + T3[b][q]));
+      for (int q = 0; q < 3; ++q) a += Ji[i][3 + q] * (T(0.5) * (T3[q][b] + T3[b][q]));
       KT[i][b] = a;
     }
 #pragma unroll

@@ -9,17 +9,21 @@
 
 // map [nl][nz] (float32, null: none), zhalf [nl], eloss, fr, fz: the detector model;
 // use_model = 0 runs the plain step.
-template <class T>
+// kF32: the step's C_p^-1 block in float with its condition check (det_thr), counting
+// in *fallbacks the steps that redo it in double.
+template <class T, bool kF32 = false>
 static int smooth_host(int nl, const double* radius, double B, double srphi, double sz, double sr, double mass,
                        const double* align, const double* xX0, long n, const double* rec, const int* lend,
                        double* xs_out, double* Cs_out, int use_model = 0, const float* map = nullptr, int nz = 0,
-                       const double* zhalf = nullptr, double eloss = 0.0, double fr = 0.0, double fz = 0.0) {
+                       const double* zhalf = nullptr, double eloss = 0.0, double fr = 0.0, double fz = 0.0,
+                       double det_thr = 1e-2) {
   kfa::Consts<T> k;
   k.kB = (T)(0.299792458e-2 * B);
   k.v_r = (T)(sr * sr);
   k.v_rphi = (T)(srphi * srphi);
   k.v_z = (T)(sz * sz);
   k.mass2 = (T)(mass * mass);
+  k.det_thr = (T)det_thr;
   std::vector<kfa::Lay<T>> lays(nl);
   for (int l = 0; l < nl; ++l) {
     lays[l].r = (T)radius[l];
@@ -52,7 +56,7 @@ static int smooth_host(int nl, const double* radius, double B, double srphi, dou
       for (int q = 0; q < 6; ++q) xf[q] = (T)r[(long)l * 27 + q];
       for (int q = 0; q < 21; ++q) Cf[q] = (T)r[(long)l * 27 + 6 + q];
       kfs::StepModel<T> sm{map ? map + (long)(l + 1) * nz : nullptr, nz, (T)eloss, (T)fr, (T)fz};
-      if (!kfs::rts_step<T>(xf, Cf, xf1, lays[l + 1], k, ds, Cs1, use_model ? &sm : nullptr)) {
+      if (!kfs::rts_step<T, kF32>(xf, Cf, xf1, lays[l + 1], k, ds, Cs1, use_model ? &sm : nullptr)) {
         ++bad;
         break;
       }
@@ -90,4 +94,11 @@ extern "C" int smooth_host_model_f64(int nl, const double* radius, double B, dou
                                      const double* zhalf, double eloss, double fr, double fz) {
   return smooth_host<double>(nl, radius, B, srphi, sz, sr, mass, align, xX0, n, rec, lend, xs_out, Cs_out, 1, map, nz,
                              zhalf, eloss, fr, fz);
+}
+
+extern "C" int smooth_host_f32_check(int nl, const double* radius, double B, double srphi, double sz, double sr,
+                                     double mass, const double* align, const double* xX0, long n, const double* rec,
+                                     const int* lend, double* xs_out, double* Cs_out, double det_thr) {
+  return smooth_host<float, true>(nl, radius, B, srphi, sz, sr, mass, align, xX0, n, rec, lend, xs_out, Cs_out, 0,
+                                  nullptr, 0, nullptr, 0.0, 0.0, 0.0, det_thr);
 }

@@ -124,3 +124,43 @@ def test_library_step_under_the_detector_model(host_smooth):
         print(f"[{fn}] max rel state err {wx:.2e}, max cov err {wc:.2e}")
     assert worst["smooth_host_model_f64"][0] < 1e-9 and worst["smooth_host_model_f64"][1] < 1e-7
     assert worst["smooth_host_model_f32"][0] < 1e-4 and worst["smooth_host_model_f32"][1] < 1e-4
+
+
+@pytest.mark.parametrize("kind", ["aligned", "misaligned_gaps"])
+def test_float_block_with_condition_check(host_smooth, kind):
+    """The step's C_p^-1 block in float, redone in double where its condition check
+    fails (smallest equilibrated pivot, or smallest diagonal element of I - R Q3, below
+    det_thr): at det_thr 1e-2 the float step meets the 1e-4 bar; with no fallback at all
+    (det_thr 0) the covariance error is measured above it (1.2e-4 aligned, 2.3e-4 with
+    misalignment and gaps, where the scattering dominates the filtered angles); det_thr
+    above 1 redoes every step in double."""
+    geom, align, hits, mask = _case(kind)
+    sm = oracle.smooth(geom, hits, mask, align=align)
+    o = oracle.fit(geom, hits, mask, align=align, records=True)
+    lend = np.ascontiguousarray(sm["lend"], np.int32)
+    rec = np.ascontiguousarray(o["records"].astype(np.float32).astype(np.float64))
+    recT = np.transpose(rec, (1, 2, 0))
+    ref = oracle.smooth_filtered(geom, recT[:, :6], recT[:, 6:], lend, align=align)
+    ok = ((sm["status"] & (oracle.ST_NEAR_TANGENT | oracle.ST_PROP_FAIL)) == 0) & (ref["first"] == 0)
+    L, n = geom.n_layers, lend.size
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    f64 = lambda a: np.ascontiguousarray(a, np.float64)
+    worst = {}
+    for thr in (0.0, 1e-2, 2.0):
+        xs, Cs = np.zeros((L, 6, n)), np.zeros((L, 21, n))
+        bad = host_smooth.smooth_host_f32_check(
+            C.c_int(L), p(f64(geom.radius)), C.c_double(geom.B), C.c_double(geom.sigma_rphi), C.c_double(geom.sigma_z),
+            C.c_double(geom.sigma_r), C.c_double(geom.mass), p(f64(align)), p(f64(geom.xX0)), C.c_long(n), p(rec),
+            p(lend), p(xs), p(Cs), C.c_double(thr))
+        assert bad == 0
+        wx = wc = 0.0
+        for l in range(L):
+            sel = ok & (lend >= l)
+            if sel.any():
+                wx = max(wx, rel_state_err(xs[l][:, sel], ref["state"][l][:, sel]).max())
+                wc = max(wc, cov_err(Cs[l][:, sel], ref["cov"][l][:, sel]).max())
+        worst[thr] = (wx, wc)
+        print(f"[float block, det_thr {thr:g}, {kind}] max rel state err {wx:.2e}, max cov err {wc:.2e}")
+    assert worst[1e-2][0] < 1e-4 and worst[1e-2][1] < 1e-4
+    assert worst[2.0][1] < 2e-5
+    assert worst[0.0][1] > worst[1e-2][1]
