@@ -10,6 +10,7 @@ returns the ctypes handle, building on first use when the library is absent.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import os
 import subprocess
 
@@ -312,6 +313,66 @@ def fit(geom, hits, mask, align=None, xX0=None, seed_state=None, seed_cov=None, 
            _p(out["ndf"]), _p(out["status"]), _p(rec))
     if records:
         out["records"] = rec
+    return out
+
+
+def reverse_state(state, cov=None):
+    """The same particle run backwards: the path traced in the opposite direction is
+    that of the opposite charge, so (x, y, z, kappa, phi, theta) -> (x, y, z, -kappa,
+    phi + pi, pi - theta); the covariance follows with D = diag(1, 1, 1, -1, 1, -1).
+    Its own inverse.  state [6][n], cov [21][n] packed."""
+    x = np.array(state, np.float64)
+    x[3] = -x[3]
+    x[4] = (x[4] + 2 * np.pi) % (2 * np.pi) - np.pi   # phi + pi, wrapped to [-pi, pi)
+    x[5] = np.pi - x[5]
+    if cov is None:
+        return x
+    d = np.array([1.0, 1.0, 1.0, -1.0, 1.0, -1.0])
+    c = np.array(cov, np.float64).copy()
+    for i in range(6):
+        for j in range(i + 1):
+            c[i * (i + 1) // 2 + j] *= d[i] * d[j]
+    return x, c
+
+
+def fit_outside_in(geom, hits, mask, seed_state=None, seed_cov=None, align=None, xX0=None):
+    """Outside-in fit (the backward propagation and final fit of Sec. 4.2 and Sec. 5):
+    every track is filtered from its outermost hit layer inwards, seeded there from its
+    three outermost hits as fit() seeds from the three innermost (these must be the
+    three outermost layers the track reaches), or by seed_state [6][n] / seed_cov [21][n]
+    (the particle's own direction; the position on that layer's surface), and the
+    estimate at its innermost hit layer is returned as fit() returns the outermost one.  The backward pass is the forward filter of the
+    reversed particle (reverse_state) through the layers in reverse order: each layer's
+    scattering is added where the reversed particle reaches it, i.e. on the side of the
+    layer nearer the beam, and the innermost layer's own material enters the result (its
+    direction is the one before that layer)."""
+    hits = np.asarray(hits)
+    mask = np.ascontiguousarray(mask, np.uint32)
+    L, _, n = hits.shape
+    xx = np.asarray(geom.xX0 if xX0 is None else xX0, np.float64)
+    al = np.zeros((L, 4)) if align is None else np.asarray(align, np.float64)
+    rs, rc = (None, None) if seed_state is None else reverse_state(seed_state, seed_cov)
+    out = dict(state=np.zeros((6, n)), cov=np.zeros((21, n)), chi2=np.zeros(n), ndf=np.zeros(n, np.int32),
+               status=np.zeros(n, np.uint32))
+    last = np.array([int(m).bit_length() - 1 for m in mask])
+    for m in np.unique(last):
+        if m < 0:
+            continue
+        sel = np.nonzero(last == m)[0]
+        ls = np.arange(m, -1, -1)   # the layers, outermost first
+        kw = {f: getattr(geom, f)[ls] for f in ("disk_z", "disk_rmin", "disk_rmax", "cyl_zmax")
+              if getattr(geom, f, None) is not None}
+        g = dataclasses.replace(geom, radius=geom.radius[ls], zhalf=geom.zhalf[ls], xX0=xx[ls], **kw)
+        rmask = np.zeros(sel.size, np.uint32)
+        for k, l in enumerate(ls):
+            rmask |= ((mask[sel] >> np.uint32(l)) & np.uint32(1)) << np.uint32(k)
+        o = fit(g, np.ascontiguousarray(hits[ls][:, :, sel]), rmask, align=np.ascontiguousarray(al[ls]),
+                seed_state=None if rs is None else rs[:, sel], seed_cov=None if rc is None else rc[:, sel])
+        st, cv = reverse_state(o["state"], o["cov"])
+        out["state"][:, sel] = st
+        out["cov"][:, sel] = cv
+        for k in ("chi2", "ndf", "status"):
+            out[k][sel] = o[k]
     return out
 
 

@@ -259,9 +259,10 @@ void helix_at(const T x[6], const T& s, const T& kB, T out[6]) {
 }
 
 // Transverse arc length to the first forward crossing with |p - c| = r, within the
-// first half turn.  f(s) = |p(s) - c|^2 - r^2 is negative at s = 0 (inside); march
-// along the helix until it changes sign, bisect the bracket, then polish with
-// Newton steps (which also settle the derivative parts of dual numbers).
+// first half turn.  f(s) = |p(s) - c|^2 - r^2 is negative at s = 0 inside the cylinder
+// (the crossing is the exit) and positive outside it (the entry, for a particle run
+// inwards); march along the helix until it changes sign, bisect the bracket, then
+// polish with Newton steps (which also settle the derivative parts of dual numbers).
 template <class T>
 T crossing_residual(const T x[6], const T& s, const T& cx, const T& cy, double r, const T& kB, T* fp) {
   using std::cos; using std::sin;
@@ -276,14 +277,16 @@ template <class T>
 bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, const T& kB, T& s) {
   T ex = x[0] - cx, ey = x[1] - cy;
   double c0 = val(ex * ex + ey * ey) - r * r;
-  if (!(c0 < 0)) return false;
+  if (!(c0 != 0)) return false;
+  const double sg = c0 < 0 ? 1.0 : -1.0;  // f * sg turns non-negative at the crossing
   double w = -val(kB) * val(x[3]);
   double smax = w != 0 ? kPi / std::fabs(w) : 4.0 * r;
   double h = 0.125 * r;
   if (w != 0) h = std::min(h, 0.125 / std::fabs(w));
   // Along the helix circle the squared distance to the layer axis is a sinusoid of
-  // the turning angle, largest where the circle is farthest from the axis.  That
-  // point is always sampled, so a helix that only grazes the layer is bracketed too.
+  // the turning angle, largest where the circle is farthest from the axis and smallest
+  // opposite.  That point (the farthest for an exit, the nearest for an entry) is
+  // always sampled, so a helix that only grazes the layer is bracketed too.
   double speak = -1.0;
   if (w != 0) {
     double tx = std::cos(val(x[4])), ty = std::sin(val(x[4]));
@@ -291,6 +294,7 @@ bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, const T& kB,
     if (ccx * ccx + ccy * ccy > 0) {
       double psi_p = std::atan2(val(ey) - ccy, val(ex) - ccx);  // start, seen from the centre
       double psi_f = std::atan2(ccy, ccx);                      // farthest point, seen from the centre
+      if (sg < 0) psi_f += kPi;                                 // nearest point
       double du = std::fmod((psi_f - psi_p) * (w > 0 ? 1.0 : -1.0), 2 * kPi);
       if (du < 0) du += 2 * kPi;
       speak = du / std::fabs(w);
@@ -302,10 +306,10 @@ bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, const T& kB,
     double tt = std::min(t, smax);
     if (!peak_done && speak <= tt) {
       peak_done = true;
-      if (val(crossing_residual<T>(x, T(speak), cx, cy, r, kB, nullptr)) >= 0) { hi = speak; break; }
+      if (sg * val(crossing_residual<T>(x, T(speak), cx, cy, r, kB, nullptr)) >= 0) { hi = speak; break; }
       lo = speak;
     }
-    double f = val(crossing_residual<T>(x, T(tt), cx, cy, r, kB, nullptr));
+    double f = sg * val(crossing_residual<T>(x, T(tt), cx, cy, r, kB, nullptr));
     if (f >= 0) { hi = tt; break; }
     lo = tt;
     if (tt >= smax) break;
@@ -313,7 +317,7 @@ bool crossing_arc(const T x[6], const T& cx, const T& cy, double r, const T& kB,
   if (hi < 0) return false;
   for (int it = 0; it < 200 && hi - lo > 1e-14 * hi; ++it) {
     double mid = 0.5 * (lo + hi);
-    if (val(crossing_residual<T>(x, T(mid), cx, cy, r, kB, nullptr)) >= 0) hi = mid; else lo = mid;
+    if (sg * val(crossing_residual<T>(x, T(mid), cx, cy, r, kB, nullptr)) >= 0) hi = mid; else lo = mid;
   }
   s = T(0.5 * (lo + hi));
   for (int it = 0; it < 3; ++it) {
