@@ -122,7 +122,12 @@ typedef struct kf_layer_params {
  * seed_from_hits != 0: each seed is the helix through the (aligned) hits on layers
  * 0, 1, 2 (needs mask bits 0-2) with a diagonal prior covariance inflated ten times
  * in variance.  Otherwise seed_state [6][n] and seed_cov [21][n] are used; the seed's
- * position must lie on layer 0's surface (the layer-0 update does not propagate). */
+ * position must lie on layer 0's surface (the layer-0 update does not propagate).
+ * ckpt_every = k (0 and 1: every layer; at most KF_MAX_LAYERS): the checkpoints are
+ * kept for layers 0, k, 2k, ... only (kf_fit_out.ckpt), and kf_fit_backward recomputes
+ * the layers between them: a memory/compute trade (checkpoint bytes / k, one more
+ * forward step per layer between checkpoints, a [k-1][27][n] segment in its
+ * workspace).  kf_smooth needs every layer (k <= 1). */
 typedef struct kf_fit_in {
   int64_t n;
   const float* hits;
@@ -130,11 +135,14 @@ typedef struct kf_fit_in {
   const float* seed_state;
   const float* seed_cov;
   int32_t seed_from_hits;
+  int32_t ckpt_every;
 } kf_fit_in;
 
 /* Fit output: state [6][n], cov [21][n], chi2 [n], ndf [n] = 2 * n_hits - 5,
- * status [n]; ckpt (optional, required by kf_fit_backward) [L][27][n] holds the state
- * and covariance after each processed layer. */
+ * status [n]; ckpt (optional, required by kf_fit_backward) [ceil(L / k)][27][n] with
+ * k = max(1, ckpt_every): slot s holds the state and covariance after layer s k (after
+ * each processed layer for k = 1; a layer the track passes over, or beyond its last
+ * hit, keeps the previous slot's values or is not written). */
 typedef struct kf_fit_out {
   float* state;
   float* cov;
@@ -340,10 +348,12 @@ int kf_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, co
 int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* in, const kf_find_out* out,
                      void* ws, size_t ws_bytes, void* stream, kf_find_config* best);
 
-/* Adjoint of kf_fit (seed_from_hits must be 1 and ckpt filled by the forward call):
- * given dchi2 [n] = dLoss/dchi2_i, accumulates dLoss/dalign [L][4] and dLoss/dxX0 [L]
- * (overwritten, float32) by a reverse sweep over each track's layers that recomputes
- * every step from its checkpoint.  The paper has no differentiation; this is the
+/* Adjoint of kf_fit (seed_from_hits must be 1 and ckpt filled by the forward call, `in`
+ * with that call's ckpt_every): given dchi2 [n] = dLoss/dchi2_i, accumulates
+ * dLoss/dalign [L][4] and dLoss/dxX0 [L] (overwritten, float32) by a reverse sweep
+ * over each track's layers that recomputes every step from its checkpoint (with sparse
+ * checkpoints, each run of layers between two stored ones is first recomputed forward
+ * from the lower one into the workspace).  The paper has no differentiation; this is the
  * vector-Jacobian product of the fit as implemented by kf_fit: every S^-1 is recomputed
  * as the forward formed it (equilibrated, in FP64 below the context's fallback
  * threshold).  Under a parameterised field (kf_ctx_set_field; the forward call must
@@ -396,8 +406,9 @@ typedef struct kf_smooth_out {
  * layer is not reached from a checkpoint, or C_p is not positive definite) the
  * smoothing of that track stops and `first` records where.  A track whose fit ended
  * with BAD_INPUT has last = first = -1.  KF_E_INVALID for a NULL context, input or
- * output array, n < 0, or fwd->ckpt NULL; KF_E_WORKSPACE for a short or misaligned
- * workspace.  Workspace: kf_workspace_size(KF_OP_SMOOTH, in). */
+ * output array, n < 0, or fwd->ckpt NULL; KF_E_UNSUPPORTED for in->ckpt_every > 1;
+ * KF_E_WORKSPACE for a short or misaligned workspace.  Workspace:
+ * kf_workspace_size(KF_OP_SMOOTH, in). */
 int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
               const kf_smooth_out* out, void* ws, size_t ws_bytes, void* stream);
 

@@ -733,6 +733,37 @@ KFA_HD void place(const Lay<T>& ly, T hx, T hy, T hz, T m[3]) {
   m[2] = hz + ly.dz;
 }
 
+// One forward step of the fit, in place, from the filtered estimate after layer l - 1
+// to the one after layer l: propagation, transport, the layer's scattering and, where
+// the track has a hit on l (mask bit l), the update; under a parameterised field (fk)
+// the helix of the field at the step's start.  The adjoint uses it to recompute the
+// layers between sparse checkpoints.  False if layer l is not reached.
+template <class T, class Hit>
+KFA_HD bool forward_step(int l, uint32_t mask, const Lay<T>* lays, const Consts<T>& k, const FieldK<T>* fk, Hit hit,
+                         T x[6], T C[21]) {
+  const Lay<T>& ly = lays[l];
+  Consts<T> ks = k;
+  if (fk) ks.kB = field_kB(k, *fk, x[0], x[1], x[2]);
+  Prop<T> P;
+  T xp[6];
+  if (!propagate(x, ly, ks, P, xp)) return false;
+  T B[6][6], Cp[21];
+  transport_cov(P, C, B, Cp);
+  const Frm<T> fr = frame(xp, ly);
+  Scat<T> Q;
+  scatter(xp, fr, ly, ks, Q, Cp);
+  if ((mask >> l) & 1u) {
+    T h[3], m[3];
+    hit(l, h);
+    place(ly, h[0], h[1], h[2], m);
+    Upd<T> U;
+    update(xp, Cp, ly, ks, m[0], m[1], m[2], U);
+  }
+  for (int q = 0; q < 6; ++q) x[q] = xp[q];
+  for (int q = 0; q < 21; ++q) C[q] = Cp[q];
+  return true;
+}
+
 // Reverse sweep of one track.
 //   hit(l, h[3])     nominal hit on layer l;
 //   ckpt(l, x, C)    state and covariance after layer l of the forward fit;

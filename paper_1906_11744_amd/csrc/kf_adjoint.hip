@@ -44,19 +44,47 @@ __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
         h[1] = p[n];
         h[2] = p[2 * n];
       };
-      auto ckpt = [&](int l, float x[6], float C[21]) {
-        const float* p = a.ckpt + (int64_t)l * 27 * n + i;
+      auto load = [&](const float* p, float x[6], float C[21]) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) x[q] = p[q * n];
 #pragma unroll
         for (int q = 0; q < 21; ++q) C[q] = p[(6 + q) * n];
+      };
+      const kfa::FieldK<float> fk{a.fr, a.fz, a.srphi, a.sz, a.dr02};
+      // The filtered estimate after layer l.  With checkpoints every k > 1 layers the
+      // sweep (which asks for l = lstart - 1, lstart - 2, ..., 0) meets each run of
+      // layers c + 1 .. c + k - 1 from its top: the run is then recomputed forward from
+      // checkpoint c into the segment buffer, and read from it until the sweep reaches c.
+      const int every = a.every;
+      int seg_base = -1;
+      auto ckpt = [&](int l, float x[6], float C[21]) {
+        const int c = l - l % every;
+        if (l == c) {
+          load(a.ckpt + (int64_t)(c / every) * 27 * n + i, x, C);
+          return;
+        }
+        if (seg_base != c) {
+          float xr[6], Cr[21];
+          load(a.ckpt + (int64_t)(c / every) * 27 * n + i, xr, Cr);
+          const int top = min(c + every - 1, lstart - 1);
+          for (int q = c + 1; q <= top; ++q) {
+            if (!kfa::forward_step<float>(q, mask, lays, a.k, kField ? &fk : nullptr, hit, xr, Cr))
+              xr[0] = NAN;  // the sweep's own propagation from here then fails the track
+            float* p = a.seg + (int64_t)(q - c - 1) * 27 * n + i;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) p[t * n] = xr[t];
+#pragma unroll
+            for (int t = 0; t < 21; ++t) p[(6 + t) * n] = Cr[t];
+          }
+          seg_base = c;
+        }
+        load(a.seg + (int64_t)(l - c - 1) * 27 * n + i, x, C);
       };
       // layers 0..2 receive several contributions (the seed uses their hits)
       auto emit = [&](int l, const float g[5]) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) my[l * 5 + q] += g[q];
       };
-      const kfa::FieldK<float> fk{a.fr, a.fz, a.srphi, a.sz, a.dr02};
       if (!kfa::track_adjoint<float>(lstart, nl - 1, mask, lays, a.k, Cs, w, hit, ckpt, emit,
                                      kField ? &fk : nullptr))
         for (int o = 0; o < R; ++o) my[o] = 0.f;

@@ -97,10 +97,17 @@ bool valid_geometry(const kf_geometry* g) {
 // Workspace of a fit: the per-layer constants.
 size_t fit_ws_bytes() { return round_up(sizeof(kfd::LayerK) * KF_MAX_LAYERS); }
 
-// Workspace of the adjoint: the layer table, then [L][5][blocks] FP64 partials.
-size_t backward_ws_bytes(const kf_ctx* ctx, int64_t n) {
-  return fit_ws_bytes() + round_up((size_t)ctx->g.n_layers * 5 * (size_t)kfi::adjoint_blocks(n > 0 ? n : 0) *
-                                   sizeof(double));
+// Checkpoint stride of a fit input (ckpt_every 0 and 1: every layer).
+int ckpt_stride(const kf_fit_in* in) { return in->ckpt_every > 1 ? in->ckpt_every : 1; }
+
+// Workspace of the adjoint: the layer table, then [L][5][blocks] FP64 partials, then
+// with checkpoints every k > 1 layers the recomputed segment [k-1][27][n].
+size_t backward_partials_bytes(const kf_ctx* ctx, int64_t n) {
+  return round_up((size_t)ctx->g.n_layers * 5 * (size_t)kfi::adjoint_blocks(n > 0 ? n : 0) * sizeof(double));
+}
+size_t backward_ws_bytes(const kf_ctx* ctx, int64_t n, int every) {
+  const size_t nn = (size_t)(n > 0 ? n : 0);
+  return fit_ws_bytes() + backward_partials_bytes(ctx, n) + (every > 1 ? round_up((size_t)(every - 1) * 27 * nn * 4) : 0);
 }
 
 // Workspace of a find: layer constants | binned records [H] float4 | binned indices [H]
@@ -329,7 +336,7 @@ int kf_workspace_size(const kf_ctx* ctx, int op, const void* in, size_t* bytes) 
       return KF_OK;
     case KF_OP_FIT_BACKWARD: {
       const kf_fit_in* f = static_cast<const kf_fit_in*>(in);
-      *bytes = backward_ws_bytes(ctx, f->n);
+      *bytes = backward_ws_bytes(ctx, f->n, ckpt_stride(f));
       return KF_OK;
     }
     case KF_OP_CLEAN_SEEDS: {
@@ -357,6 +364,7 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   if (!in->seed_from_hits && (!in->seed_state || !in->seed_cov)) return KF_E_INVALID;
   if (in->seed_from_hits && !(ctx->g.B_tesla != 0.f)) return KF_E_UNSUPPORTED;  // no curvature from hits at B = 0
   if (in->n > (int64_t)INT32_MAX * 256) return KF_E_INVALID;
+  if (in->ckpt_every < 0 || in->ckpt_every > KF_MAX_LAYERS) return KF_E_INVALID;
   (void)ws;  // the fit needs no workspace
   (void)ws_bytes;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -389,6 +397,7 @@ int kf_fit(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, cons
   a.ndf = out->ndf;
   a.status = out->status;
   a.ckpt = out->ckpt;
+  a.ckpt_every = ckpt_stride(in);
   return kfi::launch_fit(a, st, ctx->ev_start, ctx->ev_stop) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
@@ -653,7 +662,7 @@ namespace {
 int check_backward(const kf_ctx* ctx, const kf_fit_in* in, const kf_fit_out* fwd, const float* dchi2,
                    const float* dalign, const float* dxX0) {
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
-  if (in->n < 0) return KF_E_INVALID;
+  if (in->n < 0 || in->ckpt_every < 0 || in->ckpt_every > KF_MAX_LAYERS) return KF_E_INVALID;
   if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
   // the adjoint differentiates the per-layer material model and the field (with the
   // points each step and the seed take it at)
@@ -697,6 +706,8 @@ int enqueue_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in
   a.layers = layers;
   a.n_blocks = kfi::adjoint_blocks(in->n);
   a.part = reinterpret_cast<double*>(base + fit_ws_bytes());
+  a.every = ckpt_stride(in);
+  a.seg = a.every > 1 ? reinterpret_cast<float*>(base + fit_ws_bytes() + backward_partials_bytes(ctx, in->n)) : nullptr;
   return kfi::launch_adjoint(a, dalign, dxX0, st) == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
@@ -732,7 +743,7 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream) {
   int rc = check_backward(ctx, in, fwd, dchi2, dalign, dxX0);
   if (rc != KF_OK) return rc;
-  rc = check_ws(ws, ws_bytes, backward_ws_bytes(ctx, in->n));
+  rc = check_ws(ws, ws_bytes, backward_ws_bytes(ctx, in->n, ckpt_stride(in)));
   if (rc != KF_OK) return rc;
   return enqueue_backward(ctx, params, in, fwd, dchi2, dalign, dxX0, static_cast<char*>(ws),
                           reinterpret_cast<hipStream_t>(stream));
@@ -742,7 +753,7 @@ int kf_fit_backward_static(kf_ctx* ctx, const kf_layer_params* params, const kf_
                            const float* dchi2, float* dalign, float* dxX0, void* stream) {
   int rc = check_backward(ctx, in, fwd, dchi2, dalign, dxX0);
   if (rc != KF_OK) return rc;
-  if (backward_ws_bytes(ctx, in->n) > kStaticScratchBytes) return KF_E_SCRATCH;
+  if (backward_ws_bytes(ctx, in->n, ckpt_stride(in)) > kStaticScratchBytes) return KF_E_SCRATCH;
   void* base = nullptr;
   rc = static_scratch(&base);
   if (rc != KF_OK) return rc;
@@ -757,6 +768,7 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
   if (!ctx || !in || !fwd || !out) return KF_E_INVALID;
   if (in->n < 0) return KF_E_INVALID;
   if (ctx->bounded) return KF_E_UNSUPPORTED;  // the smoother is for cylinders only
+  if (in->ckpt_every > 1) return KF_E_UNSUPPORTED;  // it reads every layer's checkpoint
   if (in->n == 0) return KF_OK;
   if (!in->hit_mask || !fwd->ndf || !fwd->status || !fwd->ckpt || !out->state || !out->cov || !out->first ||
       !out->last)

@@ -146,7 +146,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
       float phx, phy, phz;
       src.get(i, n, l, phx, phy, phz);
       if (kBounded && ly.bounded != 0.f && !((mask >> l) & 1u)) {  // passed over
-        if (kCkpt) store_ckpt(a.ckpt, n, i, l, k);
+        if (kCkpt && l % a.ckpt_every == 0) store_ckpt(a.ckpt, n, i, l / a.ckpt_every, k);
         continue;
       }
       const bool disk = kBounded && ly.disk != 0.f;  // (layer 0 is a cylinder)
@@ -189,7 +189,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, const kfd::LayerK* __r
         chi2 += r.chi2;
         ++nh;
       }
-      if (kCkpt) store_ckpt(a.ckpt, n, i, l, k);
+      if (kCkpt && l % a.ckpt_every == 0) store_ckpt(a.ckpt, n, i, l / a.ckpt_every, k);
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q)

@@ -53,6 +53,7 @@ struct FitArgs {
   int32_t* ndf;
   uint32_t* status;
   float* ckpt;
+  int32_t ckpt_every = 1;  // checkpoint slot s holds layer s * ckpt_every
 };
 
 struct BinArgs {
@@ -125,6 +126,8 @@ struct AdjArgs {
   const kfd::LayerK* layers;
   int64_t n_blocks;  // adjoint_blocks(n)
   double* part;      // [L][5][n_blocks] per-block gradient sums
+  int32_t every = 1;     // checkpoints every `every` layers (slot s = layer s * every)
+  float* seg = nullptr;  // [every - 1][27][n]: the layers between two checkpoints, recomputed
 };
 
 // Blocks of the adjoint kernel for n tracks (one FP64 partial per block and parameter).

@@ -48,7 +48,8 @@ class LayerParams(C.Structure):
 
 class FitIn(C.Structure):
     _fields_ = [("n", C.c_int64), ("hits", C.c_void_p), ("hit_mask", C.c_void_p),
-                ("seed_state", C.c_void_p), ("seed_cov", C.c_void_p), ("seed_from_hits", C.c_int32)]
+                ("seed_state", C.c_void_p), ("seed_cov", C.c_void_p), ("seed_from_hits", C.c_int32),
+                ("ckpt_every", C.c_int32)]
 
 
 class FitOut(C.Structure):
@@ -274,10 +275,11 @@ class Context:
         return p
 
     def fit(self, hits, hit_mask, align=None, xX0=None, seed_state=None, seed_cov=None, ckpt=False,
-            out=None, stream=None):
+            out=None, stream=None, ckpt_every=1):
         """kf_fit.  hits [L][3][n] float32, hit_mask [n] int32/uint32 bits; seeds from
         hits 0-2 unless seed_state [6][n] / seed_cov [21][n] are given.  Returns a dict
-        with state, cov, chi2, ndf, status (and ckpt [L][27][n] if requested)."""
+        with state, cov, chi2, ndf, status (and, with ckpt, ckpt [ceil(L / k)][27][n]
+        holding layers 0, k, 2k, ... for k = ckpt_every, and ckpt_every)."""
         L = self.n_layers
         n = hits.shape[2]
         dev = hits.device
@@ -298,9 +300,12 @@ class Context:
                        ndf=torch.empty(n, dtype=torch.int32, device=dev),
                        status=torch.empty(n, dtype=torch.int32, device=dev))
             if ckpt:
-                out["ckpt"] = torch.empty((L, 27, n), dtype=torch.float32, device=dev)
+                k = max(1, int(ckpt_every))
+                out["ckpt"] = torch.empty(((L + k - 1) // k, 27, n), dtype=torch.float32, device=dev)
+        if out.get("ckpt") is not None:
+            out["ckpt_every"] = max(1, int(ckpt_every))
         fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None if from_hits else seed_state.data_ptr(),
-                    None if from_hits else seed_cov.data_ptr(), int(from_hits))
+                    None if from_hits else seed_cov.data_ptr(), int(from_hits), int(ckpt_every))
         fo = FitOut(out["state"].data_ptr(), out["cov"].data_ptr(), out["chi2"].data_ptr(),
                     out["ndf"].data_ptr(), out["status"].data_ptr(),
                     out["ckpt"].data_ptr() if out.get("ckpt") is not None else None)
@@ -438,7 +443,7 @@ class Context:
                        cov=torch.empty((L, 21, n), dtype=torch.float32, device=dev),
                        first=torch.empty(n, dtype=torch.int32, device=dev),
                        last=torch.empty(n, dtype=torch.int32, device=dev))
-        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1)
+        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1, int(fwd.get("ckpt_every", 1)))
         fo = FitOut(fwd["state"].data_ptr(), fwd["cov"].data_ptr(), fwd["chi2"].data_ptr(),
                     fwd["ndf"].data_ptr(), fwd["status"].data_ptr(), fwd["ckpt"].data_ptr())
         so = SmoothOut(out["state"].data_ptr(), out["cov"].data_ptr(), out["first"].data_ptr(),
@@ -459,7 +464,7 @@ class Context:
         _dev(dchi2, torch.float32, (n,), "dchi2")
         if fwd.get("ckpt") is None:
             raise ValueError("the forward fit must be run with ckpt=True")
-        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1)
+        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1, int(fwd.get("ckpt_every", 1)))
         fo = FitOut(fwd["state"].data_ptr(), fwd["cov"].data_ptr(), fwd["chi2"].data_ptr(),
                     fwd["ndf"].data_ptr(), fwd["status"].data_ptr(), fwd["ckpt"].data_ptr())
         da = torch.empty((L, 4), dtype=torch.float32, device=dev)
@@ -487,7 +492,7 @@ class Context:
         da, dx = out
         _dev(da, torch.float32, (L, 4), "dalign")
         _dev(dx, torch.float32, (L,), "dxX0")
-        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1)
+        fin = FitIn(n, hits.data_ptr(), hit_mask.data_ptr(), None, None, 1, int(fwd.get("ckpt_every", 1)))
         fo = FitOut(fwd["state"].data_ptr(), fwd["cov"].data_ptr(), fwd["chi2"].data_ptr(),
                     fwd["ndf"].data_ptr(), fwd["status"].data_ptr(), fwd["ckpt"].data_ptr())
         p = self._params(align, xX0)

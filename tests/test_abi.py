@@ -303,3 +303,31 @@ def test_endcap_geometry_validation_and_the_calls_it_excludes():
     fin = kf.FindIn(1, fake, 100, fake, 10, fake, fake, 30.0, 3.0, 6, 3, 0)
     fo = kf.FindOut(*([fake] * 13))
     assert lib.kf_find(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -3
+
+
+def test_sparse_checkpoint_arguments():
+    """ckpt_every: 0..KF_MAX_LAYERS (0 and 1 keep every layer); the adjoint's workspace
+    grows by the recomputed segment [k-1][27][n]; the smoother refuses k > 1; each error
+    before anything is launched."""
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    fake = C.c_void_p(0x1000)
+    fo = kf.FitOut(fake, fake, fake, fake, fake, fake)
+    p = kf.LayerParams()
+    for bad in (-1, 33):
+        fin = kf.FitIn(10, fake, fake, None, None, 1, bad)
+        assert lib.kf_fit(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), None, 0, None) == -1
+        assert lib.kf_fit_backward(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), fake, fake, fake, None, 0,
+                                   None) == -1
+    ws = C.c_size_t()
+    sizes = {}
+    for k in (0, 1, 2, 4):
+        fin = kf.FitIn(100_000, fake, fake, None, None, 1, k)
+        assert lib.kf_workspace_size(ctx._h, kf.KF_OP_FIT_BACKWARD, C.byref(fin), C.byref(ws)) == 0
+        sizes[k] = ws.value
+    assert sizes[0] == sizes[1]
+    seg = lambda k: -(-(k - 1) * 27 * 100_000 * 4 // 256) * 256
+    assert sizes[2] - sizes[1] == seg(2) and sizes[4] - sizes[1] == seg(4)
+    so = kf.SmoothOut(fake, fake, fake, fake)
+    fin = kf.FitIn(10, fake, fake, None, None, 1, 2)
+    assert lib.kf_smooth(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), C.byref(so), None, 0, None) == -2

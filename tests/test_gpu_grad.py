@@ -23,7 +23,7 @@ def _case(n, at_truth):
     return geom, ts, align
 
 
-def _gpu_grad(geom, ts, align, w, field=None, det_threshold=None):
+def _gpu_grad(geom, ts, align, w, field=None, det_threshold=None, ckpt_every=1, static=False):
     need_gpu()
     from paper_1906_11744_amd import Context
     kf = Context(geom)
@@ -34,8 +34,9 @@ def _gpu_grad(geom, ts, align, w, field=None, det_threshold=None):
     hits, mask = to_dev(ts.hits), mask_dev(ts.hit_mask)
     a = to_dev(np.asarray(align, np.float32))
     x = to_dev(geom.xX0.astype(np.float32))
-    fwd = kf.fit(hits, mask, align=a, xX0=x, ckpt=True)
-    da, dx = kf.fit_backward(hits, mask, fwd, to_dev(np.asarray(w, np.float32)), align=a, xX0=x)
+    fwd = kf.fit(hits, mask, align=a, xX0=x, ckpt=True, ckpt_every=ckpt_every)
+    back = kf.fit_backward_static if static else kf.fit_backward
+    da, dx = back(hits, mask, fwd, to_dev(np.asarray(w, np.float32)), align=a, xX0=x)
     torch.cuda.synchronize()
     return da.cpu().numpy().astype(np.float64), dx.cpu().numpy().astype(np.float64), fwd
 
@@ -155,3 +156,34 @@ def test_autograd_function():
     assert torch.equal(chi2.detach(), plain["chi2"])
     ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w.cpu().numpy().astype(np.float64))
     _check(a.grad.cpu().numpy().astype(np.float64), x.grad.cpu().numpy().astype(np.float64), ra, rx, "autograd")
+
+
+@pytest.mark.parametrize("every", [2, 3, 5, 17])
+def test_sparse_checkpoints_recompute_the_gradient(every):
+    """Checkpoints on every k-th layer only (the fit stores ceil(17 / k) of them); the
+    backward recomputes each run of layers between two from the lower one.  The
+    gradient equals the dense-checkpoint one to float rounding (the recomputed states
+    come from the adjoint's own forward step, not the fit kernel's bits) and meets the
+    oracle's bar; the field's variant and the allocation-free entry point alike."""
+    geom, ts, align = _case(3000, False)
+    w = np.random.default_rng(6).uniform(0.5, 1.5, ts.hits.shape[2])
+    ga1, gx1, _ = _gpu_grad(geom, ts, align, w)
+    ga, gx, fwd = _gpu_grad(geom, ts, align, w, ckpt_every=every)
+    assert fwd["ckpt"].shape[0] == -(-geom.n_layers // every)
+    g1 = np.concatenate([ga1.ravel(), gx1])
+    g = np.concatenate([ga.ravel(), gx])
+    rel = np.linalg.norm(g - g1) / np.linalg.norm(g1)
+    print(f"[every {every}] ||g_sparse - g_dense|| / ||g_dense|| = {rel:.2e}")
+    assert rel < 1e-5
+    ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w)
+    _check(ga, gx, ra, rx, f"checkpoints every {every}")
+    gas, gxs, _ = _gpu_grad(geom, ts, align, w, ckpt_every=every, static=True)
+    np.testing.assert_array_equal(gas, ga)
+    np.testing.assert_array_equal(gxs, gx)
+    if every == 3:
+        field = (-1e-6, -4e-6)
+        gaf1, gxf1, _ = _gpu_grad(geom, ts, align, w, field=field)
+        gaf, gxf, _ = _gpu_grad(geom, ts, align, w, field=field, ckpt_every=every)
+        gf1 = np.concatenate([gaf1.ravel(), gxf1])
+        gf = np.concatenate([gaf.ravel(), gxf])
+        assert np.linalg.norm(gf - gf1) / np.linalg.norm(gf1) < 1e-5
