@@ -376,19 +376,28 @@ def fit_outside_in(geom, hits, mask, seed_state=None, seed_cov=None, align=None,
     return out
 
 
-def total_chi2(geom, hits, mask, align, xX0, weight=None, field=None):
+def total_chi2(geom, hits, mask, align, xX0, weight=None, field=None, material=None):
+    """sum_i weight_i chi2_i of the FP64 fit (seeds from hits); field and material as
+    for fit_grad()."""
     hits = np.ascontiguousarray(hits, np.float32)
     mask = np.ascontiguousarray(mask, np.uint32)
     g = ogeom(geom)
     fr, fz = (0.0, 0.0) if field is None else (float(field[0]), float(field[1]))
+    xmap, eloss = (None, 0.0) if material is None else material
+    xmap = None if xmap is None else np.ascontiguousarray(xmap, np.float64)
+    nz = 0 if xmap is None else int(xmap.shape[1])
     return load().oracle_total_chi2(C.byref(g), _p(_f64(align)), _p(_f64(xX0)), C.c_int64(hits.shape[2]),
-                                    _p(hits), _p(mask), _p(_f64(weight)), C.c_double(fr), C.c_double(fz))
+                                    _p(hits), _p(mask), _p(_f64(weight)), C.c_double(fr), C.c_double(fz), _p(xmap),
+                                    C.c_int32(nz), C.c_double(float(eloss)))
 
 
-def fit_grad(geom, hits, mask, align, xX0, weight=None, field=None):
+def fit_grad(geom, hits, mask, align, xX0, weight=None, field=None, material=None):
     """FP64 gradient of sum_i weight_i chi2_i w.r.t. align [L][4] and xX0 [L] (dual
     numbers).  field = (c_r, c_z): the parameterised field; the derivative includes the
-    field's change where a parameter moves a step's start point or the seed's first hit."""
+    field's change where a parameter moves a step's start point or the seed's first hit.
+    material = (xX0_map [L][nz] or None, eloss): the material model as for fit(); with a
+    map the second result is the derivative w.r.t. an additive offset of each layer's
+    map row (xX0 is then not used)."""
     hits = np.ascontiguousarray(hits, np.float32)
     mask = np.ascontiguousarray(mask, np.uint32)
     L = hits.shape[0]
@@ -396,9 +405,22 @@ def fit_grad(geom, hits, mask, align, xX0, weight=None, field=None):
     gx = np.zeros(L)
     g = ogeom(geom)
     fr, fz = (0.0, 0.0) if field is None else (float(field[0]), float(field[1]))
+    xmap, eloss = (None, 0.0) if material is None else material
+    xmap = None if xmap is None else np.ascontiguousarray(xmap, np.float64)
+    nz = 0 if xmap is None else int(xmap.shape[1])
     load().oracle_fit_grad(C.byref(g), _p(_f64(align)), _p(_f64(xX0)), C.c_int64(hits.shape[2]), _p(hits),
-                           _p(mask), _p(_f64(weight)), _p(ga), _p(gx), C.c_double(fr), C.c_double(fz))
+                           _p(mask), _p(_f64(weight)), _p(ga), _p(gx), C.c_double(fr), C.c_double(fz), _p(xmap),
+                           C.c_int32(nz), C.c_double(float(eloss)))
     return ga, gx
+
+
+def loss_map(geom, eloss, kappa, theta, xe):
+    """(kappa1, dkappa1/dkappa, dkappa1/dtheta) of the mean energy loss over a path of
+    xe radiation lengths, or None if the particle stops."""
+    out = np.zeros(3)
+    ok = load().oracle_loss_map(C.byref(ogeom(geom)), C.c_double(eloss), C.c_double(kappa), C.c_double(theta),
+                                C.c_double(xe), _p(out))
+    return out if ok else None
 
 
 def find(geom, ev, chi2_cut=30.0, nsigma=3.0, keep=6, max_miss=3, brute=False, refit=False,

@@ -145,6 +145,7 @@ constexpr double kIllCond = 1e-2;
 template <class T>
 struct Layer {
   T cx, cy, dz, cphi, sphi, xX0;  // alignment (centre, z shift, rotation) and x/X0
+  T moff = T(0.0);  // additive offset of the layer's material-map row (0; a gradient seed)
   double r;
   int idx = 0;  // layer index (row of a material map)
   // a disk: the plane z = zd + dz, active for rmin <= rho <= rmax (rho about its axis);
@@ -420,60 +421,85 @@ void add_scattering(const Geo& g, const Layer<T>& ly, const T x[6], T C[6][6]) {
 
 // x/X0 of layer l at z (the layer's own frame) from the material map: linear
 // interpolation between the centres of the map's equal z bins over [-Z_L, Z_L],
-// constant beyond the outer centres.
-double map_xX0(const Geo& g, int l, double z) {
+// constant beyond the outer centres.  (T: z may carry derivatives, which the
+// interpolation's slope passes on.)
+template <class T>
+T map_xX0(const Geo& g, int l, const T& z) {
   const double* m = g.map + (int64_t)l * g.map_nz;
   const int nz = g.map_nz;
-  if (nz == 1) return m[0];
+  if (nz == 1) return T(m[0]);
   const double Z = g.zhalf[l];
-  const double u = (z + Z) / (2.0 * Z) * nz - 0.5;
-  if (u <= 0.0) return m[0];
-  if (u >= nz - 1) return m[nz - 1];
-  int k = (int)std::floor(u);
+  const T u = (z + Z) / (2.0 * Z) * (double)nz - 0.5;
+  if (val(u) <= 0.0) return T(m[0]);
+  if (val(u) >= nz - 1) return T(m[nz - 1]);
+  int k = (int)std::floor(val(u));
   if (k > nz - 2) k = nz - 2;
-  const double t = u - k;
+  const T t = u - (double)k;
   return m[k] + t * (m[k + 1] - m[k]);
 }
 
-// The material of a thin layer at the predicted state (Sec. 3), in FP64 only:
-// multiple scattering with the layer's x/X0 there (the map, else the layer's
-// constant), then the mean ionisation loss dE = eloss * x_eff / beta^2 (x_eff the
-// path length of the scattering term, beta at the incoming momentum): the energy
-// drops to E - dE at fixed direction, so kappa becomes kappa * p / p'.  The
-// covariance follows kappa' as a function of (kappa, theta), differentiated here by
-// dual numbers; the path-length factor enters the mean only.  False if the particle
-// is left without kinetic energy.
-bool material_step(const Geo& g, const Layer<double>& ly, double x[6], double C[6][6], double (*A_out)[6] = nullptr) {
+// The mean ionisation loss of a thin layer as a map of kappa (Sec. 3): with
+// p = 1 / (|kappa| sin(theta)), E = sqrt(p^2 + m^2) and c = eloss * x_eff, the energy
+// drops by dE = c E^2 / p^2 (= c / beta^2) to E1 and kappa becomes kappa p / p1 (p1 the
+// new momentum).  Returns false if E1 <= m.  With it, the derivatives of kappa1 in
+// kappa and theta at fixed x_eff (the covariance's linearisation A: D = dkappa1/dkappa,
+// Tt = dkappa1/dtheta), written out from those definitions: for p,
+//   dE1/dp = p / E + 2 c m^2 / p^3,   dp1/dp = (E1 / p1) dE1/dp,
+//   dkappa1/dp = kappa (p1 - p dp1/dp) / p1^2,
+// and dp/dkappa = -p / kappa, dp/dtheta = -p cot(theta).
+template <class T>
+bool loss_map(const Geo& g, const T& kap, const T& th, const T& xe, T& k1, T& D, T& Tt) {
+  using std::sin; using std::cos; using std::sqrt; using std::fabs;
+  const double m2 = g.mass * g.mass;
+  const T s = sin(th), ct = cos(th);
+  const T p = 1.0 / (fabs(kap) * s);
+  const T E = sqrt(p * p + m2);
+  const T c = g.eloss * xe;
+  const T E1 = E - c * (p * p + m2) / (p * p);
+  if (!(val(E1) > g.mass)) return false;
+  const T p1 = sqrt(E1 * E1 - m2);
+  k1 = kap * p / p1;
+  const T dE1 = p / E + 2.0 * c * m2 / (p * p * p);
+  const T dp1 = E1 / p1 * dE1;
+  const T dk1 = kap * (p1 - p * dp1) / (p1 * p1);
+  D = p / p1 - dk1 * p / kap;
+  Tt = -dk1 * p * ct / s;
+  return true;
+}
+
+// The material of a thin layer at the predicted state (Sec. 3): multiple scattering
+// with the layer's x/X0 there (the map plus its row's offset, else the layer's
+// constant), then the mean ionisation loss dE = eloss * x_eff / beta^2 (x_eff the path
+// length of the scattering term, beta at the incoming momentum): the energy drops to
+// E - dE at fixed direction, so kappa becomes kappa * p / p' (loss_map).  The covariance
+// follows kappa' as a function of (kappa, theta); the path-length factor enters the
+// mean only.  False if the particle is left without kinetic energy.
+template <class T>
+bool material_step(const Geo& g, const Layer<T>& ly, T x[6], T C[6][6], double (*A_out)[6] = nullptr) {
+  using std::cos; using std::sin; using std::sqrt; using std::fabs;
   if (A_out)
     for (int i = 0; i < 6; ++i)
       for (int j = 0; j < 6; ++j) A_out[i][j] = i == j ? 1.0 : 0.0;
-  Layer<double> lm = ly;
-  if (g.map && !ly.disk) lm.xX0 = map_xX0(g, ly.idx, x[2] - ly.dz);
+  Layer<T> lm = ly;
+  if (g.map && !ly.disk) lm.xX0 = map_xX0<T>(g, ly.idx, x[2] - ly.dz) + ly.moff;
   add_scattering(g, lm, x, C);
-  if (!(g.eloss > 0.0) || !(lm.xX0 > 0.0)) return true;
-  const double ex = x[0] - ly.cx, ey = x[1] - ly.cy;
-  const double cpsi = ly.disk ? std::fabs(std::cos(x[5]))
-                              : std::sin(x[5]) * std::fabs((ex * std::cos(x[4]) + ey * std::sin(x[4])) /
-                                                           std::sqrt(ex * ex + ey * ey));
-  const double xe = lm.xX0 / cpsi;
-  const double m2 = g.mass * g.mass;
-  Dual<2> kap(x[3]), th(x[5]);
-  kap.d[0] = 1.0;
-  th.d[1] = 1.0;
-  const Dual<2> p = 1.0 / (fabs(kap) * sin(th));
-  const Dual<2> E2 = p * p + m2;
-  const Dual<2> E1 = sqrt(E2) - g.eloss * xe * E2 / (p * p);
-  if (!(E1.v > g.mass)) return false;
-  const Dual<2> k1 = kap * p / sqrt(E1 * E1 - m2);
-  double A[6][6] = {};
-  for (int i = 0; i < 6; ++i) A[i][i] = 1.0;
-  A[3][3] = k1.d[0];
-  A[3][5] = k1.d[1];
+  if (!(g.eloss > 0.0) || !(val(lm.xX0) > 0.0)) return true;
+  const T ex = x[0] - ly.cx, ey = x[1] - ly.cy;
+  const T cpsi = ly.disk ? fabs(cos(x[5])) : sin(x[5]) * fabs((ex * cos(x[4]) + ey * sin(x[4])) / sqrt(ex * ex + ey * ey));
+  const T xe = lm.xX0 / cpsi;
+  T k1, D, Tt;
+  if (!loss_map<T>(g, x[3], x[5], xe, k1, D, Tt)) return false;
+  T A[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) A[i][j] = T(i == j ? 1.0 : 0.0);
+  A[3][3] = D;
+  A[3][5] = Tt;
   sandwich(A, C);
-  x[3] = k1.v;
-  if (A_out)
-    for (int i = 0; i < 6; ++i)
-      for (int j = 0; j < 6; ++j) A_out[i][j] = A[i][j];
+  x[3] = k1;
+  if (A_out) {
+    A_out[3][3] = val(D);
+    A_out[3][5] = val(Tt);
+  }
   return true;
 }
 
@@ -698,17 +724,12 @@ bool predict(const Geo& g, const Layer<T>& ly, Track<T>& tk, T (*J_out)[6] = nul
     if (std::fabs(ca) < 0.3) tk.status |= ST_NEAR_TANGENT;
   }
   if (g.map || g.eloss > 0.0) {
-    if constexpr (std::is_same<T, double>::value) {
-      double A[6][6];
-      if (!material_step(g, ly, tk.x, tk.C, A)) { tk.status |= ST_PROP_FAIL; return false; }
-      if (J_out) {  // the step's linearisation is A J: the loss maps kappa after the transport
-        double row[6];
-        for (int j = 0; j < 6; ++j) row[j] = A[3][3] * J_out[3][j] + A[3][5] * J_out[5][j];
-        for (int j = 0; j < 6; ++j) J_out[3][j] = row[j];
-      }
-    } else {
-      tk.status |= ST_BAD_INPUT;  // the material model is not differentiated
-      return false;
+    double A[6][6];
+    if (!material_step(g, ly, tk.x, tk.C, A)) { tk.status |= ST_PROP_FAIL; return false; }
+    if (J_out) {  // the step's linearisation is A J: the loss maps kappa after the transport
+      T row[6];
+      for (int j = 0; j < 6; ++j) row[j] = A[3][3] * J_out[3][j] + A[3][5] * J_out[5][j];
+      for (int j = 0; j < 6; ++j) J_out[3][j] = row[j];
     }
   } else {
     add_scattering(g, ly, tk.x, tk.C);
@@ -923,6 +944,19 @@ int oracle_kalman_update(int n, int m, double* x, double* C, const double* H, co
   return 1;
 }
 
+// The energy loss's map of kappa (loss_map): out = (kappa1, dkappa1/dkappa,
+// dkappa1/dtheta) at path length xe; returns 0 if the particle stops.
+int oracle_loss_map(const OGeom* og, double eloss, double kap, double th, double xe, double* out) {
+  Geo g = make_geo(og);
+  g.eloss = eloss;
+  double k1, D, Tt;
+  if (!loss_map<double>(g, kap, th, xe, k1, D, Tt)) return 0;
+  out[0] = k1;
+  out[1] = D;
+  out[2] = Tt;
+  return 1;
+}
+
 // Three-hit seed (state 6, covariance row-major 6x6) from three placed hits.
 void oracle_seed(const OGeom* og, const double* m0, const double* m1, const double* m2, double* state, double* cov) {
   Geo g = make_geo(og);
@@ -1039,10 +1073,14 @@ void oracle_fit_f64(const OGeom* og, const double* align, const double* xX0, int
 // Weighted total chi2, sum_i weight[i] * chi2_i (weight may be null: all ones),
 // summed in track order, seeds built from hits.  For central finite differences.
 double oracle_total_chi2(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
-                         const uint32_t* mask, const double* weight, double fr, double fz) {
+                         const uint32_t* mask, const double* weight, double fr, double fz, const double* map,
+                         int32_t map_nz, double eloss) {
   Geo g = make_geo(og);
   g.fr = fr;
   g.fz = fz;
+  g.map = map;
+  g.map_nz = map ? map_nz : 0;
+  g.eloss = eloss;
   Layer<double> lay[32];
   make_layers<double>(g, align, xX0, lay);
   std::vector<double> c(n);
@@ -1063,13 +1101,19 @@ double oracle_total_chi2(const OGeom* og, const double* align, const double* xX0
 // is taken at its start and the seed's at hit 0, points that move with the parameters;
 // the dual numbers carry that dependence, so this is the exact derivative of the total
 // chi2 that oracle_total_chi2 evaluates.
+// The material model (map [L][nz] or null, eloss) enters as in the fit; with a map,
+// g_xX0[l] is the derivative with respect to an additive offset of the map's row l (the
+// per-layer xX0 is then not used).
 void oracle_fit_grad(const OGeom* og, const double* align, const double* xX0, int64_t n, const float* hits,
                      const uint32_t* mask, const double* weight, double* g_align, double* g_xX0, double fr,
-                     double fz) {
+                     double fz, const double* map, int32_t map_nz, double eloss) {
   using D = Dual<5>;
   Geo g = make_geo(og);
   g.fr = fr;
   g.fz = fz;
+  g.map = map;
+  g.map_nz = map ? map_nz : 0;
+  g.eloss = eloss;
   for (int pl = 0; pl < g.nl; ++pl) {
     D al[32 * 4], xx[32];
     for (int l = 0; l < g.nl; ++l) {
@@ -1077,9 +1121,10 @@ void oracle_fit_grad(const OGeom* og, const double* align, const double* xX0, in
       xx[l] = D(xX0 ? xX0[l] : 0.0);
     }
     for (int k = 0; k < 4; ++k) al[4 * pl + k].d[k] = 1.0;
-    xx[pl].d[4] = 1.0;
+    if (!map) xx[pl].d[4] = 1.0;
     Layer<D> lay[32];
     make_layers<D>(g, al, xx, lay);
+    if (map) lay[pl].moff.d[4] = 1.0;
     std::vector<double> part((size_t)n * 5);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {

@@ -197,3 +197,78 @@ def test_field_model_pulls(oracle_lib, model):
         assert abs(kq) < 0.1
     else:
         assert widths[0] > 2.0 and kq < -2.0
+
+
+# --------------------------------------------------------------------------------------
+# the material model's gradient (dual numbers through the map lookup and the loss)
+# --------------------------------------------------------------------------------------
+def test_loss_map_derivatives(oracle_lib):
+    """kappa1 of the loss map from its definitions (numpy), and the closed-form
+    dkappa1/dkappa, dkappa1/dtheta against central differences of kappa1."""
+    geom = synth.workload_geometry(2)
+    rng = np.random.default_rng(41)
+    el = synth.ELOSS_SI_GEV_PER_X0
+    m2 = geom.mass ** 2
+    for _ in range(200):
+        kap = rng.choice([-1, 1]) * rng.uniform(0.02, 2.0)
+        th = rng.uniform(0.3, 2.8)
+        xe = rng.uniform(0.01, 0.3)
+        out = oracle.loss_map(geom, el, kap, th, xe)
+        p = 1.0 / (abs(kap) * math.sin(th))
+        E = math.sqrt(p * p + m2)
+        E1 = E - el * xe * (p * p + m2) / (p * p)
+        if E1 <= geom.mass:
+            assert out is None
+            continue
+        k1 = kap * p / math.sqrt(E1 * E1 - m2)
+        assert out[0] == pytest.approx(k1, rel=1e-13)
+        for j, (dk, dt) in enumerate(((1e-7 * abs(kap), 0.0), (0.0, 1e-7))):
+            up = oracle.loss_map(geom, el, kap + dk, th + dt, xe)[0]
+            dn = oracle.loss_map(geom, el, kap - dk, th - dt, xe)[0]
+            fd = (up - dn) / (2 * (dk + dt))
+            assert out[1 + j] == pytest.approx(fd, rel=1e-6, abs=1e-8 * max(1.0, abs(k1) / (dk + dt) * 1e-7)), j
+
+
+@pytest.mark.parametrize("part", ["map", "map + loss", "loss"])
+def test_material_gradient_against_central_differences(oracle_lib, part):
+    """The gradient of the total chi2 under the material model: with a map, the fifth
+    component per layer is the derivative with respect to an additive offset of that
+    layer's map row (x/X0 then comes from the map; the slope of the interpolation in z
+    carries the alignment's effect on the crossing point); with the loss, kappa's
+    change at each crossing and the covariance's linearisation are differentiated too.
+    Both against central differences of the FP64 total chi2."""
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    xmap = synth.material_map(geom)
+    el = synth.ELOSS_SI_GEV_PER_X0 if "loss" in part else 0.0
+    use_map = "map" in part
+    mat = (xmap if use_map else None, el)
+    sim = mat if use_map else (geom.xX0[:, None], el)   # the generator takes the loss with a map
+    ts = synth.simulate(geom, synth.rng_for(78), 20, (0.5, 50.0), True, 1.5, align=a_true, material=sim)
+    align = np.zeros_like(a_true)
+    xX0 = geom.xX0.copy()
+    ga, gx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, xX0, material=mat)
+    scale = max(np.abs(ga).max(), np.abs(gx).max())
+    h = 1e-6
+    rng = np.random.default_rng(3)
+    comps = [(l, k) for l in range(geom.n_layers) for k in range(5)]
+    for (l, k) in [comps[j] for j in rng.choice(len(comps), 30, replace=False)]:
+        ap, am = align.copy(), align.copy()
+        xp, xm = xX0.copy(), xX0.copy()
+        mp, mm = xmap.copy(), xmap.copy()
+        if k < 4:
+            ap[l, k] += h
+            am[l, k] -= h
+            g = ga[l, k]
+        else:
+            if use_map:
+                mp[l] += h
+                mm[l] -= h
+            else:
+                xp[l] += h
+                xm[l] -= h
+            g = gx[l]
+        fp = oracle.total_chi2(geom, ts.hits, ts.hit_mask, ap, xp, material=(mp if use_map else None, el))
+        fm = oracle.total_chi2(geom, ts.hits, ts.hit_mask, am, xm, material=(mm if use_map else None, el))
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g) <= 1e-6 * abs(g) + 2e-6 * scale, (l, k, fd, g)
