@@ -237,9 +237,9 @@ int kf_ctx_set_launch_events(kf_ctx* ctx, void* start, void* stop);
  * search and in the refit; a candidate whose particle stops ends there
  * (KF_ST_PROP_FAIL), holding its prediction transported to that layer.  kf_smooth
  * takes it in every step (the step's linearisation then includes the loss; the
- * batch must have been fitted under the same setting).  While a map or a nonzero
- * loss is set, kf_fit_backward returns KF_E_UNSUPPORTED (it differentiates one x/X0
- * per layer and no loss).  KF_E_INVALID for a NULL context, a negative or non-finite
+ * batch must have been fitted under the same setting).  kf_fit_backward differentiates
+ * both (with a map, its dLoss/dxX0 [l] is the derivative with respect to an additive
+ * offset of map row l).  KF_E_INVALID for a NULL context, a negative or non-finite
  * loss, nz out of range with a map, or a geometry with a zhalf_cm that is not
  * positive. */
 int kf_ctx_set_material(kf_ctx* ctx, const float* xX0_map, int32_t nz, float eloss_gev_per_x0);
@@ -358,8 +358,12 @@ int kf_find_autotune(kf_ctx* ctx, const kf_layer_params* params, const kf_find_i
  * as the forward formed it (equilibrated, in FP64 below the context's fallback
  * threshold).  Under a parameterised field (kf_ctx_set_field; the forward call must
  * have run under the same field) the field at each step's start and at the seed's
- * first hit is differentiated with those points; KF_E_UNSUPPORTED while a material
- * map or an energy loss is set (kf_ctx_set_material). */
+ * first hit is differentiated with those points.  Under the material model
+ * (kf_ctx_set_material; the forward call under the same setting) the map's value at
+ * each crossing moves with the crossing's z (its interpolation's slope), the energy
+ * loss's change of kappa and its linearisation of the covariance are differentiated,
+ * and with a map dxX0 [l] is the derivative with respect to an additive offset of the
+ * map's row l (the per-layer xX0 is then not used). */
 int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,
                     const float* dchi2, float* dalign, float* dxX0, void* ws, size_t ws_bytes, void* stream);
 

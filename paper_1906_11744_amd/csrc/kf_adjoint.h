@@ -504,10 +504,12 @@ KFA_HD void update_adj(const T x[6], const T C[21], const Upd<T>& U, T chib, T x
 }
 
 // Adjoint of the scattering noise: Cb (of C + Q) is unchanged; adds to xb, the frame
-// (through cos alpha), cxb/cyb and the material adjoint.
+// (through cos alpha), cxb/cyb and the material adjoint.  xeb_more: an adjoint of the
+// path length x_e = x/X0 / (sin theta |cos alpha|) from elsewhere (the energy loss),
+// passed on with the scattering's own.
 template <class T>
 KFA_HD void scatter_adj(const T x[6], const Frm<T>& f, const Lay<T>& ly, const Consts<T>& k, const Scat<T>& Q,
-                        const T Cb[21], T xb[6], T& cxb, T& cyb, T& xX0b) {
+                        const T Cb[21], T xb[6], T& cxb, T& cyb, T& xX0b, T xeb_more = T(0)) {
   using std::fabs;
   if (!Q.on) return;
   const T kap = x[3];
@@ -522,7 +524,7 @@ KFA_HD void scatter_adj(const T x[6], const Frm<T>& f, const Lay<T>& ly, const C
   // th2 = A0^2 ks^2 (1 + m^2 ks^2) xe lg^2
   const T ks2 = Q.ks * Q.ks;
   const T ksb = G * Q.th2 * (T(2) / Q.ks + T(2) * k.mass2 * Q.ks / (T(1) + k.mass2 * ks2));
-  const T xeb = G * Q.th2 / Q.xe * (T(1) + T(0.076) / Q.lg);
+  const T xeb = G * Q.th2 / Q.xe * (T(1) + T(0.076) / Q.lg) + xeb_more;  // (xeb_more: the energy loss's)
   kapb += ksb * Q.st;
   stb += ksb * kap;
   // xe = xX0 / (st |ca|)
@@ -733,6 +735,193 @@ KFA_HD void place(const Lay<T>& ly, T hx, T hy, T hz, T m[3]) {
   m[2] = hz + ly.dz;
 }
 
+// ---------------------------------------------------------------------------------
+// the detector model of Sec. 3 in the sweep: material map and mean energy loss
+// ---------------------------------------------------------------------------------
+
+// A material map [L][nz] (float32, null: each layer's x/X0) and the mean ionisation loss
+// per radiation length (0: none).
+template <class T>
+struct MatK {
+  const float* map;
+  int nz;
+  T eloss;
+};
+
+// x/X0 of a layer at z from its map row, as the fit reads it (linear between the centres
+// of nz equal bins over the layer's frame, constant beyond the outer centres), and its
+// slope in z (0 beyond the centres).
+template <class T>
+KFA_HD T map_lookup(const float* row, int nz, const Lay<T>& ly, T z, T& slope) {
+  slope = T(0);
+  if (nz == 1) return (T)row[0];
+  const T u0 = (z - ly.dz) * ly.zs + ly.zo;
+  const T u = u0 < T(0) ? T(0) : (u0 > T(nz - 1) ? T(nz - 1) : u0);
+  int b = (int)u;
+  if (b > nz - 2) b = nz - 2;
+  const T t = u - (T)b;
+  const T v0 = (T)row[b], d = (T)row[b + 1] - v0;
+  if (u0 > T(0) && u0 < T(nz - 1)) slope = d * ly.zs;
+  return v0 + t * d;
+}
+
+// A value with its derivatives in three variables (forward mode), for the Jacobian of
+// the energy loss's local map below.
+template <class T>
+struct D3 {
+  T v, d[3];
+};
+template <class T>
+KFA_HD D3<T> d3(T v, int i) {
+  D3<T> r{v, {T(0), T(0), T(0)}};
+  if (i >= 0) r.d[i] = T(1);
+  return r;
+}
+template <class T> KFA_HD T vof(const D3<T>& a) { return a.v; }
+template <class T> KFA_HD T vof(T a) { return a; }
+template <class T> KFA_HD D3<T> operator+(const D3<T>& a, const D3<T>& b) { return {a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2]}}; }
+template <class T> KFA_HD D3<T> operator-(const D3<T>& a, const D3<T>& b) { return {a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2]}}; }
+template <class T> KFA_HD D3<T> operator*(const D3<T>& a, const D3<T>& b) {
+  return {a.v * b.v, {a.d[0] * b.v + a.v * b.d[0], a.d[1] * b.v + a.v * b.d[1], a.d[2] * b.v + a.v * b.d[2]}};
+}
+template <class T> KFA_HD D3<T> operator*(const D3<T>& a, T b) { return {a.v * b, {a.d[0] * b, a.d[1] * b, a.d[2] * b}}; }
+template <class T> KFA_HD D3<T> operator*(T b, const D3<T>& a) { return a * b; }
+template <class T> KFA_HD D3<T> operator+(const D3<T>& a, T b) { return {a.v + b, {a.d[0], a.d[1], a.d[2]}}; }
+template <class T> KFA_HD D3<T> operator+(T b, const D3<T>& a) { return a + b; }
+template <class T> KFA_HD D3<T> operator-(const D3<T>& a, T b) { return {a.v - b, {a.d[0], a.d[1], a.d[2]}}; }
+template <class T> KFA_HD D3<T> inv(const D3<T>& a) {
+  const T r = T(1) / a.v, r2 = -r * r;
+  return {r, {a.d[0] * r2, a.d[1] * r2, a.d[2] * r2}};
+}
+template <class T> KFA_HD D3<T> operator/(const D3<T>& a, const D3<T>& b) { return a * inv(b); }
+template <class T> KFA_HD D3<T> operator/(T a, const D3<T>& b) { return inv(b) * a; }
+template <class T> KFA_HD D3<T> sqrt(const D3<T>& a) {
+  using std::sqrt;
+  const T s = sqrt(a.v), h = T(0.5) / s;
+  return {s, {a.d[0] * h, a.d[1] * h, a.d[2] * h}};
+}
+template <class T> KFA_HD D3<T> fabs(const D3<T>& a) { return a.v < T(0) ? a * T(-1) : a; }
+template <class T> KFA_HD void sin_cos(const D3<T>& a, D3<T>& s, D3<T>& c) {
+  T sv, cv;
+  sin_cos(a.v, sv, cv);
+  s = {sv, {a.d[0] * cv, a.d[1] * cv, a.d[2] * cv}};
+  c = {cv, {-a.d[0] * sv, -a.d[1] * sv, -a.d[2] * sv}};
+}
+
+// The mean energy loss over a path of xe radiation lengths as a map of kappa (the fit's:
+// p = 1 / (|kappa| sin theta), E = p sqrt(1 + m^2 / p^2), dE = eloss xe / beta^2,
+// E1 = E - dE, kappa1 = kappa p / p1), with its derivatives D = dkappa1/dkappa and
+// Tt = dkappa1/dtheta at fixed xe (the covariance's linearisation), evaluated as the fit
+// evaluates them.  S = T, or D3<T> to differentiate (kappa1, D, Tt) in (kappa, theta, xe).
+// False if the particle stops.
+template <class S, class T>
+KFA_HD bool loss_kappa(const S& kap, const S& th, const S& xe, T eloss, T mass2, S& k1, S& D, S& Tt) {
+  using std::fabs; using std::sqrt;
+  S st, ct;
+  sin_cos(th, st, ct);
+  const S ks = fabs(kap) * st;
+  const S p = T(1) / ks;
+  const S c = xe * eloss;
+  const S ib2 = T(1) + ks * ks * mass2;
+  const S E = p * sqrt(ib2);
+  const S dE = c * ib2;
+  const S E1 = E - dE;
+  const S q2 = E1 * E1 - mass2;
+  if (!(vof(E1) > T(0)) || !(vof(q2) > T(0))) return false;
+  const S ip1 = T(1) / sqrt(q2);
+  const S X = dE * (mass2 / E + E1) + T(2) * mass2 * c * E1 * ks * ks;
+  const S W = p * X * (ip1 * ip1 * ip1);
+  const S g = p * ip1;
+  D = g + W;
+  Tt = kap * (ct / st) * W;
+  k1 = g * kap;
+  return true;
+}
+
+// Tape of a step's material beyond the scattering: the map's slope at the crossing and
+// the loss's Jacobian J[o][i] of (kappa1, D, Tt) in (kappa, theta, x_e).
+template <class T>
+struct MatT {
+  T xx, slope;   // x/X0 at the crossing and its slope in z (map)
+  bool loss;
+  T D, Tt, J[3][3];
+};
+
+// The step's material after its transport (x, C: the transported state and covariance):
+// x/X0 (from the map's row of layer l, else the layer's), the scattering term, then the
+// energy loss on kappa with C <- A C A^T (A the identity but for kappa's row: D at
+// kappa, Tt at theta).  Cl receives C before the loss.  False if the particle stops.
+template <class T>
+KFA_HD bool material_fwd(int l, const Lay<T>& ly, const Consts<T>& k, const MatK<T>* mk, const Frm<T>& fr, T x[6],
+                         T C[21], Scat<T>& Q, MatT<T>& M, T Cl[21]) {
+  Lay<T> lym = ly;
+  M.slope = T(0);
+  M.loss = false;
+  if (mk && mk->map) lym.xX0 = map_lookup(mk->map + (int64_t)l * mk->nz, mk->nz, ly, x[2], M.slope);
+  M.xx = lym.xX0;
+  scatter(x, fr, lym, k, Q, C);
+  if (!mk || !(mk->eloss > T(0)) || !(M.xx > T(0))) return true;
+  D3<T> k1, D, Tt;
+  if (!loss_kappa(d3(x[3], 0), d3(x[5], 1), d3(Q.xe, 2), mk->eloss, k.mass2, k1, D, Tt)) return false;
+  M.loss = true;
+  M.D = D.v;
+  M.Tt = Tt.v;
+  for (int i = 0; i < 3; ++i) {
+    M.J[0][i] = k1.d[i];
+    M.J[1][i] = D.d[i];
+    M.J[2][i] = Tt.d[i];
+  }
+  for (int q = 0; q < 21; ++q) Cl[q] = C[q];
+  const T c53 = C[tri(5, 3)], c55 = C[tri(5, 5)], c33 = C[tri(3, 3)];
+  for (int j = 0; j < 6; ++j)
+    if (j != 3 && j != 5) C[tri(3, j)] = M.D * C[tri(3, j)] + M.Tt * C[tri(5, j)];
+  C[tri(5, 3)] = M.D * c53 + M.Tt * c55;
+  C[tri(3, 3)] = M.D * M.D * c33 + T(2) * M.D * M.Tt * c53 + M.Tt * M.Tt * c55;
+  x[3] = k1.v;
+  return true;
+}
+
+// Adjoint of the energy loss: xb, Cb of (x, C) after the loss in, of them before it out
+// (x: the state before the loss; Cl: C before it); returns the adjoint of x_e.  The
+// covariance map C' = A C A^T gives C-bar = A^T C'-bar A and A-bar = 2 C'-bar A C.
+template <class T>
+KFA_HD T loss_adj(const T x[6], const T Cl[21], const MatT<T>& M, T xb[6], T Cb[21]) {
+  T CbF[6][6], AC3[6], AC5[6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) CbF[i][j] = Cb[tri(i, j)];
+  // columns 3 and 5 of A C (only A's row 3 differs from the identity)
+  for (int kk = 0; kk < 6; ++kk) {
+    AC3[kk] = kk == 3 ? M.D * Cl[tri(3, 3)] + M.Tt * Cl[tri(5, 3)] : Cl[tri(kk, 3)];
+    AC5[kk] = kk == 3 ? M.D * Cl[tri(3, 5)] + M.Tt * Cl[tri(5, 5)] : Cl[tri(kk, 5)];
+  }
+  T Db = T(0), Ttb = T(0);
+  for (int kk = 0; kk < 6; ++kk) {
+    Db += CbF[3][kk] * AC3[kk];
+    Ttb += CbF[3][kk] * AC5[kk];
+  }
+  Db *= T(2);
+  Ttb *= T(2);
+  // C-bar = A^T C'-bar A: column i of A is e_i, but D e_3 for i = 3 and e_5 + Tt e_3
+  // for i = 5
+  T V[6][6];  // C'-bar A
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j)
+      V[i][j] = j == 3 ? M.D * CbF[i][3] : (j == 5 ? CbF[i][5] + M.Tt * CbF[i][3] : CbF[i][j]);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j <= i; ++j) {
+      auto col = [&](int r, int c) {  // (A^T V)(r, c) = sum_k A(k, r) V(k, c)
+        return r == 3 ? M.D * V[3][c] : (r == 5 ? V[5][c] + M.Tt * V[3][c] : V[r][c]);
+      };
+      Cb[tri(i, j)] = col(i, j);
+    }
+  // kappa1, D, Tt in (kappa, theta, x_e)
+  const T k1b = xb[3];
+  xb[3] = k1b * M.J[0][0] + Db * M.J[1][0] + Ttb * M.J[2][0];
+  xb[5] += k1b * M.J[0][1] + Db * M.J[1][1] + Ttb * M.J[2][1];
+  (void)x;
+  return k1b * M.J[0][2] + Db * M.J[1][2] + Ttb * M.J[2][2];
+}
+
 // One forward step of the fit, in place, from the filtered estimate after layer l - 1
 // to the one after layer l: propagation, transport, the layer's scattering and, where
 // the track has a hit on l (mask bit l), the update; under a parameterised field (fk)
@@ -740,7 +929,7 @@ KFA_HD void place(const Lay<T>& ly, T hx, T hy, T hz, T m[3]) {
 // layers between sparse checkpoints.  False if layer l is not reached.
 template <class T, class Hit>
 KFA_HD bool forward_step(int l, uint32_t mask, const Lay<T>* lays, const Consts<T>& k, const FieldK<T>* fk, Hit hit,
-                         T x[6], T C[21]) {
+                         T x[6], T C[21], const MatK<T>* mk = nullptr) {
   const Lay<T>& ly = lays[l];
   Consts<T> ks = k;
   if (fk) ks.kB = field_kB(k, *fk, x[0], x[1], x[2]);
@@ -751,7 +940,9 @@ KFA_HD bool forward_step(int l, uint32_t mask, const Lay<T>* lays, const Consts<
   transport_cov(P, C, B, Cp);
   const Frm<T> fr = frame(xp, ly);
   Scat<T> Q;
-  scatter(xp, fr, ly, ks, Q, Cp);
+  MatT<T> M;
+  T Cl[21];
+  if (!material_fwd(l, ly, ks, mk, fr, xp, Cp, Q, M, Cl)) return false;
   if ((mask >> l) & 1u) {
     T h[3], m[3];
     hit(l, h);
@@ -779,7 +970,8 @@ KFA_HD bool forward_step(int l, uint32_t mask, const Lay<T>* lays, const Consts<
 // Returns false if a recomputed step fails (no contribution then).
 template <class T, class Hit, class Ckpt, class Emit>
 KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lays, const Consts<T>& k,
-                          const T Cs[21], T w, Hit hit, Ckpt ckpt, Emit emit, const FieldK<T>* fk = nullptr) {
+                          const T Cs[21], T w, Hit hit, Ckpt ckpt, Emit emit, const FieldK<T>* fk = nullptr,
+                          const MatK<T>* mk = nullptr) {
   T xb[6] = {0, 0, 0, 0, 0, 0};
   T Cb[21];
   for (int q = 0; q < 21; ++q) Cb[q] = T(0);
@@ -797,7 +989,10 @@ KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lay
     transport_cov(P, C, B, Cp);
     const Frm<T> fr = frame(xp, ly);
     Scat<T> Q;
-    scatter(xp, fr, ly, ks, Q, Cp);
+    MatT<T> M;
+    T Cl[21], xl[6];  // C and x before the energy loss (with a loss)
+    for (int q = 0; q < 6; ++q) xl[q] = xp[q];
+    if (!material_fwd(l, ly, ks, mk, fr, xp, Cp, Q, M, Cl)) return false;
     T g[5] = {0, 0, 0, 0, 0};
     if ((mask >> l) & 1u) {
       T h[3], m[3];
@@ -812,7 +1007,16 @@ KFA_HD bool track_adjoint(int lstart, int ltop, uint32_t mask, const Lay<T>* lay
       update_adj(xp, Cp, U, w, xb, Cb, mb[0], mb[1], mb[2], g[0], g[1]);
       place_adj(ly, h[0], h[1], mb[0], mb[1], mb[2], g);
     }
-    scatter_adj(xp, fr, ly, ks, Q, Cb, xb, g[0], g[1], g[4]);
+    const T xeb = M.loss ? loss_adj(xl, Cl, M, xb, Cb) : T(0);
+    Lay<T> lym = ly;
+    lym.xX0 = M.xx;
+    T xxb = T(0);
+    scatter_adj(xl, fr, lym, ks, Q, Cb, xb, g[0], g[1], xxb, xeb);
+    if (mk && mk->map) {  // the map's row offset, and its slope at the crossing's z - dz
+      xb[2] += xxb * M.slope;
+      g[2] -= xxb * M.slope;
+    }
+    g[4] += xxb;
     T kBb = 0;
     propagate_adj(x, C, B, P, ks, xb, Cb, g[0], g[1], fk ? &kBb : nullptr);
     if (fk) field_adj(k, *fk, x[0], x[1], x[2], kBb, xb[0], xb[1], xb[2]);  // the step's start point

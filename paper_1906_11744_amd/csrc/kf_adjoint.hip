@@ -17,7 +17,8 @@ constexpr int kAdjBlock = 64;
 
 __host__ __device__ inline int adj_row_stride(int nl) { return 5 * nl + ((5 * nl) % 2 == 0 ? 1 : 0); }
 
-template <bool kField>
+// kField: the parameterised field; kMat: the material map and/or the energy loss.
+template <bool kField, bool kMat>
 __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
   extern __shared__ float red[];
   const int R = 5 * a.nl;
@@ -51,6 +52,7 @@ __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
         for (int q = 0; q < 21; ++q) C[q] = p[(6 + q) * n];
       };
       const kfa::FieldK<float> fk{a.fr, a.fz, a.srphi, a.sz, a.dr02};
+      const kfa::MatK<float> mk{a.mat_map, a.mat_nz, a.eloss};
       // The filtered estimate after layer l.  With checkpoints every k > 1 layers the
       // sweep (which asks for l = lstart - 1, lstart - 2, ..., 0) meets each run of
       // layers c + 1 .. c + k - 1 from its top: the run is then recomputed forward from
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
           load(a.ckpt + (int64_t)(c / every) * 27 * n + i, xr, Cr);
           const int top = min(c + every - 1, lstart - 1);
           for (int q = c + 1; q <= top; ++q) {
-            if (!kfa::forward_step<float>(q, mask, lays, a.k, kField ? &fk : nullptr, hit, xr, Cr))
+            if (!kfa::forward_step<float>(q, mask, lays, a.k, kField ? &fk : nullptr, hit, xr, Cr, kMat ? &mk : nullptr))
               xr[0] = NAN;  // the sweep's own propagation from here then fails the track
             float* p = a.seg + (int64_t)(q - c - 1) * 27 * n + i;
 #pragma unroll
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(kAdjBlock) void fit_adjoint_kernel(AdjArgs a) {
         for (int q = 0; q < 5; ++q) my[l * 5 + q] += g[q];
       };
       if (!kfa::track_adjoint<float>(lstart, nl - 1, mask, lays, a.k, Cs, w, hit, ckpt, emit,
-                                     kField ? &fk : nullptr))
+                                     kField ? &fk : nullptr, kMat ? &mk : nullptr))
         for (int o = 0; o < R; ++o) my[o] = 0.f;
     }
   }
@@ -125,10 +127,15 @@ int64_t adjoint_blocks(int64_t n) { return (n + kAdjBlock - 1) / kAdjBlock; }
 hipError_t launch_adjoint(const AdjArgs& a, float* dalign, float* dxX0, hipStream_t stream) {
   if (a.n_blocks > 0) {
     const size_t lds = (size_t)kAdjBlock * adj_row_stride(a.nl) * sizeof(float);
-    if (a.fr != 0.f || a.fz != 0.f)
-      hipLaunchKernelGGL((fit_adjoint_kernel<true>), dim3((unsigned)a.n_blocks), dim3(kAdjBlock), lds, stream, a);
-    else
-      hipLaunchKernelGGL((fit_adjoint_kernel<false>), dim3((unsigned)a.n_blocks), dim3(kAdjBlock), lds, stream, a);
+    const dim3 g((unsigned)a.n_blocks), b(kAdjBlock);
+    const bool field = a.fr != 0.f || a.fz != 0.f, mat = a.mat_map != nullptr || a.eloss > 0.f;
+    if (mat) {
+      if (field) hipLaunchKernelGGL((fit_adjoint_kernel<true, true>), g, b, lds, stream, a);
+      else hipLaunchKernelGGL((fit_adjoint_kernel<false, true>), g, b, lds, stream, a);
+    } else {
+      if (field) hipLaunchKernelGGL((fit_adjoint_kernel<true, false>), g, b, lds, stream, a);
+      else hipLaunchKernelGGL((fit_adjoint_kernel<false, false>), g, b, lds, stream, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -664,9 +664,8 @@ int check_backward(const kf_ctx* ctx, const kf_fit_in* in, const kf_fit_out* fwd
   if (!ctx || !in || !fwd || !dalign || !dxX0) return KF_E_INVALID;
   if (in->n < 0 || in->ckpt_every < 0 || in->ckpt_every > KF_MAX_LAYERS) return KF_E_INVALID;
   if (!in->seed_from_hits) return KF_E_UNSUPPORTED;
-  // the adjoint differentiates the per-layer material model and the field (with the
-  // points each step and the seed take it at)
-  if (ctx->mat_map != nullptr || ctx->eloss > 0.f) return KF_E_UNSUPPORTED;
+  // the adjoint differentiates the material model (x/X0 per layer or the map, the energy
+  // loss) and the field (with the points each step and the seed take it at)
   if (!(ctx->g.B_tesla != 0.f) || ctx->bounded) return KF_E_UNSUPPORTED;  // cylinders only
   if (in->n > 0 && (!in->hits || !in->hit_mask || !dchi2 || !fwd->ndf || !fwd->status || !fwd->ckpt))
     return KF_E_INVALID;
@@ -680,10 +679,14 @@ int enqueue_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base);
   const float* align = params ? params->align : nullptr;
   const float* xX0 = params ? params->xX0 : nullptr;
-  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st) != hipSuccess)
+  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st, ctx->g.zhalf_cm,
+                             ctx->mat_nz) != hipSuccess)
     return KF_E_HIP;
   const kfd::Model md = model_of(ctx);
   kfi::AdjArgs a;
+  a.mat_map = ctx->mat_map;
+  a.mat_nz = ctx->mat_nz;
+  a.eloss = ctx->eloss;
   a.n = in->n;
   a.nl = ctx->g.n_layers;
   a.k.kB = md.kB;

@@ -128,6 +128,10 @@ struct AdjArgs {
   double* part;      // [L][5][n_blocks] per-block gradient sums
   int32_t every = 1;     // checkpoints every `every` layers (slot s = layer s * every)
   float* seg = nullptr;  // [every - 1][27][n]: the layers between two checkpoints, recomputed
+  // the material model (as in FitArgs): map [nl][mat_nz] or null, mean loss per X0
+  const float* mat_map = nullptr;
+  int32_t mat_nz = 0;
+  float eloss = 0.f;
 };
 
 // Blocks of the adjoint kernel for n tracks (one FP64 partial per block and parameter).

@@ -178,10 +178,9 @@ def test_dedup_calls_reject_bad_arguments_before_launch():
 
 
 def test_material_setting_validation_and_the_calls_it_excludes():
-    """kf_ctx_set_material stores its arguments (no device work here); while a map or
-    a loss is set, the adjoint refuses before launching (the finder and the smoother
-    take the model and go on to their own checks), and clearing the setting lets its
-    own validation run again."""
+    """kf_ctx_set_material stores its arguments (no device work here); the finder, the
+    smoother and the adjoint take the model and go on to their own checks (here: the
+    missing workspace)."""
     kf, lib = _lib()
     ctx = kf.Context(synth.workload_geometry(2))
     fake = C.c_void_p(0x1000)   # never dereferenced: no kf_fit is called here
@@ -206,7 +205,7 @@ def test_material_setting_validation_and_the_calls_it_excludes():
     assert codes() == (-3, -3, -3)
     for args in ((fake, 1, 0.0), (fake, 64, 0.0363), (None, 0, 0.0363)):
         assert lib.kf_ctx_set_material(ctx._h, args[0], args[1], C.c_float(args[2])) == 0
-        assert codes() == (-3, -3, -2), args
+        assert codes() == (-3, -3, -3), args
     assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
     assert codes() == (-3, -3, -3)
 
@@ -228,7 +227,7 @@ def test_field_setting_validation_and_the_calls_it_excludes():
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(-1e-6), C.c_float(-4e-6)) == 0
     assert back() == -3           # the adjoint takes the field: it stops at the workspace
     assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0363)) == 0
-    assert back() == -2           # but not the energy loss
+    assert back() == -3           # and the energy loss
     assert lib.kf_ctx_set_material(ctx._h, None, 0, C.c_float(0.0)) == 0
     assert lib.kf_ctx_set_field(ctx._h, C.c_float(0.0), C.c_float(0.0)) == 0
     assert back() == -3

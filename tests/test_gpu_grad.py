@@ -23,12 +23,16 @@ def _case(n, at_truth):
     return geom, ts, align
 
 
-def _gpu_grad(geom, ts, align, w, field=None, det_threshold=None, ckpt_every=1, static=False):
+def _gpu_grad(geom, ts, align, w, field=None, det_threshold=None, ckpt_every=1, static=False, material=None):
     need_gpu()
     from paper_1906_11744_amd import Context
     kf = Context(geom)
     if field is not None:
         kf.set_field(*field)
+    keep = None
+    if material is not None:   # (map [L][nz] float32 or None, eloss)
+        keep = None if material[0] is None else to_dev(np.asarray(material[0], np.float32))
+        kf.set_material(keep, material[1])
     if det_threshold is not None:
         kf.set_fallback_threshold(det_threshold)
     hits, mask = to_dev(ts.hits), mask_dev(ts.hit_mask)
@@ -187,3 +191,28 @@ def test_sparse_checkpoints_recompute_the_gradient(every):
         gf1 = np.concatenate([gaf1.ravel(), gxf1])
         gf = np.concatenate([gaf.ravel(), gxf])
         assert np.linalg.norm(gf - gf1) / np.linalg.norm(gf1) < 1e-5
+
+
+@pytest.mark.parametrize("part", ["map", "map + loss", "loss"])
+def test_gradient_under_the_material_model(part):
+    """The material model in the adjoint: the map's value at each crossing (its slope in
+    z; with a map the fifth component is the derivative w.r.t. an additive offset of
+    each layer's row) and the energy loss (kappa's change and its linearisation of the
+    covariance), against the oracle's dual-number gradient on what the GPU reads (the
+    map rounded to float32); and the same with checkpoints every third layer."""
+    geom = synth.workload_geometry(2)
+    a_true = synth.misalignment(geom.n_layers)
+    xmap = synth.material_map(geom).astype(np.float32)
+    el = synth.ELOSS_SI_GEV_PER_X0 if "loss" in part else 0.0
+    use_map = "map" in part
+    sim = (xmap, el) if use_map else (geom.xX0[:, None], el)
+    ts = synth.simulate(geom, synth.rng_for(80), 2000, (0.5, 50.0), True, 1.5, align=a_true, material=sim)
+    align = np.zeros_like(a_true)
+    w = np.random.default_rng(11).uniform(0.5, 1.5, ts.hits.shape[2])
+    mat = (xmap if use_map else None, float(np.float32(el)))
+    ga, gx, _ = _gpu_grad(geom, ts, align, w, material=mat)
+    ra, rx = oracle.fit_grad(geom, ts.hits, ts.hit_mask, align, geom.xX0, w,
+                             material=(xmap.astype(np.float64) if use_map else None, mat[1]))
+    _check(ga, gx, ra, rx, f"material model: {part}")
+    ga3, gx3, _ = _gpu_grad(geom, ts, align, w, material=mat, ckpt_every=3)
+    _check(ga3, gx3, ra, rx, f"material model: {part}, checkpoints every 3")
