@@ -63,15 +63,15 @@ PEAK_HBM_GBS = 8000.0
 # runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean over every launch of the run), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "6458d7323ffdf1b1", "tracks": 1_000_000,
-               "fetch_kib": 105389.2, "write_kib": 117242.8,
+FIT_TRAFFIC = {"sources": "320dbfc10a9bf36f", "tracks": 1_000_000,
+               "fetch_kib": 108077.9, "write_kib": 117298.1,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
 
 # The same for one smooth_kernel launch on that workload.
-SMOOTH_TRAFFIC = {"sources": "d1de2197c326dcae", "tracks": 1_000_000,
-                  "fetch_kib": 902506.5, "write_kib": 1800781.3,
+SMOOTH_TRAFFIC = {"sources": "124fa2d6b71c3d04", "tracks": 1_000_000,
+                  "fetch_kib": 902523.8, "write_kib": 1800781.3,
                   "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 SMOOTH_SOURCES = ("paper_1906_11744_amd/csrc/kf_smooth.hip", "paper_1906_11744_amd/csrc/kf_smooth.h",
                   "paper_1906_11744_amd/csrc/kf_adjoint.h")
@@ -89,8 +89,9 @@ def _traffic_bytes(table, sources, n_tracks):
 
 
 # The same for one find_kernel launch on the 64-event batch (773 995 seeds) in its
-# benchmarked configuration; valid only while the finder's sources hash to `sources`.
-FIND_TRAFFIC = {"sources": None, "tracks": 773995, "fetch_kib": 0.0, "write_kib": 0.0,
+# benchmarked configuration (6 lanes per seed, 16 wide-window bins, every seed's branches
+# kept for the refit); valid only while the finder's sources hash to `sources`.
+FIND_TRAFFIC = {"sources": "4fe08e645ea18a79", "tracks": 773995, "fetch_kib": 4470519.8, "write_kib": 3313160.4,
                 "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIND_SOURCES = ("paper_1906_11744_amd/csrc/kf_find.hip", "paper_1906_11744_amd/csrc/kf_device.h",
                 "paper_1906_11744_amd/csrc/kf_internal.h")
@@ -378,9 +379,28 @@ def bench_grad(steps, warmup):
     fwdb = kfb.fit(hits, mask, align=al, xX0=xX0, ckpt=True)
     t_fb, _, _ = _time_launches(lambda: kfb.fit(hits, mask, align=al, xX0=xX0, ckpt=True, out=fwdb), steps, warmup)
     t_bb, _, _ = _time_launches(lambda: kfb.fit_backward(hits, mask, fwdb, w, align=al, xX0=xX0), steps, warmup)
+    # sparse checkpoints: the forward keeps every k-th layer, the adjoint recomputes the rest
+    sparse = {}
+    for k in (2, 4, 17):
+        fk = kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True, ckpt_every=k)
+        tkf, _, _ = _time_launches(lambda: kf.fit(hits, mask, align=al, xX0=xX0, ckpt=True, ckpt_every=k, out=fk),
+                                   steps, warmup)
+        tkb, _, _ = _time_launches(lambda: kf.fit_backward(hits, mask, fk, w, align=al, xX0=xX0), steps, warmup)
+        sparse[str(k)] = {"checkpoint_bytes": int(fk["ckpt"].numel() * 4), "forward_ms": tkf * 1e3,
+                          "backward_ms": tkb * 1e3, "backward_over_forward": tkb / tkf}
+    # the material model (16-bin map per layer, silicon's energy loss) in forward and adjoint
+    xmap = synth.material_map(geom).astype(np.float32)
+    kfm = Context(geom)
+    dmap = t(xmap)
+    kfm.set_material(dmap, synth.ELOSS_SI_GEV_PER_X0)
+    fwdm = kfm.fit(hits, mask, align=al, xX0=xX0, ckpt=True)
+    t_fm, _, _ = _time_launches(lambda: kfm.fit(hits, mask, align=al, xX0=xX0, ckpt=True, out=fwdm), steps, warmup)
+    t_bm, _, _ = _time_launches(lambda: kfm.fit_backward(hits, mask, fwdm, w, align=al, xX0=xX0), steps, warmup)
     return {"tracks": n, "kalman_steps": n_steps, "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
-            "backward_over_forward": t_b / t_f,
+            "backward_over_forward": t_b / t_f, "checkpoint_bytes": int(fwd["ckpt"].numel() * 4),
             "field_forward_ms": t_fb * 1e3, "field_backward_ms": t_bb * 1e3,
+            "material_forward_ms": t_fm * 1e3, "material_backward_ms": t_bm * 1e3,
+            "sparse_checkpoints": sparse,
             "forward_algorithmic_bytes": b_f, "forward_GB_per_s": b_f / t_f / 1e9,
             "backward_algorithmic_bytes": b_b, "backward_GB_per_s": b_b / t_b / 1e9}
 
@@ -447,6 +467,42 @@ def bench_material(steps, warmup):
     fwd = ctx.fit(hits, mask, xX0=xX0, ckpt=True, out=fwd)
     t_sp = _time_kernel(ctx, lambda: ctx.smooth(hits, mask, fwd, xX0=xX0, out=sout), steps, warmup)
     res["smooth_1e6_tracks"] = {"kernel_ms": t_sm * 1e3, "kernel_ms_one_xX0_per_layer_uniform_field": t_sp * 1e3}
+    return res
+
+
+def bench_endcap(steps, warmup):
+    """Barrel and endcap (17 bounded cylinders, 7 disks per side, |eta| < 2.5): the fit of
+    1e5 tracks and the finder (with refit) on 8 events of 5 000 tracks."""
+    import torch
+
+    import synth
+    from paper_1906_11744_amd import Context
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    geom, ts = synth.endcap_workload(n=100_000)
+    ctx = Context(geom)
+    hits, mask, xX0 = t(ts.hits), t(ts.hit_mask.view(np.int32)), t(geom.xX0.astype(np.float32))
+    out = ctx.fit(hits, mask, xX0=xX0)
+    torch.cuda.synchronize()
+    ndf = out["ndf"].cpu().numpy()
+    status = out["status"].cpu().numpy().view(np.uint32)
+    n_steps = int(np.where(status & 16, 0, (ndf + 5) // 2).sum())
+    tm = _time_launches(lambda: ctx.fit(hits, mask, xX0=xX0, out=out), steps, warmup)
+    tk = _time_kernel(ctx, lambda: ctx.fit(hits, mask, xX0=xX0, out=out), steps, warmup)
+    last = np.array([int(m).bit_length() - 1 for m in ts.hit_mask])
+    res = {"fit": {"tracks": 100_000, "kalman_steps": n_steps, "steps_per_s": n_steps / tm.wall,
+                   "ms_per_call": tm.wall * 1e3, "kernel_ms": tk * 1e3,
+                   "tracks_ending_on_a_disk": float(np.mean(geom.is_disk[last]))}}
+    geom, ev = synth.endcap_find_workload(n_tracks=5000, n_events=8)
+    cf = Context(geom)
+    args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
+    xf = t(geom.xX0.astype(np.float32))
+    fo = cf.find(*args, xX0=xf, refit=True)
+    torch.cuda.synchronize()
+    tf = _time_launches(lambda: cf.find(*args, xX0=xf, refit=True, out=fo), max(3, steps // 4), warmup)
+    S = ev.seed_hits.shape[1]
+    res["find"] = {"events": 8, "seeds": S, "hits": int(ev.hits.shape[1]), "ms_per_call": tf.wall * 1e3,
+                   "seeds_per_s": S / tf.wall}
     return res
 
 
@@ -622,7 +678,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "material", "cpu_scaling", "copy"],
+    ap.add_argument("--only", choices=["all", "fit", "find", "grad", "smooth", "dedup", "material", "endcap",
+                                       "cpu_scaling", "copy"],
                     default="all")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -732,6 +789,8 @@ def main():
         res["dedup"] = bench_dedup(args.steps, args.warmup)
     if args.only in ("all", "material"):
         res["material"] = bench_material(args.steps, args.warmup)
+    if args.only in ("all", "endcap"):
+        res["endcap"] = bench_endcap(args.steps, args.warmup)
     if args.only in ("all", "cpu_scaling") and not args.no_cpu_baseline:
         res["cpu_finder_scaling"] = cpu_scaling()
     print(json.dumps(res), flush=True)
