@@ -88,10 +88,11 @@ def _traffic_bytes(table, sources, n_tracks):
     return 1024.0 * (table["fetch_kib"] * table["fetch_scale"] + table["write_kib"] * table["write_scale"])
 
 
-# The same for one find_kernel launch on the 64-event batch (773 995 seeds) in its
-# benchmarked configuration (6 lanes per seed, 16 wide-window bins, every seed's branches
-# kept for the refit); valid only while the finder's sources hash to `sources`.
-FIND_TRAFFIC = {"sources": "4fe08e645ea18a79", "tracks": 773995, "fetch_kib": 4470519.8, "write_kib": 3313160.4,
+# The same for one find_kernel launch on the 64-event batch (773 995 seeds) with the refit
+# of each seed's best candidate: the median over the run's launches (most of them are of
+# the configuration the autotuner keeps; the others are its trials); valid only while
+# the finder's sources hash to `sources`.
+FIND_TRAFFIC = {"sources": "66ec8893fc1a4c6d", "tracks": 773995, "fetch_kib": 4353164.7, "write_kib": 3314705.5,
                 "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIND_SOURCES = ("paper_1906_11744_amd/csrc/kf_find.hip", "paper_1906_11744_amd/csrc/kf_device.h",
                 "paper_1906_11744_amd/csrc/kf_internal.h")

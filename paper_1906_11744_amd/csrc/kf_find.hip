@@ -1,12 +1,14 @@
 // Combinatorial track finding on gfx950.
 //
 //  * bin_kernel: one workgroup per (event, layer) slice; places every hit on its
-//    (aligned) layer and counting-sorts it into n_phi x n_z bins in LDS.  Binned
+//    (aligned) layer and counting-sorts it into n_phi x n_z bins in LDS, writing the
+//    binned records range by range from an LDS staging area.  Binned
 //    records are (x, y, z, phi about the layer axis) plus the caller's hit index; the
 //    same records are also written in the caller's hit order, so that a hit known by
 //    its index is one 16-byte load away.
-//  * find_kernel: persistent one-wave workgroups pull tiles of 8 seeds from a counter.
-//    A seed owns a group of 8 lanes; lane k holds candidate k (state in registers).
+//  * find_kernel: persistent one-wave workgroups pull tiles of 64 / G seeds from a
+//    counter.  A seed owns a group of G lanes (G = 4, 6 or 8); lane k holds candidate k
+//    (state in registers).
 //    Per layer every live candidate predicts, parks its predicted covariance in LDS,
 //    scans the bins its window overlaps keeping its best hit branches in registers,
 //    the group merges all branches with min-reductions of 64-bit score keys over DPP
@@ -38,100 +40,135 @@ __device__ __forceinline__ int bin_index(float v, float lo, float scale, int nb)
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
-  extern __shared__ int cnt[];  // [nbins + 1] counts, then running write offsets
-  __shared__ int part[256];
+// The bin kernel: one workgroup of kBinThreads lanes per (event, layer) slice.  A slice
+// of up to kBinThreads * kBinHold hits is sorted with its placed hits held in registers
+// (lane t holds hits t, t + kBinThreads, ...): an LDS histogram, its scan, an LDS
+// atomic per hit for its place, then the binned records are assembled range by range in
+// LDS and written out contiguously, so that every global store is coalesced.  (Storing
+// each record at its place directly scatters 16- and 4-byte writes over the slice's
+// output; with a thousand slices in flight their cache lines leave the L2 part-written
+// and the writes reach memory at 2.4 times their size.)  Larger slices take the direct
+// scatter.
+constexpr int kBinThreads = 1024;
+constexpr int kBinHold = 24;
+
+__global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
+  // LDS: [nbins + 1] counts, then running places; then each held hit's bin or place
+  // (16 bits) and the staging of a range of binned hits (a.stage float4: position and
+  // index in the slice)
+  extern __shared__ __align__(16) unsigned char bin_lds[];
+  int* const cnt = reinterpret_cast<int*>(bin_lds);
+  __shared__ int part[kBinThreads];
   const int tid = threadIdx.x;
   const int seg = blockIdx.x;
   const int e = seg / a.nl, l = seg % a.nl;
   if (seg == 0 && tid == 0 && a.counter) *a.counter = 0;  // the find kernel's tile queue
   const int nb = a.nphi * a.nz;
-  for (int b = tid; b <= nb; b += 256) cnt[b] = 0;
+  for (int b = tid; b <= nb; b += kBinThreads) cnt[b] = 0;
   __syncthreads();
   // slices outside [0, H] or reversed are clamped (never read out of bounds)
   int64_t beg = a.hit_off[(int64_t)e * (a.nl + 1) + l];
   int64_t end = a.hit_off[(int64_t)e * (a.nl + 1) + l + 1];
   beg = beg < 0 ? 0 : (beg > a.H ? a.H : beg);
   end = end < beg ? beg : (end > a.H ? a.H : end);
+  const int n = (int)(end - beg);
   const kfd::LayerK ly = a.layers[l];
   // the bins' second coordinate: z over [-Z, Z] on a cylinder, rho over [lo, hi] on a disk
   const bool disk = ly.disk != 0.f;
   const float Z = a.zhalf[l];
   const float lo2 = disk ? ly.lo : -Z;
   const float sphi = a.nphi / kfd::kTwoPi, sz = a.nz / (disk ? ly.hi - ly.lo : 2.f * Z);
-  auto place_bin = [&](float hx, float hy, float hz, float4& rec) -> int {
-    float mx, my, mz;
-    kfd::place(ly, hx, hy, hz, mx, my, mz);
+  auto azimuth = [&](float mx, float my) { return atan2f(my - ly.cy, mx - ly.cx); };
+  auto bin_of = [&](float mx, float my, float mz, float ph) {
     const float ex = mx - ly.cx, ey = my - ly.cy;
-    const float ph = atan2f(ey, ex);
-    rec = make_float4(mx, my, mz, ph);
     const float c2 = disk ? sqrtf(fmaf(ex, ex, ey * ey)) : mz;
     return bin_index(ph, -kfd::kPi, sphi, a.nphi) * a.nz + bin_index(c2, lo2, sz, a.nz);
   };
-  // Each lane takes hits beg + tid + 256 k; kU of them are loaded before any is
-  // binned, so that their loads are in flight together.  Out-of-slice slots read the
-  // slice's first hit and are skipped.
-  constexpr int kU = 4;
-  auto load_hits = [&](int64_t j0, float (&hx)[kU], float (&hy)[kU], float (&hz)[kU]) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t j = j0 + (int64_t)u * 256;
-      const int64_t jj = j < end ? j : beg;
-      hx[u] = a.hits[jj];
-      hy[u] = a.hits[a.H + jj];
-      hz[u] = a.hits[2 * a.H + jj];
+  auto scan = [&]() {  // cnt[b] <- the slice's exclusive prefix of the counts; boff written
+    const int chunk = (nb + kBinThreads - 1) / kBinThreads;
+    const int c0 = min(nb, tid * chunk), c1 = min(nb, c0 + chunk);
+    int acc = 0;
+    for (int b = c0; b < c1; ++b) acc += cnt[b];
+    part[tid] = acc;
+    __syncthreads();
+    for (int off = 1; off < kBinThreads; off <<= 1) {
+      const int v = tid >= off ? part[tid - off] : 0;
+      __syncthreads();
+      part[tid] += v;
+      __syncthreads();
     }
+    int run = tid > 0 ? part[tid - 1] : 0;
+    int32_t* out_off = a.boff + ((int64_t)e * a.nl + l) * (nb + 1);
+    for (int b = c0; b < c1; ++b) {
+      const int c = cnt[b];
+      cnt[b] = run;
+      out_off[b] = (int)beg + run;
+      run += c;
+    }
+    if (tid == 0) out_off[nb] = (int)end;
+    __syncthreads();
   };
-  for (int64_t j0 = beg + tid; j0 < end; j0 += 256 * kU) {
-    float hx[kU], hy[kU], hz[kU];
-    load_hits(j0, hx, hy, hz);
+  if (n <= kBinThreads * kBinHold && a.stage > 0) {
+    // each hit's bin, then its place in the slice, as 16 bits in LDS (both < 32 768)
+    uint16_t* const sbin = reinterpret_cast<uint16_t*>(bin_lds + a.stage_off);
+    float4* const srec = reinterpret_cast<float4*>(bin_lds + a.stage_off + a.hold_bytes);
+    float px[kBinHold], py[kBinHold], pz[kBinHold];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      if (j0 + (int64_t)u * 256 < end) {
-        float4 rec;
-        atomicAdd(&cnt[place_bin(hx[u], hy[u], hz[u], rec)], 1);
+    for (int r = 0; r < kBinHold; ++r) {
+      const int q = tid + r * kBinThreads;
+      if (q < n) {
+        const int64_t j = beg + q;
+        kfd::place(ly, a.hits[j], a.hits[a.H + j], a.hits[2 * a.H + j], px[r], py[r], pz[r]);
+        const float ph = azimuth(px[r], py[r]);
+        a.hpos[j] = make_float4(px[r], py[r], pz[r], ph);
+        const int b = bin_of(px[r], py[r], pz[r], ph);
+        sbin[q] = (uint16_t)b;
+        atomicAdd(&cnt[b], 1);
       }
     }
-  }
-  __syncthreads();
-  // exclusive scan of nb counts: each thread a contiguous chunk, then the 256 chunk sums
-  const int chunk = (nb + 255) / 256;
-  const int c0 = tid * chunk, c1 = min(nb, c0 + chunk);
-  int acc = 0;
-  for (int b = c0; b < c1; ++b) acc += cnt[b];
-  part[tid] = acc;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int v = tid >= off ? part[tid - off] : 0;
     __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int run = (int)beg + (tid > 0 ? part[tid - 1] : 0);
-  int32_t* out_off = a.boff + ((int64_t)e * a.nl + l) * (nb + 1);
-  for (int b = c0; b < c1; ++b) {
-    const int c = cnt[b];
-    cnt[b] = run;
-    out_off[b] = run;
-    run += c;
-  }
-  if (tid == 0) out_off[nb] = (int)end;
-  __syncthreads();
-  for (int64_t j0 = beg + tid; j0 < end; j0 += 256 * kU) {
-    float hx[kU], hy[kU], hz[kU];
-    load_hits(j0, hx, hy, hz);
+    scan();
+    for (int q = tid; q < n; q += kBinThreads) sbin[q] = (uint16_t)atomicAdd(&cnt[sbin[q]], 1);
+    // staged: the placed position and the hit's index in the slice; the azimuth is
+    // evaluated again by the lane that writes the record out (the same function of the
+    // same values)
+    for (int p0 = 0; p0 < n; p0 += a.stage) {
+      __syncthreads();  // the places are in; the previous range has been written out
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t j = j0 + (int64_t)u * 256;
-      if (j < end) {
-        float4 rec;
-        const int b = place_bin(hx[u], hy[u], hz[u], rec);
-        const int p = atomicAdd(&cnt[b], 1);
-        a.brec[p] = rec;
-        a.bidx[p] = (int32_t)j;
-        a.hpos[j] = rec;
+      for (int r = 0; r < kBinHold; ++r) {
+        const int q = tid + r * kBinThreads;
+        if (q < n) {
+          const int d = (int)sbin[q] - p0;
+          if (d >= 0 && d < a.stage) srec[d] = make_float4(px[r], py[r], pz[r], __int_as_float(q));
+        }
+      }
+      __syncthreads();
+      const int m = min(a.stage, n - p0);
+      for (int d = tid; d < m; d += kBinThreads) {
+        const float4 h = srec[d];
+        a.brec[beg + p0 + d] = make_float4(h.x, h.y, h.z, azimuth(h.x, h.y));
+        a.bidx[beg + p0 + d] = (int32_t)beg + __float_as_int(h.w);
       }
     }
+    return;
+  }
+  // direct scatter: each hit is placed and binned twice (count, then store)
+  for (int64_t j = beg + tid; j < end; j += kBinThreads) {
+    float mx, my, mz;
+    kfd::place(ly, a.hits[j], a.hits[a.H + j], a.hits[2 * a.H + j], mx, my, mz);
+    atomicAdd(&cnt[bin_of(mx, my, mz, azimuth(mx, my))], 1);
+  }
+  __syncthreads();
+  scan();
+  for (int64_t j = beg + tid; j < end; j += kBinThreads) {
+    float mx, my, mz;
+    kfd::place(ly, a.hits[j], a.hits[a.H + j], a.hits[2 * a.H + j], mx, my, mz);
+    const float ph = azimuth(mx, my);
+    const float4 rec = make_float4(mx, my, mz, ph);
+    const int p = (int)beg + atomicAdd(&cnt[bin_of(mx, my, mz, ph)], 1);
+    a.brec[p] = rec;
+    a.bidx[p] = (int32_t)j;
+    a.hpos[j] = rec;
   }
 }
 
@@ -720,14 +757,34 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
   }
 }
 
+namespace {
+// dynamic LDS the bin kernel may take on the current device (its static part aside)
+int bin_lds_budget = 0;
+}  // namespace
+
 hipError_t prepare_bin(int nbins) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (nbins + 1) * (int)sizeof(int));
+  int dev = 0, per_block = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err == hipSuccess) err = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (err != hipSuccess) return err;
+  const int budget = per_block - (int)(kBinThreads * sizeof(int));
+  if (budget < (nbins + 1) * (int)sizeof(int)) return hipErrorInvalidValue;
+  err = hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            budget);
+  if (err == hipSuccess) bin_lds_budget = budget;
+  return err;
 }
 
-hipError_t launch_bin(const BinArgs& a, hipStream_t stream) {
-  const size_t lds = (size_t)(a.nphi * a.nz + 1) * sizeof(int);
-  hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(a.n_events * a.nl)), dim3(256), lds, stream, a);
+hipError_t launch_bin(BinArgs a, hipStream_t stream) {
+  // the counts, the held hits' 16-bit bins or places, then as many staged hits (16
+  // bytes) as the rest of the budget holds
+  const int cnt_bytes = ((a.nphi * a.nz + 1) * (int)sizeof(int) + 15) & ~15;
+  a.hold_bytes = kBinThreads * kBinHold * (int)sizeof(uint16_t);
+  const int room = (bin_lds_budget - cnt_bytes - a.hold_bytes) / (int)sizeof(float4);
+  a.stage_off = cnt_bytes;
+  a.stage = room >= 256 ? room : 0;  // below that, the direct scatter
+  const size_t lds = a.stage > 0 ? (size_t)bin_lds_budget : (size_t)cnt_bytes;
+  hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(a.n_events * a.nl)), dim3(kBinThreads), lds, stream, a);
   return hipGetLastError();
 }
 

@@ -68,6 +68,9 @@ struct BinArgs {
   int32_t* bidx;           // [H] caller's index of each binned hit
   int32_t* boff;           // [E][L][nbins + 1] absolute start of every bin
   int32_t* counter;        // find tile queue, zeroed here
+  // set by launch_bin: the number of hits staged in LDS per range, the LDS offset of
+  // the per-hit bins (then places), and their size
+  int32_t stage, stage_off, hold_bytes;
 };
 
 struct FindArgs {
@@ -203,7 +206,7 @@ hipError_t launch_dedup(const DedupArgs& a, bool seeds, hipStream_t stream);
 
 hipError_t launch_smooth(const SmoothArgs& a, hipStream_t stream, hipEvent_t ev_start = nullptr,
                          hipEvent_t ev_stop = nullptr);
-hipError_t launch_bin(const BinArgs& a, hipStream_t stream);
+hipError_t launch_bin(BinArgs a, hipStream_t stream);
 hipError_t prepare_bin(int nbins);  // allows the bin kernel's LDS for nbins bins
 size_t find_lds_bytes(int nl);
 int find_tile_seeds(int lanes_per_seed);        // seeds per find tile (one workgroup)

@@ -41,7 +41,7 @@ def _fit_gpu(geom, ts, align=None, ckpt=False):
     out = ctx.fit(to_dev(ts.hits), mask_dev(ts.hit_mask), align=a, xX0=to_dev(geom.xX0.astype(np.float32)),
                   ckpt=ckpt)
     torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in out.items()}
+    return {k: v.cpu().numpy() for k, v in out.items() if torch.is_tensor(v)}
 
 
 def _compare_fit(out, ref, label, idx=None):

@@ -44,7 +44,7 @@ def _gpu_smooth(geom, ts, align=None, seeds=None):
     fwd = ctx.fit(hits, mask, align=a, xX0=x, ckpt=True, **kw)
     out = ctx.smooth(hits, mask, fwd, align=a, xX0=x)
     torch.cuda.synchronize()
-    g = {k: v.cpu().numpy() for k, v in out.items()}
+    g = {k: v.cpu().numpy() for k, v in out.items() if torch.is_tensor(v)}
     g["ckpt"] = fwd["ckpt"].cpu().numpy()
     return g
 
