@@ -385,8 +385,8 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       // does, and otherwise takes the entry before it: one select per slot, no element
       // moves under a lane mask (register-pair copies followed by a partial overwrite
       // of the same pair have lost the new element on gfx950).
-      auto consider = [&](const float4 rec, int hh, const kfd::Trk& kk, const kfd::Frame& ff, const kfd::Pred& pp,
-                          float php, float zpp, float wph, float wzz, float cbase) __attribute__((always_inline)) {
+      auto in_window = [&](const float4 rec, float php, float zpp, float wph, float wzz)
+                           __attribute__((always_inline)) {
         const float dphi = kfd::wrap_pi(rec.w - php);
         float dz;
         if (disk) {  // the window's second coordinate: the hit's radius about the axis
@@ -395,7 +395,11 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         } else {
           dz = rec.z - zpp;
         }
-        if (!(fabsf(dphi) <= wph && fabsf(dz) <= wzz)) return;
+        return fabsf(dphi) <= wph && fabsf(dz) <= wzz;
+      };
+      auto consider = [&](const float4 rec, int hh, const kfd::Trk& kk, const kfd::Frame& ff, const kfd::Pred& pp,
+                          float php, float zpp, float wph, float wzz, float cbase) __attribute__((always_inline)) {
+        if (!in_window(rec, php, zpp, wph, wzz)) return;
         const kfd::Resid r = kfd::residual(kk, ff, ly, pp, rec.x, rec.y, rec.z, disk);
         if (!(r.chi2 < a.chi2_cut)) return;
         const float cc = cbase + r.chi2;
@@ -474,7 +478,20 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
 #pragma unroll
       for (int q = 0; q < 21; ++q) sC[q * kWave + lane] = k.C[q];
       if (predicted && !wide) {
+        // Two passes.  The window's records are tested against the rectangle alone, and
+        // the places of the first kMaxList that pass go to this lane's column of the LDS
+        // list area (unused until the wide-window scans); then only those are evaluated
+        // (chi2 and insertion, whose result does not depend on the order).  Most records
+        // fail the rectangle, and the lanes of a wave scan windows of different sizes, so
+        // the costly part no longer runs once per record of the wave's largest window.  A
+        // lane with more passing records than that (rare) evaluates its whole window.
+        int32_t* const spass = reinterpret_cast<int32_t*>(stc);
         const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
+        int npass = 0;
+        auto keep_place = [&](int q) __attribute__((always_inline)) {
+          if (npass < kMaxList) spass[npass * kWave + lane] = q;
+          ++npass;
+        };
         for (int b = blo; b <= bhi; ++b) {
           const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
           const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
@@ -482,11 +499,30 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
           int q = q0;
           for (; q + 1 < q1; q += 2) {
             const float4 r0 = a.brec[q], r1 = a.brec[q + 1];
-            const int h0 = a.bidx[q], h1 = a.bidx[q + 1];
-            consider(r0, h0, k, f, p, phip, zp, wphi, wz, c2);
-            consider(r1, h1, k, f, p, phip, zp, wphi, wz, c2);
+            if (in_window(r0, phip, zp, wphi, wz)) keep_place(q);
+            if (in_window(r1, phip, zp, wphi, wz)) keep_place(q + 1);
           }
-          if (q < q1) consider(a.brec[q], a.bidx[q], k, f, p, phip, zp, wphi, wz, c2);
+          if (q < q1 && in_window(a.brec[q], phip, zp, wphi, wz)) keep_place(q);
+        }
+        if (npass <= kMaxList) {
+          int t = 0;
+          for (; t + 1 < npass; t += 2) {
+            const int qa = spass[t * kWave + lane], qb = spass[(t + 1) * kWave + lane];
+            const float4 ra = a.brec[qa], rb = a.brec[qb];
+            const int ha = a.bidx[qa], hb = a.bidx[qb];
+            consider(ra, ha, k, f, p, phip, zp, wphi, wz, c2);
+            consider(rb, hb, k, f, p, phip, zp, wphi, wz, c2);
+          }
+          if (t < npass) {
+            const int qa = spass[t * kWave + lane];
+            consider(a.brec[qa], a.bidx[qa], k, f, p, phip, zp, wphi, wz, c2);
+          }
+        } else {
+          for (int b = blo; b <= bhi; ++b) {
+            const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
+            const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
+            for (int q = q0; q < q1; ++q) consider(a.brec[q], a.bidx[q], k, f, p, phip, zp, wphi, wz, c2);
+          }
         }
       }
       // ---- wide windows: each is scanned by the whole wave ----
@@ -706,34 +742,65 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
     // whole tile loop.
     int64_t So = S;
     asm volatile("" : "+s"(So));
-    if (active) {
-      const int keep = a.keep;
-      if (slot < keep) {
-        const bool have = slot < ncand;
-        auto at = [&](int kk, int64_t inner) { return ((int64_t)kk * inner) * So + s; };
-        int cur = slot;
-        const bool rank0 = slot == 0 && bpos != nullptr;
-        uint32_t rmask = 0;
-        for (int l = nl - 1; l >= 0; --l) {
+    const bool writer = active && slot < a.keep;
+    const bool have = writer && slot < ncand;
+    const bool rank0 = writer && slot == 0 && bpos != nullptr;
+    // The candidates' hit lists, from the last layer down: every lane loads its own
+    // backpointers (and placed hits) of eight layers at once, and each candidate follows
+    // its chain of ancestors by lane shuffles within its group, so that the walk waits
+    // on memory once per eight layers rather than once per layer.  All lanes take part
+    // in the shuffles; only the writers store.
+    {
+      int cur = slot;
+      uint32_t rmask = 0;
+      for (int l0 = nl - 1; l0 >= 0; l0 -= 8) {
+        int v[8];
+        float px[8], py[8], pz[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int l = l0 - j;
+          v[j] = l >= 3 ? bp[l * kWave + lane] : 0;
+          if (bpos && l >= 0) {
+            px[j] = bpos[(l * 3 + 0) * kWave + lane];
+            py[j] = bpos[(l * 3 + 1) * kWave + lane];
+            pz[j] = bpos[(l * 3 + 2) * kWave + lane];
+          } else {
+            px[j] = py[j] = pz[j] = 0.f;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int l = l0 - j;
+          if (l < 0) break;
+          const int at_lane = gbase + cur;  // the lane of this candidate's ancestor on layer l
+          const int vv = shfl_i(v[j], at_lane);
           int h = -2;
-          int at_lane = gbase + cur;  // the lane of this candidate's ancestor on layer l
           if (have) {
             if (l >= 3) {
-              const int v = bp[l * kWave + at_lane];
-              h = (v >> 3) - 2;
-              cur = v & 7;
+              h = (vv >> 3) - 2;
+              cur = vv & 7;
             } else {
               h = sh[l];
             }
           }
-          a.hit_idx[((int64_t)slot * nl + l) * So + s] = h;
-          if (rank0 && h >= 0) {  // the rank-0 candidate's placed hits, for the refit
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a.rpos[((int64_t)l * 3 + c) * So + s] = bpos[(l * 3 + c) * kWave + at_lane];
-            rmask |= 1u << l;
+          if (writer) a.hit_idx[((int64_t)slot * nl + l) * So + s] = h;
+          if (bpos) {
+            const float qx = shfl_f(px[j], at_lane), qy = shfl_f(py[j], at_lane), qz = shfl_f(pz[j], at_lane);
+            if (rank0 && h >= 0) {  // the rank-0 candidate's placed hits, for the refit
+              a.rpos[((int64_t)l * 3 + 0) * So + s] = qx;
+              a.rpos[((int64_t)l * 3 + 1) * So + s] = qy;
+              a.rpos[((int64_t)l * 3 + 2) * So + s] = qz;
+              rmask |= 1u << l;
+            }
           }
         }
-        if (rank0) a.rmask[s] = rmask;
+      }
+      if (rank0) a.rmask[s] = rmask;
+    }
+    if (active) {
+      const int keep = a.keep;
+      if (slot < keep) {
+        auto at = [&](int kk, int64_t inner) { return ((int64_t)kk * inner) * So + s; };
         a.n_hits[at(slot, 1)] = have ? nh : 0;
         a.n_miss[at(slot, 1)] = have ? nm : 0;
         a.chi2[at(slot, 1)] = have ? c2 : 0.f;
