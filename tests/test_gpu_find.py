@@ -308,6 +308,38 @@ def test_find_independent_of_launch_configuration():
         np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k], err_msg=f"{k} autotuned")
 
 
+def test_find_slices_beyond_the_held_hits():
+    """One event of 21 000 tracks: most of its layers hold more hits than the bin kernel
+    keeps in registers (24 576 per slice), so those slices are scattered directly while
+    the others are staged through LDS.  The candidates equal, bit for bit, those of a bin
+    tiling whose counts leave no LDS for the staging (every slice scattered directly),
+    and a sample of 1 500 seeds follows the oracle's finder under the parity rule."""
+    need_gpu()
+    from types import SimpleNamespace
+    geom, ev = synth.find_workload(3, n_tracks=21000)
+    sizes = np.diff(ev.hit_off[0])
+    assert sizes.max() > 24576 and sizes.min() < 24576, sizes
+    rng = np.random.default_rng(5)
+    sel = np.sort(rng.choice(ev.seed_hits.shape[1], 1500, replace=False))
+    sub = SimpleNamespace(hits=ev.hits, hit_off=ev.hit_off, seed_hits=np.ascontiguousarray(ev.seed_hits[:, sel]),
+                          seed_event=np.ascontiguousarray(ev.seed_event[sel]))
+    from paper_1906_11744_amd import Context
+    ctx = Context(geom)
+    args = (to_dev(sub.hits), to_dev(sub.hit_off), to_dev(sub.seed_hits), to_dev(sub.seed_event))
+    xX0 = to_dev(geom.xX0.astype(np.float32))
+    outs = []
+    for nphi, nz in [(0, 0), (256, 128)]:
+        ctx.set_find_config(n_phi_bins=nphi, n_z_bins=nz)
+        o = ctx.find(*args, xX0=xX0, refit=True)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in o.items() if torch.is_tensor(v)})
+    for k in outs[0]:
+        np.testing.assert_array_equal(outs[1][k], outs[0][k], err_msg=k)
+    r = oracle_find(geom, sub)
+    st = compare(geom, sub, outs[0], r, "21 000 tracks, 1 500 seeds")
+    assert st["exact"] + st["reordered"] >= 0.95 * sel.size
+
+
 def test_find_batched_equals_per_event():
     """Events in one call give the same candidates, bit for bit, as one call per event
     (hit indices rebased to the event's slice)."""
