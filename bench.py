@@ -271,13 +271,21 @@ def bench_find(steps, warmup):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     xX0 = t(geom.xX0.astype(np.float32))
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
+    # the context's default configuration first (the geometry's bins, the default lanes
+    # per seed and wide-window threshold), then the autotuned one
+    out = kf.find(*args, xX0=xX0)
+    kf.set_find_config(use_graph=1)
+    avg_d, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
+    cfg_d = kf.find_config()
+    kf.set_find_config(use_graph=0)
     out = kf.find(*args, xX0=xX0, autotune=True)
     avg, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
     kf.set_find_config(use_graph=1)
     avg_g, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, out=out), steps, warmup)
     res["single_event_5000_tracks"] = {"events_per_s": 1.0 / avg_g, "ms_per_event": avg_g * 1e3,
                                        "ms_per_event_without_graph": avg * 1e3,
-                                       "seeds": int(ev.seed_hits.shape[1]), "config": kf.find_config()}
+                                       "seeds": int(ev.seed_hits.shape[1]), "config": kf.find_config(),
+                                       "ms_per_event_default_config": avg_d * 1e3, "default_config": cfg_d}
     t0 = time.time()
     geom, ev = synth.find_workload(5)
     print(f"# generated 64 events ({ev.seed_hits.shape[1]} seeds, {ev.hits.shape[1]} hits) in "
@@ -285,7 +293,12 @@ def bench_find(steps, warmup):
     kf = Context(geom)
     xX0 = t(geom.xX0.astype(np.float32))
     args = (t(ev.hits), t(ev.hit_off), t(ev.seed_hits), t(ev.seed_event))
-    out = kf.find(*args, xX0=xX0, refit=True, autotune=True)
+    out = kf.find(*args, xX0=xX0, refit=True)
+    kf.set_find_config(use_graph=1)
+    avg_bd, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
+    cfg_bd = kf.find_config()
+    kf.set_find_config(use_graph=0)
+    out = kf.find(*args, xX0=xX0, refit=True, autotune=True, out=out)
     kf.set_find_config(use_graph=1)
     avg_b, _, _ = _time_launches(lambda: kf.find(*args, xX0=xX0, refit=True, out=out), max(3, steps // 4), warmup)
     # per-event calls on the same data
@@ -306,6 +319,7 @@ def bench_find(steps, warmup):
             kf.find(*a, xX0=xX0, refit=True, out=o)
     avg_l, _, _ = _time_launches(loop, max(3, steps // 4), warmup)
     res["batched_64_events"] = {"events_per_s": E / avg_b, "ms_per_call": avg_b * 1e3, "config": cfg_batched,
+                                "ms_per_call_default_config": avg_bd * 1e3, "default_config": cfg_bd,
                                 "seeds": int(ev.seed_hits.shape[1]), "hits": int(ev.hits.shape[1]),
                                 "fp64_fallback": _fallback_rates(out)}
     # the search kernel alone, on its own launch events (plain launches, the tuned

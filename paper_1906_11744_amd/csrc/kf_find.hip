@@ -495,8 +495,24 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         for (int b = blo; b <= bhi; ++b) {
           const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
           const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
-          // two records in flight per iteration
           int q = q0;
+          if (!kBounded) {
+            // on a cylinder the rectangle needs a record's (z, phi) half only: four of
+            // them in flight per iteration
+            const float2* const zw = reinterpret_cast<const float2*>(a.brec) + 1;
+            auto in_zw = [&](const float2 r) __attribute__((always_inline)) {
+              return in_window(make_float4(0.f, 0.f, r.x, r.y), phip, zp, wphi, wz);
+            };
+            for (; q + 3 < q1; q += 4) {
+              const float2 r0 = zw[2 * (int64_t)q], r1 = zw[2 * (int64_t)q + 2], r2 = zw[2 * (int64_t)q + 4],
+                           r3 = zw[2 * (int64_t)q + 6];
+              if (in_zw(r0)) keep_place(q);
+              if (in_zw(r1)) keep_place(q + 1);
+              if (in_zw(r2)) keep_place(q + 2);
+              if (in_zw(r3)) keep_place(q + 3);
+            }
+          }
+          // two records in flight per iteration
           for (; q + 1 < q1; q += 2) {
             const float4 r0 = a.brec[q], r1 = a.brec[q + 1];
             if (in_window(r0, phip, zp, wphi, wz)) keep_place(q);
@@ -677,6 +693,10 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         ++new_n;
       }
       // ---- every surviving slot takes its parent's (predicted) candidate ----
+      // (a hit branch's placed position is loaded first, so that its latency hides
+      // behind the exchange of the parent's state)
+      float4 hwin = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (active && slot < new_n && my_kind == K_HIT) hwin = a.hpos[my_hit];
       const int src = gbase + my_par;
       wave_sync();
 #pragma unroll
@@ -704,8 +724,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
             kfd::Pred pu;
             kfd::prepare(k, fu, a.md, pu, disk);
             if (pu.fp64) st |= kfd::ST_FP64;
-            const float4 h = a.hpos[my_hit];  // placed on its layer by the binning
-            const float mx = h.x, my = h.y, mz = h.z;
+            const float mx = hwin.x, my = hwin.y, mz = hwin.z;  // placed on its layer by the binning
             if (bpos) {
               bpos[(l * 3 + 0) * kWave + lane] = mx;
               bpos[(l * 3 + 1) * kWave + lane] = my;
