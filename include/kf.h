@@ -370,11 +370,13 @@ int kf_fit_backward(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in*
 /* kf_fit_backward for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation): the same
  * reverse sweep and the same bits as kf_fit_backward, with its workspace (the layer
- * table and the per-block FP64 partials, kf_workspace_size(KF_OP_FIT_BACKWARD, in)
- * bytes) taken from a scratch array that the library holds in every GPU's memory
- * instead of from a caller's `ws`.  The scratch is kf_static_scratch_bytes() = 16 MiB
- * per GPU, held from the first call on that GPU until the process ends (17 layers:
- * up to ~1.5e6 tracks; 32 layers: ~8e5).  A larger request returns KF_E_SCRATCH
+ * table, the per-block FP64 partials and, with checkpoints every k > 1 layers, the
+ * recomputed segment: kf_workspace_size(KF_OP_FIT_BACKWARD, in) bytes) taken from a
+ * scratch array that the library holds in every GPU's memory instead of from a
+ * caller's `ws`.  The scratch is kf_static_scratch_bytes() = 16 MiB per GPU, held from
+ * the first call on that GPU until the process ends (17 layers with every layer's
+ * checkpoint: up to ~1.5e6 tracks; 32 layers: ~8e5; the segment takes (k - 1) x 108
+ * bytes per track more).  A larger request returns KF_E_SCRATCH
  * before anything is launched; other errors as kf_fit_backward.  The call allocates
  * nothing.  Every call on one GPU shares that GPU's scratch, whatever the context or
  * stream: calls that may overlap on one GPU (different streams, threads) race and
