@@ -498,7 +498,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
           int q = q0;
           if (!kBounded) {
             // on a cylinder the rectangle needs a record's (z, phi) half only: four of
-            // them in flight per iteration
+            // them in flight per iteration (record q's half is zw[2 q])
             const float2* const zw = reinterpret_cast<const float2*>(a.brec) + 1;
             auto in_zw = [&](const float2 r) __attribute__((always_inline)) {
               return in_window(make_float4(0.f, 0.f, r.x, r.y), phip, zp, wphi, wz);
