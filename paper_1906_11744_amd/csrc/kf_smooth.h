@@ -61,6 +61,14 @@ KFA_HD void transport_cov_u(const kfa::Prop<T>& P, const T C[21], U Co[21]) {
   }
 }
 
+// Structural non-zeros of J^-1 = I - N + N^2 for the transport's six off-diagonal
+// terms N (at (0|1, 3|4), (2, 5), (4, 3); N^2 adds only to (0|1, 3)): products with the
+// other entries, exactly zero, are skipped (a float product with a literal zero is not
+// folded away, since the other factor could be infinite).
+KFA_HD constexpr bool ji_nz(int i, int j) {
+  return i == j || ((i == 0 || i == 1) && (j == 3 || j == 4)) || (i == 2 && j == 5) || (i == 4 && j == 3);
+}
+
 // The smoothed state is carried as its offset from the filtered one, ds = x_s - x_f:
 // offsets are small, so their float rounding is relative to the offset and does not
 // accumulate over the layers (a smoothed theta carried whole, rounded at every step,
@@ -313,7 +321,8 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
     for (int j = 0; j < 6; ++j) {
       T g = Ji[i][j];
 #pragma unroll
-      for (int q = 3; q < 6; ++q) g -= Ji[i][q] * W[q][j];
+      for (int q = 3; q < 6; ++q)
+        if (ji_nz(i, q)) g -= Ji[i][q] * W[q][j];
       G[i][j] = g;
     }
   // state: x_s - x_f = G (x_s1 - x_p), with x_s1 - x_p = ds1 + (x_f1 - x_p) and x_f1 -
@@ -344,7 +353,8 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
     for (int j = 0; j < 6; ++j) a += G[i][j] * d[j];
     ds[i] = a;
   }
-  // covariance: C_s = K T K^T + G (Q + C_s1) G^T
+  // covariance: C_s = K T K^T + G (Q + C_s1) G^T (Q is zero outside its (kappa, phi,
+  // theta) block)
   T KT[6][3], GE[6][6];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
@@ -352,7 +362,8 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
     for (int b = 0; b < 3; ++b) {
       T a = T(0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) a += Ji[i][3 + q] * (T(0.5) * (T3[q][b] + T3[b][q]));
+      for (int q = 0; q < 3; ++q)
+        if (ji_nz(i, 3 + q)) a += Ji[i][3 + q] * (T(0.5) * (T3[q][b] + T3[b][q]));
       KT[i][b] = a;
     }
 #pragma unroll
@@ -361,7 +372,7 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
     for (int j = 0; j < 6; ++j) {
       T b = T(0);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) b += G[i][q] * (Q[tri(q, j)] + Cs[tri(q, j)]);
+      for (int q = 0; q < 6; ++q) b += G[i][q] * (q >= 3 && j >= 3 ? Q[tri(q, j)] + Cs[tri(q, j)] : Cs[tri(q, j)]);
       GE[i][j] = b;
     }
 #pragma unroll
@@ -370,7 +381,8 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
     for (int j = 0; j <= i; ++j) {
       T acc = T(0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) acc += KT[i][q] * Ji[j][3 + q];
+      for (int q = 0; q < 3; ++q)
+        if (ji_nz(j, 3 + q)) acc += KT[i][q] * Ji[j][3 + q];
 #pragma unroll
       for (int q = 0; q < 6; ++q) acc += GE[i][q] * G[j][q];
       Cs[tri(i, j)] = acc;
