@@ -17,6 +17,8 @@
 //    Backpointers (parent slot and hit, one dword per layer and slot) go to a small
 //    per-workgroup buffer in global memory; candidates' hit lists are rebuilt from
 //    them at the end of the tile.
+#include <atomic>
+
 #include "kf_internal.h"
 
 namespace kfi {
@@ -485,13 +487,14 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         // fail the rectangle, and the lanes of a wave scan windows of different sizes, so
         // the costly part no longer runs once per record of the wave's largest window.  A
         // lane with more passing records than that (rare) evaluates its whole window.
-        int32_t* const spass = reinterpret_cast<int32_t*>(stc);
+        // (the places are kept as the bits of floats: the area is float-typed)
         const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
         int npass = 0;
         auto keep_place = [&](int q) __attribute__((always_inline)) {
-          if (npass < kMaxList) spass[npass * kWave + lane] = q;
+          if (npass < kMaxList) stc[npass * kWave + lane] = __int_as_float(q);
           ++npass;
         };
+        auto place_at = [&](int t) __attribute__((always_inline)) { return __float_as_int(stc[t * kWave + lane]); };
         for (int b = blo; b <= bhi; ++b) {
           const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
           const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
@@ -523,14 +526,14 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
         if (npass <= kMaxList) {
           int t = 0;
           for (; t + 1 < npass; t += 2) {
-            const int qa = spass[t * kWave + lane], qb = spass[(t + 1) * kWave + lane];
+            const int qa = place_at(t), qb = place_at(t + 1);
             const float4 ra = a.brec[qa], rb = a.brec[qb];
             const int ha = a.bidx[qa], hb = a.bidx[qb];
             consider(ra, ha, k, f, p, phip, zp, wphi, wz, c2);
             consider(rb, hb, k, f, p, phip, zp, wphi, wz, c2);
           }
           if (t < npass) {
-            const int qa = spass[t * kWave + lane];
+            const int qa = place_at(t);
             consider(a.brec[qa], a.bidx[qa], k, f, p, phip, zp, wphi, wz, c2);
           }
         } else {
@@ -844,8 +847,9 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
 }
 
 namespace {
-// dynamic LDS the bin kernel may take on the current device (its static part aside)
-int bin_lds_budget = 0;
+// dynamic LDS the bin kernel may take (its static part aside); set by prepare_bin,
+// which contexts on several host threads may call
+std::atomic<int> bin_lds_budget{0};
 }  // namespace
 
 hipError_t prepare_bin(int nbins) {
@@ -857,19 +861,20 @@ hipError_t prepare_bin(int nbins) {
   if (budget < (nbins + 1) * (int)sizeof(int)) return hipErrorInvalidValue;
   err = hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                             budget);
-  if (err == hipSuccess) bin_lds_budget = budget;
+  if (err == hipSuccess) bin_lds_budget.store(budget, std::memory_order_relaxed);
   return err;
 }
 
 hipError_t launch_bin(BinArgs a, hipStream_t stream) {
   // the counts, the held hits' 16-bit bins or places, then as many staged hits (16
   // bytes) as the rest of the budget holds
+  const int budget = bin_lds_budget.load(std::memory_order_relaxed);
   const int cnt_bytes = ((a.nphi * a.nz + 1) * (int)sizeof(int) + 15) & ~15;
   a.hold_bytes = kBinThreads * kBinHold * (int)sizeof(uint16_t);
-  const int room = (bin_lds_budget - cnt_bytes - a.hold_bytes) / (int)sizeof(float4);
+  const int room = (budget - cnt_bytes - a.hold_bytes) / (int)sizeof(float4);
   a.stage_off = cnt_bytes;
   a.stage = room >= 256 ? room : 0;  // below that, the direct scatter
-  const size_t lds = a.stage > 0 ? (size_t)bin_lds_budget : (size_t)cnt_bytes;
+  const size_t lds = a.stage > 0 ? (size_t)budget : (size_t)cnt_bytes;
   hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(a.n_events * a.nl)), dim3(kBinThreads), lds, stream, a);
   return hipGetLastError();
 }
