@@ -33,12 +33,11 @@ KFA_HD T wrap(T a) {
   return a;
 }
 
-// J C J^T (J = I + N, the transport of the step) accumulated in the precision U from
-// C: in double the transported covariance keeps what a float C itself holds, which
-// the C_p^-1 block below can need.
+// (I + A) C (I + A)^T for an A with the transport's six off-diagonal positions (0|1,
+// 3|4), (2, 5), (4, 3), accumulated in the precision U from C.  J^-1 = I - N + N^2 has
+// the same pattern as J = I + N.
 template <class U, class T>
-KFA_HD void transport_cov_u(const kfa::Prop<T>& P, const T C[21], U Co[21]) {
-  const U a03 = P.a03, a04 = P.a04, a13 = P.a13, a14 = P.a14, a25 = P.a25, a43 = P.a43;
+KFA_HD void sandwich_n(U a03, U a04, U a13, U a14, U a25, U a43, const T C[21], U Co[21]) {
   auto c = [&](int i, int j) { return (U)C[tri(i, j)]; };
   U B[6][6];
 #pragma unroll
@@ -59,6 +58,14 @@ KFA_HD void transport_cov_u(const kfa::Prop<T>& P, const T C[21], U Co[21]) {
     if (i >= 4) Co[tri(i, 4)] = B[i][4] + a43 * B[i][3];
     if (i >= 5) Co[tri(i, 5)] = B[i][5];
   }
+}
+
+// J C J^T (J = I + N, the transport of the step) accumulated in the precision U from
+// C: in double the transported covariance keeps what a float C itself holds, which
+// the C_p^-1 block below can need.
+template <class U, class T>
+KFA_HD void transport_cov_u(const kfa::Prop<T>& P, const T C[21], U Co[21]) {
+  sandwich_n<U>((U)P.a03, (U)P.a04, (U)P.a13, (U)P.a14, (U)P.a25, (U)P.a43, C, Co);
 }
 
 // Structural non-zeros of J^-1 = I - N + N^2 for the transport's six off-diagonal
@@ -313,18 +320,13 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
   if (!kF32 || !cp_terms<T, T>(P, Cf, Q, W, T3, piv) || !(piv >= k0.det_thr)) {
     if (!cp_terms<double, T>(P, Cf, Q, W, T3, piv)) return false;
   }
-  // G = J^-1 (I - W)
-  T G[6][6];
+  // G = J^-1 V with V = I - W, which differs from I in rows 3..5 only (V3 below); G is
+  // applied as its two factors
+  T V3[3][6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      T g = Ji[i][j];
-#pragma unroll
-      for (int q = 3; q < 6; ++q)
-        if (ji_nz(i, q)) g -= Ji[i][q] * W[q][j];
-      G[i][j] = g;
-    }
+    for (int j = 0; j < 6; ++j) V3[a][j] = (j == 3 + a ? T(1) : T(0)) - W[3 + a][j];
   // state: x_s - x_f = G (x_s1 - x_p), with x_s1 - x_p = ds1 + (x_f1 - x_p) and x_f1 -
   // x_p taken as the difference of the two filtered states less the step (exact or
   // nearly so in float: the rounding of x_p's ~100 cm coordinates would otherwise cost
@@ -346,16 +348,63 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
     Cs[tri(5, 3)] = iD * c53 - a * c55;
     Cs[tri(3, 3)] = iD * iD * c33 - T(2) * iD * a * c53 + a * a * c55;
   }
+  T vd[6];  // V d
+#pragma unroll
+  for (int i = 0; i < 3; ++i) vd[i] = d[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T v = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v += V3[a][j] * d[j];
+    vd[3 + a] = v;
+  }
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     T a = T(0);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a += G[i][j] * d[j];
+    for (int q = 0; q < 6; ++q)
+      if (ji_nz(i, q)) a += Ji[i][q] * vd[q];
     ds[i] = a;
   }
-  // covariance: C_s = K T K^T + G (Q + C_s1) G^T (Q is zero outside its (kappa, phi,
-  // theta) block)
-  T KT[6][3], GE[6][6];
+  // covariance: C_s = K T K^T + J^-1 F J^-T with F = V E V^T, E = Q + C_s1 (Q is zero
+  // outside its (kappa, phi, theta) block): V's identity rows leave rows and columns
+  // 0..2 of E as they are, so only rows 3..5 of V E (P3) and the (3..5, 3..5) block of
+  // F are products; J^-1 has the transport's sparsity
+  T E[21];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) E[q] = Cs[q];
+#pragma unroll
+  for (int i = 3; i < 6; ++i)
+#pragma unroll
+    for (int j = 3; j <= i; ++j) E[tri(i, j)] += Q[tri(i, j)];
+  T P3[3][6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      T v = T(0);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) v += V3[a][q] * E[tri(q, j)];
+      P3[a][j] = v;
+    }
+  T F[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      if (i < 3) {
+        F[tri(i, j)] = E[tri(i, j)];
+      } else if (j < 3) {
+        F[tri(i, j)] = P3[i - 3][j];
+      } else {
+        T v = T(0);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v += P3[i - 3][q] * V3[j - 3][q];
+        F[tri(i, j)] = v;
+      }
+    }
+  sandwich_n<T>(Ji[0][3], Ji[0][4], Ji[1][3], Ji[1][4], Ji[2][5], Ji[4][3], F, Cs);
+  T KT[6][3];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -369,22 +418,11 @@ KFA_HD bool rts_step(const T xf[6], const T Cf[21], const T xf1[6], const kfa::L
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      T b = T(0);
-#pragma unroll
-      for (int q = 0; q < 6; ++q) b += G[i][q] * (q >= 3 && j >= 3 ? Q[tri(q, j)] + Cs[tri(q, j)] : Cs[tri(q, j)]);
-      GE[i][j] = b;
-    }
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
     for (int j = 0; j <= i; ++j) {
-      T acc = T(0);
+      T acc = Cs[tri(i, j)];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
         if (ji_nz(j, 3 + q)) acc += KT[i][q] * Ji[j][3 + q];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) acc += GE[i][q] * G[j][q];
       Cs[tri(i, j)] = acc;
     }
   return true;
