@@ -70,8 +70,8 @@ FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csr
 
 
 # The same for one smooth_kernel launch on that workload.
-SMOOTH_TRAFFIC = {"sources": "3d9f5577b6b8d584", "tracks": 1_000_000,
-                  "fetch_kib": 902493.7, "write_kib": 1800781.2,
+SMOOTH_TRAFFIC = {"sources": "069c027262fcc2b9", "tracks": 1_000_000,
+                  "fetch_kib": 902497.8, "write_kib": 1800781.2,
                   "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 SMOOTH_SOURCES = ("paper_1906_11744_amd/csrc/kf_smooth.hip", "paper_1906_11744_amd/csrc/kf_smooth.h",
                   "paper_1906_11744_amd/csrc/kf_adjoint.h")

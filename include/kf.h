@@ -412,7 +412,9 @@ typedef struct kf_smooth_out {
  * layer is not reached from a checkpoint, or C_p is not positive definite) the
  * smoothing of that track stops and `first` records where.  A track whose fit ended
  * with BAD_INPUT has last = first = -1.  KF_E_INVALID for a NULL context, input or
- * output array, n < 0, or fwd->ckpt NULL; KF_E_UNSUPPORTED for in->ckpt_every > 1;
+ * output array, n < 0, n > 2^29 (far beyond what the checkpoints of one GPU's memory
+ * hold: 1.8 KB per track at 17 layers), or fwd->ckpt NULL; KF_E_UNSUPPORTED for
+ * in->ckpt_every > 1;
  * KF_E_WORKSPACE for a short or misaligned workspace.  Workspace:
  * kf_workspace_size(KF_OP_SMOOTH, in). */
 int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, const kf_fit_out* fwd,

@@ -776,7 +776,7 @@ int kf_smooth(kf_ctx* ctx, const kf_layer_params* params, const kf_fit_in* in, c
   if (!in->hit_mask || !fwd->ndf || !fwd->status || !fwd->ckpt || !out->state || !out->cov || !out->first ||
       !out->last)
     return KF_E_INVALID;
-  if (in->n > (int64_t)INT32_MAX * 64) return KF_E_INVALID;
+  if (in->n > ((int64_t)1 << 29)) return KF_E_INVALID;  // rows addressed by 32-bit byte offsets
   int rc = check_ws(ws, ws_bytes, fit_ws_bytes());
   if (rc != KF_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

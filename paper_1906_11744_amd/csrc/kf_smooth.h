@@ -150,7 +150,9 @@ KFA_HD bool cp_terms(const kfa::Prop<T>& P, const T Cf[21], const T Q[21], T W[6
   U dsc[6], L[21], linv[6];
   transport_cov_u<U>(P, Cf, L);
 #pragma unroll
-  for (int q = 0; q < 21; ++q) L[q] += (U)Q[q];
+  for (int i = 3; i < 6; ++i)
+#pragma unroll
+    for (int j = 3; j <= i; ++j) L[tri(i, j)] += (U)Q[tri(i, j)];  // Q's (kappa, phi, theta) block
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     const U cii = L[tri(i, i)];

@@ -6,6 +6,9 @@
 
 namespace kfi {
 
+// Word 3 of a raw buffer resource on gfx9-family parts: 32-bit data format, no swizzle.
+constexpr int32_t kBufWord3 = 0x00020000;
+
 // kModel: each step under the detector model (material map, energy loss, field).
 // Three waves per SIMD (at most 168 VGPRs, no spills): the other waves hide each
 // checkpoint load's latency, which beats holding a prefetched checkpoint (27 more live
@@ -15,6 +18,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sm
   const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (i >= a.n) return;
   const int64_t n = a.n;
+  // Each row of n floats is read and written through a buffer resource of its own
+  // (built in scalar registers) at this lane's 32-bit byte offset (n <= 2^29 on the
+  // host), so that a load or store takes no vector address arithmetic.
+  const uint32_t bo = (uint32_t)i * 4u;
+  const int32_t row_bytes = (int32_t)(n * 4);
+  auto ld = [bo, row_bytes](const float* row) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)row, 0, row_bytes, kBufWord3);
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, bo, 0, 0));
+  };
+  auto st4 = [bo, row_bytes](float* row, float v) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)row, 0, row_bytes, kBufWord3);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, bo, 0, 0);
+  };
   const int nl = a.nl;
   const kfa::Lay<float>* lays = reinterpret_cast<const kfa::Lay<float>*>(a.layers);
   const uint32_t st = a.status[i];
@@ -36,11 +52,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sm
   bool live = false;
   for (int l = nl - 1; l >= 0; --l) {
     float xf[6], Cf[21], xs[6];
-    const float* c = a.ckpt + (int64_t)l * 27 * n + i;  // the filtered estimate at layer l
+    const float* c = a.ckpt + (int64_t)l * 27 * n;  // the filtered estimates at layer l
 #pragma unroll
-    for (int q = 0; q < 6; ++q) xf[q] = c[q * n];
+    for (int q = 0; q < 6; ++q) xf[q] = ld(c + q * n);
 #pragma unroll
-    for (int q = 0; q < 21; ++q) Cf[q] = c[(6 + q) * n];
+    for (int q = 0; q < 21; ++q) Cf[q] = ld(c + (6 + q) * n);
     if (l == lend) {
       live = true;
 #pragma unroll
@@ -54,9 +70,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sm
     }
     kfs::smoothed_state<float>(xf, ds, xs);  // ds = 0 at l == lend
 #pragma unroll
-    for (int q = 0; q < 6; ++q) a.state[((int64_t)l * 6 + q) * n + i] = live ? xs[q] : 0.f;
+    for (int q = 0; q < 6; ++q) st4(a.state + ((int64_t)l * 6 + q) * n, live ? xs[q] : 0.f);
 #pragma unroll
-    for (int q = 0; q < 21; ++q) a.cov[((int64_t)l * 21 + q) * n + i] = live ? Cs[q] : 0.f;
+    for (int q = 0; q < 21; ++q) st4(a.cov + ((int64_t)l * 21 + q) * n, live ? Cs[q] : 0.f);
 #pragma unroll
     for (int q = 0; q < 6; ++q) xf1[q] = xf[q];
   }
