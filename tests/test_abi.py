@@ -330,3 +330,18 @@ def test_sparse_checkpoint_arguments():
     so = kf.SmoothOut(fake, fake, fake, fake)
     fin = kf.FitIn(10, fake, fake, None, None, 1, 2)
     assert lib.kf_smooth(ctx._h, C.byref(p), C.byref(fin), C.byref(fo), C.byref(so), None, 0, None) == -2
+
+
+def test_smooth_rejects_batches_beyond_its_row_offsets():
+    """kf_smooth addresses each [.][n] row by 32-bit byte offsets: n above 2^29 is
+    KF_E_INVALID before anything else; n = 2^29 goes on to the workspace check."""
+    kf, lib = _lib()
+    ctx = kf.Context(synth.workload_geometry(2))
+    fake = C.c_void_p(0x1000)   # never dereferenced: both calls return before any launch
+    p = kf.LayerParams()
+    fit_out = kf.FitOut(fake, fake, fake, fake, fake, fake)
+    so = kf.SmoothOut(fake, fake, fake, fake)
+    for n, code in (((1 << 29) + 1, -1), (1 << 29, -3)):
+        fit_in = kf.FitIn(n, fake, fake, None, None, 1)
+        assert lib.kf_smooth(ctx._h, C.byref(p), C.byref(fit_in), C.byref(fit_out), C.byref(so), None, 0,
+                             None) == code, n
