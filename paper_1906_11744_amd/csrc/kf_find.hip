@@ -18,6 +18,7 @@
 //    per-workgroup buffer in global memory; candidates' hit lists are rebuilt from
 //    them at the end of the tile.
 #include <atomic>
+#include <type_traits>
 
 #include "kf_internal.h"
 
@@ -27,6 +28,9 @@ namespace {
 
 constexpr int kWave = 64;     // one wave per find workgroup
 constexpr int kMaxList = 8;   // hit branches kept per candidate
+// azimuth differences wrapped to (-pi, pi], or taken as they are
+constexpr std::integral_constant<bool, true> kWrap{};
+constexpr std::integral_constant<bool, false> kNoWrap{};
 // A seed's candidates sit in a group of G consecutive lanes (G = 4, 6 or 8, >= keep);
 // a wave holds kWave / G seeds (the tile) and leaves the kWave % G lanes after them idle.
 
@@ -387,9 +391,10 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       // does, and otherwise takes the entry before it: one select per slot, no element
       // moves under a lane mask (register-pair copies followed by a partial overwrite
       // of the same pair have lost the new element on gfx950).
-      auto in_window = [&](const float4 rec, float php, float zpp, float wph, float wzz)
+      auto in_window = [&](const float4 rec, float php, float zpp, float wph, float wzz, auto wrap)
                            __attribute__((always_inline)) {
-        const float dphi = kfd::wrap_pi(rec.w - php);
+        float dphi = rec.w - php;
+        if constexpr (decltype(wrap)::value) dphi = kfd::wrap_pi(dphi);
         float dz;
         if (disk) {  // the window's second coordinate: the hit's radius about the axis
           const float ex = rec.x - ly.cx, ey = rec.y - ly.cy;
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       };
       auto consider = [&](const float4 rec, int hh, const kfd::Trk& kk, const kfd::Frame& ff, const kfd::Pred& pp,
                           float php, float zpp, float wph, float wzz, float cbase) __attribute__((always_inline)) {
-        if (!in_window(rec, php, zpp, wph, wzz)) return;
+        if (!in_window(rec, php, zpp, wph, wzz, kWrap)) return;
         const kfd::Resid r = kfd::residual(kk, ff, ly, pp, rec.x, rec.y, rec.z, disk);
         if (!(r.chi2 < a.chi2_cut)) return;
         const float cc = cbase + r.chi2;
@@ -481,22 +486,32 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
       for (int q = 0; q < 21; ++q) sC[q * kWave + lane] = k.C[q];
       if (predicted && !wide) {
         // Two passes.  The window's records are tested against the rectangle alone, and
-        // the places of the first kMaxList that pass go to this lane's column of the LDS
-        // list area (unused until the wide-window scans); then only those are evaluated
-        // (chi2 and insertion, whose result does not depend on the order).  Most records
-        // fail the rectangle, and the lanes of a wave scan windows of different sizes, so
-        // the costly part no longer runs once per record of the wave's largest window.  A
-        // lane with more passing records than that (rare) evaluates its whole window.
-        // (the places are kept as the bits of floats: the area is float-typed)
+        // the places of the first kMaxList - 1 that pass go to this lane's column of the
+        // LDS list area (unused until the wide-window scans); then only those are
+        // evaluated (chi2 and insertion, whose result does not depend on the order).
+        // Most records fail the rectangle, and the lanes of a wave scan windows of
+        // different sizes, so the costly part no longer runs once per record of the
+        // wave's largest window.  A lane with more passing records than that (rare)
+        // evaluates its whole window.  (The places are kept as the bits of floats: the
+        // area is float-typed.)
+        // The first pass needs only to keep a superset of the window: it compares a
+        // record's azimuth with the prediction's shifted by 2 pi where the bin lies
+        // across the -pi/pi seam (no wrap per record), with a margin for the rounding
+        // of that shift; the second pass applies the exact test.  A window within two
+        // bins of the whole ring keeps every azimuth.  Every record's place is written,
+        // branch-free, into the next free row, and only a passing one advances it: the
+        // last of the kMaxList rows is that spare once kMaxList - 1 are kept.
+        const float wph1 = wphi < kfd::kPi - 2.f / kphi ? wphi + 4e-6f : INFINITY;
         const int32_t* boff = a.boff + ((int64_t)e * nl + l) * (nb_all + 1);
         int npass = 0;
-        auto keep_place = [&](int q) __attribute__((always_inline)) {
-          if (npass < kMaxList) stc[npass * kWave + lane] = __int_as_float(q);
-          ++npass;
+        auto keep_place = [&](int q, bool pass) __attribute__((always_inline)) {
+          stc[min(npass, kMaxList - 1) * kWave + lane] = __int_as_float(q);
+          npass += pass ? 1 : 0;
         };
         auto place_at = [&](int t) __attribute__((always_inline)) { return __float_as_int(stc[t * kWave + lane]); };
         for (int b = blo; b <= bhi; ++b) {
           const int pb = b < 0 ? b + a.nphi : (b >= a.nphi ? b - a.nphi : b);
+          const float phb = b < 0 ? phip + kfd::kTwoPi : (b >= a.nphi ? phip - kfd::kTwoPi : phip);
           const int q0 = boff[pb * a.nz + zlo], q1 = boff[pb * a.nz + zhi + 1];
           int q = q0;
           if (!kBounded) {
@@ -504,26 +519,26 @@ __global__ __launch_bounds__(kWave, 4) void find_kernel(FindArgs a) {
             // them in flight per iteration (record q's half is zw[2 q])
             const float2* const zw = reinterpret_cast<const float2*>(a.brec) + 1;
             auto in_zw = [&](const float2 r) __attribute__((always_inline)) {
-              return in_window(make_float4(0.f, 0.f, r.x, r.y), phip, zp, wphi, wz);
+              return in_window(make_float4(0.f, 0.f, r.x, r.y), phb, zp, wph1, wz, kNoWrap);
             };
             for (; q + 3 < q1; q += 4) {
               const float2 r0 = zw[2 * (int64_t)q], r1 = zw[2 * (int64_t)q + 2], r2 = zw[2 * (int64_t)q + 4],
                            r3 = zw[2 * (int64_t)q + 6];
-              if (in_zw(r0)) keep_place(q);
-              if (in_zw(r1)) keep_place(q + 1);
-              if (in_zw(r2)) keep_place(q + 2);
-              if (in_zw(r3)) keep_place(q + 3);
+              keep_place(q, in_zw(r0));
+              keep_place(q + 1, in_zw(r1));
+              keep_place(q + 2, in_zw(r2));
+              keep_place(q + 3, in_zw(r3));
             }
           }
           // two records in flight per iteration
           for (; q + 1 < q1; q += 2) {
             const float4 r0 = a.brec[q], r1 = a.brec[q + 1];
-            if (in_window(r0, phip, zp, wphi, wz)) keep_place(q);
-            if (in_window(r1, phip, zp, wphi, wz)) keep_place(q + 1);
+            keep_place(q, in_window(r0, phb, zp, wph1, wz, kNoWrap));
+            keep_place(q + 1, in_window(r1, phb, zp, wph1, wz, kNoWrap));
           }
-          if (q < q1 && in_window(a.brec[q], phip, zp, wphi, wz)) keep_place(q);
+          if (q < q1) keep_place(q, in_window(a.brec[q], phb, zp, wph1, wz, kNoWrap));
         }
-        if (npass <= kMaxList) {
+        if (npass < kMaxList) {
           int t = 0;
           for (; t + 1 < npass; t += 2) {
             const int qa = place_at(t), qb = place_at(t + 1);
