@@ -63,7 +63,7 @@ PEAK_HBM_GBS = 8000.0
 # runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean over every launch of the run), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "320dbfc10a9bf36f", "tracks": 1_000_000,
+FIT_TRAFFIC = {"sources": "dcbff708a538cb38", "tracks": 1_000_000,
                "fetch_kib": 108077.9, "write_kib": 117298.1,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
@@ -92,7 +92,7 @@ def _traffic_bytes(table, sources, n_tracks):
 # of each seed's best candidate: the median over the run's launches (most of them are of
 # the configuration the autotuner keeps; the others are its trials); valid only while
 # the finder's sources hash to `sources`.
-FIND_TRAFFIC = {"sources": "3b6461e83c0f8624", "tracks": 773995, "fetch_kib": 4252272.7, "write_kib": 3137996.8,
+FIND_TRAFFIC = {"sources": "39a3b25550978c89", "tracks": 773995, "fetch_kib": 4252272.7, "write_kib": 3137996.8,
                 "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIND_SOURCES = ("paper_1906_11744_amd/csrc/kf_find.hip", "paper_1906_11744_amd/csrc/kf_device.h",
                 "paper_1906_11744_amd/csrc/kf_internal.h")

@@ -439,11 +439,7 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   kfd::LayerK* layers = reinterpret_cast<kfd::LayerK*>(base + w.layers);
   const float* align = params ? params->align : nullptr;
   const float* xX0 = params ? params->xX0 : nullptr;
-  const kfi::Surfaces sf = ctx->surfaces();
-  if (kfi::launch_layer_prep(ctx->g.n_layers, ctx->g.radius_cm, align, xX0, layers, st, ctx->g.zhalf_cm,
-                             ctx->mat_nz, &sf) != hipSuccess)
-    return KF_E_HIP;
-  kfi::BinArgs b;
+  kfi::BinArgs b;  // (the bin kernel also builds the layer table)
   b.nl = ctx->g.n_layers;
   find_bins(ctx, &b.nphi, &b.nz);
   b.n_events = in->n_events;
@@ -451,7 +447,14 @@ int enqueue_find(kf_ctx* ctx, const kf_layer_params* params, const kf_find_in* i
   b.hit_off = in->hit_off;
   b.hits = in->hits;
   b.layers = layers;
-  for (int l = 0; l < 32; ++l) b.zhalf[l] = l < ctx->g.n_layers ? ctx->g.zhalf_cm[l] : 1.f;
+  b.align = align;
+  b.xX0 = xX0;
+  b.mat_nz = ctx->mat_nz;
+  b.sf = ctx->surfaces();
+  for (int l = 0; l < 32; ++l) {
+    b.radius[l] = l < ctx->g.n_layers ? ctx->g.radius_cm[l] : 0.f;
+    b.zhalf[l] = l < ctx->g.n_layers ? ctx->g.zhalf_cm[l] : 1.f;
+  }
   b.brec = reinterpret_cast<float4*>(base + w.brec);
   b.hpos = reinterpret_cast<float4*>(base + w.hpos);
   b.bidx = reinterpret_cast<int32_t*>(base + w.bidx);

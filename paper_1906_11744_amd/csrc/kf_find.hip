@@ -78,7 +78,10 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
   beg = beg < 0 ? 0 : (beg > a.H ? a.H : beg);
   end = end < beg ? beg : (end > a.H ? a.H : end);
   const int n = (int)(end - beg);
-  const kfd::LayerK ly = a.layers[l];
+  const kfd::LayerK ly =
+      make_layer(l, a.radius, a.align, a.xX0, a.zhalf, a.mat_nz, a.sf.disk_z[l], a.sf.rmin[l], a.sf.rmax[l],
+                 a.sf.zmax[l]);
+  if (e == 0 && tid == 0) a.layers[l] = ly;
   // the bins' second coordinate: z over [-Z, Z] on a cylinder, rho over [lo, hi] on a disk
   const bool disk = ly.disk != 0.f;
   const float Z = a.zhalf[l];

@@ -7,33 +7,6 @@ struct Radii {
   float r[32];
 };
 
-// Constants of layer l: radius, alignment (centre shift, z shift, cos/sin of the
-// rotation), material, endcap surface.  align / xX0 may be null (all zero); zhalf / nz
-// place the bins of a material map (nz = 0: none); zd, rmin, rmax, zmax: the layer's
-// Surfaces entries (all 0: an infinite cylinder).
-__device__ __forceinline__ kfd::LayerK make_layer(int l, const float* radius, const float* __restrict__ align,
-                                                  const float* __restrict__ xX0, const float* zhalf = nullptr,
-                                                  int nz = 0, float zd = 0.f, float rmin = 0.f, float rmax = 0.f,
-                                                  float zmax = 0.f) {
-  kfd::LayerK k;
-  k.zs = (nz > 1) ? (float)nz / (2.f * zhalf[l]) : 0.f;
-  k.zo = 0.5f * (float)nz - 0.5f;
-  k.r = radius[l];
-  k.cx = align ? align[4 * l + 0] : 0.f;
-  k.cy = align ? align[4 * l + 1] : 0.f;
-  k.dz = align ? align[4 * l + 2] : 0.f;
-  const float dphi = align ? align[4 * l + 3] : 0.f;
-  sincosf(dphi, &k.sphi, &k.cphi);
-  k.xX0 = xX0 ? xX0[l] : 0.f;
-  k.moved = (k.cx != 0.f || k.cy != 0.f || k.dz != 0.f || dphi != 0.f) ? 1.f : 0.f;
-  k.disk = zd != 0.f ? 1.f : 0.f;
-  k.bounded = (zd != 0.f || zmax > 0.f) ? 1.f : 0.f;
-  k.zp = zd != 0.f ? zd + k.dz : 0.f;
-  k.lo = zd != 0.f ? rmin : 0.f;
-  k.hi = zd != 0.f ? rmax : zmax;
-  return k;
-}
-
 __global__ void layer_prep_kernel(int nl, Radii rad, Radii zh, int map_nz, const float* __restrict__ align,
                                   const float* __restrict__ xX0, kfd::LayerK* __restrict__ out, Surfaces sf) {
   const int l = threadIdx.x;
