@@ -63,8 +63,8 @@ PEAK_HBM_GBS = 8000.0
 # runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean over every launch of the run), each scaled by
 # what the same counter reads for a device copy of 1 GiB (FETCH_SIZE 524 300 KiB,
 # WRITE_SIZE 1 048 576 KiB).  Valid only while the fit kernel's sources hash to `sources`.
-FIT_TRAFFIC = {"sources": "dcbff708a538cb38", "tracks": 1_000_000,
-               "fetch_kib": 108077.9, "write_kib": 117298.1,
+FIT_TRAFFIC = {"sources": "df523bda9e7396ef", "tracks": 1_000_000,
+               "fetch_kib": 108222.4, "write_kib": 117298.2,
                "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIT_SOURCES = ("paper_1906_11744_amd/csrc/kf_fit.hip", "paper_1906_11744_amd/csrc/kf_device.h")
 
