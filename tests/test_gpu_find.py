@@ -189,6 +189,30 @@ def test_find_wide_windows_wrap():
     compare(geom, ev, g, r, "wide windows", nsigma=300.0, chi2_cut=50.0)
 
 
+@pytest.mark.parametrize("nsigma", [30.0, 300.0])
+def test_find_narrow_scan_across_the_seam(nsigma):
+    """Every window scanned lane by lane (its first pass compares azimuths with the
+    prediction shifted by 2 pi across the -pi/pi seam, no wrap per record; windows within
+    two bins of the whole ring keep every azimuth) against every window scanned by the
+    whole wave (the exact wrapped test on each record): at many sigma most windows span
+    several bins, many cross the seam and some the whole ring; every output bit agrees."""
+    need_gpu()
+    from paper_1906_11744_amd import Context
+    geom, ev = synth.find_workload(3, n_tracks=400)
+    ctx = Context(geom)
+    args = (to_dev(ev.hits), to_dev(ev.hit_off), to_dev(ev.seed_hits), to_dev(ev.seed_event))
+    xX0 = to_dev(geom.xX0.astype(np.float32))
+    got = []
+    for wide in (1 << 30, 0):
+        ctx.set_find_config(wide_window_bins=wide)
+        out = ctx.find(*args, xX0=xX0, nsigma=nsigma, chi2_cut=50.0)
+        torch.cuda.synchronize()
+        got.append({k: v.cpu().numpy() for k, v in out.items() if torch.is_tensor(v)})
+    for k in got[0]:
+        np.testing.assert_array_equal(got[0][k], got[1][k], err_msg=f"{k} nsigma={nsigma}")
+    assert (got[0]["n_cand"] > 0).mean() > 0.9
+
+
 def test_find_batched_events_and_refit():
     """Several events of uneven size in one call; the rank-0 refit matches the oracle's."""
     geom, ev = synth.find_workload(5, n_tracks=400, n_events=6)
