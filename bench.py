@@ -92,7 +92,7 @@ def _traffic_bytes(table, sources, n_tracks):
 # of each seed's best candidate: the median over the run's launches (most of them are of
 # the configuration the autotuner keeps; the others are its trials); valid only while
 # the finder's sources hash to `sources`.
-FIND_TRAFFIC = {"sources": "39a3b25550978c89", "tracks": 773995, "fetch_kib": 4252272.7, "write_kib": 3137996.8,
+FIND_TRAFFIC = {"sources": "b3bdc3bfb3b7b275", "tracks": 773995, "fetch_kib": 4252272.7, "write_kib": 3137996.8,
                 "fetch_scale": 1048576.0 / 524300.0, "write_scale": 1.0}
 FIND_SOURCES = ("paper_1906_11744_amd/csrc/kf_find.hip", "paper_1906_11744_amd/csrc/kf_device.h",
                 "paper_1906_11744_amd/csrc/kf_internal.h")

@@ -57,6 +57,8 @@ __device__ __forceinline__ int bin_index(float v, float lo, float scale, int nb)
 // scatter.
 constexpr int kBinThreads = 1024;
 constexpr int kBinHold = 24;
+constexpr int kBinWaves = kBinThreads / 64;
+constexpr int kBinStaticLds = 256;  // the static LDS (the waves' scan totals), rounded up
 
 __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
   // LDS: [nbins + 1] counts, then running places; then each held hit's bin or place
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
   // index in the slice)
   extern __shared__ __align__(16) unsigned char bin_lds[];
   int* const cnt = reinterpret_cast<int*>(bin_lds);
-  __shared__ int part[kBinThreads];
+  __shared__ int wsum[kBinWaves];
   const int tid = threadIdx.x;
   const int seg = blockIdx.x;
   const int e = seg / a.nl, l = seg % a.nl;
@@ -98,15 +100,28 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
     const int c0 = min(nb, tid * chunk), c1 = min(nb, c0 + chunk);
     int acc = 0;
     for (int b = c0; b < c1; ++b) acc += cnt[b];
-    part[tid] = acc;
-    __syncthreads();
-    for (int off = 1; off < kBinThreads; off <<= 1) {
-      const int v = tid >= off ? part[tid - off] : 0;
-      __syncthreads();
-      part[tid] += v;
-      __syncthreads();
+    // the exclusive prefix of acc over the workgroup: an inclusive scan inside each wave
+    // by lane shuffles, then one over the waves' totals (two barriers)
+    const int lane = tid & 63, wid = tid >> 6;
+    int v = acc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(v, off, 64);
+      if (lane >= off) v += t;
     }
-    int run = tid > 0 ? part[tid - 1] : 0;
+    if (lane == 63) wsum[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+      int w = lane < kBinWaves ? wsum[lane] : 0;
+#pragma unroll
+      for (int off = 1; off < kBinWaves; off <<= 1) {
+        const int t = __shfl_up(w, off, 64);
+        if (lane >= off) w += t;
+      }
+      if (lane < kBinWaves) wsum[lane] = w;
+    }
+    __syncthreads();
+    int run = (wid > 0 ? wsum[wid - 1] : 0) + v - acc;
     int32_t* out_off = a.boff + ((int64_t)e * a.nl + l) * (nb + 1);
     for (int b = c0; b < c1; ++b) {
       const int c = cnt[b];
@@ -875,7 +890,7 @@ hipError_t prepare_bin(int nbins) {
   hipError_t err = hipGetDevice(&dev);
   if (err == hipSuccess) err = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (err != hipSuccess) return err;
-  const int budget = per_block - (int)(kBinThreads * sizeof(int));
+  const int budget = per_block - kBinStaticLds;
   if (budget < (nbins + 1) * (int)sizeof(int)) return hipErrorInvalidValue;
   err = hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                             budget);
